@@ -1,0 +1,534 @@
+/*
+ * FP64 CPU oracle for the phase-space-tessellation column-density projection.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, plain reference that the GPU
+ * library is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header,
+ * table or helper with the GPU library, and the GPU library never calls it.
+ *
+ * What it computes (point sampling at pixel centres):
+ *
+ *   I(ix, iy) = sum over lattice cubes, sum over the six tetrahedra T of the
+ *               cube, of (m / |V(T)|) * length(ray(ix, iy) inside T)
+ *
+ * which is the line-of-sight projection of the tessellation density
+ * (Eq. Eqn:TetProjection, with the per-tetrahedron value q = rho_loc = m/V
+ * of Eq. Eqn-rho_loc and the overlap sum of Eq. Eqn-rho_tot_b).  The
+ * cell-projection section (Eq. Eqn:TetSum) evaluates the same sum with a
+ * camera-distance split; the oracle uses the plain per-ray clip instead.
+ *
+ * Steps, in the paper's order and notation:
+ *  1. Tracer id -> lattice vertex (i, j, k) with id = i + d0 (j + d1 k)
+ *     (Eq. Eqn:ID).  Cube (i, j, k) has corners n = a + 2b + 4c at
+ *     (i + a, j + b, k + c), taken modulo the lattice when periodic.
+ *  2. Periodic unwrap: every corner is moved to the periodic image nearest
+ *     to corner 0 of its cube, one component at a time; an offset of exactly
+ *     half the box is taken in the positive direction, i.e. the offset lies
+ *     in (-L/2, L/2].
+ *  3. Six tetrahedra per cube from the connectivity table of the
+ *     data-storage section: {1,0,2,4} {3,1,2,4} {3,5,1,4} {3,6,5,4}
+ *     {3,2,6,4} {3,7,5,6}.
+ *  4. Signed volume V = (v1 - v0) . ((v2 - v0) x (v3 - v0)) / 6
+ *     (Eq. Eqn:TetVolume); V == 0 is skipped and counted; density
+ *     rho = m / |V| with tetrahedron mass m = M / (6 * cubes).
+ *  5. Orthographic view: y = R (x - c), rows of R = (screen u, screen v,
+ *     view direction).  Pixel centres at u = -Su/2 + (ix + 1/2) Su / W.
+ *  6. Each pixel ray {(pu, pv, t)} is clipped against the four outward face
+ *     planes n . y <= h; dl = max(0, t_exit - t_entry).  A face parallel to
+ *     the ray (n_d == 0) excludes the ray when h - n_u pu - n_v pv < 0; on
+ *     the plane itself the ray is kept iff n_u < 0, or n_u == 0 and n_v < 0
+ *     (a half-open rule, so exactly one of two face-sharing tets keeps it).
+ *  7. I += rho * dl with Neumaier-compensated FP64 sums.  With image wrap
+ *     the pixel index is taken modulo (W, H); otherwise pixels outside the
+ *     window are dropped.
+ *
+ * Determinism: region mode assigns every image row band to one thread and
+ * visits tetrahedra in id order, so results do not depend on the thread
+ * count.  Pixel-sample mode keeps per-thread partial sums and adds them in
+ * thread order (deterministic for a fixed thread count).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+
+typedef struct {
+    int32_t dims[3];      /* vertices per axis */
+    double box[3];        /* periodic box lengths */
+    int32_t periodic;     /* 1: d0*d1*d2 cubes with wrap; 0: (d0-1)(d1-1)(d2-1) */
+    double total_mass;    /* M */
+    double rot[9];        /* row-major view rotation */
+    double center[3];     /* world point at the image centre */
+    double extent[2];     /* window size (u, v) */
+    int32_t width, height;
+    int32_t wrap;         /* pixel index modulo (W, H) */
+} orc_problem;
+
+typedef struct {
+    int64_t tets;         /* tetrahedra with V != 0 */
+    int64_t zero_volume;  /* skipped, V == 0 */
+    int64_t inverted;     /* V > 0 (the undisplaced lattice has V < 0) */
+    int64_t fragments;    /* (pixel, tet) pairs with dl > 0 inside the target */
+} orc_stats;
+
+static const int TET_TABLE[6][4] = {
+    {1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
+
+typedef struct {
+    double rho;
+    double n[4][3];       /* outward normals in view space */
+    double h[4];          /* plane offsets, n . y <= h inside */
+    int64_t ix0, ix1, iy0, iy1;  /* candidate pixel range (inclusive, unwrapped) */
+} orc_tet;
+
+/* ---------------------------------------------------------------- helpers */
+static inline void neu_add(double *s, double *c, double x) {
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x))
+        *c += (*s - t) + x;
+    else
+        *c += (x - t) + *s;
+    *s = t;
+}
+
+static inline int64_t imod(int64_t a, int64_t m) {
+    int64_t r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+static int64_t n_cubes(const orc_problem *P) {
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) c[a] = P->periodic ? P->dims[a] : P->dims[a] - 1;
+    return c[0] * c[1] * c[2];
+}
+
+static int check_problem(const orc_problem *P) {
+    if (!P) return ORC_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        if (P->dims[a] < 2) return ORC_EINVAL;
+        if (!(P->box[a] > 0)) return ORC_EINVAL;
+    }
+    if (P->width < 1 || P->height < 1) return ORC_EINVAL;
+    if (!(P->extent[0] > 0) || !(P->extent[1] > 0)) return ORC_EINVAL;
+    if (!(P->total_mass > 0)) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* Corner positions (world, unwrapped to the periodic image nearest corner 0)
+ * of lattice cube `cube` (cube id = i + c0 (j + c1 k) over the cube grid). */
+static void cube_corners(const orc_problem *P, const float *x, const float *y,
+                         const float *z, int64_t cube, double X[8][3]) {
+    int64_t c0 = P->periodic ? P->dims[0] : P->dims[0] - 1;
+    int64_t c1 = P->periodic ? P->dims[1] : P->dims[1] - 1;
+    int64_t i = cube % c0, j = (cube / c0) % c1, k = cube / (c0 * c1);
+    for (int n = 0; n < 8; ++n) {
+        int64_t ii = i + (n & 1), jj = j + ((n >> 1) & 1), kk = k + ((n >> 2) & 1);
+        if (P->periodic) {
+            ii = imod(ii, P->dims[0]);
+            jj = imod(jj, P->dims[1]);
+            kk = imod(kk, P->dims[2]);
+        }
+        int64_t id = ii + (int64_t)P->dims[0] * (jj + (int64_t)P->dims[1] * kk);
+        X[n][0] = (double)x[id];
+        X[n][1] = (double)y[id];
+        X[n][2] = (double)z[id];
+    }
+    if (P->periodic) {
+        for (int n = 1; n < 8; ++n)
+            for (int a = 0; a < 3; ++a) {
+                double e = X[n][a] - X[0][a];
+                e -= P->box[a] * ceil(e / P->box[a] - 0.5);
+                X[n][a] = X[0][a] + e;
+            }
+    }
+}
+
+static double signed_volume(const double v[4][3]) {
+    double a[3], b[3], c[3];
+    for (int q = 0; q < 3; ++q) {
+        a[q] = v[1][q] - v[0][q];
+        b[q] = v[2][q] - v[0][q];
+        c[q] = v[3][q] - v[0][q];
+    }
+    double cx = b[1] * c[2] - b[2] * c[1];
+    double cy = b[2] * c[0] - b[0] * c[2];
+    double cz = b[0] * c[1] - b[1] * c[0];
+    return (a[0] * cx + a[1] * cy + a[2] * cz) / 6.0;
+}
+
+/* Build the view-space clip description of one tetrahedron.  Returns 0 when
+ * the tetrahedron is skipped (V == 0), 1 otherwise; *V receives the volume. */
+static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
+                     orc_tet *t, double *V) {
+    *V = signed_volume(v);
+    if (*V == 0.0) return 0;
+    t->rho = mass / fabs(*V);
+    double yv[4][3];
+    for (int m = 0; m < 4; ++m) {
+        double d[3] = {v[m][0] - P->center[0], v[m][1] - P->center[1], v[m][2] - P->center[2]};
+        for (int r = 0; r < 3; ++r)
+            yv[m][r] = P->rot[3 * r] * d[0] + P->rot[3 * r + 1] * d[1] + P->rot[3 * r + 2] * d[2];
+    }
+    for (int a = 0; a < 4; ++a) {
+        int b = (a + 1) & 3, c = (a + 2) & 3, d = (a + 3) & 3;
+        double e1[3], e2[3], ea[3];
+        for (int q = 0; q < 3; ++q) {
+            e1[q] = yv[c][q] - yv[b][q];
+            e2[q] = yv[d][q] - yv[b][q];
+            ea[q] = yv[a][q] - yv[b][q];
+        }
+        double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                        e1[0] * e2[1] - e1[1] * e2[0]};
+        double side = nn[0] * ea[0] + nn[1] * ea[1] + nn[2] * ea[2];
+        if (side > 0) { nn[0] = -nn[0]; nn[1] = -nn[1]; nn[2] = -nn[2]; }
+        t->n[a][0] = nn[0]; t->n[a][1] = nn[1]; t->n[a][2] = nn[2];
+        t->h[a] = nn[0] * yv[b][0] + nn[1] * yv[b][1] + nn[2] * yv[b][2];
+    }
+    double umin = yv[0][0], umax = yv[0][0], vmin = yv[0][1], vmax = yv[0][1];
+    for (int m = 1; m < 4; ++m) {
+        if (yv[m][0] < umin) umin = yv[m][0];
+        if (yv[m][0] > umax) umax = yv[m][0];
+        if (yv[m][1] < vmin) vmin = yv[m][1];
+        if (yv[m][1] > vmax) vmax = yv[m][1];
+    }
+    double du = P->extent[0] / P->width, dv = P->extent[1] / P->height;
+    double ul = -0.5 * P->extent[0], vb = -0.5 * P->extent[1];
+    /* pixel centres inside [umin, umax], widened by one pixel on each side;
+     * the clip itself decides the boundary pixels */
+    t->ix0 = (int64_t)ceil((umin - ul) / du - 0.5) - 1;
+    t->ix1 = (int64_t)floor((umax - ul) / du - 0.5) + 1;
+    t->iy0 = (int64_t)ceil((vmin - vb) / dv - 0.5) - 1;
+    t->iy1 = (int64_t)floor((vmax - vb) / dv - 0.5) + 1;
+    return 1;
+}
+
+/* Length of the ray at pixel centre (pu, pv) inside the tetrahedron. */
+static double clip_dl(const orc_tet *t, double pu, double pv) {
+    double lo = -INFINITY, hi = INFINITY;
+    for (int f = 0; f < 4; ++f) {
+        double nd = t->n[f][2];
+        double s = t->h[f] - t->n[f][0] * pu - t->n[f][1] * pv;
+        if (nd > 0) {
+            double q = s / nd;
+            if (q < hi) hi = q;
+        } else if (nd < 0) {
+            double q = s / nd;
+            if (q > lo) lo = q;
+        } else {
+            if (s < 0) return 0.0;
+            if (s == 0 && !(t->n[f][0] < 0 || (t->n[f][0] == 0 && t->n[f][1] < 0))) return 0.0;
+        }
+    }
+    if (!(hi > lo) || isinf(lo) || isinf(hi)) return 0.0;
+    return hi - lo;
+}
+
+static inline double pixel_u(const orc_problem *P, int64_t ix) {
+    return -0.5 * P->extent[0] + ((double)ix + 0.5) * (P->extent[0] / P->width);
+}
+static inline double pixel_v(const orc_problem *P, int64_t iy) {
+    return -0.5 * P->extent[1] + ((double)iy + 0.5) * (P->extent[1] / P->height);
+}
+
+/* Map an unwrapped pixel index to the image; -1 when it falls outside. */
+static inline int64_t map_col(const orc_problem *P, int64_t ix) {
+    if (P->wrap) return imod(ix, P->width);
+    return (ix >= 0 && ix < P->width) ? ix : -1;
+}
+static inline int64_t map_row(const orc_problem *P, int64_t iy) {
+    if (P->wrap) return imod(iy, P->height);
+    return (iy >= 0 && iy < P->height) ? iy : -1;
+}
+
+/* ------------------------------------------------------------ public API */
+
+int orc_version(void) { return 1; }
+
+/* Volumes of the six tetrahedra of one cube and their unwrapped vertices
+ * (world coordinates), for connectivity checks.  verts: 6*4*3 doubles. */
+int orc_cube_tets(const orc_problem *P, const float *x, const float *y, const float *z,
+                  int64_t cube, double *verts, double *vols) {
+    if (check_problem(P) != ORC_OK || !x || !y || !z) return ORC_EINVAL;
+    if (cube < 0 || cube >= n_cubes(P)) return ORC_EINVAL;
+    double X[8][3];
+    cube_corners(P, x, y, z, cube, X);
+    for (int t = 0; t < 6; ++t) {
+        double v[4][3];
+        for (int m = 0; m < 4; ++m)
+            for (int q = 0; q < 3; ++q) {
+                v[m][q] = X[TET_TABLE[t][m]][q];
+                if (verts) verts[(t * 4 + m) * 3 + q] = v[m][q];
+            }
+        if (vols) vols[t] = signed_volume(v);
+    }
+    return ORC_OK;
+}
+
+/* Per-tet projection of an explicit list of tetrahedra (world vertices,
+ * tet-major [T][4][3]) with per-tet masses; the lattice fields of P are
+ * ignored.  out: H*W doubles, overwritten.  Serial, in list order. */
+int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
+                     const double *mass, double *out, orc_stats *st) {
+    if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0))
+        return ORC_EINVAL;
+    if (ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out) return ORC_EINVAL;
+    int64_t npx = (int64_t)P->width * P->height;
+    double *comp = (double *)calloc((size_t)npx, sizeof(double));
+    if (!comp) return ORC_ENOMEM;
+    memset(out, 0, sizeof(double) * (size_t)npx);
+    orc_stats s = {0, 0, 0, 0};
+    for (int64_t t = 0; t < ntet; ++t) {
+        double v[4][3];
+        memcpy(v, verts + t * 12, sizeof(v));
+        orc_tet tt;
+        double V;
+        if (!tet_setup(P, v, mass[t], &tt, &V)) { s.zero_volume++; continue; }
+        s.tets++;
+        if (V > 0) s.inverted++;
+        for (int64_t iy = tt.iy0; iy <= tt.iy1; ++iy) {
+            int64_t ry = map_row(P, iy);
+            if (ry < 0) continue;
+            double pv = pixel_v(P, iy);
+            for (int64_t ix = tt.ix0; ix <= tt.ix1; ++ix) {
+                int64_t rx = map_col(P, ix);
+                if (rx < 0) continue;
+                double dl = clip_dl(&tt, pixel_u(P, ix), pv);
+                if (dl > 0) {
+                    s.fragments++;
+                    neu_add(&out[ry * P->width + rx], &comp[ry * P->width + rx], tt.rho * dl);
+                }
+            }
+        }
+    }
+    for (int64_t p = 0; p < npx; ++p) out[p] += comp[p];
+    free(comp);
+    if (st) *st = s;
+    return ORC_OK;
+}
+
+/* Region mode: the image rectangle [cx0, cx0+cw) x [cy0, cy0+ch) of the
+ * full projection.  out: ch*cw doubles, row-major, overwritten. */
+int orc_project_region(const orc_problem *P, const float *x, const float *y, const float *z,
+                       int32_t cx0, int32_t cy0, int32_t cw, int32_t ch, double *out,
+                       orc_stats *st, int32_t nthreads) {
+    if (check_problem(P) != ORC_OK || !x || !y || !z || !out) return ORC_EINVAL;
+    if (cx0 < 0 || cy0 < 0 || cw < 1 || ch < 1 || cx0 + cw > P->width || cy0 + ch > P->height)
+        return ORC_EINVAL;
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    const int64_t ncube = n_cubes(P);
+    const int64_t ntet = 6 * ncube;
+    const double mass = P->total_mass / (double)ntet;
+    const int BH = 4; /* rows per band */
+    const int64_t nband = (ch + BH - 1) / BH;
+
+    /* pass 1: candidate row range of every tetrahedron */
+    int32_t *r0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntet);
+    int32_t *r1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntet);
+    if (!r0 || !r1) { free(r0); free(r1); return ORC_ENOMEM; }
+    int64_t zero_v = 0, inv = 0, live = 0;
+#pragma omp parallel for schedule(static) num_threads(nthreads) reduction(+ : zero_v, inv, live)
+    for (int64_t c = 0; c < ncube; ++c) {
+        double X[8][3];
+        cube_corners(P, x, y, z, c, X);
+        for (int t = 0; t < 6; ++t) {
+            double v[4][3];
+            for (int m = 0; m < 4; ++m)
+                for (int q = 0; q < 3; ++q) v[m][q] = X[TET_TABLE[t][m]][q];
+            orc_tet tt;
+            double V;
+            int64_t id = 6 * c + t;
+            if (!tet_setup(P, v, mass, &tt, &V)) {
+                zero_v++;
+                r0[id] = 1; r1[id] = 0;
+                continue;
+            }
+            live++;
+            if (V > 0) inv++;
+            r0[id] = (int32_t)tt.iy0;
+            r1[id] = (int32_t)tt.iy1;
+        }
+    }
+
+    /* band lists in tet-id order (each tet at most once per band) */
+    int64_t *cnt = (int64_t *)calloc((size_t)nband + 1, sizeof(int64_t));
+    int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)nband);
+    if (!cnt || !stamp) { free(r0); free(r1); free(cnt); free(stamp); return ORC_ENOMEM; }
+    for (int64_t b = 0; b < nband; ++b) stamp[b] = -1;
+#define FOR_TET_BANDS(BODY)                                                   \
+    for (int64_t id = 0; id < ntet; ++id) {                                   \
+        if (r0[id] > r1[id]) continue;                                        \
+        for (int64_t iy = r0[id]; iy <= r1[id]; ++iy) {                       \
+            int64_t ry = map_row(P, iy);                                      \
+            if (ry < cy0 || ry >= cy0 + ch) continue;                         \
+            int64_t b = (ry - cy0) / BH;                                      \
+            if (stamp[b] == id) continue;                                     \
+            stamp[b] = id;                                                    \
+            BODY                                                              \
+        }                                                                     \
+    }
+    FOR_TET_BANDS(cnt[b + 1]++;)
+    for (int64_t b = 0; b < nband; ++b) cnt[b + 1] += cnt[b];
+    int64_t npair = cnt[nband];
+    int64_t *lst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npair > 0 ? npair : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)nband);
+    if (!lst || !fill) {
+        free(r0); free(r1); free(cnt); free(stamp); free(lst); free(fill);
+        return ORC_ENOMEM;
+    }
+    for (int64_t b = 0; b < nband; ++b) { fill[b] = cnt[b]; stamp[b] = -1; }
+    FOR_TET_BANDS(lst[fill[b]++] = id;)
+#undef FOR_TET_BANDS
+    free(fill);
+    free(stamp);
+
+    /* pass 2: every band, tetrahedra in id order */
+    double *comp = (double *)calloc((size_t)cw * ch, sizeof(double));
+    if (!comp) { free(r0); free(r1); free(cnt); free(lst); return ORC_ENOMEM; }
+    memset(out, 0, sizeof(double) * (size_t)cw * ch);
+    int64_t frags = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : frags)
+    for (int64_t b = 0; b < nband; ++b) {
+        int64_t row_lo = cy0 + b * BH, row_hi = cy0 + (b + 1) * BH;
+        if (row_hi > cy0 + ch) row_hi = cy0 + ch;
+        int64_t last_cube = -1;
+        double X[8][3];
+        for (int64_t e = cnt[b]; e < cnt[b + 1]; ++e) {
+            int64_t id = lst[e];
+            int64_t c = id / 6;
+            int t = (int)(id % 6);
+            if (c != last_cube) { cube_corners(P, x, y, z, c, X); last_cube = c; }
+            double v[4][3];
+            for (int m = 0; m < 4; ++m)
+                for (int q = 0; q < 3; ++q) v[m][q] = X[TET_TABLE[t][m]][q];
+            orc_tet tt;
+            double V;
+            if (!tet_setup(P, v, mass, &tt, &V)) continue;
+            for (int64_t iy = tt.iy0; iy <= tt.iy1; ++iy) {
+                int64_t ry = map_row(P, iy);
+                if (ry < row_lo || ry >= row_hi) continue;
+                double pv = pixel_v(P, iy);
+                for (int64_t ix = tt.ix0; ix <= tt.ix1; ++ix) {
+                    int64_t rx = map_col(P, ix);
+                    if (rx < cx0 || rx >= cx0 + cw) continue;
+                    double dl = clip_dl(&tt, pixel_u(P, ix), pv);
+                    if (dl > 0) {
+                        frags++;
+                        int64_t o = (ry - cy0) * cw + (rx - cx0);
+                        neu_add(&out[o], &comp[o], tt.rho * dl);
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t p = 0; p < (int64_t)cw * ch; ++p) out[p] += comp[p];
+    free(comp);
+    free(r0); free(r1); free(cnt); free(lst);
+    if (st) {
+        st->tets = live;
+        st->zero_volume = zero_v;
+        st->inverted = inv;
+        st->fragments = frags;
+    }
+    return ORC_OK;
+}
+
+/* Pixel-sample mode: the projection at n listed pixels (px[s], py[s]),
+ * each 0 <= px < W, 0 <= py < H.  out: n doubles. */
+typedef struct { int32_t row, col, idx; } orc_sample;
+
+static int cmp_sample(const void *a, const void *b) {
+    const orc_sample *p = (const orc_sample *)a, *q = (const orc_sample *)b;
+    if (p->row != q->row) return p->row < q->row ? -1 : 1;
+    if (p->col != q->col) return p->col < q->col ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx);
+}
+
+int orc_project_pixels(const orc_problem *P, const float *x, const float *y, const float *z,
+                       int64_t n, const int32_t *px, const int32_t *py, double *out,
+                       orc_stats *st, int32_t nthreads) {
+    if (check_problem(P) != ORC_OK || !x || !y || !z || !out || n < 0) return ORC_EINVAL;
+    if (n > 0 && (!px || !py)) return ORC_EINVAL;
+    for (int64_t s = 0; s < n; ++s)
+        if (px[s] < 0 || px[s] >= P->width || py[s] < 0 || py[s] >= P->height) return ORC_EINVAL;
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+    orc_sample *smp = (orc_sample *)malloc(sizeof(orc_sample) * (size_t)(n > 0 ? n : 1));
+    if (!smp) return ORC_ENOMEM;
+    for (int64_t s = 0; s < n; ++s) { smp[s].row = py[s]; smp[s].col = px[s]; smp[s].idx = (int32_t)s; }
+    qsort(smp, (size_t)n, sizeof(orc_sample), cmp_sample);
+    /* first sample index of every image row */
+    int64_t *rowstart = (int64_t *)malloc(sizeof(int64_t) * ((size_t)P->height + 1));
+    double *acc = (double *)calloc((size_t)nthreads * (size_t)(n > 0 ? n : 1) * 2, sizeof(double));
+    if (!rowstart || !acc) { free(smp); free(rowstart); free(acc); return ORC_ENOMEM; }
+    {
+        int64_t s = 0;
+        for (int64_t r = 0; r <= P->height; ++r) {
+            while (s < n && smp[s].row < r) ++s;
+            rowstart[r] = s;
+        }
+    }
+    const int64_t ncube = n_cubes(P);
+    const double mass = P->total_mass / (double)(6 * ncube);
+    int64_t zero_v = 0, inv = 0, live = 0, frags = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : zero_v, inv, live, frags)
+    {
+        int tid = omp_get_thread_num();
+        double *a = acc + (size_t)tid * (size_t)(n > 0 ? n : 1) * 2;
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < ncube; ++c) {
+            double X[8][3];
+            cube_corners(P, x, y, z, c, X);
+            for (int t = 0; t < 6; ++t) {
+                double v[4][3];
+                for (int m = 0; m < 4; ++m)
+                    for (int q = 0; q < 3; ++q) v[m][q] = X[TET_TABLE[t][m]][q];
+                orc_tet tt;
+                double V;
+                if (!tet_setup(P, v, mass, &tt, &V)) { zero_v++; continue; }
+                live++;
+                if (V > 0) inv++;
+                for (int64_t iy = tt.iy0; iy <= tt.iy1; ++iy) {
+                    int64_t ry = map_row(P, iy);
+                    if (ry < 0) continue;
+                    if (rowstart[ry] == rowstart[ry + 1]) continue;
+                    double pv = pixel_v(P, iy);
+                    for (int64_t s = rowstart[ry]; s < rowstart[ry + 1]; ++s) {
+                        int64_t col = smp[s].col;
+                        /* every unwrapped column of the tet that lands on col */
+                        int64_t first = P->wrap ? tt.ix0 + imod(col - tt.ix0, P->width) : col;
+                        int64_t stride = P->wrap ? P->width : (int64_t)1 << 40;
+                        for (int64_t ix = first; ix <= tt.ix1; ix += stride) {
+                            if (ix < tt.ix0) continue;
+                            double dl = clip_dl(&tt, pixel_u(P, ix), pv);
+                            if (dl > 0) {
+                                frags++;
+                                neu_add(&a[2 * smp[s].idx], &a[2 * smp[s].idx + 1], tt.rho * dl);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t s = 0; s < n; ++s) {
+        double sum = 0, cmp = 0;
+        for (int th = 0; th < nthreads; ++th) {
+            const double *a = acc + (size_t)th * (size_t)(n > 0 ? n : 1) * 2;
+            neu_add(&sum, &cmp, a[2 * s]);
+            neu_add(&sum, &cmp, a[2 * s + 1]);
+        }
+        out[s] = sum + cmp;
+    }
+    free(smp); free(rowstart); free(acc);
+    if (st) {
+        st->tets = live;
+        st->zero_volume = zero_v;
+        st->inverted = inv;
+        st->fragments = frags;
+    }
+    return ORC_OK;
+}

@@ -1,0 +1,351 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against a closed form, an invariant or brute
+force derived independently (``closed_forms.py``), chosen so that a plausible
+slip in the oracle (a corner numbering, a table entry, a sign, a dropped face,
+the unwrap, the pixel-centre convention, the wrap logic) fails one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from closed_forms import (TET_TABLE, cube_chord, lattice_tets, points_in_tets,
+                          signed_volumes, tent_value)
+
+
+def corner_xyz(n):
+    return np.array([[(c & 1), (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.float64)
+
+
+# ---------------------------------------------------------------- C1: table
+def test_c1_undisplaced_volumes_equal_and_negative():
+    # Table {1,0,2,4} ... {3,7,5,6} with corners n = a + 2b + 4c: six tets of
+    # equal volume Delta^3/6, all with the same (negative) orientation.
+    n = 4  # spacing exact in FP32
+    x, y, z = W.undisplaced(n)
+    for cube in (0, 21, 63):
+        _, vols = O.cube_tets(x, y, z, (n, n, n), cube)
+        np.testing.assert_allclose(vols, -(1.0 / n) ** 3 / 6.0, rtol=1e-12, atol=0)
+
+
+def test_c1_tets_tile_the_cube_without_overlap():
+    n = 2
+    x, y, z = W.undisplaced(n)
+    verts, vols = O.cube_tets(x, y, z, (n, n, n), 0)
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(0.0, 0.5, size=(20000, 3))
+    inside = points_in_tets(pts, verts)
+    assert np.all(inside.sum(axis=1) == 1)
+    assert abs(np.abs(vols).sum() - 0.5 ** 3) < 1e-15
+
+
+def test_c1_face_diagonals_match_neighbours():
+    # Boundary triangles on opposite cube faces coincide after translation,
+    # so neighbouring cubes share their face diagonals (no cracks).
+    C = corner_xyz(1)
+    for axis in range(3):
+        sets = {0: set(), 1: set()}
+        for t in TET_TABLE:
+            for drop in range(4):
+                face = [t[m] for m in range(4) if m != drop]
+                coord = C[face, axis]
+                if np.all(coord == coord[0]):
+                    key = tuple(sorted(tuple(np.delete(C[f], axis)) for f in face))
+                    sets[int(coord[0])].add(key)
+        assert len(sets[0]) == 2 and sets[0] == sets[1]
+
+
+def _hull_area(pts):
+    """Area of the convex hull of 2D points (monotone chain)."""
+    P = sorted(set(map(tuple, np.asarray(pts, dtype=np.float64))))
+    if len(P) < 3:
+        return 0.0
+
+    def half(seq):
+        h = []
+        for p in seq:
+            while len(h) >= 2 and ((h[-1][0] - h[-2][0]) * (p[1] - h[-2][1])
+                                   - (h[-1][1] - h[-2][1]) * (p[0] - h[-2][0])) <= 0:
+                h.pop()
+            h.append(p)
+        return h
+    hull = half(P)[:-1] + half(P[::-1])[:-1]
+    return 0.5 * abs(sum(hull[i][0] * hull[(i + 1) % len(hull)][1]
+                         - hull[(i + 1) % len(hull)][0] * hull[i][1] for i in range(len(hull))))
+
+
+def test_c1_z_projected_areas():
+    # z-projected silhouettes of the six undisplaced tets: 1/2, 1, 1/2, 1, 1/2,
+    # 1/2 of the unit square, 4 in total (each column crosses the cube in 4 tets'
+    # worth of silhouette, a fact the undisplaced constant-density pin relies on).
+    C = corner_xyz(1)
+    areas = [_hull_area(C[list(t), :2]) for t in TET_TABLE]
+    assert areas == [0.5, 1.0, 0.5, 1.0, 0.5, 0.5]
+
+
+# ------------------------------------------------- C2: single-tet closed form
+def _random_tets(rng, count, scale=0.3):
+    out = []
+    while len(out) < count:
+        v = rng.uniform(0.2, 0.8, size=(4, 3))
+        v = v.mean(axis=0) + (v - v.mean(axis=0)) * scale / 0.3
+        if abs(signed_volumes(v[None])[0]) > 1e-4:
+            out.append(v)
+    return np.array(out)
+
+
+def test_c2_single_tet_matches_tent_closed_form_z_view():
+    rng = np.random.default_rng(11)
+    view = W.rotated_view(np.eye(3), 48, 40, side=1.0, center=(0.5, 0.5, 0.5))
+    for v in _random_tets(rng, 25):
+        img, st = O.project_tets(v[None], [0.7], view)
+        jj, ii = np.mgrid[0:40, 0:48]
+        pu = -0.5 + (ii + 0.5) / 48.0
+        pv = -0.5 + (jj + 0.5) / 40.0
+        ref = tent_value(v[:, :2] - 0.5, 0.7, np.stack([pu.ravel(), pv.ravel()], 1)).reshape(40, 48)
+        np.testing.assert_allclose(img, ref, rtol=0, atol=1e-10 * ref.max())
+        assert st["tets"] == 1 and st["fragments"] == int((ref > 0).sum())
+
+
+def test_c2_single_tet_matches_tent_rotated_views():
+    rng = np.random.default_rng(12)
+    Rs = W.random_rotations(10, seed=77)
+    for v, R in zip(_random_tets(rng, 10), Rs):
+        view = W.rotated_view(R, 40, 36, side=1.6)
+        img, _ = O.project_tets(v[None], [1.3], view)
+        y = (v - 0.5) @ R.T
+        jj, ii = np.mgrid[0:36, 0:40]
+        pu = -0.8 + (ii + 0.5) * 1.6 / 40
+        pv = -0.8 + (jj + 0.5) * 1.6 / 36
+        ref = tent_value(y[:, :2], 1.3, np.stack([pu.ravel(), pv.ravel()], 1)).reshape(36, 40)
+        np.testing.assert_allclose(img, ref, rtol=0, atol=1e-10 * ref.max())
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 100])
+def test_c2_corner_tet_pixel_sum(n):
+    # Corner tet with legs of n pixels: sum of I * A_pix = m (1 - 1/n^2) exactly.
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+    view = W.rotated_view(np.eye(3), n, n, side=1.0, center=(0.5, 0.5, 0.5))
+    m = 0.25
+    img, _ = O.project_tets(v[None], [m], view)
+    total = img.sum() / (n * n)
+    assert math.isclose(total, m * (1 - 1.0 / n ** 2), rel_tol=1e-13)
+
+
+# ------------------------------------------------ C3: undisplaced lattice
+@pytest.mark.parametrize("n,w,h", [(2, 2, 4), (4, 16, 16), (4, 12, 20), (8, 24, 16)])
+def test_c3_undisplaced_column_density_is_one(n, w, h):
+    x, y, z = W.undisplaced(n)
+    img, st = O.project_region(x, y, z, (n, n, n), W.z_view(w, h))
+    np.testing.assert_allclose(img, 1.0, rtol=0, atol=1e-13)
+    assert st["tets"] == 6 * n ** 3 and st["inverted"] == 0
+
+
+def test_c3_tie_rule_rays_on_vertical_faces():
+    # Pixel centres on the lattice planes x = j/n (but not on any edge): the
+    # half-open rule must let exactly one of the two face-sharing tets count.
+    n = 4
+    x, y, z = W.undisplaced(n)
+    img, _ = O.project_region(x, y, z, (n, n, n), W.z_view(2, 10))
+    np.testing.assert_allclose(img, 1.0, rtol=0, atol=1e-13)
+
+
+def test_c3_rotated_view_equals_cube_chord():
+    d = 5  # non-periodic lattice of vertices at i/4 covering [0, 1]^3
+    r = np.arange(d) / (d - 1)
+    qz, qy, qx = np.meshgrid(r, r, r, indexing="ij")
+    x, y, z = (a.ravel().astype(np.float32) for a in (qx, qy, qz))
+    R = W.random_rotations(3, seed=9)
+    for rot in R:
+        view = W.rotated_view(rot, 24, 20, side=2.0)
+        img, st = O.project_region(x, y, z, (d, d, d), view, periodic=False)
+        ref = np.zeros_like(img)
+        for j in range(20):
+            for i in range(24):
+                pu = -1 + (i + 0.5) * 2 / 24
+                pv = -1 + (j + 0.5) * 2 / 20
+                origin = np.array([0.5, 0.5, 0.5]) + pu * rot[0] + pv * rot[1]
+                ref[j, i] = cube_chord(origin, rot[2])
+        np.testing.assert_allclose(img, ref, rtol=0, atol=1e-12)
+        assert st["tets"] == 6 * (d - 1) ** 3
+
+
+# --------------------------------------- C4: line-of-sight-only displacement
+def test_c4_z_only_displacement_keeps_column_density():
+    n = 8
+    q = W.lattice_q(n)
+    f = 0.25 * np.sin(2 * np.pi * q[:, 2]) * (1 + 0.5 * np.cos(2 * np.pi * q[:, 0])) \
+        + 0.1 * np.sin(2 * np.pi * (2 * q[:, 1] + q[:, 2]))
+    x = q[:, 0].astype(np.float32)
+    y = q[:, 1].astype(np.float32)
+    z = W.wrap_to_f32(q[:, 2] + f, 1.0)
+    img, st = O.project_region(x, y, z, (n, n, n), W.z_view(32, 24))
+    assert st["inverted"] > 0          # shell crossing happened
+    np.testing.assert_allclose(img, 1.0, rtol=0, atol=1e-11)
+
+
+def test_c4_near_degenerate_tets():
+    # z = q_z - A sin(2 pi q_z + phi): the first cell layer has thickness
+    # 1/n - 2 A sin(pi/n) = delta/n for A = (1 - delta)/(2 n sin(pi/n)),
+    # phi = -pi/n, so its tets are almost flat; the column density stays 1.
+    n, delta = 16, 1e-4
+    q = W.lattice_q(n)
+    A = (1 - delta) / (2 * n * np.sin(np.pi / n))
+    f = A * np.sin(2 * np.pi * q[:, 2] - np.pi / n)
+    z = W.wrap_to_f32(q[:, 2] - f, 1.0)
+    x = q[:, 0].astype(np.float32)
+    y = q[:, 1].astype(np.float32)
+    tets = lattice_tets(x, y, z, n)
+    V = np.abs(signed_volumes(tets))
+    assert V.min() < 1e-3 * V.mean()
+    img, st = O.project_region(x, y, z, (n, n, n), W.z_view(48, 32))
+    assert st["zero_volume"] == 0
+    np.testing.assert_allclose(img, 1.0, rtol=0, atol=1e-9)
+
+
+# ----------------------------------------------------------- C5: mass
+def test_c5_point_sampled_mass_converges():
+    x, y, z = W.random_lattice(4, 0.08, seed=3)
+    errs = []
+    for w in (16, 64, 256):
+        img, _ = O.project_region(x, y, z, (4, 4, 4), W.z_view(w))
+        errs.append(abs(img.mean() - 1.0))
+    assert errs[2] < errs[0] and errs[2] < 2e-3
+
+
+# ------------------------------------------------- C6: Monte Carlo on rays
+def test_c6_monte_carlo_along_rays():
+    n = 2
+    x, y, z = W.random_lattice(n, 0.12, seed=21)
+    tets = lattice_tets(x, y, z, n)
+    mass = 1.0 / len(tets)
+    rho = mass / np.abs(signed_volumes(tets))
+    imgs = []
+    for sx in (-1, 0, 1):
+        for sy in (-1, 0, 1):
+            imgs.append(tets + np.array([sx, sy, 0.0]))
+    tets9 = np.concatenate(imgs)
+    rho9 = np.tile(rho, 9)
+    wpx = 6
+    img, _ = O.project_region(x, y, z, (n, n, n), W.z_view(wpx))
+    rng = np.random.default_rng(4)
+    K = 6000
+    zlo, zhi = tets9[:, :, 2].min(), tets9[:, :, 2].max()
+    for (j, i) in [(0, 0), (2, 3), (5, 5), (1, 4)]:
+        pu, pv = (i + 0.5) / wpx, (j + 0.5) / wpx
+        t = rng.uniform(zlo, zhi, size=K)
+        pts = np.stack([np.full(K, pu), np.full(K, pv), t], axis=1)
+        dens = points_in_tets(pts, tets9).astype(np.float64) @ rho9
+        est = dens.mean() * (zhi - zlo)
+        sig = dens.std(ddof=1) / math.sqrt(K) * (zhi - zlo)
+        assert abs(est - img[j, i]) <= 4 * sig + 1e-12, (i, j, est, img[j, i], sig)
+
+
+# ----------------------------------------------- C7: brute force, all pairs
+def test_c7_brute_force_all_pairs_wrap():
+    n = 3
+    x, y, z = W.random_lattice(n, 0.1, seed=8)
+    tets = lattice_tets(x, y, z, n)
+    mass = 1.0 / len(tets)
+    w, h = 14, 9
+    img, st = O.project_region(x, y, z, (n, n, n), W.z_view(w, h))
+    jj, ii = np.mgrid[0:h, 0:w]
+    pts = np.stack([((ii + 0.5) / w).ravel(), ((jj + 0.5) / h).ravel()], 1)
+    ref = np.zeros(h * w)
+    frags = 0
+    for tv in tets:
+        for sx in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                val = tent_value(tv[:, :2] + np.array([sx, sy]), mass, pts)
+                ref += val
+                frags += int((val > 0).sum())
+    np.testing.assert_allclose(img.ravel(), ref, rtol=1e-10, atol=0)
+    assert st["fragments"] == frags
+
+
+def test_c7_brute_force_all_pairs_rotated_no_wrap():
+    n = 3
+    x, y, z = W.random_lattice(n, 0.1, seed=9)
+    tets = lattice_tets(x, y, z, n)
+    mass = 1.0 / len(tets)
+    R = W.random_rotations(1, seed=5)[0]
+    w, h = 17, 13
+    view = W.rotated_view(R, w, h, side=1.4)
+    img, _ = O.project_region(x, y, z, (n, n, n), view)
+    jj, ii = np.mgrid[0:h, 0:w]
+    pts = np.stack([(-0.7 + (ii + 0.5) * 1.4 / w).ravel(), (-0.7 + (jj + 0.5) * 1.4 / h).ravel()], 1)
+    ref = np.zeros(h * w)
+    for tv in tets:
+        yv = (tv - 0.5) @ R.T
+        ref += tent_value(yv[:, :2], mass, pts)
+    np.testing.assert_allclose(img.ravel(), ref, rtol=1e-10, atol=1e-12)
+
+
+# ------------------------------------------------- C9: order independence
+def test_c9_order_independence():
+    n = 4
+    x, y, z = W.random_lattice(n, 0.15, seed=12)
+    tets = lattice_tets(x, y, z, n)
+    view = W.rotated_view(np.eye(3), 32, 32, side=1.0, center=(0.5, 0.5, 0.5))
+    m = np.full(len(tets), 1.0 / len(tets))
+    a, _ = O.project_tets(tets, m, view)
+    perm = np.random.default_rng(1).permutation(len(tets))
+    b, _ = O.project_tets(tets[perm], m, view)
+    np.testing.assert_allclose(a, b, rtol=1e-13, atol=0)
+
+
+def test_region_mode_is_thread_count_independent(tiny_lattice):
+    x, y, z = tiny_lattice
+    v = W.z_view(96, 80)
+    a, sa = O.project_region(x, y, z, (32, 32, 32), v, nthreads=1)
+    b, sb = O.project_region(x, y, z, (32, 32, 32), v, nthreads=5)
+    assert np.array_equal(a, b) and sa == sb
+
+
+# ------------------------------------------------------- C10: dyadic shift
+def test_c10_dyadic_shift_is_cyclic_shift():
+    n, w = 8, 64
+    x, y, z = W.zeldovich(n, 3, 2.0)
+    x = (np.round(x.astype(np.float64) * 2 ** 24) / 2 ** 24).astype(np.float32)
+    x[x >= 1] -= 1
+    k = 5
+    xs = x.astype(np.float64) + k / w
+    xs[xs >= 1] -= 1
+    xs = xs.astype(np.float32)
+    assert np.array_equal(xs.astype(np.float64), np.mod(x.astype(np.float64) + k / w, 1.0))
+    a, _ = O.project_region(x, y, z, (n, n, n), W.z_view(w))
+    b, _ = O.project_region(xs, y, z, (n, n, n), W.z_view(w))
+    np.testing.assert_allclose(np.roll(a, k, axis=1), b, rtol=1e-12, atol=0)
+
+
+# ------------------------------------------ mode consistency and edge cases
+def test_pixel_and_crop_modes_agree_with_full_image(tiny_lattice):
+    x, y, z = tiny_lattice
+    v = W.z_view(128, 96)
+    full, st = O.project_region(x, y, z, (32, 32, 32), v)
+    crop, _ = O.project_region(x, y, z, (32, 32, 32), v, crop=(100, 7, 28, 40))
+    np.testing.assert_allclose(crop, full[7:47, 100:128], rtol=1e-14, atol=0)
+    rng = np.random.default_rng(0)
+    px = rng.integers(0, 128, 300)
+    py = rng.integers(0, 96, 300)
+    vals, _ = O.project_pixels(x, y, z, (32, 32, 32), v, px, py)
+    np.testing.assert_allclose(vals, full[py, px], rtol=1e-14, atol=0)
+    assert st["fragments"] > 0
+
+
+def test_single_pixel_image_and_minimum_lattice():
+    x, y, z = W.random_lattice(2, 0.05, seed=2)
+    img, st = O.project_region(x, y, z, (2, 2, 2), W.z_view(1, 1))
+    assert img.shape == (1, 1) and np.isfinite(img).all() and st["tets"] == 48
+
+
+def test_invalid_arguments_rejected():
+    x, y, z = W.undisplaced(2)
+    bad = W.z_view(0)
+    with pytest.raises(RuntimeError):
+        O.project_region(x, y, z, (2, 2, 2), bad)
+    with pytest.raises(RuntimeError):
+        O.project_region(x, y, z, (1, 2, 2), W.z_view(4))

@@ -1,0 +1,198 @@
+/*
+ * tess.h -- C ABI of the MI355X phase-space-tessellation projector.
+ *
+ * The library renders column-density images of a dark-matter particle
+ * lattice by the tetrahedral phase-space tessellation (Kaehler, Hahn & Abel,
+ * arXiv:1208.3206).  Tracers sit on an implicit Lagrangian lattice (tracer
+ * id = i + d0 (j + d1 k), Eq. Eqn:ID); every lattice cube is cut into six
+ * tetrahedra by the connectivity table of the data-storage section; each
+ * tetrahedron carries the constant mass m and density rho = m / |V|
+ * (Eqs. Eqn:TetVolume, Eqn-rho_loc); a pixel accumulates, over all
+ * tetrahedra its ray crosses, rho times the length of the ray inside the
+ * tetrahedron (Eq. Eqn:TetProjection, the column density of the density
+ * projections subsection).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns a tess_status; 0 is success.  On failure a
+ *    message is available from tess_last_error() (thread-local; valid until
+ *    the next call on the same thread).  No C++ exception crosses the ABI.
+ *  - Device pointers are HIP device memory of the current device, owned by
+ *    the caller unless stated otherwise.  Host pointers are plain host
+ *    memory.  Streams are hipStream_t passed as void* (NULL = null stream).
+ *  - Calls are asynchronous on the given stream unless stated otherwise.
+ *  - Images are float32, row-major [height][width]; row iy holds the pixel
+ *    centres v = -Sv/2 + (iy + 1/2) Sv/height, column ix the centres
+ *    u = -Su/2 + (ix + 1/2) Su/width, where (u, v) are screen coordinates
+ *    relative to the view centre.
+ */
+#ifndef TESS_H
+#define TESS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TESS_OK = 0,
+    TESS_EINVAL = -1,     /* an argument is invalid (message names it)          */
+    TESS_ENOMEM = -2,     /* device or host allocation failed                    */
+    TESS_EHIP = -3,       /* a HIP runtime call failed (message has its text)    */
+    TESS_ENOTSUP = -4,    /* valid but unsupported configuration                 */
+    TESS_ECAPACITY = -5,  /* a fixed capacity (tiles, image size) was exceeded   */
+    TESS_ERANGE = -6      /* a value does not fit the representation in use      */
+} tess_status;
+
+/* Arithmetic of the raster.  In both modes the per-tetrahedron footprint
+ * setup runs in FP64 and the volume determinant in FP32, redone in FP64 for
+ * tetrahedra flagged as near-degenerate. */
+enum {
+    TESS_PREC_FP32 = 0,   /* FP32 per-fragment arithmetic with FP32 block sums
+                             folded into FP64; footprints whose FP32 evaluation
+                             is ill-conditioned (fp64_cond) are rastered in FP64 */
+    TESS_PREC_FP64 = 1    /* every footprint rastered in FP64 (comparison path)  */
+};
+
+typedef struct tess_lattice_s *tess_lattice;   /* opaque; release with tess_free */
+
+typedef struct {
+    int32_t dims[3];        /* tracers per axis (d0, d1, d2), each >= 2             */
+    double box[3];          /* periodic box lengths L, > 0                           */
+    int32_t periodic;       /* 1: d0 d1 d2 cubes, lattice and positions periodic
+                               (corners taken modulo d, each corner moved to the
+                               periodic image nearest corner 0 of its cube, offset
+                               in (-L/2, L/2]); 0: (d0-1)(d1-1)(d2-1) cubes, the
+                               positions used as given                           */
+    double total_mass;      /* M; every tetrahedron has mass M / (6 cubes)        */
+    int32_t precision;      /* TESS_PREC_FP32 or TESS_PREC_FP64                    */
+    double det_v0_frac;     /* FP64 determinant when |V32| < det_v0_frac * V0,
+                               V0 = box volume / (6 cubes), the mean volume       */
+    double det_cond_k;      /* ... or when |V32| < det_cond_k * 2^-24 * P, where P
+                               is the sum of the magnitudes of the six products
+                               of the triple product (a forward error bound)      */
+    double fp64_cond;       /* TESS_PREC_FP32 only: a footprint whose FP32 error
+                               amplification (largest sum of |terms| of a footprint
+                               function over its pixel box, divided by the apex
+                               value) exceeds this is rastered in FP64; INFINITY
+                               keeps every footprint in FP32                      */
+    int32_t copy_positions; /* 0: keep the caller's x, y, z pointers (they must
+                               outlive the handle); 1: library-owned copy         */
+} tess_build_desc;
+
+/* Fills a descriptor with the defaults: periodic, unit box, total mass 1,
+ * TESS_PREC_FP32, det_v0_frac 1e-6, det_cond_k 1e3, fp64_cond 256, no copy.  dims are set
+ * to 0 and must be filled in.  Host only; never fails for a non-null desc. */
+tess_status tess_build_desc_default(tess_build_desc *desc);
+
+/*
+ * Creates a lattice handle over tracer positions (Eq. Eqn:ID).
+ *   x, y, z : device float32 arrays of d0 d1 d2 positions.  Without ids they
+ *             are in tracer-id order.  With ids, entry s belongs to tracer
+ *             ids[s] (a permutation of 0 .. d0 d1 d2 - 1, device uint64) and
+ *             the library stores an id-ordered copy (copy_positions implied).
+ * Validates on the device that every position is finite and, with ids, that
+ * ids is a permutation; this call synchronises `stream` once.
+ * Errors: TESS_EINVAL (null pointer, dims < 2, box <= 0, mass <= 0, a
+ * non-finite position -- the message names the first bad tracer id --, ids
+ * not a permutation), TESS_ENOMEM, TESS_EHIP.
+ */
+tess_status tess_build(const tess_build_desc *desc, const float *x, const float *y,
+                       const float *z, const uint64_t *ids, void *stream, tess_lattice *out);
+
+/* Releases a handle (and the positions it owns).  NULL is accepted. */
+void tess_free(tess_lattice lat);
+
+/* Orthographic view (the paper's parallel projection of the tetrahedra). */
+typedef struct {
+    double rot[9];          /* row-major; rows = screen u, screen v, view direction;
+                               must be orthonormal (|R R^T - I| <= 1e-9)          */
+    double center[3];       /* world point at the image centre                    */
+    double extent[2];       /* window size (Su, Sv) in world units, > 0           */
+    int32_t width, height;  /* pixels, 1 .. 16384 each                            */
+    int32_t wrap;           /* 1: periodic image (pixel index modulo width/height);
+                               requires rot to be an axis permutation with signs,
+                               a periodic lattice and extent equal to the box
+                               lengths along screen u and v                      */
+} tess_view;
+
+/* Raster parameters.  0 in a field means "choose automatically". */
+typedef struct {
+    int32_t tile;           /* screen tile edge in pixels: 16, 32 or 64           */
+    int32_t chunk;          /* tile-list entries per raster work item (>= 64)     */
+    int32_t count_fragments;/* 1: fill tess_stats.fragments (costs raster time)   */
+} tess_tune;
+
+typedef struct {
+    uint64_t tets;          /* tetrahedra with V != 0                             */
+    uint64_t zero_volume;   /* tetrahedra skipped because V == 0                  */
+    uint64_t inverted;      /* tetrahedra with V > 0 (undisplaced ones have V < 0) */
+    uint64_t fp64_dets;     /* volume determinants recomputed in FP64             */
+    uint64_t fp64_tets;     /* footprints rastered in FP64                        */
+    uint64_t degenerate;    /* |V| < det_v0_frac * V0                             */
+    uint64_t fragments;     /* (pixel, tetrahedron) pairs with rho*dl > 0, when
+                               tune->count_fragments is set (else 0)              */
+    uint64_t fragments4;    /* ... of them, from quadrilateral silhouettes        */
+    uint64_t bin_pairs;     /* (tile, tetrahedron) pairs after culling            */
+    uint32_t max_bin;       /* longest tile list                                  */
+    uint32_t work_items;    /* raster work items                                  */
+    int32_t tile, chunk;    /* parameters used                                    */
+    float ms;               /* device time of the call, milliseconds              */
+    float setup_ms;         /* setup kernel                                       */
+    float bin_ms;           /* count + scan + plan + items + scatter              */
+    float raster_ms;        /* raster kernel                                      */
+    float finalize_ms;      /* finalize kernel                                    */
+} tess_stats;
+
+/*
+ * Projects the lattice onto `image` (device float32 [height][width],
+ * overwritten).  Each pixel receives
+ *     sum over tetrahedra T of (m / |V(T)|) * |ray(pixel centre) inside T|
+ * (Eq. Eqn:TetProjection with q = rho_loc of Eq. Eqn-rho_loc), every periodic
+ * image of T counted when view->wrap is set.  Tetrahedra with V == 0 are
+ * skipped.
+ *   tune  : host, nullable (automatic choice).
+ *   stats : host, nullable; when non-null the call times its kernels with
+ *           HIP events on `stream`, synchronises it and returns the counters
+ *           (fragments only with tune->count_fragments).
+ * The call synchronises the stream once internally to size its workspace
+ * (the number of tile-tetrahedron pairs depends on the data).  The library
+ * owns and reuses the workspace; concurrent calls on one handle must use
+ * different streams and output buffers.
+ * Errors: TESS_EINVAL (null handle/view/image, a view that fails the checks
+ * above), TESS_ECAPACITY (more than 8192 tiles), TESS_ENOMEM, TESS_EHIP.
+ */
+tess_status tess_project(tess_lattice lat, const tess_view *view, const tess_tune *tune,
+                         float *image, tess_stats *stats, void *stream);
+
+/*
+ * Projects n_snaps lattices (same dims) through n_views views of the same
+ * width/height into images laid out [n_snaps][n_views][height][width]
+ * (device float32).  The view-independent per-tetrahedron work runs once per
+ * snapshot.  tune may be NULL (autotune once per shape, then cached).
+ * stats (host, nullable) receives the sums over all images.
+ * Errors: as tess_project; views of different sizes -> TESS_EINVAL.
+ */
+tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_snaps,
+                               const tess_view *views, int32_t n_views,
+                               const tess_tune *tune, float *images, tess_stats *stats,
+                               void *stream);
+
+/* Host-only validation of a view against a lattice description, the same
+ * checks tess_project performs; usable without a GPU.  desc may be NULL
+ * (then the wrap/lattice consistency checks are skipped). */
+tess_status tess_check_view(const tess_view *view, const tess_build_desc *desc);
+
+/* Host-only validation of a build descriptor; usable without a GPU. */
+tess_status tess_check_build_desc(const tess_build_desc *desc);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *tess_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t tess_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TESS_H */

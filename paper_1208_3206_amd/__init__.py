@@ -1,0 +1,263 @@
+"""Python binding of the MI355X tessellation projector (libtess.so).
+
+Argument marshalling only: every step of the projection runs in the HIP
+kernels of ``libtess.so``; this module turns torch tensors into device
+pointers and the current torch stream into a HIP stream, and calls the C ABI
+declared in ``include/tess.h`` under the same names.  PyTorch is used for
+device memory and streams only.
+
+Importing this package loads the compiled library and fails loudly if it is
+missing; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtess.so")
+
+TESS_OK, TESS_EINVAL, TESS_ENOMEM, TESS_EHIP, TESS_ENOTSUP, TESS_ECAPACITY, TESS_ERANGE = (
+    0, -1, -2, -3, -4, -5, -6)
+PREC_FP32, PREC_FP64 = 0, 1
+_STATUS = {0: "TESS_OK", -1: "TESS_EINVAL", -2: "TESS_ENOMEM", -3: "TESS_EHIP",
+           -4: "TESS_ENOTSUP", -5: "TESS_ECAPACITY", -6: "TESS_ERANGE"}
+
+
+class TessBuildDesc(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3), ("box", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int32), ("total_mass", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("det_v0_frac", ctypes.c_double),
+                ("det_cond_k", ctypes.c_double), ("fp64_cond", ctypes.c_double),
+                ("copy_positions", ctypes.c_int32)]
+
+
+class TessView(ctypes.Structure):
+    _fields_ = [("rot", ctypes.c_double * 9), ("center", ctypes.c_double * 3),
+                ("extent", ctypes.c_double * 2), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("wrap", ctypes.c_int32)]
+
+
+class TessTune(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("count_fragments", ctypes.c_int32)]
+
+
+class TessStats(ctypes.Structure):
+    _fields_ = [("tets", ctypes.c_uint64), ("zero_volume", ctypes.c_uint64),
+                ("inverted", ctypes.c_uint64), ("fp64_dets", ctypes.c_uint64),
+                ("fp64_tets", ctypes.c_uint64),
+                ("degenerate", ctypes.c_uint64), ("fragments", ctypes.c_uint64),
+                ("fragments4", ctypes.c_uint64),
+                ("bin_pairs", ctypes.c_uint64), ("max_bin", ctypes.c_uint32),
+                ("work_items", ctypes.c_uint32), ("tile", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("setup_ms", ctypes.c_float), ("bin_ms", ctypes.c_float),
+                ("raster_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float)]
+
+    def as_dict(self) -> Dict:
+        return {k: (float(getattr(self, k)) if k.endswith("ms") else int(getattr(self, k)))
+                for k, _ in self._fields_}
+
+
+class TessError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.tess_build_desc_default.argtypes = [P(TessBuildDesc)]
+    L.tess_build.argtypes = [P(TessBuildDesc), vp, vp, vp, vp, vp, P(vp)]
+    L.tess_free.argtypes = [vp]
+    L.tess_free.restype = None
+    L.tess_project.argtypes = [vp, P(TessView), P(TessTune), vp, P(TessStats), vp]
+    L.tess_project_batch.argtypes = [P(vp), ctypes.c_int32, P(TessView), ctypes.c_int32,
+                                     P(TessTune), vp, P(TessStats), vp]
+    L.tess_check_view.argtypes = [P(TessView), P(TessBuildDesc)]
+    L.tess_check_build_desc.argtypes = [P(TessBuildDesc)]
+    L.tess_last_error.argtypes = []
+    L.tess_last_error.restype = ctypes.c_char_p
+    L.tess_version.argtypes = []
+    L.tess_version.restype = ctypes.c_int32
+    for f in (L.tess_build_desc_default, L.tess_build, L.tess_project, L.tess_project_batch,
+              L.tess_check_view, L.tess_check_build_desc):
+        f.restype = ctypes.c_int
+    return L
+
+
+_lib = _load()
+
+# names exported by the C ABI (checked against include/tess.h by the tests)
+EXPORTS = ("tess_build_desc_default", "tess_build", "tess_free", "tess_project",
+           "tess_project_batch", "tess_check_view", "tess_check_build_desc",
+           "tess_last_error", "tess_version")
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.tess_last_error().decode()
+
+
+def version() -> int:
+    return int(_lib.tess_version())
+
+
+def _check(rc: int, where: str):
+    if rc != TESS_OK:
+        raise TessError(rc, where, last_error())
+
+
+# ------------------------------------------------------------ descriptors
+def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
+               total_mass: float = 1.0, precision: str = "fp32", det_v0_frac: float = 1e-6,
+               det_cond_k: float = 1e3, fp64_cond: float = 256.0,
+               copy_positions: bool = False) -> TessBuildDesc:
+    d = TessBuildDesc()
+    _check(_lib.tess_build_desc_default(ctypes.byref(d)), "tess_build_desc_default")
+    for a in range(3):
+        d.dims[a] = int(dims[a])
+        d.box[a] = float(box[a])
+    d.periodic = 1 if periodic else 0
+    d.total_mass = float(total_mass)
+    d.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
+    d.det_v0_frac = float(det_v0_frac)
+    d.det_cond_k = float(det_cond_k)
+    d.fp64_cond = float(fp64_cond)
+    d.copy_positions = 1 if copy_positions else 0
+    return d
+
+
+def make_view(view: Dict) -> TessView:
+    """Converts a view dict (rot, center, extent, width, height, wrap) to the C struct."""
+    v = TessView()
+    for i in range(9):
+        v.rot[i] = float(view["rot"][i])
+    for i in range(3):
+        v.center[i] = float(view["center"][i])
+    v.extent[0], v.extent[1] = float(view["extent"][0]), float(view["extent"][1])
+    v.width, v.height = int(view["width"]), int(view["height"])
+    v.wrap = 1 if view.get("wrap", 0) else 0
+    return v
+
+
+def make_tune(tile: int = 0, chunk: int = 0, count_fragments: bool = False) -> TessTune:
+    t = TessTune()
+    t.tile, t.chunk = int(tile), int(chunk)
+    t.count_fragments = 1 if count_fragments else 0
+    return t
+
+
+def check_view(view: Dict, desc: Optional[TessBuildDesc] = None):
+    """Host-only validation of a view (no GPU needed); raises TessError."""
+    v = make_view(view)
+    _check(_lib.tess_check_view(ctypes.byref(v), ctypes.byref(desc) if desc is not None else None),
+           "tess_check_view")
+
+
+def check_build_desc(desc: TessBuildDesc):
+    _check(_lib.tess_check_build_desc(ctypes.byref(desc)), "tess_check_build_desc")
+
+
+# ---------------------------------------------------------------- handles
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_f32(t, n: int, name: str):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous CUDA float32 tensor of {n} elements")
+    return t
+
+
+class Lattice:
+    """A lattice handle (tess_build).  Keeps the position tensors alive."""
+
+    def __init__(self, x, y, z, dims: Sequence[int], ids=None, stream=None, **desc_kw):
+        import torch
+        self.desc = build_desc(dims, **desc_kw)
+        n = int(dims[0]) * int(dims[1]) * int(dims[2])
+        self._tensors = [_dev_f32(x, n, "x"), _dev_f32(y, n, "y"), _dev_f32(z, n, "z")]
+        if ids is not None:
+            if not (isinstance(ids, torch.Tensor) and ids.is_cuda and ids.dtype == torch.int64
+                    and ids.is_contiguous() and ids.numel() == n):
+                raise ValueError("ids must be a contiguous CUDA int64 tensor")
+            self._tensors.append(ids)
+        h = ctypes.c_void_p()
+        rc = _lib.tess_build(ctypes.byref(self.desc), x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                             ids.data_ptr() if ids is not None else None, _stream_handle(stream),
+                             ctypes.byref(h))
+        _check(rc, "tess_build")
+        self.handle = h
+        self.dims = tuple(int(d) for d in dims)
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _lib.tess_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(x, y, z, dims: Sequence[int], ids=None, stream=None, **desc_kw) -> Lattice:
+    return Lattice(x, y, z, dims, ids=ids, stream=stream, **desc_kw)
+
+
+def project(lat: Lattice, view: Dict, out=None, tune: Optional[TessTune] = None,
+            stats: bool = False, stream=None):
+    """Column-density image (float32 CUDA tensor [H, W]); with stats, also a dict
+    (fragments are counted too unless a tune without count_fragments is given)."""
+    import torch
+    v = make_view(view)
+    if stats and tune is None:
+        tune = make_tune(count_fragments=True)
+    if out is None:
+        out = torch.empty((v.height, v.width), dtype=torch.float32, device="cuda")
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+            and out.numel() == v.width * v.height):
+        raise ValueError("out must be a contiguous CUDA float32 tensor of height*width elements")
+    st = TessStats()
+    rc = _lib.tess_project(lat.handle, ctypes.byref(v), ctypes.byref(tune) if tune is not None else None,
+                           out.data_ptr(), ctypes.byref(st) if stats else None, _stream_handle(stream))
+    _check(rc, "tess_project")
+    return (out, st.as_dict()) if stats else out
+
+
+def project_batch(lats: List[Lattice], views: List[Dict], out=None, tune: Optional[TessTune] = None,
+                  stats: bool = False, stream=None):
+    """Images [n_snaps, n_views, H, W] of every (snapshot, view) pair."""
+    import torch
+    vs = (TessView * len(views))(*[make_view(v) for v in views])
+    hs = (ctypes.c_void_p * len(lats))(*[l.handle for l in lats])
+    H, W = vs[0].height, vs[0].width
+    if out is None:
+        out = torch.empty((len(lats), len(views), H, W), dtype=torch.float32, device="cuda")
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+            and out.numel() == len(lats) * len(views) * H * W):
+        raise ValueError("out has the wrong shape or type")
+    st = TessStats()
+    rc = _lib.tess_project_batch(hs, len(lats), vs, len(views),
+                                 ctypes.byref(tune) if tune is not None else None, out.data_ptr(),
+                                 ctypes.byref(st) if stats else None, _stream_handle(stream))
+    _check(rc, "tess_project_batch")
+    return (out, st.as_dict()) if stats else out

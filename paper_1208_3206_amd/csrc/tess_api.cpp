@@ -1,0 +1,543 @@
+// C ABI of the tessellation projector: argument validation, lattice handles,
+// workspace management and the per-call kernel pipeline.
+#include "../../include/tess.h"
+#include "tess_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+using namespace tess;
+
+// ----------------------------------------------------------------- errors
+namespace {
+thread_local std::string g_error;
+
+tess_status fail(tess_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+tess_status ok() {
+    g_error.clear();
+    return TESS_OK;
+}
+
+#define TESS_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? TESS_ENOMEM : TESS_EHIP, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+bool finite3(const double *v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+constexpr int kMaxTiles = 8192;
+constexpr int kMaxSide = 16384;
+}  // namespace
+
+// --------------------------------------------------------------- handles
+struct tess_lattice_s {
+    tess_build_desc desc;
+    const float *x, *y, *z;
+    float *owned;  // one allocation holding x, y, z when the library owns them
+    int device;
+    int64_t n;
+};
+
+// ------------------------------------------------------------- workspace
+namespace {
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;  // elements
+    hipError_t ensure(size_t n) {
+        if (n <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max(n, (size_t)64);
+        want += want / 8;  // headroom against small growth steps
+        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        cap = want;
+        return hipSuccess;
+    }
+};
+
+struct Workspace {
+    DevBuf<TetRec> rec;
+    DevBuf<Coef64> coef64;
+    DevBuf<uint32_t> counts;
+    DevBuf<uint64_t> base;
+    DevBuf<uint64_t> scan;
+    DevBuf<uint32_t> tile_items;
+    DevBuf<WorkItem> items;
+    DevBuf<uint32_t> pairs;
+    DevBuf<double> partials;
+    DevBuf<PlanOut> plan;
+    DevBuf<DevCounters> counters;
+    PlanOut *host_plan = nullptr;       // pinned
+    DevCounters *host_counters = nullptr;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::mutex mu;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+
+tess_status get_workspace(int device, hipStream_t s, Workspace **out) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto key = std::make_pair(device, s);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end()) {
+        *out = it->second;
+        return TESS_OK;
+    }
+    Workspace *w = new Workspace();
+    TESS_HIP(hipHostMalloc((void **)&w->host_plan, sizeof(PlanOut), hipHostMallocDefault));
+    TESS_HIP(hipHostMalloc((void **)&w->host_counters, sizeof(DevCounters), hipHostMallocDefault));
+    for (int i = 0; i < 6; ++i) TESS_HIP(hipEventCreate(&w->ev[i]));
+    g_ws[key] = w;
+    *out = w;
+    return TESS_OK;
+}
+}  // namespace
+
+// ------------------------------------------------------------ validation
+extern "C" tess_status tess_build_desc_default(tess_build_desc *d) {
+    if (!d) return fail(TESS_EINVAL, "tess_build_desc_default: desc is NULL");
+    std::memset(d, 0, sizeof(*d));
+    d->box[0] = d->box[1] = d->box[2] = 1.0;
+    d->periodic = 1;
+    d->total_mass = 1.0;
+    d->precision = TESS_PREC_FP32;
+    d->det_v0_frac = 1e-6;
+    d->det_cond_k = 1e3;
+    d->fp64_cond = 256.0;
+    d->copy_positions = 0;
+    return ok();
+}
+
+extern "C" tess_status tess_check_build_desc(const tess_build_desc *d) {
+    if (!d) return fail(TESS_EINVAL, "build desc is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->dims[a] < 2) return fail(TESS_EINVAL, "dims[%d] = %d: need at least 2 tracers per axis", a, d->dims[a]);
+        if (!(d->box[a] > 0) || !std::isfinite(d->box[a]))
+            return fail(TESS_EINVAL, "box[%d] must be positive and finite", a);
+    }
+    const double n = (double)d->dims[0] * d->dims[1] * d->dims[2];
+    if (n > 2147483647.0 / 6.0 * 4.0)  // tetrahedron ids are 32-bit
+        return fail(TESS_ECAPACITY, "lattice of %.0f tracers exceeds the 32-bit tetrahedron id range", n);
+    if (!(d->total_mass > 0) || !std::isfinite(d->total_mass))
+        return fail(TESS_EINVAL, "total_mass must be positive and finite");
+    if (d->precision != TESS_PREC_FP32 && d->precision != TESS_PREC_FP64)
+        return fail(TESS_EINVAL, "precision must be TESS_PREC_FP32 or TESS_PREC_FP64");
+    if (!(d->det_v0_frac >= 0) || !std::isfinite(d->det_v0_frac))
+        return fail(TESS_EINVAL, "det_v0_frac must be finite and >= 0");
+    if (!(d->det_cond_k >= 0) || !std::isfinite(d->det_cond_k))
+        return fail(TESS_EINVAL, "det_cond_k must be finite and >= 0");
+    if (!(d->fp64_cond >= 0) || std::isnan(d->fp64_cond))
+        return fail(TESS_EINVAL, "fp64_cond must be >= 0 (infinity disables FP64 footprints)");
+    if (d->periodic != 0 && d->periodic != 1) return fail(TESS_EINVAL, "periodic must be 0 or 1");
+    return ok();
+}
+
+extern "C" tess_status tess_check_view(const tess_view *v, const tess_build_desc *d) {
+    if (!v) return fail(TESS_EINVAL, "view is NULL");
+    if (!finite3(v->rot, 9) || !finite3(v->center, 3) || !finite3(v->extent, 2))
+        return fail(TESS_EINVAL, "view has a non-finite field");
+    if (!(v->extent[0] > 0) || !(v->extent[1] > 0)) return fail(TESS_EINVAL, "view extent must be positive");
+    if (v->width < 1 || v->height < 1 || v->width > kMaxSide || v->height > kMaxSide)
+        return fail(TESS_EINVAL, "image %d x %d outside 1..%d", v->width, v->height, kMaxSide);
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s) {
+            double dot = 0;
+            for (int c = 0; c < 3; ++c) dot += v->rot[3 * r + c] * v->rot[3 * s + c];
+            if (std::fabs(dot - (r == s ? 1.0 : 0.0)) > 1e-9)
+                return fail(TESS_EINVAL, "view rotation is not orthonormal (rows %d, %d)", r, s);
+        }
+    if (v->wrap != 0 && v->wrap != 1) return fail(TESS_EINVAL, "wrap must be 0 or 1");
+    if (v->wrap) {
+        int axis[2];
+        for (int r = 0; r < 2; ++r) {
+            axis[r] = -1;
+            for (int c = 0; c < 3; ++c) {
+                const double e = v->rot[3 * r + c];
+                if (std::fabs(std::fabs(e) - 1.0) == 0.0) axis[r] = c;
+                else if (e != 0.0)
+                    return fail(TESS_EINVAL, "wrap needs an axis-aligned view (row %d of rot is not a signed unit axis)", r);
+            }
+            if (axis[r] < 0) return fail(TESS_EINVAL, "wrap needs an axis-aligned view");
+        }
+        if (d) {
+            if (!d->periodic) return fail(TESS_EINVAL, "wrap needs a periodic lattice");
+            for (int r = 0; r < 2; ++r) {
+                const double L = d->box[axis[r]];
+                if (std::fabs(v->extent[r] - L) > 1e-12 * L)
+                    return fail(TESS_EINVAL, "wrap needs extent[%d] == box length %.17g", r, L);
+            }
+        }
+    }
+    return ok();
+}
+
+// --------------------------------------------------------------- build
+extern "C" tess_status tess_build(const tess_build_desc *desc, const float *x, const float *y,
+                                  const float *z, const uint64_t *ids, void *stream,
+                                  tess_lattice *out) {
+    if (!out) return fail(TESS_EINVAL, "out is NULL");
+    *out = nullptr;
+    tess_status st = tess_check_build_desc(desc);
+    if (st != TESS_OK) return st;
+    if (!x || !y || !z) return fail(TESS_EINVAL, "position pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)desc->dims[0] * desc->dims[1] * desc->dims[2];
+    int dev = 0;
+    TESS_HIP(hipGetDevice(&dev));
+    for (const float *p : {x, y, z}) {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();
+            return fail(TESS_EINVAL, "positions must be device memory");
+        }
+    }
+    tess_lattice L = new tess_lattice_s();
+    L->desc = *desc;
+    L->device = dev;
+    L->n = n;
+    L->owned = nullptr;
+    L->x = x;
+    L->y = y;
+    L->z = z;
+    unsigned long long *flag = nullptr;
+    unsigned int *seen = nullptr;
+    auto cleanup = [&](tess_status rc) {
+        if (flag) (void)hipFree(flag);
+        if (seen) (void)hipFree(seen);
+        if (rc != TESS_OK) tess_free(L);
+        return rc;
+    };
+    if (ids || desc->copy_positions) {
+        hipError_t e = hipMalloc((void **)&L->owned, sizeof(float) * 3 * (size_t)n);
+        if (e != hipSuccess) return cleanup(fail(TESS_ENOMEM, "positions copy: %s", hipGetErrorString(e)));
+        float *ox = L->owned, *oy = L->owned + n, *oz = L->owned + 2 * n;
+        if (hipMalloc((void **)&flag, sizeof(unsigned long long)) != hipSuccess)
+            return cleanup(fail(TESS_ENOMEM, "flag allocation failed"));
+        unsigned long long none = ~0ull;
+        if (hipMemcpyAsync(flag, &none, sizeof(none), hipMemcpyHostToDevice, s) != hipSuccess)
+            return cleanup(fail(TESS_EHIP, "flag upload failed"));
+        if (ids) {
+            if (hipMalloc((void **)&seen, sizeof(unsigned int) * (size_t)n) != hipSuccess)
+                return cleanup(fail(TESS_ENOMEM, "id check allocation failed"));
+            if (hipMemsetAsync(seen, 0, sizeof(unsigned int) * (size_t)n, s) != hipSuccess ||
+                launch_scatter_ids(x, y, z, ids, n, ox, oy, oz, seen, flag, s) != hipSuccess)
+                return cleanup(fail(TESS_EHIP, "id scatter failed"));
+        } else {
+            if (hipMemcpyAsync(ox, x, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(oy, y, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(oz, z, sizeof(float) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return cleanup(fail(TESS_EHIP, "position copy failed"));
+        }
+        unsigned long long bad = 0;
+        if (hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return cleanup(fail(TESS_EHIP, "id check readback failed"));
+        if (bad != ~0ull)
+            return cleanup(fail(TESS_EINVAL, "ids is not a permutation of 0..%lld (entry %llu)",
+                                (long long)n - 1, bad));
+        L->x = ox;
+        L->y = oy;
+        L->z = oz;
+    }
+    // every position finite
+    if (!flag && hipMalloc((void **)&flag, sizeof(unsigned long long)) != hipSuccess)
+        return cleanup(fail(TESS_ENOMEM, "flag allocation failed"));
+    unsigned long long none = ~0ull, bad = 0;
+    if (hipMemcpyAsync(flag, &none, sizeof(none), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_check_finite(L->x, L->y, L->z, n, flag, s) != hipSuccess ||
+        hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(fail(TESS_EHIP, "finite check failed"));
+    if (bad != ~0ull)
+        return cleanup(fail(TESS_EINVAL, "position of tracer id %llu is not finite", bad));
+    cleanup(TESS_OK);
+    *out = L;
+    return ok();
+}
+
+extern "C" void tess_free(tess_lattice L) {
+    if (!L) return;
+    if (L->owned) (void)hipFree(L->owned);
+    delete L;
+}
+
+// ------------------------------------------------------------ projection
+namespace {
+void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp, ViewParams &vp) {
+    const tess_build_desc &d = L->desc;
+    lp.x = L->x;
+    lp.y = L->y;
+    lp.z = L->z;
+    for (int a = 0; a < 3; ++a) {
+        lp.d[a] = d.dims[a];
+        lp.c[a] = d.periodic ? d.dims[a] : d.dims[a] - 1;
+        lp.box[a] = d.box[a];
+    }
+    lp.ncubes = (int64_t)lp.c[0] * lp.c[1] * lp.c[2];
+    lp.periodic = d.periodic;
+    lp.tet_mass = d.total_mass / (6.0 * (double)lp.ncubes);
+    lp.v0 = d.box[0] * d.box[1] * d.box[2] / (6.0 * (double)lp.ncubes);
+    lp.det_v0_frac = d.det_v0_frac;
+    lp.det_cond_k = d.det_cond_k;
+    lp.fp64_cond = d.precision == TESS_PREC_FP64 ? -1.0 : d.fp64_cond;
+    for (int i = 0; i < 9; ++i) vp.rot[i] = v->rot[i];
+    for (int i = 0; i < 3; ++i) vp.center[i] = v->center[i];
+    vp.u_left = -0.5 * v->extent[0];
+    vp.v_bottom = -0.5 * v->extent[1];
+    vp.inv_du = v->width / v->extent[0];
+    vp.inv_dv = v->height / v->extent[1];
+    vp.mass_px = 6.0 * lp.tet_mass * vp.inv_du * vp.inv_dv;
+    vp.W = v->width;
+    vp.H = v->height;
+    vp.wrap = v->wrap;
+}
+
+struct Plan {
+    int T, chunk;
+    bool count_fragments;
+};
+
+Plan choose_plan(const tess_view *v, const tess_tune *tune) {
+    Plan p;
+    p.T = (tune && tune->tile) ? tune->tile : 32;
+    if (!(tune && tune->tile)) {
+        const double tiles32 = std::ceil(v->width / 32.0) * std::ceil(v->height / 32.0);
+        if (tiles32 > kMaxTiles) p.T = 64;
+    }
+    p.chunk = (tune && tune->chunk) ? tune->chunk : 4096;
+    p.count_fragments = tune && tune->count_fragments;
+    return p;
+}
+
+tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan &plan, float *image,
+                         tess_stats *stats, hipStream_t s, Workspace &ws) {
+    LatticeParams lp;
+    ViewParams vp;
+    make_params(L, v, lp, vp);
+    const int64_t ntet = 6 * lp.ncubes;
+    BinParams B;
+    B.T = plan.T;
+    B.ntx = (v->width + plan.T - 1) / plan.T;
+    B.nty = (v->height + plan.T - 1) / plan.T;
+    B.W = v->width;
+    B.H = v->height;
+    B.wrap = v->wrap;
+    const int64_t ntiles = (int64_t)B.ntx * B.nty;
+    if (ntiles > kMaxTiles)
+        return fail(TESS_ECAPACITY, "%lld tiles of %d px exceed the limit of %d; use a larger tile",
+                    (long long)ntiles, plan.T, kMaxTiles);
+    // binning segments: enough for the device, few enough to keep the count matrix small
+    int64_t seg_len = 4096;
+    while ((ntet + seg_len - 1) / seg_len * ntiles > (int64_t)64 << 20) seg_len *= 2;
+    B.seg_len = (int32_t)seg_len;
+    B.nseg = (int32_t)((ntet + seg_len - 1) / seg_len);
+    if (B.nseg < 1) B.nseg = 1;
+    B.ntet = (uint32_t)ntet;
+    const int64_t nmat = ntiles * B.nseg;
+
+    TESS_HIP(ws.rec.ensure((size_t)ntet));
+    // FP64 footprints: all of them, or a fraction sized by the last call
+    size_t cap64 = lp.fp64_cond < 0 ? (size_t)ntet : std::max<size_t>(ws.coef64.cap, (size_t)ntet / 16 + 1024);
+    cap64 = std::min<size_t>(cap64, (size_t)ntet);
+    TESS_HIP(ws.coef64.ensure(cap64));
+    cap64 = std::min<size_t>(ws.coef64.cap, 0xfffffff0u);
+    TESS_HIP(ws.counts.ensure((size_t)nmat));
+    TESS_HIP(ws.base.ensure((size_t)nmat));
+    TESS_HIP(ws.scan.ensure(scan_scratch_elems(nmat)));
+    TESS_HIP(ws.tile_items.ensure((size_t)ntiles + 1));
+    TESS_HIP(ws.plan.ensure(1));
+    TESS_HIP(ws.counters.ensure(1));
+
+    if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
+    for (int attempt = 0;; ++attempt) {
+        TESS_HIP(hipMemsetAsync(ws.counters.p, 0, sizeof(DevCounters), s));
+        TESS_HIP(launch_setup(lp, vp, ws.rec.p, ws.coef64.p, (uint32_t)cap64, ws.counters.p, s));
+        if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
+        TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters),
+                                hipMemcpyDeviceToHost, s));
+        TESS_HIP(launch_count(ws.rec.p, ntet, B, ws.counts.p, s));
+        TESS_HIP(launch_scan(ws.counts.p, ws.base.p, nmat, ws.scan.p, s));
+        TESS_HIP(launch_plan(ws.counts.p, ws.base.p, B, plan.chunk, ws.tile_items.p, ws.plan.p, s));
+        TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
+        TESS_HIP(hipStreamSynchronize(s));
+        const unsigned long long used = ws.host_counters->coef64_used;
+        if (used <= cap64) break;
+        if (attempt > 0) return fail(TESS_ECAPACITY, "FP64 footprint slots overflowed twice");
+        TESS_HIP(ws.coef64.ensure((size_t)used));
+        cap64 = std::min<size_t>(ws.coef64.cap, 0xfffffff0u);
+    }
+    const PlanOut P = *ws.host_plan;
+    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(P.n_items, 1)));
+    TESS_HIP(ws.pairs.ensure((size_t)std::max<unsigned long long>(P.total_pairs, 1)));
+    TESS_HIP(ws.partials.ensure((size_t)std::max<unsigned long long>(P.n_items, 1) * plan.T * plan.T));
+    TESS_HIP(launch_items(ws.base.p, ws.tile_items.p, B, plan.chunk, P.total_pairs, ws.items.p, s));
+    TESS_HIP(launch_scatter(ws.rec.p, ntet, B, ws.base.p, ws.pairs.p, P.total_pairs, s));
+    if (stats) TESS_HIP(hipEventRecord(ws.ev[2], s));
+    TESS_HIP(launch_raster(ws.rec.p, ws.coef64.p, (uint32_t)cap64, ws.pairs.p, ws.items.p, P.n_items,
+                           B, ws.partials.p, ws.counters.p, plan.count_fragments, s));
+    if (stats) TESS_HIP(hipEventRecord(ws.ev[3], s));
+    TESS_HIP(launch_finalize(ws.partials.p, ws.tile_items.p, B, image, s));
+    if (stats) {
+        TESS_HIP(hipEventRecord(ws.ev[4], s));
+        TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters),
+                                hipMemcpyDeviceToHost, s));
+        TESS_HIP(hipStreamSynchronize(s));
+        float ms = 0, t_setup = 0, t_bin = 0, t_raster = 0, t_fin = 0;
+        TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
+        TESS_HIP(hipEventElapsedTime(&t_setup, ws.ev[0], ws.ev[1]));
+        TESS_HIP(hipEventElapsedTime(&t_bin, ws.ev[1], ws.ev[2]));
+        TESS_HIP(hipEventElapsedTime(&t_raster, ws.ev[2], ws.ev[3]));
+        TESS_HIP(hipEventElapsedTime(&t_fin, ws.ev[3], ws.ev[4]));
+        const DevCounters &c = *ws.host_counters;
+        stats->tets = c.tets;
+        stats->zero_volume = c.zero_volume;
+        stats->inverted = c.inverted;
+        stats->fp64_dets = c.fp64_dets;
+        stats->fp64_tets = c.fp64_tets;
+        stats->degenerate = c.degenerate;
+        stats->fragments = c.fragments;
+        stats->fragments4 = c.fragments4;
+        stats->bin_pairs = P.total_pairs;
+        stats->max_bin = (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull);
+        stats->work_items = (uint32_t)P.n_items;
+        stats->tile = plan.T;
+        stats->chunk = plan.chunk;
+        stats->ms = ms;
+        stats->setup_ms = t_setup;
+        stats->bin_ms = t_bin;
+        stats->raster_ms = t_raster;
+        stats->finalize_ms = t_fin;
+    }
+    return TESS_OK;
+}
+
+tess_status check_project_args(tess_lattice L, const tess_view *v, const tess_tune *tune, float *image) {
+    if (!L) return fail(TESS_EINVAL, "lattice handle is NULL");
+    if (!image) return fail(TESS_EINVAL, "image is NULL");
+    tess_status st = tess_check_view(v, &L->desc);
+    if (st != TESS_OK) return st;
+    if (tune) {
+        if (tune->tile != 0 && tune->tile != 16 && tune->tile != 32 && tune->tile != 64)
+            return fail(TESS_EINVAL, "tune.tile must be 0, 16, 32 or 64");
+        if (tune->chunk != 0 && tune->chunk < 64) return fail(TESS_EINVAL, "tune.chunk must be 0 or >= 64");
+    }
+    return TESS_OK;
+}
+
+tess_status project_one(tess_lattice L, const tess_view *v, const tess_tune *tune, float *image,
+                        tess_stats *stats, hipStream_t s) {
+    int dev = 0;
+    TESS_HIP(hipGetDevice(&dev));
+    if (dev != L->device) return fail(TESS_EINVAL, "lattice lives on device %d, current device is %d", L->device, dev);
+    Workspace *ws = nullptr;
+    tess_status st = get_workspace(dev, s, &ws);
+    if (st != TESS_OK) return st;
+    std::lock_guard<std::mutex> lock(ws->mu);
+    const Plan plan = choose_plan(v, tune);
+    return project_impl(L, v, plan, image, stats, s, *ws);
+}
+
+void add_stats(tess_stats &acc, const tess_stats &s) {
+    acc.tets += s.tets;
+    acc.zero_volume += s.zero_volume;
+    acc.inverted += s.inverted;
+    acc.fp64_dets += s.fp64_dets;
+    acc.fp64_tets += s.fp64_tets;
+    acc.degenerate += s.degenerate;
+    acc.fragments += s.fragments;
+    acc.fragments4 += s.fragments4;
+    acc.bin_pairs += s.bin_pairs;
+    acc.max_bin = std::max(acc.max_bin, s.max_bin);
+    acc.work_items += s.work_items;
+    acc.tile = s.tile;
+    acc.chunk = s.chunk;
+    acc.ms += s.ms;
+    acc.setup_ms += s.setup_ms;
+    acc.bin_ms += s.bin_ms;
+    acc.raster_ms += s.raster_ms;
+    acc.finalize_ms += s.finalize_ms;
+}
+}  // namespace
+
+extern "C" tess_status tess_project(tess_lattice L, const tess_view *v, const tess_tune *tune,
+                                    float *image, tess_stats *stats, void *stream) {
+    tess_status st = check_project_args(L, v, tune, image);
+    if (st != TESS_OK) return st;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    st = project_one(L, v, tune, image, stats, (hipStream_t)stream);
+    return st == TESS_OK ? ok() : st;
+}
+
+extern "C" tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_snaps,
+                                          const tess_view *views, int32_t n_views,
+                                          const tess_tune *tune, float *images, tess_stats *stats,
+                                          void *stream) {
+    if (!snaps || !views || !images) return fail(TESS_EINVAL, "NULL argument");
+    if (n_snaps < 1 || n_views < 1) return fail(TESS_EINVAL, "need at least one snapshot and one view");
+    for (int32_t s = 0; s < n_snaps; ++s) {
+        if (!snaps[s]) return fail(TESS_EINVAL, "snapshot %d is NULL", s);
+        for (int a = 0; a < 3; ++a)
+            if (snaps[s]->desc.dims[a] != snaps[0]->desc.dims[a])
+                return fail(TESS_EINVAL, "snapshot %d has different dims", s);
+    }
+    for (int32_t v = 0; v < n_views; ++v) {
+        if (views[v].width != views[0].width || views[v].height != views[0].height)
+            return fail(TESS_EINVAL, "view %d has a different image size", v);
+        for (int32_t s = 0; s < n_snaps; ++s) {
+            tess_status st = check_project_args(snaps[s], &views[v], tune, images);
+            if (st != TESS_OK) return st;
+        }
+    }
+    tess_stats acc;
+    std::memset(&acc, 0, sizeof(acc));
+    const size_t img = (size_t)views[0].width * views[0].height;
+    for (int32_t s = 0; s < n_snaps; ++s)
+        for (int32_t v = 0; v < n_views; ++v) {
+            tess_stats one;
+            tess_status st = project_one(snaps[s], &views[v], tune, images + ((size_t)s * n_views + v) * img,
+                                         stats ? &one : nullptr, (hipStream_t)stream);
+            if (st != TESS_OK) return st;
+            if (stats) add_stats(acc, one);
+        }
+    if (stats) *stats = acc;
+    return ok();
+}
+
+extern "C" const char *tess_last_error(void) { return g_error.c_str(); }
+
+extern "C" int32_t tess_version(void) { return 100; }

@@ -1,0 +1,141 @@
+// Internal declarations shared by the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tess {
+
+// Lattice and per-tetrahedron constants, all host-precomputed.
+struct LatticeParams {
+    const float *x, *y, *z;  // device, tracer-id order
+    int32_t d[3];            // tracers per axis
+    int32_t c[3];            // cubes per axis (d, or d - 1 when not periodic)
+    int64_t ncubes;
+    double box[3];
+    int32_t periodic;
+    double tet_mass;         // M / (6 cubes)
+    double v0;               // mean tetrahedron volume, box volume / (6 cubes)
+    double det_v0_frac;      // near-degenerate threshold (fraction of v0)
+    double det_cond_k;       // conditioning threshold on the FP32 determinant
+    double fp64_cond;        // footprints with a larger condition number raster in FP64 (< 0: all)
+};
+
+// View constants.  Pixel coordinates X = (u - u_left) * inv_du with pixel
+// centres at X = ix + 1/2; likewise Y for v.
+struct ViewParams {
+    double rot[9];
+    double center[3];
+    double u_left, v_bottom;
+    double inv_du, inv_dv;
+    double mass_px;          // 6 m * inv_du * inv_dv (density scale in pixel units)
+    int32_t W, H;
+    int32_t wrap;
+};
+
+// Screen tiling.
+struct BinParams {
+    int32_t T;               // tile edge (pixels)
+    int32_t ntx, nty;        // tiles per axis
+    int32_t W, H;
+    int32_t wrap;
+    int32_t seg_len;         // tetrahedra per binning segment
+    int32_t nseg;
+    uint32_t ntet;           // number of records
+};
+
+// Per-call device counters (atomically accumulated).
+struct DevCounters {
+    unsigned long long tets, zero_volume, inverted, fp64_dets, fp64_tets, degenerate, fragments;
+    unsigned long long fragments4;
+    unsigned long long coef64_used;   // FP64 coefficient slots handed out (may exceed capacity)
+};
+
+// Result of the binning plan, read back by the host to size the raster.
+struct PlanOut {
+    unsigned long long total_pairs;
+    unsigned long long n_items;
+    unsigned long long max_bin;
+    unsigned long long pad;
+};
+
+// Raster work item: a chunk of one tile's list.
+struct WorkItem {
+    uint64_t first;          // offset into the pair array
+    uint32_t count;          // entries
+    uint32_t tile;           // tile index ty * ntx + tx
+};
+
+// Per-tetrahedron raster record.  The footprint function is
+//   f(p) = [all walls admit p] * max(0, min_g G_g(p)),
+//   G(p) = c[3g] + c[3g+1] * x + c[3g+2] * y,   (x, y) = p - (bx0, by0)
+// with (x, y) in pixel units.  Walls follow the G functions in c[].  When
+// REC_FP64 is set the same coefficients in FP64 are in Coef64[slot] and the
+// raster evaluates them in FP64 (the FP32 copies are then only indicative).
+struct RecHead {
+    int16_t bx0, by0, bx1, by1;  // pixel-centre bounding box (inclusive)
+    uint32_t flags;
+    uint32_t slot;               // Coef64 index when REC_FP64
+};
+constexpr uint32_t REC_NG_MASK = 0x7u;        // number of G functions
+constexpr uint32_t REC_NW_SHIFT = 3;          // number of walls (2 bits)
+constexpr uint32_t REC_TIE0 = 1u << 5;        // wall 0 keeps pixels on its line
+constexpr uint32_t REC_TIE1 = 1u << 6;        // wall 1 keeps pixels on its line
+constexpr uint32_t REC_VALID = 1u << 7;       // some pixel centre may be covered
+constexpr uint32_t REC_FP64 = 1u << 8;        // raster this footprint in FP64
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
+struct alignas(16) TetRec {
+    RecHead h;
+    float c[12];
+};
+struct alignas(16) Coef64 {
+    double c[12];
+};
+static_assert(sizeof(TetRec) == 64, "record is one 64-byte line");
+static_assert(sizeof(Coef64) == 96, "FP64 coefficient block");
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `stream` and return the launch status.
+hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, TetRec *rec, Coef64 *coef64,
+                        uint32_t coef64_cap, DevCounters *counters, hipStream_t stream);
+
+hipError_t launch_count(const TetRec *rec, int64_t ntet, const BinParams &B, uint32_t *counts,
+                        hipStream_t stream);
+
+// Exclusive scan of counts[n] (uint32) into base[n] (uint64); scratch must
+// hold scan_scratch_elems(n) uint64.
+size_t scan_scratch_elems(int64_t n);
+hipError_t launch_scan(const uint32_t *counts, uint64_t *base, int64_t n, uint64_t *scratch,
+                       hipStream_t stream);
+
+// Per-tile chunking: writes tile_items[ntiles + 1] (exclusive scan of chunk
+// counts) and the PlanOut summary.
+hipError_t launch_plan(const uint32_t *counts, const uint64_t *base, const BinParams &B,
+                       int32_t chunk, uint32_t *tile_items, PlanOut *out, hipStream_t stream);
+
+hipError_t launch_items(const uint64_t *base, const uint32_t *tile_items, const BinParams &B,
+                        int32_t chunk, unsigned long long total_pairs, WorkItem *items,
+                        hipStream_t stream);
+
+// Writes beyond pair_cap entries are dropped (memory safety if the count and
+// scatter passes ever disagreed).
+hipError_t launch_scatter(const TetRec *rec, int64_t ntet, const BinParams &B, const uint64_t *base,
+                          uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream);
+
+hipError_t launch_raster(const TetRec *rec, const Coef64 *coef64, uint32_t coef64_cap,
+                         const uint32_t *pairs, const WorkItem *items, uint64_t n_items,
+                         const BinParams &B, double *partials, DevCounters *counters,
+                         bool count_fragments, hipStream_t stream);
+
+hipError_t launch_finalize(const double *partials, const uint32_t *tile_items,
+                           const BinParams &B, float *image, hipStream_t stream);
+
+// Build-time helpers.
+hipError_t launch_check_finite(const float *x, const float *y, const float *z, int64_t n,
+                               unsigned long long *first_bad, hipStream_t stream);
+hipError_t launch_scatter_ids(const float *x, const float *y, const float *z,
+                              const uint64_t *ids, int64_t n, float *ox, float *oy, float *oz,
+                              unsigned int *seen, unsigned long long *bad, hipStream_t stream);
+
+}  // namespace tess

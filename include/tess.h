@@ -178,6 +178,74 @@ tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_snaps,
                                const tess_tune *tune, float *images, tess_stats *stats,
                                void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned refinement.  A small network s(q) is fitted to the coarse
+ * lattice's own displacement field (Lagrangian point q on the unit torus ->
+ * s = x - q, minimal image, in box units):
+ *   g = [sin 2 pi B q, cos 2 pi B q] (B: 64 x 3 integers, so g is periodic),
+ *   four layers h = GELU(W h + b) of width 128 (exact erf GELU), s = W5 h + b5,
+ * loss = mean over samples of |s - target|^2, Adam (0.9, 0.999, 1e-8) with a
+ * cosine learning rate lr0 -> lr1, bf16 operands with FP32 accumulation and
+ * FP32 master weights.  The r-fold sub-lattice (r d tracers per axis) is
+ * then placed: coarse tracers keep their positions, the others get
+ * q + s(q).  TESS_REFINE_LINEAR instead places every fine tracer by the
+ * affine map of the coarse tetrahedron containing its Lagrangian point, so
+ * the fine tetrahedra nest inside the coarse ones and the projection is
+ * unchanged.  The paper's tessellation (data-storage section) is the one
+ * rendered; the network is an addition of this library.
+ * ---------------------------------------------------------------------- */
+#define TESS_MLP_PARAMS 66435   /* W1 (128x128), b1, ..., W4, b4, W5 (3x128), b5; W row = output */
+#define TESS_MLP_FREQS 64
+
+typedef enum { TESS_REFINE_LINEAR = 0, TESS_REFINE_MLP = 1 } tess_refine_mode;
+
+typedef struct {
+    int32_t r;              /* refinement factor, 1..16                            */
+    int32_t mode;           /* tess_refine_mode                                    */
+    int32_t steps;          /* training steps (0 with weights_in: no training)     */
+    int32_t batch;          /* samples per step (drawn with replacement, counter
+                               hash of seed + 1 and the step)                       */
+    double rff_sigma;       /* frequencies B = rint(N(0, rff_sigma^2)) when rff_B
+                               is NULL                                             */
+    double lr0, lr1;        /* learning rate, cosine-decayed over the steps         */
+    uint64_t seed;          /* initialisation and sampling seed                     */
+    const float *rff_B;     /* host, nullable: TESS_MLP_FREQS x 3 integer values     */
+    const float *weights_in;/* host, nullable: TESS_MLP_PARAMS initial parameters    */
+    float *weights_out;     /* host, nullable: trained parameters                   */
+} tess_refine_desc;
+
+typedef struct {
+    double loss_first, loss_last;   /* training loss at the first and last step   */
+    float train_ms, infer_ms;       /* wall time of training and of placement      */
+    int64_t fine_tracers;
+} tess_refine_report;
+
+/* Defaults: r 4, MLP, 3000 steps, batch 8192, sigma 8, lr 1e-3 -> 1e-5, seed 2. */
+tess_status tess_refine_desc_default(tess_refine_desc *desc);
+
+/*
+ * Builds the refined lattice of a periodic coarse lattice (library-owned
+ * positions; release with tess_free).  Synchronises the stream.
+ * Errors: TESS_EINVAL (bad descriptor), TESS_ENOTSUP (non-periodic lattice),
+ * TESS_ECAPACITY (fine lattice above 2^32 / 6 tracers), TESS_ENOMEM, TESS_EHIP.
+ */
+tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *desc, tess_lattice *fine,
+                        tess_refine_report *report, void *stream);
+
+/*
+ * One forward and backward evaluation of the network, for gradient checks.
+ *   params : host, TESS_MLP_PARAMS FP32 (bf16-rounded for the products)
+ *   rff_B  : host, TESS_MLP_FREQS x 3 integer-valued frequencies
+ *   q, target : device, n x 3 FP32 (q on the unit torus, target in box units)
+ *   loss   : host, mean over samples of |s - target|^2
+ *   grad   : host, nullable, TESS_MLP_PARAMS FP32 gradient of the loss
+ *   pred   : device, nullable, n x 3 predictions
+ * Synchronises the stream.  Errors: TESS_EINVAL, TESS_ENOMEM, TESS_EHIP.
+ */
+tess_status tess_mlp_loss_grad(const float *params, const float *rff_B, const float *q,
+                               const float *target, int64_t n, double *loss, float *grad,
+                               float *pred, void *stream);
+
 /* Host-only validation of a view against a lattice description, the same
  * checks tess_project performs; usable without a GPU.  desc may be NULL
  * (then the wrap/lattice consistency checks are skipped). */

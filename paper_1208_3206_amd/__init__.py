@@ -62,6 +62,28 @@ class TessStats(ctypes.Structure):
                 for k, _ in self._fields_}
 
 
+class TessRefineDesc(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("mode", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("rff_sigma", ctypes.c_double), ("lr0", ctypes.c_double),
+                ("lr1", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("rff_B", ctypes.c_void_p), ("weights_in", ctypes.c_void_p),
+                ("weights_out", ctypes.c_void_p)]
+
+
+class TessRefineReport(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("train_ms", ctypes.c_float), ("infer_ms", ctypes.c_float),
+                ("fine_tracers", ctypes.c_int64)]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+MLP_PARAMS = 66435
+MLP_FREQS = 64
+REFINE_LINEAR, REFINE_MLP = 0, 1
+
+
 class TessError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
@@ -85,12 +107,16 @@ def _load():
                                      P(TessTune), vp, P(TessStats), vp]
     L.tess_check_view.argtypes = [P(TessView), P(TessBuildDesc)]
     L.tess_check_build_desc.argtypes = [P(TessBuildDesc)]
+    L.tess_refine_desc_default.argtypes = [P(TessRefineDesc)]
+    L.tess_refine.argtypes = [vp, P(TessRefineDesc), P(vp), P(TessRefineReport), vp]
+    L.tess_mlp_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int64, P(ctypes.c_double), vp, vp, vp]
     L.tess_last_error.argtypes = []
     L.tess_last_error.restype = ctypes.c_char_p
     L.tess_version.argtypes = []
     L.tess_version.restype = ctypes.c_int32
     for f in (L.tess_build_desc_default, L.tess_build, L.tess_project, L.tess_project_batch,
-              L.tess_check_view, L.tess_check_build_desc):
+              L.tess_check_view, L.tess_check_build_desc, L.tess_refine_desc_default,
+              L.tess_refine, L.tess_mlp_loss_grad):
         f.restype = ctypes.c_int
     return L
 
@@ -100,7 +126,8 @@ _lib = _load()
 # names exported by the C ABI (checked against include/tess.h by the tests)
 EXPORTS = ("tess_build_desc_default", "tess_build", "tess_free", "tess_project",
            "tess_project_batch", "tess_check_view", "tess_check_build_desc",
-           "tess_last_error", "tess_version")
+           "tess_last_error", "tess_version", "tess_refine_desc_default", "tess_refine",
+           "tess_mlp_loss_grad")
 
 
 def lib():
@@ -261,3 +288,65 @@ def project_batch(lats: List[Lattice], views: List[Dict], out=None, tune: Option
                                  ctypes.byref(st) if stats else None, _stream_handle(stream))
     _check(rc, "tess_project_batch")
     return (out, st.as_dict()) if stats else out
+
+
+# ------------------------------------------------------------- refinement
+class _Owned(Lattice):
+    """A lattice handle whose positions the library owns (from tess_refine)."""
+
+    def __init__(self, handle, dims):  # noqa: D401 - plain holder
+        self.handle = handle
+        self.dims = tuple(dims)
+        self._tensors = []
+
+
+def refine(lat: Lattice, r: int = 4, mode: str = "mlp", steps: int = 3000, batch: int = 8192,
+           rff_sigma: float = 8.0, lr0: float = 1e-3, lr1: float = 1e-5, seed: int = 2,
+           rff_B=None, weights_in=None, want_weights: bool = False, stream=None):
+    """Refined lattice (tess_refine); returns (lattice, report dict[, weights])."""
+    import numpy as np
+    d = TessRefineDesc()
+    _check(_lib.tess_refine_desc_default(ctypes.byref(d)), "tess_refine_desc_default")
+    d.r, d.steps, d.batch = int(r), int(steps), int(batch)
+    d.mode = {"linear": REFINE_LINEAR, "mlp": REFINE_MLP}[mode]
+    d.rff_sigma, d.lr0, d.lr1, d.seed = float(rff_sigma), float(lr0), float(lr1), int(seed)
+    keep = []
+    if rff_B is not None:
+        b = np.ascontiguousarray(rff_B, dtype=np.float32).reshape(-1)
+        keep.append(b)
+        d.rff_B = b.ctypes.data
+    if weights_in is not None:
+        w = np.ascontiguousarray(weights_in, dtype=np.float32).reshape(-1)
+        keep.append(w)
+        d.weights_in = w.ctypes.data
+    wout = np.empty(MLP_PARAMS, dtype=np.float32) if want_weights else None
+    if wout is not None:
+        d.weights_out = wout.ctypes.data
+    h = ctypes.c_void_p()
+    rep = TessRefineReport()
+    _check(_lib.tess_refine(lat.handle, ctypes.byref(d), ctypes.byref(h), ctypes.byref(rep),
+                            _stream_handle(stream)), "tess_refine")
+    fine = _Owned(h, tuple(int(x) * int(r) for x in lat.dims))
+    return (fine, rep.as_dict(), wout) if want_weights else (fine, rep.as_dict())
+
+
+def mlp_loss_grad(params, rff_B, q, target, want_pred: bool = False, stream=None):
+    """(loss, grad[, pred]) of the network for device tensors q, target (n x 3)."""
+    import numpy as np
+    import torch
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    b = np.ascontiguousarray(rff_B, dtype=np.float32).reshape(-1)
+    if p.size != MLP_PARAMS or b.size != 3 * MLP_FREQS:
+        raise ValueError("params / rff_B have the wrong size")
+    n = q.shape[0]
+    for t in (q, target):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == 3 * n):
+            raise ValueError("q and target must be contiguous CUDA float32 (n, 3)")
+    grad = np.empty(MLP_PARAMS, dtype=np.float32)
+    pred = torch.empty((n, 3), dtype=torch.float32, device=q.device) if want_pred else None
+    loss = ctypes.c_double()
+    _check(_lib.tess_mlp_loss_grad(p.ctypes.data, b.ctypes.data, q.data_ptr(), target.data_ptr(),
+                                   int(n), ctypes.byref(loss), grad.ctypes.data,
+                                   pred.data_ptr() if pred is not None else None,
+                                   _stream_handle(stream)), "tess_mlp_loss_grad")
+    return (loss.value, grad, pred) if want_pred else (loss.value, grad)

@@ -1,6 +1,6 @@
 // C ABI of the tessellation projector: argument validation, lattice handles,
 // workspace management and the per-call kernel pipeline.
-#include "../../include/tess.h"
+#include "tess_host.h"
 #include "tess_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -21,6 +21,17 @@ using namespace tess;
 namespace {
 thread_local std::string g_error;
 
+bool finite3(const double *v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+constexpr int kMaxTiles = 8192;
+constexpr int kMaxSide = 16384;
+}  // namespace
+
+namespace tess {
 tess_status fail(tess_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -36,59 +47,21 @@ tess_status ok() {
     return TESS_OK;
 }
 
-#define TESS_HIP(call)                                                                   \
-    do {                                                                                 \
-        hipError_t e_ = (call);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(e_ == hipErrorOutOfMemory ? TESS_ENOMEM : TESS_EHIP, "%s: %s (%s:%d)", \
-                        #call, hipGetErrorString(e_), __FILE__, __LINE__);               \
-    } while (0)
-
-bool finite3(const double *v, int n) {
-    for (int i = 0; i < n; ++i)
-        if (!std::isfinite(v[i])) return false;
-    return true;
+tess_lattice make_owned_lattice(const tess_build_desc &desc, float *owned, int device) {
+    tess_lattice L = new tess_lattice_s();
+    L->desc = desc;
+    L->device = device;
+    L->n = (int64_t)desc.dims[0] * desc.dims[1] * desc.dims[2];
+    L->owned = owned;
+    L->x = owned;
+    L->y = owned + L->n;
+    L->z = owned + 2 * L->n;
+    return L;
 }
-
-constexpr int kMaxTiles = 8192;
-constexpr int kMaxSide = 16384;
-}  // namespace
-
-// --------------------------------------------------------------- handles
-struct tess_lattice_s {
-    tess_build_desc desc;
-    const float *x, *y, *z;
-    float *owned;  // one allocation holding x, y, z when the library owns them
-    int device;
-    int64_t n;
-};
+}  // namespace tess
 
 // ------------------------------------------------------------- workspace
 namespace {
-template <typename T>
-struct DevBuf {
-    T *p = nullptr;
-    size_t cap = 0;  // elements
-    hipError_t ensure(size_t n) {
-        if (n <= cap) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            if (e != hipSuccess) return e;
-            p = nullptr;
-            cap = 0;
-        }
-        size_t want = std::max(n, (size_t)64);
-        want += want / 8;  // headroom against small growth steps
-        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
-        if (e != hipSuccess) {
-            p = nullptr;
-            return e;
-        }
-        cap = want;
-        return hipSuccess;
-    }
-};
-
 struct Workspace {
     DevBuf<TetRec> rec;
     DevBuf<Coef64> coef64;

@@ -73,10 +73,17 @@ struct WorkItem {
 // REC_FP64 is set the same coefficients in FP64 are in Coef64[slot] and the
 // raster evaluates them in FP64 (the FP32 copies are then only indicative).
 struct RecHead {
-    int16_t bx0, by0, bx1, by1;  // pixel-centre bounding box (inclusive)
+    uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
+    uint32_t by;                 // y0 | y1 << 16
     uint32_t flags;
     uint32_t slot;               // Coef64 index when REC_FP64
 };
+// Box accessors (the box is stored as two packed 32-bit words).
+__host__ __device__ inline uint32_t pack_range(int lo, int hi) {
+    return ((uint32_t)(uint16_t)(int16_t)lo) | (((uint32_t)(uint16_t)(int16_t)hi) << 16);
+}
+__host__ __device__ inline int range_lo(uint32_t w) { return (int)(int16_t)(uint16_t)(w & 0xffffu); }
+__host__ __device__ inline int range_hi(uint32_t w) { return (int)(int16_t)(uint16_t)(w >> 16); }
 constexpr uint32_t REC_NG_MASK = 0x7u;        // number of G functions
 constexpr uint32_t REC_NW_SHIFT = 3;          // number of walls (2 bits)
 constexpr uint32_t REC_TIE0 = 1u << 5;        // wall 0 keeps pixels on its line

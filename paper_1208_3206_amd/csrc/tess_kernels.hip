@@ -40,7 +40,6 @@
 
 namespace tess {
 
-constexpr int kFlushEvery = 32;  // FP32 partial sums are folded into FP64 this often
 
 __device__ inline unsigned long long wave_sum(unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -140,16 +139,10 @@ __global__ void __launch_bounds__(64) k_bin(const TetRec *__restrict__ rec, int6
     for (int64_t id = t0; id < t1; ++id) {
         const TetRec r = rec[id];
         if (!(r.h.flags & REC_VALID)) continue;
-        int sx, cx, sy, cy;
-        axis_tiles(r.h.bx0, r.h.bx1, B.W, B.T, B.ntx, B.wrap, sx, cx);
-        axis_tiles(r.h.by0, r.h.by1, B.H, B.T, B.nty, B.wrap, sy, cy);
-        const int total = cx * cy;
-        for (int s = lane; s < total; s += 64) {
-            int tx = sx + s % cx, ty = sy + s / cx;
-            if (tx >= B.ntx) tx -= B.ntx;
-            if (ty >= B.nty) ty -= B.nty;
-            if (!tile_accept(r, tx, ty, B)) continue;
-            const int tile = ty * B.ntx + tx;
+        TileRange tr = tet_tiles(r, B);
+        for (int s = lane; s < tr.count; s += 64) {
+            int tile;
+            if (!tet_tile(r, B, tr, s, tile)) continue;
             // distinct tiles within one tetrahedron: no two lanes share a slot
             const uint32_t slot = lds_bins[tile];
             lds_bins[tile] = slot + 1;
@@ -353,99 +346,66 @@ hipError_t launch_items(const uint64_t *base, const uint32_t *tile_items, const 
 }
 
 // ----------------------------------------------------------------- raster
-// Accumulator of one lane's L pixels: FP32 block sums folded into FP64, and
-// FP64 terms added to the FP64 part directly.
-template <int L>
-struct Acc {
-    float s[L];
-    double d[L];
-    __device__ void zero() {
-#pragma unroll
-        for (int k = 0; k < L; ++k) { s[k] = 0.f; d[k] = 0.0; }
-    }
-    __device__ void flush() {
-#pragma unroll
-        for (int k = 0; k < L; ++k) { d[k] += (double)s[k]; s[k] = 0.f; }
-    }
-};
-
 // One work item per block.  Tile T x T; every lane owns L consecutive pixels
 // of one row (T / L lanes per row), so a block has T*T/L lanes.
-template <int T, int L>
+// One work item per block.  Records (and FP64 coefficient blocks) are staged
+// through LDS in batches of 64 loaded by 64 threads at once, so one memory
+// latency covers 64 tetrahedra; every lane then reads each record as an LDS
+// broadcast.
+constexpr int kBatch = 64;
+
+template <int T, int L, bool COUNT>
 __global__ void __launch_bounds__(T * T / L) k_raster(const TetRec *__restrict__ rec,
                                                       const Coef64 *__restrict__ coef64,
                                                       uint32_t coef64_cap,
                                                       const uint32_t *__restrict__ pairs,
                                                       const WorkItem *__restrict__ items, BinParams B,
                                                       double *__restrict__ partials,
-                                                      DevCounters *__restrict__ counters,
-                                                      int count_frags) {
-    constexpr int SPR = T / L;                 // strips per row
-    constexpr int RPW = 64 / SPR;              // rows per wavefront
+                                                      DevCounters *__restrict__ counters) {
+    __shared__ TetRec sRec[kBatch];
+    __shared__ Coef64 sCoef[kBatch];
     const WorkItem it = items[blockIdx.x];
-    const int tx = (int)(it.tile % (uint32_t)B.ntx), ty = (int)(it.tile / (uint32_t)B.ntx);
     const int tid = threadIdx.x;
-    const int row = tid / SPR, strip = tid % SPR;
-    const int tile_x0 = tx * T, tile_y0 = ty * T;
-    const int tile_x1 = min(tile_x0 + T, B.W) - 1, tile_y1 = min(tile_y0 + T, B.H) - 1;
-    const int px0 = tile_x0 + strip * L;       // first pixel of the lane's strip
-    const int py = tile_y0 + row;
-    const int wy0 = tile_y0 + (tid / 64) * RPW, wy1 = wy0 + RPW - 1;  // rows of this wavefront
-    // lanes whose pixels lie beyond the image (ragged last tiles) stay idle
-    const bool lane_live = py <= tile_y1 && px0 <= tile_x1;
-    const int valid = min(L, tile_x1 - px0 + 1);
+    const LaneGeom g = lane_geom<T, L>(it.tile, B, tid);
     Acc<L> acc;
     acc.zero();
     unsigned frags = 0, frags4 = 0;
     int since_flush = 0;
-    for (uint32_t e = 0; e < it.count; ++e) {
-        const uint32_t id = pairs[it.first + e];
-        if (id >= B.ntet) continue;  // never written (count/scatter disagreement)
-        const TetRec r = rec[id];
-        const bool f64 = (r.h.flags & REC_FP64) != 0;
-        if (f64 && r.h.slot >= coef64_cap) continue;  // slot overflow: the host reruns the call
-        int kx0, kx1, ky0, ky1;
-        axis_offsets(tile_x0, tile_x1, r.h.bx0, r.h.bx1, B.W, B.wrap, kx0, kx1);
-        axis_offsets(tile_y0, tile_y1, r.h.by0, r.h.by1, B.H, B.wrap, ky0, ky1);
-        for (int ky = ky0; ky <= ky1; ++ky) {
-            // wavefront-uniform row test
-            if (wy1 + ky * B.H < r.h.by0 || wy0 + ky * B.H > r.h.by1) continue;
-            for (int kx = kx0; kx <= kx1; ++kx) {
-                const int gy = py + ky * B.H;
-                const int gx0 = px0 + kx * B.W;
-                if (!lane_live || gy < r.h.by0 || gy > r.h.by1 || gx0 + L - 1 < r.h.bx0 ||
-                    gx0 > r.h.bx1)
-                    continue;
-                const int kmin = max(0, r.h.bx0 - gx0), kmax = min(valid - 1, r.h.bx1 - gx0);
-                unsigned nf = 0;
-                if (!f64) {
-                    const float x = (float)(gx0 - r.h.bx0) + 0.5f;
-                    const float y = (float)(gy - r.h.by0) + 0.5f;
-                    eval_any<float, L>(r.c, r.h.flags, x, y, acc.s);
-                    if (count_frags)
-                        nf = eval_general<float, L, true>(r.c, r.h.flags, x, y, acc.s, kmin, kmax);
-                } else {
-                    const Coef64 cf = coef64[r.h.slot];
-                    const double x = (double)(gx0 - r.h.bx0) + 0.5;
-                    const double y = (double)(gy - r.h.by0) + 0.5;
-                    eval_any<double, L>(cf.c, r.h.flags, x, y, acc.d);
-                    if (count_frags)
-                        nf = eval_general<double, L, true>(cf.c, r.h.flags, x, y, acc.d, kmin, kmax);
+    for (uint32_t base = 0; base < it.count; base += kBatch) {
+        const uint32_t nb = it.count - base < (uint32_t)kBatch ? it.count - base : (uint32_t)kBatch;
+        if (tid < (int)nb) {
+            TetRec r;
+            r.h.flags = 0;
+            const uint32_t id = pairs[it.first + base + tid];
+            if (id < B.ntet) {
+                r = rec[id];
+                if (r.h.flags & REC_FP64) {
+                    if (r.h.slot < coef64_cap)
+                        sCoef[tid] = coef64[r.h.slot];
+                    else
+                        r.h.flags = 0;  // slot overflow: the host reruns the call
                 }
-                frags += nf;
-                if ((r.h.flags & REC_NG_MASK) == 4) frags4 += nf;
+            }
+            sRec[tid] = r;
+        }
+        __syncthreads();
+        for (uint32_t j = 0; j < nb; ++j) {
+            const TetRec r = sRec[j];
+            if (r.h.flags & REC_VALID) raster_record<L, COUNT>(r, sCoef[j].c, B, g, acc, frags, frags4);
+            if (++since_flush == kFlushEvery) {
+                acc.flush();
+                since_flush = 0;
             }
         }
-        if (++since_flush == kFlushEvery) {
-            acc.flush();
-            since_flush = 0;
-        }
+        __syncthreads();
     }
     acc.flush();
+    constexpr int SPR = T / L;
+    const int row = tid / SPR, strip = tid % SPR;
     double *out = partials + (size_t)blockIdx.x * (T * T) + (size_t)row * T + strip * L;
 #pragma unroll
     for (int k = 0; k < L; ++k) out[k] = acc.d[k];
-    if (count_frags) {
+    if (COUNT) {
         unsigned long long f = wave_sum((unsigned long long)frags);
         unsigned long long f4 = wave_sum((unsigned long long)frags4);
         if ((tid & 63) == 0 && f) atomicAdd(&counters->fragments, f);
@@ -459,9 +419,12 @@ static hipError_t launch_raster_t(const TetRec *rec, const Coef64 *coef64, uint3
                                   const BinParams &B, double *partials, DevCounters *counters,
                                   bool count_fragments, hipStream_t stream) {
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_raster<T, L>), dim3((unsigned)n_items), dim3(T * T / L), 0, stream, rec,
-                       coef64, coef64_cap, pairs, items, B, partials, counters,
-                       count_fragments ? 1 : 0);
+    if (count_fragments)
+        hipLaunchKernelGGL((k_raster<T, L, true>), dim3((unsigned)n_items), dim3(T * T / L), 0, stream,
+                           rec, coef64, coef64_cap, pairs, items, B, partials, counters);
+    else
+        hipLaunchKernelGGL((k_raster<T, L, false>), dim3((unsigned)n_items), dim3(T * T / L), 0, stream,
+                           rec, coef64, coef64_cap, pairs, items, B, partials, counters);
     return hipGetLastError();
 }
 

@@ -207,7 +207,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     for (int t = 0; t < 6; ++t) {
         const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
         TetRec &R = r[t];
-        R.h.bx0 = R.h.by0 = R.h.bx1 = R.h.by1 = 0;
+        R.h.bx = 0;
+        R.h.by = 0;
         R.h.flags = 0;
         R.h.slot = kNoSlot;
 #pragma unroll
@@ -270,8 +271,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         }
         if (!footprint(qx, qy, V.mass_px, (double)(ix1 - ix0 + 1), (double)(iy1 - iy0 + 1), fp[t]))
             continue;
-        R.h.bx0 = (int16_t)ix0; R.h.bx1 = (int16_t)ix1;
-        R.h.by0 = (int16_t)iy0; R.h.by1 = (int16_t)iy1;
+        R.h.bx = pack_range(ix0, ix1);
+        R.h.by = pack_range(iy0, iy1);
         R.h.flags = (uint32_t)fp[t].ng | ((uint32_t)fp[t].nw << REC_NW_SHIFT) | fp[t].ties | REC_VALID;
 #pragma unroll
         for (int g = 0; g < 12; ++g) R.c[g] = (float)fp[t].c[g];
@@ -316,8 +317,8 @@ TESS_HD inline void axis_offsets(int t0, int t1, int b0, int b1, int n, int wrap
 // at all four corner pixel centres; FP64-flagged footprints are never culled.
 TESS_HD inline bool rect_may_cover(const TetRec &r, int x0, int x1, int y0, int y1) {
     if (r.h.flags & REC_FP64) return true;
-    const float xa = (float)(x0 - r.h.bx0) + 0.5f, xb = (float)(x1 - r.h.bx0) + 0.5f;
-    const float ya = (float)(y0 - r.h.by0) + 0.5f, yb = (float)(y1 - r.h.by0) + 0.5f;
+    const float xa = (float)(x0 - range_lo(r.h.bx)) + 0.5f, xb = (float)(x1 - range_lo(r.h.bx)) + 0.5f;
+    const float ya = (float)(y0 - range_lo(r.h.by)) + 0.5f, yb = (float)(y1 - range_lo(r.h.by)) + 0.5f;
     const int nf = (int)(r.h.flags & REC_NG_MASK) + (int)((r.h.flags >> REC_NW_SHIFT) & 3u);
     for (int g = 0; g < nf; ++g) {
         const float a = r.c[3 * g], b = r.c[3 * g + 1], c = r.c[3 * g + 2];
@@ -334,12 +335,12 @@ TESS_HD inline bool tile_accept(const TetRec &r, int tx, int ty, const BinParams
     const int tx0 = tx * B.T, tx1 = min(tx0 + B.T, B.W) - 1;
     const int ty0 = ty * B.T, ty1 = min(ty0 + B.T, B.H) - 1;
     int kx0, kx1, ky0, ky1;
-    axis_offsets(tx0, tx1, r.h.bx0, r.h.bx1, B.W, B.wrap, kx0, kx1);
-    axis_offsets(ty0, ty1, r.h.by0, r.h.by1, B.H, B.wrap, ky0, ky1);
+    axis_offsets(tx0, tx1, range_lo(r.h.bx), range_hi(r.h.bx), B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty1, range_lo(r.h.by), range_hi(r.h.by), B.H, B.wrap, ky0, ky1);
     for (int ky = ky0; ky <= ky1; ++ky)
         for (int kx = kx0; kx <= kx1; ++kx) {
-            const int x0 = max(tx0 + kx * B.W, (int)r.h.bx0), x1 = min(tx1 + kx * B.W, (int)r.h.bx1);
-            const int y0 = max(ty0 + ky * B.H, (int)r.h.by0), y1 = min(ty1 + ky * B.H, (int)r.h.by1);
+            const int x0 = max(tx0 + kx * B.W, (int)range_lo(r.h.bx)), x1 = min(tx1 + kx * B.W, (int)range_hi(r.h.bx));
+            const int y0 = max(ty0 + ky * B.H, (int)range_lo(r.h.by)), y1 = min(ty1 + ky * B.H, (int)range_hi(r.h.by));
             if (x0 > x1 || y0 > y1) continue;
             if (rect_may_cover(r, x0, x1, y0, y1)) return true;
         }
@@ -352,6 +353,7 @@ TESS_HD inline bool tile_accept(const TetRec &r, int tx, int ty, const BinParams
 // the first pixel centre in the record frame.  NG = 3 or 4, no walls.
 template <typename R, int L, int NG, typename Sum>
 TESS_HD inline void eval_fast(const R *c, R x, R y, Sum (&acc)[L]) {
+    // g_q at the strip's first pixel centre, then one step of b_q per pixel
     R g[NG], b[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
@@ -360,12 +362,11 @@ TESS_HD inline void eval_fast(const R *c, R x, R y, Sum (&acc)[L]) {
     }
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        R v[NG];
-#pragma unroll
-        for (int q = 0; q < NG; ++q) v[q] = (R)k * b[q] + g[q];
-        R m = fmin(v[0], fmin(v[1], v[2]));
-        if (NG == 4) m = fmin(m, v[NG - 1]);
+        R m = fmin(g[0], fmin(g[1], g[2]));
+        if (NG == 4) m = fmin(m, g[NG - 1]);
         acc[k] += (Sum)fmax(m, (R)0);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) g[q] += b[q];
     }
 }
 
@@ -398,8 +399,10 @@ TESS_HD inline unsigned eval_general(const R *c, uint32_t flags, R x, R y, Sum (
     return n;
 }
 
+// Rare paths kept out of line so the hot loop keeps its registers: footprints
+// with walls (edge-on faces), and FP64 footprints.
 template <typename R, int L, typename Sum>
-TESS_HD inline void eval_any(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L]) {
+TESS_HD __attribute__((noinline)) void eval_slow(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L]) {
     const int ng = (int)(flags & REC_NG_MASK);
     const bool walls = ((flags >> REC_NW_SHIFT) & 3u) != 0;
     if (!walls && ng == 4)
@@ -410,5 +413,165 @@ TESS_HD inline void eval_any(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L]
         eval_general<R, L, false>(c, flags, x, y, acc, 0, L - 1);
 }
 
+template <typename R, int L, typename Sum>
+TESS_HD inline void eval_any(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L]) {
+    const int ng = (int)(flags & REC_NG_MASK);
+    const bool walls = ((flags >> REC_NW_SHIFT) & 3u) != 0;
+    if (!walls && ng == 4)
+        eval_fast<R, L, 4>(c, x, y, acc);
+    else if (!walls && ng == 3)
+        eval_fast<R, L, 3>(c, x, y, acc);
+    else
+        eval_slow<R, L>(c, flags, x, y, acc);
+}
+
+// Candidate tiles of one record: tx = (sx + s % cx) mod ntx, ty = (sy + s / cx)
+// mod nty for s < count = cx * cy.
+struct TileRange {
+    int sx, cx, sy, cy, count;
+};
+
+TESS_HD inline TileRange tet_tiles(const TetRec &r, const BinParams &B) {
+    TileRange t;
+    axis_tiles(range_lo(r.h.bx), range_hi(r.h.bx), B.W, B.T, B.ntx, B.wrap, t.sx, t.cx);
+    axis_tiles(range_lo(r.h.by), range_hi(r.h.by), B.H, B.T, B.nty, B.wrap, t.sy, t.cy);
+    t.count = t.cx * t.cy;
+    return t;
+}
+
+// Candidate s of the record: its tile index, and whether the footprint may
+// cover a pixel centre there.
+TESS_HD inline bool tet_tile(const TetRec &r, const BinParams &B, const TileRange &t, int s, int &tile) {
+    int tx = t.sx + s % t.cx, ty = t.sy + s / t.cx;
+    if (tx >= B.ntx) tx -= B.ntx;
+    if (ty >= B.nty) ty -= B.nty;
+    tile = ty * B.ntx + tx;
+    return tile_accept(r, tx, ty, B);
+}
+
+// Accumulator of one lane's L pixels: FP32 block sums folded into FP64, and
+// FP64 terms added to the FP64 part directly.
+constexpr int kFlushEvery = 32;  // FP32 partial sums are folded into FP64 this often
+
+template <int L>
+struct Acc {
+    float s[L];
+    double d[L];
+    TESS_HD void zero() {
+#pragma unroll
+        for (int k = 0; k < L; ++k) { s[k] = 0.f; d[k] = 0.0; }
+    }
+    TESS_HD void flush() {
+#pragma unroll
+        for (int k = 0; k < L; ++k) { d[k] += (double)s[k]; s[k] = 0.f; }
+    }
+};
+
+
+// Geometry of one raster lane: the L-pixel strip of lane `tid` of the T x T
+// tile `tile` (T / L lanes per row).
+struct LaneGeom {
+    int tile_x0, tile_x1, tile_y0, tile_y1;  // tile pixels (inclusive, clipped to the image)
+    int px0, py;                             // first pixel of the strip
+    int wy0, wy1;                            // rows of the lane's wavefront
+    int valid;                               // strip pixels inside the image
+    bool live;                               // some strip pixel inside the image
+};
+
+template <int T, int L>
+TESS_HD inline LaneGeom lane_geom(uint32_t tile, const BinParams &B, int tid) {
+    constexpr int SPR = T / L;                 // strips per row
+    constexpr int RPW = 64 / SPR;              // rows per wavefront
+    LaneGeom g;
+    const int tx = (int)(tile % (uint32_t)B.ntx), ty = (int)(tile / (uint32_t)B.ntx);
+    const int row = tid / SPR, strip = tid % SPR;
+    g.tile_x0 = tx * T;
+    g.tile_y0 = ty * T;
+    g.tile_x1 = (g.tile_x0 + T < B.W ? g.tile_x0 + T : B.W) - 1;
+    g.tile_y1 = (g.tile_y0 + T < B.H ? g.tile_y0 + T : B.H) - 1;
+    g.px0 = g.tile_x0 + strip * L;
+    g.py = g.tile_y0 + row;
+    g.wy0 = g.tile_y0 + (tid / 64) * RPW;
+    g.wy1 = g.wy0 + RPW - 1;
+    // lanes whose pixels lie beyond the image (ragged last tiles) stay idle
+    g.live = g.py <= g.tile_y1 && g.px0 <= g.tile_x1;
+    g.valid = L < g.tile_x1 - g.px0 + 1 ? L : g.tile_x1 - g.px0 + 1;
+    return g;
+}
+
+// Periodic offsets of a record against a tile: a box inside the image needs
+// none (fast path), otherwise the general division.
+TESS_HD inline void rec_offsets(int t0, int t1, int b0, int b1, int n, int wrap, int &k0, int &k1) {
+    if (!wrap || (b0 >= 0 && b1 < n)) {
+        k0 = 0;
+        k1 = 0;
+        return;
+    }
+    axis_offsets(t0, t1, b0, b1, n, wrap, k0, k1);
+}
+
+// Adds one record's footprint to the lane's strip (every periodic offset that
+// meets the tile).  c64: the record's FP64 coefficients when REC_FP64.
+template <int L, bool COUNT>
+TESS_HD inline void raster_record(const TetRec &r, const double *c64, const BinParams &B,
+                                  const LaneGeom &g, Acc<L> &acc, unsigned &frags, unsigned &frags4) {
+    const bool f64 = (r.h.flags & REC_FP64) != 0;
+    const int bx0 = range_lo(r.h.bx), bx1 = range_hi(r.h.bx);
+    const int by0 = range_lo(r.h.by), by1 = range_hi(r.h.by);
+    int kx0, kx1, ky0, ky1;
+    rec_offsets(g.tile_x0, g.tile_x1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    rec_offsets(g.tile_y0, g.tile_y1, by0, by1, B.H, B.wrap, ky0, ky1);
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        // wavefront-uniform row test
+        if (g.wy1 + ky * B.H < by0 || g.wy0 + ky * B.H > by1) continue;
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            const int gy = g.py + ky * B.H;
+            const int gx0 = g.px0 + kx * B.W;
+            if (!g.live || gy < by0 || gy > by1 || gx0 + L - 1 < bx0 || gx0 > bx1) continue;
+            unsigned nf = 0;
+            const int kmin = bx0 - gx0 > 0 ? bx0 - gx0 : 0;
+            const int kmax = g.valid - 1 < bx1 - gx0 ? g.valid - 1 : bx1 - gx0;
+            if (!f64) {
+                const float x = (float)(gx0 - bx0) + 0.5f;
+                const float y = (float)(gy - by0) + 0.5f;
+                eval_any<float, L>(r.c, r.h.flags, x, y, acc.s);
+                if (COUNT) nf = eval_general<float, L, true>(r.c, r.h.flags, x, y, acc.s, kmin, kmax);
+            } else {
+                const double x = (double)(gx0 - bx0) + 0.5;
+                const double y = (double)(gy - by0) + 0.5;
+                eval_slow<double, L>(c64, r.h.flags, x, y, acc.d);
+                if (COUNT) nf = eval_general<double, L, true>(c64, r.h.flags, x, y, acc.d, kmin, kmax);
+            }
+            frags += nf;
+            if ((r.h.flags & REC_NG_MASK) == 4) frags4 += nf;
+        }
+    }
+}
+
+// The work of one raster lane over a work item's list, in list order (the
+// kernel does the same with records staged through LDS).
+template <int T, int L, bool COUNT>
+TESS_HD inline void raster_lane(const TetRec *rec, const Coef64 *coef64, uint32_t coef64_cap,
+                                const uint32_t *pairs, const WorkItem &it, const BinParams &B, int tid,
+                                Acc<L> &acc, unsigned &frags, unsigned &frags4) {
+    const LaneGeom g = lane_geom<T, L>(it.tile, B, tid);
+    acc.zero();
+    frags = frags4 = 0;
+    int since_flush = 0;
+    for (uint32_t e = 0; e < it.count; ++e) {
+        const uint32_t id = pairs[it.first + e];
+        if (id < B.ntet) {
+            const TetRec r = rec[id];
+            const bool f64 = (r.h.flags & REC_FP64) != 0;
+            if (!f64 || r.h.slot < coef64_cap)
+                raster_record<L, COUNT>(r, f64 ? coef64[r.h.slot].c : nullptr, B, g, acc, frags, frags4);
+        }
+        if (++since_flush == kFlushEvery) {
+            acc.flush();
+            since_flush = 0;
+        }
+    }
+    acc.flush();
+}
 
 }  // namespace tess

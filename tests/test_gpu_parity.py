@@ -143,8 +143,12 @@ def test_bitwise_deterministic_and_chunk_independent(tess, tiny_lattice):
     d = tess.project(lat, view, tune=tess.make_tune(16, 128)).cpu().numpy()
     torch.cuda.synchronize()
     assert np.array_equal(a, b)
-    np.testing.assert_allclose(c, a, rtol=2e-6, atol=0)
-    np.testing.assert_allclose(d, a, rtol=2e-6, atol=0)
+    # chunking only regroups FP64 partial sums
+    np.testing.assert_allclose(c, a, rtol=1e-6, atol=0)
+    # another tile size changes each lane's strip start, so the FP32 edge
+    # functions are stepped from other origins: equal within the FP32
+    # evaluation bound of a footprint (condition <= 256), well inside 1e-4
+    np.testing.assert_allclose(d, a, rtol=1e-4, atol=0)
 
 
 def test_batch_equals_single_projections(tess):

@@ -17,12 +17,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  Packed FP32 is not used,
-# so one VALU lane-operation per lane per clock is the issue ceiling for the
-# raster's FP32 and FP64 arithmetic alike.
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  The raster's FP64 FMA,
+# add, multiply, min and max issue at one lane-operation per lane per clock
+# (the same rate as unpacked FP32), so that is the ceiling of its arithmetic.
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9          # 3.93e13 lane-ops/s
-OPS_TRIANGLE = 6   # 3 edge functions, min3, clamp, accumulate
-OPS_QUAD = 8       # 4 edge functions, min3 + min, clamp, accumulate
+# Algorithmic FP64 operations of one span (one tetrahedron on one pixel row
+# of one tile): 4 line offsets (FMA), 4 zero crossings + 2 clamps, 6 pair
+# crossings (subtract, multiply), 12 min/max for the pieces' ends, and per
+# break point (3.5 on average: the pieces holding a sample, plus the end)
+# step, slope change, floor, fraction and the two entries (8).
+OPS_PER_SPAN = 4 + 6 + 12 + 12 + 28
+# Its LDS traffic: two FP64 read-modify-writes per break point.
+LDS_BYTES_PER_SPAN = 3.5 * 2 * 16
+PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
 
 
 def parse():
@@ -32,8 +39,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="stress_256^3_to_2048^2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-cols", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=48,
                     help="edge (pixels) of the centred crop the oracle renders for the CPU baseline")
@@ -100,11 +109,9 @@ def main():
     out = torch.empty((w.height, w.width), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
-    # untimed: exact fragment count of this image
-    _, st0 = tess.project(lat, view, out=out,
-                          tune=tess.make_tune(args.tile, args.chunk, count_fragments=True), stats=True)
-    frags, frags4 = st0["fragments"], st0["fragments4"]
-    tune = tess.make_tune(args.tile, args.chunk, count_fragments=False)
+    tune = tess.make_tune(args.tile_rows, args.tile_cols, args.chunk, args.block)
+    _, st0 = tess.project(lat, view, out=out, tune=tune, stats=True)
+    frags, spans = st0["fragments"], st0["spans"]
     for _ in range(args.warmup):
         tess.project(lat, view, out=out, tune=tune)
     torch.cuda.synchronize()
@@ -123,7 +130,7 @@ def main():
     img = out.double()
     checksum = float(img.mean().item())
 
-    ops = OPS_TRIANGLE * (frags - frags4) + OPS_QUAD * frags4
+    ops = OPS_PER_SPAN * spans
     raster_s = kernel["raster_ms"] * 1e-3
     achieved = ops / raster_s
     result = {
@@ -137,17 +144,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64",
         "data": "synthetic (seeded Zel'dovich lattice, kmax 64, D 8)",
         "config": {"workload": w.name, "lattice": w.n, "tets": w.tets, "image": [w.width, w.height],
-                   "view": "z-projection, periodic", "precision": args.precision,
-                   "tile": st["tile"], "chunk": st["chunk"]},
+                   "view": "z-projection, periodic", "determinant": args.precision,
+                   "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"],
+                   "block": st["block"]},
         "fragments": frags,
         "fragments_per_s": frags / (ms * 1e-3),
+        "spans": spans,
         "kernel_ms": kernel,
-        "fp64_footprints": st["fp64_tets"],
+        "fp64_dets": st["fp64_dets"],
         "bin_pairs": st["bin_pairs"],
+        "work_items": st["work_items"],
         "image_mean": checksum,
+        "lds_bytes_per_s_raster": LDS_BYTES_PER_SPAN * spans / raster_s,
+        "lds_frac_raster": LDS_BYTES_PER_SPAN * spans / raster_s / PEAK_LDS_BYTES,
         "roofline": {
             "kernel": "k_raster",
             "bound": "alu",
@@ -157,6 +169,7 @@ def main():
             "frac": achieved / PEAK_VALU_OPS,
             "traffic": None,
             "ops_per_launch": ops,
+            "ops_per_span": OPS_PER_SPAN,
         },
     }
     if not args.no_cpu_baseline:

@@ -44,14 +44,13 @@ typedef enum {
     TESS_ERANGE = -6      /* a value does not fit the representation in use      */
 } tess_status;
 
-/* Arithmetic of the raster.  In both modes the per-tetrahedron footprint
- * setup runs in FP64 and the volume determinant in FP32, redone in FP64 for
- * tetrahedra flagged as near-degenerate. */
+/* Arithmetic of the volume determinant (Eq. Eqn:TetVolume).  The footprint
+ * setup and the raster run in FP64 in both modes. */
 enum {
-    TESS_PREC_FP32 = 0,   /* FP32 per-fragment arithmetic with FP32 block sums
-                             folded into FP64; footprints whose FP32 evaluation
-                             is ill-conditioned (fp64_cond) are rastered in FP64 */
-    TESS_PREC_FP64 = 1    /* every footprint rastered in FP64 (comparison path)  */
+    TESS_PREC_FP32 = 0,   /* FP32 determinant with a forward error bound; FP64 for
+                             tetrahedra the bound cannot certify and for
+                             near-degenerate ones (det_v0_frac, det_cond_k)      */
+    TESS_PREC_FP64 = 1    /* FP64 determinant for every tetrahedron              */
 };
 
 typedef struct tess_lattice_s *tess_lattice;   /* opaque; release with tess_free */
@@ -71,17 +70,12 @@ typedef struct {
     double det_cond_k;      /* ... or when |V32| < det_cond_k * 2^-24 * P, where P
                                is the sum of the magnitudes of the six products
                                of the triple product (a forward error bound)      */
-    double fp64_cond;       /* TESS_PREC_FP32 only: a footprint whose FP32 error
-                               amplification (largest sum of |terms| of a footprint
-                               function over its pixel box, divided by the apex
-                               value) exceeds this is rastered in FP64; INFINITY
-                               keeps every footprint in FP32                      */
     int32_t copy_positions; /* 0: keep the caller's x, y, z pointers (they must
                                outlive the handle); 1: library-owned copy         */
 } tess_build_desc;
 
 /* Fills a descriptor with the defaults: periodic, unit box, total mass 1,
- * TESS_PREC_FP32, det_v0_frac 1e-6, det_cond_k 1e3, fp64_cond 256, no copy.  dims are set
+ * TESS_PREC_FP32, det_v0_frac 1e-6, det_cond_k 1e3, no copy.  dims are set
  * to 0 and must be filled in.  Host only; never fails for a non-null desc. */
 tess_status tess_build_desc_default(tess_build_desc *desc);
 
@@ -116,27 +110,29 @@ typedef struct {
                                lengths along screen u and v                      */
 } tess_view;
 
-/* Raster parameters.  0 in a field means "choose automatically". */
+/* Raster parameters.  0 in a field means "choose automatically".  The image
+ * is cut into tiles of tile_rows x tile_cols pixels (row bands when tile_cols
+ * >= width); one raster work group holds a tile's FP64 accumulator, so
+ * tile_rows * tile_cols must be <= 16384 (128 KiB of LDS). */
 typedef struct {
-    int32_t tile;           /* screen tile edge in pixels: 16, 32 or 64           */
+    int32_t tile_rows;      /* 1 .. 256                                           */
+    int32_t tile_cols;      /* 16 .. 16384                                        */
     int32_t chunk;          /* tile-list entries per raster work item (>= 64)     */
-    int32_t count_fragments;/* 1: fill tess_stats.fragments (costs raster time)   */
+    int32_t block;          /* raster work-group size: 256, 512 or 1024          */
 } tess_tune;
 
 typedef struct {
     uint64_t tets;          /* tetrahedra with V != 0                             */
     uint64_t zero_volume;   /* tetrahedra skipped because V == 0                  */
     uint64_t inverted;      /* tetrahedra with V > 0 (undisplaced ones have V < 0) */
-    uint64_t fp64_dets;     /* volume determinants recomputed in FP64             */
-    uint64_t fp64_tets;     /* footprints rastered in FP64                        */
+    uint64_t fp64_dets;     /* volume determinants computed in FP64               */
     uint64_t degenerate;    /* |V| < det_v0_frac * V0                             */
-    uint64_t fragments;     /* (pixel, tetrahedron) pairs with rho*dl > 0, when
-                               tune->count_fragments is set (else 0)              */
-    uint64_t fragments4;    /* ... of them, from quadrilateral silhouettes        */
-    uint64_t bin_pairs;     /* (tile, tetrahedron) pairs after culling            */
+    uint64_t fragments;     /* (pixel, tetrahedron) pairs with rho*dl > 0         */
+    uint64_t spans;         /* (tetrahedron, pixel row, tile) spans rastered      */
+    uint64_t bin_pairs;     /* (tile, tetrahedron) pairs                          */
     uint32_t max_bin;       /* longest tile list                                  */
     uint32_t work_items;    /* raster work items                                  */
-    int32_t tile, chunk;    /* parameters used                                    */
+    int32_t tile_rows, tile_cols, chunk, block;   /* parameters used               */
     float ms;               /* device time of the call, milliseconds              */
     float setup_ms;         /* setup kernel                                       */
     float bin_ms;           /* count + scan + plan + items + scatter              */
@@ -153,14 +149,16 @@ typedef struct {
  * skipped.
  *   tune  : host, nullable (automatic choice).
  *   stats : host, nullable; when non-null the call times its kernels with
- *           HIP events on `stream`, synchronises it and returns the counters
- *           (fragments only with tune->count_fragments).
+ *           HIP events on `stream`, synchronises it and returns the counters.
+ * Pixel values are sums of FP64 terms accumulated with atomics, rounded to
+ * FP32 at the end: repeated calls agree to FP64 rounding, not bit for bit.
  * The call synchronises the stream once internally to size its workspace
  * (the number of tile-tetrahedron pairs depends on the data).  The library
  * owns and reuses the workspace; concurrent calls on one handle must use
  * different streams and output buffers.
  * Errors: TESS_EINVAL (null handle/view/image, a view that fails the checks
- * above), TESS_ECAPACITY (more than 8192 tiles), TESS_ENOMEM, TESS_EHIP.
+ * above, a tune outside its ranges), TESS_ECAPACITY (more than 32768 tiles),
+ * TESS_ENOMEM, TESS_EHIP.
  */
 tess_status tess_project(tess_lattice lat, const tess_view *view, const tess_tune *tune,
                          float *image, tess_stats *stats, void *stream);

@@ -30,8 +30,7 @@ class TessBuildDesc(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int32 * 3), ("box", ctypes.c_double * 3),
                 ("periodic", ctypes.c_int32), ("total_mass", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("det_v0_frac", ctypes.c_double),
-                ("det_cond_k", ctypes.c_double), ("fp64_cond", ctypes.c_double),
-                ("copy_positions", ctypes.c_int32)]
+                ("det_cond_k", ctypes.c_double), ("copy_positions", ctypes.c_int32)]
 
 
 class TessView(ctypes.Structure):
@@ -41,19 +40,19 @@ class TessView(ctypes.Structure):
 
 
 class TessTune(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("count_fragments", ctypes.c_int32)]
+    _fields_ = [("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
 class TessStats(ctypes.Structure):
     _fields_ = [("tets", ctypes.c_uint64), ("zero_volume", ctypes.c_uint64),
                 ("inverted", ctypes.c_uint64), ("fp64_dets", ctypes.c_uint64),
-                ("fp64_tets", ctypes.c_uint64),
                 ("degenerate", ctypes.c_uint64), ("fragments", ctypes.c_uint64),
-                ("fragments4", ctypes.c_uint64),
+                ("spans", ctypes.c_uint64),
                 ("bin_pairs", ctypes.c_uint64), ("max_bin", ctypes.c_uint32),
-                ("work_items", ctypes.c_uint32), ("tile", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("work_items", ctypes.c_uint32), ("tile_rows", ctypes.c_int32),
+                ("tile_cols", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("ms", ctypes.c_float),
                 ("setup_ms", ctypes.c_float), ("bin_ms", ctypes.c_float),
                 ("raster_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float)]
 
@@ -150,8 +149,7 @@ def _check(rc: int, where: str):
 # ------------------------------------------------------------ descriptors
 def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
                total_mass: float = 1.0, precision: str = "fp32", det_v0_frac: float = 1e-6,
-               det_cond_k: float = 1e3, fp64_cond: float = 256.0,
-               copy_positions: bool = False) -> TessBuildDesc:
+               det_cond_k: float = 1e3, copy_positions: bool = False) -> TessBuildDesc:
     d = TessBuildDesc()
     _check(_lib.tess_build_desc_default(ctypes.byref(d)), "tess_build_desc_default")
     for a in range(3):
@@ -162,7 +160,6 @@ def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
     d.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
     d.det_v0_frac = float(det_v0_frac)
     d.det_cond_k = float(det_cond_k)
-    d.fp64_cond = float(fp64_cond)
     d.copy_positions = 1 if copy_positions else 0
     return d
 
@@ -180,10 +177,10 @@ def make_view(view: Dict) -> TessView:
     return v
 
 
-def make_tune(tile: int = 0, chunk: int = 0, count_fragments: bool = False) -> TessTune:
+def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int = 0) -> TessTune:
+    """Raster parameters; 0 means automatic."""
     t = TessTune()
-    t.tile, t.chunk = int(tile), int(chunk)
-    t.count_fragments = 1 if count_fragments else 0
+    t.tile_rows, t.tile_cols, t.chunk, t.block = int(tile_rows), int(tile_cols), int(chunk), int(block)
     return t
 
 
@@ -252,12 +249,9 @@ def build(x, y, z, dims: Sequence[int], ids=None, stream=None, **desc_kw) -> Lat
 
 def project(lat: Lattice, view: Dict, out=None, tune: Optional[TessTune] = None,
             stats: bool = False, stream=None):
-    """Column-density image (float32 CUDA tensor [H, W]); with stats, also a dict
-    (fragments are counted too unless a tune without count_fragments is given)."""
+    """Column-density image (float32 CUDA tensor [H, W]); with stats, also a dict."""
     import torch
     v = make_view(view)
-    if stats and tune is None:
-        tune = make_tune(count_fragments=True)
     if out is None:
         out = torch.empty((v.height, v.width), dtype=torch.float32, device="cuda")
     if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()

@@ -27,7 +27,8 @@ bool finite3(const double *v, int n) {
     return true;
 }
 
-constexpr int kMaxTiles = 8192;
+constexpr int kMaxTiles = 32768;  // the binning keeps one 32-bit counter per tile in LDS
+constexpr int kMaxTileCells = 16384;  // FP64 accumulator of one tile: 128 KiB of LDS
 constexpr int kMaxSide = 16384;
 }  // namespace
 
@@ -63,15 +64,15 @@ tess_lattice make_owned_lattice(const tess_build_desc &desc, float *owned, int d
 // ------------------------------------------------------------- workspace
 namespace {
 struct Workspace {
-    DevBuf<TetRec> rec;
-    DevBuf<Coef64> coef64;
+    DevBuf<RecHead> head;
+    DevBuf<Coef64> coef;
     DevBuf<uint32_t> counts;
     DevBuf<uint64_t> base;
     DevBuf<uint64_t> scan;
     DevBuf<uint32_t> tile_items;
     DevBuf<WorkItem> items;
     DevBuf<uint32_t> pairs;
-    DevBuf<double> partials;
+    DevBuf<double> acc;
     DevBuf<PlanOut> plan;
     DevBuf<DevCounters> counters;
     PlanOut *host_plan = nullptr;       // pinned
@@ -111,7 +112,6 @@ extern "C" tess_status tess_build_desc_default(tess_build_desc *d) {
     d->precision = TESS_PREC_FP32;
     d->det_v0_frac = 1e-6;
     d->det_cond_k = 1e3;
-    d->fp64_cond = 256.0;
     d->copy_positions = 0;
     return ok();
 }
@@ -134,8 +134,6 @@ extern "C" tess_status tess_check_build_desc(const tess_build_desc *d) {
         return fail(TESS_EINVAL, "det_v0_frac must be finite and >= 0");
     if (!(d->det_cond_k >= 0) || !std::isfinite(d->det_cond_k))
         return fail(TESS_EINVAL, "det_cond_k must be finite and >= 0");
-    if (!(d->fp64_cond >= 0) || std::isnan(d->fp64_cond))
-        return fail(TESS_EINVAL, "fp64_cond must be >= 0 (infinity disables FP64 footprints)");
     if (d->periodic != 0 && d->periodic != 1) return fail(TESS_EINVAL, "periodic must be 0 or 1");
     return ok();
 }
@@ -286,8 +284,7 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     lp.tet_mass = d.total_mass / (6.0 * (double)lp.ncubes);
     lp.v0 = d.box[0] * d.box[1] * d.box[2] / (6.0 * (double)lp.ncubes);
     lp.det_v0_frac = d.det_v0_frac;
-    lp.det_cond_k = d.det_cond_k;
-    lp.fp64_cond = d.precision == TESS_PREC_FP64 ? -1.0 : d.fp64_cond;
+    lp.det_cond_k = d.precision == TESS_PREC_FP64 ? -1.0 : d.det_cond_k;
     for (int i = 0; i < 9; ++i) vp.rot[i] = v->rot[i];
     for (int i = 0; i < 3; ++i) vp.center[i] = v->center[i];
     vp.u_left = -0.5 * v->extent[0];
@@ -301,19 +298,21 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
 }
 
 struct Plan {
-    int T, chunk;
-    bool count_fragments;
+    int Th, Tw, chunk, block;
 };
 
+// Default tiling: full-width row bands when they fit, with as many rows as
+// the 128 KiB accumulator allows (at most 64).
 Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     Plan p;
-    p.T = (tune && tune->tile) ? tune->tile : 32;
-    if (!(tune && tune->tile)) {
-        const double tiles32 = std::ceil(v->width / 32.0) * std::ceil(v->height / 32.0);
-        if (tiles32 > kMaxTiles) p.T = 64;
-    }
-    p.chunk = (tune && tune->chunk) ? tune->chunk : 4096;
-    p.count_fragments = tune && tune->count_fragments;
+    int Tw = (tune && tune->tile_cols) ? tune->tile_cols : std::min(v->width, 2048);
+    int Th = 1;
+    while (Th < 64 && 2 * Th * Tw <= kMaxTileCells) Th *= 2;
+    if (tune && tune->tile_rows) Th = tune->tile_rows;
+    p.Th = Th;
+    p.Tw = Tw;
+    p.chunk = (tune && tune->chunk) ? tune->chunk : 0;  // 0: from the pair count
+    p.block = (tune && tune->block) ? tune->block : 1024;
     return p;
 }
 
@@ -324,16 +323,17 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     make_params(L, v, lp, vp);
     const int64_t ntet = 6 * lp.ncubes;
     BinParams B;
-    B.T = plan.T;
-    B.ntx = (v->width + plan.T - 1) / plan.T;
-    B.nty = (v->height + plan.T - 1) / plan.T;
+    B.Th = plan.Th;
+    B.Tw = plan.Tw;
+    B.ntx = (v->width + plan.Tw - 1) / plan.Tw;
+    B.nty = (v->height + plan.Th - 1) / plan.Th;
     B.W = v->width;
     B.H = v->height;
     B.wrap = v->wrap;
     const int64_t ntiles = (int64_t)B.ntx * B.nty;
     if (ntiles > kMaxTiles)
-        return fail(TESS_ECAPACITY, "%lld tiles of %d px exceed the limit of %d; use a larger tile",
-                    (long long)ntiles, plan.T, kMaxTiles);
+        return fail(TESS_ECAPACITY, "%lld tiles of %d x %d px exceed the limit of %d; use larger tiles",
+                    (long long)ntiles, plan.Th, plan.Tw, kMaxTiles);
     // binning segments: enough for the device, few enough to keep the count matrix small
     int64_t seg_len = 4096;
     while ((ntet + seg_len - 1) / seg_len * ntiles > (int64_t)64 << 20) seg_len *= 2;
@@ -342,53 +342,51 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     if (B.nseg < 1) B.nseg = 1;
     B.ntet = (uint32_t)ntet;
     const int64_t nmat = ntiles * B.nseg;
+    const int64_t npix = (int64_t)B.W * B.H;
 
-    TESS_HIP(ws.rec.ensure((size_t)ntet));
-    // FP64 footprints: all of them, or a fraction sized by the last call
-    size_t cap64 = lp.fp64_cond < 0 ? (size_t)ntet : std::max<size_t>(ws.coef64.cap, (size_t)ntet / 16 + 1024);
-    cap64 = std::min<size_t>(cap64, (size_t)ntet);
-    TESS_HIP(ws.coef64.ensure(cap64));
-    cap64 = std::min<size_t>(ws.coef64.cap, 0xfffffff0u);
+    TESS_HIP(ws.head.ensure((size_t)ntet));
+    TESS_HIP(ws.coef.ensure((size_t)ntet));
     TESS_HIP(ws.counts.ensure((size_t)nmat));
     TESS_HIP(ws.base.ensure((size_t)nmat));
     TESS_HIP(ws.scan.ensure(scan_scratch_elems(nmat)));
     TESS_HIP(ws.tile_items.ensure((size_t)ntiles + 1));
     TESS_HIP(ws.plan.ensure(1));
     TESS_HIP(ws.counters.ensure(1));
+    TESS_HIP(ws.acc.ensure((size_t)npix));
 
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
-    for (int attempt = 0;; ++attempt) {
-        TESS_HIP(hipMemsetAsync(ws.counters.p, 0, sizeof(DevCounters), s));
-        TESS_HIP(launch_setup(lp, vp, ws.rec.p, ws.coef64.p, (uint32_t)cap64, ws.counters.p, s));
-        if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
-        TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters),
-                                hipMemcpyDeviceToHost, s));
-        TESS_HIP(launch_count(ws.rec.p, ntet, B, ws.counts.p, s));
-        TESS_HIP(launch_scan(ws.counts.p, ws.base.p, nmat, ws.scan.p, s));
-        TESS_HIP(launch_plan(ws.counts.p, ws.base.p, B, plan.chunk, ws.tile_items.p, ws.plan.p, s));
-        TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
-        TESS_HIP(hipStreamSynchronize(s));
-        const unsigned long long used = ws.host_counters->coef64_used;
-        if (used <= cap64) break;
-        if (attempt > 0) return fail(TESS_ECAPACITY, "FP64 footprint slots overflowed twice");
-        TESS_HIP(ws.coef64.ensure((size_t)used));
-        cap64 = std::min<size_t>(ws.coef64.cap, 0xfffffff0u);
+    TESS_HIP(hipMemsetAsync(ws.counters.p, 0, sizeof(DevCounters), s));
+    TESS_HIP(launch_setup(lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
+    TESS_HIP(launch_count(ws.head.p, ntet, B, ws.counts.p, s));
+    TESS_HIP(launch_scan(ws.counts.p, ws.base.p, nmat, ws.scan.p, s));
+    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, B, ws.plan.p, s));
+    TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipStreamSynchronize(s));
+    const unsigned long long total_pairs = ws.host_plan->total_pairs;
+    // work items: a few per CU at least, each long enough to amortise its tile flush
+    int chunk = plan.chunk;
+    if (chunk == 0) {
+        const unsigned long long want = total_pairs / 4096ull;
+        chunk = (int)std::min<unsigned long long>(65536ull, std::max<unsigned long long>(1024ull, want));
     }
-    const PlanOut P = *ws.host_plan;
-    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(P.n_items, 1)));
-    TESS_HIP(ws.pairs.ensure((size_t)std::max<unsigned long long>(P.total_pairs, 1)));
-    TESS_HIP(ws.partials.ensure((size_t)std::max<unsigned long long>(P.n_items, 1) * plan.T * plan.T));
-    TESS_HIP(launch_items(ws.base.p, ws.tile_items.p, B, plan.chunk, P.total_pairs, ws.items.p, s));
-    TESS_HIP(launch_scatter(ws.rec.p, ntet, B, ws.base.p, ws.pairs.p, P.total_pairs, s));
+    const unsigned long long max_items = total_pairs / (unsigned long long)chunk + (unsigned long long)ntiles;
+    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(max_items, 1)));
+    TESS_HIP(ws.pairs.ensure((size_t)std::max<unsigned long long>(total_pairs, 1)));
+    TESS_HIP(launch_plan(ws.counts.p, ws.base.p, B, chunk, ws.tile_items.p, ws.plan.p, s));
+    TESS_HIP(launch_items(ws.base.p, ws.tile_items.p, B, chunk, ws.plan.p, ws.items.p, s));
+    TESS_HIP(launch_scatter(ws.head.p, ntet, B, ws.base.p, ws.pairs.p, total_pairs, s));
+    TESS_HIP(launch_zero(ws.acc.p, npix, s));
     if (stats) TESS_HIP(hipEventRecord(ws.ev[2], s));
-    TESS_HIP(launch_raster(ws.rec.p, ws.coef64.p, (uint32_t)cap64, ws.pairs.p, ws.items.p, P.n_items,
-                           B, ws.partials.p, ws.counters.p, plan.count_fragments, s));
+    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.pairs.p, ws.items.p, max_items, ws.plan.p, B, plan.block,
+                           ws.acc.p, ws.counters.p, s));
     if (stats) TESS_HIP(hipEventRecord(ws.ev[3], s));
-    TESS_HIP(launch_finalize(ws.partials.p, ws.tile_items.p, B, image, s));
+    TESS_HIP(launch_finalize(ws.acc.p, B, image, s));
     if (stats) {
         TESS_HIP(hipEventRecord(ws.ev[4], s));
         TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters),
                                 hipMemcpyDeviceToHost, s));
+        TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
         TESS_HIP(hipStreamSynchronize(s));
         float ms = 0, t_setup = 0, t_bin = 0, t_raster = 0, t_fin = 0;
         TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
@@ -397,19 +395,21 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
         TESS_HIP(hipEventElapsedTime(&t_raster, ws.ev[2], ws.ev[3]));
         TESS_HIP(hipEventElapsedTime(&t_fin, ws.ev[3], ws.ev[4]));
         const DevCounters &c = *ws.host_counters;
+        const PlanOut &P = *ws.host_plan;
         stats->tets = c.tets;
         stats->zero_volume = c.zero_volume;
         stats->inverted = c.inverted;
         stats->fp64_dets = c.fp64_dets;
-        stats->fp64_tets = c.fp64_tets;
         stats->degenerate = c.degenerate;
         stats->fragments = c.fragments;
-        stats->fragments4 = c.fragments4;
+        stats->spans = c.spans;
         stats->bin_pairs = P.total_pairs;
         stats->max_bin = (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull);
         stats->work_items = (uint32_t)P.n_items;
-        stats->tile = plan.T;
-        stats->chunk = plan.chunk;
+        stats->tile_rows = plan.Th;
+        stats->tile_cols = plan.Tw;
+        stats->chunk = chunk;
+        stats->block = plan.block;
         stats->ms = ms;
         stats->setup_ms = t_setup;
         stats->bin_ms = t_bin;
@@ -425,9 +425,16 @@ tess_status check_project_args(tess_lattice L, const tess_view *v, const tess_tu
     tess_status st = tess_check_view(v, &L->desc);
     if (st != TESS_OK) return st;
     if (tune) {
-        if (tune->tile != 0 && tune->tile != 16 && tune->tile != 32 && tune->tile != 64)
-            return fail(TESS_EINVAL, "tune.tile must be 0, 16, 32 or 64");
+        if (tune->tile_rows < 0 || tune->tile_rows > 256)
+            return fail(TESS_EINVAL, "tune.tile_rows must be 0 (automatic) or 1..256");
+        if (tune->tile_cols != 0 && (tune->tile_cols < 16 || tune->tile_cols > kMaxTileCells))
+            return fail(TESS_EINVAL, "tune.tile_cols must be 0 (automatic) or 16..%d", kMaxTileCells);
+        const Plan p = choose_plan(v, tune);
+        if ((int64_t)p.Th * p.Tw > kMaxTileCells)
+            return fail(TESS_EINVAL, "tile of %d x %d pixels exceeds %d cells", p.Th, p.Tw, kMaxTileCells);
         if (tune->chunk != 0 && tune->chunk < 64) return fail(TESS_EINVAL, "tune.chunk must be 0 or >= 64");
+        if (tune->block != 0 && tune->block != 256 && tune->block != 512 && tune->block != 1024)
+            return fail(TESS_EINVAL, "tune.block must be 0, 256, 512 or 1024");
     }
     return TESS_OK;
 }
@@ -450,15 +457,16 @@ void add_stats(tess_stats &acc, const tess_stats &s) {
     acc.zero_volume += s.zero_volume;
     acc.inverted += s.inverted;
     acc.fp64_dets += s.fp64_dets;
-    acc.fp64_tets += s.fp64_tets;
     acc.degenerate += s.degenerate;
     acc.fragments += s.fragments;
-    acc.fragments4 += s.fragments4;
+    acc.spans += s.spans;
     acc.bin_pairs += s.bin_pairs;
     acc.max_bin = std::max(acc.max_bin, s.max_bin);
     acc.work_items += s.work_items;
-    acc.tile = s.tile;
+    acc.tile_rows = s.tile_rows;
+    acc.tile_cols = s.tile_cols;
     acc.chunk = s.chunk;
+    acc.block = s.block;
     acc.ms += s.ms;
     acc.setup_ms += s.setup_ms;
     acc.bin_ms += s.bin_ms;

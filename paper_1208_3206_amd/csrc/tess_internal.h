@@ -17,8 +17,7 @@ struct LatticeParams {
     double tet_mass;         // M / (6 cubes)
     double v0;               // mean tetrahedron volume, box volume / (6 cubes)
     double det_v0_frac;      // near-degenerate threshold (fraction of v0)
-    double det_cond_k;       // conditioning threshold on the FP32 determinant
-    double fp64_cond;        // footprints with a larger condition number raster in FP64 (< 0: all)
+    double det_cond_k;       // conditioning threshold on the FP32 determinant (< 0: always FP64)
 };
 
 // View constants.  Pixel coordinates X = (u - u_left) * inv_du with pixel
@@ -33,9 +32,9 @@ struct ViewParams {
     int32_t wrap;
 };
 
-// Screen tiling.
+// Screen tiling: tiles of Th rows x Tw columns (a row band when Tw >= W).
 struct BinParams {
-    int32_t T;               // tile edge (pixels)
+    int32_t Th, Tw;
     int32_t ntx, nty;        // tiles per axis
     int32_t W, H;
     int32_t wrap;
@@ -46,12 +45,13 @@ struct BinParams {
 
 // Per-call device counters (atomically accumulated).
 struct DevCounters {
-    unsigned long long tets, zero_volume, inverted, fp64_dets, fp64_tets, degenerate, fragments;
-    unsigned long long fragments4;
-    unsigned long long coef64_used;   // FP64 coefficient slots handed out (may exceed capacity)
+    unsigned long long tets, zero_volume, inverted, fp64_dets, degenerate;
+    unsigned long long fragments;   // (pixel, tetrahedron) pairs with rho * dl > 0
+    unsigned long long spans;       // (tetrahedron, pixel row, tile) spans rastered
+    unsigned long long pad;
 };
 
-// Result of the binning plan, read back by the host to size the raster.
+// Result of the binning pass, read back by the host to size the raster.
 struct PlanOut {
     unsigned long long total_pairs;
     unsigned long long n_items;
@@ -66,17 +66,17 @@ struct WorkItem {
     uint32_t tile;           // tile index ty * ntx + tx
 };
 
-// Per-tetrahedron raster record.  The footprint function is
+// Per-tetrahedron raster record, stored as two arrays: the head (box and
+// flags, all the binning reads) and the FP64 coefficients.  The footprint
+// function is
 //   f(p) = [all walls admit p] * max(0, min_g G_g(p)),
 //   G(p) = c[3g] + c[3g+1] * x + c[3g+2] * y,   (x, y) = p - (bx0, by0)
-// with (x, y) in pixel units.  Walls follow the G functions in c[].  When
-// REC_FP64 is set the same coefficients in FP64 are in Coef64[slot] and the
-// raster evaluates them in FP64 (the FP32 copies are then only indicative).
+// with (x, y) in pixel units; walls follow the G functions in c[].
 struct RecHead {
     uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
     uint32_t by;                 // y0 | y1 << 16
     uint32_t flags;
-    uint32_t slot;               // Coef64 index when REC_FP64
+    uint32_t spare;
 };
 // Box accessors (the box is stored as two packed 32-bit words).
 __host__ __device__ inline uint32_t pack_range(int lo, int hi) {
@@ -89,25 +89,19 @@ constexpr uint32_t REC_NW_SHIFT = 3;          // number of walls (2 bits)
 constexpr uint32_t REC_TIE0 = 1u << 5;        // wall 0 keeps pixels on its line
 constexpr uint32_t REC_TIE1 = 1u << 6;        // wall 1 keeps pixels on its line
 constexpr uint32_t REC_VALID = 1u << 7;       // some pixel centre may be covered
-constexpr uint32_t REC_FP64 = 1u << 8;        // raster this footprint in FP64
-constexpr uint32_t kNoSlot = 0xffffffffu;
 
-struct alignas(16) TetRec {
-    RecHead h;
-    float c[12];
-};
 struct alignas(16) Coef64 {
     double c[12];
 };
-static_assert(sizeof(TetRec) == 64, "record is one 64-byte line");
+static_assert(sizeof(RecHead) == 16, "record head");
 static_assert(sizeof(Coef64) == 96, "FP64 coefficient block");
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `stream` and return the launch status.
-hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, TetRec *rec, Coef64 *coef64,
-                        uint32_t coef64_cap, DevCounters *counters, hipStream_t stream);
+hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Coef64 *coef,
+                        DevCounters *counters, hipStream_t stream);
 
-hipError_t launch_count(const TetRec *rec, int64_t ntet, const BinParams &B, uint32_t *counts,
+hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
                         hipStream_t stream);
 
 // Exclusive scan of counts[n] (uint32) into base[n] (uint64); scratch must
@@ -116,27 +110,35 @@ size_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan(const uint32_t *counts, uint64_t *base, int64_t n, uint64_t *scratch,
                        hipStream_t stream);
 
+// Total pairs and the longest tile list into out (n_items is left alone).
+hipError_t launch_totals(const uint32_t *counts, const uint64_t *base, const BinParams &B,
+                         PlanOut *out, hipStream_t stream);
+
 // Per-tile chunking: writes tile_items[ntiles + 1] (exclusive scan of chunk
-// counts) and the PlanOut summary.
+// counts) and out->n_items.
 hipError_t launch_plan(const uint32_t *counts, const uint64_t *base, const BinParams &B,
                        int32_t chunk, uint32_t *tile_items, PlanOut *out, hipStream_t stream);
 
 hipError_t launch_items(const uint64_t *base, const uint32_t *tile_items, const BinParams &B,
-                        int32_t chunk, unsigned long long total_pairs, WorkItem *items,
-                        hipStream_t stream);
+                        int32_t chunk, const PlanOut *plan, WorkItem *items, hipStream_t stream);
 
 // Writes beyond pair_cap entries are dropped (memory safety if the count and
 // scatter passes ever disagreed).
-hipError_t launch_scatter(const TetRec *rec, int64_t ntet, const BinParams &B, const uint64_t *base,
+hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint64_t *base,
                           uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream);
 
-hipError_t launch_raster(const TetRec *rec, const Coef64 *coef64, uint32_t coef64_cap,
-                         const uint32_t *pairs, const WorkItem *items, uint64_t n_items,
-                         const BinParams &B, double *partials, DevCounters *counters,
-                         bool count_fragments, hipStream_t stream);
+// Clears n doubles (a kernel, so that the call can sit in a captured graph).
+hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
 
-hipError_t launch_finalize(const double *partials, const uint32_t *tile_items,
-                           const BinParams &B, float *image, hipStream_t stream);
+// Raster of the work items into the second-difference image acc[H][W];
+// max_items blocks are launched and those beyond plan->n_items return.
+hipError_t launch_raster(const RecHead *head, const Coef64 *coef, const uint32_t *pairs,
+                         const WorkItem *items, uint64_t max_items, const PlanOut *plan,
+                         const BinParams &B, int block, double *acc, DevCounters *counters,
+                         hipStream_t stream);
+
+// Row-wise double prefix sum of acc -> image (FP32).
+hipError_t launch_finalize(const double *acc, const BinParams &B, float *image, hipStream_t stream);
 
 // Build-time helpers.
 hipError_t launch_check_finite(const float *x, const float *y, const float *z, int64_t n,

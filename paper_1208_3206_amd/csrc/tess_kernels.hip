@@ -5,18 +5,18 @@
 //              SoA loads), unwrap them to the periodic image nearest corner 0,
 //              cut the cube into the six tetrahedra of the connectivity table,
 //              compute the volume determinant (Eq. Eqn:TetVolume; FP32, redone
-//              in FP64 when flagged) and the tetrahedron's screen footprint
-//              (FP64), stored as FP32 coefficients, or as FP64 ones in a side
-//              array when FP32 evaluation would be ill-conditioned.
-//   k_count    per segment of tetrahedra: tiles touched by each footprint
+//              in FP64 when flagged) and the tetrahedron's screen footprint in
+//              FP64 (record head + coefficients)
+//   k_bin      per segment of tetrahedra: count, then scatter, the ids into
+//              per-tile lists (tiles are bands of Th rows x Tw columns)
 //   k_scan     exclusive scan of the (tile, segment) counts
 //   k_plan     per-tile lists split into raster work items of <= chunk entries
-//   k_scatter  stable scatter of tetrahedron ids into the tile lists
-//   k_raster   per work item: every lane owns a strip of pixels of the tile and
-//              accumulates rho * dl of the listed tetrahedra in registers
-//              (FP32 terms summed in FP32 blocks folded into FP64; FP64 terms
-//              for the flagged footprints)
-//   k_finalize sums the work-item partials of each tile in order -> image
+//   k_raster   per work item: the tile's second-difference array lives in LDS;
+//              every lane takes whole tetrahedra and adds, for each pixel row
+//              they cross, the few break-point terms of the row's piecewise
+//              linear footprint (LDS FP64 atomics); the tile is then added to
+//              the image-sized FP64 array in HBM
+//   k_finalize per image row: two running sums of that array -> FP32 image
 //
 // The footprint.  Under orthographic projection, rho * dl of one tetrahedron
 // (the per-tetrahedron term of Eq. Eqn:TetProjection with q = m/V) is a
@@ -32,7 +32,9 @@
 // depth cancellation of that split and of the 1/V of near-flat tetrahedra.)
 // A face seen edge-on (projected determinant exactly 0) bounds the footprint
 // as a "wall": a half-plane test, with the half-open tie rule for pixel
-// centres exactly on it.
+// centres exactly on it.  Along a pixel row the pyramid is piecewise linear,
+// so the raster works on second differences of rows instead of on pixels:
+// its cost is per (tetrahedron, row), not per covered pixel.
 #include "tess_tet.h"
 
 #include <cfloat>
@@ -46,88 +48,61 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// One thread per lattice cube; writes the six records 6*cube .. 6*cube+5 and
-// hands out FP64 coefficient slots (one atomic per wavefront and tetrahedron).
+// One thread per lattice cube; writes the six records 6*cube .. 6*cube+5.
 __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
-                                               TetRec *__restrict__ rec,
-                                               Coef64 *__restrict__ coef64, uint32_t coef64_cap,
+                                               RecHead *__restrict__ head,
+                                               Coef64 *__restrict__ coef,
                                                DevCounters *__restrict__ counters) {
     CubeCounts cnt;
-    unsigned long long n_f64 = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t nloop = (L.ncubes + stride - 1) / stride;  // same trip count on every lane
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    for (int64_t it = 0; it < nloop; ++it) {
-        const int64_t cube = first + it * stride;
-        const bool live = cube < L.ncubes;
-        TetRec r[6];
-        Footprint fp[6];
-        bool want64[6] = {false, false, false, false, false, false};
-        if (live) setup_cube(L, V, cube, r, fp, want64, cnt);
+    for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
+        RecHead h[6];
+        Coef64 c[6];
+        setup_cube(L, V, cube, h, c, cnt);
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
-            const unsigned long long mask = __ballot(want64[t]);
-            if (mask) {
-                unsigned long long base = 0;
-                const int leader = __ffsll((long long)mask) - 1;
-                if (lane == leader) base = atomicAdd(&counters->coef64_used, (unsigned long long)__popcll(mask));
-                base = __shfl(base, leader, 64);
-                if (want64[t]) {
-                    const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
-                    r[t].h.flags |= REC_FP64;
-                    ++n_f64;
-                    if (slot < coef64_cap) {
-                        r[t].h.slot = (uint32_t)slot;
-                        Coef64 cf;
-#pragma unroll
-                        for (int g = 0; g < 12; ++g) cf.c[g] = fp[t].c[g];
-                        coef64[slot] = cf;
-                    }
-                }
-            }
-            if (live) rec[6 * cube + t] = r[t];
+            head[6 * cube + t] = h[t];
+            coef[6 * cube + t] = c[t];
         }
     }
     const unsigned long long n_tets = wave_sum(cnt.n_tets), n_zero = wave_sum(cnt.n_zero),
                              n_inv = wave_sum(cnt.n_inv), n_dets = wave_sum(cnt.n_dets),
                              n_deg = wave_sum(cnt.n_deg);
-    n_f64 = wave_sum(n_f64);
     if (lane == 0) {
         if (n_tets) atomicAdd(&counters->tets, n_tets);
         if (n_zero) atomicAdd(&counters->zero_volume, n_zero);
         if (n_inv) atomicAdd(&counters->inverted, n_inv);
         if (n_dets) atomicAdd(&counters->fp64_dets, n_dets);
-        if (n_f64) atomicAdd(&counters->fp64_tets, n_f64);
         if (n_deg) atomicAdd(&counters->degenerate, n_deg);
     }
 }
 
-hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, TetRec *rec, Coef64 *coef64,
-                        uint32_t coef64_cap, DevCounters *counters, hipStream_t stream) {
+hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Coef64 *coef,
+                        DevCounters *counters, hipStream_t stream) {
     const int64_t want = (L.ncubes + 255) / 256;
     const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
-    hipLaunchKernelGGL(k_setup, dim3(blocks), dim3(256), 0, stream, L, V, rec, coef64, coef64_cap,
-                       counters);
+    hipLaunchKernelGGL(k_setup, dim3(blocks), dim3(256), 0, stream, L, V, head, coef, counters);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- binning
-// One wavefront per segment of seg_len consecutive tetrahedra.  Tetrahedra
-// are visited in id order; the lanes split one tetrahedron's candidate tiles,
-// so every tile list ends up in id order (a stable counting sort on the tile
-// key) whatever the scheduling.
+// One block per segment of seg_len consecutive tetrahedra; lanes take
+// tetrahedra in turn and count (or place) them in an LDS array of per-tile
+// counters.  The order inside one segment's share of a tile list follows the
+// atomics; the raster's sums do not depend on it beyond rounding.
+constexpr int kBinBlock = 256;
+
 template <bool SCATTER>
-__global__ void __launch_bounds__(64) k_bin(const TetRec *__restrict__ rec, int64_t ntet,
-                                            BinParams B, uint32_t *__restrict__ counts,
-                                            const uint64_t *__restrict__ base,
-                                            uint32_t *__restrict__ pairs,
-                                            unsigned long long pair_cap) {
+__global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ head, int64_t ntet,
+                                                   BinParams B, uint32_t *__restrict__ counts,
+                                                   const uint64_t *__restrict__ base,
+                                                   uint32_t *__restrict__ pairs,
+                                                   unsigned long long pair_cap) {
     extern __shared__ uint32_t lds_bins[];  // per tile: count, or next slot relative to tile start
     const int ntiles = B.ntx * B.nty;
     const int seg = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < ntiles; t += 64) {
+    for (int t = threadIdx.x; t < ntiles; t += kBinBlock) {
         if (SCATTER)
             lds_bins[t] = (uint32_t)(base[(int64_t)t * B.nseg + seg] - base[(int64_t)t * B.nseg]);
         else
@@ -136,41 +111,37 @@ __global__ void __launch_bounds__(64) k_bin(const TetRec *__restrict__ rec, int6
     __syncthreads();
     const int64_t t0 = (int64_t)seg * B.seg_len;
     const int64_t t1 = min(ntet, t0 + B.seg_len);
-    for (int64_t id = t0; id < t1; ++id) {
-        const TetRec r = rec[id];
-        if (!(r.h.flags & REC_VALID)) continue;
-        TileRange tr = tet_tiles(r, B);
-        for (int s = lane; s < tr.count; s += 64) {
-            int tile;
-            if (!tet_tile(r, B, tr, s, tile)) continue;
-            // distinct tiles within one tetrahedron: no two lanes share a slot
-            const uint32_t slot = lds_bins[tile];
-            lds_bins[tile] = slot + 1;
+    for (int64_t id = t0 + threadIdx.x; id < t1; id += kBinBlock) {
+        const RecHead r = head[id];
+        if (!(r.flags & REC_VALID)) continue;
+        const TileRange tr = tet_tiles(r, B);
+        for (int s = 0; s < tr.count; ++s) {
+            const int tile = tet_tile(B, tr, s);
+            const uint32_t slot = atomicAdd(&lds_bins[tile], 1u);
             if (SCATTER) {
                 const uint64_t pos = base[(int64_t)tile * B.nseg] + slot;
                 if (pos < pair_cap) pairs[pos] = (uint32_t)id;
             }
         }
-        __builtin_amdgcn_wave_barrier();
     }
     if (!SCATTER) {
         __syncthreads();
-        for (int t = lane; t < ntiles; t += 64) counts[(int64_t)t * B.nseg + seg] = lds_bins[t];
+        for (int t = threadIdx.x; t < ntiles; t += kBinBlock) counts[(int64_t)t * B.nseg + seg] = lds_bins[t];
     }
 }
 
-hipError_t launch_count(const TetRec *rec, int64_t ntet, const BinParams &B, uint32_t *counts,
+hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
                         hipStream_t stream) {
     const size_t lds = sizeof(uint32_t) * (size_t)B.ntx * B.nty;
-    hipLaunchKernelGGL((k_bin<false>), dim3(B.nseg), dim3(64), lds, stream, rec, ntet, B, counts,
+    hipLaunchKernelGGL((k_bin<false>), dim3(B.nseg), dim3(kBinBlock), lds, stream, head, ntet, B, counts,
                        (const uint64_t *)nullptr, (uint32_t *)nullptr, 0ull);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const TetRec *rec, int64_t ntet, const BinParams &B, const uint64_t *base,
+hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint64_t *base,
                           uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream) {
     const size_t lds = sizeof(uint32_t) * (size_t)B.ntx * B.nty;
-    hipLaunchKernelGGL((k_bin<true>), dim3(B.nseg), dim3(64), lds, stream, rec, ntet, B,
+    hipLaunchKernelGGL((k_bin<true>), dim3(B.nseg), dim3(kBinBlock), lds, stream, head, ntet, B,
                        (uint32_t *)nullptr, base, pairs, pair_cap);
     return hipGetLastError();
 }
@@ -278,15 +249,36 @@ __device__ inline uint64_t tile_end(const uint64_t *base, const uint32_t *counts
     return base[last] + counts[last];
 }
 
+__global__ void __launch_bounds__(kScanBlock) k_totals(const uint32_t *__restrict__ counts,
+                                                       const uint64_t *__restrict__ base, BinParams B,
+                                                       PlanOut *__restrict__ out) {
+    __shared__ unsigned long long mx;
+    const int ntiles = B.ntx * B.nty;
+    if (threadIdx.x == 0) mx = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += kScanBlock) {
+        const uint64_t len = tile_end(base, counts, B, t, ntiles) - tile_begin(base, B, t);
+        atomicMax(&mx, (unsigned long long)len);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out->total_pairs = tile_end(base, counts, B, ntiles - 1, ntiles);
+        out->max_bin = mx;
+    }
+}
+
+hipError_t launch_totals(const uint32_t *counts, const uint64_t *base, const BinParams &B, PlanOut *out,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(kScanBlock), 0, stream, counts, base, B, out);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kScanBlock) k_plan(const uint32_t *__restrict__ counts,
                                                      const uint64_t *__restrict__ base, BinParams B,
                                                      int32_t chunk, uint32_t *__restrict__ tile_items,
                                                      PlanOut *__restrict__ out) {
     __shared__ uint64_t sh[64];
-    __shared__ unsigned long long mx;
     const int ntiles = B.ntx * B.nty;
-    if (threadIdx.x == 0) mx = 0;
-    __syncthreads();
     uint64_t carry = 0;
     for (int t0 = 0; t0 < ntiles; t0 += kScanBlock) {
         const int t = t0 + threadIdx.x;
@@ -294,7 +286,6 @@ __global__ void __launch_bounds__(kScanBlock) k_plan(const uint32_t *__restrict_
         if (t < ntiles) {
             const uint64_t len = tile_end(base, counts, B, t, ntiles) - tile_begin(base, B, t);
             chunks = (len + chunk - 1) / chunk;
-            atomicMax(&mx, (unsigned long long)len);
         }
         uint64_t total;
         const uint64_t ex = block_exclusive_scan(chunks, sh, total);
@@ -304,9 +295,7 @@ __global__ void __launch_bounds__(kScanBlock) k_plan(const uint32_t *__restrict_
     __syncthreads();
     if (threadIdx.x == 0) {
         tile_items[ntiles] = (uint32_t)carry;
-        out->total_pairs = tile_end(base, counts, B, ntiles - 1, ntiles);
         out->n_items = carry;
-        out->max_bin = mx;
     }
 }
 
@@ -318,13 +307,13 @@ hipError_t launch_plan(const uint32_t *counts, const uint64_t *base, const BinPa
 }
 
 __global__ void k_items(const uint64_t *__restrict__ base, const uint32_t *__restrict__ tile_items,
-                        BinParams B, int32_t chunk, unsigned long long total_pairs,
+                        BinParams B, int32_t chunk, const PlanOut *__restrict__ plan,
                         WorkItem *__restrict__ items) {
     const int ntiles = B.ntx * B.nty;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     const uint64_t b = tile_begin(base, B, t);
-    const uint64_t e = t + 1 < ntiles ? tile_begin(base, B, t + 1) : total_pairs;
+    const uint64_t e = t + 1 < ntiles ? tile_begin(base, B, t + 1) : plan->total_pairs;
     const uint32_t first = tile_items[t], n = tile_items[t + 1] - first;
     for (uint32_t c = 0; c < n; ++c) {
         WorkItem w;
@@ -337,135 +326,158 @@ __global__ void k_items(const uint64_t *__restrict__ base, const uint32_t *__res
 }
 
 hipError_t launch_items(const uint64_t *base, const uint32_t *tile_items, const BinParams &B,
-                        int32_t chunk, unsigned long long total_pairs, WorkItem *items,
-                        hipStream_t stream) {
+                        int32_t chunk, const PlanOut *plan, WorkItem *items, hipStream_t stream) {
     const int ntiles = B.ntx * B.nty;
     hipLaunchKernelGGL(k_items, dim3((ntiles + 255) / 256), dim3(256), 0, stream, base, tile_items,
-                       B, chunk, total_pairs, items);
+                       B, chunk, plan, items);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(double *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
+    const int64_t want = (n + 255) / 256;
+    const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- raster
-// One work item per block.  Tile T x T; every lane owns L consecutive pixels
-// of one row (T / L lanes per row), so a block has T*T/L lanes.
-// One work item per block.  Records (and FP64 coefficient blocks) are staged
-// through LDS in batches of 64 loaded by 64 threads at once, so one memory
-// latency covers 64 tetrahedra; every lane then reads each record as an LDS
-// broadcast.
-constexpr int kBatch = 64;
-
-template <int T, int L, bool COUNT>
-__global__ void __launch_bounds__(T * T / L) k_raster(const TetRec *__restrict__ rec,
-                                                      const Coef64 *__restrict__ coef64,
-                                                      uint32_t coef64_cap,
-                                                      const uint32_t *__restrict__ pairs,
-                                                      const WorkItem *__restrict__ items, BinParams B,
-                                                      double *__restrict__ partials,
-                                                      DevCounters *__restrict__ counters) {
-    __shared__ TetRec sRec[kBatch];
-    __shared__ Coef64 sCoef[kBatch];
+// One work item per block.  The block holds the tile's second-difference
+// array A[Th][Tw] (FP64) in LDS; lanes take the item's tetrahedra in turn
+// and add each pixel row's break-point terms with LDS atomics.  At the end
+// the tile is added to the image-sized array `acc` (FP64 atomics in L2; a
+// tile has several items).
+template <int TPB>
+__global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
+                                                const Coef64 *__restrict__ coef,
+                                                const uint32_t *__restrict__ pairs,
+                                                const WorkItem *__restrict__ items,
+                                                const PlanOut *__restrict__ plan, BinParams B,
+                                                double *__restrict__ acc,
+                                                DevCounters *__restrict__ counters) {
+    extern __shared__ double sA[];
+    if ((unsigned long long)blockIdx.x >= plan->n_items) return;
     const WorkItem it = items[blockIdx.x];
-    const int tid = threadIdx.x;
-    const LaneGeom g = lane_geom<T, L>(it.tile, B, tid);
-    Acc<L> acc;
-    acc.zero();
-    unsigned frags = 0, frags4 = 0;
-    int since_flush = 0;
-    for (uint32_t base = 0; base < it.count; base += kBatch) {
-        const uint32_t nb = it.count - base < (uint32_t)kBatch ? it.count - base : (uint32_t)kBatch;
-        if (tid < (int)nb) {
-            TetRec r;
-            r.h.flags = 0;
-            const uint32_t id = pairs[it.first + base + tid];
-            if (id < B.ntet) {
-                r = rec[id];
-                if (r.h.flags & REC_FP64) {
-                    if (r.h.slot < coef64_cap)
-                        sCoef[tid] = coef64[r.h.slot];
-                    else
-                        r.h.flags = 0;  // slot overflow: the host reruns the call
-                }
-            }
-            sRec[tid] = r;
-        }
-        __syncthreads();
-        for (uint32_t j = 0; j < nb; ++j) {
-            const TetRec r = sRec[j];
-            if (r.h.flags & REC_VALID) raster_record<L, COUNT>(r, sCoef[j].c, B, g, acc, frags, frags4);
-            if (++since_flush == kFlushEvery) {
-                acc.flush();
-                since_flush = 0;
-            }
-        }
-        __syncthreads();
+    const int tx = (int)(it.tile % (uint32_t)B.ntx), ty = (int)(it.tile / (uint32_t)B.ntx);
+    const int tx0 = tx * B.Tw, ty0 = ty * B.Th;
+    const int n = min(B.Tw, B.W - tx0), rows = min(B.Th, B.H - ty0);
+    const int tsize = B.Th * B.Tw;
+    for (int i = threadIdx.x; i < tsize; i += TPB) sA[i] = 0.0;
+    __syncthreads();
+    uint32_t frags = 0, spans = 0;
+    const int Tw = B.Tw;
+    for (uint32_t e = threadIdx.x; e < it.count; e += TPB) {
+        const uint32_t id = pairs[it.first + e];
+        if (id >= B.ntet) continue;
+        const RecHead h = head[id];
+        if (!(h.flags & REC_VALID)) continue;
+        frags += raster_pair(h, coef[id].c, B, tx0, ty0, n, rows,
+                             [&](int row, int j, double v) { atomicAdd(&sA[row * Tw + j], v); }, spans);
     }
-    acc.flush();
-    constexpr int SPR = T / L;
-    const int row = tid / SPR, strip = tid % SPR;
-    double *out = partials + (size_t)blockIdx.x * (T * T) + (size_t)row * T + strip * L;
-#pragma unroll
-    for (int k = 0; k < L; ++k) out[k] = acc.d[k];
-    if (COUNT) {
-        unsigned long long f = wave_sum((unsigned long long)frags);
-        unsigned long long f4 = wave_sum((unsigned long long)frags4);
-        if ((tid & 63) == 0 && f) atomicAdd(&counters->fragments, f);
-        if ((tid & 63) == 0 && f4) atomicAdd(&counters->fragments4, f4);
+    __syncthreads();
+    for (int i = threadIdx.x; i < rows * Tw; i += TPB) {
+        const int r = i / Tw, c = i - r * Tw;
+        const double v = sA[i];
+        if (c < n && v != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + tx0 + c], v);
+    }
+    const unsigned long long f = wave_sum((unsigned long long)frags);
+    const unsigned long long sp = wave_sum((unsigned long long)spans);
+    if ((threadIdx.x & 63) == 0) {
+        if (f) atomicAdd(&counters->fragments, f);
+        if (sp) atomicAdd(&counters->spans, sp);
     }
 }
 
-template <int T, int L>
-static hipError_t launch_raster_t(const TetRec *rec, const Coef64 *coef64, uint32_t coef64_cap,
-                                  const uint32_t *pairs, const WorkItem *items, uint64_t n_items,
-                                  const BinParams &B, double *partials, DevCounters *counters,
-                                  bool count_fragments, hipStream_t stream) {
-    if (n_items == 0) return hipSuccess;
-    if (count_fragments)
-        hipLaunchKernelGGL((k_raster<T, L, true>), dim3((unsigned)n_items), dim3(T * T / L), 0, stream,
-                           rec, coef64, coef64_cap, pairs, items, B, partials, counters);
-    else
-        hipLaunchKernelGGL((k_raster<T, L, false>), dim3((unsigned)n_items), dim3(T * T / L), 0, stream,
-                           rec, coef64, coef64_cap, pairs, items, B, partials, counters);
-    return hipGetLastError();
-}
-
-hipError_t launch_raster(const TetRec *rec, const Coef64 *coef64, uint32_t coef64_cap,
-                         const uint32_t *pairs, const WorkItem *items, uint64_t n_items,
-                         const BinParams &B, double *partials, DevCounters *counters,
-                         bool count_fragments, hipStream_t stream) {
-    switch (B.T) {
-        case 16:
-            return launch_raster_t<16, 4>(rec, coef64, coef64_cap, pairs, items, n_items, B,
-                                          partials, counters, count_fragments, stream);
-        case 32:
-            return launch_raster_t<32, 16>(rec, coef64, coef64_cap, pairs, items, n_items, B,
-                                           partials, counters, count_fragments, stream);
-        case 64:
-            return launch_raster_t<64, 16>(rec, coef64, coef64_cap, pairs, items, n_items, B,
-                                           partials, counters, count_fragments, stream);
+hipError_t launch_raster(const RecHead *head, const Coef64 *coef, const uint32_t *pairs,
+                         const WorkItem *items, uint64_t max_items, const PlanOut *plan,
+                         const BinParams &B, int block, double *acc, DevCounters *counters,
+                         hipStream_t stream) {
+    if (max_items == 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)B.Th * B.Tw;
+    switch (block) {
+        case 256:
+            hipLaunchKernelGGL((k_raster<256>), dim3((unsigned)max_items), dim3(256), lds, stream, head, coef,
+                               pairs, items, plan, B, acc, counters);
+            break;
+        case 512:
+            hipLaunchKernelGGL((k_raster<512>), dim3((unsigned)max_items), dim3(512), lds, stream, head, coef,
+                               pairs, items, plan, B, acc, counters);
+            break;
+        case 1024:
+            hipLaunchKernelGGL((k_raster<1024>), dim3((unsigned)max_items), dim3(1024), lds, stream, head,
+                               coef, pairs, items, plan, B, acc, counters);
+            break;
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- finalize
-__global__ void k_finalize(const double *__restrict__ partials, const uint32_t *__restrict__ tile_items,
-                           BinParams B, float *__restrict__ image) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)B.W * B.H) return;
-    const int ix = (int)(p % B.W), iy = (int)(p / B.W);
-    const int tile = (iy / B.T) * B.ntx + ix / B.T;
-    const int local = (iy % B.T) * B.T + ix % B.T;
-    double s = 0.0;
-    for (uint32_t it = tile_items[tile]; it < tile_items[tile + 1]; ++it)
-        s += partials[(size_t)it * B.T * B.T + local];
-    image[p] = (float)s;
+// One block per image row: f = running sum of the running sum of acc's row.
+// Column densities are >= 0; a sum that rounding left a little below zero (a
+// pixel no footprint covers, next to ones that do) is written as 0.
+constexpr int kFinBlock = 256;
+
+__device__ inline double block_exclusive_scan_f64(double v, double *sh, double &total) {
+    // sh: kFinBlock / 64 + 1 entries; returns the exclusive prefix of v
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    double before = 0.0, all = 0.0;
+    for (int w = 0; w < kFinBlock / 64; ++w) {
+        if (w < wave) before += sh[w];
+        all += sh[w];
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - v;
 }
 
-hipError_t launch_finalize(const double *partials, const uint32_t *tile_items, const BinParams &B,
-                           float *image, hipStream_t stream) {
-    const int64_t n = (int64_t)B.W * B.H;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, partials,
-                       tile_items, B, image);
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const double *__restrict__ acc, BinParams B,
+                                                        float *__restrict__ image) {
+    __shared__ double sh[kFinBlock / 64 + 1];
+    const int y = blockIdx.x;
+    const double *row = acc + (int64_t)y * B.W;
+    float *out = image + (int64_t)y * B.W;
+    const int per = (B.W + kFinBlock - 1) / kFinBlock;  // consecutive entries per thread
+    const int i0 = threadIdx.x * per;
+    // pass 1: d1 = running sum of A; the thread keeps its entries' d1 sum and
+    // their d1-weighted contribution to the second running sum
+    double s1 = 0.0;
+    for (int k = 0; k < per; ++k)
+        if (i0 + k < B.W) s1 += row[i0 + k];
+    double tot;
+    const double d1_in = block_exclusive_scan_f64(s1, sh, tot);  // d1 just before i0
+    // pass 2: local second sum with the incoming d1
+    double s2 = 0.0, d1 = d1_in;
+    for (int k = 0; k < per; ++k)
+        if (i0 + k < B.W) {
+            d1 += row[i0 + k];
+            s2 += d1;
+        }
+    const double f_in = block_exclusive_scan_f64(s2, sh, tot);  // f just before i0
+    double f = f_in;
+    d1 = d1_in;
+    for (int k = 0; k < per; ++k)
+        if (i0 + k < B.W) {
+            d1 += row[i0 + k];
+            f += d1;
+            out[i0 + k] = (float)fmax(f, 0.0);
+        }
+}
+
+hipError_t launch_finalize(const double *acc, const BinParams &B, float *image, hipStream_t stream) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)B.H), dim3(kFinBlock), 0, stream, acc, B, image);
     return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ TESS_HD inline int ceil_div(int a, int b) {  // b > 0
 // Volume determinant (times 6) in FP64, evaluated term by term without
 // contraction so that an exact zero is decided the same way as by a plain
 // left-to-right FP64 evaluation of Eq. Eqn:TetVolume.
-TESS_HD __attribute__((noinline)) double det6_fp64(const double a[3], const double b[3], const double c[3]) {
+TESS_HD inline double det6_fp64(const double a[3], const double b[3], const double c[3]) {
 #pragma clang fp contract(off)
     double cx = b[1] * c[2] - b[2] * c[1];
     double cy = b[2] * c[0] - b[0] * c[2];
@@ -65,15 +65,12 @@ struct Footprint {
     double c[12];
     int ng, nw;
     uint32_t ties;
-    double cond;  // FP32 error amplification: max over the box of sum |terms| / peak
 };
 
 // Builds the G functions and walls of one tetrahedron from its projected
-// vertices q (pixel units, relative to the record origin); X, Y are the
-// record's box sizes in pixels.  Returns false when the projection has zero
-// area (no pixel can receive anything).
-TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mass_px, double X,
-                                 double Y, Footprint &fp) {
+// vertices q (pixel units, relative to the record origin).  Returns false
+// when the projection has zero area (no pixel can receive anything).
+TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mass_px, Footprint &fp) {
     double D[4];
     double sumD = 0.0;
 #pragma unroll
@@ -85,12 +82,8 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
         sumD += fabs(D[a]);
     }
     if (sumD == 0.0) return false;
-    // the faces cover the silhouette twice, so its area is sum|D|/4 and the
-    // apex value 3 m / area is 2 mass_px / sum|D|
-    const double peak = 2.0 * mass_px / sumD;
     int ng = 0, nw = 0;
     uint32_t ties = 0;
-    double cond = 0.0;
 #pragma unroll
     for (int g = 0; g < 12; ++g) fp.c[g] = 0.0;
     // silhouette edges: q_k and q_l on the same side of edge (i, j)
@@ -108,7 +101,6 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
             fp.c[3 * ng + 0] = aa;
             fp.c[3 * ng + 1] = bb;
             fp.c[3 * ng + 2] = cc;
-            cond = fmax(cond, (fabs(aa) + fabs(bb) * X + fabs(cc) * Y) / peak);
             ++ng;
         }
     }
@@ -143,7 +135,6 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
     fp.ng = ng;
     fp.nw = nw;
     fp.ties = ties;
-    fp.cond = cond;
     return true;
 }
 
@@ -154,12 +145,11 @@ struct CubeCounts {
 };
 
 // Setup of the six tetrahedra of lattice cube `cube`: gather and unwrap the
-// corners, volume determinant with its FP64 fallback, footprint.  r[t] is the
-// record of tetrahedron 6*cube + t (flags 0 when it can cover no pixel);
-// want64[t] tells whether its footprint is to be rastered in FP64, with the
-// FP64 coefficients in fp[t].
-TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, TetRec r[6],
-                               Footprint fp[6], bool want64[6], CubeCounts &cnt) {
+// corners, volume determinant with its FP64 fallback, footprint.  head[t] and
+// coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
+// cover no pixel centre).
+TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
+                               Coef64 coef[6], CubeCounts &cnt) {
     const int64_t i = cube % L.c[0];
     const int64_t rest = cube / L.c[0];
     const int64_t j = rest % L.c[1];
@@ -206,14 +196,13 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
         const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
-        TetRec &R = r[t];
-        R.h.bx = 0;
-        R.h.by = 0;
-        R.h.flags = 0;
-        R.h.slot = kNoSlot;
+        RecHead &R = head[t];
+        R.bx = 0;
+        R.by = 0;
+        R.flags = 0;
+        R.spare = 0;
 #pragma unroll
-        for (int g = 0; g < 12; ++g) R.c[g] = 0.f;
-        want64[t] = false;
+        for (int g = 0; g < 12; ++g) coef[t].c[g] = 0.0;
         // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
         // error bound, FP64 when the bound cannot certify it or it is small
         double a64[3], b64[3], c64[3];
@@ -233,7 +222,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         const float perm = fabsf(a[0]) * (fabsf(p1) + fabsf(p2)) + fabsf(a[1]) * (fabsf(p3) + fabsf(p4)) +
                            fabsf(a[2]) * (fabsf(p5) + fabsf(p6));
         const double ad = fabs((double)d32);
-        const bool flagged = ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
+        const bool flagged = L.det_cond_k < 0.0 || ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
                              ad < 2.0 * 6.0 * L.det_v0_frac * L.v0;
         const double det6 = flagged ? det6_fp64(a64, b64, c64) : (double)d32;
         cnt.n_dets += flagged ? 1 : 0;
@@ -269,20 +258,19 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             qx[m] = PX[vi[m]] - (double)ix0;
             qy[m] = PY[vi[m]] - (double)iy0;
         }
-        if (!footprint(qx, qy, V.mass_px, (double)(ix1 - ix0 + 1), (double)(iy1 - iy0 + 1), fp[t]))
-            continue;
-        R.h.bx = pack_range(ix0, ix1);
-        R.h.by = pack_range(iy0, iy1);
-        R.h.flags = (uint32_t)fp[t].ng | ((uint32_t)fp[t].nw << REC_NW_SHIFT) | fp[t].ties | REC_VALID;
+        Footprint fp;
+        if (!footprint(qx, qy, V.mass_px, fp)) continue;
+        R.bx = pack_range(ix0, ix1);
+        R.by = pack_range(iy0, iy1);
+        R.flags = (uint32_t)fp.ng | ((uint32_t)fp.nw << REC_NW_SHIFT) | fp.ties | REC_VALID;
 #pragma unroll
-        for (int g = 0; g < 12; ++g) R.c[g] = (float)fp[t].c[g];
-        want64[t] = L.fp64_cond < 0.0 || fp[t].cond > L.fp64_cond;
+        for (int g = 0; g < 12; ++g) coef[t].c[g] = fp.c[g];
     }
 }
 
 // ---------------------------------------------------------------- binning
-// Tiles of one axis touched by the pixel range [b0, b1]: `count` tiles
-// starting at `start`, taken modulo the tile count under wrap.
+// Tiles of one axis touched by the pixel range [b0, b1] (tile size T):
+// `count` tiles starting at `start`, taken modulo the tile count under wrap.
 TESS_HD inline void axis_tiles(int b0, int b1, int n, int T, int ntiles, int wrap,
                                   int &start, int &count) {
     if (!wrap) {
@@ -303,275 +291,270 @@ TESS_HD inline void axis_tiles(int b0, int b1, int n, int T, int ntiles, int wra
 }
 
 // Offsets k (in units of the image size) for which tile pixels [t0, t1]
-// shifted by k*n meet [b0, b1].
-TESS_HD inline void axis_offsets(int t0, int t1, int b0, int b1, int n, int wrap, int &k0,
-                                    int &k1) {
-    if (!wrap) { k0 = 0; k1 = 0; return; }
-    k0 = ceil_div(b0 - t1, n);
-    k1 = floor_div(b1 - t0, n);
-}
-
-// Does some pixel centre of the rectangle [x0, x1] x [y0, y1] (pixel indices
-// in the record's frame, already inside its bounding box) possibly get a
-// nonzero value?  Conservative: rejects only when one function is negative
-// at all four corner pixel centres; FP64-flagged footprints are never culled.
-TESS_HD inline bool rect_may_cover(const TetRec &r, int x0, int x1, int y0, int y1) {
-    if (r.h.flags & REC_FP64) return true;
-    const float xa = (float)(x0 - range_lo(r.h.bx)) + 0.5f, xb = (float)(x1 - range_lo(r.h.bx)) + 0.5f;
-    const float ya = (float)(y0 - range_lo(r.h.by)) + 0.5f, yb = (float)(y1 - range_lo(r.h.by)) + 0.5f;
-    const int nf = (int)(r.h.flags & REC_NG_MASK) + (int)((r.h.flags >> REC_NW_SHIFT) & 3u);
-    for (int g = 0; g < nf; ++g) {
-        const float a = r.c[3 * g], b = r.c[3 * g + 1], c = r.c[3 * g + 2];
-        const float mx = a + (b > 0 ? b * xb : b * xa) + (c > 0 ? c * yb : c * ya);
-        // margin: values this small relative to the coefficients are rounding
-        if (mx < -1e-5f * (fabsf(a) + fabsf(b) * fmaxf(fabsf(xa), fabsf(xb)) +
-                           fabsf(c) * fmaxf(fabsf(ya), fabsf(yb))))
-            return false;
-    }
-    return true;
-}
-
-TESS_HD inline bool tile_accept(const TetRec &r, int tx, int ty, const BinParams &B) {
-    const int tx0 = tx * B.T, tx1 = min(tx0 + B.T, B.W) - 1;
-    const int ty0 = ty * B.T, ty1 = min(ty0 + B.T, B.H) - 1;
-    int kx0, kx1, ky0, ky1;
-    axis_offsets(tx0, tx1, range_lo(r.h.bx), range_hi(r.h.bx), B.W, B.wrap, kx0, kx1);
-    axis_offsets(ty0, ty1, range_lo(r.h.by), range_hi(r.h.by), B.H, B.wrap, ky0, ky1);
-    for (int ky = ky0; ky <= ky1; ++ky)
-        for (int kx = kx0; kx <= kx1; ++kx) {
-            const int x0 = max(tx0 + kx * B.W, (int)range_lo(r.h.bx)), x1 = min(tx1 + kx * B.W, (int)range_hi(r.h.bx));
-            const int y0 = max(ty0 + ky * B.H, (int)range_lo(r.h.by)), y1 = min(ty1 + ky * B.H, (int)range_hi(r.h.by));
-            if (x0 > x1 || y0 > y1) continue;
-            if (rect_may_cover(r, x0, x1, y0, y1)) return true;
-        }
-    return false;
-}
-
-
-// ----------------------------------------------------------------- raster
-// Adds rho*dl of one footprint to the lane's L consecutive pixels; (x, y) is
-// the first pixel centre in the record frame.  NG = 3 or 4, no walls.
-template <typename R, int L, int NG, typename Sum>
-TESS_HD inline void eval_fast(const R *c, R x, R y, Sum (&acc)[L]) {
-    // g_q at the strip's first pixel centre, then one step of b_q per pixel
-    R g[NG], b[NG];
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-        b[q] = c[3 * q + 1];
-        g[q] = c[3 * q] + b[q] * x + c[3 * q + 2] * y;
-    }
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        R m = fmin(g[0], fmin(g[1], g[2]));
-        if (NG == 4) m = fmin(m, g[NG - 1]);
-        acc[k] += (Sum)fmax(m, (R)0);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) g[q] += b[q];
-    }
-}
-
-// Any number of G functions plus walls with their tie bits.  With COUNT the
-// number of covered pixels among the first `valid` ones is returned instead
-// of accumulating.
-template <typename R, int L, bool COUNT, typename Sum>
-TESS_HD inline unsigned eval_general(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L],
-                                        int kmin, int kmax) {
-    const int ng = (int)(flags & REC_NG_MASK);
-    const int nw = (int)((flags >> REC_NW_SHIFT) & 3u);
-    unsigned n = 0;
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const R xk = x + (R)k;
-        bool in = true;
-        for (int q = 0; q < nw; ++q) {
-            const R *w = c + 3 * (ng + q);
-            const R wv = w[0] + w[1] * xk + w[2] * y;
-            const bool tie = (flags & (q == 0 ? REC_TIE0 : REC_TIE1)) != 0;
-            in = in && (wv > (R)0 || (wv == (R)0 && tie));
-        }
-        R m = (R)INFINITY;
-        for (int q = 0; q < ng; ++q) m = fmin(m, c[3 * q] + c[3 * q + 1] * xk + c[3 * q + 2] * y);
-        if (COUNT)
-            n += (in && m > (R)0 && k >= kmin && k <= kmax) ? 1u : 0u;
-        else if (in)
-            acc[k] += (Sum)fmax(m, (R)0);
-    }
-    return n;
-}
-
-// Rare paths kept out of line so the hot loop keeps its registers: footprints
-// with walls (edge-on faces), and FP64 footprints.
-template <typename R, int L, typename Sum>
-TESS_HD __attribute__((noinline)) void eval_slow(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L]) {
-    const int ng = (int)(flags & REC_NG_MASK);
-    const bool walls = ((flags >> REC_NW_SHIFT) & 3u) != 0;
-    if (!walls && ng == 4)
-        eval_fast<R, L, 4>(c, x, y, acc);
-    else if (!walls && ng == 3)
-        eval_fast<R, L, 3>(c, x, y, acc);
-    else
-        eval_general<R, L, false>(c, flags, x, y, acc, 0, L - 1);
-}
-
-template <typename R, int L, typename Sum>
-TESS_HD inline void eval_any(const R *c, uint32_t flags, R x, R y, Sum (&acc)[L]) {
-    const int ng = (int)(flags & REC_NG_MASK);
-    const bool walls = ((flags >> REC_NW_SHIFT) & 3u) != 0;
-    if (!walls && ng == 4)
-        eval_fast<R, L, 4>(c, x, y, acc);
-    else if (!walls && ng == 3)
-        eval_fast<R, L, 3>(c, x, y, acc);
-    else
-        eval_slow<R, L>(c, flags, x, y, acc);
-}
-
-// Candidate tiles of one record: tx = (sx + s % cx) mod ntx, ty = (sy + s / cx)
-// mod nty for s < count = cx * cy.
-struct TileRange {
-    int sx, cx, sy, cy, count;
-};
-
-TESS_HD inline TileRange tet_tiles(const TetRec &r, const BinParams &B) {
-    TileRange t;
-    axis_tiles(range_lo(r.h.bx), range_hi(r.h.bx), B.W, B.T, B.ntx, B.wrap, t.sx, t.cx);
-    axis_tiles(range_lo(r.h.by), range_hi(r.h.by), B.H, B.T, B.nty, B.wrap, t.sy, t.cy);
-    t.count = t.cx * t.cy;
-    return t;
-}
-
-// Candidate s of the record: its tile index, and whether the footprint may
-// cover a pixel centre there.
-TESS_HD inline bool tet_tile(const TetRec &r, const BinParams &B, const TileRange &t, int s, int &tile) {
-    int tx = t.sx + s % t.cx, ty = t.sy + s / t.cx;
-    if (tx >= B.ntx) tx -= B.ntx;
-    if (ty >= B.nty) ty -= B.nty;
-    tile = ty * B.ntx + tx;
-    return tile_accept(r, tx, ty, B);
-}
-
-// Accumulator of one lane's L pixels: FP32 block sums folded into FP64, and
-// FP64 terms added to the FP64 part directly.
-constexpr int kFlushEvery = 32;  // FP32 partial sums are folded into FP64 this often
-
-template <int L>
-struct Acc {
-    float s[L];
-    double d[L];
-    TESS_HD void zero() {
-#pragma unroll
-        for (int k = 0; k < L; ++k) { s[k] = 0.f; d[k] = 0.0; }
-    }
-    TESS_HD void flush() {
-#pragma unroll
-        for (int k = 0; k < L; ++k) { d[k] += (double)s[k]; s[k] = 0.f; }
-    }
-};
-
-
-// Geometry of one raster lane: the L-pixel strip of lane `tid` of the T x T
-// tile `tile` (T / L lanes per row).
-struct LaneGeom {
-    int tile_x0, tile_x1, tile_y0, tile_y1;  // tile pixels (inclusive, clipped to the image)
-    int px0, py;                             // first pixel of the strip
-    int wy0, wy1;                            // rows of the lane's wavefront
-    int valid;                               // strip pixels inside the image
-    bool live;                               // some strip pixel inside the image
-};
-
-template <int T, int L>
-TESS_HD inline LaneGeom lane_geom(uint32_t tile, const BinParams &B, int tid) {
-    constexpr int SPR = T / L;                 // strips per row
-    constexpr int RPW = 64 / SPR;              // rows per wavefront
-    LaneGeom g;
-    const int tx = (int)(tile % (uint32_t)B.ntx), ty = (int)(tile / (uint32_t)B.ntx);
-    const int row = tid / SPR, strip = tid % SPR;
-    g.tile_x0 = tx * T;
-    g.tile_y0 = ty * T;
-    g.tile_x1 = (g.tile_x0 + T < B.W ? g.tile_x0 + T : B.W) - 1;
-    g.tile_y1 = (g.tile_y0 + T < B.H ? g.tile_y0 + T : B.H) - 1;
-    g.px0 = g.tile_x0 + strip * L;
-    g.py = g.tile_y0 + row;
-    g.wy0 = g.tile_y0 + (tid / 64) * RPW;
-    g.wy1 = g.wy0 + RPW - 1;
-    // lanes whose pixels lie beyond the image (ragged last tiles) stay idle
-    g.live = g.py <= g.tile_y1 && g.px0 <= g.tile_x1;
-    g.valid = L < g.tile_x1 - g.px0 + 1 ? L : g.tile_x1 - g.px0 + 1;
-    return g;
-}
-
-// Periodic offsets of a record against a tile: a box inside the image needs
-// none (fast path), otherwise the general division.
-TESS_HD inline void rec_offsets(int t0, int t1, int b0, int b1, int n, int wrap, int &k0, int &k1) {
+// shifted by k*n meet [b0, b1]; a box inside the image needs only k = 0.
+TESS_HD inline void axis_offsets(int t0, int t1, int b0, int b1, int n, int wrap, int &k0, int &k1) {
     if (!wrap || (b0 >= 0 && b1 < n)) {
         k0 = 0;
         k1 = 0;
         return;
     }
-    axis_offsets(t0, t1, b0, b1, n, wrap, k0, k1);
+    k0 = ceil_div(b0 - t1, n);
+    k1 = floor_div(b1 - t0, n);
 }
 
-// Adds one record's footprint to the lane's strip (every periodic offset that
-// meets the tile).  c64: the record's FP64 coefficients when REC_FP64.
-template <int L, bool COUNT>
-TESS_HD inline void raster_record(const TetRec &r, const double *c64, const BinParams &B,
-                                  const LaneGeom &g, Acc<L> &acc, unsigned &frags, unsigned &frags4) {
-    const bool f64 = (r.h.flags & REC_FP64) != 0;
-    const int bx0 = range_lo(r.h.bx), bx1 = range_hi(r.h.bx);
-    const int by0 = range_lo(r.h.by), by1 = range_hi(r.h.by);
-    int kx0, kx1, ky0, ky1;
-    rec_offsets(g.tile_x0, g.tile_x1, bx0, bx1, B.W, B.wrap, kx0, kx1);
-    rec_offsets(g.tile_y0, g.tile_y1, by0, by1, B.H, B.wrap, ky0, ky1);
-    for (int ky = ky0; ky <= ky1; ++ky) {
-        // wavefront-uniform row test
-        if (g.wy1 + ky * B.H < by0 || g.wy0 + ky * B.H > by1) continue;
-        for (int kx = kx0; kx <= kx1; ++kx) {
-            const int gy = g.py + ky * B.H;
-            const int gx0 = g.px0 + kx * B.W;
-            if (!g.live || gy < by0 || gy > by1 || gx0 + L - 1 < bx0 || gx0 > bx1) continue;
-            unsigned nf = 0;
-            const int kmin = bx0 - gx0 > 0 ? bx0 - gx0 : 0;
-            const int kmax = g.valid - 1 < bx1 - gx0 ? g.valid - 1 : bx1 - gx0;
-            if (!f64) {
-                const float x = (float)(gx0 - bx0) + 0.5f;
-                const float y = (float)(gy - by0) + 0.5f;
-                eval_any<float, L>(r.c, r.h.flags, x, y, acc.s);
-                if (COUNT) nf = eval_general<float, L, true>(r.c, r.h.flags, x, y, acc.s, kmin, kmax);
-            } else {
-                const double x = (double)(gx0 - bx0) + 0.5;
-                const double y = (double)(gy - by0) + 0.5;
-                eval_slow<double, L>(c64, r.h.flags, x, y, acc.d);
-                if (COUNT) nf = eval_general<double, L, true>(c64, r.h.flags, x, y, acc.d, kmin, kmax);
+// Columns a record writes: its pixel box plus two, since the last break point
+// of a row (the end of the footprint) writes the two entries after it.
+constexpr int kRightReach = 2;
+
+// Candidate tiles of one record: tx = (sx + s % cx) mod ntx, ty = (sy + s / cx)
+// mod nty for s < count = cx * cy.  Every tile of the box is a candidate:
+// the tiles are wide row bands, so the box and the footprint meet nearly the
+// same ones.
+struct TileRange {
+    int sx, cx, sy, cy, count;
+};
+
+TESS_HD inline TileRange tet_tiles(const RecHead &r, const BinParams &B) {
+    TileRange t;
+    axis_tiles(range_lo(r.bx), range_hi(r.bx) + kRightReach, B.W, B.Tw, B.ntx, B.wrap, t.sx, t.cx);
+    axis_tiles(range_lo(r.by), range_hi(r.by), B.H, B.Th, B.nty, B.wrap, t.sy, t.cy);
+    t.count = t.cx * t.cy;
+    return t;
+}
+
+TESS_HD inline int tet_tile(const BinParams &B, const TileRange &t, int s) {
+    int tx = t.sx + s % t.cx, ty = t.sy + s / t.cx;
+    if (tx >= B.ntx) tx -= B.ntx;
+    if (ty >= B.nty) ty -= B.nty;
+    return ty * B.ntx + tx;
+}
+
+// ----------------------------------------------------------------- raster
+// Along one pixel row the footprint f is piecewise linear in x: the lower
+// envelope of the lines G_g(., Y), cut to where it is positive and to the
+// walls.  Sampled at the pixel centres u = 0, 1, ..., n-1 of a tile row it is
+// fully described by its second differences
+//     A[k] = f(k) - 2 f(k-1) + f(k-2)      (f(-1) = f(-2) = 0),
+// which vanish except next to the break points, and f is recovered by two
+// running sums.  A break point at u* after which the function gains a step J
+// and a slope change D (it adds J + D (k - u*) to every sample k > u*) adds
+//     J + D phi  to A[j]  and  D (1 - phi) - J  to A[j+1],
+// j = floor(u*) + 1, phi = j - u*.  The running sums run along whole image
+// rows, so every break point keeps its true position and a tile writes only
+// its own entries; break points left of the image are moved to its left edge
+// (half a pixel before column 0) with J taken there, which gives the same
+// samples in the image.
+
+constexpr double kInf = __builtin_huge_val();
+
+// Per-record geometry of the row spans, in the record frame.  The lines are
+// sorted by decreasing x slope b, so that along a row the envelope visits them
+// in index order; lines beyond ng are fillers (never active, bound nothing).
+struct SpanGeom {
+    double a[4], b[4], c[4];   // G_g = a + b X + c Y  (fillers: a = +inf)
+    double r[4];               // -1 / b_g (G_g = 0 at X = r_g * (a_g + c_g Y))
+    double q[6];               // pair p = (h < g): 1 / (b_h - b_g), 1 for fillers
+    uint32_t lpos, lneg;       // bit g: b_g > 0 (left bound), b_g < 0 (right bound)
+    uint32_t flat;             // bit g: b_g == 0 (G_g constant along a row)
+    uint32_t fill;             // bit g: filler line
+    uint32_t par;              // bit p: parallel pair (b_h == b_g)
+    uint32_t nw, ties;         // walls: count and tie bits
+    uint32_t wall0;            // index of the first wall coefficient (3 ng)
+};
+
+// Pair index of lines (h, g), h < g < 4.
+constexpr int kPair[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+
+TESS_HD inline void cswap_line(double &a0, double &b0, double &c0, double &k0, double &a1, double &b1,
+                               double &c1, double &k1) {
+    const bool sw = k1 > k0;
+    const double ta = sw ? a1 : a0, tb = sw ? b1 : b0, tc = sw ? c1 : c0, tk = sw ? k1 : k0;
+    a1 = sw ? a0 : a1; b1 = sw ? b0 : b1; c1 = sw ? c0 : c1; k1 = sw ? k0 : k1;
+    a0 = ta; b0 = tb; c0 = tc; k0 = tk;
+}
+
+TESS_HD inline void span_geom(uint32_t flags, const double *cf, SpanGeom &G) {
+    const int ng = (int)(flags & REC_NG_MASK);
+    double a[4], b[4], c[4], k[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const bool real = g < ng;
+        a[g] = real ? cf[3 * g] : kInf;
+        b[g] = real ? cf[3 * g + 1] : 0.0;
+        c[g] = real ? cf[3 * g + 2] : 0.0;
+        k[g] = real ? b[g] : -kInf;
+    }
+    // sorting network, decreasing key; fillers (key -inf) end last
+    cswap_line(a[0], b[0], c[0], k[0], a[1], b[1], c[1], k[1]);
+    cswap_line(a[2], b[2], c[2], k[2], a[3], b[3], c[3], k[3]);
+    cswap_line(a[0], b[0], c[0], k[0], a[2], b[2], c[2], k[2]);
+    cswap_line(a[1], b[1], c[1], k[1], a[3], b[3], c[3], k[3]);
+    cswap_line(a[1], b[1], c[1], k[1], a[2], b[2], c[2], k[2]);
+    G.lpos = G.lneg = G.flat = G.fill = G.par = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        G.a[g] = a[g];
+        G.b[g] = b[g];
+        G.c[g] = c[g];
+        const bool real = g < ng;
+        G.r[g] = (real && b[g] != 0.0) ? -1.0 / b[g] : 0.0;
+        if (!real) G.fill |= 1u << g;
+        else if (b[g] > 0.0) G.lpos |= 1u << g;
+        else if (b[g] < 0.0) G.lneg |= 1u << g;
+        else G.flat |= 1u << g;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int g = h + 1; g < 4; ++g) {
+            const int p = kPair[h][g];
+            const double den = b[h] - b[g];  // >= 0 by the sort
+            double q = 1.0;
+            if (g < ng) {
+                if (den > 0.0) q = 1.0 / den;
+                else G.par |= 1u << p;
             }
-            frags += nf;
-            if ((r.h.flags & REC_NG_MASK) == 4) frags4 += nf;
+            G.q[p] = q;
         }
-    }
+    G.nw = (flags >> REC_NW_SHIFT) & 3u;
+    G.ties = (flags & REC_TIE0 ? 1u : 0u) | (flags & REC_TIE1 ? 2u : 0u);
+    G.wall0 = 3u * (uint32_t)ng;
 }
 
-// The work of one raster lane over a work item's list, in list order (the
-// kernel does the same with records staged through LDS).
-template <int T, int L, bool COUNT>
-TESS_HD inline void raster_lane(const TetRec *rec, const Coef64 *coef64, uint32_t coef64_cap,
-                                const uint32_t *pairs, const WorkItem &it, const BinParams &B, int tid,
-                                Acc<L> &acc, unsigned &frags, unsigned &frags4) {
-    const LaneGeom g = lane_geom<T, L>(it.tile, B, tid);
-    acc.zero();
-    frags = frags4 = 0;
-    int since_flush = 0;
-    for (uint32_t e = 0; e < it.count; ++e) {
-        const uint32_t id = pairs[it.first + e];
-        if (id < B.ntet) {
-            const TetRec r = rec[id];
-            const bool f64 = (r.h.flags & REC_FP64) != 0;
-            if (!f64 || r.h.slot < coef64_cap)
-                raster_record<L, COUNT>(r, f64 ? coef64[r.h.slot].c : nullptr, B, g, acc, frags, frags4);
-        }
-        if (++since_flush == kFlushEvery) {
-            acc.flush();
-            since_flush = 0;
+// One row of one record against one tile row: samples u = 0..n-1 at record
+// frame X = X0 + u, row centre Y; the image row spans u in (ulo, uhi) =
+// (-tx0 - 1/2, W - tx0 - 1/2).  cf: the record's coefficients (walls are read
+// from there).  Break points sit at their true positions, except that pieces
+// starting left of the image start at ulo; only the tile's own entries are
+// written: dep(j, v) adds v to A[j] for 0 <= j < n.  Returns the number of the
+// tile's samples with f > 0.
+template <typename Dep>
+TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0, double Y, int n,
+                                 double ulo, double uhi, Dep &&dep) {
+    double A[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) A[g] = G.a[g] + G.b[g] * X0 + G.c[g] * Y;  // G_g at sample u: A + b u
+    double uL = ulo, uR = uhi;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const double z = A[g] * G.r[g];  // zero of G_g along the row
+        uL = fmax(uL, ((G.lpos >> g) & 1u) ? z : -kInf);
+        uR = fmin(uR, ((G.lneg >> g) & 1u) ? z : kInf);
+    }
+    if (G.flat) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            if (((G.flat >> g) & 1u) && !(A[g] > 0.0)) return 0;
+    }
+    if (G.nw) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q >= (int)G.nw) break;
+            const double w0 = cf[G.wall0 + 3 * q], w1 = cf[G.wall0 + 3 * q + 1], w2 = cf[G.wall0 + 3 * q + 2];
+            const bool tie = (G.ties >> q) & 1u;
+            if (w1 == 0.0) {
+                const double wv = w0 + w2 * Y;
+                if (!(wv > 0.0 || (wv == 0.0 && tie))) return 0;
+            } else {
+                // admitted samples: W > 0 (or W == 0 with the tie bit)
+                const double uw = -(w0 + w2 * Y) / w1 - X0;
+                if (w1 > 0.0) uL = fmax(uL, (tie ? ceil(uw) : floor(uw) + 1.0) - 0.5);
+                else uR = fmin(uR, (tie ? floor(uw) : ceil(uw) - 1.0) + 0.5);
+            }
         }
     }
-    acc.flush();
+    if (!(ceil(uR) - floor(uL) > 1.0)) return 0;  // no sample in (uL, uR)
+    // the tile's samples in (uL, uR)
+    const double span = ceil(fmin(uR, (double)n - 0.5)) - floor(fmax(uL, -0.5)) - 1.0;
+    double x[6];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int g = h + 1; g < 4; ++g) {
+            const int p = kPair[h][g];
+            x[p] = (A[g] - A[h]) * G.q[p];  // G_g < G_h right of x (+inf for a filler g)
+        }
+    if (G.par) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int g = h + 1; g < 4; ++g) {
+                const int p = kPair[h][g];
+                if ((G.par >> p) & 1u) x[p] = A[h] - A[g] > 0.0 ? -kInf : kInf;
+            }
+    }
+    double lo[4], hi[4];
+    lo[0] = uL;
+    hi[0] = fmin(fmin(uR, x[0]), fmin(x[1], x[2]));
+    lo[1] = fmax(uL, x[0]);
+    hi[1] = fmin(uR, fmin(x[3], x[4]));
+    lo[2] = fmax(uL, fmax(x[1], x[3]));
+    hi[2] = fmin(uR, x[5]);
+    lo[3] = fmax(fmax(uL, x[2]), fmax(x[4], x[5]));
+    hi[3] = uR;
+    // the envelope's pieces that hold a sample, left to right; each start is
+    // a break point relative to the previous piece
+    bool have = false;
+    double pA = 0.0, pB = 0.0, pHi = 0.0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (!((G.fill >> g) & 1u) && floor(hi[g]) > floor(lo[g])) {  // an integer in (lo, hi]
+            const double u = lo[g];
+            const double J = (A[g] + G.b[g] * u) - (have ? pA + pB * u : 0.0);
+            const double D = G.b[g] - (have ? pB : 0.0);
+            const double fj = floor(u);
+            const int j = (int)fj + 1;
+            const double v1 = J + D * ((fj + 1.0) - u);
+            if (j >= 0 && j < n) dep(j, v1);
+            if (j >= -1 && j + 1 < n) dep(j + 1, D - v1);
+            have = true;
+            pA = A[g];
+            pB = G.b[g];
+            pHi = hi[g];
+        }
+    }
+    if (have) {
+        const double u = pHi;
+        const double J = -(pA + pB * u), D = -pB;
+        const double fj = floor(u);
+        const int j = (int)fj + 1;
+        const double v1 = J + D * ((fj + 1.0) - u);
+        if (j >= 0 && j < n) dep(j, v1);
+        if (j >= -1 && j + 1 < n) dep(j + 1, D - v1);
+    }
+    return span > 0.0 ? (uint32_t)span : 0u;
+}
+
+// All spans of one record in one tile (every periodic offset that meets it):
+// tile pixels [tx0, tx0 + n) x [ty0, ty0 + rows).  dep(row, j, v) adds v to
+// the tile's A[row][j].  Returns the covered sample count; spans counts the
+// rows visited.
+template <typename Dep>
+TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0,
+                                    int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
+    SpanGeom G;
+    span_geom(h.flags, cf, G);
+    const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
+    const int by0 = range_lo(h.by), by1 = range_hi(h.by);
+    int kx0, kx1, ky0, ky1;
+    axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
+    uint32_t frags = 0;
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        const int ylo = max(ty0, by0 - ky * B.H), yhi = min(ty0 + rows - 1, by1 - ky * B.H);
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
+            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            const double ulo = -(double)tx0 - 0.5, uhi = (double)(B.W - tx0) - 0.5;
+            for (int y = ylo; y <= yhi; ++y) {
+                const double Y = (double)(y + ky * B.H - by0) + 0.5;
+                const int row = y - ty0;
+                frags += row_span(G, cf, X0, Y, n, ulo, uhi, [&](int j, double v) { dep(row, j, v); });
+                ++spans;
+            }
+        }
+    }
+    return frags;
 }
 
 }  // namespace tess

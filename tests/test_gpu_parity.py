@@ -1,7 +1,10 @@
 """GPU path (through the C ABI) against the FP64 oracle on identical inputs.
 
 Bar: per pixel |I_gpu - I_orc| / max(|I_orc|, tau) <= 1e-4 with
-tau = 1e-6 * mean(I_orc), and total mass within 1e-6 relative.
+tau = 1e-6 * mean(I_orc), and total mass within 1e-6 relative.  The raster
+accumulates in FP64, so the tests also hold every pixel with I_orc above
+1e-3 of the mean to 1e-6 (the FP32 output's rounding plus FP64 noise); empty
+pixels carry the row sums' FP64 cancellation noise, about 1e-12 of the mean.
 """
 import numpy as np
 import pytest
@@ -12,7 +15,8 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 PIX_TOL = 1e-4
-MASS_TOL = 1e-6
+COVERED_TOL = 1e-6
+MASS_TOL = 1e-7    # the contract's bar is 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -36,10 +40,13 @@ def rel_err(got, ref):
 
 def assert_parity(got, ref, pix_tol=PIX_TOL, mass_tol=MASS_TOL, what=""):
     r = rel_err(got, ref)
+    covered = np.abs(ref) > 1e-3 * np.abs(ref).mean()
+    rc = r[covered].max() if covered.any() else 0.0
     mass = abs(got.astype(np.float64).sum() - ref.sum()) / abs(ref.sum())
-    print(f"{what}: max rel {r.max():.3e} at {np.unravel_index(r.argmax(), r.shape)}, mass {mass:.3e}",
-          flush=True)
+    print(f"{what}: max rel {r.max():.3e} at {np.unravel_index(r.argmax(), r.shape)}, covered {rc:.3e}, "
+          f"mass {mass:.3e}", flush=True)
     assert r.max() <= pix_tol, f"{what}: per-pixel error {r.max():.3e}"
+    assert rc <= COVERED_TOL, f"{what}: covered-pixel error {rc:.3e}"
     assert mass <= mass_tol, f"{what}: mass error {mass:.3e}"
 
 
@@ -59,19 +66,22 @@ def test_tiny_config_full_image(tess, tiny_lattice):
     assert_parity(got, ref, what="tiny 32^3 -> 256^2")
     assert st["tets"] == ost["tets"] and st["inverted"] == ost["inverted"]
     assert st["zero_volume"] == ost["zero_volume"]
-    # fragments may differ only at pixel centres on a silhouette (rounding)
-    assert abs(st["fragments"] - ost["fragments"]) <= 1e-5 * ost["fragments"] + 8
+    # fragments may differ only at pixel centres exactly on a silhouette (rounding)
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-6 * ost["fragments"] + 8
 
 
-@pytest.mark.parametrize("tile", [16, 32, 64])
-def test_ragged_image_all_tiles(tess, tile):
+@pytest.mark.parametrize("rows,cols,chunk,block", [(0, 0, 0, 0), (4, 64, 256, 256), (16, 16, 64, 512),
+                                                   (1, 200, 100, 1024), (3, 37, 1000, 256),
+                                                   (64, 256, 128, 1024)])
+def test_ragged_image_all_tilings(tess, rows, cols, chunk, block):
     n = 16
     xyz = W.zeldovich(n, 5, 6.0, seed=99)
     view = W.z_view(200, 136)
-    got, st = gpu_image(tess, xyz, (n, n, n), view, tune=tess.make_tune(tile, 256))
-    ref, _ = O.project_region(*xyz, (n, n, n), view)
-    assert_parity(got, ref, what=f"16^3 -> 200x136 tile {tile}")
-    assert st["tile"] == tile and st["work_items"] > 0
+    got, st = gpu_image(tess, xyz, (n, n, n), view, tune=tess.make_tune(rows, cols, chunk, block))
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert_parity(got, ref, what=f"16^3 -> 200x136 tile {rows}x{cols} chunk {chunk} block {block}")
+    assert st["work_items"] > 0 and (rows == 0 or st["tile_rows"] == rows)
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-6 * ost["fragments"] + 8
 
 
 def test_rotated_views_no_wrap(tess):
@@ -84,12 +94,13 @@ def test_rotated_views_no_wrap(tess):
         assert_parity(got, ref, what="rotated 16^3 -> 96x80")
 
 
-def test_fp64_path_matches_oracle_tightly(tess, tiny_lattice):
+def test_fp64_determinant_path(tess, tiny_lattice):
     view = W.z_view(128, 96)
     got, st = gpu_image(tess, tiny_lattice, (32, 32, 32), view, precision="fp64")
-    ref, _ = O.project_region(*tiny_lattice, (32, 32, 32), view)
-    assert_parity(got, ref, pix_tol=3e-7, mass_tol=1e-7, what="fp64 path")
-    assert st["fp64_tets"] >= 0.99 * st["tets"]
+    ref, ost = O.project_region(*tiny_lattice, (32, 32, 32), view)
+    assert_parity(got, ref, what="fp64 determinants")
+    assert st["fp64_dets"] == st["tets"] + st["zero_volume"]
+    assert st["inverted"] == ost["inverted"]
 
 
 def test_non_periodic_lattice(tess):
@@ -107,10 +118,12 @@ def test_non_periodic_lattice(tess):
 
 
 # ---------------------------------------------------- closed forms on GPU
-@pytest.mark.parametrize("n,w,h", [(4, 16, 16), (8, 24, 40), (4, 2, 10)])
+@pytest.mark.parametrize("n,w,h", [(4, 16, 16), (8, 24, 40), (4, 2, 10), (4, 7, 5)])
 def test_undisplaced_lattice_is_exactly_one(tess, n, w, h):
-    got, st = gpu_image(tess, W.undisplaced(n), (n, n, n), W.z_view(w, h))
-    np.testing.assert_allclose(got, 1.0, rtol=0, atol=2e-6)
+    # pixel centres on cube faces and tetrahedron faces seen edge-on (walls)
+    got, st = gpu_image(tess, W.undisplaced(n), (n, n, n), W.z_view(w, h),
+                        tune=tess.make_tune(3, max(16, w // 2)))
+    np.testing.assert_allclose(got, 1.0, rtol=0, atol=1e-7)
 
 
 def test_z_only_displacement_column_density_one(tess):
@@ -121,7 +134,7 @@ def test_z_only_displacement_column_density_one(tess):
     xyz = (q[:, 0].astype(np.float32), q[:, 1].astype(np.float32), W.wrap_to_f32(q[:, 2] - f, 1.0))
     got, st = gpu_image(tess, xyz, (n, n, n), W.z_view(64, 48))
     assert st["inverted"] > 0
-    np.testing.assert_allclose(got, 1.0, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(got, 1.0, rtol=0, atol=2e-7)
 
 
 def test_single_pixel_and_minimum_lattice(tess):
@@ -133,22 +146,19 @@ def test_single_pixel_and_minimum_lattice(tess):
 
 
 # --------------------------------------------------- determinism, batching
-def test_bitwise_deterministic_and_chunk_independent(tess, tiny_lattice):
+def test_repeatable_and_tiling_independent(tess, tiny_lattice):
+    # FP64 atomics commit in hardware order, so repeated calls agree to FP64
+    # rounding (well below the FP32 output's half ulp), not bit for bit
     import torch
     lat = tess.build(*dev(tiny_lattice), (32, 32, 32))
     view = W.z_view(256)
-    a = tess.project(lat, view, tune=tess.make_tune(32, 4096)).cpu().numpy()
-    b = tess.project(lat, view, tune=tess.make_tune(32, 4096)).cpu().numpy()
-    c = tess.project(lat, view, tune=tess.make_tune(32, 64)).cpu().numpy()
-    d = tess.project(lat, view, tune=tess.make_tune(16, 128)).cpu().numpy()
+    a = tess.project(lat, view).cpu().numpy().astype(np.float64)
+    outs = [tess.project(lat, view, tune=t).cpu().numpy().astype(np.float64)
+            for t in (None, tess.make_tune(0, 0, 64), tess.make_tune(2, 64, 0, 256),
+                      tess.make_tune(64, 256, 512, 1024))]
     torch.cuda.synchronize()
-    assert np.array_equal(a, b)
-    # chunking only regroups FP64 partial sums
-    np.testing.assert_allclose(c, a, rtol=1e-6, atol=0)
-    # another tile size changes each lane's strip start, so the FP32 edge
-    # functions are stepped from other origins: equal within the FP32
-    # evaluation bound of a footprint (condition <= 256), well inside 1e-4
-    np.testing.assert_allclose(d, a, rtol=1e-4, atol=0)
+    for b in outs:
+        np.testing.assert_allclose(b, a, rtol=2.4e-7, atol=1e-12 * a.max())
 
 
 def test_batch_equals_single_projections(tess):
@@ -164,7 +174,7 @@ def test_batch_equals_single_projections(tess):
     for s in range(2):
         for v in range(3):
             one = tess.project(lats[s], views[v])
-            assert torch.equal(imgs[s, v], one)
+            torch.testing.assert_close(imgs[s, v], one, rtol=2.4e-7, atol=1e-12)
     ref, _ = O.project_region(*xyzs[1], (n, n, n), views[2])
     assert_parity(imgs[1, 2].cpu().numpy(), ref, what="batch image")
 
@@ -202,10 +212,14 @@ def test_stress_config_sampled_pixels(tess):
     py = np.concatenate([rng.integers(768, 1280, 96), [0, 2047]])
     ref, ost = O.project_pixels(*xyz, (w.n,) * 3, view, px, py)
     r = rel_err(got[py, px], ref)
-    print(f"stress: sampled max rel {r.max():.3e}, gpu tets {st['tets']}, fp64 {st['fp64_tets']}, "
-          f"fragments {st['fragments']:.4e}", flush=True)
+    print(f"stress: sampled max rel {r.max():.3e}, gpu tets {st['tets']}, fp64 dets {st['fp64_dets']}, "
+          f"fragments {st['fragments']:.4e}, {st['ms']:.1f} ms", flush=True)
     assert r.max() <= PIX_TOL
     assert st["tets"] == ost["tets"] and st["inverted"] == ost["inverted"]
+    # column tiles instead of full-width bands: the same image to FP32 rounding
+    img2 = tess.project(tess.build(*dev(xyz), (w.n,) * 3), view,
+                        tune=tess.make_tune(16, 1024)).cpu().numpy()
+    np.testing.assert_allclose(img2, got, rtol=2.4e-7, atol=1e-12)
 
 
 # ---------------------------------------------------------------- errors
@@ -228,7 +242,7 @@ def test_ids_scatter_and_permutation_check(tess):
     lat = tess.build(*dev((xs, ys, zs)), (8, 8, 8), ids=ids)
     got = tess.project(lat, view).cpu().numpy()
     ref = tess.project(tess.build(*dev((x, y, z)), (8, 8, 8)), view).cpu().numpy()
-    assert np.array_equal(got, ref)
+    np.testing.assert_allclose(got, ref, rtol=2.4e-7, atol=1e-12)
     bad = perm.copy()
     bad[5] = bad[6]
     with pytest.raises(tess.TessError):
@@ -243,4 +257,9 @@ def test_invalid_views_rejected(tess):
     for v in bad:
         with pytest.raises(tess.TessError) as ei:
             tess.project(lat, v)
+        assert ei.value.status == tess.TESS_EINVAL
+    for t in (tess.make_tune(64, 512), tess.make_tune(0, 8), tess.make_tune(0, 0, 0, 100),
+              tess.make_tune(0, 0, 10)):
+        with pytest.raises(tess.TessError) as ei:
+            tess.project(lat, W.z_view(32), tune=t)
         assert ei.value.status == tess.TESS_EINVAL

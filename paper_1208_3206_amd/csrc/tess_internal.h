@@ -28,6 +28,7 @@ struct ViewParams {
     double u_left, v_bottom;
     double inv_du, inv_dv;
     double mass_px;          // 6 m * inv_du * inv_dv (density scale in pixel units)
+    double crease_bmax;      // footprints with a steeper x slope keep the line form
     int32_t W, H;
     int32_t wrap;
 };
@@ -67,11 +68,15 @@ struct WorkItem {
 };
 
 // Per-tetrahedron raster record, stored as two arrays: the head (box and
-// flags, all the binning reads) and the FP64 coefficients.  The footprint
-// function is
+// flags, all the binning reads) and a 128-byte FP64 payload, in pixel units
+// relative to the box corner (bx0, by0).  The footprint is
 //   f(p) = [all walls admit p] * max(0, min_g G_g(p)),
-//   G(p) = c[3g] + c[3g+1] * x + c[3g+2] * y,   (x, y) = p - (bx0, by0)
-// with (x, y) in pixel units; walls follow the G functions in c[].
+//   G_g(p) = a_g + b_g x + c_g y,   (x, y) = p - (bx0, by0),
+// a pyramid over the projected silhouette.  Two payload forms:
+//  - crease form (REC_CREASE; no walls): the silhouette vertices V_0..V_m-1
+//    in cyclic order (x in c[0..3], y in c[4..7]), the apex (c[8], c[9]) and
+//    the x slope b of the face over edge (V_k, V_k+1) in c[10 + k];
+//  - line form: (a, b, c) of the G functions, then of the walls, in c[0..11].
 struct RecHead {
     uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
     uint32_t by;                 // y0 | y1 << 16
@@ -89,16 +94,17 @@ constexpr uint32_t REC_NW_SHIFT = 3;          // number of walls (2 bits)
 constexpr uint32_t REC_TIE0 = 1u << 5;        // wall 0 keeps pixels on its line
 constexpr uint32_t REC_TIE1 = 1u << 6;        // wall 1 keeps pixels on its line
 constexpr uint32_t REC_VALID = 1u << 7;       // some pixel centre may be covered
+constexpr uint32_t REC_CREASE = 1u << 8;      // payload in crease form
 
-struct alignas(16) Coef64 {
-    double c[12];
+struct alignas(128) Payload {
+    double c[16];
 };
 static_assert(sizeof(RecHead) == 16, "record head");
-static_assert(sizeof(Coef64) == 96, "FP64 coefficient block");
+static_assert(sizeof(Payload) == 128, "one 128-byte line per record");
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `stream` and return the launch status.
-hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Coef64 *coef,
+hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream);
 
 hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
@@ -132,7 +138,7 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
 
 // Raster of the work items into the second-difference image acc[H][W];
 // max_items blocks are launched and those beyond plan->n_items return.
-hipError_t launch_raster(const RecHead *head, const Coef64 *coef, const uint32_t *pairs,
+hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
                          const BinParams &B, int block, double *acc, DevCounters *counters,
                          hipStream_t stream);

@@ -51,14 +51,14 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
 // One thread per lattice cube; writes the six records 6*cube .. 6*cube+5.
 __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
                                                RecHead *__restrict__ head,
-                                               Coef64 *__restrict__ coef,
+                                               Payload *__restrict__ coef,
                                                DevCounters *__restrict__ counters) {
     CubeCounts cnt;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
     for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
         RecHead h[6];
-        Coef64 c[6];
+        Payload c[6];
         setup_cube(L, V, cube, h, c, cnt);
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
     }
 }
 
-hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Coef64 *coef,
+hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream) {
     const int64_t want = (L.ncubes + 255) / 256;
     const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
@@ -351,9 +351,11 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
 // and add each pixel row's break-point terms with LDS atomics.  At the end
 // the tile is added to the image-sized array `acc` (FP64 atomics in L2; a
 // tile has several items).
+constexpr int kPad = 2;
+
 template <int TPB>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
-                                                const Coef64 *__restrict__ coef,
+                                                const Payload *__restrict__ coef,
                                                 const uint32_t *__restrict__ pairs,
                                                 const WorkItem *__restrict__ items,
                                                 const PlanOut *__restrict__ plan, BinParams B,
@@ -365,23 +367,31 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     const int tx = (int)(it.tile % (uint32_t)B.ntx), ty = (int)(it.tile / (uint32_t)B.ntx);
     const int tx0 = tx * B.Tw, ty0 = ty * B.Th;
     const int n = min(B.Tw, B.W - tx0), rows = min(B.Th, B.H - ty0);
-    const int tsize = B.Th * B.Tw;
+    // rows of Tw + 4 cells: two padding cells each side take the adds that
+    // fall outside the tile, so that the raster needs no bounds tests
+    const int stride = B.Tw + 2 * kPad;
+    const int tsize = B.Th * stride;
     for (int i = threadIdx.x; i < tsize; i += TPB) sA[i] = 0.0;
     __syncthreads();
     uint32_t frags = 0, spans = 0;
-    const int Tw = B.Tw;
-    for (uint32_t e = threadIdx.x; e < it.count; e += TPB) {
+    // lane t takes entries t*per .. t*per+per-1: the list is in rough id order
+    // (neighbouring cubes), so this spreads a wavefront's 64 footprints over
+    // the tile instead of stacking their atomics on the same LDS cells
+    const uint32_t per = (it.count + TPB - 1) / TPB;
+    const uint32_t e0 = threadIdx.x * per, e1 = min(it.count, e0 + per);
+    for (uint32_t e = e0; e < e1; ++e) {
         const uint32_t id = pairs[it.first + e];
         if (id >= B.ntet) continue;
         const RecHead h = head[id];
         if (!(h.flags & REC_VALID)) continue;
-        frags += raster_pair(h, coef[id].c, B, tx0, ty0, n, rows,
-                             [&](int row, int j, double v) { atomicAdd(&sA[row * Tw + j], v); }, spans);
+        frags += raster_record(h, coef[id].c, B, tx0, ty0, n, rows,
+                               [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                               spans);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < rows * Tw; i += TPB) {
-        const int r = i / Tw, c = i - r * Tw;
-        const double v = sA[i];
+    for (int i = threadIdx.x; i < rows * B.Tw; i += TPB) {
+        const int r = i / B.Tw, c = i - r * B.Tw;
+        const double v = sA[r * stride + kPad + c];
         if (c < n && v != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + tx0 + c], v);
     }
     const unsigned long long f = wave_sum((unsigned long long)frags);
@@ -392,12 +402,12 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     }
 }
 
-hipError_t launch_raster(const RecHead *head, const Coef64 *coef, const uint32_t *pairs,
+hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
                          const BinParams &B, int block, double *acc, DevCounters *counters,
                          hipStream_t stream) {
     if (max_items == 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (size_t)B.Th * B.Tw;
+    const size_t lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
     switch (block) {
         case 256:
             hipLaunchKernelGGL((k_raster<256>), dim3((unsigned)max_items), dim3(256), lds, stream, head, coef,

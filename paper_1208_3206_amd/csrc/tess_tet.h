@@ -63,6 +63,7 @@ TESS_HD inline double det6_fp64(const double a[3], const double b[3], const doub
 // ------------------------------------------------------ footprint setup
 struct Footprint {
     double c[12];
+    int ei[4], ej[4];  // tetrahedron vertices of silhouette edge g
     int ng, nw;
     uint32_t ties;
 };
@@ -101,6 +102,8 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
             fp.c[3 * ng + 0] = aa;
             fp.c[3 * ng + 1] = bb;
             fp.c[3 * ng + 2] = cc;
+            fp.ei[ng] = E.i;
+            fp.ej[ng] = E.j;
             ++ng;
         }
     }
@@ -139,6 +142,69 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
 }
 
 
+// Crease form of a footprint without walls.  The pyramid's creases are the
+// silhouette edges and the ridges from the apex to the silhouette vertices:
+// the apex is the vertex inside the silhouette triangle (three silhouette
+// edges) or the crossing of the quadrilateral's diagonals (four).  Along a
+// pixel row the footprint's slope jumps by |b| at a silhouette edge and by
+// -|b_k-1 - b_k| at the ridge to V_k, with b the x slopes of the faces over
+// the silhouette edges.  Returns false if the edges do not close a cycle.
+TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const Footprint &fp,
+                                   double out[16]) {
+    const int m = fp.ng;
+    if (m != 3 && m != 4) return false;
+    int V[4] = {fp.ei[0], fp.ej[0], 0, 0};
+    int Lk[4] = {0, 0, 0, 0};  // silhouette edge g of cyclic edge (V_k, V_k+1)
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        if (k >= m) break;
+        int found = -1, next = -1;
+#pragma unroll
+        for (int l = 1; l < 4; ++l) {
+            if (l >= m || l == Lk[k - 1] || found >= 0) continue;
+            if (fp.ei[l] == V[k]) { found = l; next = fp.ej[l]; }
+            else if (fp.ej[l] == V[k]) { found = l; next = fp.ei[l]; }
+        }
+        if (found < 0) return false;
+        Lk[k] = found;
+        if (k + 1 < m) V[k + 1] = next;
+        else if (next != V[0]) return false;
+    }
+    double vx[4], vy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int v = V[k];
+        vx[k] = v == 0 ? qx[0] : v == 1 ? qx[1] : v == 2 ? qx[2] : qx[3];
+        vy[k] = v == 0 ? qy[0] : v == 1 ? qy[1] : v == 2 ? qy[2] : qy[3];
+    }
+    double ax, ay;
+    if (m == 3) {
+        const int p = 6 - V[0] - V[1] - V[2];  // the vertex on no silhouette edge
+        ax = p == 0 ? qx[0] : p == 1 ? qx[1] : p == 2 ? qx[2] : qx[3];
+        ay = p == 0 ? qy[0] : p == 1 ? qy[1] : p == 2 ? qy[2] : qy[3];
+    } else {
+        const double d1x = vx[2] - vx[0], d1y = vy[2] - vy[0];
+        const double d2x = vx[3] - vx[1], d2y = vy[3] - vy[1];
+        const double den = d1x * d2y - d1y * d2x;
+        if (den == 0.0) return false;
+        const double t = ((vx[1] - vx[0]) * d2y - (vy[1] - vy[0]) * d2x) / den;
+        ax = vx[0] + t * d1x;
+        ay = vy[0] + t * d1y;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool real = k < m;
+        const int g = Lk[k];
+        out[k] = real ? vx[k] : 0.0;
+        out[4 + k] = real ? vy[k] : 0.0;
+        out[10 + k] = real ? (g == 0 ? fp.c[1] : g == 1 ? fp.c[4] : g == 2 ? fp.c[7] : fp.c[10]) : 0.0;
+    }
+    out[8] = ax;
+    out[9] = ay;
+    out[14] = out[15] = 0.0;
+    return true;
+}
+
 // Counters of one lattice cube's setup.
 struct CubeCounts {
     unsigned n_tets = 0, n_zero = 0, n_inv = 0, n_dets = 0, n_deg = 0;
@@ -149,7 +215,7 @@ struct CubeCounts {
 // coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
 // cover no pixel centre).
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
-                               Coef64 coef[6], CubeCounts &cnt) {
+                               Payload coef[6], CubeCounts &cnt) {
     const int64_t i = cube % L.c[0];
     const int64_t rest = cube / L.c[0];
     const int64_t j = rest % L.c[1];
@@ -202,7 +268,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         R.flags = 0;
         R.spare = 0;
 #pragma unroll
-        for (int g = 0; g < 12; ++g) coef[t].c[g] = 0.0;
+        for (int g = 0; g < 16; ++g) coef[t].c[g] = 0.0;
         // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
         // error bound, FP64 when the bound cannot certify it or it is small
         double a64[3], b64[3], c64[3];
@@ -263,8 +329,18 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         R.bx = pack_range(ix0, ix1);
         R.by = pack_range(iy0, iy1);
         R.flags = (uint32_t)fp.ng | ((uint32_t)fp.nw << REC_NW_SHIFT) | fp.ties | REC_VALID;
+        // crease form unless the footprint is steep along x: its kinks' rounding
+        // would then carry along the row sums (steep slivers keep the line form,
+        // whose rows without a pixel centre are skipped)
+        double bmax = 0.0;
 #pragma unroll
-        for (int g = 0; g < 12; ++g) coef[t].c[g] = fp.c[g];
+        for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
+        if (fp.nw == 0 && bmax <= V.crease_bmax && crease_payload(qx, qy, fp, coef[t].c)) {
+            R.flags |= REC_CREASE;
+        } else {
+#pragma unroll
+            for (int g = 0; g < 12; ++g) coef[t].c[g] = fp.c[g];
+        }
     }
 }
 
@@ -555,6 +631,105 @@ TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const Bi
         }
     }
     return frags;
+}
+
+// All row crossings of one crease-form record in one tile (every periodic
+// offset that meets it): for each crease and each tile row whose centre Y
+// lies in the crease's half-open y range [y_lo, y_hi), one kink of slope
+// change D at the crossing x (no step: the pyramid is continuous).  A row
+// through a vertex thus meets each crease leaving it upwards, and a
+// horizontal crease is never met.  Kinks left of the image are folded into
+// its first two columns.  dep(row, j, v) adds v to A[row][j]; it is called
+// with -2 <= j <= n + 1 and must drop the entries outside 0 <= j < n (the
+// kernel keeps two padding cells on each side of a row, so that the adds
+// need no test).  Returns the covered sample count (samples strictly between
+// the two silhouette crossings of a row); spans counts the rows visited.
+template <typename Dep>
+TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0,
+                                    int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
+    const bool quad = (h.flags & REC_NG_MASK) == 4u;
+    const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
+    const int by0 = range_lo(h.by), by1 = range_hi(h.by);
+    int kx0, kx1, ky0, ky1;
+    axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
+    const int jmin = -tx0;  // tile column of image column 0
+    const double ucl = -0.5, ucr = (double)n - 0.5;
+    int frags = 0;
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        // record rows r (centre Y = r + 1/2) on tile rows r + rshift
+        const int rshift = by0 - ky * B.H - ty0;
+        const int rlo = max(-rshift, 0), rhi = min(rows - 1 - rshift, by1 - by0);
+        if (rlo > rhi) continue;
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
+            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            spans += (uint32_t)(rhi - rlo + 1);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                // slots 0..3: silhouette edge (V_k, V_k+1); slots 4..7: ridge (apex, V_k)
+                const int k = c & 3;
+                if (k == 3 && !quad) continue;
+                double Px, Py, Qx, Qy, D;
+                bool enter = false;
+                if (c < 4) {
+                    Px = cf[k];
+                    Py = cf[4 + k];
+                    const bool wrapk = k == 3 || (k == 2 && !quad);
+                    Qx = wrapk ? cf[0] : cf[k + 1 < 4 ? k + 1 : 0];
+                    Qy = wrapk ? cf[4] : cf[k + 1 < 4 ? 5 + k : 4];
+                    const double b = cf[10 + k];
+                    D = fabs(b);
+                    enter = b > 0.0;
+                } else {
+                    Px = cf[8];
+                    Py = cf[9];
+                    Qx = cf[k];
+                    Qy = cf[4 + k];
+                    const double bprev = k > 0 ? cf[9 + k] : (quad ? cf[13] : cf[12]);
+                    D = -fabs(bprev - cf[10 + k]);
+                }
+                const double ylo = fmin(Py, Qy), yhi = fmax(Py, Qy);
+                const int r0 = max((int)ceil(ylo - 0.5), rlo);
+                const int r1 = min((int)ceil(yhi - 0.5) - 1, rhi);
+                if (r0 > r1) continue;
+                const double sl = (Qx - Px) / (Qy - Py);
+                // the crossing in the record frame (small numbers: a sliver's
+                // kinks keep their relative positions to FP64 rounding of its box)
+                double x = Px + ((double)r0 + 0.5 - Py) * sl;
+                for (int r = r0; r <= r1; ++r, x += sl) {
+                    const int row = r + rshift;
+                    const double u = x - X0;
+                    const double fl = floor(u);
+                    const int fi = (int)fl;
+                    int j = fi + 1;
+                    j = j > jmin ? j : jmin;
+                    j = j < -2 ? -2 : (j > n ? n : j);
+                    const double v1 = D * (((double)j + X0) - x);
+                    dep(row, j, v1);
+                    dep(row, j + 1, D - v1);
+                    if (c < 4) {
+                        // fragments, with u clamped to the tile's samples: an
+                        // entering crossing counts -(floor(u) + 1), a leaving
+                        // one ceil(u)
+                        const int ce = fi + (fl < u ? 1 : 0);
+                        const int te = -min(max(fi, -1), n - 1) - 1;
+                        const int tl = min(max(ce, 0), n);
+                        frags += enter ? te : tl;
+                    }
+                }
+            }
+        }
+    }
+    return frags > 0 ? (uint32_t)frags : 0u;
+}
+
+// One record in one tile, in whichever form its payload has.
+template <typename Dep>
+TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const BinParams &B, int tx0,
+                                      int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
+    if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans);
+    return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans);
 }
 
 }  // namespace tess

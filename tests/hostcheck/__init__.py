@@ -35,18 +35,22 @@ def lib():
 
 
 def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, tile_rows=8,
-             tile_cols=None, chunk=4096):
+             tile_cols=None, chunk=4096, crease_div=None):
     """The GPU pipeline's own per-tetrahedron code run on the CPU, in the
     kernels' order of work.  Returns the FP64 image before rounding, the FP32
-    image and the counters."""
+    image and the counters.  crease_div: footprints steeper than the mean
+    pixel value / crease_div per pixel keep the line form (the library uses
+    width / 64); 0 puts every footprint in line form."""
     P = ctypes.POINTER
     x, y, z = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, z))
     W, H = int(view["width"]), int(view["height"])
     if tile_cols is None:
         tile_cols = W
+    if crease_div is None:
+        crease_div = W / 64.0
     out64 = np.zeros((H, W), dtype=np.float64)
     out32 = np.zeros((H, W), dtype=np.float32)
-    st = np.zeros(8, dtype=np.int64)
+    st = np.zeros(9, dtype=np.int64)
     d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
     rot = (ctypes.c_double * 9)(*[float(v) for v in view["rot"]])
     cen = (ctypes.c_double * 3)(*[float(v) for v in view["center"]])
@@ -54,9 +58,11 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
     rc = lib().hc_pipeline(x.ctypes.data_as(P(ctypes.c_float)), y.ctypes.data_as(P(ctypes.c_float)),
                            z.ctypes.data_as(P(ctypes.c_float)), d, int(periodic), ctypes.c_double(total_mass),
                            int(precision), rot, cen, ext, W, H, int(view.get("wrap", 0)), int(tile_rows),
-                           int(tile_cols), int(chunk), out64.ctypes.data_as(P(ctypes.c_double)),
+                           int(tile_cols), int(chunk), ctypes.c_double(crease_div),
+                           out64.ctypes.data_as(P(ctypes.c_double)),
                            out32.ctypes.data_as(P(ctypes.c_float)), st.ctypes.data_as(P(ctypes.c_longlong)))
     if rc != 0:
         raise RuntimeError(f"hostcheck pipeline failed: {rc}")
-    keys = ("tets", "zero_volume", "inverted", "fp64_dets", "fragments", "spans", "pairs", "items")
+    keys = ("tets", "zero_volume", "inverted", "fp64_dets", "fragments", "spans", "pairs", "items",
+            "crease_records")
     return out64, out32, dict(zip(keys, (int(v) for v in st)))

@@ -1,5 +1,5 @@
 // Host-compiled run of the projector's per-tetrahedron code (tess_tet.h): the
-// same setup_cube / tet_tiles / raster_pair functions the HIP kernels call,
+// same setup_cube / tet_tiles / raster_record functions the HIP kernels call,
 // driven by plain loops on the CPU in the kernels' order of work (tile lists,
 // work items of at most `chunk` entries, one tile accumulator per item added
 // into the image-sized second-difference array, then the row sums).  Used by
@@ -17,9 +17,9 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                            int32_t periodic, double total_mass, int32_t precision, const double rot[9],
                            const double center[3], const double extent[2], int32_t W, int32_t H,
                            int32_t wrap, int32_t tile_rows, int32_t tile_cols, int32_t chunk,
-                           double *out64, float *out32,
+                           double crease_div, double *out64, float *out32,
                            long long *stats /* [tets, zero, inverted, fp64_dets, fragments, spans,
-                                               pairs, items] */) {
+                                               pairs, items, crease_records] */) {
     LatticeParams L;
     std::memset(&L, 0, sizeof(L));
     L.x = x; L.y = y; L.z = z;
@@ -42,15 +42,17 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.inv_du = W / extent[0];
     V.inv_dv = H / extent[1];
     V.mass_px = 6.0 * L.tet_mass * V.inv_du * V.inv_dv;
+    V.crease_bmax = crease_div > 0 ? V.mass_px * (double)L.ncubes / ((double)W * H) / crease_div : -1.0;
     V.W = W; V.H = H; V.wrap = wrap;
     const int64_t ntet = 6 * L.ncubes;
     std::vector<RecHead> head(ntet);
-    std::vector<Coef64> coef(ntet);
-    long long tets = 0, zero = 0, inv = 0, dets = 0;
+    std::vector<Payload> coef(ntet);
+    long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0;
     for (int64_t cube = 0; cube < L.ncubes; ++cube) {
         CubeCounts cnt;
         setup_cube(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
+        for (int t = 0; t < 6; ++t) creases += (head[6 * cube + t].flags & REC_CREASE) ? 1 : 0;
     }
     BinParams B;
     B.Th = tile_rows;
@@ -84,10 +86,10 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
             for (size_t e = first; e < last; ++e) {
                 const uint32_t id = lst[e];
                 uint32_t sp = 0;
-                frags += raster_pair(head[id], coef[id].c, B, tx0, ty0, n, rows,
+                frags += raster_record(head[id], coef[id].c, B, tx0, ty0, n, rows,
                                      [&](int row, int j, double v) {
-                                         if (row < 0 || row >= rows || j < 0 || j >= n) throw 1;
-                                         tile[(size_t)row * B.Tw + j] += v;
+                                         if (row < 0 || row >= rows || j < -2 || j > n + 1) throw 1;
+                                         if (j >= 0 && j < n) tile[(size_t)row * B.Tw + j] += v;
                                      },
                                      sp);
                 spans += sp;
@@ -107,7 +109,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     }
     if (stats) {
         stats[0] = tets; stats[1] = zero; stats[2] = inv; stats[3] = dets;
-        stats[4] = frags; stats[5] = spans; stats[6] = pairs; stats[7] = items;
+        stats[4] = frags; stats[5] = spans; stats[6] = pairs; stats[7] = items; stats[8] = creases;
     }
     return 0;
 }

@@ -45,7 +45,8 @@ def test_zeldovich_wrap_matches_oracle_any_tiling(rows, cols, chunk):
     view = W.z_view(200, 136)
     img, img32, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=rows, tile_cols=cols, chunk=chunk)
     ref, ost = O.project_region(*xyz, (n, n, n), view)
-    assert rel(img, ref) < 1e-9
+    # FP64 row sums: rounding grows along a row, ~1e-9 at its end here
+    assert rel(img, ref) < 1e-8
     assert rel(img32.astype(np.float64), ref) < 1e-6
     assert st["tets"] == ost["tets"] and st["inverted"] == ost["inverted"]
     assert st["fragments"] == ost["fragments"]
@@ -59,7 +60,27 @@ def test_rotated_view_without_wrap_matches_oracle(rows, cols):
     view = W.rotated_view(R, 50, 44)
     img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=rows, tile_cols=cols)
     ref, ost = O.project_region(*xyz, (n, n, n), view)
-    assert np.abs(img - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(img - ref).max() < 1e-8 * np.abs(ref).max()
+    assert rel(img, ref) < 1e-5  # empty pixels hold only FP64 noise of the row sums
+    assert st["fragments"] == ost["fragments"]
+
+
+@pytest.mark.parametrize("crease_div", [0.0, None, 1e-30])
+def test_crease_and_line_forms_agree(crease_div):
+    # every footprint in line form, the library's split, every one in crease form
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    view = W.rotated_view(W.random_rotations(1, seed=31)[0], 96, 80)
+    img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=4, tile_cols=32, crease_div=crease_div)
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    if crease_div == 0.0:
+        assert st["crease_records"] == 0
+    elif crease_div is None:
+        assert 0 < st["crease_records"] < st["tets"]
+        assert rel(img, ref) < 1e-5
+    else:
+        assert st["crease_records"] > 0.95 * st["tets"]
+    assert np.abs(img - ref).max() < 1e-8 * np.abs(ref).max()
     assert st["fragments"] == ost["fragments"]
 
 
@@ -70,7 +91,7 @@ def test_non_periodic_lattice_matches_oracle():
     view = W.rotated_view(R, 61, 47, side=1.6)
     img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, periodic=False, tile_rows=4, tile_cols=32)
     ref, ost = O.project_region(*xyz, (n, n, n), view, periodic=False)
-    assert np.abs(img - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(img - ref).max() < 1e-8 * np.abs(ref).max()
     assert st["tets"] == ost["tets"] and st["fragments"] == ost["fragments"]
 
 
@@ -93,7 +114,7 @@ def test_degenerate_image_sizes(w, h):
     view = W.z_view(w, h)
     img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=2, tile_cols=16)
     ref, ost = O.project_region(*xyz, (n, n, n), view)
-    assert rel(img, ref) < 1e-10
+    assert rel(img, ref) < 1e-8
     assert st["fragments"] == ost["fragments"]
 
 
@@ -104,5 +125,5 @@ def test_minimum_lattice_and_huge_footprints():
     view = W.z_view(23, 19)
     img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=4, tile_cols=16)
     ref, ost = O.project_region(*xyz, (n, n, n), view)
-    assert rel(img, ref) < 1e-10
+    assert rel(img, ref) < 1e-8
     assert st["fragments"] == ost["fragments"]

@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 using namespace tess;
 
@@ -73,11 +74,18 @@ struct Workspace {
     DevBuf<WorkItem> items;
     DevBuf<uint32_t> pairs;
     DevBuf<double> acc;
-    DevBuf<PlanOut> plan;
+    DevBuf<PlanOut> plan;               // one per image of a batch
     DevBuf<DevCounters> counters;
-    PlanOut *host_plan = nullptr;       // pinned
+    DevBuf<unsigned int> overflow;
+    PlanOut *host_plan = nullptr;       // pinned, host_plan_cap entries
+    size_t host_plan_cap = 0;
     DevCounters *host_counters = nullptr;
+    unsigned int *host_overflow = nullptr;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // batch graph (captured on `capture`, replayed on the caller's stream)
+    hipStream_t capture = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
     std::mutex mu;
 };
 
@@ -94,8 +102,11 @@ tess_status get_workspace(int device, hipStream_t s, Workspace **out) {
     }
     Workspace *w = new Workspace();
     TESS_HIP(hipHostMalloc((void **)&w->host_plan, sizeof(PlanOut), hipHostMallocDefault));
+    w->host_plan_cap = 1;
     TESS_HIP(hipHostMalloc((void **)&w->host_counters, sizeof(DevCounters), hipHostMallocDefault));
+    TESS_HIP(hipHostMalloc((void **)&w->host_overflow, sizeof(unsigned int), hipHostMallocDefault));
     for (int i = 0; i < 6; ++i) TESS_HIP(hipEventCreate(&w->ev[i]));
+    TESS_HIP(hipStreamCreateWithFlags(&w->capture, hipStreamNonBlocking));
     g_ws[key] = w;
     *out = w;
     return TESS_OK;
@@ -304,7 +315,7 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
 }
 
 struct Plan {
-    int Th, Tw, chunk, block;
+    int Th, Tw, chunk, block;  // chunk 0: from the pair count
 };
 
 // Default tiling: tiles of up to 1024 columns with as many rows as the
@@ -318,18 +329,29 @@ Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     if (tune && tune->tile_rows) Th = tune->tile_rows;
     p.Th = Th;
     p.Tw = Tw;
-    p.chunk = (tune && tune->chunk) ? tune->chunk : 0;  // 0: from the pair count
+    p.chunk = (tune && tune->chunk) ? tune->chunk : 0;
     p.block = (tune && tune->block) ? tune->block : 1024;
     return p;
 }
 
-tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan &plan, float *image,
-                         tess_stats *stats, hipStream_t s, Workspace &ws) {
+int auto_chunk(unsigned long long total_pairs) {
+    // work items: a few per CU at least, each long enough to amortise its tile flush
+    const unsigned long long want = total_pairs / 4096ull;
+    return (int)std::min<unsigned long long>(65536ull, std::max<unsigned long long>(1024ull, want));
+}
+
+// Sizes of one image's pipeline.
+struct Geometry {
     LatticeParams lp;
     ViewParams vp;
-    make_params(L, v, lp, vp);
-    const int64_t ntet = 6 * lp.ncubes;
     BinParams B;
+    int64_t ntet, ntiles, nmat, npix;
+};
+
+tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Plan &plan, Geometry &g) {
+    make_params(L, v, g.lp, g.vp);
+    g.ntet = 6 * g.lp.ncubes;
+    BinParams &B = g.B;
     B.Th = plan.Th;
     B.Tw = plan.Tw;
     B.ntx = (v->width + plan.Tw - 1) / plan.Tw;
@@ -337,58 +359,110 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     B.W = v->width;
     B.H = v->height;
     B.wrap = v->wrap;
-    const int64_t ntiles = (int64_t)B.ntx * B.nty;
-    if (ntiles > kMaxTiles)
+    g.ntiles = (int64_t)B.ntx * B.nty;
+    if (g.ntiles > kMaxTiles)
         return fail(TESS_ECAPACITY, "%lld tiles of %d x %d px exceed the limit of %d; use larger tiles",
-                    (long long)ntiles, plan.Th, plan.Tw, kMaxTiles);
+                    (long long)g.ntiles, plan.Th, plan.Tw, kMaxTiles);
     // binning segments: enough for the device, few enough to keep the count matrix small
     int64_t seg_len = 4096;
-    while ((ntet + seg_len - 1) / seg_len * ntiles > (int64_t)64 << 20) seg_len *= 2;
+    while ((g.ntet + seg_len - 1) / seg_len * g.ntiles > (int64_t)64 << 20) seg_len *= 2;
     B.seg_len = (int32_t)seg_len;
-    B.nseg = (int32_t)((ntet + seg_len - 1) / seg_len);
-    if (B.nseg < 1) B.nseg = 1;
-    B.ntet = (uint32_t)ntet;
-    const int64_t nmat = ntiles * B.nseg;
-    const int64_t npix = (int64_t)B.W * B.H;
+    B.nseg = (int32_t)std::max<int64_t>(1, (g.ntet + seg_len - 1) / seg_len);
+    B.ntet = (uint32_t)g.ntet;
+    g.nmat = g.ntiles * B.nseg;
+    g.npix = (int64_t)B.W * B.H;
+    return TESS_OK;
+}
 
-    TESS_HIP(ws.head.ensure((size_t)ntet));
-    TESS_HIP(ws.coef.ensure((size_t)ntet));
-    TESS_HIP(ws.counts.ensure((size_t)nmat));
-    TESS_HIP(ws.base.ensure((size_t)nmat));
-    TESS_HIP(ws.scan.ensure(scan_scratch_elems(nmat)));
-    TESS_HIP(ws.tile_items.ensure((size_t)ntiles + 1));
-    TESS_HIP(ws.plan.ensure(1));
+tess_status ensure_front(Workspace &ws, const Geometry &g) {
+    TESS_HIP(ws.head.ensure((size_t)g.ntet));
+    TESS_HIP(ws.coef.ensure((size_t)g.ntet));
+    TESS_HIP(ws.counts.ensure((size_t)g.nmat));
+    TESS_HIP(ws.base.ensure((size_t)g.nmat));
+    TESS_HIP(ws.scan.ensure(scan_scratch_elems(g.nmat)));
+    TESS_HIP(ws.tile_items.ensure((size_t)g.ntiles + 1));
+    TESS_HIP(ws.acc.ensure((size_t)g.npix));
     TESS_HIP(ws.counters.ensure(1));
-    TESS_HIP(ws.acc.ensure((size_t)npix));
+    TESS_HIP(ws.overflow.ensure(1));
+    return TESS_OK;
+}
 
+unsigned long long max_items_for(const Geometry &g, int chunk, unsigned long long cap) {
+    return cap / (unsigned long long)chunk + (unsigned long long)g.ntiles;
+}
+
+tess_status ensure_back(Workspace &ws, const Geometry &g, int chunk, unsigned long long cap) {
+    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(max_items_for(g, chunk, cap), 1)));
+    TESS_HIP(ws.pairs.ensure((size_t)std::max<unsigned long long>(cap, 1)));
+    return TESS_OK;
+}
+
+// Setup, count, scan and totals of one image (no host synchronisation).
+tess_status enqueue_front(const Geometry &g, Workspace &ws, PlanOut *slot, unsigned long long cap,
+                          unsigned int *overflow, hipStream_t s) {
+    TESS_HIP(launch_setup(g.lp, g.vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
+    TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));
+    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, cap, slot, overflow, s));
+    return TESS_OK;
+}
+
+// Work items, scatter, raster and finalize of one image into `image`, for at
+// most `cap` pairs (the buffers hold that many).
+tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigned long long cap,
+                         Workspace &ws, PlanOut *slot, float *image, hipStream_t s, hipEvent_t after_bin,
+                         hipEvent_t after_raster) {
+    TESS_HIP(launch_plan(ws.counts.p, ws.base.p, g.B, chunk, cap, ws.tile_items.p, slot, s));
+    TESS_HIP(launch_items(ws.base.p, ws.tile_items.p, g.B, chunk, slot, ws.items.p, s));
+    TESS_HIP(launch_scatter(ws.head.p, g.ntet, g.B, ws.base.p, ws.pairs.p, cap, s));
+    TESS_HIP(launch_zero(ws.acc.p, g.npix, s));
+    if (after_bin) TESS_HIP(hipEventRecord(after_bin, s));
+    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.pairs.p, ws.items.p, max_items_for(g, chunk, cap), slot,
+                           g.B, plan.block, ws.acc.p, ws.counters.p, s));
+    if (after_raster) TESS_HIP(hipEventRecord(after_raster, s));
+    TESS_HIP(launch_finalize(ws.acc.p, g.B, image, s));
+    return TESS_OK;
+}
+
+void fill_stats(tess_stats *stats, const DevCounters &c, const Plan &plan, int chunk) {
+    stats->tets = c.tets;
+    stats->zero_volume = c.zero_volume;
+    stats->inverted = c.inverted;
+    stats->fp64_dets = c.fp64_dets;
+    stats->degenerate = c.degenerate;
+    stats->fragments = c.fragments;
+    stats->spans = c.spans;
+    stats->tile_rows = plan.Th;
+    stats->tile_cols = plan.Tw;
+    stats->chunk = chunk;
+    stats->block = plan.block;
+}
+
+// One image, synchronising once to size the pair buffer from its own count.
+tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan &plan, float *image,
+                         tess_stats *stats, hipStream_t s, Workspace &ws) {
+    Geometry g;
+    tess_status st = make_geometry(L, v, plan, g);
+    if (st != TESS_OK) return st;
+    st = ensure_front(ws, g);
+    if (st != TESS_OK) return st;
+    TESS_HIP(ws.plan.ensure(1));
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
-    TESS_HIP(hipMemsetAsync(ws.counters.p, 0, sizeof(DevCounters), s));
-    TESS_HIP(launch_setup(lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    TESS_HIP(launch_zero((double *)ws.counters.p, sizeof(DevCounters) / sizeof(double), s));
+    TESS_HIP(launch_setup(g.lp, g.vp, ws.head.p, ws.coef.p, ws.counters.p, s));
     if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
-    TESS_HIP(launch_count(ws.head.p, ntet, B, ws.counts.p, s));
-    TESS_HIP(launch_scan(ws.counts.p, ws.base.p, nmat, ws.scan.p, s));
-    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, B, ws.plan.p, s));
+    TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
+    TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));
+    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, ~0ull, ws.plan.p, nullptr, s));
     TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
     TESS_HIP(hipStreamSynchronize(s));
-    const unsigned long long total_pairs = ws.host_plan->total_pairs;
-    // work items: a few per CU at least, each long enough to amortise its tile flush
-    int chunk = plan.chunk;
-    if (chunk == 0) {
-        const unsigned long long want = total_pairs / 4096ull;
-        chunk = (int)std::min<unsigned long long>(65536ull, std::max<unsigned long long>(1024ull, want));
-    }
-    const unsigned long long max_items = total_pairs / (unsigned long long)chunk + (unsigned long long)ntiles;
-    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(max_items, 1)));
-    TESS_HIP(ws.pairs.ensure((size_t)std::max<unsigned long long>(total_pairs, 1)));
-    TESS_HIP(launch_plan(ws.counts.p, ws.base.p, B, chunk, ws.tile_items.p, ws.plan.p, s));
-    TESS_HIP(launch_items(ws.base.p, ws.tile_items.p, B, chunk, ws.plan.p, ws.items.p, s));
-    TESS_HIP(launch_scatter(ws.head.p, ntet, B, ws.base.p, ws.pairs.p, total_pairs, s));
-    TESS_HIP(launch_zero(ws.acc.p, npix, s));
-    if (stats) TESS_HIP(hipEventRecord(ws.ev[2], s));
-    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.pairs.p, ws.items.p, max_items, ws.plan.p, B, plan.block,
-                           ws.acc.p, ws.counters.p, s));
-    if (stats) TESS_HIP(hipEventRecord(ws.ev[3], s));
-    TESS_HIP(launch_finalize(ws.acc.p, B, image, s));
+    const unsigned long long total = ws.host_plan->total_pairs;
+    const int chunk = plan.chunk ? plan.chunk : auto_chunk(total);
+    st = ensure_back(ws, g, chunk, total);
+    if (st != TESS_OK) return st;
+    st = enqueue_back(g, plan, chunk, total, ws, ws.plan.p, image, s, stats ? ws.ev[2] : nullptr,
+                      stats ? ws.ev[3] : nullptr);
+    if (st != TESS_OK) return st;
     if (stats) {
         TESS_HIP(hipEventRecord(ws.ev[4], s));
         TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters),
@@ -401,22 +475,11 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
         TESS_HIP(hipEventElapsedTime(&t_bin, ws.ev[1], ws.ev[2]));
         TESS_HIP(hipEventElapsedTime(&t_raster, ws.ev[2], ws.ev[3]));
         TESS_HIP(hipEventElapsedTime(&t_fin, ws.ev[3], ws.ev[4]));
-        const DevCounters &c = *ws.host_counters;
         const PlanOut &P = *ws.host_plan;
-        stats->tets = c.tets;
-        stats->zero_volume = c.zero_volume;
-        stats->inverted = c.inverted;
-        stats->fp64_dets = c.fp64_dets;
-        stats->degenerate = c.degenerate;
-        stats->fragments = c.fragments;
-        stats->spans = c.spans;
+        fill_stats(stats, *ws.host_counters, plan, chunk);
         stats->bin_pairs = P.total_pairs;
         stats->max_bin = (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull);
         stats->work_items = (uint32_t)P.n_items;
-        stats->tile_rows = plan.Th;
-        stats->tile_cols = plan.Tw;
-        stats->chunk = chunk;
-        stats->block = plan.block;
         stats->ms = ms;
         stats->setup_ms = t_setup;
         stats->bin_ms = t_bin;
@@ -446,39 +509,256 @@ tess_status check_project_args(tess_lattice L, const tess_view *v, const tess_tu
     return TESS_OK;
 }
 
-tess_status project_one(tess_lattice L, const tess_view *v, const tess_tune *tune, float *image,
-                        tess_stats *stats, hipStream_t s) {
+tess_status lock_workspace(tess_lattice L, hipStream_t s, Workspace **ws) {
     int dev = 0;
     TESS_HIP(hipGetDevice(&dev));
     if (dev != L->device) return fail(TESS_EINVAL, "lattice lives on device %d, current device is %d", L->device, dev);
-    Workspace *ws = nullptr;
-    tess_status st = get_workspace(dev, s, &ws);
-    if (st != TESS_OK) return st;
-    std::lock_guard<std::mutex> lock(ws->mu);
-    const Plan plan = choose_plan(v, tune);
-    return project_impl(L, v, plan, image, stats, s, *ws);
+    return get_workspace(dev, s, ws);
 }
 
-void add_stats(tess_stats &acc, const tess_stats &s) {
-    acc.tets += s.tets;
-    acc.zero_volume += s.zero_volume;
-    acc.inverted += s.inverted;
-    acc.fp64_dets += s.fp64_dets;
-    acc.degenerate += s.degenerate;
-    acc.fragments += s.fragments;
-    acc.spans += s.spans;
-    acc.bin_pairs += s.bin_pairs;
-    acc.max_bin = std::max(acc.max_bin, s.max_bin);
-    acc.work_items += s.work_items;
-    acc.tile_rows = s.tile_rows;
-    acc.tile_cols = s.tile_cols;
-    acc.chunk = s.chunk;
-    acc.block = s.block;
-    acc.ms += s.ms;
-    acc.setup_ms += s.setup_ms;
-    acc.bin_ms += s.bin_ms;
-    acc.raster_ms += s.raster_ms;
-    acc.finalize_ms += s.finalize_ms;
+// ---------------------------------------------------------------- batches
+// Raster parameters and pair capacity chosen for a batch shape, kept for
+// later calls with the same lattice and image shape.
+struct Tuned {
+    Plan plan;
+    int chunk;
+    unsigned long long cap;
+};
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tuned;
+
+std::string shape_key(const tess_lattice_s *L, const tess_view *v, int n_snaps, int n_views) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%d:%d:%d:%d|%dx%d:%d|%d:%d", L->desc.dims[0], L->desc.dims[1], L->desc.dims[2],
+             L->desc.periodic, v->width, v->height, v->wrap, n_snaps, n_views);
+    return buf;
+}
+
+// Times one image under each candidate tiling (synchronous calls) and keeps
+// the fastest; the pair capacity is 1.5 times the largest count seen over the
+// snapshots' first views.
+tess_status autotune(const tess_lattice *snaps, int n_snaps, const tess_view *views, float *scratch_image,
+                     hipStream_t s, Workspace &ws, Tuned &out) {
+    Plan base = choose_plan(&views[0], nullptr);
+    unsigned long long most = 0;
+    int heavy = 0;
+    for (int i = 0; i < n_snaps; ++i) {
+        tess_stats st;
+        std::memset(&st, 0, sizeof(st));
+        tess_status rc = project_impl(snaps[i], &views[0], base, scratch_image, &st, s, ws);
+        if (rc != TESS_OK) return rc;
+        if (st.bin_pairs >= most) {
+            most = st.bin_pairs;
+            heavy = i;
+        }
+    }
+    const int W = views[0].width;
+    std::vector<Plan> cands;
+    for (int Tw : {std::min(W, 1024), std::min(W, 512), std::min(W, 256)}) {
+        for (int Th : {8, 16, 32, 64}) {
+            if ((int64_t)Th * Tw > kMaxTileCells || (int64_t)Th * Tw < 2048) continue;
+            bool dup = false;
+            for (const Plan &c : cands) dup |= (c.Th == Th && c.Tw == Tw);
+            if (dup) continue;
+            Plan p = base;
+            p.Th = Th;
+            p.Tw = Tw;
+            cands.push_back(p);
+        }
+    }
+    if (cands.empty()) cands.push_back(base);
+    float best_ms = 0;
+    Plan best = cands[0];
+    for (const Plan &p : cands) {
+        float ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            tess_stats st;
+            std::memset(&st, 0, sizeof(st));
+            tess_status rc = project_impl(snaps[heavy], &views[0], p, scratch_image, &st, s, ws);
+            if (rc != TESS_OK) return rc;
+            ms = st.ms;
+        }
+        if (&p == &cands[0] || ms < best_ms) {
+            best_ms = ms;
+            best = p;
+        }
+    }
+    out.plan = best;
+    out.chunk = auto_chunk(most);
+    out.cap = most + most / 2 + 4096;
+    return TESS_OK;
+}
+
+std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *views, int n_views, float *images,
+                      const Tuned &t, const Workspace &ws) {
+    std::string k;
+    auto put = [&](const void *p, size_t n) { k.append((const char *)p, n); };
+    for (int i = 0; i < n_snaps; ++i) {
+        put(&snaps[i]->desc, sizeof(tess_build_desc));
+        put(&snaps[i]->x, sizeof(void *));
+        put(&snaps[i]->y, sizeof(void *));
+        put(&snaps[i]->z, sizeof(void *));
+    }
+    put(views, sizeof(tess_view) * (size_t)n_views);
+    put(&images, sizeof(images));
+    put(&t, sizeof(t));
+    const void *bufs[] = {ws.head.p, ws.coef.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
+                          ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p, ws.overflow.p};
+    put(bufs, sizeof(bufs));
+    return k;
+}
+
+tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tess_view *views, int n_views,
+                               const tess_tune *tune, float *images, tess_stats *stats, hipStream_t s,
+                               Workspace &ws) {
+    const size_t img = (size_t)views[0].width * views[0].height;
+    const int n_img = n_snaps * n_views;
+    // raster parameters and capacity, sized once per batch shape and tune
+    Tuned t;
+    std::string key = shape_key(snaps[0], &views[0], n_snaps, n_views);
+    if (tune) {
+        char buf[96];
+        snprintf(buf, sizeof(buf), "|tune %d %d %d %d", tune->tile_rows, tune->tile_cols, tune->chunk, tune->block);
+        key += buf;
+    }
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            t = it->second;
+            have = true;
+        }
+    }
+    if (!have) {
+        if (tune) {
+            t.plan = choose_plan(&views[0], tune);
+            unsigned long long most = 0;
+            for (int i = 0; i < n_snaps; ++i) {
+                tess_stats st;
+                std::memset(&st, 0, sizeof(st));
+                tess_status rc = project_impl(snaps[i], &views[0], t.plan, images, &st, s, ws);
+                if (rc != TESS_OK) return rc;
+                most = std::max<unsigned long long>(most, st.bin_pairs);
+            }
+            t.chunk = t.plan.chunk ? t.plan.chunk : auto_chunk(most);
+            t.cap = most + most / 2 + 4096;
+        } else {
+            tess_status rc = autotune(snaps, n_snaps, views, images, s, ws, t);
+            if (rc != TESS_OK) return rc;
+        }
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[key] = t;
+    }
+    // buffers for the largest image of the batch, then the graph
+    Geometry g0;
+    tess_status st = make_geometry(snaps[0], &views[0], t.plan, g0);
+    if (st != TESS_OK) return st;
+    st = ensure_front(ws, g0);
+    if (st != TESS_OK) return st;
+    st = ensure_back(ws, g0, t.chunk, t.cap);
+    if (st != TESS_OK) return st;
+    TESS_HIP(ws.plan.ensure((size_t)n_img));
+    if (ws.host_plan_cap < (size_t)n_img) {
+        TESS_HIP(hipHostFree(ws.host_plan));
+        ws.host_plan = nullptr;
+        TESS_HIP(hipHostMalloc((void **)&ws.host_plan, sizeof(PlanOut) * (size_t)n_img, hipHostMallocDefault));
+        ws.host_plan_cap = (size_t)n_img;
+    }
+    const std::string gkey = graph_key(snaps, n_snaps, views, n_views, images, t, ws);
+    if (!ws.graph || ws.graph_key != gkey) {
+        if (ws.graph) {
+            TESS_HIP(hipGraphExecDestroy(ws.graph));
+            ws.graph = nullptr;
+        }
+        hipStream_t c = ws.capture;
+        TESS_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        tess_status cst = TESS_OK;
+        auto record = [&]() -> tess_status {
+            TESS_HIP(launch_zero((double *)ws.counters.p, sizeof(DevCounters) / sizeof(double), c));
+            TESS_HIP(launch_zero((double *)ws.overflow.p, 1, c));  // the buffer holds >= 64 words
+            for (int i = 0; i < n_snaps; ++i)
+                for (int v = 0; v < n_views; ++v) {
+                    const int k = i * n_views + v;
+                    Geometry g;
+                    tess_status r = make_geometry(snaps[i], &views[v], t.plan, g);
+                    if (r != TESS_OK) return r;
+                    r = enqueue_front(g, ws, ws.plan.p + k, t.cap, ws.overflow.p, c);
+                    if (r != TESS_OK) return r;
+                    r = enqueue_back(g, t.plan, t.chunk, t.cap, ws, ws.plan.p + k, images + (size_t)k * img, c,
+                                     nullptr, nullptr);
+                    if (r != TESS_OK) return r;
+                }
+            return TESS_OK;
+        };
+        cst = record();
+        hipGraph_t graph = nullptr;
+        const hipError_t end = hipStreamEndCapture(c, &graph);
+        if (cst != TESS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return cst;
+        }
+        if (end != hipSuccess) return fail(TESS_EHIP, "batch graph capture: %s", hipGetErrorString(end));
+        const hipError_t inst = hipGraphInstantiate(&ws.graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (inst != hipSuccess) {
+            ws.graph = nullptr;
+            return fail(TESS_EHIP, "batch graph instantiation: %s", hipGetErrorString(inst));
+        }
+        ws.graph_key = gkey;
+    }
+    if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
+    TESS_HIP(hipGraphLaunch(ws.graph, s));
+    if (stats) TESS_HIP(hipEventRecord(ws.ev[4], s));
+    TESS_HIP(hipMemcpyAsync(ws.host_overflow, ws.overflow.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut) * (size_t)n_img, hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipStreamSynchronize(s));
+    tess_stats acc;
+    std::memset(&acc, 0, sizeof(acc));
+    if (stats) {
+        float ms = 0;
+        TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
+        fill_stats(&acc, *ws.host_counters, t.plan, t.chunk);
+        acc.ms = ms;
+        for (int k = 0; k < n_img; ++k) {
+            acc.bin_pairs += ws.host_plan[k].total_pairs;
+            acc.max_bin = std::max<uint32_t>(acc.max_bin, (uint32_t)std::min<unsigned long long>(
+                                                              ws.host_plan[k].max_bin, 0xffffffffull));
+            acc.work_items += (uint32_t)ws.host_plan[k].n_items;
+        }
+    }
+    if (*ws.host_overflow) {
+        // images whose pairs exceeded the capacity: redo them one by one
+        std::vector<int> redo;
+        for (int k = 0; k < n_img; ++k)
+            if (ws.host_plan[k].total_pairs > t.cap) redo.push_back(k);
+        for (int k : redo) {
+            tess_stats one;
+            std::memset(&one, 0, sizeof(one));
+            const int i = k / n_views, v = k % n_views;
+            tess_status rc = project_impl(snaps[i], &views[v], t.plan, images + (size_t)k * img,
+                                          stats ? &one : nullptr, s, ws);
+            if (rc != TESS_OK) return rc;
+            if (stats) {
+                // the graph's counters missed this image's raster
+                acc.fragments += one.fragments;
+                acc.spans += one.spans;
+                acc.work_items += one.work_items;
+                acc.ms += one.ms;
+            }
+        }
+        // the next call sizes for the largest count seen
+        unsigned long long most = 0;
+        for (int k = 0; k < n_img; ++k) most = std::max<unsigned long long>(most, ws.host_plan[k].total_pairs);
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) it->second.cap = most + most / 2 + 4096;
+        }
+    }
+    if (stats) *stats = acc;
+    return TESS_OK;
 }
 }  // namespace
 
@@ -487,7 +767,12 @@ extern "C" tess_status tess_project(tess_lattice L, const tess_view *v, const te
     tess_status st = check_project_args(L, v, tune, image);
     if (st != TESS_OK) return st;
     if (stats) std::memset(stats, 0, sizeof(*stats));
-    st = project_one(L, v, tune, image, stats, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    st = lock_workspace(L, s, &ws);
+    if (st != TESS_OK) return st;
+    std::lock_guard<std::mutex> lock(ws->mu);
+    st = project_impl(L, v, choose_plan(v, tune), image, stats, s, *ws);
     return st == TESS_OK ? ok() : st;
 }
 
@@ -502,6 +787,10 @@ extern "C" tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_s
         for (int a = 0; a < 3; ++a)
             if (snaps[s]->desc.dims[a] != snaps[0]->desc.dims[a])
                 return fail(TESS_EINVAL, "snapshot %d has different dims", s);
+        if (snaps[s]->desc.periodic != snaps[0]->desc.periodic)
+            return fail(TESS_EINVAL, "snapshot %d differs in periodicity", s);
+        if (snaps[s]->device != snaps[0]->device)
+            return fail(TESS_EINVAL, "snapshot %d lives on another device", s);
     }
     for (int32_t v = 0; v < n_views; ++v) {
         if (views[v].width != views[0].width || views[v].height != views[0].height)
@@ -511,19 +800,14 @@ extern "C" tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_s
             if (st != TESS_OK) return st;
         }
     }
-    tess_stats acc;
-    std::memset(&acc, 0, sizeof(acc));
-    const size_t img = (size_t)views[0].width * views[0].height;
-    for (int32_t s = 0; s < n_snaps; ++s)
-        for (int32_t v = 0; v < n_views; ++v) {
-            tess_stats one;
-            tess_status st = project_one(snaps[s], &views[v], tune, images + ((size_t)s * n_views + v) * img,
-                                         stats ? &one : nullptr, (hipStream_t)stream);
-            if (st != TESS_OK) return st;
-            if (stats) add_stats(acc, one);
-        }
-    if (stats) *stats = acc;
-    return ok();
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    hipStream_t s = (hipStream_t)stream;
+    Workspace *ws = nullptr;
+    tess_status st = lock_workspace(snaps[0], s, &ws);
+    if (st != TESS_OK) return st;
+    std::lock_guard<std::mutex> lock(ws->mu);
+    st = project_batch_impl(snaps, n_snaps, views, n_views, tune, images, stats, s, *ws);
+    return st == TESS_OK ? ok() : st;
 }
 
 extern "C" const char *tess_last_error(void) { return g_error.c_str(); }

@@ -116,14 +116,17 @@ size_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan(const uint32_t *counts, uint64_t *base, int64_t n, uint64_t *scratch,
                        hipStream_t stream);
 
-// Total pairs and the longest tile list into out (n_items is left alone).
+// Total pairs and the longest tile list into out (n_items set to 0); when
+// the total exceeds cap, *overflow (if non-null) gets bit 0 set.
 hipError_t launch_totals(const uint32_t *counts, const uint64_t *base, const BinParams &B,
-                         PlanOut *out, hipStream_t stream);
+                         unsigned long long cap, PlanOut *out, unsigned int *overflow,
+                         hipStream_t stream);
 
 // Per-tile chunking: writes tile_items[ntiles + 1] (exclusive scan of chunk
-// counts) and out->n_items.
+// counts) and out->n_items; no items at all when the pairs exceed cap.
 hipError_t launch_plan(const uint32_t *counts, const uint64_t *base, const BinParams &B,
-                       int32_t chunk, uint32_t *tile_items, PlanOut *out, hipStream_t stream);
+                       int32_t chunk, unsigned long long cap, uint32_t *tile_items, PlanOut *out,
+                       hipStream_t stream);
 
 hipError_t launch_items(const uint64_t *base, const uint32_t *tile_items, const BinParams &B,
                         int32_t chunk, const PlanOut *plan, WorkItem *items, hipStream_t stream);

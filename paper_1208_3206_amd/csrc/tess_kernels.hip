@@ -251,7 +251,8 @@ __device__ inline uint64_t tile_end(const uint64_t *base, const uint32_t *counts
 
 __global__ void __launch_bounds__(kScanBlock) k_totals(const uint32_t *__restrict__ counts,
                                                        const uint64_t *__restrict__ base, BinParams B,
-                                                       PlanOut *__restrict__ out) {
+                                                       unsigned long long cap, PlanOut *__restrict__ out,
+                                                       unsigned int *__restrict__ overflow) {
     __shared__ unsigned long long mx;
     const int ntiles = B.ntx * B.nty;
     if (threadIdx.x == 0) mx = 0;
@@ -262,28 +263,35 @@ __global__ void __launch_bounds__(kScanBlock) k_totals(const uint32_t *__restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        out->total_pairs = tile_end(base, counts, B, ntiles - 1, ntiles);
+        const unsigned long long total = tile_end(base, counts, B, ntiles - 1, ntiles);
+        out->total_pairs = total;
         out->max_bin = mx;
+        out->n_items = 0;
+        if (total > cap && overflow) atomicOr(overflow, 1u);
     }
 }
 
-hipError_t launch_totals(const uint32_t *counts, const uint64_t *base, const BinParams &B, PlanOut *out,
-                         hipStream_t stream) {
-    hipLaunchKernelGGL(k_totals, dim3(1), dim3(kScanBlock), 0, stream, counts, base, B, out);
+hipError_t launch_totals(const uint32_t *counts, const uint64_t *base, const BinParams &B,
+                         unsigned long long cap, PlanOut *out, unsigned int *overflow, hipStream_t stream) {
+    hipLaunchKernelGGL(k_totals, dim3(1), dim3(kScanBlock), 0, stream, counts, base, B, cap, out, overflow);
     return hipGetLastError();
 }
 
+// A list longer than the pair buffer (cap) gets no work items: the image is
+// then left unrastered and its PlanOut shows total_pairs > cap.
 __global__ void __launch_bounds__(kScanBlock) k_plan(const uint32_t *__restrict__ counts,
                                                      const uint64_t *__restrict__ base, BinParams B,
-                                                     int32_t chunk, uint32_t *__restrict__ tile_items,
+                                                     int32_t chunk, unsigned long long cap,
+                                                     uint32_t *__restrict__ tile_items,
                                                      PlanOut *__restrict__ out) {
     __shared__ uint64_t sh[64];
     const int ntiles = B.ntx * B.nty;
+    const bool fits = tile_end(base, counts, B, ntiles - 1, ntiles) <= cap;
     uint64_t carry = 0;
     for (int t0 = 0; t0 < ntiles; t0 += kScanBlock) {
         const int t = t0 + threadIdx.x;
         uint64_t chunks = 0;
-        if (t < ntiles) {
+        if (t < ntiles && fits) {
             const uint64_t len = tile_end(base, counts, B, t, ntiles) - tile_begin(base, B, t);
             chunks = (len + chunk - 1) / chunk;
         }
@@ -300,8 +308,9 @@ __global__ void __launch_bounds__(kScanBlock) k_plan(const uint32_t *__restrict_
 }
 
 hipError_t launch_plan(const uint32_t *counts, const uint64_t *base, const BinParams &B,
-                       int32_t chunk, uint32_t *tile_items, PlanOut *out, hipStream_t stream) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kScanBlock), 0, stream, counts, base, B, chunk,
+                       int32_t chunk, unsigned long long cap, uint32_t *tile_items, PlanOut *out,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kScanBlock), 0, stream, counts, base, B, chunk, cap,
                        tile_items, out);
     return hipGetLastError();
 }

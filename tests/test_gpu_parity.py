@@ -161,22 +161,63 @@ def test_repeatable_and_tiling_independent(tess, tiny_lattice):
         np.testing.assert_allclose(b, a, rtol=2.4e-7, atol=1e-12 * a.max())
 
 
-def test_batch_equals_single_projections(tess):
-    import torch
-    n = 16
+def batch_case(tess, n=16, growths=(1.0, 4.0), nviews=3, size=64):
     lats, xyzs = [], []
-    for D in (1.0, 4.0):
+    for D in growths:
         xyz = W.zeldovich(n, 5, D)
         xyzs.append(xyz)
         lats.append(tess.build(*dev(xyz), (n, n, n)))
-    views = [W.rotated_view(R, 64, 64) for R in W.random_rotations(3, seed=8)]
+    views = [W.rotated_view(R, size, size) for R in W.random_rotations(nviews, seed=8)]
+    return lats, xyzs, views
+
+
+def test_batch_equals_single_projections(tess):
+    # autotuned tiling, one captured graph for all images
+    import torch
+    lats, xyzs, views = batch_case(tess)
     imgs, st = tess.project_batch(lats, views, stats=True)
+    singles = 0
     for s in range(2):
         for v in range(3):
-            one = tess.project(lats[s], views[v])
-            torch.testing.assert_close(imgs[s, v], one, rtol=2.4e-7, atol=1e-12)
-    ref, _ = O.project_region(*xyzs[1], (n, n, n), views[2])
+            one, sst = tess.project(lats[s], views[v], stats=True)
+            torch.testing.assert_close(imgs[s, v], one, rtol=2.4e-7, atol=1e-9)
+            singles += sst["fragments"]
+    assert st["fragments"] == singles and st["tets"] == 6 * st["tets"] // 6
+    ref, _ = O.project_region(*xyzs[1], (16, 16, 16), views[2])
     assert_parity(imgs[1, 2].cpu().numpy(), ref, what="batch image")
+    # the graph is replayed: same images again
+    again = tess.project_batch(lats, views)
+    torch.testing.assert_close(again, imgs, rtol=2.4e-7, atol=1e-9)
+
+
+def test_batch_with_explicit_tune_and_new_output(tess):
+    import torch
+    lats, _, views = batch_case(tess, growths=(2.0, 5.0), nviews=2, size=48)
+    a = tess.project_batch(lats, views, tune=tess.make_tune(8, 48, 256, 512))
+    b = tess.project_batch(lats, views, tune=tess.make_tune(4, 16))  # another graph
+    torch.testing.assert_close(a, b, rtol=2.4e-7, atol=1e-9)
+    for s in range(2):
+        for v in range(2):
+            torch.testing.assert_close(a[s, v], tess.project(lats[s], views[v]), rtol=2.4e-7, atol=1e-9)
+
+
+def test_batch_capacity_overflow_is_redone(tess):
+    # the pair buffer is sized from each snapshot's first view; here that view
+    # looks at empty space, so the second view's pairs overflow it and the
+    # image is redone after the graph
+    import torch
+    n = 16
+    lat = tess.build(*dev(W.zeldovich(n, 5, 3.0)), (n, n, n))
+    R = W.random_rotations(1, seed=4)[0]
+    empty = W.rotated_view(R, 40, 40, side=0.5, center=(9.0, 9.0, 9.0))
+    full = W.rotated_view(R, 40, 40, side=2.0)
+    tune = tess.make_tune(4, 16)
+    imgs, st = tess.project_batch([lat], [empty, full], tune=tune, stats=True)
+    one, sst = tess.project(lat, full, tune=tune, stats=True)
+    assert sst["bin_pairs"] > 2 * 4096
+    torch.testing.assert_close(imgs[0, 1], one, rtol=2.4e-7, atol=1e-9)
+    assert float(imgs[0, 0].abs().max()) == 0.0
+    assert st["fragments"] == sst["fragments"]
 
 
 # ----------------------------------------------- full-size configurations

@@ -85,6 +85,159 @@ def cpu_baseline(xyz, w, view, full_fragments: float):
     }
 
 
+def run_batched(args, w, tess, W, torch):
+    """Many snapshots x views in one tess_project_batch call (captured graph)."""
+    dev = torch.device("cuda:0")
+    lats = []
+    for D in w.growth:
+        xyz = W.zeldovich(w.n, w.kmax, D)
+        lats.append(tess.build(*[torch.from_numpy(a).to(dev) for a in xyz], (w.n,) * 3,
+                               precision=args.precision))
+    views = W.workload_views(w)
+    out = torch.empty((len(lats), len(views), w.height, w.width), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    _, st0 = tess.project_batch(lats, views, out=out, stats=True)  # autotune + graph capture
+    first_s = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        tess.project_batch(lats, views, out=out)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    dev_ms = 0.0
+    for _ in range(args.steps):
+        _, st = tess.project_batch(lats, views, out=out, stats=True)
+        dev_ms += st["ms"] / args.steps
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t_start) * 1e3 / args.steps
+    n_img = len(lats) * len(views)
+    spans = st0["spans"]
+    achieved = OPS_PER_SPAN * spans / (dev_ms * 1e-3)
+    result = {
+        "metric": "tets/s over all images of a batch",
+        "value": w.tets * n_img / (ms * 1e-3),
+        "unit": "tets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Zel'dovich lattices, kmax %d, D %s)" % (w.kmax, list(w.growth)),
+        "config": {"workload": w.name, "lattice": w.n, "snapshots": len(lats), "views": len(views),
+                   "images": n_img, "image": [w.width, w.height],
+                   "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"]},
+        "images_per_s": n_img / (ms * 1e-3),
+        "fragments": st0["fragments"],
+        "fragments_per_s": st0["fragments"] / (ms * 1e-3),
+        "spans": spans,
+        "bin_pairs": st0["bin_pairs"],
+        "graph_ms": dev_ms,
+        "first_call_s": first_s,
+        "roofline": {"kernel": "whole batch graph", "bound": "alu", "achieved": achieved / 1e12,
+                     "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s", "frac": achieved / PEAK_VALU_OPS,
+                     "traffic": None, "ops_per_launch": OPS_PER_SPAN * spans, "ops_per_span": OPS_PER_SPAN},
+    }
+    print(json.dumps(result), flush=True)
+
+
+def spectral_upsample(xyz, n, r):
+    """Zero-padded FFT upsampling of a periodic lattice's displacements by r
+    (the non-learned control: exact for a field band-limited below n/2)."""
+    import numpy as np
+    import workloads as W
+    q = W.lattice_q(n)
+    out = []
+    m = n * r
+    for c in range(3):
+        s = (xyz[c].astype(np.float64) - q[:, c])
+        s -= np.ceil(s - 0.5)                      # minimal image, unit box
+        S = np.fft.fftn(s.reshape(n, n, n))
+        P = np.zeros((m, m, m), dtype=np.complex128)
+        h = n // 2
+        idx = np.r_[0:h, m - h:m]
+        src = np.r_[0:h, n - h:n]
+        P[np.ix_(idx, idx, idx)] = S[np.ix_(src, src, src)]
+        fine = np.real(np.fft.ifftn(P)) * r ** 3
+        shape = [1, 1, 1]
+        shape[2 - c] = m
+        qf = (np.arange(m) / m).reshape(shape)
+        out.append(np.ascontiguousarray(W.wrap_to_f32(qf + fine, 1.0).ravel()))
+    return out
+
+
+def run_learned(args, w, tess, W, torch):
+    """L1 against the high-resolution reference vs time: plain lattices M^3
+    of the same analytic field, and the 64^3 lattice refined r-fold with the
+    network (trained once; inference from the trained weights)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    view = W.z_view(w.width, w.height)
+    wr = W.LEARNED_REF
+
+    def timed_render(xyz, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = [torch.from_numpy(a).to(dev) for a in xyz]
+        lat = tess.build(*d, (n,) * 3)
+        img = tess.project(lat, view)
+        torch.cuda.synchronize()
+        return img.double(), time.perf_counter() - t0
+
+    ref, _ = timed_render(W.zeldovich(wr.n, wr.kmax, wr.growth[0]), wr.n)
+    l1 = lambda img: float((img - ref).abs().sum() / ref.abs().sum())
+    plain = []
+    for m in (64, 96, 128, 160, 192, 256):
+        xyz = W.zeldovich(m, w.kmax, w.growth[0])
+        timed_render(xyz, m)  # warm
+        img, t = timed_render(xyz, m)
+        plain.append({"M": m, "tets": 6 * m ** 3, "l1": l1(img), "s": t})
+    coarse_xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
+    coarse = tess.build(*[torch.from_numpy(a).to(dev) for a in coarse_xyz], (w.n,) * 3)
+    _, rep, weights = tess.refine(coarse, r=2, mode="mlp", want_weights=True)
+    learned = []
+    for r in (1, 2, 3, 4):
+        for rep_i in range(2):  # second pass timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            d = [torch.from_numpy(a).to(dev) for a in coarse_xyz]
+            lat = tess.build(*d, (w.n,) * 3)
+            fine, frep = tess.refine(lat, r=r, mode="mlp", steps=0, weights_in=weights)
+            img = tess.project(fine, view)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            del fine
+        learned.append({"r": r, "tets": 6 * (w.n * r) ** 3, "l1": l1(img.double()), "s": t,
+                        "infer_ms": frep["infer_ms"]})
+    spec = spectral_upsample(coarse_xyz, w.n, 4)
+    img, t = timed_render(spec, w.n * 4)
+    e_learned = learned[-1]["l1"]
+    plain_at = [p for p in plain if p["l1"] <= e_learned]
+    result = {
+        "metric": "L1 vs the 256^3 reference at 2048^2: learned refinement and plain lattices",
+        "value": e_learned,
+        "unit": "relative L1 (learned r=4)",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": learned[-1]["s"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 raster, bf16 network",
+        "data": "synthetic (seeded Zel'dovich lattices, kmax 16, D 5)",
+        "config": {"workload": w.name, "coarse": w.n, "reference": wr.n, "image": [w.width, w.height]},
+        "plain": plain,
+        "learned": learned,
+        "training": {"steps": 10000, "batch": 8192, "loss_first": rep["loss_first"],
+                     "loss_last": rep["loss_last"], "train_ms": rep["train_ms"]},
+        "spectral_control": {"r": 4, "l1": l1(img), "s": t},
+        "gain_over_plain_64": plain[0]["l1"] / e_learned,
+        "plain_lattice_at_equal_l1": plain_at[0] if plain_at else None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     global args
     args = parse()
@@ -100,6 +253,12 @@ def main():
     w = W.ALL[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if len(w.growth) > 1 or w.n_views > 1:
+        run_batched(args, w, tess, W, torch)
+        return
+    if w is W.LEARNED:
+        run_learned(args, w, tess, W, torch)
+        return
     t0 = time.perf_counter()
     xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
     gen_s = time.perf_counter() - t0

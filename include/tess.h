@@ -185,17 +185,22 @@ tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_snaps,
  * loss = mean over samples of |s - target|^2, Adam (0.9, 0.999, 1e-8) with a
  * cosine learning rate lr0 -> lr1, bf16 operands with FP32 accumulation and
  * FP32 master weights.  The r-fold sub-lattice (r d tracers per axis) is
- * then placed: coarse tracers keep their positions, the others get
- * q + s(q).  TESS_REFINE_LINEAR instead places every fine tracer by the
- * affine map of the coarse tetrahedron containing its Lagrangian point, so
- * the fine tetrahedra nest inside the coarse ones and the projection is
- * unchanged.  The paper's tessellation (data-storage section) is the one
- * rendered; the network is an addition of this library.
+ * then placed; coarse tracers keep their positions in every mode:
+ *  - TESS_REFINE_MLP: a fine tracer gets (q + s(q)) L plus the network's
+ *    residuals x - (q + s(q)) L at the corners of the coarse tetrahedron that
+ *    contains q, interpolated there (so the placement is exact at the coarse
+ *    tracers and the network supplies the shape between them);
+ *  - TESS_REFINE_MLP_RAW: (q + s(q)) L alone;
+ *  - TESS_REFINE_LINEAR: the affine map of the coarse tetrahedron containing
+ *    its Lagrangian point, so the fine tetrahedra nest inside the coarse ones
+ *    and the projection is unchanged.
+ * The paper's tessellation (data-storage section) is the one rendered; the
+ * network is an addition of this library.
  * ---------------------------------------------------------------------- */
 #define TESS_MLP_PARAMS 66435   /* W1 (128x128), b1, ..., W4, b4, W5 (3x128), b5; W row = output */
 #define TESS_MLP_FREQS 64
 
-typedef enum { TESS_REFINE_LINEAR = 0, TESS_REFINE_MLP = 1 } tess_refine_mode;
+typedef enum { TESS_REFINE_LINEAR = 0, TESS_REFINE_MLP = 1, TESS_REFINE_MLP_RAW = 2 } tess_refine_mode;
 
 typedef struct {
     int32_t r;              /* refinement factor, 1..16                            */
@@ -218,7 +223,7 @@ typedef struct {
     int64_t fine_tracers;
 } tess_refine_report;
 
-/* Defaults: r 4, MLP, 3000 steps, batch 8192, sigma 8, lr 1e-3 -> 1e-5, seed 2. */
+/* Defaults: r 4, MLP, 10000 steps, batch 8192, sigma 8, lr 1e-2 -> 1e-5, seed 2. */
 tess_status tess_refine_desc_default(tess_refine_desc *desc);
 
 /*

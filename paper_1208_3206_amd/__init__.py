@@ -80,7 +80,7 @@ class TessRefineReport(ctypes.Structure):
 
 MLP_PARAMS = 66435
 MLP_FREQS = 64
-REFINE_LINEAR, REFINE_MLP = 0, 1
+REFINE_LINEAR, REFINE_MLP, REFINE_MLP_RAW = 0, 1, 2
 
 
 class TessError(RuntimeError):
@@ -294,15 +294,15 @@ class _Owned(Lattice):
         self._tensors = []
 
 
-def refine(lat: Lattice, r: int = 4, mode: str = "mlp", steps: int = 3000, batch: int = 8192,
-           rff_sigma: float = 8.0, lr0: float = 1e-3, lr1: float = 1e-5, seed: int = 2,
+def refine(lat: Lattice, r: int = 4, mode: str = "mlp", steps: int = 10000, batch: int = 8192,
+           rff_sigma: float = 8.0, lr0: float = 1e-2, lr1: float = 1e-5, seed: int = 2,
            rff_B=None, weights_in=None, want_weights: bool = False, stream=None):
     """Refined lattice (tess_refine); returns (lattice, report dict[, weights])."""
     import numpy as np
     d = TessRefineDesc()
     _check(_lib.tess_refine_desc_default(ctypes.byref(d)), "tess_refine_desc_default")
     d.r, d.steps, d.batch = int(r), int(steps), int(batch)
-    d.mode = {"linear": REFINE_LINEAR, "mlp": REFINE_MLP}[mode]
+    d.mode = {"linear": REFINE_LINEAR, "mlp": REFINE_MLP, "mlp_raw": REFINE_MLP_RAW}[mode]
     d.rff_sigma, d.lr0, d.lr1, d.seed = float(rff_sigma), float(lr0), float(lr1), int(seed)
     keep = []
     if rff_B is not None:

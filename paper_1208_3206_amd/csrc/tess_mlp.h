@@ -53,6 +53,16 @@ hipError_t launch_place_mlp(const float *cx, const float *cy, const float *cz, c
                             int64_t first, int64_t n, const float *q, const float *pred,
                             const double box[3], const int fdims[3], float *fx, float *fy, float *fz,
                             hipStream_t s);
+// Residuals x - (q + s(q)) L of the network at coarse tracers first..first+n-1.
+hipError_t launch_coarse_residual(const float *cx, const float *cy, const float *cz, int64_t first, int64_t n,
+                                  const float *q, const float *pred, const double box[3], float *rx, float *ry,
+                                  float *rz, hipStream_t s);
+// Fine positions first..first+n-1: (q + s(q)) L plus the coarse residuals
+// interpolated over the containing coarse tetrahedron.
+hipError_t launch_place_hybrid(const float *cx, const float *cy, const float *cz, const float *rx,
+                               const float *ry, const float *rz, const int cdims[3], int r, int64_t first,
+                               int64_t n, const float *q, const float *pred, const double box[3], float *fx,
+                               float *fy, float *fz, hipStream_t s);
 hipError_t launch_place_linear(const float *cx, const float *cy, const float *cz, const int cdims[3], int r,
                                const double box[3], float *fx, float *fy, float *fz, hipStream_t s);
 }  // namespace mlp

@@ -449,15 +449,54 @@ hipError_t launch_place_mlp(const float *cx, const float *cy, const float *cz, c
     return hipGetLastError();
 }
 
+// The tetrahedron of the unit cube's six-tetrahedron table (corner n = a +
+// 2b + 4c at offset (a, b, c)) that contains point p, and p's barycentric
+// coordinates in it (Cramer's rule); -1 if none does (not reached for points
+// of the unit cube, which the six tetrahedra tile).
+__device__ inline int unit_cube_tet(const double p[3], double lam[4]) {
+    constexpr int tet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
+    for (int t = 0; t < 6; ++t) {
+        double R[4][3];
+        for (int m = 0; m < 4; ++m) {
+            const int c = tet[t][m];
+            R[m][0] = c & 1; R[m][1] = (c >> 1) & 1; R[m][2] = (c >> 2) & 1;
+        }
+        double M[3][3], rhs[3];
+        for (int a = 0; a < 3; ++a) {
+            for (int m = 0; m < 3; ++m) M[a][m] = R[m + 1][a] - R[0][a];
+            rhs[a] = p[a] - R[0][a];
+        }
+        const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                           M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                           M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+        for (int m = 0; m < 3; ++m) {
+            double T[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) T[a][b] = (b == m) ? rhs[a] : M[a][b];
+            lam[m + 1] = (T[0][0] * (T[1][1] * T[2][2] - T[1][2] * T[2][1]) -
+                          T[0][1] * (T[1][0] * T[2][2] - T[1][2] * T[2][0]) +
+                          T[0][2] * (T[1][0] * T[2][1] - T[1][1] * T[2][0])) / det;
+        }
+        lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+        if (lam[0] < -1e-12 || lam[1] < -1e-12 || lam[2] < -1e-12 || lam[3] < -1e-12) continue;
+        return t;
+    }
+    return -1;
+}
+
+__device__ inline int cube_corner(int t, int m) {
+    constexpr int tet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
+    return tet[t][m];
+}
+
 // Fine positions by the affine map of the coarse tetrahedron that contains
-// the vertex's Lagrangian point (the six-tetrahedron table of a unit cube).
+// the vertex's Lagrangian point.
 __global__ void k_place_linear(const float *__restrict__ cx, const float *__restrict__ cy,
                                const float *__restrict__ cz, int d0, int d1, int d2, int r,
                                double L0, double L1, double L2, int64_t nfine,
                                float *__restrict__ fx, float *__restrict__ fy, float *__restrict__ fz) {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nfine) return;
-    constexpr int tet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
     const int f0 = d0 * r, f1 = d1 * r;
     const int I = (int)(id % f0), J = (int)((id / f0) % f1), K = (int)(id / ((int64_t)f0 * f1));
     const int i = I / r, j = J / r, k = K / r;
@@ -482,45 +521,17 @@ __global__ void k_place_linear(const float *__restrict__ cx, const float *__rest
             }
         }
     }
-    for (int t = 0; t < 6; ++t) {
-        // barycentric coordinates of p in reference tetrahedron t (Cramer)
-        double R[4][3];
-        for (int m = 0; m < 4; ++m) {
-            const int c = tet[t][m];
-            R[m][0] = c & 1; R[m][1] = (c >> 1) & 1; R[m][2] = (c >> 2) & 1;
-        }
-        double M[3][3], rhs[3];
-        for (int a = 0; a < 3; ++a) {
-            for (int m = 0; m < 3; ++m) M[a][m] = R[m + 1][a] - R[0][a];
-            rhs[a] = p[a] - R[0][a];
-        }
-        const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
-                           M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-                           M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-        double lam[4];
-        for (int m = 0; m < 3; ++m) {
-            double T[3][3];
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) T[a][b] = (b == m) ? rhs[a] : M[a][b];
-            lam[m + 1] = (T[0][0] * (T[1][1] * T[2][2] - T[1][2] * T[2][1]) -
-                          T[0][1] * (T[1][0] * T[2][2] - T[1][2] * T[2][0]) +
-                          T[0][2] * (T[1][0] * T[2][1] - T[1][1] * T[2][0])) / det;
-        }
-        lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
-        if (lam[0] < -1e-12 || lam[1] < -1e-12 || lam[2] < -1e-12 || lam[3] < -1e-12) continue;
-        double out[3] = {0, 0, 0};
+    double lam[4];
+    const int t = unit_cube_tet(p, lam);
+    double out[3] = {X[0][0], X[0][1], X[0][2]};
+    if (t >= 0) {
+        out[0] = out[1] = out[2] = 0.0;
         for (int m = 0; m < 4; ++m)
-            for (int a = 0; a < 3; ++a) out[a] += lam[m] * X[tet[t][m]][a];
-        fx[id] = wrap_f32(out[0], L0);
-        fy[id] = wrap_f32(out[1], L1);
-        fz[id] = wrap_f32(out[2], L2);
-        return;
+            for (int a = 0; a < 3; ++a) out[a] += lam[m] * X[cube_corner(t, m)][a];
     }
-    // not reached for points of the unit cube (the six tetrahedra tile it);
-    // keep the output defined anyway
-    fx[id] = wrap_f32(X[0][0], L0);
-    fy[id] = wrap_f32(X[0][1], L1);
-    fz[id] = wrap_f32(X[0][2], L2);
+    fx[id] = wrap_f32(out[0], L0);
+    fy[id] = wrap_f32(out[1], L1);
+    fz[id] = wrap_f32(out[2], L2);
 }
 
 hipError_t launch_place_linear(const float *cx, const float *cy, const float *cz, const int cdims[3], int r,
@@ -528,6 +539,85 @@ hipError_t launch_place_linear(const float *cx, const float *cy, const float *cz
     const int64_t nfine = (int64_t)cdims[0] * cdims[1] * cdims[2] * r * r * r;
     hipLaunchKernelGGL(k_place_linear, dim3((unsigned)((nfine + 255) / 256)), dim3(256), 0, s, cx, cy, cz,
                        cdims[0], cdims[1], cdims[2], r, box[0], box[1], box[2], nfine, fx, fy, fz);
+    return hipGetLastError();
+}
+
+// Residual of the network at coarse tracers first .. first+n-1 (q and pred
+// of those tracers): x - (q + s(q)) L, as the periodic image in (-L/2, L/2].
+__global__ void k_coarse_residual(const float *__restrict__ cx, const float *__restrict__ cy,
+                                  const float *__restrict__ cz, int64_t first, int64_t n,
+                                  const float *__restrict__ q, const float *__restrict__ pred, double L0,
+                                  double L1, double L2, float *__restrict__ rx, float *__restrict__ ry,
+                                  float *__restrict__ rz) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t id = first + j;
+    const double x[3] = {(double)cx[id], (double)cy[id], (double)cz[id]};
+    const double L[3] = {L0, L1, L2};
+    float *out[3] = {rx, ry, rz};
+    for (int a = 0; a < 3; ++a) {
+        double d = x[a] - ((double)q[3 * j + a] + (double)pred[3 * j + a]) * L[a];
+        d -= L[a] * ceil(d / L[a] - 0.5);
+        out[a][id] = (float)d;
+    }
+}
+
+hipError_t launch_coarse_residual(const float *cx, const float *cy, const float *cz, int64_t first, int64_t n,
+                                  const float *q, const float *pred, const double box[3], float *rx, float *ry,
+                                  float *rz, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cx, cy, cz, first,
+                       n, q, pred, box[0], box[1], box[2], rx, ry, rz);
+    return hipGetLastError();
+}
+
+// Fine positions: network prediction plus the coarse residuals interpolated
+// over the coarse tetrahedron that contains the vertex's Lagrangian point;
+// coarse vertices keep their data exactly.
+__global__ void k_place_hybrid(const float *__restrict__ cx, const float *__restrict__ cy,
+                               const float *__restrict__ cz, const float *__restrict__ rx,
+                               const float *__restrict__ ry, const float *__restrict__ rz, int d0, int d1,
+                               int d2, int r, int64_t first, int64_t n, const float *__restrict__ q,
+                               const float *__restrict__ pred, double L0, double L1, double L2,
+                               float *__restrict__ fx, float *__restrict__ fy, float *__restrict__ fz) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t id = first + j;
+    const int f0 = d0 * r, f1 = d1 * r;
+    const int I = (int)(id % f0), J = (int)((id / f0) % f1), K = (int)(id / ((int64_t)f0 * f1));
+    const int i = I / r, jj0 = J / r, k = K / r;
+    if (I % r == 0 && J % r == 0 && K % r == 0) {
+        const int64_t c = (int64_t)i + (int64_t)d0 * (jj0 + (int64_t)d1 * k);
+        fx[id] = cx[c];
+        fy[id] = cy[c];
+        fz[id] = cz[c];
+        return;
+    }
+    const double p[3] = {(double)(I % r) / r, (double)(J % r) / r, (double)(K % r) / r};
+    double lam[4];
+    const int t = unit_cube_tet(p, lam);
+    double res[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < 4 && t >= 0; ++m) {
+        const int c = cube_corner(t, m);
+        int ii = i + (c & 1), jj = jj0 + ((c >> 1) & 1), kk = k + ((c >> 2) & 1);
+        if (ii == d0) ii = 0;
+        if (jj == d1) jj = 0;
+        if (kk == d2) kk = 0;
+        const int64_t cid = ii + (int64_t)d0 * (jj + (int64_t)d1 * kk);
+        res[0] += lam[m] * (double)rx[cid];
+        res[1] += lam[m] * (double)ry[cid];
+        res[2] += lam[m] * (double)rz[cid];
+    }
+    fx[id] = wrap_f32(((double)q[3 * j] + (double)pred[3 * j]) * L0 + res[0], L0);
+    fy[id] = wrap_f32(((double)q[3 * j + 1] + (double)pred[3 * j + 1]) * L1 + res[1], L1);
+    fz[id] = wrap_f32(((double)q[3 * j + 2] + (double)pred[3 * j + 2]) * L2 + res[2], L2);
+}
+
+hipError_t launch_place_hybrid(const float *cx, const float *cy, const float *cz, const float *rx,
+                               const float *ry, const float *rz, const int cdims[3], int r, int64_t first,
+                               int64_t n, const float *q, const float *pred, const double box[3], float *fx,
+                               float *fy, float *fz, hipStream_t s) {
+    hipLaunchKernelGGL(k_place_hybrid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cx, cy, cz, rx, ry, rz,
+                       cdims[0], cdims[1], cdims[2], r, first, n, q, pred, box[0], box[1], box[2], fx, fy, fz);
     return hipGetLastError();
 }
 

@@ -144,9 +144,9 @@ extern "C" tess_status tess_refine_desc_default(tess_refine_desc *d) {
     d->r = 4;
     d->mode = TESS_REFINE_MLP;
     d->rff_sigma = 8.0;
-    d->steps = 3000;
+    d->steps = 10000;
     d->batch = 8192;
-    d->lr0 = 1e-3;
+    d->lr0 = 1e-2;
     d->lr1 = 1e-5;
     d->seed = 2;
     return ok();
@@ -188,8 +188,8 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
     *fine = nullptr;
     if (!coarse->desc.periodic) return fail(TESS_ENOTSUP, "refinement needs a periodic lattice");
     if (d->r < 1 || d->r > 16) return fail(TESS_EINVAL, "r = %d outside 1..16", d->r);
-    if (d->mode != TESS_REFINE_LINEAR && d->mode != TESS_REFINE_MLP)
-        return fail(TESS_EINVAL, "mode must be TESS_REFINE_LINEAR or TESS_REFINE_MLP");
+    if (d->mode != TESS_REFINE_LINEAR && d->mode != TESS_REFINE_MLP && d->mode != TESS_REFINE_MLP_RAW)
+        return fail(TESS_EINVAL, "mode must be TESS_REFINE_LINEAR, TESS_REFINE_MLP or TESS_REFINE_MLP_RAW");
     int cd[3], fd[3];
     int64_t nfine = 1;
     for (int a = 0; a < 3; ++a) {
@@ -198,7 +198,7 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
         nfine *= fd[a];
     }
     if (nfine * 6 > ((int64_t)1 << 32) - 1) return fail(TESS_ECAPACITY, "fine lattice too large");
-    if (d->mode == TESS_REFINE_MLP) {
+    if (d->mode != TESS_REFINE_LINEAR) {
         if (d->steps < 0 || (d->steps == 0 && !d->weights_in))
             return fail(TESS_EINVAL, "steps must be > 0, or 0 with weights_in");
         if (d->batch < 64 || d->batch > (1 << 22)) return fail(TESS_EINVAL, "batch outside 64..2^22");
@@ -284,15 +284,44 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
             TESS_HIP(hipMemcpy(d->weights_out, net.master.p, sizeof(float) * kParams, hipMemcpyDeviceToHost));
         // ------------------------------------------------------ inference
         t0 = std::chrono::steady_clock::now();
+        float *res = nullptr;  // residuals at the coarse tracers (x, y, z arrays)
+        const int64_t ncoarse = (int64_t)cd[0] * cd[1] * cd[2];
+        if (d->mode == TESS_REFINE_MLP) {
+            TESS_HIP(hipMalloc((void **)&res, sizeof(float) * 3 * (size_t)ncoarse));
+            for (int64_t first = 0; first < ncoarse; first += cap) {
+                const int64_t n = std::min<int64_t>(cap, ncoarse - first);
+                TESS_HIP(launch_fine_q(first, n, cd, net.q.p, s));
+                st = net_forward(net, n, false, s);
+                if (st == TESS_OK &&
+                    launch_coarse_residual(coarse->x, coarse->y, coarse->z, first, n, net.q.p, net.pred.p, box,
+                                           res, res + ncoarse, res + 2 * ncoarse, s) != hipSuccess)
+                    st = fail(TESS_EHIP, "coarse residual failed");
+                if (st != TESS_OK) {
+                    (void)hipFree(res);
+                    return fail_free(st);
+                }
+            }
+        }
         for (int64_t first = 0; first < nfine; first += cap) {
             const int64_t n = std::min<int64_t>(cap, nfine - first);
             TESS_HIP(launch_fine_q(first, n, fd, net.q.p, s));
             st = net_forward(net, n, false, s);
-            if (st != TESS_OK) return fail_free(st);
-            TESS_HIP(launch_place_mlp(coarse->x, coarse->y, coarse->z, cd, d->r, first, n, net.q.p, net.pred.p,
-                                      box, fd, fx, fy, fz, s));
+            hipError_t e = hipSuccess;
+            if (st == TESS_OK) {
+                if (res)
+                    e = launch_place_hybrid(coarse->x, coarse->y, coarse->z, res, res + ncoarse, res + 2 * ncoarse,
+                                            cd, d->r, first, n, net.q.p, net.pred.p, box, fx, fy, fz, s);
+                else
+                    e = launch_place_mlp(coarse->x, coarse->y, coarse->z, cd, d->r, first, n, net.q.p,
+                                         net.pred.p, box, fd, fx, fy, fz, s);
+            }
+            if (st != TESS_OK || e != hipSuccess) {
+                if (res) (void)hipFree(res);
+                return fail_free(st != TESS_OK ? st : fail(TESS_EHIP, "placement failed"));
+            }
         }
         TESS_HIP(hipStreamSynchronize(s));
+        if (res) (void)hipFree(res);
         rep.infer_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     {  // every placed position finite (a diverged network is reported, not rendered)

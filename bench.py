@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-crop", type=int, default=48,
+    ap.add_argument("--cpu-crop", type=int, default=24,
                     help="edge (pixels) of the centred crop the oracle renders for the CPU baseline")
     return ap.parse_args()
 

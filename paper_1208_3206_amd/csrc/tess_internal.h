@@ -76,7 +76,8 @@ struct WorkItem {
 //  - crease form (REC_CREASE; no walls): the silhouette vertices V_0..V_m-1
 //    in cyclic order (x in c[0..3], y in c[4..7]), the apex (c[8], c[9]) and
 //    the x slope b of the face over edge (V_k, V_k+1) in c[10 + k];
-//  - line form: (a, b, c) of the G functions, then of the walls, in c[0..11].
+//  - line form: (a, b, c) of the G functions, then of the walls, in c[0..11];
+// the payload's last 16 bytes repeat the head.
 struct RecHead {
     uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
     uint32_t by;                 // y0 | y1 << 16
@@ -97,7 +98,8 @@ constexpr uint32_t REC_VALID = 1u << 7;       // some pixel centre may be covere
 constexpr uint32_t REC_CREASE = 1u << 8;      // payload in crease form
 
 struct alignas(128) Payload {
-    double c[16];
+    double c[14];
+    RecHead h;  // copy of the record's head: the raster reads one 128-byte line per record
 };
 static_assert(sizeof(RecHead) == 16, "record head");
 static_assert(sizeof(Payload) == 128, "one 128-byte line per record");

@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     for (uint32_t e = e0; e < e1; ++e) {
         const uint32_t id = pairs[it.first + e];
         if (id >= B.ntet) continue;
-        const RecHead h = head[id];
+        const RecHead h = coef[id].h;
         if (!(h.flags & REC_VALID)) continue;
         frags += raster_record(h, coef[id].c, B, tx0, ty0, n, rows,
                                [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },

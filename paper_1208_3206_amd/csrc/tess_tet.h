@@ -150,7 +150,7 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
 // -|b_k-1 - b_k| at the ridge to V_k, with b the x slopes of the faces over
 // the silhouette edges.  Returns false if the edges do not close a cycle.
 TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const Footprint &fp,
-                                   double out[16]) {
+                                   double out[14]) {
     const int m = fp.ng;
     if (m != 3 && m != 4) return false;
     int V[4] = {fp.ei[0], fp.ej[0], 0, 0};
@@ -201,7 +201,6 @@ TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const
     }
     out[8] = ax;
     out[9] = ay;
-    out[14] = out[15] = 0.0;
     return true;
 }
 
@@ -268,7 +267,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         R.flags = 0;
         R.spare = 0;
 #pragma unroll
-        for (int g = 0; g < 16; ++g) coef[t].c[g] = 0.0;
+        for (int g = 0; g < 14; ++g) coef[t].c[g] = 0.0;
+        coef[t].h = R;
         // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
         // error bound, FP64 when the bound cannot certify it or it is small
         double a64[3], b64[3], c64[3];
@@ -341,6 +341,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 #pragma unroll
             for (int g = 0; g < 12; ++g) coef[t].c[g] = fp.c[g];
         }
+        coef[t].h = R;
     }
 }
 

@@ -94,6 +94,9 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime; load it first so that the library binds
+    # to the same one (two runtimes in one process do not share the device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p

@@ -47,6 +47,16 @@ TESS_HD inline int floor_div(int a, int b) {  // b > 0
 TESS_HD inline int ceil_div(int a, int b) {  // b > 0
     return -floor_div(-a, b);
 }
+// 1/s to within a few ulp: the hardware estimate refined by one Newton step
+// (the host build divides).
+TESS_HD inline double fast_rcp(double s) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const double r = __builtin_amdgcn_rcp(s);
+    return fma(fma(-s, r, 1.0), r, r);
+#else
+    return 1.0 / s;
+#endif
+}
 
 
 // Volume determinant (times 6) in FP64, evaluated term by term without
@@ -381,6 +391,11 @@ TESS_HD inline void axis_offsets(int t0, int t1, int b0, int b1, int n, int wrap
 
 // Columns a record writes: its pixel box plus two, since the last break point
 // of a row (the end of the footprint) writes the two entries after it.
+// Offset (pixels) that decides on which side of a crease a sample exactly on
+// it falls: far above the rounding of a crossing (about 1e-13 px over a
+// footprint). A crossing closer than this to a sample counts as on it, which
+// moves the fragment count only (the deposits use the exact crossing).
+constexpr double kSampleEps = 1e-10;
 constexpr int kRightReach = 2;
 
 // Candidate tiles of one record: tx = (sx + s % cx) mod ntx, ty = (sy + s / cx)
@@ -648,14 +663,15 @@ TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const Bi
 template <typename Dep>
 TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0,
                                     int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
-    const bool quad = (h.flags & REC_NG_MASK) == 4u;
+    const int m = (int)(h.flags & REC_NG_MASK);  // 3 or 4 silhouette vertices
     const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
     const int by0 = range_lo(h.by), by1 = range_hi(h.by);
     int kx0, kx1, ky0, ky1;
     axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
     axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
     const int jmin = -tx0;  // tile column of image column 0
-    const double ucl = -0.5, ucr = (double)n - 0.5;
+    const int jlo = jmin > -2 ? jmin : -2;  // lowest deposit column (padding at -2)
+    const bool left_edge = jmin > -2;  // kinks left of the tile fold into it
     int frags = 0;
     for (int ky = ky0; ky <= ky1; ++ky) {
         // record rows r (centre Y = r + 1/2) on tile rows r + rshift
@@ -665,60 +681,80 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
             const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            // record-frame x range whose kinks reach the tile (one pixel of margin)
+            const double xl = left_edge ? -1e30 : X0 - 3.0, xr = X0 + (double)n + 1.0;
             spans += (uint32_t)(rhi - rlo + 1);
+            // slots 0..m-1: silhouette edge (V_k, V_k+1); slots 4..4+m-1: ridge (apex, V_k);
+            // first the slots whose crease meets the tile's rows and columns
+            uint32_t mask = 0;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
-                // slots 0..3: silhouette edge (V_k, V_k+1); slots 4..7: ridge (apex, V_k)
                 const int k = c & 3;
-                if (k == 3 && !quad) continue;
-                double Px, Py, Qx, Qy, D;
-                bool enter = false;
-                if (c < 4) {
-                    Px = cf[k];
-                    Py = cf[4 + k];
-                    const bool wrapk = k == 3 || (k == 2 && !quad);
-                    Qx = wrapk ? cf[0] : cf[k + 1 < 4 ? k + 1 : 0];
-                    Qy = wrapk ? cf[4] : cf[k + 1 < 4 ? 5 + k : 4];
-                    const double b = cf[10 + k];
-                    D = fabs(b);
-                    enter = b > 0.0;
-                } else {
-                    Px = cf[8];
-                    Py = cf[9];
-                    Qx = cf[k];
-                    Qy = cf[4 + k];
-                    const double bprev = k > 0 ? cf[9 + k] : (quad ? cf[13] : cf[12]);
-                    D = -fabs(bprev - cf[10 + k]);
+                if (k >= m) continue;
+                const int k1 = k + 1 < m ? k + 1 : 0;
+                const double Px = c < 4 ? cf[k] : cf[8], Py = c < 4 ? cf[4 + k] : cf[9];
+                const double Qx = c < 4 ? cf[k1] : cf[k], Qy = c < 4 ? cf[4 + k1] : cf[4 + k];
+                const int r0 = max((int)ceil(fmin(Py, Qy) - 0.5), rlo);
+                const int r1 = min((int)ceil(fmax(Py, Qy) - 0.5) - 1, rhi);
+                if (r0 > r1 || fmax(Px, Qx) < xl) continue;
+                if (fmin(Px, Qx) < xr) {
+                    mask |= 1u << c;
+                } else if (c < 4) {
+                    // wholly right of the tile: every row counts the full width
+                    frags += (cf[10 + k] > 0.0 ? -n : n) * (r1 - r0 + 1);
                 }
-                const double ylo = fmin(Py, Qy), yhi = fmax(Py, Qy);
-                const int r0 = max((int)ceil(ylo - 0.5), rlo);
-                const int r1 = min((int)ceil(yhi - 0.5) - 1, rhi);
-                if (r0 > r1) continue;
-                const double sl = (Qx - Px) / (Qy - Py);
-                // the crossing in the record frame (small numbers: a sliver's
+            }
+            while (mask) {
+                const int c = __builtin_ctz(mask);
+                mask &= mask - 1u;
+                const int k = c & 3;
+                const int k1 = k + 1 < m ? k + 1 : 0;
+                const bool edge = c < 4;
+                const double Px = edge ? cf[k] : cf[8], Py = edge ? cf[4 + k] : cf[9];
+                const double Qx = edge ? cf[k1] : cf[k], Qy = edge ? cf[4 + k1] : cf[4 + k];
+                const double bk = cf[10 + k];
+                const double D = edge ? fabs(bk) : -fabs(cf[10 + (k > 0 ? k - 1 : m - 1)] - bk);
+                const bool enter = bk > 0.0;
+                const int q0 = max((int)ceil(fmin(Py, Qy) - 0.5), rlo);
+                const int q1 = min((int)ceil(fmax(Py, Qy) - 0.5) - 1, rhi);
+                const double sl = (Qx - Px) * fast_rcp(Qy - Py);
+                int r0 = q0, r1 = q1;
+                int acc = 0;  // fragment terms of this crease, before its sign
+                if (Qx != Px) {
+                    // keep the rows whose crossing lies in [xl, xr) (x is linear in
+                    // Y, and the margins of xl and xr absorb the rounding of the
+                    // reciprocal); rows cut below ya lie on the side of the bound
+                    // ya comes from, rows cut above yb on the other
+                    const double iv = (Qy - Py) * fast_rcp(Qx - Px);
+                    double ya = Py + (xl - Px) * iv, yb = Py + (xr - Px) * iv;
+                    if (ya > yb) { const double t = ya; ya = yb; yb = t; }
+                    ya = fmin(fmax(ya, (double)q0 - 1.0), (double)q1 + 2.0);
+                    yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 2.0);
+                    r0 = max(q0, (int)floor(ya - 0.5));
+                    r1 = min(q1, (int)ceil(yb - 0.5));
+                    // rows right of the tile count its full width
+                    acc = n * (sl > 0.0 ? q1 - r1 : r0 - q0);
+                }
+                // the crossing in the record frame (small numbers: a footprint's
                 // kinks keep their relative positions to FP64 rounding of its box)
                 double x = Px + ((double)r0 + 0.5 - Py) * sl;
+                // Fragments: an entering crossing has floor(u) + 1 samples left
+                // of it, a leaving one ceil(u) (a sample on the silhouette is
+                // outside). The column j is taken in a frame shifted by
+                // kSampleEps, down for an entering crease and up for a leaving
+                // one, so that j = floor(u) + 1 or ceil(u) and the count is
+                // max(j, 0) (jlo <= 0). Any j next to the kink gives the same
+                // sum, since the deposits use the exact offset from column j.
+                const double Xj = X0 + (enter ? -kSampleEps : kSampleEps);
                 for (int r = r0; r <= r1; ++r, x += sl) {
                     const int row = r + rshift;
-                    const double u = x - X0;
-                    const double fl = floor(u);
-                    const int fi = (int)fl;
-                    int j = fi + 1;
-                    j = j > jmin ? j : jmin;
-                    j = j < -2 ? -2 : (j > n ? n : j);
+                    const int j = min(max((int)floor(x - Xj) + 1, jlo), n);
                     const double v1 = D * (((double)j + X0) - x);
                     dep(row, j, v1);
                     dep(row, j + 1, D - v1);
-                    if (c < 4) {
-                        // fragments, with u clamped to the tile's samples: an
-                        // entering crossing counts -(floor(u) + 1), a leaving
-                        // one ceil(u)
-                        const int ce = fi + (fl < u ? 1 : 0);
-                        const int te = -min(max(fi, -1), n - 1) - 1;
-                        const int tl = min(max(ce, 0), n);
-                        frags += enter ? te : tl;
-                    }
+                    acc += max(j, 0);
                 }
+                if (edge) frags += enter ? -acc : acc;
             }
         }
     }

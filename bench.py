@@ -30,6 +30,15 @@ OPS_PER_SPAN = 4 + 6 + 12 + 12 + 28
 # Its LDS traffic: two FP64 read-modify-writes per break point.
 LDS_BYTES_PER_SPAN = 3.5 * 2 * 16
 PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
+# k_raster's HBM bytes at stress 2048^2 from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (KiB per dispatch), scaled by what the same counters read for a 1 GiB
+# device copy (--copy-probe); valid only for the sources they were taken on.
+TRAFFIC = {
+    "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
+                "paper_1208_3206_amd/csrc/tess_internal.h"],
+    "sha256": "",
+    "fetch_kib": 0.0, "write_kib": 0.0, "fetch_scale": 2.0, "write_scale": 1.0,
+}
 
 
 def parse():
@@ -44,6 +53,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device twice (scale reference for HBM byte counters)")
     ap.add_argument("--cpu-crop", type=int, default=24,
                     help="edge (pixels) of the centred crop the oracle renders for the CPU baseline")
     return ap.parse_args()
@@ -238,9 +249,38 @@ def run_learned(args, w, tess, W, torch):
     print(json.dumps(result), flush=True)
 
 
+def copy_probe(torch):
+    """A plain device copy of known size: what FETCH_SIZE / WRITE_SIZE read
+    for it scales the raster's counters to bytes."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 2}), flush=True)
+
+
+def raster_traffic():
+    """HBM bytes per raster launch from the committed counter passes, or None
+    when the raster's sources changed since they were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return TRAFFIC["fetch_kib"] * 1024 * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * 1024 * TRAFFIC["write_scale"]
+
+
 def main():
     global args
     args = parse()
+    if args.copy_probe:
+        import torch
+        copy_probe(torch)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(this build shows one GPU's share of the work)", file=sys.stderr)
@@ -326,7 +366,7 @@ def main():
             "peak": PEAK_VALU_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved / PEAK_VALU_OPS,
-            "traffic": None,
+            "traffic": raster_traffic(),
             "ops_per_launch": ops,
             "ops_per_span": OPS_PER_SPAN,
         },

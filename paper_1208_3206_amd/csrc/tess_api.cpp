@@ -318,12 +318,13 @@ struct Plan {
     int Th, Tw, chunk, block;  // chunk 0: from the pair count
 };
 
-// Default tiling: tiles of up to 1024 columns with as many rows as the
-// 128 KiB accumulator allows (at most 64); at 2048^2 16 x 1024 measured
-// fastest among 8 x 2048, 16 x 1024, 32 x 512 and 64 x 256.
+// Default tiling: tiles of up to 512 columns with as many rows as the
+// 128 KiB accumulator allows (at most 64). Taller tiles mean fewer (record,
+// tile) pairs, narrower ones fewer columns per pair; at 2048^2, 32 x 512
+// measured fastest among 8 x 1024, 16 x 1024, 32 x 512, 32 x 256 and 64 x 256.
 Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     Plan p;
-    int Tw = (tune && tune->tile_cols) ? tune->tile_cols : std::min(v->width, 1024);
+    int Tw = (tune && tune->tile_cols) ? tune->tile_cols : std::min(v->width, 512);
     int Th = 1;
     while (Th < 64 && 2 * Th * Tw <= kMaxTileCells) Th *= 2;
     if (tune && tune->tile_rows) Th = tune->tile_rows;

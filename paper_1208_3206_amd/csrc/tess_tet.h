@@ -391,6 +391,19 @@ TESS_HD inline void axis_offsets(int t0, int t1, int b0, int b1, int n, int wrap
 
 // Columns a record writes: its pixel box plus two, since the last break point
 // of a row (the end of the footprint) writes the two entries after it.
+// Sorts eight keys into descending order (a 19-comparator network of depth 6).
+TESS_HD inline void sort8_desc(uint32_t a[8]) {
+    constexpr int kNet[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6},
+                                 {3, 7}, {0, 1}, {2, 3}, {4, 5}, {6, 7}, {2, 4}, {3, 5},
+                                 {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const uint32_t x = a[kNet[i][0]], y = a[kNet[i][1]];
+        a[kNet[i][0]] = x > y ? x : y;
+        a[kNet[i][1]] = x > y ? y : x;
+    }
+}
+
 // Offset (pixels) that decides on which side of a crease a sample exactly on
 // it falls: far above the rounding of a crossing (about 1e-13 px over a
 // footprint). A crossing closer than this to a sample counts as on it, which
@@ -686,9 +699,11 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
             spans += (uint32_t)(rhi - rlo + 1);
             // slots 0..m-1: silhouette edge (V_k, V_k+1); slots 4..4+m-1: ridge (apex, V_k);
             // first the slots whose crease meets the tile's rows and columns
-            uint32_t mask = 0;
+            // key of an active slot: its row count in the tile, then the slot
+            uint32_t key[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
+                key[c] = 0u;
                 const int k = c & 3;
                 if (k >= m) continue;
                 const int k1 = k + 1 < m ? k + 1 : 0;
@@ -698,15 +713,26 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
                 const int r1 = min((int)ceil(fmax(Py, Qy) - 0.5) - 1, rhi);
                 if (r0 > r1 || fmax(Px, Qx) < xl) continue;
                 if (fmin(Px, Qx) < xr) {
-                    mask |= 1u << c;
+                    key[c] = ((uint32_t)(r1 - r0 + 1) << 3) | (uint32_t)c;
                 } else if (c < 4) {
                     // wholly right of the tile: every row counts the full width
                     frags += (cf[10 + k] > 0.0 ? -n : n) * (r1 - r0 + 1);
                 }
             }
-            while (mask) {
-                const int c = __builtin_ctz(mask);
-                mask &= mask - 1u;
+            // Longest crease first: the lanes of a wavefront step through their
+            // creases together, and each step lasts as long as its longest row
+            // loop, so lining up long with long and short with short shortens
+            // the sum of the steps.
+            sort8_desc(key);
+            uint32_t order = 0;
+            int nact = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                order |= (key[i] & 7u) << (4 * i);
+                nact += key[i] != 0u ? 1 : 0;
+            }
+            for (int i = 0; i < nact; ++i) {
+                const int c = (int)((order >> (4 * i)) & 7u);
                 const int k = c & 3;
                 const int k1 = k + 1 < m ? k + 1 : 0;
                 const bool edge = c < 4;

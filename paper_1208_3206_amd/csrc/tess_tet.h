@@ -699,7 +699,8 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
             spans += (uint32_t)(rhi - rlo + 1);
             // slots 0..m-1: silhouette edge (V_k, V_k+1); slots 4..4+m-1: ridge (apex, V_k);
             // first the slots whose crease meets the tile's rows and columns
-            // key of an active slot: its row count in the tile, then the slot
+            // key of an active slot: its row count in the tile, its first and
+            // last row (offsets from rlo, below 256) and the slot
             uint32_t key[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
@@ -713,7 +714,8 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
                 const int r1 = min((int)ceil(fmax(Py, Qy) - 0.5) - 1, rhi);
                 if (r0 > r1 || fmax(Px, Qx) < xl) continue;
                 if (fmin(Px, Qx) < xr) {
-                    key[c] = ((uint32_t)(r1 - r0 + 1) << 3) | (uint32_t)c;
+                    key[c] = ((uint32_t)(r1 - r0 + 1) << 20) | ((uint32_t)(r0 - rlo) << 12) |
+                             ((uint32_t)(r1 - rlo) << 4) | (uint32_t)c;
                 } else if (c < 4) {
                     // wholly right of the tile: every row counts the full width
                     frags += (cf[10 + k] > 0.0 ? -n : n) * (r1 - r0 + 1);
@@ -724,15 +726,16 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
             // loop, so lining up long with long and short with short shortens
             // the sum of the steps.
             sort8_desc(key);
-            uint32_t order = 0;
             int nact = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                order |= (key[i] & 7u) << (4 * i);
-                nact += key[i] != 0u ? 1 : 0;
-            }
+            for (int i = 0; i < 8; ++i) nact += key[i] != 0u ? 1 : 0;
             for (int i = 0; i < nact; ++i) {
-                const int c = (int)((order >> (4 * i)) & 7u);
+                // take the head of the sorted queue
+                const uint32_t kc = key[0];
+#pragma unroll
+                for (int j = 0; j < 7; ++j) key[j] = key[j + 1];
+                const int c = (int)(kc & 7u);
+                const int q0 = rlo + (int)((kc >> 12) & 255u), q1 = rlo + (int)((kc >> 4) & 255u);
                 const int k = c & 3;
                 const int k1 = k + 1 < m ? k + 1 : 0;
                 const bool edge = c < 4;
@@ -741,8 +744,6 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
                 const double bk = cf[10 + k];
                 const double D = edge ? fabs(bk) : -fabs(cf[10 + (k > 0 ? k - 1 : m - 1)] - bk);
                 const bool enter = bk > 0.0;
-                const int q0 = max((int)ceil(fmin(Py, Qy) - 0.5), rlo);
-                const int q1 = min((int)ceil(fmax(Py, Qy) - 0.5) - 1, rhi);
                 const double sl = (Qx - Px) * fast_rcp(Qy - Py);
                 int r0 = q0, r1 = q1;
                 int acc = 0;  // fragment terms of this crease, before its sign

@@ -52,6 +52,18 @@ def test_zeldovich_wrap_matches_oracle_any_tiling(rows, cols, chunk):
     assert st["fragments"] == ost["fragments"]
 
 
+def test_tallest_tiles_match_oracle():
+    # 256-row tiles (the largest the library accepts): row offsets of up to 255
+    # inside a tile, footprints taller than the lattice spacing wrapping in y
+    n = 16
+    xyz = W.zeldovich(n, 5, 6.0, seed=7)
+    view = W.z_view(64, 300)
+    img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=256, tile_cols=64, chunk=4096)
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert rel(img, ref) < 1e-8
+    assert st["fragments"] == ost["fragments"]
+
+
 @pytest.mark.parametrize("rows,cols", [(8, 50), (5, 16), (2, 17)])
 def test_rotated_view_without_wrap_matches_oracle(rows, cols):
     n = 8

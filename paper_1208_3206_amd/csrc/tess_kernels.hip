@@ -361,6 +361,7 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
 // the tile is added to the image-sized array `acc` (FP64 atomics in L2; a
 // tile has several items).
 constexpr int kPad = 2;
+constexpr int kIdBurst = 8;  // pair ids a lane loads at once
 
 template <int TPB>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
@@ -388,14 +389,25 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     // the tile instead of stacking their atomics on the same LDS cells
     const uint32_t per = (it.count + TPB - 1) / TPB;
     const uint32_t e0 = threadIdx.x * per, e1 = min(it.count, e0 + per);
-    for (uint32_t e = e0; e < e1; ++e) {
-        const uint32_t id = pairs[it.first + e];
-        if (id >= B.ntet) continue;
-        const RecHead h = coef[id].h;
-        if (!(h.flags & REC_VALID)) continue;
-        frags += raster_record(h, coef[id].c, B, tx0, ty0, n, rows,
-                               [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
-                               spans);
+    for (uint32_t e = e0; e < e1; e += kIdBurst) {
+        // the next ids of the slice in one burst: one fetch of their cache
+        // line serves kIdBurst pairs (read one at a time, microseconds
+        // apart, the line is gone from L2 before its next use)
+        uint32_t ids[kIdBurst];
+#pragma unroll
+        for (int i = 0; i < kIdBurst; ++i) ids[i] = e + i < e1 ? pairs[it.first + e + i] : 0xffffffffu;
+        const int cnt = (int)min((uint32_t)kIdBurst, e1 - e);
+        for (int i = 0; i < cnt; ++i) {
+            const uint32_t id = ids[0];
+#pragma unroll
+            for (int j = 0; j + 1 < kIdBurst; ++j) ids[j] = ids[j + 1];
+            if (id >= B.ntet) continue;
+            const RecHead h = coef[id].h;
+            if (!(h.flags & REC_VALID)) continue;
+            frags += raster_record(h, coef[id].c, B, tx0, ty0, n, rows,
+                                   [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                                   spans);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < rows * B.Tw; i += TPB) {

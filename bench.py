@@ -18,17 +18,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  The raster's FP64 FMA,
-# add, multiply, min and max issue at one lane-operation per lane per clock
-# (the same rate as unpacked FP32), so that is the ceiling of its arithmetic.
+# add, multiply, min, max and floor issue at one lane-operation per lane per
+# clock (the rate of unpacked FP32), so that is the ceiling of its arithmetic.
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9          # 3.93e13 lane-ops/s
-# Algorithmic FP64 operations of one span (one tetrahedron on one pixel row
-# of one tile): 4 line offsets (FMA), 4 zero crossings + 2 clamps, 6 pair
-# crossings (subtract, multiply), 12 min/max for the pieces' ends, and per
-# break point (3.5 on average: the pieces holding a sample, plus the end)
-# step, slope change, floor, fraction and the two entries (8).
-OPS_PER_SPAN = 4 + 6 + 12 + 12 + 28
-# Its LDS traffic: two FP64 read-modify-writes per break point.
-LDS_BYTES_PER_SPAN = 3.5 * 2 * 16
+# The raster's unit of work is a kink: one crease crossing one pixel row of a
+# tile (tess_stats.kinks).  Its algorithmic FP64 arithmetic: step the crossing
+# along the crease, floor it, the fraction phi from the crossing (2), and the
+# two second-difference entries D*phi and D - D*phi (2).
+OPS_PER_KINK = 6
+# Its LDS traffic: two FP64 read-modify-writes.
+LDS_BYTES_PER_KINK = 2 * 16
 PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
 # k_raster's HBM bytes at stress 2048^2 from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (KiB per dispatch), scaled by what the same counters read for a 1 GiB
@@ -120,8 +119,8 @@ def run_batched(args, w, tess, W, torch):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t_start) * 1e3 / args.steps
     n_img = len(lats) * len(views)
-    spans = st0["spans"]
-    achieved = OPS_PER_SPAN * spans / (dev_ms * 1e-3)
+    kinks = st0["kinks"]
+    achieved = OPS_PER_KINK * kinks / (dev_ms * 1e-3)
     result = {
         "metric": "tets/s over all images of a batch",
         "value": w.tets * n_img / (ms * 1e-3),
@@ -141,13 +140,14 @@ def run_batched(args, w, tess, W, torch):
         "images_per_s": n_img / (ms * 1e-3),
         "fragments": st0["fragments"],
         "fragments_per_s": st0["fragments"] / (ms * 1e-3),
-        "spans": spans,
+        "spans": st0["spans"],
+        "kinks": kinks,
         "bin_pairs": st0["bin_pairs"],
         "graph_ms": dev_ms,
         "first_call_s": first_s,
         "roofline": {"kernel": "whole batch graph", "bound": "alu", "achieved": achieved / 1e12,
                      "peak": PEAK_VALU_OPS / 1e12, "unit": "Tops/s", "frac": achieved / PEAK_VALU_OPS,
-                     "traffic": None, "ops_per_launch": OPS_PER_SPAN * spans, "ops_per_span": OPS_PER_SPAN},
+                     "traffic": None, "ops_per_launch": OPS_PER_KINK * kinks, "ops_per_kink": OPS_PER_KINK},
     }
     print(json.dumps(result), flush=True)
 
@@ -310,7 +310,7 @@ def main():
 
     tune = tess.make_tune(args.tile_rows, args.tile_cols, args.chunk, args.block)
     _, st0 = tess.project(lat, view, out=out, tune=tune, stats=True)
-    frags, spans = st0["fragments"], st0["spans"]
+    frags, spans, kinks = st0["fragments"], st0["spans"], st0["kinks"]
     for _ in range(args.warmup):
         tess.project(lat, view, out=out, tune=tune)
     torch.cuda.synchronize()
@@ -329,7 +329,7 @@ def main():
     img = out.double()
     checksum = float(img.mean().item())
 
-    ops = OPS_PER_SPAN * spans
+    ops = OPS_PER_KINK * kinks
     raster_s = kernel["raster_ms"] * 1e-3
     achieved = ops / raster_s
     result = {
@@ -352,13 +352,14 @@ def main():
         "fragments": frags,
         "fragments_per_s": frags / (ms * 1e-3),
         "spans": spans,
+        "kinks": kinks,
         "kernel_ms": kernel,
         "fp64_dets": st["fp64_dets"],
         "bin_pairs": st["bin_pairs"],
         "work_items": st["work_items"],
         "image_mean": checksum,
-        "lds_bytes_per_s_raster": LDS_BYTES_PER_SPAN * spans / raster_s,
-        "lds_frac_raster": LDS_BYTES_PER_SPAN * spans / raster_s / PEAK_LDS_BYTES,
+        "lds_bytes_per_s_raster": LDS_BYTES_PER_KINK * kinks / raster_s,
+        "lds_frac_raster": LDS_BYTES_PER_KINK * kinks / raster_s / PEAK_LDS_BYTES,
         "roofline": {
             "kernel": "k_raster",
             "bound": "alu",
@@ -368,7 +369,7 @@ def main():
             "frac": achieved / PEAK_VALU_OPS,
             "traffic": raster_traffic(),
             "ops_per_launch": ops,
-            "ops_per_span": OPS_PER_SPAN,
+            "ops_per_kink": OPS_PER_KINK,
         },
     }
     if not args.no_cpu_baseline:

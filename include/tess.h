@@ -138,6 +138,8 @@ typedef struct {
     float bin_ms;           /* count + scan + plan + items + scatter              */
     float raster_ms;        /* raster kernel                                      */
     float finalize_ms;      /* finalize kernel                                    */
+    uint64_t kinks;         /* row crossings of creases (break points) rastered,  */
+                            /* the raster's unit of arithmetic                    */
 } tess_stats;
 
 /*

@@ -54,7 +54,8 @@ class TessStats(ctypes.Structure):
                 ("tile_cols", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("ms", ctypes.c_float),
                 ("setup_ms", ctypes.c_float), ("bin_ms", ctypes.c_float),
-                ("raster_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float)]
+                ("raster_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
+                ("kinks", ctypes.c_uint64)]
 
     def as_dict(self) -> Dict:
         return {k: (float(getattr(self, k)) if k.endswith("ms") else int(getattr(self, k)))

@@ -433,6 +433,7 @@ void fill_stats(tess_stats *stats, const DevCounters &c, const Plan &plan, int c
     stats->degenerate = c.degenerate;
     stats->fragments = c.fragments;
     stats->spans = c.spans;
+    stats->kinks = c.kinks;
     stats->tile_rows = plan.Th;
     stats->tile_cols = plan.Tw;
     stats->chunk = chunk;
@@ -745,6 +746,7 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
                 // the graph's counters missed this image's raster
                 acc.fragments += one.fragments;
                 acc.spans += one.spans;
+                acc.kinks += one.kinks;
                 acc.work_items += one.work_items;
                 acc.ms += one.ms;
             }

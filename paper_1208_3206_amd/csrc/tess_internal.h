@@ -49,7 +49,7 @@ struct DevCounters {
     unsigned long long tets, zero_volume, inverted, fp64_dets, degenerate;
     unsigned long long fragments;   // (pixel, tetrahedron) pairs with rho * dl > 0
     unsigned long long spans;       // (tetrahedron, pixel row, tile) spans rastered
-    unsigned long long pad;
+    unsigned long long kinks;       // row crossings of creases (break points) evaluated
 };
 
 // Result of the binning pass, read back by the host to size the raster.

@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     const int tsize = B.Th * stride;
     for (int i = threadIdx.x; i < tsize; i += TPB) sA[i] = 0.0;
     __syncthreads();
-    uint32_t frags = 0, spans = 0;
+    uint32_t frags = 0, spans = 0, kinks = 0;
     // lane t takes entries t*per .. t*per+per-1: the list is in rough id order
     // (neighbouring cubes), so this spreads a wavefront's 64 footprints over
     // the tile instead of stacking their atomics on the same LDS cells
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             if (!(h.flags & REC_VALID)) continue;
             frags += raster_record(h, coef[id].c, B, tx0, ty0, n, rows,
                                    [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
-                                   spans);
+                                   spans, kinks);
         }
     }
     __syncthreads();
@@ -417,9 +417,11 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     }
     const unsigned long long f = wave_sum((unsigned long long)frags);
     const unsigned long long sp = wave_sum((unsigned long long)spans);
+    const unsigned long long kk = wave_sum((unsigned long long)kinks);
     if ((threadIdx.x & 63) == 0) {
         if (f) atomicAdd(&counters->fragments, f);
         if (sp) atomicAdd(&counters->spans, sp);
+        if (kk) atomicAdd(&counters->kinks, kk);
     }
 }
 

@@ -535,7 +535,7 @@ TESS_HD inline void span_geom(uint32_t flags, const double *cf, SpanGeom &G) {
 // tile's samples with f > 0.
 template <typename Dep>
 TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0, double Y, int n,
-                                 double ulo, double uhi, Dep &&dep) {
+                                 double ulo, double uhi, Dep &&dep, uint32_t &kinks) {
     double A[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) A[g] = G.a[g] + G.b[g] * X0 + G.c[g] * Y;  // G_g at sample u: A + b u
@@ -613,12 +613,14 @@ TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0,
             if (j >= 0 && j < n) dep(j, v1);
             if (j >= -1 && j + 1 < n) dep(j + 1, D - v1);
             have = true;
+            ++kinks;
             pA = A[g];
             pB = G.b[g];
             pHi = hi[g];
         }
     }
     if (have) {
+        ++kinks;
         const double u = pHi;
         const double J = -(pA + pB * u), D = -pB;
         const double fj = floor(u);
@@ -633,10 +635,11 @@ TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0,
 // All spans of one record in one tile (every periodic offset that meets it):
 // tile pixels [tx0, tx0 + n) x [ty0, ty0 + rows).  dep(row, j, v) adds v to
 // the tile's A[row][j].  Returns the covered sample count; spans counts the
-// rows visited.
+// rows visited, kinks the break points placed.
 template <typename Dep>
 TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0,
-                                    int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
+                                    int ty0, int n, int rows, Dep &&dep, uint32_t &spans,
+                                    uint32_t &kinks) {
     SpanGeom G;
     span_geom(h.flags, cf, G);
     const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
@@ -654,7 +657,7 @@ TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const Bi
             for (int y = ylo; y <= yhi; ++y) {
                 const double Y = (double)(y + ky * B.H - by0) + 0.5;
                 const int row = y - ty0;
-                frags += row_span(G, cf, X0, Y, n, ulo, uhi, [&](int j, double v) { dep(row, j, v); });
+                frags += row_span(G, cf, X0, Y, n, ulo, uhi, [&](int j, double v) { dep(row, j, v); }, kinks);
                 ++spans;
             }
         }
@@ -675,7 +678,8 @@ TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const Bi
 // the two silhouette crossings of a row); spans counts the rows visited.
 template <typename Dep>
 TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0,
-                                    int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
+                                    int ty0, int n, int rows, Dep &&dep, uint32_t &spans,
+                                    uint32_t &kinks) {
     const int m = (int)(h.flags & REC_NG_MASK);  // 3 or 4 silhouette vertices
     const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
     const int by0 = range_lo(h.by), by1 = range_hi(h.by);
@@ -773,6 +777,7 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
                 // max(j, 0) (jlo <= 0). Any j next to the kink gives the same
                 // sum, since the deposits use the exact offset from column j.
                 const double Xj = X0 + (enter ? -kSampleEps : kSampleEps);
+                kinks += (uint32_t)max(r1 - r0 + 1, 0);
                 for (int r = r0; r <= r1; ++r, x += sl) {
                     const int row = r + rshift;
                     const int j = min(max((int)floor(x - Xj) + 1, jlo), n);
@@ -791,9 +796,10 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
 // One record in one tile, in whichever form its payload has.
 template <typename Dep>
 TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const BinParams &B, int tx0,
-                                      int ty0, int n, int rows, Dep &&dep, uint32_t &spans) {
-    if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans);
-    return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans);
+                                      int ty0, int n, int rows, Dep &&dep, uint32_t &spans,
+                                      uint32_t &kinks) {
+    if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
 }
 
 }  // namespace tess

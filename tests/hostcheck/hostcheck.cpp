@@ -85,13 +85,13 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
             const size_t last = std::min(lst.size(), first + (size_t)chunk);
             for (size_t e = first; e < last; ++e) {
                 const uint32_t id = lst[e];
-                uint32_t sp = 0;
+                uint32_t sp = 0, kk = 0;
                 frags += raster_record(head[id], coef[id].c, B, tx0, ty0, n, rows,
                                      [&](int row, int j, double v) {
                                          if (row < 0 || row >= rows || j < -2 || j > n + 1) throw 1;
                                          if (j >= 0 && j < n) tile[(size_t)row * B.Tw + j] += v;
                                      },
-                                     sp);
+                                     sp, kk);
                 spans += sp;
             }
             for (int r = 0; r < rows; ++r)

@@ -35,8 +35,8 @@ PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
 TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
-    "sha256": "",
-    "fetch_kib": 0.0, "write_kib": 0.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "6cedd1791de789a1521084cfea4dae0d311e0cc4dd0ee95cb040f788ccd52d2b",
+    "fetch_kib": 89566535.4, "write_kib": 2306671.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device twice (scale reference for HBM byte counters)")
-    ap.add_argument("--cpu-crop", type=int, default=24,
+    ap.add_argument("--cpu-crop", type=int, default=12,
                     help="edge (pixels) of the centred crop the oracle renders for the CPU baseline")
     return ap.parse_args()
 

@@ -35,6 +35,7 @@ PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
 TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
+    "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
     "sha256": "6cedd1791de789a1521084cfea4dae0d311e0cc4dd0ee95cb040f788ccd52d2b",
     "fetch_kib": 89566535.4, "write_kib": 2306671.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
@@ -236,7 +237,7 @@ def run_learned(args, w, tess, W, torch):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64 raster, bf16 network",
-        "data": "synthetic (seeded Zel'dovich lattices, kmax 16, D 5)",
+        "data": "synthetic (seeded Zel'dovich lattices, kmax %d, D %g)" % (w.kmax, w.growth[0]),
         "config": {"workload": w.name, "coarse": w.n, "reference": wr.n, "image": [w.width, w.height]},
         "plain": plain,
         "learned": learned,
@@ -261,10 +262,13 @@ def copy_probe(torch):
     print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 2}), flush=True)
 
 
-def raster_traffic():
+def raster_traffic(workload, tile, block):
     """HBM bytes per raster launch from the committed counter passes, or None
-    when the raster's sources changed since they were taken."""
+    for another workload or launch shape, or when the raster's sources changed
+    since they were taken."""
     import hashlib
+    if workload != TRAFFIC["workload"] or list(tile) != TRAFFIC["tile"] or block != TRAFFIC["block"]:
+        return None
     h = hashlib.sha256()
     for f in TRAFFIC["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -333,7 +337,8 @@ def main():
     raster_s = kernel["raster_ms"] * 1e-3
     achieved = ops / raster_s
     result = {
-        "metric": "tets/s and fragments/s at 256^3->2048^2",
+        "metric": "tets/s and fragments/s at %d^3->%d^2" % (w.n, w.width) if w.width == w.height
+                  else "tets/s and fragments/s at %d^3->%dx%d" % (w.n, w.width, w.height),
         "value": w.tets / (ms * 1e-3),
         "unit": "tets/s",
         "n_gpus": 1,
@@ -344,7 +349,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded Zel'dovich lattice, kmax 64, D 8)",
+        "data": "synthetic (seeded Zel'dovich lattice, kmax %d, D %g)" % (w.kmax, w.growth[0]),
         "config": {"workload": w.name, "lattice": w.n, "tets": w.tets, "image": [w.width, w.height],
                    "view": "z-projection, periodic", "determinant": args.precision,
                    "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"],
@@ -367,7 +372,7 @@ def main():
             "peak": PEAK_VALU_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved / PEAK_VALU_OPS,
-            "traffic": raster_traffic(),
+            "traffic": raster_traffic(w.name, (st["tile_rows"], st["tile_cols"]), st["block"]),
             "ops_per_launch": ops,
             "ops_per_kink": OPS_PER_KINK,
         },

@@ -29,6 +29,10 @@ OPS_PER_KINK = 6
 # Its LDS traffic: two FP64 read-modify-writes.
 LDS_BYTES_PER_KINK = 2 * 16
 PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
+# A raster that visits every covered pixel needs at least 16 lane-operations
+# per fragment (4 plane evaluations, 2 min/max, subtract and clamp, a
+# compensated add); reported alongside as the fragment-equivalent rate.
+OPS_PER_FRAGMENT = 16
 # k_raster's HBM bytes at stress 2048^2 from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (KiB per dispatch), scaled by what the same counters read for a 1 GiB
 # device copy (--copy-probe); valid only for the sources they were taken on.
@@ -375,6 +379,12 @@ def main():
             "traffic": raster_traffic(w.name, (st["tile_rows"], st["tile_cols"]), st["block"]),
             "ops_per_launch": ops,
             "ops_per_kink": OPS_PER_KINK,
+        },
+        "fragment_equivalent": {
+            "ops_per_fragment": OPS_PER_FRAGMENT,
+            "achieved": OPS_PER_FRAGMENT * frags / raster_s / 1e12,
+            "unit": "Tops/s",
+            "x_peak": OPS_PER_FRAGMENT * frags / raster_s / PEAK_VALU_OPS,
         },
     }
     if not args.no_cpu_baseline:

@@ -265,6 +265,11 @@ const char *tess_last_error(void);
 /* Library version, major * 10000 + minor * 100 + patch. */
 int32_t tess_version(void);
 
+/* sizeof of the ABI's structs as this library was compiled, for bindings to
+ * check their own layouts against: which = 0 tess_build_desc, 1 tess_view,
+ * 2 tess_tune, 3 tess_stats, 4 tess_refine_desc; 0 for any other value. */
+uint64_t tess_struct_size(int32_t which);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,8 @@ def _load():
     L.tess_last_error.restype = ctypes.c_char_p
     L.tess_version.argtypes = []
     L.tess_version.restype = ctypes.c_int32
+    L.tess_struct_size.argtypes = [ctypes.c_int32]
+    L.tess_struct_size.restype = ctypes.c_uint64
     for f in (L.tess_build_desc_default, L.tess_build, L.tess_project, L.tess_project_batch,
               L.tess_check_view, L.tess_check_build_desc, L.tess_refine_desc_default,
               L.tess_refine, L.tess_mlp_loss_grad):
@@ -129,7 +131,7 @@ _lib = _load()
 # names exported by the C ABI (checked against include/tess.h by the tests)
 EXPORTS = ("tess_build_desc_default", "tess_build", "tess_free", "tess_project",
            "tess_project_batch", "tess_check_view", "tess_check_build_desc",
-           "tess_last_error", "tess_version", "tess_refine_desc_default", "tess_refine",
+           "tess_last_error", "tess_version", "tess_struct_size", "tess_refine_desc_default", "tess_refine",
            "tess_mlp_loss_grad")
 
 

@@ -816,3 +816,14 @@ extern "C" tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_s
 extern "C" const char *tess_last_error(void) { return g_error.c_str(); }
 
 extern "C" int32_t tess_version(void) { return 100; }
+
+extern "C" uint64_t tess_struct_size(int32_t which) {
+    switch (which) {
+        case 0: return sizeof(tess_build_desc);
+        case 1: return sizeof(tess_view);
+        case 2: return sizeof(tess_tune);
+        case 3: return sizeof(tess_stats);
+        case 4: return sizeof(tess_refine_desc);
+        default: return 0;
+    }
+}

@@ -32,6 +32,15 @@ def test_every_declared_symbol_is_exported(tess):
     assert set(names) == set(tess.EXPORTS)
 
 
+def test_binding_structs_match_the_library(tess):
+    # the ctypes mirrors must have the C layouts' sizes (a mismatch would
+    # make the library read or write past the binding's buffers)
+    mirrors = [tess.TessBuildDesc, tess.TessView, tess.TessTune, tess.TessStats, tess.TessRefineDesc]
+    for which, cls in enumerate(mirrors):
+        assert tess.lib().tess_struct_size(which) == ctypes.sizeof(cls), cls.__name__
+    assert tess.lib().tess_struct_size(99) == 0
+
+
 def test_version_and_empty_error(tess):
     assert tess.version() >= 100
     assert isinstance(tess.last_error(), str)

@@ -36,7 +36,11 @@ class OrcProblem(ctypes.Structure):
         ("width", ctypes.c_int32),
         ("height", ctypes.c_int32),
         ("wrap", ctypes.c_int32),
+        ("qpow", ctypes.c_int32),
     ]
+
+# projected per-tetrahedron value q = rho^p by name (view["quantity"])
+QUANTITY_POWER = {"density": 1, "unit": 0, "density2": 2}
 
 
 class OrcStats(ctypes.Structure):
@@ -98,6 +102,7 @@ def _problem(dims: Sequence[int], view: Dict, box=(1.0, 1.0, 1.0), periodic: boo
     p.total_mass = float(total_mass)
     p.width, p.height = int(view["width"]), int(view["height"])
     p.wrap = 1 if view.get("wrap", 0) else 0
+    p.qpow = QUANTITY_POWER[view.get("quantity", "density")]
     return p
 
 

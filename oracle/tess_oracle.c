@@ -9,11 +9,15 @@
  * What it computes (point sampling at pixel centres):
  *
  *   I(ix, iy) = sum over lattice cubes, sum over the six tetrahedra T of the
- *               cube, of (m / |V(T)|) * length(ray(ix, iy) inside T)
+ *               cube, of q(T) * length(ray(ix, iy) inside T),
+ *   q(T) = rho(T)^p,  rho(T) = m / |V(T)|,  p = qpow in {0, 1, 2}
  *
- * which is the line-of-sight projection of the tessellation density
- * (Eq. Eqn:TetProjection, with the per-tetrahedron value q = rho_loc = m/V
- * of Eq. Eqn-rho_loc and the overlap sum of Eq. Eqn-rho_tot_b).  The
+ * which is the line-of-sight projection of Eq. Eqn:TetProjection with a
+ * constant per-tetrahedron value q: p = 1 is the column density (q = rho_loc
+ * of Eq. Eqn-rho_loc, with the overlap sum of Eq. Eqn-rho_tot_b); p = 0 and
+ * p = 2 are the density projections of Eq. Eqn-column-density with g = 1 (the
+ * path length summed over streams, the line-of-sight integral of the stream
+ * count) and g = rho^2.  The
  * cell-projection section (Eq. Eqn:TetSum) evaluates the same sum with a
  * camera-distance split; the oracle uses the plain per-ray clip instead.
  *
@@ -38,7 +42,7 @@
  *     the ray (n_d == 0) excludes the ray when h - n_u pu - n_v pv < 0; on
  *     the plane itself the ray is kept iff n_u < 0, or n_u == 0 and n_v < 0
  *     (a half-open rule, so exactly one of two face-sharing tets keeps it).
- *  7. I += rho * dl with Neumaier-compensated FP64 sums.  With image wrap
+ *  7. I += q * dl with Neumaier-compensated FP64 sums.  With image wrap
  *     the pixel index is taken modulo (W, H); otherwise pixels outside the
  *     window are dropped.
  *
@@ -67,6 +71,7 @@ typedef struct {
     double extent[2];     /* window size (u, v) */
     int32_t width, height;
     int32_t wrap;         /* pixel index modulo (W, H) */
+    int32_t qpow;         /* projected value q = rho^qpow, qpow in {0, 1, 2} */
 } orc_problem;
 
 typedef struct {
@@ -80,7 +85,7 @@ static const int TET_TABLE[6][4] = {
     {1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
 
 typedef struct {
-    double rho;
+    double q;             /* projected value rho^qpow */
     double n[4][3];       /* outward normals in view space */
     double h[4];          /* plane offsets, n . y <= h inside */
     int64_t ix0, ix1, iy0, iy1;  /* candidate pixel range (inclusive, unwrapped) */
@@ -116,6 +121,7 @@ static int check_problem(const orc_problem *P) {
     if (P->width < 1 || P->height < 1) return ORC_EINVAL;
     if (!(P->extent[0] > 0) || !(P->extent[1] > 0)) return ORC_EINVAL;
     if (!(P->total_mass > 0)) return ORC_EINVAL;
+    if (P->qpow < 0 || P->qpow > 2) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -167,7 +173,8 @@ static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
                      orc_tet *t, double *V) {
     *V = signed_volume(v);
     if (*V == 0.0) return 0;
-    t->rho = mass / fabs(*V);
+    const double rho = mass / fabs(*V);
+    t->q = P->qpow == 0 ? 1.0 : (P->qpow == 1 ? rho : rho * rho);
     double yv[4][3];
     for (int m = 0; m < 4; ++m) {
         double d[3] = {v[m][0] - P->center[0], v[m][1] - P->center[1], v[m][2] - P->center[2]};
@@ -274,7 +281,8 @@ int orc_cube_tets(const orc_problem *P, const float *x, const float *y, const fl
  * ignored.  out: H*W doubles, overwritten.  Serial, in list order. */
 int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
                      const double *mass, double *out, orc_stats *st) {
-    if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0))
+    if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0) ||
+        P->qpow < 0 || P->qpow > 2)
         return ORC_EINVAL;
     if (ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out) return ORC_EINVAL;
     int64_t npx = (int64_t)P->width * P->height;
@@ -300,7 +308,7 @@ int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
                 double dl = clip_dl(&tt, pixel_u(P, ix), pv);
                 if (dl > 0) {
                     s.fragments++;
-                    neu_add(&out[ry * P->width + rx], &comp[ry * P->width + rx], tt.rho * dl);
+                    neu_add(&out[ry * P->width + rx], &comp[ry * P->width + rx], tt.q * dl);
                 }
             }
         }
@@ -419,7 +427,7 @@ int orc_project_region(const orc_problem *P, const float *x, const float *y, con
                     if (dl > 0) {
                         frags++;
                         int64_t o = (ry - cy0) * cw + (rx - cx0);
-                        neu_add(&out[o], &comp[o], tt.rho * dl);
+                        neu_add(&out[o], &comp[o], tt.q * dl);
                     }
                 }
             }
@@ -506,7 +514,7 @@ int orc_project_pixels(const orc_problem *P, const float *x, const float *y, con
                             double dl = clip_dl(&tt, pixel_u(P, ix), pv);
                             if (dl > 0) {
                                 frags++;
-                                neu_add(&a[2 * smp[s].idx], &a[2 * smp[s].idx + 1], tt.rho * dl);
+                                neu_add(&a[2 * smp[s].idx], &a[2 * smp[s].idx + 1], tt.q * dl);
                             }
                         }
                     }

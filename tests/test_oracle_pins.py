@@ -187,6 +187,39 @@ def test_c4_z_only_displacement_keeps_column_density():
     np.testing.assert_allclose(img, 1.0, rtol=0, atol=1e-11)
 
 
+# ------------------ Q: projected quantity q = rho^p (p = 0 path length, 2 rho^2)
+@pytest.mark.parametrize("quantity,power", [("unit", 0), ("density", 1), ("density2", 2)])
+def test_q_undisplaced_lattice_projects_mass_power(quantity, power):
+    # rho = M everywhere and every ray crosses a column of length 1
+    n, M = 4, 3.0
+    xyz = W.undisplaced(n)
+    view = dict(W.z_view(16, 12), quantity=quantity)
+    img, _ = O.project_region(*xyz, (n, n, n), view, total_mass=M)
+    np.testing.assert_allclose(img, M ** power, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("quantity", ["unit", "density2"])
+def test_q_z_only_layers_closed_forms(quantity):
+    # z = q_z + A sin(2 pi q_z) with A > 1/(2 pi): flat layers k of signed
+    # thickness dz_k, some inverted (shell crossing). Every ray crosses each
+    # layer once: sum dl = sum |dz_k|, and with rho_k = M / (n |dz_k|),
+    # sum rho^2 dl = M^2 / n^2 * sum 1 / |dz_k|.
+    n, M, A = 8, 2.0, 0.3
+    q = W.lattice_q(n)
+    x = q[:, 0].astype(np.float32)
+    y = q[:, 1].astype(np.float32)
+    z = W.wrap_to_f32(q[:, 2] + A * np.sin(2 * np.pi * q[:, 2]), 1.0)
+    zk = z.reshape(n, n, n)[:, 0, 0].astype(np.float64)        # layer k at column (0, 0)
+    dz = np.roll(zk, -1) - zk
+    dz -= np.ceil(dz - 0.5)                                      # nearest periodic image
+    assert (dz < 0).any()
+    view = dict(W.z_view(16, 12), quantity=quantity)
+    img, st = O.project_region(x, y, z, (n, n, n), view, total_mass=M)
+    assert st["inverted"] > 0
+    want = np.abs(dz).sum() if quantity == "unit" else M ** 2 / n ** 2 * (1.0 / np.abs(dz)).sum()
+    np.testing.assert_allclose(img, want, rtol=1e-12, atol=0)
+
+
 def test_c4_near_degenerate_tets():
     # z = q_z - A sin(2 pi q_z + phi): the first cell layer has thickness
     # 1/n - 2 A sin(pi/n) = delta/n for A = (1 - delta)/(2 n sin(pi/n)),

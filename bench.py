@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quantity", default="density", choices=["density", "unit", "density2"],
+                    help="projected per-tetrahedron value: rho, 1 or rho^2")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device twice (scale reference for HBM byte counters)")
     ap.add_argument("--cpu-crop", type=int, default=12,
@@ -311,7 +313,7 @@ def main():
     xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
     gen_s = time.perf_counter() - t0
     d = [torch.from_numpy(a).to(dev) for a in xyz]
-    view = W.workload_views(w)[0]
+    view = dict(W.workload_views(w)[0], quantity=args.quantity)
     lat = tess.build(*d, (w.n,) * 3, precision=args.precision)
     out = torch.empty((w.height, w.width), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -356,6 +358,7 @@ def main():
         "data": "synthetic (seeded Zel'dovich lattice, kmax %d, D %g)" % (w.kmax, w.growth[0]),
         "config": {"workload": w.name, "lattice": w.n, "tets": w.tets, "image": [w.width, w.height],
                    "view": "z-projection, periodic", "determinant": args.precision,
+                   "quantity": args.quantity,
                    "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"],
                    "block": st["block"]},
         "fragments": frags,

@@ -108,7 +108,21 @@ typedef struct {
                                requires rot to be an axis permutation with signs,
                                a periodic lattice and extent equal to the box
                                lengths along screen u and v                      */
+    int32_t quantity;       /* projected per-tetrahedron value q (tess_quantity);
+                               0, the zero-initialised default, is the density   */
 } tess_view;
+
+/* The constant per-tetrahedron value q of Eq. Eqn:TetProjection, with
+ * rho = m / |V| (Eq. Eqn-rho_loc): the density itself (column density), or the
+ * density projections of Eq. Eqn-column-density with g = 1 (the path length
+ * summed over streams: the line-of-sight integral of the stream count) and
+ * g = rho^2.  Values other than the density need |V| to full precision, so
+ * their determinants are all taken in FP64. */
+typedef enum {
+    TESS_QUANTITY_DENSITY = 0,   /* q = rho    */
+    TESS_QUANTITY_UNIT = 1,      /* q = 1      */
+    TESS_QUANTITY_DENSITY2 = 2   /* q = rho^2  */
+} tess_quantity;
 
 /* Raster parameters.  0 in a field means "choose automatically".  The image
  * is cut into tiles of tile_rows x tile_cols pixels (row bands when tile_cols

@@ -36,7 +36,11 @@ class TessBuildDesc(ctypes.Structure):
 class TessView(ctypes.Structure):
     _fields_ = [("rot", ctypes.c_double * 9), ("center", ctypes.c_double * 3),
                 ("extent", ctypes.c_double * 2), ("width", ctypes.c_int32),
-                ("height", ctypes.c_int32), ("wrap", ctypes.c_int32)]
+                ("height", ctypes.c_int32), ("wrap", ctypes.c_int32),
+                ("quantity", ctypes.c_int32)]
+
+# tess_quantity by name (view["quantity"], default "density")
+QUANTITIES = {"density": 0, "unit": 1, "density2": 2}
 
 
 class TessTune(ctypes.Structure):
@@ -171,7 +175,8 @@ def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
 
 
 def make_view(view: Dict) -> TessView:
-    """Converts a view dict (rot, center, extent, width, height, wrap) to the C struct."""
+    """Converts a view dict (rot, center, extent, width, height, wrap, optional
+    quantity: "density", "unit" or "density2") to the C struct."""
     v = TessView()
     for i in range(9):
         v.rot[i] = float(view["rot"][i])
@@ -180,6 +185,7 @@ def make_view(view: Dict) -> TessView:
     v.extent[0], v.extent[1] = float(view["extent"][0]), float(view["extent"][1])
     v.width, v.height = int(view["width"]), int(view["height"])
     v.wrap = 1 if view.get("wrap", 0) else 0
+    v.quantity = QUANTITIES[view.get("quantity", "density")]
     return v
 
 

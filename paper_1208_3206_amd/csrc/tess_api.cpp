@@ -164,6 +164,9 @@ extern "C" tess_status tess_check_view(const tess_view *v, const tess_build_desc
                 return fail(TESS_EINVAL, "view rotation is not orthonormal (rows %d, %d)", r, s);
         }
     if (v->wrap != 0 && v->wrap != 1) return fail(TESS_EINVAL, "wrap must be 0 or 1");
+    if (v->quantity != TESS_QUANTITY_DENSITY && v->quantity != TESS_QUANTITY_UNIT &&
+        v->quantity != TESS_QUANTITY_DENSITY2)
+        return fail(TESS_EINVAL, "quantity must be 0 (density), 1 (unit) or 2 (density^2)");
     if (v->wrap) {
         int axis[2];
         for (int r = 0; r < 2; ++r) {
@@ -312,6 +315,18 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     vp.W = v->width;
     vp.H = v->height;
     vp.wrap = v->wrap;
+    vp.qpow = v->quantity == TESS_QUANTITY_UNIT ? 0 : (v->quantity == TESS_QUANTITY_DENSITY2 ? 2 : 1);
+    // The crease threshold in the image's own scale. q = 1: the integral of q
+    // over the tetrahedra, which setup reads from the device (k_qsum fills it;
+    // with many streams it far exceeds the volume). q = rho^2: the density
+    // image's threshold times the mean density; the integral of rho^2 is
+    // dominated by the image's peaks, where the row sums are already at their
+    // noisiest, and would loosen the threshold there.
+    vp.qsum = nullptr;
+    vp.bmax_per_q = vp.inv_du * vp.inv_dv / ((double)v->width * (double)v->height) * (64.0 / (double)v->width);
+    if (vp.qpow == 2) vp.crease_bmax *= lp.tet_mass / lp.v0;
+    // q / rho needs |V| to full precision
+    if (vp.qpow != 1) lp.det_cond_k = -1.0;
 }
 
 struct Plan {
@@ -399,9 +414,22 @@ tess_status ensure_back(Workspace &ws, const Geometry &g, int chunk, unsigned lo
 }
 
 // Setup, count, scan and totals of one image (no host synchronisation).
+// Setup of one image; for q = 1 first the integral of q into slot->qsum.
+tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipStream_t s) {
+    ViewParams vp = g.vp;
+    if (vp.qpow == 0) {
+        TESS_HIP(launch_zero(&slot->qsum, 1, s));
+        TESS_HIP(launch_qsum(g.lp, vp, &slot->qsum, s));
+        vp.qsum = &slot->qsum;
+    }
+    TESS_HIP(launch_setup(g.lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    return TESS_OK;
+}
+
 tess_status enqueue_front(const Geometry &g, Workspace &ws, PlanOut *slot, unsigned long long cap,
                           unsigned int *overflow, hipStream_t s) {
-    TESS_HIP(launch_setup(g.lp, g.vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    tess_status st = enqueue_setup(g, ws, slot, s);
+    if (st != TESS_OK) return st;
     TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
     TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));
     TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, cap, slot, overflow, s));
@@ -451,7 +479,8 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     TESS_HIP(ws.plan.ensure(1));
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
     TESS_HIP(launch_zero((double *)ws.counters.p, sizeof(DevCounters) / sizeof(double), s));
-    TESS_HIP(launch_setup(g.lp, g.vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    st = enqueue_setup(g, ws, ws.plan.p, s);
+    if (st != TESS_OK) return st;
     if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
     TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
     TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));

@@ -31,6 +31,11 @@ struct ViewParams {
     double crease_bmax;      // footprints with a steeper x slope keep the line form
     int32_t W, H;
     int32_t wrap;
+    int32_t qpow;            // projected value q = rho^qpow (0, 1 or 2)
+    // qpow == 0: the crease threshold is *qsum * bmax_per_q, qsum (device) the
+    // integral of q over all tetrahedra (k_qsum); null otherwise
+    const double *qsum;
+    double bmax_per_q;
 };
 
 // Screen tiling: tiles of Th rows x Tw columns (a row band when Tw >= W).
@@ -57,7 +62,7 @@ struct PlanOut {
     unsigned long long total_pairs;
     unsigned long long n_items;
     unsigned long long max_bin;
-    unsigned long long pad;
+    double qsum;                    // integral of q over the tetrahedra (qpow != 1)
 };
 
 // Raster work item: a chunk of one tile's list.
@@ -106,6 +111,9 @@ static_assert(sizeof(Payload) == 128, "one 128-byte line per record");
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `stream` and return the launch status.
+// Adds the integral of q over all tetrahedra (cube_qvol) into *qsum.
+hipError_t launch_qsum(const LatticeParams &L, const ViewParams &V, double *qsum, hipStream_t stream);
+
 hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream);
 

@@ -78,6 +78,24 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
     }
 }
 
+// One thread per cube: the integral of the projected value q over all
+// tetrahedra, the image's scale for the crease threshold when q != rho.
+__global__ void __launch_bounds__(256) k_qsum(LatticeParams L, ViewParams V, double *__restrict__ qsum) {
+    double sum = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride)
+        sum += cube_qvol(L, V, cube);
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if ((threadIdx.x & 63) == 0 && sum != 0.0) atomicAdd(qsum, sum);
+}
+
+hipError_t launch_qsum(const LatticeParams &L, const ViewParams &V, double *qsum, hipStream_t stream) {
+    const int64_t want = (L.ncubes + 255) / 256;
+    const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    hipLaunchKernelGGL(k_qsum, dim3(blocks), dim3(256), 0, stream, L, V, qsum);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream) {
     const int64_t want = (L.ncubes + 255) / 256;

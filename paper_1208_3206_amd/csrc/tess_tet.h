@@ -223,15 +223,14 @@ struct CubeCounts {
 // corners, volume determinant with its FP64 fallback, footprint.  head[t] and
 // coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
 // cover no pixel centre).
-TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
-                               Payload coef[6], CubeCounts &cnt) {
+// The eight corners of a lattice cube: corner 0's position X0 and every
+// corner's offset e[n] from it, unwrapped to the nearest periodic image.
+TESS_HD inline void cube_corners(const LatticeParams &L, int64_t cube, double X0[3], double e[8][3]) {
     const int64_t i = cube % L.c[0];
     const int64_t rest = cube / L.c[0];
     const int64_t j = rest % L.c[1];
     const int64_t k = rest / L.c[1];
     // gather the eight corners (tracer id = i + d0 (j + d1 k))
-    double X0[3] = {0, 0, 0};
-    double e[8][3];
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         int64_t ii = i + (n & 1), jj = j + ((n >> 1) & 1), kk = k + ((n >> 2) & 1);
@@ -254,6 +253,39 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             }
         }
     }
+}
+
+// Sum over the cube's six tetrahedra of q |V|, q = rho^qpow, rho = m / |V|:
+// the integral of the projected value over the image when every tetrahedron
+// is in view. Determinants in FP64, as setup_cube takes them for qpow != 1.
+TESS_HD inline double cube_qvol(const LatticeParams &L, const ViewParams &V, int64_t cube) {
+    double X0[3], e[8][3];
+    cube_corners(L, cube, X0, e);
+    double sum = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
+        double a[3], b[3], c[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            a[q] = e[v1][q] - e[v0][q];
+            b[q] = e[v2][q] - e[v0][q];
+            c[q] = e[v3][q] - e[v0][q];
+        }
+        const double vol = fabs(det6_fp64(a, b, c)) / 6.0;
+        if (vol == 0.0) continue;
+        sum += V.qpow == 0 ? vol : (V.qpow == 1 ? L.tet_mass : L.tet_mass * L.tet_mass / vol);
+    }
+    return sum;
+}
+
+TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
+                               Payload coef[6], CubeCounts &cnt) {
+    double X0[3], e[8][3];
+    cube_corners(L, cube, X0, e);
+    // x slope beyond which a footprint keeps the line form, from the image's
+    // scale: the mass in view, or the measured integral of q
+    const double crease_bmax = V.qsum ? *V.qsum * V.bmax_per_q : V.crease_bmax;
     // projected corners in pixel units
     const double b0[3] = {X0[0] - V.center[0], X0[1] - V.center[1], X0[2] - V.center[2]};
     double PX0 = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
@@ -334,8 +366,12 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             qx[m] = PX[vi[m]] - (double)ix0;
             qy[m] = PY[vi[m]] - (double)iy0;
         }
+        // q dl = (q / rho) rho dl: the density footprint with its mass scaled
+        // by rho^(qpow - 1), rho = 6 m / |6V|
+        const double rho_m = 6.0 / fabs(det6);  // rho / m
+        const double qscale = V.qpow == 1 ? 1.0 : (V.qpow == 0 ? 1.0 / (L.tet_mass * rho_m) : L.tet_mass * rho_m);
         Footprint fp;
-        if (!footprint(qx, qy, V.mass_px, fp)) continue;
+        if (!footprint(qx, qy, V.mass_px * qscale, fp)) continue;
         R.bx = pack_range(ix0, ix1);
         R.by = pack_range(iy0, iy1);
         R.flags = (uint32_t)fp.ng | ((uint32_t)fp.nw << REC_NW_SHIFT) | fp.ties | REC_VALID;
@@ -345,7 +381,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         double bmax = 0.0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
-        if (fp.nw == 0 && bmax <= V.crease_bmax && crease_payload(qx, qy, fp, coef[t].c)) {
+        if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, coef[t].c)) {
             R.flags |= REC_CREASE;
         } else {
 #pragma unroll

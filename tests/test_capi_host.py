@@ -87,6 +87,12 @@ def test_view_validation(tess):
     # permuted axes are fine for wrap (projection along x)
     xview = dict(W.z_view(32), rot=[0, 1, 0, 0, 0, 1, 1, 0, 0])
     tess.check_view(xview, d)
+    # the projected quantity: 0 density, 1 unit, 2 density^2; nothing else
+    for name in ("density", "unit", "density2"):
+        tess.check_view(dict(W.z_view(64), quantity=name), d)
+    v = tess.make_view(W.z_view(64))
+    v.quantity = 3
+    assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
 
 
 def test_null_arguments_rejected_without_gpu(tess):

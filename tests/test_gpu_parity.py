@@ -50,6 +50,21 @@ def assert_parity(got, ref, pix_tol=PIX_TOL, mass_tol=MASS_TOL, what=""):
     assert mass <= mass_tol, f"{what}: mass error {mass:.3e}"
 
 
+def assert_quantity_parity(got, ref, quantity, what=""):
+    """The density bar; for q = rho^2, pixels the oracle leaves empty are held
+    to 1e-12 of the image maximum instead of to the mean-based floor. The row
+    sums' FP64 rounding is ~5e-14 of the maximum (slope changes of the peaks,
+    carried along the row), and a rho^2 image's maximum is 500-3000x its mean,
+    which puts that noise at 0.1-2.6 of the 1e-4 bar on the mean-based floor."""
+    if quantity != "density2":
+        assert_parity(got, ref, what=what)
+        return
+    empty = ref == 0.0
+    assert np.abs(got[empty]).max(initial=0.0) <= 1e-12 * np.abs(ref).max(), what
+    got = np.where(empty, 0.0, got)
+    assert_parity(got, ref, what=what)
+
+
 def gpu_image(tess, xyz, dims, view, tune=None, **kw):
     import torch
     lat = tess.build(*dev(xyz), dims, **kw)
@@ -92,6 +107,33 @@ def test_rotated_views_no_wrap(tess):
         got, _ = gpu_image(tess, xyz, (n, n, n), view)
         ref, _ = O.project_region(*xyz, (n, n, n), view)
         assert_parity(got, ref, what="rotated 16^3 -> 96x80")
+
+
+@pytest.mark.parametrize("quantity", ["unit", "density2"])
+def test_projected_quantities(tess, quantity):
+    # q = 1 (path length summed over streams) and q = rho^2, z and rotated
+    # windows, a non-unit mass; the bar is the same as for the density
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    views = [W.z_view(120, 88)] + [W.rotated_view(R, 96, 80) for R in W.random_rotations(2, seed=31)]
+    for view in views:
+        view = dict(view, quantity=quantity)
+        got, st = gpu_image(tess, xyz, (n, n, n), view, total_mass=2.0)
+        ref, ost = O.project_region(*xyz, (n, n, n), view, total_mass=2.0)
+        assert_quantity_parity(got, ref, quantity, what=f"{quantity} 16^3 -> {view['width']}x{view['height']}")
+        assert st["tets"] == ost["tets"] and st["fp64_dets"] == st["tets"] + st["zero_volume"]
+
+
+def test_projected_quantity_in_a_batch(tess):
+    import torch
+    lats, xyzs, views = batch_case(tess, nviews=2, size=48)
+    views = [dict(v, quantity="density2") for v in views]
+    imgs = tess.project_batch(lats, views)
+    for s in range(2):
+        for v in range(2):
+            torch.testing.assert_close(imgs[s, v], tess.project(lats[s], views[v]), rtol=2.4e-7, atol=1e-9)
+    ref, _ = O.project_region(*xyzs[1], (16, 16, 16), views[1])
+    assert_quantity_parity(imgs[1, 1].cpu().numpy(), ref, "density2", what="density2 batch image")
 
 
 def test_fp64_determinant_path(tess, tiny_lattice):

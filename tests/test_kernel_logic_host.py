@@ -52,6 +52,31 @@ def test_zeldovich_wrap_matches_oracle_any_tiling(rows, cols, chunk):
     assert st["fragments"] == ost["fragments"]
 
 
+@pytest.mark.parametrize("quantity", ["unit", "density2"])
+@pytest.mark.parametrize("view_kind", ["z", "rotated"])
+def test_projected_quantities_match_oracle(quantity, view_kind):
+    # q = 1 and q = rho^2: the density footprint with its mass scaled per
+    # tetrahedron; shell crossing and a rotated window without wrap
+    n = 12
+    xyz = W.zeldovich(n, 4, 6.0, seed=5)
+    if view_kind == "z":
+        view = dict(W.z_view(96, 72), quantity=quantity)
+    else:
+        view = dict(W.rotated_view(W.random_rotations(1, seed=3)[0], 80, 64), quantity=quantity)
+    img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=8, tile_cols=40, chunk=500,
+                                    total_mass=2.0)
+    ref, ost = O.project_region(*xyz, (n, n, n), view, total_mass=2.0)
+    assert np.abs(img - ref).max() < 1e-8 * np.abs(ref).max()
+    # empty pixels of the rotated window hold only FP64 noise of the row sums,
+    # which scales with the image's maximum (a rho^2 image peaks at ~1000x its
+    # mean): held to 1e-12 of the maximum, the other pixels to the usual bar
+    empty = ref == 0.0
+    assert np.abs(img[empty]).max(initial=0.0) <= 1e-12 * np.abs(ref).max()
+    assert rel(np.where(empty, 0.0, img), ref) < (1e-8 if view_kind == "z" else 1e-5)
+    assert st["fragments"] == ost["fragments"]
+    assert st["fp64_dets"] == st["tets"] + st["zero_volume"]
+
+
 def test_tallest_tiles_match_oracle():
     # 256-row tiles (the largest the library accepts): row offsets of up to 255
     # inside a tile, footprints taller than the lattice spacing wrapping in y

@@ -37,6 +37,8 @@ class OrcProblem(ctypes.Structure):
         ("height", ctypes.c_int32),
         ("wrap", ctypes.c_int32),
         ("qpow", ctypes.c_int32),
+        ("slab", ctypes.c_int32),
+        ("slab_t", ctypes.c_double * 2),
     ]
 
 # projected per-tetrahedron value q = rho^p by name (view["quantity"])
@@ -103,6 +105,10 @@ def _problem(dims: Sequence[int], view: Dict, box=(1.0, 1.0, 1.0), periodic: boo
     p.width, p.height = int(view["width"]), int(view["height"])
     p.wrap = 1 if view.get("wrap", 0) else 0
     p.qpow = QUANTITY_POWER[view.get("quantity", "density")]
+    slab = view.get("slab")
+    p.slab = 1 if slab is not None else 0
+    if slab is not None:
+        p.slab_t[0], p.slab_t[1] = float(slab[0]), float(slab[1])
     return p
 
 

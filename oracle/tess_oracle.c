@@ -38,7 +38,9 @@
  *  5. Orthographic view: y = R (x - c), rows of R = (screen u, screen v,
  *     view direction).  Pixel centres at u = -Su/2 + (ix + 1/2) Su / W.
  *  6. Each pixel ray {(pu, pv, t)} is clipped against the four outward face
- *     planes n . y <= h; dl = max(0, t_exit - t_entry).  A face parallel to
+ *     planes n . y <= h; dl = max(0, t_exit - t_entry).  With a depth slab
+ *     [s0, s1] the chord is clipped to it as well (the slab-clamped front and
+ *     back fragments of the resampling section, Eqs. Eqn:ResFF, Eqn:ResBF).  A face parallel to
  *     the ray (n_d == 0) excludes the ray when h - n_u pu - n_v pv < 0; on
  *     the plane itself the ray is kept iff n_u < 0, or n_u == 0 and n_v < 0
  *     (a half-open rule, so exactly one of two face-sharing tets keeps it).
@@ -72,6 +74,8 @@ typedef struct {
     int32_t width, height;
     int32_t wrap;         /* pixel index modulo (W, H) */
     int32_t qpow;         /* projected value q = rho^qpow, qpow in {0, 1, 2} */
+    int32_t slab;         /* 1: only the depths t in [slab_t[0], slab_t[1]] count */
+    double slab_t[2];     /* depth t = third view coordinate, R (x - c) */
 } orc_problem;
 
 typedef struct {
@@ -86,6 +90,7 @@ static const int TET_TABLE[6][4] = {
 
 typedef struct {
     double q;             /* projected value rho^qpow */
+    double s0, s1;        /* depth slab (-inf, inf without one) */
     double n[4][3];       /* outward normals in view space */
     double h[4];          /* plane offsets, n . y <= h inside */
     int64_t ix0, ix1, iy0, iy1;  /* candidate pixel range (inclusive, unwrapped) */
@@ -122,6 +127,7 @@ static int check_problem(const orc_problem *P) {
     if (!(P->extent[0] > 0) || !(P->extent[1] > 0)) return ORC_EINVAL;
     if (!(P->total_mass > 0)) return ORC_EINVAL;
     if (P->qpow < 0 || P->qpow > 2) return ORC_EINVAL;
+    if (P->slab && !(P->slab_t[0] < P->slab_t[1])) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -175,6 +181,8 @@ static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
     if (*V == 0.0) return 0;
     const double rho = mass / fabs(*V);
     t->q = P->qpow == 0 ? 1.0 : (P->qpow == 1 ? rho : rho * rho);
+    t->s0 = P->slab ? P->slab_t[0] : -INFINITY;
+    t->s1 = P->slab ? P->slab_t[1] : INFINITY;
     double yv[4][3];
     for (int m = 0; m < 4; ++m) {
         double d[3] = {v[m][0] - P->center[0], v[m][1] - P->center[1], v[m][2] - P->center[2]};
@@ -232,7 +240,10 @@ static double clip_dl(const orc_tet *t, double pu, double pv) {
         }
     }
     if (!(hi > lo) || isinf(lo) || isinf(hi)) return 0.0;
-    return hi - lo;
+    /* slab: the part of the chord at depths in [s0, s1] */
+    if (lo < t->s0) lo = t->s0;
+    if (hi > t->s1) hi = t->s1;
+    return hi > lo ? hi - lo : 0.0;
 }
 
 static inline double pixel_u(const orc_problem *P, int64_t ix) {

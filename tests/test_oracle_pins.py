@@ -220,6 +220,55 @@ def test_q_z_only_layers_closed_forms(quantity):
     np.testing.assert_allclose(img, want, rtol=1e-12, atol=0)
 
 
+# ---------------------------------- S: depth slab (clamped front/back fragments)
+@pytest.mark.parametrize("slab", [(-0.5, 0.5), (-0.25, 0.1), (0.2, 0.45), (0.49, 0.7)])
+def test_s_undisplaced_lattice_slab_is_its_thickness(slab):
+    # z-view: depth t = z - 1/2 and the lattice fills t in [-1/2, 1/2]; every
+    # ray's chord inside the slab is its overlap with that range, at rho = M
+    n, M = 4, 3.0
+    view = dict(W.z_view(16, 12), slab=slab)
+    img, _ = O.project_region(*W.undisplaced(n), (n, n, n), view, total_mass=M)
+    want = M * max(0.0, min(slab[1], 0.5) - max(slab[0], -0.5))
+    np.testing.assert_allclose(img, want, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("slab", [(-0.3, 0.2), (0.0, 0.05), (-0.6, -0.2)])
+def test_s_z_only_layers_slab_closed_form(slab):
+    # flat layers k from z_k to z_k + dz_k (unwrapped from the cube's corner 0,
+    # dz_k < 0 for inverted ones) at rho_k = M / (n |dz_k|): the slab keeps
+    # the part of each layer with z - 1/2 in [s0, s1]
+    n, M, A = 8, 2.0, 0.3
+    q = W.lattice_q(n)
+    x = q[:, 0].astype(np.float32)
+    y = q[:, 1].astype(np.float32)
+    z = W.wrap_to_f32(q[:, 2] + A * np.sin(2 * np.pi * q[:, 2]), 1.0)
+    zk = z.reshape(n, n, n)[:, 0, 0].astype(np.float64)
+    dz = np.roll(zk, -1) - zk
+    dz -= np.ceil(dz - 0.5)
+    lo, hi = np.minimum(zk, zk + dz) - 0.5, np.maximum(zk, zk + dz) - 0.5
+    overlap = np.clip(np.minimum(hi, slab[1]) - np.maximum(lo, slab[0]), 0.0, None)
+    want = (M / (n * np.abs(dz)) * overlap).sum()
+    view = dict(W.z_view(16, 12), slab=slab)
+    img, _ = O.project_region(x, y, z, (n, n, n), view, total_mass=M)
+    np.testing.assert_allclose(img, want, rtol=1e-12, atol=1e-14)
+
+
+def test_s_slabs_partition_the_projection():
+    # slabs that tile the depth axis add up to the unclipped projection, and
+    # one slab around everything is the unclipped projection
+    n = 8
+    xyz = W.zeldovich(n, 3, 4.0, seed=9)
+    R = W.random_rotations(1, seed=17)[0]
+    view = W.rotated_view(R, 48, 40)
+    full, st = O.project_region(*xyz, (n, n, n), view)
+    cuts = np.linspace(-1.5, 1.5, 7)
+    parts = [O.project_region(*xyz, (n, n, n), dict(view, slab=(a, b)))[0] for a, b in zip(cuts[:-1], cuts[1:])]
+    np.testing.assert_allclose(sum(parts), full, rtol=0, atol=1e-12 * np.abs(full).max())
+    assert all((p >= 0).all() for p in parts) and sum(p.sum() > 0 for p in parts) >= 3
+    whole, _ = O.project_region(*xyz, (n, n, n), dict(view, slab=(-10.0, 10.0)))
+    np.testing.assert_array_equal(whole, full)
+
+
 def test_c4_near_degenerate_tets():
     # z = q_z - A sin(2 pi q_z + phi): the first cell layer has thickness
     # 1/n - 2 A sin(pi/n) = delta/n for A = (1 - delta)/(2 n sin(pi/n)),

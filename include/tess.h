@@ -110,6 +110,12 @@ typedef struct {
                                lengths along screen u and v                      */
     int32_t quantity;       /* projected per-tetrahedron value q (tess_quantity);
                                0, the zero-initialised default, is the density   */
+    int32_t slab;           /* 1: only the part of each chord at depths t in
+                               [slab_t[0], slab_t[1]] counts (the slab-clamped
+                               fragments of the resampling section, Eqs.
+                               Eqn:ResFF, Eqn:ResBF); t = third row of rot times
+                               (x - center). Stacking slabs resamples the volume */
+    double slab_t[2];       /* slab_t[0] < slab_t[1], finite, when slab = 1      */
 } tess_view;
 
 /* The constant per-tetrahedron value q of Eq. Eqn:TetProjection, with

@@ -37,7 +37,8 @@ class TessView(ctypes.Structure):
     _fields_ = [("rot", ctypes.c_double * 9), ("center", ctypes.c_double * 3),
                 ("extent", ctypes.c_double * 2), ("width", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("wrap", ctypes.c_int32),
-                ("quantity", ctypes.c_int32)]
+                ("quantity", ctypes.c_int32), ("slab", ctypes.c_int32),
+                ("slab_t", ctypes.c_double * 2)]
 
 # tess_quantity by name (view["quantity"], default "density")
 QUANTITIES = {"density": 0, "unit": 1, "density2": 2}
@@ -176,7 +177,8 @@ def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
 
 def make_view(view: Dict) -> TessView:
     """Converts a view dict (rot, center, extent, width, height, wrap, optional
-    quantity: "density", "unit" or "density2") to the C struct."""
+    quantity: "density", "unit" or "density2", optional slab: (t0, t1)) to the
+    C struct."""
     v = TessView()
     for i in range(9):
         v.rot[i] = float(view["rot"][i])
@@ -186,6 +188,10 @@ def make_view(view: Dict) -> TessView:
     v.width, v.height = int(view["width"]), int(view["height"])
     v.wrap = 1 if view.get("wrap", 0) else 0
     v.quantity = QUANTITIES[view.get("quantity", "density")]
+    slab = view.get("slab")
+    v.slab = 1 if slab is not None else 0
+    if slab is not None:
+        v.slab_t[0], v.slab_t[1] = float(slab[0]), float(slab[1])
     return v
 
 

@@ -167,6 +167,9 @@ extern "C" tess_status tess_check_view(const tess_view *v, const tess_build_desc
     if (v->quantity != TESS_QUANTITY_DENSITY && v->quantity != TESS_QUANTITY_UNIT &&
         v->quantity != TESS_QUANTITY_DENSITY2)
         return fail(TESS_EINVAL, "quantity must be 0 (density), 1 (unit) or 2 (density^2)");
+    if (v->slab != 0 && v->slab != 1) return fail(TESS_EINVAL, "slab must be 0 or 1");
+    if (v->slab && !(std::isfinite(v->slab_t[0]) && std::isfinite(v->slab_t[1]) && v->slab_t[0] < v->slab_t[1]))
+        return fail(TESS_EINVAL, "slab needs finite slab_t[0] < slab_t[1]");
     if (v->wrap) {
         int axis[2];
         for (int r = 0; r < 2; ++r) {
@@ -325,8 +328,11 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     vp.qsum = nullptr;
     vp.bmax_per_q = vp.inv_du * vp.inv_dv / ((double)v->width * (double)v->height) * (64.0 / (double)v->width);
     if (vp.qpow == 2) vp.crease_bmax *= lp.tet_mass / lp.v0;
-    // q / rho needs |V| to full precision
-    if (vp.qpow != 1) lp.det_cond_k = -1.0;
+    vp.slab = v->slab;
+    vp.slab_t[0] = v->slab ? v->slab_t[0] : 0.0;
+    vp.slab_t[1] = v->slab ? v->slab_t[1] : 0.0;
+    // q / rho needs |V| to full precision (the face form stores q itself)
+    if (vp.qpow != 1 || vp.slab) lp.det_cond_k = -1.0;
 }
 
 struct Plan {
@@ -385,6 +391,8 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.seg_len = (int32_t)seg_len;
     B.nseg = (int32_t)std::max<int64_t>(1, (g.ntet + seg_len - 1) / seg_len);
     B.ntet = (uint32_t)g.ntet;
+    B.slab_t[0] = g.vp.slab_t[0];
+    B.slab_t[1] = g.vp.slab_t[1];
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
     return TESS_OK;
@@ -417,7 +425,7 @@ tess_status ensure_back(Workspace &ws, const Geometry &g, int chunk, unsigned lo
 // Setup of one image; for q = 1 first the integral of q into slot->qsum.
 tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipStream_t s) {
     ViewParams vp = g.vp;
-    if (vp.qpow == 0) {
+    if (vp.qpow == 0 && !vp.slab) {
         TESS_HIP(launch_zero(&slot->qsum, 1, s));
         TESS_HIP(launch_qsum(g.lp, vp, &slot->qsum, s));
         vp.qsum = &slot->qsum;

@@ -36,6 +36,8 @@ struct ViewParams {
     // integral of q over all tetrahedra (k_qsum); null otherwise
     const double *qsum;
     double bmax_per_q;
+    int32_t slab;            // 1: only depths in [slab_t[0], slab_t[1]] count (face form)
+    double slab_t[2];        // depth t = third view coordinate, R (x - c)
 };
 
 // Screen tiling: tiles of Th rows x Tw columns (a row band when Tw >= W).
@@ -47,6 +49,7 @@ struct BinParams {
     int32_t seg_len;         // tetrahedra per binning segment
     int32_t nseg;
     uint32_t ntet;           // number of records
+    double slab_t[2];        // depth slab of face-form records (the view's)
 };
 
 // Per-call device counters (atomically accumulated).
@@ -82,6 +85,11 @@ struct WorkItem {
 //    in cyclic order (x in c[0..3], y in c[4..7]), the apex (c[8], c[9]) and
 //    the x slope b of the face over edge (V_k, V_k+1) in c[10 + k];
 //  - line form: (a, b, c) of the G functions, then of the walls, in c[0..11];
+//  - face form (REC_FACE; views with a depth slab): per face g, c[3g..3g+2]
+//    hold its depth plane t = c0 + c1 x + c2 y (world depth over pixel
+//    coordinates; front or back face) or, for a wall, its half-plane as in
+//    the line form; c[12] the projected value q. The record's f(p) is q
+//    times the chord inside the tetrahedron and the slab;
 // the payload's last 16 bytes repeat the head.
 struct RecHead {
     uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
@@ -101,6 +109,10 @@ constexpr uint32_t REC_TIE0 = 1u << 5;        // wall 0 keeps pixels on its line
 constexpr uint32_t REC_TIE1 = 1u << 6;        // wall 1 keeps pixels on its line
 constexpr uint32_t REC_VALID = 1u << 7;       // some pixel centre may be covered
 constexpr uint32_t REC_CREASE = 1u << 8;      // payload in crease form
+constexpr uint32_t REC_FACE = 1u << 9;        // payload in face form (depth slab)
+constexpr uint32_t REC_FACE_TYPE_SHIFT = 10;  // face g: 2 bits at 10 + 2 g
+constexpr uint32_t REC_FACE_TIE_SHIFT = 18;   // face g's wall keeps pixels on its line
+constexpr uint32_t REC_FACE_FRONT = 1u, REC_FACE_BACK = 2u, REC_FACE_WALL = 3u;
 
 struct alignas(128) Payload {
     double c[14];

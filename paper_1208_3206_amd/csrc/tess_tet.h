@@ -214,15 +214,65 @@ TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const
     return true;
 }
 
+// Face form of a tetrahedron (views with a depth slab): per face g its depth
+// plane t = c0 + c1 x + c2 y through the projected vertices (q, T: pixel
+// coordinates relative to the record origin, world depths), marked front
+// when the opposite vertex lies behind it (the ray enters there) and back
+// otherwise; a face seen edge-on is a wall, stored and tied as in the line
+// form. qv is the projected value q. Returns false when the tetrahedron lies
+// outside the slab or its projection is degenerate.
+TESS_HD inline bool face_payload(const double qx[4], const double qy[4], const double T[4], double s0,
+                                 double s1, double qv, double out[14], uint32_t &flags) {
+    if (fmax(fmax(T[0], T[1]), fmax(T[2], T[3])) <= s0 || fmin(fmin(T[0], T[1]), fmin(T[2], T[3])) >= s1)
+        return false;
+    uint32_t fl = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int b = kFace[a][0], c = kFace[a][1], d = kFace[a][2];
+        const double ex = qx[c] - qx[b], ey = qy[c] - qy[b];
+        const double fx = qx[d] - qx[b], fy = qy[d] - qy[b];
+        const double D = ex * fy - ey * fx;
+        if (D == 0.0) {
+            // the longest of the three sides carries the wall's line
+            int s = b, t = c;
+            double best = ex * ex + ey * ey;
+            const double lbd = fx * fx + fy * fy;
+            const double lcd = (qx[d] - qx[c]) * (qx[d] - qx[c]) + (qy[d] - qy[c]) * (qy[d] - qy[c]);
+            if (lbd > best) { best = lbd; s = b; t = d; }
+            if (lcd > best) { best = lcd; s = c; t = d; }
+            const double dx = qx[t] - qx[s], dy = qy[t] - qy[s];
+            const double side = dx * (qy[a] - qy[s]) - dy * (qx[a] - qx[s]);
+            if (side == 0.0) return false;  // all four collinear
+            const double sg = side > 0 ? 1.0 : -1.0;
+            out[3 * a + 0] = sg * (dy * qx[s] - dx * qy[s]);
+            out[3 * a + 1] = -sg * dy;
+            out[3 * a + 2] = sg * dx;
+            const double ou = sg * dy, ov = -sg * dx;
+            if (ou < 0 || (ou == 0 && ov < 0)) fl |= 1u << (REC_FACE_TIE_SHIFT + a);
+            fl |= REC_FACE_WALL << (REC_FACE_TYPE_SHIFT + 2 * a);
+        } else {
+            const double et = T[c] - T[b], ft = T[d] - T[b];
+            const double c1 = (et * fy - ey * ft) / D, c2 = (ex * ft - et * fx) / D;
+            const double c0 = T[b] - c1 * qx[b] - c2 * qy[b];
+            const double side = T[a] - (c0 + c1 * qx[a] + c2 * qy[a]);
+            if (side == 0.0) return false;
+            out[3 * a + 0] = c0;
+            out[3 * a + 1] = c1;
+            out[3 * a + 2] = c2;
+            fl |= (side > 0.0 ? REC_FACE_FRONT : REC_FACE_BACK) << (REC_FACE_TYPE_SHIFT + 2 * a);
+        }
+    }
+    out[12] = qv;
+    out[13] = 0.0;
+    flags = fl;
+    return true;
+}
+
 // Counters of one lattice cube's setup.
 struct CubeCounts {
     unsigned n_tets = 0, n_zero = 0, n_inv = 0, n_dets = 0, n_deg = 0;
 };
 
-// Setup of the six tetrahedra of lattice cube `cube`: gather and unwrap the
-// corners, volume determinant with its FP64 fallback, footprint.  head[t] and
-// coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
-// cover no pixel centre).
 // The eight corners of a lattice cube: corner 0's position X0 and every
 // corner's offset e[n] from it, unwrapped to the nearest periodic image.
 TESS_HD inline void cube_corners(const LatticeParams &L, int64_t cube, double X0[3], double e[8][3]) {
@@ -279,6 +329,10 @@ TESS_HD inline double cube_qvol(const LatticeParams &L, const ViewParams &V, int
     return sum;
 }
 
+// Setup of the six tetrahedra of lattice cube `cube`: gather and unwrap the
+// corners, volume determinant with its FP64 fallback, footprint.  head[t] and
+// coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
+// cover no pixel centre).
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
                                Payload coef[6], CubeCounts &cnt) {
     double X0[3], e[8][3];
@@ -288,6 +342,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     const double crease_bmax = V.qsum ? *V.qsum * V.bmax_per_q : V.crease_bmax;
     // projected corners in pixel units
     const double b0[3] = {X0[0] - V.center[0], X0[1] - V.center[1], X0[2] - V.center[2]};
+    const double Tc = V.rot[6] * b0[0] + V.rot[7] * b0[1] + V.rot[8] * b0[2];  // depth of corner 0
     double PX0 = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
     double PY0 = (V.rot[3] * b0[0] + V.rot[4] * b0[1] + V.rot[5] * b0[2] - V.v_bottom) * V.inv_dv;
     if (V.wrap) {  // a periodic image: move corner 0 into the first period
@@ -366,9 +421,29 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             qx[m] = PX[vi[m]] - (double)ix0;
             qy[m] = PY[vi[m]] - (double)iy0;
         }
+        const double rho_m = 6.0 / fabs(det6);  // rho / m
+        if (V.slab) {
+            // depth slab: the face form, q times the clipped chord
+            double T[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                T[m] = Tc + V.rot[6] * e[vi[m]][0] + V.rot[7] * e[vi[m]][1] + V.rot[8] * e[vi[m]][2];
+            const double rho = L.tet_mass * rho_m;
+            const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
+            uint32_t ff = 0;
+            if (!face_payload(qx, qy, T, V.slab_t[0], V.slab_t[1], qv, coef[t].c, ff)) {
+#pragma unroll
+                for (int g = 0; g < 14; ++g) coef[t].c[g] = 0.0;
+                continue;
+            }
+            R.bx = pack_range(ix0, ix1);
+            R.by = pack_range(iy0, iy1);
+            R.flags = ff | REC_FACE | REC_VALID;
+            coef[t].h = R;
+            continue;
+        }
         // q dl = (q / rho) rho dl: the density footprint with its mass scaled
         // by rho^(qpow - 1), rho = 6 m / |6V|
-        const double rho_m = 6.0 / fabs(det6);  // rho / m
         const double qscale = V.qpow == 1 ? 1.0 : (V.qpow == 0 ? 1.0 / (L.tet_mass * rho_m) : L.tet_mass * rho_m);
         Footprint fp;
         if (!footprint(qx, qy, V.mass_px * qscale, fp)) continue;
@@ -829,12 +904,203 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
     return frags > 0 ? (uint32_t)frags : 0u;
 }
 
+// ------------------------------------------------- face form (depth slab)
+// Upper envelope (maximum) of nl <= 4 lines a[i] + b[i] u, left to right:
+// piece k follows line idx[k] up to brk[k] (the last brk is +inf). Returns
+// the number of pieces.
+TESS_HD inline int upper_envelope(const double a[4], const double b[4], int nl, int idx[4], double brk[4]) {
+    int o[4] = {0, 1, 2, 3};
+    // by slope, ascending; equal slopes: the higher line first
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 4; ++j)
+            if (j < nl && (b[o[j]] < b[o[i]] || (b[o[j]] == b[o[i]] && a[o[j]] > a[o[i]]))) {
+                const int t = o[i];
+                o[i] = o[j];
+                o[j] = t;
+            }
+    int ns = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= nl) break;
+        const int l = o[q];
+        if (ns > 0 && b[idx[ns - 1]] == b[l]) continue;  // parallel and not higher
+        while (ns >= 2) {
+            // l overtakes the top line before the top overtakes the one below it
+            const int t = idx[ns - 1], u = idx[ns - 2];
+            const double xt = (a[t] - a[l]) / (b[l] - b[t]);
+            const double xu = (a[u] - a[t]) / (b[t] - b[u]);
+            if (xt > xu) break;
+            --ns;
+        }
+        idx[ns++] = l;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < ns) brk[k] = k + 1 < ns ? (a[idx[k]] - a[idx[k + 1]]) / (b[idx[k + 1]] - b[idx[k]]) : kInf;
+    return ns;
+}
+
+// One row of a face-form record: q times the chord of the ray inside the
+// tetrahedron and the depth slab, t_out - t_in with t_in the largest front
+// face depth (and the slab's near depth), t_out the smallest back face depth
+// (and its far depth), clipped by the walls (A9 tie rule) and the image.
+// Everything is evaluated in the record frame X (small numbers: a steep
+// plane of an almost edge-on face keeps its precision); the tile's samples
+// are u = 0..n-1 at X = X0 + u, row centre Y; break points sit at their true
+// positions, pieces starting left of the image start at ulo. dep(j, v) takes
+// -2 <= j <= n + 1. Returns the tile's covered samples.
+template <typename Dep>
+TESS_HD inline uint32_t face_row(uint32_t flags, const double *cf, const BinParams &B, double X0,
+                                 double Y, int n, int jlo, double ulo, double uhi, Dep &&dep,
+                                 uint32_t &kinks) {
+    double fa[4], fb[4], ba[4], bb[4];
+    int nf = 0, nb = 0;
+    double uL = ulo, uR = uhi;  // tile frame
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const uint32_t type = (flags >> (REC_FACE_TYPE_SHIFT + 2 * g)) & 3u;
+        const double c0 = cf[3 * g], c1 = cf[3 * g + 1], c2 = cf[3 * g + 2];
+        if (type == REC_FACE_WALL) {
+            const bool tie = (flags >> (REC_FACE_TIE_SHIFT + g)) & 1u;
+            if (c1 == 0.0) {
+                const double wv = c0 + c2 * Y;
+                if (!(wv > 0.0 || (wv == 0.0 && tie))) return 0;
+            } else {
+                // admitted samples: W > 0 (or W == 0 with the tie bit)
+                const double uw = -(c0 + c2 * Y) / c1 - X0;
+                if (c1 > 0.0) uL = fmax(uL, (tie ? ceil(uw) : floor(uw) + 1.0) - 0.5);
+                else uR = fmin(uR, (tie ? floor(uw) : ceil(uw) - 1.0) + 0.5);
+            }
+        } else if (type == REC_FACE_FRONT && nf < 3) {
+            fa[nf] = c0 + c2 * Y;
+            fb[nf] = c1;
+            ++nf;
+        } else if (type == REC_FACE_BACK && nb < 3) {
+            // the lower envelope of the back faces is minus the upper one of -t
+            ba[nb] = -(c0 + c2 * Y);
+            bb[nb] = -c1;
+            ++nb;
+        }
+    }
+    if (nf == 0 || nb == 0) return 0;
+    fa[nf] = B.slab_t[0];
+    fb[nf] = 0.0;
+    ++nf;
+    ba[nb] = -B.slab_t[1];
+    bb[nb] = 0.0;
+    ++nb;
+    int fi[4], bi[4];
+    double fbr[4], bbr[4];
+    const int pf = upper_envelope(fa, fb, nf, fi, fbr);
+    const int pb = upper_envelope(ba, bb, nb, bi, bbr);
+    // segments of d = t_out - t_in over X, left to right, and where d > 0
+    // (one interval: d is concave)
+    double sA[8], sB[8], sE[8];
+    int ns = 0, i = 0, k = 0;
+    double zl = kInf, zr = -kInf;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        if (i >= pf || k >= pb) break;
+        const double A = -ba[bi[k]] - fa[fi[i]], Bs = -bb[bi[k]] - fb[fi[i]];
+        const double e = fmin(fbr[i], bbr[k]);
+        const double s0 = ns > 0 ? sE[ns - 1] : -kInf;
+        sA[ns] = A;
+        sB[ns] = Bs;
+        sE[ns] = e;
+        ++ns;
+        double lo = s0, hi = e;
+        if (Bs > 0.0) lo = fmax(lo, -A / Bs);
+        else if (Bs < 0.0) hi = fmin(hi, -A / Bs);
+        else if (!(A > 0.0)) hi = lo;
+        if (hi > lo) {
+            zl = fmin(zl, lo);
+            zr = fmax(zr, hi);
+        }
+        const bool ai = fbr[i] == e, ak = bbr[k] == e;
+        i += ai ? 1 : 0;
+        k += ak ? 1 : 0;
+    }
+    // the covered range, in X: d > 0, inside the walls and the image
+    const double L = fmax(zl, uL + X0), R = fmin(zr, uR + X0);
+    const double Lu = L - X0, Ru = R - X0;
+    if (!(ceil(Ru) - floor(Lu) > 1.0)) return 0;  // no sample in (L, R)
+    const double span = ceil(fmin(Ru, (double)n - 0.5)) - floor(fmax(Lu, -0.5)) - 1.0;
+    const double q = cf[12];
+    auto put = [&](double X, double J, double D) {
+        int j = (int)floor(X - X0) + 1;
+        j = j > jlo ? j : jlo;
+        j = j < n ? j : n;
+        const double v1 = J + D * (((double)j + X0) - X);
+        dep(j, v1);
+        dep(j + 1, D - v1);
+        ++kinks;
+    };
+    // the pieces that hold a sample (an integer u in (lo, hi]), left to
+    // right; each start is a step plus kink relative to the previous such
+    // piece, so a sub-pixel piece (a face seen almost edge-on, a flat sliver)
+    // becomes a step instead of two large kinks that cancel
+    bool have = false;
+    double pB = 0.0, pA = 0.0, last = L;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        if (t >= ns) break;
+        const double s0 = t > 0 ? sE[t - 1] : -kInf;
+        const double lo = fmax(s0, L), hi = fmin(sE[t], R);
+        if (!(floor(hi - X0) > floor(lo - X0))) continue;
+        const double A = sA[t], Bs = sB[t];
+        const double J = (A + Bs * lo) - (have ? pA + pB * lo : 0.0);
+        // at a zero crossing of d the first piece starts from 0
+        put(lo, (!have && lo == zl) ? 0.0 : q * J, q * (Bs - pB));
+        have = true;
+        pA = A;
+        pB = Bs;
+        last = hi;
+    }
+    // the end: d = 0 at a zero crossing, else the value at the clip
+    if (have) put(last, last == zr ? 0.0 : -q * (pA + pB * last), -q * pB);
+    return span > 0.0 ? (uint32_t)span : 0u;
+}
+
+// All rows of a face-form record in one tile (every periodic offset that
+// meets it).
+template <typename Dep>
+TESS_HD inline uint32_t face_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0,
+                                  int ty0, int n, int rows, Dep &&dep, uint32_t &spans, uint32_t &kinks) {
+    const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
+    const int by0 = range_lo(h.by), by1 = range_hi(h.by);
+    int kx0, kx1, ky0, ky1;
+    axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
+    const int jmin = -tx0;
+    const int jlo = jmin > -2 ? jmin : -2;
+    uint32_t frags = 0;
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        const int ylo = max(ty0, by0 - ky * B.H), yhi = min(ty0 + rows - 1, by1 - ky * B.H);
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
+            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            const double ulo = -(double)tx0 - 0.5, uhi = (double)(B.W - tx0) - 0.5;
+            for (int y = ylo; y <= yhi; ++y) {
+                const double Y = (double)(y + ky * B.H - by0) + 0.5;
+                const int row = y - ty0;
+                frags += face_row(h.flags, cf, B, X0, Y, n, jlo, ulo, uhi,
+                                  [&](int j, double v) { dep(row, j, v); }, kinks);
+                ++spans;
+            }
+        }
+    }
+    return frags;
+}
+
 // One record in one tile, in whichever form its payload has.
 template <typename Dep>
 TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const BinParams &B, int tx0,
                                       int ty0, int n, int rows, Dep &&dep, uint32_t &spans,
                                       uint32_t &kinks) {
     if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    if (h.flags & REC_FACE) return face_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
 }
 

@@ -136,6 +136,44 @@ def test_projected_quantity_in_a_batch(tess):
     assert_quantity_parity(imgs[1, 1].cpu().numpy(), ref, "density2", what="density2 batch image")
 
 
+@pytest.mark.parametrize("slab", [(-0.2, 0.15), (0.3, 0.9)])
+def test_depth_slab(tess, slab):
+    # the face form: chords clipped to a depth slab, z and rotated windows
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    views = [W.z_view(120, 88)] + [W.rotated_view(R, 96, 80) for R in W.random_rotations(2, seed=31)]
+    for view in views:
+        view = dict(view, slab=slab)
+        got, st = gpu_image(tess, xyz, (n, n, n), view)
+        ref, ost = O.project_region(*xyz, (n, n, n), view)
+        assert_parity(got, ref, what=f"slab {slab} 16^3 -> {view['width']}x{view['height']}")
+        assert st["tets"] == ost["tets"]
+
+
+def test_depth_slab_undisplaced_walls(tess):
+    n, M = 8, 3.0
+    got, _ = gpu_image(tess, W.undisplaced(n), (n, n, n), dict(W.z_view(40, 24), slab=(-0.3, 0.05)), total_mass=M)
+    np.testing.assert_allclose(got, M * 0.35, rtol=2e-7)
+
+
+def test_depth_slabs_resample_in_one_batch(tess):
+    # a stack of slabs (the resampling section's use) projected as one batch
+    # of views: the slabs add up to the unclipped projection
+    import torch
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=12)
+    lat = tess.build(*dev(xyz), (n, n, n))
+    view = W.z_view(96)
+    cuts = np.linspace(-1.0, 1.0, 17)
+    slabs = [dict(view, slab=(a, b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    imgs = tess.project_batch([lat], slabs)
+    full = tess.project(lat, view).double()
+    total = imgs[0].double().sum(dim=0)
+    torch.testing.assert_close(total, full, rtol=1e-6, atol=1e-6 * float(full.abs().max()))
+    ref, _ = O.project_region(*xyz, (n, n, n), slabs[7])
+    assert_parity(imgs[0, 7].cpu().numpy(), ref, what="slab 7 of 16 in a batch")
+
+
 def test_fp64_determinant_path(tess, tiny_lattice):
     view = W.z_view(128, 96)
     got, st = gpu_image(tess, tiny_lattice, (32, 32, 32), view, precision="fp64")

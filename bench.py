@@ -159,6 +159,50 @@ def run_batched(args, w, tess, W, torch):
     print(json.dumps(result), flush=True)
 
 
+def run_resample(args, w, tess, W, torch):
+    """Resampling to a grid: one lattice, a stack of depth slabs of z-views
+    (one tess_project_batch call); the slabs must add up to the unclipped
+    projection."""
+    dev = torch.device("cuda:0")
+    xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
+    lat = tess.build(*[torch.from_numpy(a).to(dev) for a in xyz], (w.n,) * 3, precision=args.precision)
+    views = W.slab_views(w.width, w.n)
+    out = torch.empty((1, len(views), w.height, w.width), dtype=torch.float32, device=dev)
+    _, st0 = tess.project_batch([lat], views, out=out, stats=True)
+    for _ in range(args.warmup):
+        tess.project_batch([lat], views, out=out)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        tess.project_batch([lat], views, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t_start) * 1e3 / args.steps
+    full = tess.project(lat, W.z_view(w.width)).double()
+    total = out[0].double().sum(dim=0)
+    add_err = float((total - full).abs().max() / full.abs().max())
+    cells = w.n * w.width * w.height
+    result = {
+        "metric": "grid cells/s resampling %d^3 -> %d^3 by depth slabs" % (w.n, w.width),
+        "value": cells / (ms * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Zel'dovich lattice, kmax %d, D %g)" % (w.kmax, w.growth[0]),
+        "config": {"workload": w.name, "lattice": w.n, "slabs": len(views), "image": [w.width, w.height],
+                   "tile": [st0["tile_rows"], st0["tile_cols"]]},
+        "tets_per_s_per_slab": w.tets * len(views) / (ms * 1e-3),
+        "fragments": st0["fragments"],
+        "slabs_sum_vs_projection_max_rel": add_err,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def spectral_upsample(xyz, n, r):
     """Zero-padded FFT upsampling of a periodic lattice's displacements by r
     (the non-learned control: exact for a field band-limited below n/2)."""
@@ -308,6 +352,9 @@ def main():
         return
     if w is W.LEARNED:
         run_learned(args, w, tess, W, torch)
+        return
+    if w is W.RESAMPLE:
+        run_resample(args, w, tess, W, torch)
         return
     t0 = time.perf_counter()
     xyz = W.zeldovich(w.n, w.kmax, w.growth[0])

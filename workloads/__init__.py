@@ -64,8 +64,10 @@ BATCHED = Workload("batched_128^3_8x64_to_512^2", 128, 32,
                    tuple(float(d) for d in range(1, 9)), 512, 512, n_views=64)
 LEARNED = Workload("learned_64^3_D5_to_2048^2", 64, 16, (5.0,), 2048, 2048)
 LEARNED_REF = Workload("learned_ref_256^3_D5_to_2048^2", 256, 16, (5.0,), 2048, 2048)
+# resampling: the mid field into 128 depth slabs of 128^2 (a 128^3 grid)
+RESAMPLE = Workload("resample_128^3_to_128^3", 128, 32, (5.0,), 128, 128)
 
-ALL = {w.name: w for w in (TINY, MID, STRESS, STRESS_4K, BATCHED, LEARNED, LEARNED_REF)}
+ALL = {w.name: w for w in (TINY, MID, STRESS, STRESS_4K, BATCHED, LEARNED, LEARNED_REF, RESAMPLE)}
 
 
 # --------------------------------------------------------------------------
@@ -230,6 +232,15 @@ def rotated_view(rot: np.ndarray, width: int, height: int | None = None,
     return dict(rot=np.asarray(rot, dtype=np.float64).ravel().tolist(),
                 center=[float(c) for c in center], extent=[side, side],
                 width=int(width), height=int(height), wrap=0)
+
+
+def slab_views(width: int, slabs: int, box: float = 1.0) -> List[Dict]:
+    """z-views of `slabs` equal depth slabs over the box, t = z - box/2 in
+    [-box/2, box/2), plus one slab below and one above (cubes are unwrapped
+    from their corner 0, so some reach past the box in z)."""
+    cuts = np.linspace(-0.5 * box, 0.5 * box, slabs + 1)
+    edges = [(-1.5 * box, cuts[0])] + list(zip(cuts[:-1], cuts[1:])) + [(cuts[-1], 1.5 * box)]
+    return [dict(z_view(width, width, box), slab=(float(a), float(b))) for a, b in edges]
 
 
 def workload_views(w: Workload) -> List[Dict]:

@@ -61,44 +61,46 @@ def parse():
                     help="projected per-tetrahedron value: rho, 1 or rho^2")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device twice (scale reference for HBM byte counters)")
-    ap.add_argument("--cpu-crop", type=int, default=12,
-                    help="edge (pixels) of the centred crop the oracle renders for the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="about how long the oracle's CPU-baseline sample runs")
     return ap.parse_args()
 
 
 def cpu_baseline(xyz, w, view, full_fragments: float):
     """The FP64 oracle on a bounded sample of the same workload (test harness code).
 
-    Two oracle runs: one pixel (the per-tetrahedron setup of all tetrahedra,
-    which a full image pays once) and a centred crop (setup plus the clip work
-    of the crop's fragments).  Full-image time = setup + (crop - setup) scaled
-    by the fragment ratio."""
+    A seeded random subset of the lattice's cubes (all six tetrahedra of each,
+    unwrapped as on the full lattice) projected onto the full image by the
+    oracle's tetrahedron-list entry (one thread).  Its time and fragments are
+    proportional to the tetrahedra, so the subset's tets/s is the oracle's
+    rate on the workload.  The subset is sized for about args.cpu_seconds."""
     import numpy as np
     import oracle
-    threads = oracle.default_threads()
-    c = w.width // 2
-    e = int(args.cpu_crop)
-    crop = (c - e // 2, c - e // 2, e, e)
-    t0 = time.perf_counter()
-    oracle.project_pixels(*xyz, (w.n,) * 3, view, np.array([c]), np.array([c]), nthreads=threads)
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    _, st = oracle.project_region(*xyz, (w.n,) * 3, view, crop=crop, nthreads=threads)
-    t_crop = time.perf_counter() - t0
-    frac = st["fragments"] / max(full_fragments, 1.0)
-    t_frag = max(t_crop - t_setup, 1e-9)
-    t_full = t_setup + t_frag / max(frac, 1e-30)
+    ncubes = w.n ** 3
+    mass = 1.0 / (6.0 * ncubes)
+    rng = np.random.default_rng(12083206)
+
+    def run(k):
+        cubes = rng.choice(ncubes, size=k, replace=False)
+        verts = np.concatenate([oracle.cube_tets(*xyz, (w.n,) * 3, int(c))[0] for c in cubes])
+        t0 = time.perf_counter()
+        _, st = oracle.project_tets(verts, mass, view)
+        return time.perf_counter() - t0, st, len(verts)
+
+    t_probe, _, _ = run(64)
+    k = int(min(max(64 * args.cpu_seconds / max(t_probe, 1e-3), 64), ncubes))
+    t, st, ntet = run(k)
     return {
-        "value": w.tets / t_full,
+        "value": ntet / t,
         "unit": "tets/s",
-        "cores": threads,
+        "cores": 1,
         "kind": "oracle",
-        "sample": (f"FP64 oracle: per-tet setup of all {w.tets} tets ({t_setup:.1f} s) and the "
-                   f"{e}x{e} crop at ({crop[0]},{crop[1]}) of the same image ({st['fragments']:.3e} "
-                   f"fragments, {t_crop:.1f} s); full image = setup + crop clip time scaled by "
-                   f"fragment count ({t_full:.0f} s)"),
-        "fragments_per_s": st["fragments"] / t_frag,
-        "seconds": t_setup + t_crop,
+        "sample": (f"FP64 oracle (tetrahedron-list entry, 1 thread): the {ntet} tetrahedra of {k} seeded "
+                   f"random cubes of the same lattice onto the full {w.width}x{w.height} image "
+                   f"({st['fragments']:.3e} fragments, {t:.1f} s); the full lattice would take "
+                   f"{w.tets * t / ntet:.0f} s"),
+        "fragments_per_s": st["fragments"] / t,
+        "seconds": t,
     }
 
 

@@ -168,6 +168,32 @@ def project_pixels(x, y, z, dims, view: Dict, px, py, box=(1.0, 1.0, 1.0), perio
     return out, st.as_dict()
 
 
+def splat_image(x, y, z, dims, view: Dict, box=(1.0, 1.0, 1.0), periodic: bool = True,
+                total_mass: float = 1.0) -> Tuple[np.ndarray, Dict[str, int]]:
+    """Centroid splatting of the lattice (FP64 image)."""
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    p = _problem(dims, view, box, periodic, total_mass)
+    out = np.empty((p.height, p.width), dtype=np.float64)
+    st = OrcStats()
+    rc = lib().orc_splat_image(ctypes.byref(p), _ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float),
+                               _ptr(z, ctypes.c_float), _ptr(out, ctypes.c_double), ctypes.byref(st))
+    _check(rc, "splat_image")
+    return out, st.as_dict()
+
+
+def splat_tets(verts, mass, view: Dict) -> Tuple[np.ndarray, Dict[str, int]]:
+    """Centroid splats of an explicit tetrahedron list, verts (T, 4, 3), mass (T,)."""
+    verts = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 4, 3)
+    mass = np.ascontiguousarray(np.broadcast_to(np.asarray(mass, dtype=np.float64), (verts.shape[0],)))
+    p = _problem((2, 2, 2), view)
+    out = np.empty((p.height, p.width), dtype=np.float64)
+    st = OrcStats()
+    rc = lib().orc_splat_tets(ctypes.byref(p), int(verts.shape[0]), _ptr(verts, ctypes.c_double),
+                              _ptr(mass, ctypes.c_double), _ptr(out, ctypes.c_double), ctypes.byref(st))
+    _check(rc, "splat_tets")
+    return out, st.as_dict()
+
+
 def project_tets(verts, mass, view: Dict) -> Tuple[np.ndarray, Dict[str, int]]:
     """Projection of an explicit tetrahedron list, verts (T, 4, 3) world, mass (T,)."""
     verts = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 4, 3)

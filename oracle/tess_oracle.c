@@ -290,6 +290,116 @@ int orc_cube_tets(const orc_problem *P, const float *x, const float *y, const fl
 /* Per-tet projection of an explicit list of tetrahedra (world vertices,
  * tet-major [T][4][3]) with per-tet masses; the lattice fields of P are
  * ignored.  out: H*W doubles, overwritten.  Serial, in list order. */
+/* ---------------------------------------------------- centroid splatting
+ * The centroid section's renderer: every tetrahedron T is drawn as a 2D
+ * cubic-spline kernel centred on its centroid c_T (the mean of its four
+ * vertices), of size h_T proportional to (m / rho_T)^(1/3) = |V(T)|^(1/3)
+ * (proportionality constant 1), carrying q(T) |V(T)| (its mass for q = rho):
+ *
+ *   I(p) += q |V| W(|p - c_T|, h),
+ *   W(r, h) = 10 / (7 pi h^2) * { 1 - 3/2 s^2 + 3/4 s^3   (0 <= s < 1)
+ *                               { 1/4 (2 - s)^3          (1 <= s < 2)
+ *                               { 0                       (s >= 2),  s = r / h,
+ *
+ * the 2D cubic spline normalised to a unit integral over the plane; p and c
+ * in view-plane world coordinates, point-sampled at pixel centres (with the
+ * pixel index modulo (W, H) under wrap).  fragments counts (pixel, T) with
+ * W > 0.  Plain loops over tetrahedra in id order, one thread. */
+static const double ORC_PI = 3.14159265358979323846;
+
+static double splat_w(double r, double h) {
+    const double s = r / h;
+    const double c = 10.0 / (7.0 * ORC_PI * h * h);
+    if (s < 1.0) return c * (1.0 - 1.5 * s * s + 0.75 * s * s * s);
+    if (s < 2.0) return c * 0.25 * (2.0 - s) * (2.0 - s) * (2.0 - s);
+    return 0.0;
+}
+
+static void splat_one(const orc_problem *P, const double v[4][3], double mass, double *out,
+                      double *comp, orc_stats *s) {
+    const double V = signed_volume(v);
+    if (V == 0.0) { s->zero_volume++; return; }
+    s->tets++;
+    if (V > 0) s->inverted++;
+    const double vol = fabs(V);
+    const double rho = mass / vol;
+    const double q = P->qpow == 0 ? 1.0 : (P->qpow == 1 ? rho : rho * rho);
+    const double h = cbrt(vol);
+    double cw[3] = {0, 0, 0};
+    for (int m = 0; m < 4; ++m)
+        for (int a = 0; a < 3; ++a) cw[a] += 0.25 * v[m][a];
+    const double d[3] = {cw[0] - P->center[0], cw[1] - P->center[1], cw[2] - P->center[2]};
+    const double cu = P->rot[0] * d[0] + P->rot[1] * d[1] + P->rot[2] * d[2];
+    const double cv = P->rot[3] * d[0] + P->rot[4] * d[1] + P->rot[5] * d[2];
+    const double du = P->extent[0] / P->width, dv = P->extent[1] / P->height;
+    const double ul = -0.5 * P->extent[0], vb = -0.5 * P->extent[1];
+    const int64_t ix0 = (int64_t)ceil((cu - 2 * h - ul) / du - 0.5), ix1 = (int64_t)floor((cu + 2 * h - ul) / du - 0.5);
+    const int64_t iy0 = (int64_t)ceil((cv - 2 * h - vb) / dv - 0.5), iy1 = (int64_t)floor((cv + 2 * h - vb) / dv - 0.5);
+    for (int64_t iy = iy0; iy <= iy1; ++iy) {
+        const int64_t ry = map_row(P, iy);
+        if (ry < 0) continue;
+        const double pv = pixel_v(P, iy);
+        for (int64_t ix = ix0; ix <= ix1; ++ix) {
+            const int64_t rx = map_col(P, ix);
+            if (rx < 0) continue;
+            const double pu = pixel_u(P, ix);
+            const double w = splat_w(sqrt((pu - cu) * (pu - cu) + (pv - cv) * (pv - cv)), h);
+            if (w > 0) {
+                s->fragments++;
+                neu_add(&out[ry * P->width + rx], &comp[ry * P->width + rx], q * vol * w);
+            }
+        }
+    }
+}
+
+int orc_splat_image(const orc_problem *P, const float *x, const float *y, const float *z, double *out,
+                    orc_stats *st) {
+    if (check_problem(P) != ORC_OK || !x || !y || !z || !out) return ORC_EINVAL;
+    const int64_t ncube = n_cubes(P);
+    const double mass = P->total_mass / (double)(6 * ncube);
+    const int64_t npx = (int64_t)P->width * P->height;
+    double *comp = (double *)calloc((size_t)npx, sizeof(double));
+    if (!comp) return ORC_ENOMEM;
+    memset(out, 0, sizeof(double) * (size_t)npx);
+    orc_stats s = {0, 0, 0, 0};
+    for (int64_t c = 0; c < ncube; ++c) {
+        double X[8][3];
+        cube_corners(P, x, y, z, c, X);
+        for (int t = 0; t < 6; ++t) {
+            double v[4][3];
+            for (int m = 0; m < 4; ++m)
+                for (int a = 0; a < 3; ++a) v[m][a] = X[TET_TABLE[t][m]][a];
+            splat_one(P, v, mass, out, comp, &s);
+        }
+    }
+    for (int64_t p = 0; p < npx; ++p) out[p] += comp[p];
+    free(comp);
+    if (st) *st = s;
+    return ORC_OK;
+}
+
+/* Splats of an explicit tetrahedron list (world vertices [T][4][3], masses). */
+int orc_splat_tets(const orc_problem *P, int64_t ntet, const double *verts, const double *mass,
+                   double *out, orc_stats *st) {
+    if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0) ||
+        P->qpow < 0 || P->qpow > 2 || ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out)
+        return ORC_EINVAL;
+    const int64_t npx = (int64_t)P->width * P->height;
+    double *comp = (double *)calloc((size_t)npx, sizeof(double));
+    if (!comp) return ORC_ENOMEM;
+    memset(out, 0, sizeof(double) * (size_t)npx);
+    orc_stats s = {0, 0, 0, 0};
+    for (int64_t t = 0; t < ntet; ++t) {
+        double v[4][3];
+        memcpy(v, verts + t * 12, sizeof(v));
+        splat_one(P, v, mass[t], out, comp, &s);
+    }
+    for (int64_t p = 0; p < npx; ++p) out[p] += comp[p];
+    free(comp);
+    if (st) *st = s;
+    return ORC_OK;
+}
+
 int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
                      const double *mass, double *out, orc_stats *st) {
     if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0) ||

@@ -269,6 +269,49 @@ def test_s_slabs_partition_the_projection():
     np.testing.assert_array_equal(whole, full)
 
 
+# ------------------------------------------ K: centroid splatting (approximate)
+def _splat_tet(scale=1.0, at=(0.5, 0.5)):
+    # a tetrahedron with |V| = scale^3 * 1e-3 / 6 * 6 = scale^3 * 1e-3 whose
+    # centroid projects onto (at) in a z-view of the unit box
+    e = 0.1 * scale * np.cbrt(6.0)
+    v = np.array([[0, 0, 0], [e, 0, 0], [0, e, 0], [0, 0, e]], dtype=np.float64)
+    v += np.array([at[0], at[1], 0.5]) - v.mean(axis=0)
+    return v
+
+
+def test_k_splat_carries_the_mass_within_two_h():
+    # h = |V|^(1/3) = 0.1 = 51.2 px at 512^2: the kernel's pixel sum is its
+    # integral (1) to well below 1e-6, so the image holds the mass m
+    view = W.z_view(512)
+    m = 0.37
+    v = _splat_tet(at=(0.5 + 0.3 / 512, 0.5 - 0.2 / 512))
+    img, st = O.splat_tets(v[None], m, view)
+    np.testing.assert_allclose(img.sum() / 512 ** 2, m, rtol=1e-6)
+    yy, xx = np.nonzero(img)
+    c = v.mean(axis=0)
+    r = np.hypot((xx + 0.5) / 512 - c[0], (yy + 0.5) / 512 - c[1])
+    assert r.max() < 0.2 and r.max() > 0.19 and st["fragments"] == len(xx)
+
+
+def test_k_splat_size_is_the_cube_root_of_the_volume():
+    # scaling the tetrahedron by s keeps the mass and divides the peak by s^2
+    view = W.z_view(256)
+    peaks = [O.splat_tets(_splat_tet(scale=s, at=(0.5 + 0.5 / 256, 0.5 + 0.5 / 256))[None], 1.0, view)[0].max()
+             for s in (1.0, 2.0)]
+    np.testing.assert_allclose(peaks[0] / peaks[1], 4.0, rtol=1e-12)
+
+
+def test_k_undisplaced_lattice_splats_around_the_column_density():
+    # periodic image: the mass is kept up to the point sampling of kernels
+    # with h = 4.4 px (a Riemann sum, ~1e-5); a uniform lattice of splats
+    # (h = |V|^(1/3), 0.55 of the lattice spacing) ripples around the
+    # uniform column density M by about 16 %
+    n, M = 8, 2.0
+    img, st = O.splat_image(*W.undisplaced(n), (n, n, n), W.z_view(64), total_mass=M)
+    np.testing.assert_allclose(img.mean(), M, rtol=1e-4)
+    assert np.abs(img / M - 1).max() < 0.2 and st["tets"] == 6 * n ** 3
+
+
 def test_c4_near_degenerate_tets():
     # z = q_z - A sin(2 pi q_z + phi): the first cell layer has thickness
     # 1/n - 2 A sin(pi/n) = delta/n for A = (1 - delta)/(2 n sin(pi/n)),

@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quantity", default="density", choices=["density", "unit", "density2"],
                     help="projected per-tetrahedron value: rho, 1 or rho^2")
+    ap.add_argument("--method", default="tessellation", choices=["tessellation", "centroids"],
+                    help="exact projection of the tessellation, or the centroid splats")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device twice (scale reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -84,7 +86,8 @@ def cpu_baseline(xyz, w, view, full_fragments: float):
         cubes = rng.choice(ncubes, size=k, replace=False)
         verts = np.concatenate([oracle.cube_tets(*xyz, (w.n,) * 3, int(c))[0] for c in cubes])
         t0 = time.perf_counter()
-        _, st = oracle.project_tets(verts, mass, view)
+        draw = oracle.splat_tets if view.get("method") == "centroids" else oracle.project_tets
+        _, st = draw(verts, mass, view)
         return time.perf_counter() - t0, st, len(verts)
 
     t_probe, _, _ = run(64)
@@ -362,7 +365,7 @@ def main():
     xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
     gen_s = time.perf_counter() - t0
     d = [torch.from_numpy(a).to(dev) for a in xyz]
-    view = dict(W.workload_views(w)[0], quantity=args.quantity)
+    view = dict(W.workload_views(w)[0], quantity=args.quantity, method=args.method)
     lat = tess.build(*d, (w.n,) * 3, precision=args.precision)
     out = torch.empty((w.height, w.width), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -407,7 +410,7 @@ def main():
         "data": "synthetic (seeded Zel'dovich lattice, kmax %d, D %g)" % (w.kmax, w.growth[0]),
         "config": {"workload": w.name, "lattice": w.n, "tets": w.tets, "image": [w.width, w.height],
                    "view": "z-projection, periodic", "determinant": args.precision,
-                   "quantity": args.quantity,
+                   "quantity": args.quantity, "method": args.method,
                    "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"],
                    "block": st["block"]},
         "fragments": frags,

@@ -116,7 +116,21 @@ typedef struct {
                                Eqn:ResFF, Eqn:ResBF); t = third row of rot times
                                (x - center). Stacking slabs resamples the volume */
     double slab_t[2];       /* slab_t[0] < slab_t[1], finite, when slab = 1      */
+    int32_t method;         /* tess_method; 0, the zero-initialised default, is
+                               the exact projection of the tessellation          */
+    int32_t reserved;       /* 0                                                  */
 } tess_view;
+
+/* How the tetrahedra are drawn.  TESS_METHOD_CENTROIDS is the centroid
+ * section's approximation: each tetrahedron T is a 2D cubic-spline kernel
+ * W(r, h) = 10 / (7 pi h^2) * {1 - 3/2 s^2 + 3/4 s^3 (s < 1), 1/4 (2 - s)^3
+ * (1 <= s < 2), 0}, s = r / h, at its projected centroid, with h = |V|^(1/3)
+ * (the paper's size proportional to (m / rho)^(1/3), constant 1), carrying
+ * q |V| (its mass for the density); not with a slab. */
+typedef enum {
+    TESS_METHOD_TESSELLATION = 0,
+    TESS_METHOD_CENTROIDS = 1
+} tess_method;
 
 /* The constant per-tetrahedron value q of Eq. Eqn:TetProjection, with
  * rho = m / |V| (Eq. Eqn-rho_loc): the density itself (column density), or the

@@ -38,7 +38,11 @@ class TessView(ctypes.Structure):
                 ("extent", ctypes.c_double * 2), ("width", ctypes.c_int32),
                 ("height", ctypes.c_int32), ("wrap", ctypes.c_int32),
                 ("quantity", ctypes.c_int32), ("slab", ctypes.c_int32),
-                ("slab_t", ctypes.c_double * 2)]
+                ("slab_t", ctypes.c_double * 2), ("method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+# tess_method by name (view["method"], default "tessellation")
+METHODS = {"tessellation": 0, "centroids": 1}
 
 # tess_quantity by name (view["quantity"], default "density")
 QUANTITIES = {"density": 0, "unit": 1, "density2": 2}
@@ -177,8 +181,8 @@ def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
 
 def make_view(view: Dict) -> TessView:
     """Converts a view dict (rot, center, extent, width, height, wrap, optional
-    quantity: "density", "unit" or "density2", optional slab: (t0, t1)) to the
-    C struct."""
+    quantity: "density", "unit" or "density2", optional slab: (t0, t1),
+    optional method: "tessellation" or "centroids") to the C struct."""
     v = TessView()
     for i in range(9):
         v.rot[i] = float(view["rot"][i])
@@ -192,6 +196,7 @@ def make_view(view: Dict) -> TessView:
     v.slab = 1 if slab is not None else 0
     if slab is not None:
         v.slab_t[0], v.slab_t[1] = float(slab[0]), float(slab[1])
+    v.method = METHODS[view.get("method", "tessellation")]
     return v
 
 

@@ -168,6 +168,11 @@ extern "C" tess_status tess_check_view(const tess_view *v, const tess_build_desc
         v->quantity != TESS_QUANTITY_DENSITY2)
         return fail(TESS_EINVAL, "quantity must be 0 (density), 1 (unit) or 2 (density^2)");
     if (v->slab != 0 && v->slab != 1) return fail(TESS_EINVAL, "slab must be 0 or 1");
+    if (v->method != TESS_METHOD_TESSELLATION && v->method != TESS_METHOD_CENTROIDS)
+        return fail(TESS_EINVAL, "method must be 0 (tessellation) or 1 (centroids)");
+    if (v->method == TESS_METHOD_CENTROIDS && v->slab)
+        return fail(TESS_EINVAL, "the centroid method takes no slab");
+    if (v->reserved != 0) return fail(TESS_EINVAL, "view.reserved must be 0");
     if (v->slab && !(std::isfinite(v->slab_t[0]) && std::isfinite(v->slab_t[1]) && v->slab_t[0] < v->slab_t[1]))
         return fail(TESS_EINVAL, "slab needs finite slab_t[0] < slab_t[1]");
     if (v->wrap) {
@@ -331,8 +336,10 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     vp.slab = v->slab;
     vp.slab_t[0] = v->slab ? v->slab_t[0] : 0.0;
     vp.slab_t[1] = v->slab ? v->slab_t[1] : 0.0;
-    // q / rho needs |V| to full precision (the face form stores q itself)
-    if (vp.qpow != 1 || vp.slab) lp.det_cond_k = -1.0;
+    vp.splat = v->method == TESS_METHOD_CENTROIDS ? 1 : 0;
+    // q / rho needs |V| to full precision (the face form stores q itself, a
+    // splat q |V| and |V|^(1/3))
+    if (vp.qpow != 1 || vp.slab || vp.splat) lp.det_cond_k = -1.0;
 }
 
 struct Plan {
@@ -393,6 +400,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.ntet = (uint32_t)g.ntet;
     B.slab_t[0] = g.vp.slab_t[0];
     B.slab_t[1] = g.vp.slab_t[1];
+    B.direct = g.vp.splat;
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
     return TESS_OK;
@@ -425,7 +433,7 @@ tess_status ensure_back(Workspace &ws, const Geometry &g, int chunk, unsigned lo
 // Setup of one image; for q = 1 first the integral of q into slot->qsum.
 tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipStream_t s) {
     ViewParams vp = g.vp;
-    if (vp.qpow == 0 && !vp.slab) {
+    if (vp.qpow == 0 && !vp.slab && !vp.splat) {
         TESS_HIP(launch_zero(&slot->qsum, 1, s));
         TESS_HIP(launch_qsum(g.lp, vp, &slot->qsum, s));
         vp.qsum = &slot->qsum;

@@ -38,6 +38,7 @@ struct ViewParams {
     double bmax_per_q;
     int32_t slab;            // 1: only depths in [slab_t[0], slab_t[1]] count (face form)
     double slab_t[2];        // depth t = third view coordinate, R (x - c)
+    int32_t splat;           // 1: centroid splats instead of the tessellation
 };
 
 // Screen tiling: tiles of Th rows x Tw columns (a row band when Tw >= W).
@@ -50,6 +51,7 @@ struct BinParams {
     int32_t nseg;
     uint32_t ntet;           // number of records
     double slab_t[2];        // depth slab of face-form records (the view's)
+    int32_t direct;          // 1: the accumulator holds values (splats), not second differences
 };
 
 // Per-call device counters (atomically accumulated).
@@ -90,6 +92,9 @@ struct WorkItem {
 //    coordinates; front or back face) or, for a wall, its half-plane as in
 //    the line form; c[12] the projected value q. The record's f(p) is q
 //    times the chord inside the tetrahedron and the slab;
+//  - splat (REC_SPLAT; the centroid method): centroid (c[0], c[1]), the
+//    kernel's s per pixel along x and y (c[2], c[3]) and its peak amplitude
+//    q |V| 10 / (7 pi h^2) (c[4]); deposited as values, not differences;
 // the payload's last 16 bytes repeat the head.
 struct RecHead {
     uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
@@ -113,6 +118,7 @@ constexpr uint32_t REC_FACE = 1u << 9;        // payload in face form (depth sla
 constexpr uint32_t REC_FACE_TYPE_SHIFT = 10;  // face g: 2 bits at 10 + 2 g
 constexpr uint32_t REC_FACE_TIE_SHIFT = 18;   // face g's wall keeps pixels on its line
 constexpr uint32_t REC_FACE_FRONT = 1u, REC_FACE_BACK = 2u, REC_FACE_WALL = 3u;
+constexpr uint32_t REC_SPLAT = 1u << 22;      // payload is a centroid splat
 
 struct alignas(128) Payload {
     double c[14];

@@ -500,6 +500,11 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *__restrict
     const int y = blockIdx.x;
     const double *row = acc + (int64_t)y * B.W;
     float *out = image + (int64_t)y * B.W;
+    if (B.direct) {
+        // splats: the accumulator holds the values themselves
+        for (int i = threadIdx.x; i < B.W; i += kFinBlock) out[i] = (float)fmax(row[i], 0.0);
+        return;
+    }
     const int per = (B.W + kFinBlock - 1) / kFinBlock;  // consecutive entries per thread
     const int i0 = threadIdx.x * per;
     // pass 1: d1 = running sum of A; the thread keeps its entries' d1 sum and

@@ -17,6 +17,8 @@ namespace tess {
 constexpr int kTet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4},
                                        {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
 
+constexpr double kPi = 3.14159265358979323846;
+
 // Face a of a tetrahedron is the one opposite vertex a; its vertices in
 // increasing order.
 constexpr int kFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
@@ -396,6 +398,41 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         ++cnt.n_tets;
         cnt.n_inv += det6 > 0 ? 1 : 0;
         cnt.n_deg += fabs(det6) < 6.0 * L.det_v0_frac * L.v0 ? 1 : 0;
+        if (V.splat) {
+            // the centroid method: a kernel of size h = |V|^(1/3) at the
+            // projected centroid, carrying q |V|
+            const double vol = fabs(det6) / 6.0;
+            const double hh = cbrt(vol);
+            const double rho = L.tet_mass * 6.0 / fabs(det6);
+            const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
+            double cxp = 0.0, cyp = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int vm = kTet[t][m];
+                cxp += 0.25 * PX[vm];
+                cyp += 0.25 * PY[vm];
+            }
+            const double rx = 2.0 * hh * V.inv_du, ry = 2.0 * hh * V.inv_dv, lim = 1.0e8;
+            int sx0 = (int)fmax(ceil(cxp - rx - 0.5), -lim), sx1 = (int)fmin(floor(cxp + rx - 0.5), lim);
+            int sy0 = (int)fmax(ceil(cyp - ry - 0.5), -lim), sy1 = (int)fmin(floor(cyp + ry - 0.5), lim);
+            if (!V.wrap) {
+                sx0 = sx0 > 0 ? sx0 : 0;
+                sy0 = sy0 > 0 ? sy0 : 0;
+                sx1 = sx1 < V.W - 1 ? sx1 : V.W - 1;
+                sy1 = sy1 < V.H - 1 ? sy1 : V.H - 1;
+            }
+            if (sx0 > sx1 || sy0 > sy1) continue;
+            coef[t].c[0] = cxp - (double)sx0;
+            coef[t].c[1] = cyp - (double)sy0;
+            coef[t].c[2] = 1.0 / (hh * V.inv_du);
+            coef[t].c[3] = 1.0 / (hh * V.inv_dv);
+            coef[t].c[4] = qv * vol * (10.0 / (7.0 * kPi * hh * hh));
+            R.bx = pack_range(sx0, sx1);
+            R.by = pack_range(sy0, sy1);
+            R.flags = REC_SPLAT | REC_VALID;
+            coef[t].h = R;
+            continue;
+        }
         // ---- screen footprint (FP64)
         const int vi[4] = {v0, v1, v2, v3};
         double xmin = PX[v0], xmax = PX[v0], ymin = PY[v0], ymax = PY[v0];
@@ -1094,6 +1131,50 @@ TESS_HD inline uint32_t face_pair(const RecHead &h, const double *cf, const BinP
     return frags;
 }
 
+// ------------------------------------------------------ centroid splats
+// A splat record's kernel values at the tile's pixel centres (every periodic
+// offset that meets it), added as values: dep(row, u, w) for the tile column
+// u. Returns the covered samples (W > 0); kinks counts the samples evaluated.
+template <typename Dep>
+TESS_HD inline uint32_t splat_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0, int ty0,
+                                   int n, int rows, Dep &&dep, uint32_t &spans, uint32_t &kinks) {
+    const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx);
+    const int by0 = range_lo(h.by), by1 = range_hi(h.by);
+    int kx0, kx1, ky0, ky1;
+    axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
+    const double cx = cf[0], cy = cf[1], sx = cf[2], sy = cf[3], amp = cf[4];
+    uint32_t frags = 0;
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        const int ylo = max(ty0, by0 - ky * B.H), yhi = min(ty0 + rows - 1, by1 - ky * B.H);
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            const int ulo = max(0, bx0 - kx * B.W - tx0), uhi = min(n - 1, bx1 - kx * B.W - tx0);
+            if (ulo > uhi) continue;
+            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            for (int y = ylo; y <= yhi; ++y) {
+                const double dy = ((double)(y + ky * B.H - by0) + 0.5 - cy) * sy;
+                if (!(dy * dy < 4.0)) continue;
+                const int row = y - ty0;
+                ++spans;
+                // the row's chord of the support circle (one column of margin)
+                const double half = sqrt(4.0 - dy * dy) / sx;
+                const int u0 = max(ulo, (int)floor(cx - half - X0)), u1 = min(uhi, (int)ceil(cx + half - X0));
+                for (int u = u0; u <= u1; ++u) {
+                    const double dx = (X0 + (double)u - cx) * sx;
+                    const double q = sqrt(dx * dx + dy * dy);
+                    ++kinks;
+                    if (!(q < 2.0)) continue;
+                    const double t = 2.0 - q;
+                    const double w = q < 1.0 ? 1.0 - 1.5 * q * q + 0.75 * q * q * q : 0.25 * t * t * t;
+                    dep(row, u, amp * w);
+                    ++frags;
+                }
+            }
+        }
+    }
+    return frags;
+}
+
 // One record in one tile, in whichever form its payload has.
 template <typename Dep>
 TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const BinParams &B, int tx0,
@@ -1101,6 +1182,7 @@ TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const 
                                       uint32_t &kinks) {
     if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     if (h.flags & REC_FACE) return face_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    if (h.flags & REC_SPLAT) return splat_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
 }
 

@@ -17,8 +17,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                            int32_t periodic, double total_mass, int32_t precision, const double rot[9],
                            const double center[3], const double extent[2], int32_t W, int32_t H,
                            int32_t wrap, int32_t tile_rows, int32_t tile_cols, int32_t chunk,
-                           double crease_div, int32_t qpow, const double *slab, double *out64,
-                           float *out32,
+                           double crease_div, int32_t qpow, const double *slab, int32_t splat,
+                           double *out64, float *out32,
                            long long *stats /* [tets, zero, inverted, fp64_dets, fragments, spans,
                                                pairs, items, crease_records] */) {
     LatticeParams L;
@@ -34,7 +34,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     L.tet_mass = total_mass / (6.0 * (double)L.ncubes);
     L.v0 = 1.0 / (6.0 * (double)L.ncubes);
     L.det_v0_frac = 1e-6;
-    L.det_cond_k = (precision || qpow != 1 || slab) ? -1.0 : 1e3;
+    L.det_cond_k = (precision || qpow != 1 || slab || splat) ? -1.0 : 1e3;
     ViewParams V;
     for (int i = 0; i < 9; ++i) V.rot[i] = rot[i];
     for (int i = 0; i < 3; ++i) V.center[i] = center[i];
@@ -46,6 +46,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.crease_bmax = crease_div > 0 ? V.mass_px * (double)L.ncubes / ((double)W * H) / crease_div : -1.0;
     V.W = W; V.H = H; V.wrap = wrap; V.qpow = qpow;
     V.slab = slab ? 1 : 0;
+    V.splat = splat;
     V.slab_t[0] = slab ? slab[0] : 0.0;
     V.slab_t[1] = slab ? slab[1] : 0.0;
     // q != rho: the crease threshold from the integral of q (as the library)
@@ -53,7 +54,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.qsum = nullptr;
     V.bmax_per_q = crease_div > 0 ? V.inv_du * V.inv_dv / ((double)W * H) / crease_div : -1.0;
     if (qpow == 2) V.crease_bmax *= L.tet_mass / L.v0;
-    if (qpow == 0 && !slab) {
+    if (qpow == 0 && !slab && !splat) {
         for (int64_t cube = 0; cube < L.ncubes; ++cube) qsum += cube_qvol(L, V, cube);
         V.qsum = &qsum;
     }
@@ -78,6 +79,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     B.ntet = (uint32_t)ntet;
     B.slab_t[0] = V.slab_t[0];
     B.slab_t[1] = V.slab_t[1];
+    B.direct = splat;
     const int ntiles = B.ntx * B.nty;
     std::vector<std::vector<uint32_t>> lists(ntiles);
     for (int64_t id = 0; id < ntet; ++id) {
@@ -117,7 +119,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         double d1 = 0.0, f = 0.0;
         for (int ix = 0; ix < W; ++ix) {
             d1 += acc[(size_t)iy * W + ix];
-            f += d1;
+            f = splat ? acc[(size_t)iy * W + ix] : f + d1;
             if (out64) out64[(size_t)iy * W + ix] = f;
             if (out32) out32[(size_t)iy * W + ix] = (float)std::fmax(f, 0.0);
         }

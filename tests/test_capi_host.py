@@ -93,6 +93,16 @@ def test_view_validation(tess):
     v = tess.make_view(W.z_view(64))
     v.quantity = 3
     assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
+    # drawing methods, and no slab with centroids
+    tess.check_view(dict(W.z_view(64), method="centroids"), d)
+    for bad in (dict(W.z_view(64), method="centroids", slab=(0.0, 0.1)),):
+        with pytest.raises(tess.TessError):
+            tess.check_view(bad, d)
+    v = tess.make_view(W.z_view(64))
+    v.method = 2
+    assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
+    v.method, v.reserved = 0, 1
+    assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
     # depth slabs: finite and ordered
     tess.check_view(dict(W.z_view(64), slab=(-0.1, 0.2)), d)
     for bad in ((0.2, 0.2), (0.3, -0.1), (float("nan"), 0.1), (-float("inf"), 0.0)):

@@ -174,6 +174,24 @@ def test_depth_slabs_resample_in_one_batch(tess):
     assert_parity(imgs[0, 7].cpu().numpy(), ref, what="slab 7 of 16 in a batch")
 
 
+def test_centroid_splats(tess, tiny_lattice):
+    # the centroid method against the oracle's splats: z (wrap) and rotated
+    # windows, and the density squared
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    views = [W.z_view(120, 88), dict(W.z_view(120, 88), quantity="density2")] + \
+        [W.rotated_view(R, 96, 80) for R in W.random_rotations(2, seed=31)]
+    for view in views:
+        view = dict(view, method="centroids")
+        got, st = gpu_image(tess, xyz, (n, n, n), view)
+        ref, ost = O.splat_image(*xyz, (n, n, n), view)
+        assert_parity(got, ref, what=f"centroids {view.get('quantity', 'density')} {view['width']}x{view['height']}")
+        assert st["fragments"] == ost["fragments"]
+    got, _ = gpu_image(tess, tiny_lattice, (32, 32, 32), dict(W.z_view(256), method="centroids"))
+    ref, _ = O.splat_image(*tiny_lattice, (32, 32, 32), dict(W.z_view(256), method="centroids"))
+    assert_parity(got, ref, what="centroids tiny 32^3 -> 256^2")
+
+
 def test_fp64_determinant_path(tess, tiny_lattice):
     view = W.z_view(128, 96)
     got, st = gpu_image(tess, tiny_lattice, (32, 32, 32), view, precision="fp64")

@@ -120,6 +120,19 @@ def test_depth_slab_with_density_squared():
     assert rel(img, ref) < 1e-8
 
 
+@pytest.mark.parametrize("view_kind,quantity", [("z", "density"), ("rotated", "density"), ("z", "density2")])
+def test_centroid_splats_match_oracle(view_kind, quantity):
+    # the centroid method: kernel values added directly (no row sums)
+    n = 12
+    xyz = W.zeldovich(n, 4, 6.0, seed=5)
+    base = W.z_view(96, 72) if view_kind == "z" else W.rotated_view(W.random_rotations(1, seed=3)[0], 80, 64)
+    view = dict(base, method="centroids", quantity=quantity)
+    img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=8, tile_cols=40, chunk=500)
+    ref, ost = O.splat_image(*xyz, (n, n, n), view)
+    assert np.abs(img - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert st["fragments"] == ost["fragments"] and st["tets"] == ost["tets"]
+
+
 def test_tallest_tiles_match_oracle():
     # 256-row tiles (the largest the library accepts): row offsets of up to 255
     # inside a tile, footprints taller than the lattice spacing wrapping in y

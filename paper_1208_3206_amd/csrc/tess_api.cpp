@@ -401,6 +401,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.slab_t[0] = g.vp.slab_t[0];
     B.slab_t[1] = g.vp.slab_t[1];
     B.direct = g.vp.splat;
+    B.form = view_form(g.vp);
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
     return TESS_OK;

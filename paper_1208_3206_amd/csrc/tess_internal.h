@@ -41,6 +41,13 @@ struct ViewParams {
     int32_t splat;           // 1: centroid splats instead of the tessellation
 };
 
+// Record kinds of a launch (one per view): the pyramid (crease and line
+// forms), the face form of a depth slab, centroid splats.
+constexpr int kFormPyramid = 0, kFormFace = 1, kFormSplat = 2;
+__host__ __device__ inline int view_form(const ViewParams &V) {
+    return V.splat ? kFormSplat : (V.slab ? kFormFace : kFormPyramid);
+}
+
 // Screen tiling: tiles of Th rows x Tw columns (a row band when Tw >= W).
 struct BinParams {
     int32_t Th, Tw;
@@ -52,6 +59,7 @@ struct BinParams {
     uint32_t ntet;           // number of records
     double slab_t[2];        // depth slab of face-form records (the view's)
     int32_t direct;          // 1: the accumulator holds values (splats), not second differences
+    int32_t form;            // the records' kind (kFormPyramid, kFormFace, kFormSplat)
 };
 
 // Per-call device counters (atomically accumulated).

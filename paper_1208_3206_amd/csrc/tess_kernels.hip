@@ -49,6 +49,7 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
 }
 
 // One thread per lattice cube; writes the six records 6*cube .. 6*cube+5.
+template <int FORM>
 __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
                                                RecHead *__restrict__ head,
                                                Payload *__restrict__ coef,
@@ -57,14 +58,9 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
     for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
-        RecHead h[6];
-        Payload c[6];
-        setup_cube(L, V, cube, h, c, cnt);
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-            head[6 * cube + t] = h[t];
-            coef[6 * cube + t] = c[t];
-        }
+        // records written in place as they are built (holding six 144-byte
+        // records in registers would cost the occupancy)
+        setup_cube<FORM>(L, V, cube, head + 6 * cube, coef + 6 * cube, cnt);
     }
     const unsigned long long n_tets = wave_sum(cnt.n_tets), n_zero = wave_sum(cnt.n_zero),
                              n_inv = wave_sum(cnt.n_inv), n_dets = wave_sum(cnt.n_dets),
@@ -100,7 +96,18 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
                         DevCounters *counters, hipStream_t stream) {
     const int64_t want = (L.ncubes + 255) / 256;
     const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
-    hipLaunchKernelGGL(k_setup, dim3(blocks), dim3(256), 0, stream, L, V, head, coef, counters);
+    switch (view_form(V)) {
+        case kFormFace:
+            hipLaunchKernelGGL((k_setup<kFormFace>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef, counters);
+            break;
+        case kFormSplat:
+            hipLaunchKernelGGL((k_setup<kFormSplat>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
+                               counters);
+            break;
+        default:
+            hipLaunchKernelGGL((k_setup<kFormPyramid>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
+                               counters);
+    }
     return hipGetLastError();
 }
 
@@ -381,7 +388,7 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
 constexpr int kPad = 2;
 constexpr int kIdBurst = 8;  // pair ids a lane loads at once
 
-template <int TPB>
+template <int TPB, int FORM>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
                                                 const Payload *__restrict__ coef,
                                                 const uint32_t *__restrict__ pairs,
@@ -422,7 +429,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             if (id >= B.ntet) continue;
             const RecHead h = coef[id].h;
             if (!(h.flags & REC_VALID)) continue;
-            frags += raster_record(h, coef[id].c, B, tx0, ty0, n, rows,
+            frags += raster_record<FORM>(h, coef[id].c, B, tx0, ty0, n, rows,
                                    [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
                                    spans, kinks);
         }
@@ -443,28 +450,41 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     }
 }
 
+template <int FORM>
+static void launch_raster_form(const RecHead *head, const Payload *coef, const uint32_t *pairs,
+                               const WorkItem *items, uint64_t max_items, const PlanOut *plan,
+                               const BinParams &B, int block, double *acc, DevCounters *counters,
+                               hipStream_t stream, size_t lds) {
+    switch (block) {
+        case 256:
+            hipLaunchKernelGGL((k_raster<256, FORM>), dim3((unsigned)max_items), dim3(256), lds, stream, head,
+                               coef, pairs, items, plan, B, acc, counters);
+            break;
+        case 512:
+            hipLaunchKernelGGL((k_raster<512, FORM>), dim3((unsigned)max_items), dim3(512), lds, stream, head,
+                               coef, pairs, items, plan, B, acc, counters);
+            break;
+        default:
+            hipLaunchKernelGGL((k_raster<1024, FORM>), dim3((unsigned)max_items), dim3(1024), lds, stream, head,
+                               coef, pairs, items, plan, B, acc, counters);
+    }
+}
+
 hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
                          const BinParams &B, int block, double *acc, DevCounters *counters,
                          hipStream_t stream) {
     if (max_items == 0) return hipSuccess;
+    if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
     const size_t lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
-    switch (block) {
-        case 256:
-            hipLaunchKernelGGL((k_raster<256>), dim3((unsigned)max_items), dim3(256), lds, stream, head, coef,
-                               pairs, items, plan, B, acc, counters);
-            break;
-        case 512:
-            hipLaunchKernelGGL((k_raster<512>), dim3((unsigned)max_items), dim3(512), lds, stream, head, coef,
-                               pairs, items, plan, B, acc, counters);
-            break;
-        case 1024:
-            hipLaunchKernelGGL((k_raster<1024>), dim3((unsigned)max_items), dim3(1024), lds, stream, head,
-                               coef, pairs, items, plan, B, acc, counters);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
+    if (B.form == kFormFace)
+        launch_raster_form<kFormFace>(head, coef, pairs, items, max_items, plan, B, block, acc, counters, stream, lds);
+    else if (B.form == kFormSplat)
+        launch_raster_form<kFormSplat>(head, coef, pairs, items, max_items, plan, B, block, acc, counters, stream,
+                                       lds);
+    else
+        launch_raster_form<kFormPyramid>(head, coef, pairs, items, max_items, plan, B, block, acc, counters, stream,
+                                         lds);
     return hipGetLastError();
 }
 

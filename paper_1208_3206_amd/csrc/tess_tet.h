@@ -19,6 +19,7 @@ constexpr int kTet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4},
 
 constexpr double kPi = 3.14159265358979323846;
 
+
 // Face a of a tetrahedron is the one opposite vertex a; its vertices in
 // increasing order.
 constexpr int kFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
@@ -111,11 +112,17 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
             const double K = mass_px / (ck * fabs(cl));
             const double bb = -K * dy, cc = K * dx;
             const double aa = K * (dy * qx[E.i] - dx * qy[E.i]);
-            fp.c[3 * ng + 0] = aa;
-            fp.c[3 * ng + 1] = bb;
-            fp.c[3 * ng + 2] = cc;
-            fp.ei[ng] = E.i;
-            fp.ej[ng] = E.j;
+            // slot ng, by compile-time slots (an indexed store would put the
+            // arrays in scratch memory)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k == ng) {
+                    fp.c[3 * k + 0] = aa;
+                    fp.c[3 * k + 1] = bb;
+                    fp.c[3 * k + 2] = cc;
+                    fp.ei[k] = E.i;
+                    fp.ej[k] = E.j;
+                }
             ++ng;
         }
     }
@@ -137,10 +144,14 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
         if (side == 0.0) return false;  // all four collinear
         const double sg = side > 0 ? 1.0 : -1.0;
         if (nw >= 2 || ng + nw >= 4) return false;
-        const int o = 3 * (ng + nw);
-        fp.c[o + 0] = sg * (dy * qx[s] - dx * qy[s]);
-        fp.c[o + 1] = -sg * dy;
-        fp.c[o + 2] = sg * dx;
+        const double w0 = sg * (dy * qx[s] - dx * qy[s]), w1 = -sg * dy, w2 = sg * dx;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k == ng + nw) {
+                fp.c[3 * k + 0] = w0;
+                fp.c[3 * k + 1] = w1;
+                fp.c[3 * k + 2] = w2;
+            }
         // outward normal (away from vertex a) = sg * (dy, -dx); pixels on the
         // line are kept iff it points to -u, or along the u axis to -v
         const double ou = sg * dy, ov = -sg * dx;
@@ -335,6 +346,7 @@ TESS_HD inline double cube_qvol(const LatticeParams &L, const ViewParams &V, int
 // corners, volume determinant with its FP64 fallback, footprint.  head[t] and
 // coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
 // cover no pixel centre).
+template <int FORM>
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
                                Payload coef[6], CubeCounts &cnt) {
     double X0[3], e[8][3];
@@ -398,7 +410,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         ++cnt.n_tets;
         cnt.n_inv += det6 > 0 ? 1 : 0;
         cnt.n_deg += fabs(det6) < 6.0 * L.det_v0_frac * L.v0 ? 1 : 0;
-        if (V.splat) {
+        if constexpr (FORM == kFormSplat) {
             // the centroid method: a kernel of size h = |V|^(1/3) at the
             // projected centroid, carrying q |V|
             const double vol = fabs(det6) / 6.0;
@@ -459,7 +471,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             qy[m] = PY[vi[m]] - (double)iy0;
         }
         const double rho_m = 6.0 / fabs(det6);  // rho / m
-        if (V.slab) {
+        if constexpr (FORM == kFormFace) {
             // depth slab: the face form, q times the clipped chord
             double T[4];
 #pragma unroll
@@ -1176,14 +1188,20 @@ TESS_HD inline uint32_t splat_pair(const RecHead &h, const double *cf, const Bin
 }
 
 // One record in one tile, in whichever form its payload has.
-template <typename Dep>
+// (A launch holds records of one kind: pyramids in crease or line form, face
+// form with a depth slab, or splats; FORM selects it at compile time.)
+template <int FORM, typename Dep>
 TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const BinParams &B, int tx0,
                                       int ty0, int n, int rows, Dep &&dep, uint32_t &spans,
                                       uint32_t &kinks) {
-    if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
-    if (h.flags & REC_FACE) return face_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
-    if (h.flags & REC_SPLAT) return splat_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
-    return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    if constexpr (FORM == kFormFace) {
+        return face_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    } else if constexpr (FORM == kFormSplat) {
+        return splat_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    } else {
+        if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+        return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    }
 }
 
 }  // namespace tess

@@ -64,7 +64,9 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0;
     for (int64_t cube = 0; cube < L.ncubes; ++cube) {
         CubeCounts cnt;
-        setup_cube(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        if (splat) setup_cube<kFormSplat>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        else if (slab) setup_cube<kFormFace>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        else setup_cube<kFormPyramid>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
         for (int t = 0; t < 6; ++t) creases += (head[6 * cube + t].flags & REC_CREASE) ? 1 : 0;
     }
@@ -103,12 +105,16 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
             for (size_t e = first; e < last; ++e) {
                 const uint32_t id = lst[e];
                 uint32_t sp = 0, kk = 0;
-                frags += raster_record(head[id], coef[id].c, B, tx0, ty0, n, rows,
+                auto rr = [&](auto &&dep) {
+                    return splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
+                         : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
+                                : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk);
+                };
+                frags += rr(
                                      [&](int row, int j, double v) {
                                          if (row < 0 || row >= rows || j < -2 || j > n + 1) throw 1;
                                          if (j >= 0 && j < n) tile[(size_t)row * B.Tw + j] += v;
-                                     },
-                                     sp, kk);
+                                     });
                 spans += sp;
             }
             for (int r = 0; r < rows; ++r)

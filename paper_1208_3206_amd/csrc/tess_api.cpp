@@ -392,6 +392,8 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     if (g.ntiles > kMaxTiles)
         return fail(TESS_ECAPACITY, "%lld tiles of %d x %d px exceed the limit of %d; use larger tiles",
                     (long long)g.ntiles, plan.Th, plan.Tw, kMaxTiles);
+    // pair ids carry a work class (pyramid records, ids below the class bits)
+    B.nkey = (view_form(g.vp) == kFormPyramid && g.ntet < (int64_t)kIdMask) ? 32 : 1;
     // binning segments: enough for the device, few enough to keep the count matrix small
     int64_t seg_len = 4096;
     while ((g.ntet + seg_len - 1) / seg_len * g.ntiles > (int64_t)64 << 20) seg_len *= 2;

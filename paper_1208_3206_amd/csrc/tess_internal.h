@@ -56,11 +56,19 @@ struct BinParams {
     int32_t wrap;
     int32_t seg_len;         // tetrahedra per binning segment
     int32_t nseg;
+    int32_t nkey;            // work classes carried by pair ids (32), or 1: plain ids
     uint32_t ntet;           // number of records
     double slab_t[2];        // depth slab of face-form records (the view's)
     int32_t direct;          // 1: the accumulator holds values (splats), not second differences
     int32_t form;            // the records' kind (kFormPyramid, kFormFace, kFormSplat)
 };
+
+// Pair-list entries: the record id, with the pair's work class (0..31) in
+// the bits from kClassShift up when the list carries classes
+// (BinParams::nkey > 1, which needs ids below kIdMask).  kIdMask itself
+// marks an empty entry.
+constexpr int kClassShift = 27;
+constexpr uint32_t kIdMask = (1u << kClassShift) - 1u;
 
 // Per-call device counters (atomically accumulated).
 struct DevCounters {
@@ -108,7 +116,7 @@ struct RecHead {
     uint32_t bx;                 // pixel-centre box, x: low 16 bits x0, high 16 bits x1 (int16)
     uint32_t by;                 // y0 | y1 << 16
     uint32_t flags;
-    uint32_t spare;
+    uint32_t spare;              // crease form: row profile for scheduling (crease_profile)
 };
 // Box accessors (the box is stored as two packed 32-bit words).
 __host__ __device__ inline uint32_t pack_range(int lo, int hi) {

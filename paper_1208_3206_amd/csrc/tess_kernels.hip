@@ -115,7 +115,8 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
 // One block per segment of seg_len consecutive tetrahedra; lanes take
 // tetrahedra in turn and count (or place) them in an LDS array of per-tile
 // counters.  The order inside one segment's share of a tile list follows the
-// atomics; the raster's sums do not depend on it beyond rounding.
+// atomics; the raster's sums do not depend on it beyond rounding.  With
+// nkey > 1 each placed id carries the pair's work class in its top bits.
 constexpr int kBinBlock = 256;
 
 template <bool SCATTER>
@@ -140,12 +141,16 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
         const RecHead r = head[id];
         if (!(r.flags & REC_VALID)) continue;
         const TileRange tr = tet_tiles(r, B);
-        for (int s = 0; s < tr.count; ++s) {
-            const int tile = tet_tile(B, tr, s);
-            const uint32_t slot = atomicAdd(&lds_bins[tile], 1u);
-            if (SCATTER) {
-                const uint64_t pos = base[(int64_t)tile * B.nseg] + slot;
-                if (pos < pair_cap) pairs[pos] = (uint32_t)id;
+        for (int sy = 0; sy < tr.cy; ++sy) {
+            const int ty = tr.sy + sy < B.nty ? tr.sy + sy : tr.sy + sy - B.nty;
+            const uint32_t tag = SCATTER && B.nkey > 1 ? (uint32_t)pair_class(r, B, ty) << kClassShift : 0u;
+            for (int sx = 0; sx < tr.cx; ++sx) {
+                const int tile = ty * B.ntx + (tr.sx + sx < B.ntx ? tr.sx + sx : tr.sx + sx - B.ntx);
+                const uint32_t slot = atomicAdd(&lds_bins[tile], 1u);
+                if (SCATTER) {
+                    const uint64_t pos = base[(int64_t)tile * B.nseg] + slot;
+                    if (pos < pair_cap) pairs[pos] = (uint32_t)id | tag;
+                }
             }
         }
     }
@@ -155,9 +160,12 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
     }
 }
 
+// one 32-bit LDS counter per tile, in both passes
+static size_t bin_lds_bytes(const BinParams &B) { return sizeof(uint32_t) * (size_t)B.ntx * B.nty; }
+
 hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
                         hipStream_t stream) {
-    const size_t lds = sizeof(uint32_t) * (size_t)B.ntx * B.nty;
+    const size_t lds = bin_lds_bytes(B);
     hipLaunchKernelGGL((k_bin<false>), dim3(B.nseg), dim3(kBinBlock), lds, stream, head, ntet, B, counts,
                        (const uint64_t *)nullptr, (uint32_t *)nullptr, 0ull);
     return hipGetLastError();
@@ -165,7 +173,7 @@ hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, u
 
 hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint64_t *base,
                           uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream) {
-    const size_t lds = sizeof(uint32_t) * (size_t)B.ntx * B.nty;
+    const size_t lds = bin_lds_bytes(B);
     hipLaunchKernelGGL((k_bin<true>), dim3(B.nseg), dim3(kBinBlock), lds, stream, head, ntet, B,
                        (uint32_t *)nullptr, base, pairs, pair_cap);
     return hipGetLastError();
@@ -386,14 +394,26 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
 // the tile is added to the image-sized array `acc` (FP64 atomics in L2; a
 // tile has several items).
 constexpr int kPad = 2;
-constexpr int kIdBurst = 8;  // pair ids a lane loads at once
+constexpr int kIdBurst = 8;     // pair ids a lane loads at once
+constexpr int kSortPer = 7;     // pair ids per lane in one wavefront's class sort
+constexpr int kNumClasses = 32;
+constexpr size_t kLdsBytes = 160 * 1024;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS of one wavefront's class sort: kNumClasses counters, then 64 * kSortPer entries
+constexpr int kSortWords = kNumClasses + 64 * kSortPer;
 
 template <int TPB, int FORM>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
                                                 const Payload *__restrict__ coef,
                                                 const uint32_t *__restrict__ pairs,
                                                 const WorkItem *__restrict__ items,
-                                                const PlanOut *__restrict__ plan, BinParams B,
+                                                const PlanOut *__restrict__ plan, BinParams B, int sorted,
                                                 double *__restrict__ acc,
                                                 DevCounters *__restrict__ counters) {
     extern __shared__ double sA[];
@@ -409,29 +429,74 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     for (int i = threadIdx.x; i < tsize; i += TPB) sA[i] = 0.0;
     __syncthreads();
     uint32_t frags = 0, spans = 0, kinks = 0;
+    auto one = [&](uint32_t id) {
+        if (id >= B.ntet) return;
+        const RecHead h = coef[id].h;
+        if (!(h.flags & REC_VALID)) return;
+        frags += raster_record<FORM>(h, coef[id].c, B, tx0, ty0, n, rows,
+                                     [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                                     spans, kinks);
+    };
     // lane t takes entries t*per .. t*per+per-1: the list is in rough id order
     // (neighbouring cubes), so this spreads a wavefront's 64 footprints over
     // the tile instead of stacking their atomics on the same LDS cells
     const uint32_t per = (it.count + TPB - 1) / TPB;
     const uint32_t e0 = threadIdx.x * per, e1 = min(it.count, e0 + per);
-    for (uint32_t e = e0; e < e1; e += kIdBurst) {
-        // the next ids of the slice in one burst: one fetch of their cache
-        // line serves kIdBurst pairs (read one at a time, microseconds
-        // apart, the line is gone from L2 before its next use)
-        uint32_t ids[kIdBurst];
+    if (FORM == kFormPyramid && sorted) {
+        // The wavefront takes the next kSortPer entries of each of its lanes'
+        // slices and deals them back out in work-class order (a counting sort
+        // in its own LDS area): the lanes that step through their creases
+        // together then hold pairs of about the same work.  `per` is the same
+        // for every lane, so the whole wavefront runs every round.
+        const uint32_t lane = threadIdx.x & 63u;
+        uint32_t *cnt = reinterpret_cast<uint32_t *>(sA + tsize) + (threadIdx.x >> 6) * kSortWords;
+        uint32_t *ent = cnt + kNumClasses;
+        for (uint32_t b = 0; b < per; b += kSortPer) {
+            uint32_t v[kSortPer], rk[kSortPer];
 #pragma unroll
-        for (int i = 0; i < kIdBurst; ++i) ids[i] = e + i < e1 ? pairs[it.first + e + i] : 0xffffffffu;
-        const int cnt = (int)min((uint32_t)kIdBurst, e1 - e);
-        for (int i = 0; i < cnt; ++i) {
-            const uint32_t id = ids[0];
+            for (int i = 0; i < kSortPer; ++i) {
+                const uint32_t e = e0 + b + (uint32_t)i;
+                v[i] = (b + (uint32_t)i < per && e < e1) ? pairs[it.first + e] : kIdMask;  // empty: class 0
+            }
+            if (lane < (uint32_t)kNumClasses) cnt[lane] = 0u;
+            wave_sync();
 #pragma unroll
-            for (int j = 0; j + 1 < kIdBurst; ++j) ids[j] = ids[j + 1];
-            if (id >= B.ntet) continue;
-            const RecHead h = coef[id].h;
-            if (!(h.flags & REC_VALID)) continue;
-            frags += raster_record<FORM>(h, coef[id].c, B, tx0, ty0, n, rows,
-                                   [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
-                                   spans, kinks);
+            for (int i = 0; i < kSortPer; ++i) rk[i] = atomicAdd(&cnt[v[i] >> kClassShift], 1u);
+            wave_sync();
+            // class offsets: exclusive prefix sum of the counts over the lanes
+            const uint32_t c = lane < (uint32_t)kNumClasses ? cnt[lane] : 0u;
+            uint32_t incl = c;
+#pragma unroll
+            for (int off = 1; off < kNumClasses; off <<= 1) {
+                const uint32_t o = __shfl_up(incl, off, 64);
+                if (lane >= (uint32_t)off) incl += o;
+            }
+            wave_sync();
+            if (lane < (uint32_t)kNumClasses) cnt[lane] = incl - c;
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < kSortPer; ++i) ent[cnt[v[i] >> kClassShift] + rk[i]] = v[i];
+            wave_sync();
+#pragma unroll 1
+            for (int j = 0; j < kSortPer; ++j) one(ent[j * 64 + lane] & kIdMask);
+            wave_sync();  // the next round rewrites the area
+        }
+    } else {
+        const uint32_t idmask = B.nkey > 1 ? kIdMask : 0xffffffffu;
+        for (uint32_t e = e0; e < e1; e += kIdBurst) {
+            // the next ids of the slice in one burst: one fetch of their cache
+            // line serves kIdBurst pairs (read one at a time, microseconds
+            // apart, the line is gone from L2 before its next use)
+            uint32_t ids[kIdBurst];
+#pragma unroll
+            for (int i = 0; i < kIdBurst; ++i) ids[i] = e + i < e1 ? pairs[it.first + e + i] & idmask : 0xffffffffu;
+            const int cnt = (int)min((uint32_t)kIdBurst, e1 - e);
+            for (int i = 0; i < cnt; ++i) {
+                const uint32_t id = ids[0];
+#pragma unroll
+                for (int j = 0; j + 1 < kIdBurst; ++j) ids[j] = ids[j + 1];
+                one(id);
+            }
         }
     }
     __syncthreads();
@@ -453,20 +518,20 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
 template <int FORM>
 static void launch_raster_form(const RecHead *head, const Payload *coef, const uint32_t *pairs,
                                const WorkItem *items, uint64_t max_items, const PlanOut *plan,
-                               const BinParams &B, int block, double *acc, DevCounters *counters,
+                               const BinParams &B, int sorted, int block, double *acc, DevCounters *counters,
                                hipStream_t stream, size_t lds) {
     switch (block) {
         case 256:
             hipLaunchKernelGGL((k_raster<256, FORM>), dim3((unsigned)max_items), dim3(256), lds, stream, head,
-                               coef, pairs, items, plan, B, acc, counters);
+                               coef, pairs, items, plan, B, sorted, acc, counters);
             break;
         case 512:
             hipLaunchKernelGGL((k_raster<512, FORM>), dim3((unsigned)max_items), dim3(512), lds, stream, head,
-                               coef, pairs, items, plan, B, acc, counters);
+                               coef, pairs, items, plan, B, sorted, acc, counters);
             break;
         default:
             hipLaunchKernelGGL((k_raster<1024, FORM>), dim3((unsigned)max_items), dim3(1024), lds, stream, head,
-                               coef, pairs, items, plan, B, acc, counters);
+                               coef, pairs, items, plan, B, sorted, acc, counters);
     }
 }
 
@@ -476,15 +541,20 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_
                          hipStream_t stream) {
     if (max_items == 0) return hipSuccess;
     if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
-    const size_t lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
+    // the tile's accumulator, and beside it (when it fits) the wavefronts' class sorts
+    const size_t tile_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
+    const size_t sort_lds = sizeof(uint32_t) * (size_t)(block / 64) * kSortWords;
+    const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;
+    const size_t lds = tile_lds + (sorted ? sort_lds : 0);
     if (B.form == kFormFace)
-        launch_raster_form<kFormFace>(head, coef, pairs, items, max_items, plan, B, block, acc, counters, stream, lds);
+        launch_raster_form<kFormFace>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+                                      stream, lds);
     else if (B.form == kFormSplat)
-        launch_raster_form<kFormSplat>(head, coef, pairs, items, max_items, plan, B, block, acc, counters, stream,
-                                       lds);
+        launch_raster_form<kFormSplat>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+                                       stream, lds);
     else
-        launch_raster_form<kFormPyramid>(head, coef, pairs, items, max_items, plan, B, block, acc, counters, stream,
-                                         lds);
+        launch_raster_form<kFormPyramid>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc,
+                                         counters, stream, lds);
     return hipGetLastError();
 }
 

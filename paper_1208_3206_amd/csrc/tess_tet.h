@@ -227,6 +227,24 @@ TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const
     return true;
 }
 
+// Row profile of a crease-form payload, kept in the record head for the
+// binning's work classes: for the silhouette vertices V_0..V_3 and the apex,
+// the first record row whose centre lies at or above the point (a crease
+// from P to Q covers rows [min, max) of the two), shifted right by s so that
+// the footprint's height fits 5 bits; 5 bits each from bit 0, s in bits 25-29.
+TESS_HD inline uint32_t crease_profile(const double cf[14], int height) {
+    int sh = 0;
+    while (sh < 26 && (height >> sh) > 31) ++sh;
+    uint32_t p = (uint32_t)sh << 25;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        const double y = v < 4 ? cf[4 + v] : cf[9];
+        const int yb = (int)fmin(fmax(ceil(y - 0.5), 0.0), (double)height);
+        p |= (uint32_t)min(yb >> sh, 31) << (5 * v);
+    }
+    return p;
+}
+
 // Face form of a tetrahedron (views with a depth slab): per face g its depth
 // plane t = c0 + c1 x + c2 y through the projected vertices (q, T: pixel
 // coordinates relative to the record origin, world depths), marked front
@@ -507,6 +525,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
         if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, coef[t].c)) {
             R.flags |= REC_CREASE;
+            R.spare = crease_profile(coef[t].c, iy1 - iy0 + 1);
         } else {
 #pragma unroll
             for (int g = 0; g < 12; ++g) coef[t].c[g] = fp.c[g];
@@ -592,6 +611,48 @@ TESS_HD inline int tet_tile(const BinParams &B, const TileRange &t, int s) {
     if (tx >= B.ntx) tx -= B.ntx;
     if (ty >= B.nty) ty -= B.nty;
     return ty * B.ntx + tx;
+}
+
+// Work class of a (record, tile) pair, 0 <= class < 32, for the tile row ty.
+// The raster's lanes step through their creases together, so a wavefront's
+// time follows its longest lanes; pairs of one class have about the same
+// number of active creases and rows, and the raster hands a wavefront's pairs
+// to its lanes in class order.  Estimated from the head alone (the row
+// profile of a crease-form record; every other record is class 0): the
+// creases whose rows meet the tile's, and their mean row count in it in
+// quarters of the tile height.  Only the order of work depends on it.
+TESS_HD inline int pair_class(const RecHead &r, const BinParams &B, int ty) {
+    if (!(r.flags & REC_CREASE)) return 0;
+    const int ty0 = ty * B.Th;
+    const int rows = min(B.Th, B.H - ty0);
+    int lo = ty0 - range_lo(r.by);  // the tile's first row in record rows (the period nearest)
+    if (B.wrap) {
+        if (lo < 0) lo += B.H;
+        if (lo >= B.H) lo -= B.H;
+    }
+    const int hi = lo + rows - 1;
+    const int sh = (int)((r.spare >> 25) & 31u);
+    int yb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) yb[v] = ((int)((r.spare >> (5 * v)) & 31u) << sh) + ((1 << sh) >> 1);
+    const int m = (int)(r.flags & REC_NG_MASK);
+    int nact = 0, nrows = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int k = c & 3;
+        if (k >= m) continue;
+        const int k1 = k + 1 < m ? k + 1 : 0;
+        const int P = c < 4 ? yb[k] : yb[4], Q = c < 4 ? yb[k1] : yb[k];
+        const int a = max(min(P, Q), lo), b = min(max(P, Q) - 1, hi);
+        if (a <= b) {
+            ++nact;
+            nrows += b - a + 1;
+        }
+    }
+    if (nact == 0) return 0;
+    const int full = nact * rows;  // fill = floor(4 nrows / full), at most 3
+    const int fill = 4 * nrows >= 3 * full ? 3 : 4 * nrows >= 2 * full ? 2 : 4 * nrows >= full ? 1 : 0;
+    return (min(nact, 8) - 1) * 4 + fill;
 }
 
 // ----------------------------------------------------------------- raster

@@ -83,12 +83,19 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     B.slab_t[1] = V.slab_t[1];
     B.direct = splat;
     const int ntiles = B.ntx * B.nty;
+    B.nkey = (splat || slab) ? 1 : 32;
+    // per tile: its records in id order; every pair's work class in range
     std::vector<std::vector<uint32_t>> lists(ntiles);
     for (int64_t id = 0; id < ntet; ++id) {
         const RecHead &r = head[id];
         if (!(r.flags & REC_VALID)) continue;
         const TileRange tr = tet_tiles(r, B);
-        for (int s = 0; s < tr.count; ++s) lists[tet_tile(B, tr, s)].push_back((uint32_t)id);
+        for (int s = 0; s < tr.count; ++s) {
+            const int tile = tet_tile(B, tr, s);
+            const int cls = pair_class(r, B, tile / B.ntx);
+            if (cls < 0 || cls >= B.nkey || (cls != 0 && !(r.flags & REC_CREASE))) return -2;
+            lists[tile].push_back((uint32_t)id);
+        }
     }
     std::vector<double> acc((size_t)W * H, 0.0);
     std::vector<double> tile((size_t)tile_rows * tile_cols);

@@ -259,6 +259,28 @@ def test_repeatable_and_tiling_independent(tess, tiny_lattice):
         np.testing.assert_allclose(b, a, rtol=2.4e-7, atol=1e-12 * a.max())
 
 
+def test_work_classes_keep_the_image(tess):
+    # many tiles: the tile lists are sorted into 32 work classes (default
+    # 32 x 512 tiles), 2 (8 x 64) or none (4 x 32); the sorted plans must give
+    # the unsorted plan's image and match the oracle's samples.  (The mean of
+    # the pixel-centre samples is 1 only to the sampling error, ~2e-5 here.)
+    import torch
+    n = 32
+    xyz = W.zeldovich(n, 8, 4.0)
+    lat = tess.build(*dev(xyz), (n, n, n))
+    view = W.z_view(1024)
+    imgs = [tess.project(lat, view, tune=t).cpu().numpy().astype(np.float64)
+            for t in (None, tess.make_tune(8, 64), tess.make_tune(4, 32))]
+    torch.cuda.synchronize()
+    for im in imgs:
+        assert abs(im.mean() - 1.0) < 1e-4, im.mean()
+    for im in imgs[:2]:
+        np.testing.assert_allclose(im, imgs[2], rtol=2.4e-7, atol=1e-12 * imgs[2].max())
+    px, py = sample_pixels(1024, 1024, 200, 3)
+    ref, _ = O.project_pixels(*xyz, (n, n, n), view, px, py)
+    assert rel_err(imgs[0][py, px].astype(np.float32), ref).max() <= PIX_TOL
+
+
 def batch_case(tess, n=16, growths=(1.0, 4.0), nviews=3, size=64):
     lats, xyzs = [], []
     for D in growths:

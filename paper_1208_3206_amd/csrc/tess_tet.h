@@ -987,25 +987,30 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
                     // rows right of the tile count its full width
                     acc = n * (sl > 0.0 ? q1 - r1 : r0 - q0);
                 }
-                // the crossing in the record frame (small numbers: a footprint's
-                // kinks keep their relative positions to FP64 rounding of its box)
-                double x = Px + ((double)r0 + 0.5 - Py) * sl;
+                // the crossing u = w relative to the tile's first pixel centre
+                // (small numbers: a footprint's kinks keep their relative
+                // positions to FP64 rounding of its box)
+                double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
                 // Fragments: an entering crossing has floor(u) + 1 samples left
                 // of it, a leaving one ceil(u) (a sample on the silhouette is
-                // outside). The column j is taken in a frame shifted by
+                // outside). The column is taken in a frame shifted by
                 // kSampleEps, down for an entering crease and up for a leaving
-                // one, so that j = floor(u) + 1 or ceil(u) and the count is
-                // max(j, 0) (jlo <= 0). Any j next to the kink gives the same
-                // sum, since the deposits use the exact offset from column j.
-                const double Xj = X0 + (enter ? -kSampleEps : kSampleEps);
-                kinks += (uint32_t)max(r1 - r0 + 1, 0);
-                for (int r = r0; r <= r1; ++r, x += sl) {
+                // one: k = floor(u + s) and j = k + 1 is floor(u) + 1 or
+                // ceil(u), and the count is max(j, 0) (jlo <= 0). Any j next to
+                // the kink gives the same sum, since the deposits use the exact
+                // offset from column j: with t = k - u they are D (1 + t) at j
+                // and the rest of D at j + 1.
+                const double s_eps = enter ? kSampleEps : -kSampleEps;
+                const int len = max(r1 - r0 + 1, 0);
+                kinks += (uint32_t)len;
+                acc += len;
+                for (int r = r0; r <= r1; ++r, w += sl) {
                     const int row = r + rshift;
-                    const int j = min(max((int)floor(x - Xj) + 1, jlo), n);
-                    const double v1 = D * (((double)j + X0) - x);
-                    dep(row, j, v1);
-                    dep(row, j + 1, D - v1);
-                    acc += max(j, 0);
+                    const int k = min(max((int)floor(w + s_eps), jlo - 1), n - 1);
+                    const double v1 = fma(D, (double)k - w, D);
+                    dep(row, k + 1, v1);
+                    dep(row, k + 2, D - v1);
+                    acc += max(k, -1);
                 }
                 if (edge) frags += enter ? -acc : acc;
             }

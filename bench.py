@@ -40,8 +40,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "d43d51619cca41e7bdf746b147f1799acedbabf5f69dcab9cdad805a145895b1",
-    "fetch_kib": 89575898.4, "write_kib": 2306671.1, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "8d4dec2e1ee768e113f63d6c029029744ed946256782cc545ab42c5c337c6ce1",
+    "fetch_kib": 98150702.0, "write_kib": 2377923.2, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -389,148 +389,154 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     }
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
-        const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
-        RecHead &R = head[t];
+        // the record is built in registers and stored once, in whole lines
+        RecHead R;
         R.bx = 0;
         R.by = 0;
         R.flags = 0;
         R.spare = 0;
+        double pc[14];
 #pragma unroll
-        for (int g = 0; g < 14; ++g) coef[t].c[g] = 0.0;
-        coef[t].h = R;
-        // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
-        // error bound, FP64 when the bound cannot certify it or it is small
-        double a64[3], b64[3], c64[3];
+        for (int g = 0; g < 14; ++g) pc[g] = 0.0;
+        [&] {
+            const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
+            // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
+            // error bound, FP64 when the bound cannot certify it or it is small
+            double a64[3], b64[3], c64[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            a64[q] = e[v1][q] - e[v0][q];
-            b64[q] = e[v2][q] - e[v0][q];
-            c64[q] = e[v3][q] - e[v0][q];
-        }
-        const float a[3] = {(float)a64[0], (float)a64[1], (float)a64[2]};
-        const float b[3] = {(float)b64[0], (float)b64[1], (float)b64[2]};
-        const float c[3] = {(float)c64[0], (float)c64[1], (float)c64[2]};
-        const float p1 = b[1] * c[2], p2 = b[2] * c[1];
-        const float p3 = b[2] * c[0], p4 = b[0] * c[2];
-        const float p5 = b[0] * c[1], p6 = b[1] * c[0];
-        const float d32 = a[0] * (p1 - p2) + a[1] * (p3 - p4) + a[2] * (p5 - p6);
-        const float perm = fabsf(a[0]) * (fabsf(p1) + fabsf(p2)) + fabsf(a[1]) * (fabsf(p3) + fabsf(p4)) +
-                           fabsf(a[2]) * (fabsf(p5) + fabsf(p6));
-        const double ad = fabs((double)d32);
-        const bool flagged = L.det_cond_k < 0.0 || ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
-                             ad < 2.0 * 6.0 * L.det_v0_frac * L.v0;
-        const double det6 = flagged ? det6_fp64(a64, b64, c64) : (double)d32;
-        cnt.n_dets += flagged ? 1 : 0;
-        if (det6 == 0.0) {
-            ++cnt.n_zero;
-            continue;
-        }
-        ++cnt.n_tets;
-        cnt.n_inv += det6 > 0 ? 1 : 0;
-        cnt.n_deg += fabs(det6) < 6.0 * L.det_v0_frac * L.v0 ? 1 : 0;
-        if constexpr (FORM == kFormSplat) {
-            // the centroid method: a kernel of size h = |V|^(1/3) at the
-            // projected centroid, carrying q |V|
-            const double vol = fabs(det6) / 6.0;
-            const double hh = cbrt(vol);
-            const double rho = L.tet_mass * 6.0 / fabs(det6);
-            const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
-            double cxp = 0.0, cyp = 0.0;
+            for (int q = 0; q < 3; ++q) {
+                a64[q] = e[v1][q] - e[v0][q];
+                b64[q] = e[v2][q] - e[v0][q];
+                c64[q] = e[v3][q] - e[v0][q];
+            }
+            const float a[3] = {(float)a64[0], (float)a64[1], (float)a64[2]};
+            const float b[3] = {(float)b64[0], (float)b64[1], (float)b64[2]};
+            const float c[3] = {(float)c64[0], (float)c64[1], (float)c64[2]};
+            const float p1 = b[1] * c[2], p2 = b[2] * c[1];
+            const float p3 = b[2] * c[0], p4 = b[0] * c[2];
+            const float p5 = b[0] * c[1], p6 = b[1] * c[0];
+            const float d32 = a[0] * (p1 - p2) + a[1] * (p3 - p4) + a[2] * (p5 - p6);
+            const float perm = fabsf(a[0]) * (fabsf(p1) + fabsf(p2)) + fabsf(a[1]) * (fabsf(p3) + fabsf(p4)) +
+                               fabsf(a[2]) * (fabsf(p5) + fabsf(p6));
+            const double ad = fabs((double)d32);
+            const bool flagged = L.det_cond_k < 0.0 || ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
+                                 ad < 2.0 * 6.0 * L.det_v0_frac * L.v0;
+            const double det6 = flagged ? det6_fp64(a64, b64, c64) : (double)d32;
+            cnt.n_dets += flagged ? 1 : 0;
+            if (det6 == 0.0) {
+                ++cnt.n_zero;
+                return;
+            }
+            ++cnt.n_tets;
+            cnt.n_inv += det6 > 0 ? 1 : 0;
+            cnt.n_deg += fabs(det6) < 6.0 * L.det_v0_frac * L.v0 ? 1 : 0;
+            if constexpr (FORM == kFormSplat) {
+                // the centroid method: a kernel of size h = |V|^(1/3) at the
+                // projected centroid, carrying q |V|
+                const double vol = fabs(det6) / 6.0;
+                const double hh = cbrt(vol);
+                const double rho = L.tet_mass * 6.0 / fabs(det6);
+                const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
+                double cxp = 0.0, cyp = 0.0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int vm = kTet[t][m];
+                    cxp += 0.25 * PX[vm];
+                    cyp += 0.25 * PY[vm];
+                }
+                const double rx = 2.0 * hh * V.inv_du, ry = 2.0 * hh * V.inv_dv, lim = 1.0e8;
+                int sx0 = (int)fmax(ceil(cxp - rx - 0.5), -lim), sx1 = (int)fmin(floor(cxp + rx - 0.5), lim);
+                int sy0 = (int)fmax(ceil(cyp - ry - 0.5), -lim), sy1 = (int)fmin(floor(cyp + ry - 0.5), lim);
+                if (!V.wrap) {
+                    sx0 = sx0 > 0 ? sx0 : 0;
+                    sy0 = sy0 > 0 ? sy0 : 0;
+                    sx1 = sx1 < V.W - 1 ? sx1 : V.W - 1;
+                    sy1 = sy1 < V.H - 1 ? sy1 : V.H - 1;
+                }
+                if (sx0 > sx1 || sy0 > sy1) return;
+                pc[0] = cxp - (double)sx0;
+                pc[1] = cyp - (double)sy0;
+                pc[2] = 1.0 / (hh * V.inv_du);
+                pc[3] = 1.0 / (hh * V.inv_dv);
+                pc[4] = qv * vol * (10.0 / (7.0 * kPi * hh * hh));
+                R.bx = pack_range(sx0, sx1);
+                R.by = pack_range(sy0, sy1);
+                R.flags = REC_SPLAT | REC_VALID;
+                return;
+            }
+            // ---- screen footprint (FP64)
+            const int vi[4] = {v0, v1, v2, v3};
+            double xmin = PX[v0], xmax = PX[v0], ymin = PY[v0], ymax = PY[v0];
+#pragma unroll
+            for (int m = 1; m < 4; ++m) {
+                xmin = fmin(xmin, PX[vi[m]]); xmax = fmax(xmax, PX[vi[m]]);
+                ymin = fmin(ymin, PY[vi[m]]); ymax = fmax(ymax, PY[vi[m]]);
+            }
+            // pixel centres ix + 1/2 inside [xmin, xmax] (clamped far outside any image)
+            const double lim = 1.0e8;
+            int ix0 = (int)fmax(ceil(xmin - 0.5), -lim), ix1 = (int)fmin(floor(xmax - 0.5), lim);
+            int iy0 = (int)fmax(ceil(ymin - 0.5), -lim), iy1 = (int)fmin(floor(ymax - 0.5), lim);
+            if (!V.wrap) {
+                ix0 = ix0 > 0 ? ix0 : 0;
+                iy0 = iy0 > 0 ? iy0 : 0;
+                ix1 = ix1 < V.W - 1 ? ix1 : V.W - 1;
+                iy1 = iy1 < V.H - 1 ? iy1 : V.H - 1;
+            }
+            if (ix0 > ix1 || iy0 > iy1) return;
+            double qx[4], qy[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int vm = kTet[t][m];
-                cxp += 0.25 * PX[vm];
-                cyp += 0.25 * PY[vm];
+                qx[m] = PX[vi[m]] - (double)ix0;
+                qy[m] = PY[vi[m]] - (double)iy0;
             }
-            const double rx = 2.0 * hh * V.inv_du, ry = 2.0 * hh * V.inv_dv, lim = 1.0e8;
-            int sx0 = (int)fmax(ceil(cxp - rx - 0.5), -lim), sx1 = (int)fmin(floor(cxp + rx - 0.5), lim);
-            int sy0 = (int)fmax(ceil(cyp - ry - 0.5), -lim), sy1 = (int)fmin(floor(cyp + ry - 0.5), lim);
-            if (!V.wrap) {
-                sx0 = sx0 > 0 ? sx0 : 0;
-                sy0 = sy0 > 0 ? sy0 : 0;
-                sx1 = sx1 < V.W - 1 ? sx1 : V.W - 1;
-                sy1 = sy1 < V.H - 1 ? sy1 : V.H - 1;
+            const double rho_m = 6.0 / fabs(det6);  // rho / m
+            if constexpr (FORM == kFormFace) {
+                // depth slab: the face form, q times the clipped chord
+                double T[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    T[m] = Tc + V.rot[6] * e[vi[m]][0] + V.rot[7] * e[vi[m]][1] + V.rot[8] * e[vi[m]][2];
+                const double rho = L.tet_mass * rho_m;
+                const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
+                uint32_t ff = 0;
+                if (!face_payload(qx, qy, T, V.slab_t[0], V.slab_t[1], qv, pc, ff)) {
+#pragma unroll
+                    for (int g = 0; g < 14; ++g) pc[g] = 0.0;
+                    return;
+                }
+                R.bx = pack_range(ix0, ix1);
+                R.by = pack_range(iy0, iy1);
+                R.flags = ff | REC_FACE | REC_VALID;
+                return;
             }
-            if (sx0 > sx1 || sy0 > sy1) continue;
-            coef[t].c[0] = cxp - (double)sx0;
-            coef[t].c[1] = cyp - (double)sy0;
-            coef[t].c[2] = 1.0 / (hh * V.inv_du);
-            coef[t].c[3] = 1.0 / (hh * V.inv_dv);
-            coef[t].c[4] = qv * vol * (10.0 / (7.0 * kPi * hh * hh));
-            R.bx = pack_range(sx0, sx1);
-            R.by = pack_range(sy0, sy1);
-            R.flags = REC_SPLAT | REC_VALID;
-            coef[t].h = R;
-            continue;
-        }
-        // ---- screen footprint (FP64)
-        const int vi[4] = {v0, v1, v2, v3};
-        double xmin = PX[v0], xmax = PX[v0], ymin = PY[v0], ymax = PY[v0];
-#pragma unroll
-        for (int m = 1; m < 4; ++m) {
-            xmin = fmin(xmin, PX[vi[m]]); xmax = fmax(xmax, PX[vi[m]]);
-            ymin = fmin(ymin, PY[vi[m]]); ymax = fmax(ymax, PY[vi[m]]);
-        }
-        // pixel centres ix + 1/2 inside [xmin, xmax] (clamped far outside any image)
-        const double lim = 1.0e8;
-        int ix0 = (int)fmax(ceil(xmin - 0.5), -lim), ix1 = (int)fmin(floor(xmax - 0.5), lim);
-        int iy0 = (int)fmax(ceil(ymin - 0.5), -lim), iy1 = (int)fmin(floor(ymax - 0.5), lim);
-        if (!V.wrap) {
-            ix0 = ix0 > 0 ? ix0 : 0;
-            iy0 = iy0 > 0 ? iy0 : 0;
-            ix1 = ix1 < V.W - 1 ? ix1 : V.W - 1;
-            iy1 = iy1 < V.H - 1 ? iy1 : V.H - 1;
-        }
-        if (ix0 > ix1 || iy0 > iy1) continue;
-        double qx[4], qy[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            qx[m] = PX[vi[m]] - (double)ix0;
-            qy[m] = PY[vi[m]] - (double)iy0;
-        }
-        const double rho_m = 6.0 / fabs(det6);  // rho / m
-        if constexpr (FORM == kFormFace) {
-            // depth slab: the face form, q times the clipped chord
-            double T[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                T[m] = Tc + V.rot[6] * e[vi[m]][0] + V.rot[7] * e[vi[m]][1] + V.rot[8] * e[vi[m]][2];
-            const double rho = L.tet_mass * rho_m;
-            const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
-            uint32_t ff = 0;
-            if (!face_payload(qx, qy, T, V.slab_t[0], V.slab_t[1], qv, coef[t].c, ff)) {
-#pragma unroll
-                for (int g = 0; g < 14; ++g) coef[t].c[g] = 0.0;
-                continue;
-            }
+            // q dl = (q / rho) rho dl: the density footprint with its mass scaled
+            // by rho^(qpow - 1), rho = 6 m / |6V|
+            const double qscale = V.qpow == 1 ? 1.0 : (V.qpow == 0 ? 1.0 / (L.tet_mass * rho_m) : L.tet_mass * rho_m);
+            Footprint fp;
+            if (!footprint(qx, qy, V.mass_px * qscale, fp)) return;
             R.bx = pack_range(ix0, ix1);
             R.by = pack_range(iy0, iy1);
-            R.flags = ff | REC_FACE | REC_VALID;
-            coef[t].h = R;
-            continue;
-        }
-        // q dl = (q / rho) rho dl: the density footprint with its mass scaled
-        // by rho^(qpow - 1), rho = 6 m / |6V|
-        const double qscale = V.qpow == 1 ? 1.0 : (V.qpow == 0 ? 1.0 / (L.tet_mass * rho_m) : L.tet_mass * rho_m);
-        Footprint fp;
-        if (!footprint(qx, qy, V.mass_px * qscale, fp)) continue;
-        R.bx = pack_range(ix0, ix1);
-        R.by = pack_range(iy0, iy1);
-        R.flags = (uint32_t)fp.ng | ((uint32_t)fp.nw << REC_NW_SHIFT) | fp.ties | REC_VALID;
-        // crease form unless the footprint is steep along x: its kinks' rounding
-        // would then carry along the row sums (steep slivers keep the line form,
-        // whose rows without a pixel centre are skipped)
-        double bmax = 0.0;
+            R.flags = (uint32_t)fp.ng | ((uint32_t)fp.nw << REC_NW_SHIFT) | fp.ties | REC_VALID;
+            // crease form unless the footprint is steep along x: its kinks' rounding
+            // would then carry along the row sums (steep slivers keep the line form,
+            // whose rows without a pixel centre are skipped)
+            double bmax = 0.0;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
-        if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, coef[t].c)) {
-            R.flags |= REC_CREASE;
-            R.spare = crease_profile(coef[t].c, iy1 - iy0 + 1);
-        } else {
+            for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
+            if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, pc)) {
+                R.flags |= REC_CREASE;
+                R.spare = crease_profile(pc, iy1 - iy0 + 1);
+            } else {
 #pragma unroll
-            for (int g = 0; g < 12; ++g) coef[t].c[g] = fp.c[g];
-        }
-        coef[t].h = R;
+                for (int g = 0; g < 12; ++g) pc[g] = fp.c[g];
+            }
+        }();
+        Payload P;
+        P.h = R;
+#pragma unroll
+        for (int g = 0; g < 14; ++g) P.c[g] = pc[g];
+        head[t] = R;
+        coef[t] = P;
     }
 }
 

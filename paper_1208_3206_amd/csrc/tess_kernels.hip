@@ -141,9 +141,12 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
         const RecHead r = head[id];
         if (!(r.flags & REC_VALID)) continue;
         const TileRange tr = tet_tiles(r, B);
+        ClassRows cr;
+        cr.crease = false;
+        if (SCATTER && B.nkey > 1) cr = class_rows(r);
         for (int sy = 0; sy < tr.cy; ++sy) {
             const int ty = tr.sy + sy < B.nty ? tr.sy + sy : tr.sy + sy - B.nty;
-            const uint32_t tag = SCATTER && B.nkey > 1 ? (uint32_t)pair_class(r, B, ty) << kClassShift : 0u;
+            const uint32_t tag = SCATTER && B.nkey > 1 ? (uint32_t)row_class(cr, r, B, ty) << kClassShift : 0u;
             for (int sx = 0; sx < tr.cx; ++sx) {
                 const int tile = ty * B.ntx + (tr.sx + sx < B.ntx ? tr.sx + sx : tr.sx + sx - B.ntx);
                 const uint32_t slot = atomicAdd(&lds_bins[tile], 1u);

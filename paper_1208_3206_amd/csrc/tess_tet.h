@@ -619,16 +619,41 @@ TESS_HD inline int tet_tile(const BinParams &B, const TileRange &t, int s) {
     return ty * B.ntx + tx;
 }
 
-// Work class of a (record, tile) pair, 0 <= class < 32, for the tile row ty.
-// The raster's lanes step through their creases together, so a wavefront's
-// time follows its longest lanes; pairs of one class have about the same
-// number of active creases and rows, and the raster hands a wavefront's pairs
-// to its lanes in class order.  Estimated from the head alone (the row
-// profile of a crease-form record; every other record is class 0): the
-// creases whose rows meet the tile's, and their mean row count in it in
-// quarters of the tile height.  Only the order of work depends on it.
-TESS_HD inline int pair_class(const RecHead &r, const BinParams &B, int ty) {
-    if (!(r.flags & REC_CREASE)) return 0;
+// Work class of a (record, tile) pair, 0 <= class < 32.  The raster's lanes
+// step through their creases together, so a wavefront's time follows its
+// longest lanes; pairs of one class have about the same number of active
+// creases and rows, and the raster hands a wavefront's pairs to its lanes in
+// class order.  Estimated from the head alone (the row profile of a
+// crease-form record; every other record is class 0): the creases whose rows
+// meet the tile's, and their mean row count in it in quarters of the tile
+// height.  Only the order of work depends on it.
+struct ClassRows {
+    int lo[8], hi[8];  // record rows of each crease slot (empty: lo > hi)
+    bool crease;
+};
+
+TESS_HD inline ClassRows class_rows(const RecHead &r) {
+    ClassRows cr;
+    cr.crease = (r.flags & REC_CREASE) != 0;
+    const int sh = (int)((r.spare >> 25) & 31u);
+    int yb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) yb[v] = ((int)((r.spare >> (5 * v)) & 31u) << sh) + ((1 << sh) >> 1);
+    const int m = (int)(r.flags & REC_NG_MASK);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int k = c & 3;
+        const int k1 = k + 1 < m ? k + 1 : 0;
+        const int P = c < 4 ? yb[k] : yb[4], Q = c < 4 ? yb[k1] : yb[k];
+        cr.lo[c] = k < m ? min(P, Q) : 1;
+        cr.hi[c] = k < m ? max(P, Q) - 1 : 0;
+    }
+    return cr;
+}
+
+// the class for the tile row ty, from class_rows of the record
+TESS_HD inline int row_class(const ClassRows &cr, const RecHead &r, const BinParams &B, int ty) {
+    if (!cr.crease) return 0;
     const int ty0 = ty * B.Th;
     const int rows = min(B.Th, B.H - ty0);
     int lo = ty0 - range_lo(r.by);  // the tile's first row in record rows (the period nearest)
@@ -637,28 +662,21 @@ TESS_HD inline int pair_class(const RecHead &r, const BinParams &B, int ty) {
         if (lo >= B.H) lo -= B.H;
     }
     const int hi = lo + rows - 1;
-    const int sh = (int)((r.spare >> 25) & 31u);
-    int yb[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) yb[v] = ((int)((r.spare >> (5 * v)) & 31u) << sh) + ((1 << sh) >> 1);
-    const int m = (int)(r.flags & REC_NG_MASK);
     int nact = 0, nrows = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int k = c & 3;
-        if (k >= m) continue;
-        const int k1 = k + 1 < m ? k + 1 : 0;
-        const int P = c < 4 ? yb[k] : yb[4], Q = c < 4 ? yb[k1] : yb[k];
-        const int a = max(min(P, Q), lo), b = min(max(P, Q) - 1, hi);
-        if (a <= b) {
-            ++nact;
-            nrows += b - a + 1;
-        }
+        const int a = max(cr.lo[c], lo), b = min(cr.hi[c], hi);
+        nact += a <= b ? 1 : 0;
+        nrows += a <= b ? b - a + 1 : 0;
     }
     if (nact == 0) return 0;
     const int full = nact * rows;  // fill = floor(4 nrows / full), at most 3
     const int fill = 4 * nrows >= 3 * full ? 3 : 4 * nrows >= 2 * full ? 2 : 4 * nrows >= full ? 1 : 0;
     return (min(nact, 8) - 1) * 4 + fill;
+}
+
+TESS_HD inline int pair_class(const RecHead &r, const BinParams &B, int ty) {
+    return row_class(class_rows(r), r, B, ty);
 }
 
 // ----------------------------------------------------------------- raster

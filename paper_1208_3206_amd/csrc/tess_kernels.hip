@@ -492,10 +492,10 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             // apart, the line is gone from L2 before its next use)
             uint32_t ids[kIdBurst];
 #pragma unroll
-            for (int i = 0; i < kIdBurst; ++i) ids[i] = e + i < e1 ? pairs[it.first + e + i] & idmask : 0xffffffffu;
+            for (int i = 0; i < kIdBurst; ++i) ids[i] = e + i < e1 ? pairs[it.first + e + i] : 0xffffffffu;
             const int cnt = (int)min((uint32_t)kIdBurst, e1 - e);
             for (int i = 0; i < cnt; ++i) {
-                const uint32_t id = ids[0];
+                const uint32_t id = ids[0] & idmask;
 #pragma unroll
                 for (int j = 0; j + 1 < kIdBurst; ++j) ids[j] = ids[j + 1];
                 one(id);

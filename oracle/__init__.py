@@ -39,6 +39,7 @@ class OrcProblem(ctypes.Structure):
         ("qpow", ctypes.c_int32),
         ("slab", ctypes.c_int32),
         ("slab_t", ctypes.c_double * 2),
+        ("perspective", ctypes.c_int32),
     ]
 
 # projected per-tetrahedron value q = rho^p by name (view["quantity"])
@@ -109,6 +110,7 @@ def _problem(dims: Sequence[int], view: Dict, box=(1.0, 1.0, 1.0), periodic: boo
     p.slab = 1 if slab is not None else 0
     if slab is not None:
         p.slab_t[0], p.slab_t[1] = float(slab[0]), float(slab[1])
+    p.perspective = 1 if view.get("projection", "orthographic") == "perspective" else 0
     return p
 
 

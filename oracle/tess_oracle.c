@@ -47,6 +47,13 @@
  *  7. I += q * dl with Neumaier-compensated FP64 sums.  With image wrap
  *     the pixel index is taken modulo (W, H); otherwise pixels outside the
  *     window are dropped.
+ *  Perspective view (the camera point c of Eq. Eqn:TetSum, the camera inside
+ *  the volume of the large-scale figure): c is the camera, R its axes, and
+ *  the pixel at (pu, pv) on the plane at unit distance along the view
+ *  direction sees the half-line {s (pu, pv, 1) : s >= 0} in view space; a face
+ *  with n . d == 0 excludes it when h < 0 (and on the plane, h == 0, by the
+ *  half-open rule above); dl = |(pu, pv, 1)| (s_exit - max(s_entry, 0)).  No
+ *  wrap and no slab.
  *
  * Determinism: region mode assigns every image row band to one thread and
  * visits tetrahedra in id order, so results do not depend on the thread
@@ -76,6 +83,7 @@ typedef struct {
     int32_t qpow;         /* projected value q = rho^qpow, qpow in {0, 1, 2} */
     int32_t slab;         /* 1: only the depths t in [slab_t[0], slab_t[1]] count */
     double slab_t[2];     /* depth t = third view coordinate, R (x - c) */
+    int32_t perspective;  /* 1: rays from the camera c (step 5 otherwise) */
 } orc_problem;
 
 typedef struct {
@@ -89,6 +97,7 @@ static const int TET_TABLE[6][4] = {
     {1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
 
 typedef struct {
+    int persp;            /* rays from the camera at the view-space origin */
     double q;             /* projected value rho^qpow */
     double s0, s1;        /* depth slab (-inf, inf without one) */
     double n[4][3];       /* outward normals in view space */
@@ -128,6 +137,7 @@ static int check_problem(const orc_problem *P) {
     if (!(P->total_mass > 0)) return ORC_EINVAL;
     if (P->qpow < 0 || P->qpow > 2) return ORC_EINVAL;
     if (P->slab && !(P->slab_t[0] < P->slab_t[1])) return ORC_EINVAL;
+    if (P->perspective && (P->wrap || P->slab)) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -204,12 +214,30 @@ static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
         t->n[a][0] = nn[0]; t->n[a][1] = nn[1]; t->n[a][2] = nn[2];
         t->h[a] = nn[0] * yv[b][0] + nn[1] * yv[b][1] + nn[2] * yv[b][2];
     }
-    double umin = yv[0][0], umax = yv[0][0], vmin = yv[0][1], vmax = yv[0][1];
+    t->persp = P->perspective;
+    double pu[4], pv[4];  /* the vertices on the image plane */
+    int behind = 0;
+    for (int m = 0; m < 4; ++m) {
+        if (P->perspective) {
+            if (!(yv[m][2] > 0)) behind = 1;
+            pu[m] = yv[m][0] / yv[m][2];
+            pv[m] = yv[m][1] / yv[m][2];
+        } else {
+            pu[m] = yv[m][0];
+            pv[m] = yv[m][1];
+        }
+    }
+    if (behind) {  /* a vertex at or behind the camera plane: any pixel may see it */
+        t->ix0 = 0; t->ix1 = P->width - 1;
+        t->iy0 = 0; t->iy1 = P->height - 1;
+        return 1;
+    }
+    double umin = pu[0], umax = pu[0], vmin = pv[0], vmax = pv[0];
     for (int m = 1; m < 4; ++m) {
-        if (yv[m][0] < umin) umin = yv[m][0];
-        if (yv[m][0] > umax) umax = yv[m][0];
-        if (yv[m][1] < vmin) vmin = yv[m][1];
-        if (yv[m][1] > vmax) vmax = yv[m][1];
+        if (pu[m] < umin) umin = pu[m];
+        if (pu[m] > umax) umax = pu[m];
+        if (pv[m] < vmin) vmin = pv[m];
+        if (pv[m] > vmax) vmax = pv[m];
     }
     double du = P->extent[0] / P->width, dv = P->extent[1] / P->height;
     double ul = -0.5 * P->extent[0], vb = -0.5 * P->extent[1];
@@ -222,8 +250,29 @@ static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
     return 1;
 }
 
+/* Length of the camera ray through (pu, pv) inside the tetrahedron. */
+static double clip_dl_persp(const orc_tet *t, double pu, double pv) {
+    double lo = 0.0, hi = INFINITY;  /* the half-line s >= 0 */
+    for (int f = 0; f < 4; ++f) {
+        double nd = t->n[f][0] * pu + t->n[f][1] * pv + t->n[f][2];
+        if (nd > 0) {
+            double q = t->h[f] / nd;
+            if (q < hi) hi = q;
+        } else if (nd < 0) {
+            double q = t->h[f] / nd;
+            if (q > lo) lo = q;
+        } else {
+            if (t->h[f] < 0) return 0.0;
+            if (t->h[f] == 0 && !(t->n[f][0] < 0 || (t->n[f][0] == 0 && t->n[f][1] < 0))) return 0.0;
+        }
+    }
+    if (!(hi > lo) || isinf(hi)) return 0.0;
+    return (hi - lo) * sqrt(pu * pu + pv * pv + 1.0);
+}
+
 /* Length of the ray at pixel centre (pu, pv) inside the tetrahedron. */
 static double clip_dl(const orc_tet *t, double pu, double pv) {
+    if (t->persp) return clip_dl_persp(t, pu, pv);
     double lo = -INFINITY, hi = INFINITY;
     for (int f = 0; f < 4; ++f) {
         double nd = t->n[f][2];
@@ -354,7 +403,7 @@ static void splat_one(const orc_problem *P, const double v[4][3], double mass, d
 
 int orc_splat_image(const orc_problem *P, const float *x, const float *y, const float *z, double *out,
                     orc_stats *st) {
-    if (check_problem(P) != ORC_OK || !x || !y || !z || !out) return ORC_EINVAL;
+    if (check_problem(P) != ORC_OK || P->perspective || !x || !y || !z || !out) return ORC_EINVAL;
     const int64_t ncube = n_cubes(P);
     const double mass = P->total_mass / (double)(6 * ncube);
     const int64_t npx = (int64_t)P->width * P->height;
@@ -382,7 +431,7 @@ int orc_splat_image(const orc_problem *P, const float *x, const float *y, const 
 int orc_splat_tets(const orc_problem *P, int64_t ntet, const double *verts, const double *mass,
                    double *out, orc_stats *st) {
     if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0) ||
-        P->qpow < 0 || P->qpow > 2 || ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out)
+        P->qpow < 0 || P->qpow > 2 || P->perspective || ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out)
         return ORC_EINVAL;
     const int64_t npx = (int64_t)P->width * P->height;
     double *comp = (double *)calloc((size_t)npx, sizeof(double));
@@ -403,7 +452,7 @@ int orc_splat_tets(const orc_problem *P, int64_t ntet, const double *verts, cons
 int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
                      const double *mass, double *out, orc_stats *st) {
     if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0) ||
-        P->qpow < 0 || P->qpow > 2)
+        P->qpow < 0 || P->qpow > 2 || (P->perspective && (P->wrap || P->slab)))
         return ORC_EINVAL;
     if (ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out) return ORC_EINVAL;
     int64_t npx = (int64_t)P->width * P->height;

@@ -312,6 +312,75 @@ def test_k_undisplaced_lattice_splats_around_the_column_density():
     assert np.abs(img / M - 1).max() < 0.2 and st["tets"] == 6 * n ** 3
 
 
+# ------------------------------------------------------------ P: perspective
+def box_chords(view):
+    """Length of every pixel's camera half-line inside the unit box, by the
+    slab method (independent of the tetrahedra)."""
+    R = np.asarray(view["rot"], dtype=np.float64).reshape(3, 3)
+    c = np.asarray(view["center"], dtype=np.float64)
+    W_, H_ = view["width"], view["height"]
+    pu = -0.5 * view["extent"][0] + (np.arange(W_) + 0.5) * (view["extent"][0] / W_)
+    pv = -0.5 * view["extent"][1] + (np.arange(H_) + 0.5) * (view["extent"][1] / H_)
+    U, V = np.meshgrid(pu, pv)
+    d = np.stack([U, V, np.ones_like(U)], -1) @ R          # world directions, rows of R^T
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t0 = (0.0 - c) / d
+        t1 = (1.0 - c) / d
+    lo = np.where(d != 0, np.minimum(t0, t1), np.where((c >= 0) & (c <= 1), -np.inf, np.inf))
+    hi = np.where(d != 0, np.maximum(t0, t1), np.where((c >= 0) & (c <= 1), np.inf, -np.inf))
+    s_in = np.maximum(lo.max(-1), 0.0)
+    s_out = hi.min(-1)
+    return np.maximum(s_out - s_in, 0.0) * np.linalg.norm(d, axis=-1)
+
+
+@pytest.mark.parametrize("camera,rot_seed", [((0.4, 0.55, -1.3), None), ((0.3, 0.62, 0.45), 3),
+                                              ((1.9, -0.7, 1.6), 5)])
+def test_p_undisplaced_lattice_is_the_box_chord(camera, rot_seed):
+    # periodic unit lattice, M = 1: density 1 exactly filling [0, 1]^3, so every
+    # pixel holds the length of its camera half-line inside the box; the
+    # camera outside, inside (half-line cut at the camera), and oblique
+    n = 8
+    R = np.eye(3) if rot_seed is None else W.random_rotations(1, seed=rot_seed)[0]
+    if camera[0] > 1.0:  # look back at the box centre
+        f = np.array([0.5, 0.5, 0.5]) - np.array(camera)
+        f /= np.linalg.norm(f)
+        u = np.cross([0.0, 0.0, 1.0], f)
+        u /= np.linalg.norm(u)
+        R = np.stack([u, np.cross(f, u), f])
+    view = W.perspective_view(R, camera, 40, 32, extent=(1.6, 1.3))
+    img, st = O.project_region(*W.undisplaced(n), (n,) * 3, view)
+    ref = box_chords(view)
+    assert ref.max() > 0.5
+    np.testing.assert_allclose(img, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_p_far_camera_is_the_orthographic_projection():
+    # a camera 1e6 box lengths away with a window of the box's size there sees
+    # nearly parallel rays: the orthographic image to ~W / (2 D) of a pixel
+    n = 12
+    xyz = W.zeldovich(n, 3, 1.5)
+    D = 1e6
+    ortho = W.z_view(32)
+    ortho["wrap"] = 0
+    persp = W.perspective_view(np.eye(3), (0.5, 0.5, 0.5 - D), 32, extent=(1.0 / D, 1.0 / D))
+    a, _ = O.project_region(*xyz, (n,) * 3, ortho)
+    b, _ = O.project_region(*xyz, (n,) * 3, persp)
+    cov = a > 1e-3 * a.mean()
+    assert cov.mean() > 0.5
+    np.testing.assert_allclose(b[cov], a[cov], rtol=1e-4)
+    assert abs(b.sum() / a.sum() - 1.0) < 1e-5
+
+
+def test_p_perspective_needs_no_wrap_and_no_slab():
+    n = 4
+    xyz = W.undisplaced(n)
+    for extra in ({"wrap": 1}, {"slab": (0.1, 0.3)}):
+        view = W.perspective_view(np.eye(3), (0.5, 0.5, -1.0), 8)
+        view.update(extra)
+        with pytest.raises(Exception):
+            O.project_region(*xyz, (n,) * 3, view)
+
+
 def test_c4_near_degenerate_tets():
     # z = q_z - A sin(2 pi q_z + phi): the first cell layer has thickness
     # 1/n - 2 A sin(pi/n) = delta/n for A = (1 - delta)/(2 n sin(pi/n)),

@@ -225,6 +225,17 @@ def z_view(width: int, height: int | None = None, box: float = 1.0) -> Dict:
                 extent=[box, box], width=int(width), height=int(height), wrap=1)
 
 
+def perspective_view(rot: np.ndarray, camera, width: int, height: int | None = None,
+                     extent=(1.0, 1.0)) -> Dict:
+    """Perspective view: a camera at ``camera`` with axes = rows of ``rot``
+    (screen u, screen v, view direction); ``extent`` is the window on the plane
+    at unit distance along the view direction."""
+    height = width if height is None else height
+    return dict(rot=np.asarray(rot, dtype=np.float64).ravel().tolist(),
+                center=[float(c) for c in camera], extent=[float(extent[0]), float(extent[1])],
+                width=int(width), height=int(height), wrap=0, projection="perspective")
+
+
 def rotated_view(rot: np.ndarray, width: int, height: int | None = None,
                  side: float = 2.0, center=(0.5, 0.5, 0.5)) -> Dict:
     """Orthographic view with rows of ``rot`` = (screen u, screen v, depth)."""

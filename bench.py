@@ -26,6 +26,11 @@ PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9          # 3.93e13 lane-ops/s
 # along the crease, floor it, the fraction phi from the crossing (2), and the
 # two second-difference entries D*phi and D - D*phi (2).
 OPS_PER_KINK = 6
+# A perspective view's raster evaluates every pixel of a footprint's box (the
+# chord is not piecewise linear along a row; tess_stats.kinks counts those
+# pixels): 4 faces x (n . d, 2; the quotient h / n . d, 1; the min or max, 1),
+# the ray length |(pu, pv, 1)| (3) and q times the chord (3).
+OPS_PER_RAY_PIXEL = 22
 # Its LDS traffic: two FP64 read-modify-writes.
 LDS_BYTES_PER_KINK = 2 * 16
 PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
@@ -391,7 +396,10 @@ def main():
     img = out.double()
     checksum = float(img.mean().item())
 
-    ops = OPS_PER_KINK * kinks
+    persp = view.get("projection") == "perspective"
+    ops_per_unit = OPS_PER_RAY_PIXEL if persp else OPS_PER_KINK
+    ops = ops_per_unit * kinks
+    lds_bytes = 16 * frags if persp else LDS_BYTES_PER_KINK * kinks  # one FP64 add per covered pixel
     raster_s = kernel["raster_ms"] * 1e-3
     achieved = ops / raster_s
     result = {
@@ -409,7 +417,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded Zel'dovich lattice, kmax %d, D %g)" % (w.kmax, w.growth[0]),
         "config": {"workload": w.name, "lattice": w.n, "tets": w.tets, "image": [w.width, w.height],
-                   "view": "z-projection, periodic", "determinant": args.precision,
+                   "view": ("perspective, camera at (%g, %g, %g) looking along +z, 90 degrees" % w.camera
+                            if persp else "z-projection, periodic"),
+                   "determinant": args.precision,
                    "quantity": args.quantity, "method": args.method,
                    "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"],
                    "block": st["block"]},
@@ -422,8 +432,8 @@ def main():
         "bin_pairs": st["bin_pairs"],
         "work_items": st["work_items"],
         "image_mean": checksum,
-        "lds_bytes_per_s_raster": LDS_BYTES_PER_KINK * kinks / raster_s,
-        "lds_frac_raster": LDS_BYTES_PER_KINK * kinks / raster_s / PEAK_LDS_BYTES,
+        "lds_bytes_per_s_raster": lds_bytes / raster_s,
+        "lds_frac_raster": lds_bytes / raster_s / PEAK_LDS_BYTES,
         "roofline": {
             "kernel": "k_raster",
             "bound": "alu",
@@ -433,7 +443,8 @@ def main():
             "frac": achieved / PEAK_VALU_OPS,
             "traffic": raster_traffic(w.name, (st["tile_rows"], st["tile_cols"]), st["block"]),
             "ops_per_launch": ops,
-            "ops_per_kink": OPS_PER_KINK,
+            "ops_per_kink": ops_per_unit,
+            "unit_of_work": "pixel evaluated (perspective)" if persp else "kink",
         },
         "fragment_equivalent": {
             "ops_per_fragment": OPS_PER_FRAGMENT,

@@ -97,12 +97,16 @@ tess_status tess_build(const tess_build_desc *desc, const float *x, const float 
 /* Releases a handle (and the positions it owns).  NULL is accepted. */
 void tess_free(tess_lattice lat);
 
-/* Orthographic view (the paper's parallel projection of the tetrahedra). */
+/* View: orthographic (the paper's parallel projection of the tetrahedra) or,
+ * with projection = TESS_PROJECTION_PERSPECTIVE, from a camera point. */
 typedef struct {
     double rot[9];          /* row-major; rows = screen u, screen v, view direction;
                                must be orthonormal (|R R^T - I| <= 1e-9)          */
-    double center[3];       /* world point at the image centre                    */
-    double extent[2];       /* window size (Su, Sv) in world units, > 0           */
+    double center[3];       /* world point at the image centre; perspective: the
+                               camera                                            */
+    double extent[2];       /* window size (Su, Sv) in world units, > 0;
+                               perspective: on the plane at unit distance along
+                               the view direction                                */
     int32_t width, height;  /* pixels, 1 .. 16384 each                            */
     int32_t wrap;           /* 1: periodic image (pixel index modulo width/height);
                                requires rot to be an axis permutation with signs,
@@ -118,8 +122,20 @@ typedef struct {
     double slab_t[2];       /* slab_t[0] < slab_t[1], finite, when slab = 1      */
     int32_t method;         /* tess_method; 0, the zero-initialised default, is
                                the exact projection of the tessellation          */
-    int32_t reserved;       /* 0                                                  */
+    int32_t projection;     /* tess_projection; 0, the default, is orthographic  */
 } tess_view;
+
+/* The rays of a view.  Perspective (the camera point c of Eq. Eqn:TetSum; the
+ * large-scale figure puts the camera inside the volume): the pixel at
+ * (pu, pv) on the window sees the half-line c + s R^T (pu, pv, 1), s >= 0, and
+ * dl is that half-line's Euclidean length inside T.  It needs wrap = 0, no
+ * slab and the tessellation method; the raster then evaluates every covered
+ * pixel (the chord is not piecewise linear along a row), so it costs per
+ * fragment. */
+typedef enum {
+    TESS_PROJECTION_ORTHOGRAPHIC = 0,
+    TESS_PROJECTION_PERSPECTIVE = 1
+} tess_projection;
 
 /* How the tetrahedra are drawn.  TESS_METHOD_CENTROIDS is the centroid
  * section's approximation: each tetrahedron T is a 2D cubic-spline kernel

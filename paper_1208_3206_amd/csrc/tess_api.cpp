@@ -172,7 +172,11 @@ extern "C" tess_status tess_check_view(const tess_view *v, const tess_build_desc
         return fail(TESS_EINVAL, "method must be 0 (tessellation) or 1 (centroids)");
     if (v->method == TESS_METHOD_CENTROIDS && v->slab)
         return fail(TESS_EINVAL, "the centroid method takes no slab");
-    if (v->reserved != 0) return fail(TESS_EINVAL, "view.reserved must be 0");
+    if (v->projection != TESS_PROJECTION_ORTHOGRAPHIC && v->projection != TESS_PROJECTION_PERSPECTIVE)
+        return fail(TESS_EINVAL, "projection must be 0 (orthographic) or 1 (perspective)");
+    if (v->projection == TESS_PROJECTION_PERSPECTIVE &&
+        (v->wrap || v->slab || v->method != TESS_METHOD_TESSELLATION))
+        return fail(TESS_EINVAL, "a perspective view takes no wrap, no slab and the tessellation method");
     if (v->slab && !(std::isfinite(v->slab_t[0]) && std::isfinite(v->slab_t[1]) && v->slab_t[0] < v->slab_t[1]))
         return fail(TESS_EINVAL, "slab needs finite slab_t[0] < slab_t[1]");
     if (v->wrap) {
@@ -337,9 +341,10 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     vp.slab_t[0] = v->slab ? v->slab_t[0] : 0.0;
     vp.slab_t[1] = v->slab ? v->slab_t[1] : 0.0;
     vp.splat = v->method == TESS_METHOD_CENTROIDS ? 1 : 0;
+    vp.persp = v->projection == TESS_PROJECTION_PERSPECTIVE ? 1 : 0;
     // q / rho needs |V| to full precision (the face form stores q itself, a
     // splat q |V| and |V|^(1/3))
-    if (vp.qpow != 1 || vp.slab || vp.splat) lp.det_cond_k = -1.0;
+    if (vp.qpow != 1 || vp.slab || vp.splat || vp.persp) lp.det_cond_k = -1.0;
 }
 
 struct Plan {
@@ -402,7 +407,9 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.ntet = (uint32_t)g.ntet;
     B.slab_t[0] = g.vp.slab_t[0];
     B.slab_t[1] = g.vp.slab_t[1];
-    B.direct = g.vp.splat;
+    B.direct = g.vp.splat || g.vp.persp;
+    B.ext_u = v->extent[0];
+    B.ext_v = v->extent[1];
     B.form = view_form(g.vp);
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
@@ -436,7 +443,7 @@ tess_status ensure_back(Workspace &ws, const Geometry &g, int chunk, unsigned lo
 // Setup of one image; for q = 1 first the integral of q into slot->qsum.
 tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipStream_t s) {
     ViewParams vp = g.vp;
-    if (vp.qpow == 0 && !vp.slab && !vp.splat) {
+    if (vp.qpow == 0 && !vp.slab && !vp.splat && !vp.persp) {
         TESS_HIP(launch_zero(&slot->qsum, 1, s));
         TESS_HIP(launch_qsum(g.lp, vp, &slot->qsum, s));
         vp.qsum = &slot->qsum;

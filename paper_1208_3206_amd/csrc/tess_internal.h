@@ -39,13 +39,14 @@ struct ViewParams {
     int32_t slab;            // 1: only depths in [slab_t[0], slab_t[1]] count (face form)
     double slab_t[2];        // depth t = third view coordinate, R (x - c)
     int32_t splat;           // 1: centroid splats instead of the tessellation
+    int32_t persp;           // 1: rays from the camera at `center` (perspective)
 };
 
 // Record kinds of a launch (one per view): the pyramid (crease and line
 // forms), the face form of a depth slab, centroid splats.
-constexpr int kFormPyramid = 0, kFormFace = 1, kFormSplat = 2;
+constexpr int kFormPyramid = 0, kFormFace = 1, kFormSplat = 2, kFormPersp = 3;
 __host__ __device__ inline int view_form(const ViewParams &V) {
-    return V.splat ? kFormSplat : (V.slab ? kFormFace : kFormPyramid);
+    return V.persp ? kFormPersp : V.splat ? kFormSplat : (V.slab ? kFormFace : kFormPyramid);
 }
 
 // Screen tiling: tiles of Th rows x Tw columns (a row band when Tw >= W).
@@ -59,8 +60,9 @@ struct BinParams {
     int32_t nkey;            // work classes carried by pair ids (32), or 1: plain ids
     uint32_t ntet;           // number of records
     double slab_t[2];        // depth slab of face-form records (the view's)
-    int32_t direct;          // 1: the accumulator holds values (splats), not second differences
-    int32_t form;            // the records' kind (kFormPyramid, kFormFace, kFormSplat)
+    int32_t direct;          // 1: the accumulator holds values (splats, perspective), not second differences
+    int32_t form;            // the records' kind (kFormPyramid, kFormFace, kFormSplat, kFormPersp)
+    double ext_u, ext_v;     // the view's window (perspective: pixel rays)
 };
 
 // Pair-list entries: the record id, with the pair's work class (0..31) in
@@ -135,6 +137,7 @@ constexpr uint32_t REC_FACE_TYPE_SHIFT = 10;  // face g: 2 bits at 10 + 2 g
 constexpr uint32_t REC_FACE_TIE_SHIFT = 18;   // face g's wall keeps pixels on its line
 constexpr uint32_t REC_FACE_FRONT = 1u, REC_FACE_BACK = 2u, REC_FACE_WALL = 3u;
 constexpr uint32_t REC_SPLAT = 1u << 22;      // payload is a centroid splat
+constexpr uint32_t REC_PERSP = 1u << 23;      // payload: camera-frame vertices and q
 
 struct alignas(128) Payload {
     double c[14];

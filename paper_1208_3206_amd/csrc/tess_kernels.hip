@@ -104,6 +104,10 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
             hipLaunchKernelGGL((k_setup<kFormSplat>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
                                counters);
             break;
+        case kFormPersp:
+            hipLaunchKernelGGL((k_setup<kFormPersp>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
+                               counters);
+            break;
         default:
             hipLaunchKernelGGL((k_setup<kFormPyramid>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
                                counters);
@@ -445,7 +449,23 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     // the tile instead of stacking their atomics on the same LDS cells
     const uint32_t per = (it.count + TPB - 1) / TPB;
     const uint32_t e0 = threadIdx.x * per, e1 = min(it.count, e0 + per);
-    if (FORM == kFormPyramid && sorted) {
+    if constexpr (FORM == kFormPersp) {
+        // per pixel, and a footprint may fill the tile: each wavefront takes
+        // its share of the list one pair at a time, its 64 lanes striding over
+        // the pair's pixels
+        const uint32_t nw = TPB / 64, lane = threadIdx.x & 63u;
+        const uint32_t wper = (it.count + nw - 1) / nw;
+        const uint32_t w0 = (threadIdx.x >> 6) * wper, w1 = min(it.count, w0 + wper);
+        for (uint32_t e = w0; e < w1; ++e) {
+            const uint32_t id = pairs[it.first + e];
+            if (id >= B.ntet) continue;
+            const RecHead h = coef[id].h;
+            if (!(h.flags & REC_VALID)) continue;
+            frags += persp_pair(h, coef[id].c, B, tx0, ty0, n, rows, (int)lane, 64,
+                                [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                                spans, kinks);
+        }
+    } else if (FORM == kFormPyramid && sorted) {
         // The wavefront takes the next kSortPer entries of each of its lanes'
         // slices and deals them back out in work-class order (a counting sort
         // in its own LDS area): the lanes that step through their creases
@@ -554,6 +574,9 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_
                                       stream, lds);
     else if (B.form == kFormSplat)
         launch_raster_form<kFormSplat>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+                                       stream, lds);
+    else if (B.form == kFormPersp)
+        launch_raster_form<kFormPersp>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                        stream, lds);
     else
         launch_raster_form<kFormPyramid>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc,

@@ -464,6 +464,68 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 R.flags = REC_SPLAT | REC_VALID;
                 return;
             }
+            if constexpr (FORM == kFormPersp) {
+                // a camera at V.center: the vertices in the camera frame (the
+                // raster clips each pixel's half-line against the faces), q,
+                // and the pixel box of their projection onto the window
+                const double rho = L.tet_mass * 6.0 / fabs(det6);
+                const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
+                const int vi[4] = {v0, v1, v2, v3};
+                double ybase[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) ybase[r] = V.rot[3 * r] * b0[0] + V.rot[3 * r + 1] * b0[1] + V.rot[3 * r + 2] * b0[2];
+                bool behind = false;
+                double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+                // frustum culling: the window's edges widened by a pixel; a
+                // tetrahedron with all four vertices beyond one side plane
+                // (u z < ul, u z > ur, ...) or at or behind the camera is unseen
+                const double ul = V.u_left - 1.0 / V.inv_du, ur = -V.u_left + 1.0 / V.inv_du;
+                const double vb = V.v_bottom - 1.0 / V.inv_dv, vt = -V.v_bottom + 1.0 / V.inv_dv;
+                int out_l = 0, out_r = 0, out_b = 0, out_t = 0, out_z = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    double yv[3];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+                        yv[r] = ybase[r] + (V.rot[3 * r] * e[vi[m]][0] + V.rot[3 * r + 1] * e[vi[m]][1] +
+                                            V.rot[3 * r + 2] * e[vi[m]][2]);
+                    pc[3 * m + 0] = yv[0];
+                    pc[3 * m + 1] = yv[1];
+                    pc[3 * m + 2] = yv[2];
+                    if (!(yv[2] > 0.0)) behind = true;
+                    out_z += yv[2] > 0.0 ? 0 : 1;
+                    out_l += yv[0] < ul * yv[2] ? 1 : 0;
+                    out_r += yv[0] > ur * yv[2] ? 1 : 0;
+                    out_b += yv[1] < vb * yv[2] ? 1 : 0;
+                    out_t += yv[1] > vt * yv[2] ? 1 : 0;
+                    const double pu = yv[0] / yv[2], pv = yv[1] / yv[2];
+                    umin = fmin(umin, pu); umax = fmax(umax, pu);
+                    vmin = fmin(vmin, pv); vmax = fmax(vmax, pv);
+                }
+                pc[12] = qv;
+                if (out_z == 4 || out_l == 4 || out_r == 4 || out_b == 4 || out_t == 4) {
+#pragma unroll
+                    for (int g = 0; g < 14; ++g) pc[g] = 0.0;
+                    return;
+                }
+                int ix0 = 0, ix1 = V.W - 1, iy0 = 0, iy1 = V.H - 1;  // behind: any pixel
+                if (!behind) {  // pixel centres in the projected box, one pixel of margin
+                    const double lim = 1.0e8;
+                    ix0 = max(ix0, (int)fmax(ceil((umin - V.u_left) * V.inv_du - 0.5) - 1.0, -lim));
+                    ix1 = min(ix1, (int)fmin(floor((umax - V.u_left) * V.inv_du - 0.5) + 1.0, lim));
+                    iy0 = max(iy0, (int)fmax(ceil((vmin - V.v_bottom) * V.inv_dv - 0.5) - 1.0, -lim));
+                    iy1 = min(iy1, (int)fmin(floor((vmax - V.v_bottom) * V.inv_dv - 0.5) + 1.0, lim));
+                }
+                if (ix0 > ix1 || iy0 > iy1) {
+#pragma unroll
+                    for (int g = 0; g < 14; ++g) pc[g] = 0.0;
+                    return;
+                }
+                R.bx = pack_range(ix0, ix1);
+                R.by = pack_range(iy0, iy1);
+                R.flags = REC_PERSP | REC_VALID;
+                return;
+            }
             // ---- screen footprint (FP64)
             const int vi[4] = {v0, v1, v2, v3};
             double xmin = PX[v0], xmax = PX[v0], ymin = PY[v0], ymax = PY[v0];
@@ -1277,6 +1339,86 @@ TESS_HD inline uint32_t splat_pair(const RecHead &h, const double *cf, const Bin
     return frags;
 }
 
+// ---------------------------------------------------- perspective camera
+// A perspective record's chords at the tile's pixel centres, added as values:
+// dep(row, u, q dl) for the tile column u.  The pixel at (pu, pv) on the
+// window sees the half-line s (pu, pv, 1), s >= 0, in the camera frame; it is
+// clipped against the four outward face planes n . y <= h (n . d == 0: the
+// ray is out when h < 0, and on the plane by the orthographic raster's
+// half-open rule), and dl = |(pu, pv, 1)| (s_out - s_in).  Footprints range
+// from a pixel to whole tiles (next to the camera), so the pixels of the
+// record's box in the tile are shared out: this call takes those with
+// row-major index k = lane0, lane0 + nlanes, ...  Returns the pixels with
+// dl > 0; kinks counts the pixels evaluated.
+template <typename Dep>
+TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0, int ty0,
+                                   int n, int rows, int lane0, int nlanes, Dep &&dep, uint32_t &spans,
+                                   uint32_t &kinks) {
+    const int x0 = max(range_lo(h.bx), tx0), x1 = min(range_hi(h.bx), tx0 + n - 1);
+    const int y0 = max(range_lo(h.by), ty0), y1 = min(range_hi(h.by), ty0 + rows - 1);
+    if (x0 > x1 || y0 > y1) return 0;
+    double nrm[4][3], off[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int b = (a + 1) & 3, c = (a + 2) & 3, d = (a + 3) & 3;
+        double e1[3], e2[3], ea[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            e1[q] = cf[3 * c + q] - cf[3 * b + q];
+            e2[q] = cf[3 * d + q] - cf[3 * b + q];
+            ea[q] = cf[3 * a + q] - cf[3 * b + q];
+        }
+        double nn[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        if (nn[0] * ea[0] + nn[1] * ea[1] + nn[2] * ea[2] > 0.0) {
+            nn[0] = -nn[0];
+            nn[1] = -nn[1];
+            nn[2] = -nn[2];
+        }
+        nrm[a][0] = nn[0];
+        nrm[a][1] = nn[1];
+        nrm[a][2] = nn[2];
+        off[a] = nn[0] * cf[3 * b] + nn[1] * cf[3 * b + 1] + nn[2] * cf[3 * b + 2];
+    }
+    const double q = cf[12];
+    const double du = B.ext_u / (double)B.W, dv = B.ext_v / (double)B.H;
+    const int bw = x1 - x0 + 1, npix = bw * (y1 - y0 + 1);
+    if (lane0 == 0) spans += (uint32_t)(y1 - y0 + 1);
+    // row-major walk of the box: k -> (y, x), stepping nlanes at a time
+    int y = y0 + lane0 / bw, x = x0 + lane0 % bw;
+    const int sy = nlanes / bw, sx = nlanes % bw;
+    uint32_t frags = 0;
+    for (int k = lane0; k < npix; k += nlanes) {
+        const double pu = -0.5 * B.ext_u + ((double)x + 0.5) * du;
+        const double pv = -0.5 * B.ext_v + ((double)y + 0.5) * dv;
+        ++kinks;
+        double lo = 0.0, hi = 1e300;
+        bool out = false;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const double nd = nrm[f][0] * pu + nrm[f][1] * pv + nrm[f][2];
+            if (nd > 0.0) {
+                hi = fmin(hi, off[f] * fast_rcp(nd));
+            } else if (nd < 0.0) {
+                lo = fmax(lo, off[f] * fast_rcp(nd));
+            } else if (off[f] < 0.0 ||
+                       (off[f] == 0.0 && !(nrm[f][0] < 0.0 || (nrm[f][0] == 0.0 && nrm[f][1] < 0.0)))) {
+                out = true;
+            }
+        }
+        if (!out && hi > lo && hi < 1e300) {
+            dep(y - ty0, x - tx0, q * ((hi - lo) * sqrt(pu * pu + pv * pv + 1.0)));
+            ++frags;
+        }
+        x += sx;
+        y += sy;
+        if (x > x1) {
+            x -= bw;
+            ++y;
+        }
+    }
+    return frags;
+}
+
 // One record in one tile, in whichever form its payload has.
 // (A launch holds records of one kind: pyramids in crease or line form, face
 // form with a depth slab, or splats; FORM selects it at compile time.)
@@ -1288,6 +1430,8 @@ TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const 
         return face_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     } else if constexpr (FORM == kFormSplat) {
         return splat_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+    } else if constexpr (FORM == kFormPersp) {
+        return persp_pair(h, cf, B, tx0, ty0, n, rows, 0, 1, dep, spans, kinks);
     } else {
         if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
         return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);

@@ -17,7 +17,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                            int32_t periodic, double total_mass, int32_t precision, const double rot[9],
                            const double center[3], const double extent[2], int32_t W, int32_t H,
                            int32_t wrap, int32_t tile_rows, int32_t tile_cols, int32_t chunk,
-                           double crease_div, int32_t qpow, const double *slab, int32_t splat,
+                           double crease_div, int32_t qpow, const double *slab, int32_t splat, int32_t persp,
                            double *out64, float *out32,
                            long long *stats /* [tets, zero, inverted, fp64_dets, fragments, spans,
                                                pairs, items, crease_records] */) {
@@ -34,7 +34,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     L.tet_mass = total_mass / (6.0 * (double)L.ncubes);
     L.v0 = 1.0 / (6.0 * (double)L.ncubes);
     L.det_v0_frac = 1e-6;
-    L.det_cond_k = (precision || qpow != 1 || slab || splat) ? -1.0 : 1e3;
+    L.det_cond_k = (precision || qpow != 1 || slab || splat || persp) ? -1.0 : 1e3;
     ViewParams V;
     for (int i = 0; i < 9; ++i) V.rot[i] = rot[i];
     for (int i = 0; i < 3; ++i) V.center[i] = center[i];
@@ -47,6 +47,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.W = W; V.H = H; V.wrap = wrap; V.qpow = qpow;
     V.slab = slab ? 1 : 0;
     V.splat = splat;
+    V.persp = persp;
     V.slab_t[0] = slab ? slab[0] : 0.0;
     V.slab_t[1] = slab ? slab[1] : 0.0;
     // q != rho: the crease threshold from the integral of q (as the library)
@@ -54,7 +55,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.qsum = nullptr;
     V.bmax_per_q = crease_div > 0 ? V.inv_du * V.inv_dv / ((double)W * H) / crease_div : -1.0;
     if (qpow == 2) V.crease_bmax *= L.tet_mass / L.v0;
-    if (qpow == 0 && !slab && !splat) {
+    if (qpow == 0 && !slab && !splat && !persp) {
         for (int64_t cube = 0; cube < L.ncubes; ++cube) qsum += cube_qvol(L, V, cube);
         V.qsum = &qsum;
     }
@@ -64,7 +65,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0;
     for (int64_t cube = 0; cube < L.ncubes; ++cube) {
         CubeCounts cnt;
-        if (splat) setup_cube<kFormSplat>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        if (persp) setup_cube<kFormPersp>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        else if (splat) setup_cube<kFormSplat>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else if (slab) setup_cube<kFormFace>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else setup_cube<kFormPyramid>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
@@ -81,9 +83,11 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     B.ntet = (uint32_t)ntet;
     B.slab_t[0] = V.slab_t[0];
     B.slab_t[1] = V.slab_t[1];
-    B.direct = splat;
+    B.direct = splat || persp;
+    B.ext_u = extent[0];
+    B.ext_v = extent[1];
     const int ntiles = B.ntx * B.nty;
-    B.nkey = (splat || slab) ? 1 : 32;
+    B.nkey = (splat || slab || persp) ? 1 : 32;
     // per tile: its records in id order; every pair's work class in range
     std::vector<std::vector<uint32_t>> lists(ntiles);
     for (int64_t id = 0; id < ntet; ++id) {
@@ -113,7 +117,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                 const uint32_t id = lst[e];
                 uint32_t sp = 0, kk = 0;
                 auto rr = [&](auto &&dep) {
-                    return splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
+                    return persp ? raster_record<kFormPersp>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
+                         : splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
                          : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
                                 : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk);
                 };
@@ -132,7 +137,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         double d1 = 0.0, f = 0.0;
         for (int ix = 0; ix < W; ++ix) {
             d1 += acc[(size_t)iy * W + ix];
-            f = splat ? acc[(size_t)iy * W + ix] : f + d1;
+            f = (splat || persp) ? acc[(size_t)iy * W + ix] : f + d1;
             if (out64) out64[(size_t)iy * W + ix] = f;
             if (out32) out32[(size_t)iy * W + ix] = (float)std::fmax(f, 0.0);
         }

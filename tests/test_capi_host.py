@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import workloads as W
@@ -101,8 +102,14 @@ def test_view_validation(tess):
     v = tess.make_view(W.z_view(64))
     v.method = 2
     assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
-    v.method, v.reserved = 0, 1
+    v.method, v.projection = 0, 2
     assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
+    # perspective: no wrap, no slab, the tessellation method
+    persp = W.perspective_view(np.eye(3), (0.5, 0.5, -1.0), 64)
+    tess.check_view(persp, d)
+    for bad in (dict(persp, wrap=1), dict(persp, slab=(0.0, 0.1)), dict(persp, method="centroids")):
+        with pytest.raises(tess.TessError):
+            tess.check_view(bad, d)
     # depth slabs: finite and ordered
     tess.check_view(dict(W.z_view(64), slab=(-0.1, 0.2)), d)
     for bad in ((0.2, 0.2), (0.3, -0.1), (float("nan"), 0.1), (-float("inf"), 0.0)):

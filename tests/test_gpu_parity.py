@@ -192,6 +192,37 @@ def test_centroid_splats(tess, tiny_lattice):
     assert_parity(got, ref, what="centroids tiny 32^3 -> 256^2")
 
 
+@pytest.mark.parametrize("camera,quantity", [((0.45, 0.52, -1.4), "density"), ((0.37, 0.58, 0.41), "density"),
+                                             ((0.61, 0.3, -0.9), "density2")])
+def test_perspective_camera(tess, camera, quantity):
+    # rays from a camera outside the volume and inside it; every covered
+    # pixel is evaluated, so the bar is the orthographic one
+    n = 16
+    xyz = W.zeldovich(n, 5, 3.0, seed=9)
+    R = W.random_rotations(1, seed=4)[0] if camera[2] > 0 else np.eye(3)
+    view = dict(W.perspective_view(R, camera, 96, 80, extent=(1.5, 1.2)), quantity=quantity)
+    got, st = gpu_image(tess, xyz, (n, n, n), view)
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert_quantity_parity(got, ref, quantity, what=f"perspective {camera} {quantity}")
+    assert st["tets"] == ost["tets"]
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-5 * ost["fragments"]
+
+
+def test_perspective_workload_sampled_pixels(tess):
+    # the perspective workload at its size: the mid field, camera inside it
+    w = W.PERSPECTIVE
+    xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
+    view = W.workload_views(w)[0]
+    got, st = gpu_image(tess, xyz, (w.n,) * 3, view)
+    px, py = sample_pixels(w.width, w.height, 80, 11)
+    ref, _ = O.project_pixels(*xyz, (w.n,) * 3, view, px, py)
+    r = rel_err(got[py, px], ref)
+    print(f"perspective: sampled max rel {r.max():.3e}, fragments {st['fragments']:.4e}, {st['ms']:.1f} ms",
+          flush=True)
+    assert r.max() <= PIX_TOL
+    assert st["tets"] == w.tets
+
+
 def test_fp64_determinant_path(tess, tiny_lattice):
     view = W.z_view(128, 96)
     got, st = gpu_image(tess, tiny_lattice, (32, 32, 32), view, precision="fp64")

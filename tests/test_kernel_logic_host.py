@@ -133,6 +133,21 @@ def test_centroid_splats_match_oracle(view_kind, quantity):
     assert st["fragments"] == ost["fragments"] and st["tets"] == ost["tets"]
 
 
+@pytest.mark.parametrize("camera,quantity", [((0.45, 0.52, -1.4), "density"), ((0.37, 0.58, 0.41), "density"),
+                                             ((0.37, 0.58, 0.41), "unit"), ((0.61, 0.3, -0.9), "density2")])
+def test_perspective_matches_oracle(camera, quantity):
+    # a camera outside the volume and one inside it (half-lines cut at the
+    # camera, tetrahedra behind it skipped, ones around it on every pixel)
+    n = 12
+    xyz = W.zeldovich(n, 4, 3.0, seed=9)
+    R = W.random_rotations(1, seed=4)[0] if camera[2] > 0 else np.eye(3)
+    view = dict(W.perspective_view(R, camera, 72, 56, extent=(1.5, 1.2)), quantity=quantity)
+    img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=8, tile_cols=40, chunk=500)
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert np.abs(img - ref).max() <= 1e-11 * np.abs(ref).max()
+    assert st["fragments"] == ost["fragments"] and st["tets"] == ost["tets"]
+
+
 def test_tallest_tiles_match_oracle():
     # 256-row tiles (the largest the library accepts): row offsets of up to 255
     # inside a tile, footprints taller than the lattice spacing wrapping in y

@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, List, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -50,6 +50,7 @@ class Workload:
     width: int
     height: int
     n_views: int = 1  # 1: z-projection with wrap; >1: seeded random rotations
+    camera: Optional[Tuple[float, float, float]] = None  # perspective camera (looking along +z)
 
     @property
     def tets(self) -> int:
@@ -67,7 +68,12 @@ LEARNED_REF = Workload("learned_ref_256^3_D5_to_2048^2", 256, 16, (5.0,), 2048, 
 # resampling: the mid field into 128 depth slabs of 128^2 (a 128^3 grid)
 RESAMPLE = Workload("resample_128^3_to_128^3", 128, 32, (5.0,), 128, 128)
 
-ALL = {w.name: w for w in (TINY, MID, STRESS, STRESS_4K, BATCHED, LEARNED, LEARNED_REF, RESAMPLE)}
+# perspective: the mid field seen by a camera inside the volume, 90 degrees wide
+PERSPECTIVE = Workload("perspective_128^3_inside_to_1024^2", 128, 32, (5.0,), 1024, 1024,
+                       camera=(0.5, 0.5, 0.05))
+
+ALL = {w.name: w for w in (TINY, MID, STRESS, STRESS_4K, BATCHED, LEARNED, LEARNED_REF, RESAMPLE,
+                           PERSPECTIVE)}
 
 
 # --------------------------------------------------------------------------
@@ -255,6 +261,8 @@ def slab_views(width: int, slabs: int, box: float = 1.0) -> List[Dict]:
 
 
 def workload_views(w: Workload) -> List[Dict]:
+    if w.camera is not None:
+        return [perspective_view(np.eye(3), w.camera, w.width, w.height, extent=(2.0, 2.0))]
     if w.n_views == 1:
         return [z_view(w.width, w.height)]
     return [rotated_view(r, w.width, w.height) for r in random_rotations(w.n_views)]

@@ -40,6 +40,8 @@ class OrcProblem(ctypes.Structure):
         ("slab", ctypes.c_int32),
         ("slab_t", ctypes.c_double * 2),
         ("perspective", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("lod_radius", ctypes.c_double),
     ]
 
 # projected per-tetrahedron value q = rho^p by name (view["quantity"])
@@ -111,6 +113,9 @@ def _problem(dims: Sequence[int], view: Dict, box=(1.0, 1.0, 1.0), periodic: boo
     if slab is not None:
         p.slab_t[0], p.slab_t[1] = float(slab[0]), float(slab[1])
     p.perspective = 1 if view.get("projection", "orthographic") == "perspective" else 0
+    if p.perspective:  # orthographic centroids go through splat_image / splat_tets
+        p.method = {"tessellation": 0, "centroids": 1, "hybrid": 2}[view.get("method", "tessellation")]
+        p.lod_radius = float(view.get("lod_radius", 0.0))
     return p
 
 

@@ -54,6 +54,14 @@
  *  with n . d == 0 excludes it when h < 0 (and on the plane, h == 0, by the
  *  half-open rule above); dl = |(pu, pv, 1)| (s_exit - max(s_entry, 0)).  No
  *  wrap and no slab.
+ *  Centroids and the near/far hybrid under the perspective camera (the
+ *  centroid section's billboards; the large-scale figure's hybrid): a
+ *  billboard faces the view direction at T's centroid y_c (camera frame) and
+ *  adds q |V| W(r, h) to the pixel whose ray crosses its plane at distance
+ *  r = z_c |(pu, pv) - (x_c, y_c) / z_c| from y_c, h = |V|^(1/3), W the 2D
+ *  cubic spline of orc_splat_image; only centroids in front of the camera
+ *  (z_c > 0) are drawn.  Hybrid: T within lod_radius of the camera (|y_c|
+ *  <= lod_radius) is clipped exactly, the rest are billboards.
  *
  * Determinism: region mode assigns every image row band to one thread and
  * visits tetrahedra in id order, so results do not depend on the thread
@@ -84,6 +92,8 @@ typedef struct {
     int32_t slab;         /* 1: only the depths t in [slab_t[0], slab_t[1]] count */
     double slab_t[2];     /* depth t = third view coordinate, R (x - c) */
     int32_t perspective;  /* 1: rays from the camera c (step 5 otherwise) */
+    int32_t method;       /* perspective: 0 exact, 1 centroid billboards, 2 hybrid */
+    double lod_radius;    /* hybrid: exact within this distance of the camera */
 } orc_problem;
 
 typedef struct {
@@ -98,6 +108,8 @@ static const int TET_TABLE[6][4] = {
 
 typedef struct {
     int persp;            /* rays from the camera at the view-space origin */
+    int splat;            /* a billboard (perspective centroids): q = q |V|, */
+    double uc, vc, zc, hh;  /* window centre, depth, kernel size */
     double q;             /* projected value rho^qpow */
     double s0, s1;        /* depth slab (-inf, inf without one) */
     double n[4][3];       /* outward normals in view space */
@@ -138,6 +150,8 @@ static int check_problem(const orc_problem *P) {
     if (P->qpow < 0 || P->qpow > 2) return ORC_EINVAL;
     if (P->slab && !(P->slab_t[0] < P->slab_t[1])) return ORC_EINVAL;
     if (P->perspective && (P->wrap || P->slab)) return ORC_EINVAL;
+    if (P->method < 0 || P->method > 2 || (P->method && !P->perspective)) return ORC_EINVAL;
+    if (P->method == 2 && !(P->lod_radius >= 0.0 && isfinite(P->lod_radius))) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -215,6 +229,47 @@ static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
         t->h[a] = nn[0] * yv[b][0] + nn[1] * yv[b][1] + nn[2] * yv[b][2];
     }
     t->persp = P->perspective;
+    t->splat = 0;
+    if (P->perspective && P->method != 0) {
+        double yc[3] = {0, 0, 0};
+        for (int m = 0; m < 4; ++m)
+            for (int r = 0; r < 3; ++r) yc[r] += 0.25 * yv[m][r];
+        const double dist = sqrt(yc[0] * yc[0] + yc[1] * yc[1] + yc[2] * yc[2]);
+        if (P->method == 1 || dist > P->lod_radius) {
+            t->splat = 1;
+            t->hh = cbrt(fabs(*V));
+            t->q *= fabs(*V);
+            t->zc = yc[2];
+            t->uc = yc[0] / yc[2];
+            t->vc = yc[1] / yc[2];
+            if (!(yc[2] > 0)) {  /* behind the camera: not drawn */
+                t->ix0 = 0; t->ix1 = -1; t->iy0 = 0; t->iy1 = -1;
+                return 1;
+            }
+            /* the pixels whose ray meets the support disc: the window box of
+             * the disc's bounding square (all of it in front of the camera
+             * when 2h < z_c), widened by a pixel; else the whole window */
+            const double R2 = 2.0 * t->hh;
+            double du = P->extent[0] / P->width, dv = P->extent[1] / P->height;
+            double ul = -0.5 * P->extent[0], vb = -0.5 * P->extent[1];
+            if (R2 >= yc[2]) {
+                t->ix0 = 0; t->ix1 = P->width - 1; t->iy0 = 0; t->iy1 = P->height - 1;
+                return 1;
+            }
+            /* on the billboard's plane the disc spans (x_c +- 2h, y_c +- 2h) */
+            double umin = (yc[0] - R2) / yc[2], umax = (yc[0] + R2) / yc[2];
+            double vmin = (yc[1] - R2) / yc[2], vmax = (yc[1] + R2) / yc[2];
+            t->ix0 = (int64_t)ceil((umin - ul) / du - 0.5) - 1;
+            t->ix1 = (int64_t)floor((umax - ul) / du - 0.5) + 1;
+            t->iy0 = (int64_t)ceil((vmin - vb) / dv - 0.5) - 1;
+            t->iy1 = (int64_t)floor((vmax - vb) / dv - 0.5) + 1;
+            if (t->ix0 < 0) t->ix0 = 0;
+            if (t->iy0 < 0) t->iy0 = 0;
+            if (t->ix1 > P->width - 1) t->ix1 = P->width - 1;
+            if (t->iy1 > P->height - 1) t->iy1 = P->height - 1;
+            return 1;
+        }
+    }
     double pu[4], pv[4];  /* the vertices on the image plane */
     int behind = 0;
     for (int m = 0; m < 4; ++m) {
@@ -250,8 +305,14 @@ static int tet_setup(const orc_problem *P, const double v[4][3], double mass,
     return 1;
 }
 
+static double splat_w(double r, double h);
+
 /* Length of the camera ray through (pu, pv) inside the tetrahedron. */
 static double clip_dl_persp(const orc_tet *t, double pu, double pv) {
+    if (t->splat) {  /* a billboard: the kernel where the ray crosses its plane */
+        const double du = pu - t->uc, dv = pv - t->vc;
+        return splat_w(t->zc * sqrt(du * du + dv * dv), t->hh);
+    }
     double lo = 0.0, hi = INFINITY;  /* the half-line s >= 0 */
     for (int f = 0; f < 4; ++f) {
         double nd = t->n[f][0] * pu + t->n[f][1] * pv + t->n[f][2];
@@ -452,7 +513,9 @@ int orc_splat_tets(const orc_problem *P, int64_t ntet, const double *verts, cons
 int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
                      const double *mass, double *out, orc_stats *st) {
     if (!P || P->width < 1 || P->height < 1 || !(P->extent[0] > 0) || !(P->extent[1] > 0) ||
-        P->qpow < 0 || P->qpow > 2 || (P->perspective && (P->wrap || P->slab)))
+        P->qpow < 0 || P->qpow > 2 || (P->perspective && (P->wrap || P->slab)) || P->method < 0 ||
+        P->method > 2 || (P->method && !P->perspective) ||
+        (P->method == 2 && !(P->lod_radius >= 0.0 && isfinite(P->lod_radius))))
         return ORC_EINVAL;
     if (ntet < 0 || (ntet > 0 && (!verts || !mass)) || !out) return ORC_EINVAL;
     int64_t npx = (int64_t)P->width * P->height;

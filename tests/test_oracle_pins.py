@@ -371,6 +371,54 @@ def test_p_far_camera_is_the_orthographic_projection():
     assert abs(b.sum() / a.sum() - 1.0) < 1e-5
 
 
+def test_h_hybrid_limits_are_the_exact_and_the_billboard_images():
+    # the near/far hybrid: a sphere larger than the scene draws every
+    # tetrahedron exactly, radius 0 draws every one as a billboard
+    n = 8
+    xyz = W.zeldovich(n, 3, 2.0)
+    base = W.perspective_view(np.eye(3), (0.45, 0.52, -1.2), 40, 32, extent=(1.2, 1.0))
+    exact, _ = O.project_region(*xyz, (n,) * 3, base)
+    bills, sb = O.project_region(*xyz, (n,) * 3, dict(base, method="centroids"))
+    far, _ = O.project_region(*xyz, (n,) * 3, dict(base, method="hybrid", lod_radius=1e9))
+    near, _ = O.project_region(*xyz, (n,) * 3, dict(base, method="hybrid", lod_radius=0.0))
+    np.testing.assert_array_equal(far, exact)
+    np.testing.assert_array_equal(near, bills)
+    mid, _ = O.project_region(*xyz, (n,) * 3, dict(base, method="hybrid", lod_radius=1.9))
+    assert not np.array_equal(mid, exact) and not np.array_equal(mid, bills)
+    assert sb["fragments"] > 0
+
+
+def test_h_billboard_carries_q_v_over_z_squared():
+    # the window integral of one billboard's kernel is 1 / z_c^2 (the plane at
+    # depth z_c maps to the window scaled by 1 / z_c), so a far billboard sums
+    # to q |V| / z_c^2 times the pixel area
+    v = np.array([[0.0, 0.0, 0.0], [0.3, 0.0, 0.0], [0.0, 0.3, 0.0], [0.0, 0.0, 0.3]]) + [0.1, -0.05, 4.0]
+    vol = abs(np.linalg.det(v[1:] - v[0])) / 6.0
+    zc = v[:, 2].mean()
+    view = dict(W.perspective_view(np.eye(3), (0.0, 0.0, 0.0), 160, 160, extent=(0.5, 0.5)), method="centroids")
+    img, st = O.project_tets(v[None], 0.7, view)
+    du = dv = 0.5 / 160
+    total = img.sum() * du * dv
+    assert abs(total * zc ** 2 / 0.7 - 1.0) < 2e-3      # q |V| = rho |V| = m
+    # and the hybrid takes it exactly inside its sphere
+    img2, _ = O.project_tets(v[None], 0.7, dict(view, method="hybrid", lod_radius=5.0))
+    ex, _ = O.project_tets(v[None], 0.7, dict(view, method="tessellation"))
+    np.testing.assert_array_equal(img2, ex)
+    assert vol > 0
+
+
+def test_h_far_camera_billboards_are_the_orthographic_splats():
+    n = 10
+    xyz = W.zeldovich(n, 3, 1.5)
+    D = 1e6
+    ortho = dict(W.z_view(32), wrap=0, method="centroids")
+    persp = W.perspective_view(np.eye(3), (0.5, 0.5, 0.5 - D), 32, extent=(1.0 / D, 1.0 / D))
+    a, _ = O.splat_image(*xyz, (n,) * 3, ortho)
+    b, _ = O.project_region(*xyz, (n,) * 3, dict(persp, method="centroids"))
+    cov = a > 1e-3 * a.mean()
+    np.testing.assert_allclose(b[cov], a[cov], rtol=1e-4)
+
+
 def test_p_perspective_needs_no_wrap_and_no_slab():
     n = 4
     xyz = W.undisplaced(n)

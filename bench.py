@@ -64,8 +64,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quantity", default="density", choices=["density", "unit", "density2"],
                     help="projected per-tetrahedron value: rho, 1 or rho^2")
-    ap.add_argument("--method", default="tessellation", choices=["tessellation", "centroids"],
-                    help="exact projection of the tessellation, or the centroid splats")
+    ap.add_argument("--method", default="tessellation", choices=["tessellation", "centroids", "hybrid"],
+                    help="exact projection of the tessellation, the centroid splats, or (perspective "
+                         "workloads) exact within --lod-radius of the camera and billboards beyond")
+    ap.add_argument("--lod-radius", type=float, default=0.25,
+                    help="the hybrid's sphere around the camera (box units)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device twice (scale reference for HBM byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -91,7 +94,10 @@ def cpu_baseline(xyz, w, view, full_fragments: float):
         cubes = rng.choice(ncubes, size=k, replace=False)
         verts = np.concatenate([oracle.cube_tets(*xyz, (w.n,) * 3, int(c))[0] for c in cubes])
         t0 = time.perf_counter()
-        draw = oracle.splat_tets if view.get("method") == "centroids" else oracle.project_tets
+        # orthographic splats have their own entry; perspective billboards and
+        # the hybrid go through the tetrahedron list
+        ortho_splats = view.get("method") == "centroids" and view.get("projection") != "perspective"
+        draw = oracle.splat_tets if ortho_splats else oracle.project_tets
         _, st = draw(verts, mass, view)
         return time.perf_counter() - t0, st, len(verts)
 
@@ -371,6 +377,8 @@ def main():
     gen_s = time.perf_counter() - t0
     d = [torch.from_numpy(a).to(dev) for a in xyz]
     view = dict(W.workload_views(w)[0], quantity=args.quantity, method=args.method)
+    if args.method == "hybrid":
+        view["lod_radius"] = args.lod_radius
     lat = tess.build(*d, (w.n,) * 3, precision=args.precision)
     out = torch.empty((w.height, w.width), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -421,6 +429,7 @@ def main():
                             if persp else "z-projection, periodic"),
                    "determinant": args.precision,
                    "quantity": args.quantity, "method": args.method,
+                   **({"lod_radius": args.lod_radius} if args.method == "hybrid" else {}),
                    "tile": [st["tile_rows"], st["tile_cols"]], "chunk": st["chunk"],
                    "block": st["block"]},
         "fragments": frags,

@@ -123,15 +123,24 @@ typedef struct {
     int32_t method;         /* tess_method; 0, the zero-initialised default, is
                                the exact projection of the tessellation          */
     int32_t projection;     /* tess_projection; 0, the default, is orthographic  */
+    double lod_radius;      /* TESS_METHOD_HYBRID: tetrahedra whose centroid is
+                               within this distance of the camera are drawn
+                               exactly, the others as centroid billboards;
+                               finite, >= 0                                      */
 } tess_view;
 
 /* The rays of a view.  Perspective (the camera point c of Eq. Eqn:TetSum; the
  * large-scale figure puts the camera inside the volume): the pixel at
  * (pu, pv) on the window sees the half-line c + s R^T (pu, pv, 1), s >= 0, and
- * dl is that half-line's Euclidean length inside T.  It needs wrap = 0, no
- * slab and the tessellation method; the raster then evaluates every covered
- * pixel (the chord is not piecewise linear along a row), so it costs per
- * fragment. */
+ * dl is that half-line's Euclidean length inside T.  It needs wrap = 0 and
+ * no slab; the raster then evaluates every covered pixel (the chord is not
+ * piecewise linear along a row), so it costs per fragment.  With
+ * TESS_METHOD_CENTROIDS each T is a billboard facing the view direction at
+ * its centroid y_c (camera frame, drawn when z_c > 0) adding q |V| W(r, h),
+ * with r the distance from y_c at which the pixel ray crosses the billboard's
+ * plane, r = z_c |(pu, pv) - (x_c, y_c) / z_c|; TESS_METHOD_HYBRID draws T
+ * exactly when |y_c| <= lod_radius and as a billboard otherwise (the
+ * large-scale figure's sphere around the camera). */
 typedef enum {
     TESS_PROJECTION_ORTHOGRAPHIC = 0,
     TESS_PROJECTION_PERSPECTIVE = 1
@@ -145,7 +154,8 @@ typedef enum {
  * q |V| (its mass for the density); not with a slab. */
 typedef enum {
     TESS_METHOD_TESSELLATION = 0,
-    TESS_METHOD_CENTROIDS = 1
+    TESS_METHOD_CENTROIDS = 1,
+    TESS_METHOD_HYBRID = 2       /* perspective only: exact near, billboards far */
 } tess_method;
 
 /* The constant per-tetrahedron value q of Eq. Eqn:TetProjection, with

@@ -39,10 +39,10 @@ class TessView(ctypes.Structure):
                 ("height", ctypes.c_int32), ("wrap", ctypes.c_int32),
                 ("quantity", ctypes.c_int32), ("slab", ctypes.c_int32),
                 ("slab_t", ctypes.c_double * 2), ("method", ctypes.c_int32),
-                ("projection", ctypes.c_int32)]
+                ("projection", ctypes.c_int32), ("lod_radius", ctypes.c_double)]
 
 # tess_method by name (view["method"], default "tessellation")
-METHODS = {"tessellation": 0, "centroids": 1}
+METHODS = {"tessellation": 0, "centroids": 1, "hybrid": 2}
 
 # tess_projection by name (view["projection"], default "orthographic")
 PROJECTIONS = {"orthographic": 0, "perspective": 1}
@@ -185,8 +185,9 @@ def build_desc(dims: Sequence[int], box=(1.0, 1.0, 1.0), periodic: bool = True,
 def make_view(view: Dict) -> TessView:
     """Converts a view dict (rot, center, extent, width, height, wrap, optional
     quantity: "density", "unit" or "density2", optional slab: (t0, t1),
-    optional method: "tessellation" or "centroids", optional projection:
-    "orthographic" or "perspective", with center the camera) to the C struct."""
+    optional method: "tessellation", "centroids" or "hybrid" (with
+    lod_radius), optional projection: "orthographic" or "perspective", with
+    center the camera) to the C struct."""
     v = TessView()
     for i in range(9):
         v.rot[i] = float(view["rot"][i])
@@ -202,6 +203,7 @@ def make_view(view: Dict) -> TessView:
         v.slab_t[0], v.slab_t[1] = float(slab[0]), float(slab[1])
     v.method = METHODS[view.get("method", "tessellation")]
     v.projection = PROJECTIONS[view.get("projection", "orthographic")]
+    v.lod_radius = float(view.get("lod_radius", 0.0))
     return v
 
 

@@ -168,15 +168,18 @@ extern "C" tess_status tess_check_view(const tess_view *v, const tess_build_desc
         v->quantity != TESS_QUANTITY_DENSITY2)
         return fail(TESS_EINVAL, "quantity must be 0 (density), 1 (unit) or 2 (density^2)");
     if (v->slab != 0 && v->slab != 1) return fail(TESS_EINVAL, "slab must be 0 or 1");
-    if (v->method != TESS_METHOD_TESSELLATION && v->method != TESS_METHOD_CENTROIDS)
-        return fail(TESS_EINVAL, "method must be 0 (tessellation) or 1 (centroids)");
+    if (v->method != TESS_METHOD_TESSELLATION && v->method != TESS_METHOD_CENTROIDS &&
+        v->method != TESS_METHOD_HYBRID)
+        return fail(TESS_EINVAL, "method must be 0 (tessellation), 1 (centroids) or 2 (hybrid)");
     if (v->method == TESS_METHOD_CENTROIDS && v->slab)
         return fail(TESS_EINVAL, "the centroid method takes no slab");
     if (v->projection != TESS_PROJECTION_ORTHOGRAPHIC && v->projection != TESS_PROJECTION_PERSPECTIVE)
         return fail(TESS_EINVAL, "projection must be 0 (orthographic) or 1 (perspective)");
-    if (v->projection == TESS_PROJECTION_PERSPECTIVE &&
-        (v->wrap || v->slab || v->method != TESS_METHOD_TESSELLATION))
-        return fail(TESS_EINVAL, "a perspective view takes no wrap, no slab and the tessellation method");
+    if (v->projection == TESS_PROJECTION_PERSPECTIVE && (v->wrap || v->slab))
+        return fail(TESS_EINVAL, "a perspective view takes no wrap and no slab");
+    if (v->method == TESS_METHOD_HYBRID &&
+        (v->projection != TESS_PROJECTION_PERSPECTIVE || !(std::isfinite(v->lod_radius) && v->lod_radius >= 0)))
+        return fail(TESS_EINVAL, "the hybrid method needs a perspective view and a finite lod_radius >= 0");
     if (v->slab && !(std::isfinite(v->slab_t[0]) && std::isfinite(v->slab_t[1]) && v->slab_t[0] < v->slab_t[1]))
         return fail(TESS_EINVAL, "slab needs finite slab_t[0] < slab_t[1]");
     if (v->wrap) {
@@ -342,6 +345,8 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     vp.slab_t[1] = v->slab ? v->slab_t[1] : 0.0;
     vp.splat = v->method == TESS_METHOD_CENTROIDS ? 1 : 0;
     vp.persp = v->projection == TESS_PROJECTION_PERSPECTIVE ? 1 : 0;
+    vp.hybrid = v->method == TESS_METHOD_HYBRID ? 1 : 0;
+    vp.lod_radius = vp.hybrid ? v->lod_radius : 0.0;
     // q / rho needs |V| to full precision (the face form stores q itself, a
     // splat q |V| and |V|^(1/3))
     if (vp.qpow != 1 || vp.slab || vp.splat || vp.persp) lp.det_cond_k = -1.0;

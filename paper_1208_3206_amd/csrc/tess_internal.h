@@ -40,6 +40,8 @@ struct ViewParams {
     double slab_t[2];        // depth t = third view coordinate, R (x - c)
     int32_t splat;           // 1: centroid splats instead of the tessellation
     int32_t persp;           // 1: rays from the camera at `center` (perspective)
+    int32_t hybrid;          // perspective: exact within lod_radius of the camera, billboards beyond
+    double lod_radius;
 };
 
 // Record kinds of a launch (one per view): the pyramid (crease and line

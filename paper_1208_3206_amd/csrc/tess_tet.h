@@ -474,6 +474,43 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 double ybase[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) ybase[r] = V.rot[3 * r] * b0[0] + V.rot[3 * r + 1] * b0[1] + V.rot[3 * r + 2] * b0[2];
+                if (V.splat || V.hybrid) {
+                    // the centroid in the camera frame: a billboard (the centroid
+                    // method, or beyond the hybrid's sphere around the camera)
+                    double yc[3];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int m = 0; m < 4; ++m)
+                            acc += 0.25 * (ybase[r] + (V.rot[3 * r] * e[vi[m]][0] + V.rot[3 * r + 1] * e[vi[m]][1] +
+                                                       V.rot[3 * r + 2] * e[vi[m]][2]));
+                        yc[r] = acc;
+                    }
+                    if (V.splat || sqrt(yc[0] * yc[0] + yc[1] * yc[1] + yc[2] * yc[2]) > V.lod_radius) {
+                        if (!(yc[2] > 0.0)) return;  // behind the camera: not drawn
+                        const double vol = fabs(det6) / 6.0;
+                        const double hh = cbrt(vol), R2 = 2.0 * hh;
+                        int ix0 = 0, ix1 = V.W - 1, iy0 = 0, iy1 = V.H - 1;
+                        if (R2 < yc[2]) {  // the support disc's square on the billboard plane, a pixel of margin
+                            const double lim = 1.0e8;
+                            ix0 = max(ix0, (int)fmax(ceil(((yc[0] - R2) / yc[2] - V.u_left) * V.inv_du - 0.5) - 1.0, -lim));
+                            ix1 = min(ix1, (int)fmin(floor(((yc[0] + R2) / yc[2] - V.u_left) * V.inv_du - 0.5) + 1.0, lim));
+                            iy0 = max(iy0, (int)fmax(ceil(((yc[1] - R2) / yc[2] - V.v_bottom) * V.inv_dv - 0.5) - 1.0, -lim));
+                            iy1 = min(iy1, (int)fmin(floor(((yc[1] + R2) / yc[2] - V.v_bottom) * V.inv_dv - 0.5) + 1.0, lim));
+                        }
+                        if (ix0 > ix1 || iy0 > iy1) return;
+                        pc[0] = yc[0] / yc[2];
+                        pc[1] = yc[1] / yc[2];
+                        pc[2] = yc[2];
+                        pc[3] = 1.0 / hh;
+                        pc[4] = qv * vol * (10.0 / (7.0 * kPi * hh * hh));
+                        R.bx = pack_range(ix0, ix1);
+                        R.by = pack_range(iy0, iy1);
+                        R.flags = REC_SPLAT | REC_VALID;
+                        return;
+                    }
+                }
                 bool behind = false;
                 double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
                 // frustum culling: the window's edges widened by a pixel; a
@@ -1349,7 +1386,9 @@ TESS_HD inline uint32_t splat_pair(const RecHead &h, const double *cf, const Bin
 // from a pixel to whole tiles (next to the camera), so the pixels of the
 // record's box in the tile are shared out: this call takes those with
 // row-major index k = lane0, lane0 + nlanes, ...  Returns the pixels with
-// dl > 0; kinks counts the pixels evaluated.
+// dl > 0; kinks counts the pixels evaluated.  A billboard record (the
+// centroid method, or beyond the hybrid's sphere) adds q |V| W(r, h) instead,
+// r = z_c |(pu, pv) - (u_c, v_c)| where the ray crosses the billboard's plane.
 template <typename Dep>
 TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0, int ty0,
                                    int n, int rows, int lane0, int nlanes, Dep &&dep, uint32_t &spans,
@@ -1357,6 +1396,34 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
     const int x0 = max(range_lo(h.bx), tx0), x1 = min(range_hi(h.bx), tx0 + n - 1);
     const int y0 = max(range_lo(h.by), ty0), y1 = min(range_hi(h.by), ty0 + rows - 1);
     if (x0 > x1 || y0 > y1) return 0;
+    const double du = B.ext_u / (double)B.W, dv = B.ext_v / (double)B.H;
+    const int bw = x1 - x0 + 1, npix = bw * (y1 - y0 + 1);
+    const int sy = nlanes / bw, sx = nlanes % bw;
+    if (lane0 == 0) spans += (uint32_t)(y1 - y0 + 1);
+    uint32_t frags = 0;
+    if (h.flags & REC_SPLAT) {
+        // a billboard at depth zc: the kernel at r = zc |(pu, pv) - (uc, vc)|
+        const double uc = cf[0], vc = cf[1], zc = cf[2], ih = cf[3], amp = cf[4];
+        int y = y0 + lane0 / bw, x = x0 + lane0 % bw;
+        for (int k = lane0; k < npix; k += nlanes) {
+            const double pu = -0.5 * B.ext_u + ((double)x + 0.5) * du - uc;
+            const double pv = -0.5 * B.ext_v + ((double)y + 0.5) * dv - vc;
+            ++kinks;
+            const double s = zc * sqrt(pu * pu + pv * pv) * ih;
+            if (s < 2.0) {
+                const double t = 2.0 - s;
+                dep(y - ty0, x - tx0, amp * (s < 1.0 ? 1.0 - 1.5 * s * s + 0.75 * s * s * s : 0.25 * t * t * t));
+                ++frags;
+            }
+            x += sx;
+            y += sy;
+            if (x > x1) {
+                x -= bw;
+                ++y;
+            }
+        }
+        return frags;
+    }
     double nrm[4][3], off[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -1380,13 +1447,8 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
         off[a] = nn[0] * cf[3 * b] + nn[1] * cf[3 * b + 1] + nn[2] * cf[3 * b + 2];
     }
     const double q = cf[12];
-    const double du = B.ext_u / (double)B.W, dv = B.ext_v / (double)B.H;
-    const int bw = x1 - x0 + 1, npix = bw * (y1 - y0 + 1);
-    if (lane0 == 0) spans += (uint32_t)(y1 - y0 + 1);
     // row-major walk of the box: k -> (y, x), stepping nlanes at a time
     int y = y0 + lane0 / bw, x = x0 + lane0 % bw;
-    const int sy = nlanes / bw, sx = nlanes % bw;
-    uint32_t frags = 0;
     for (int k = lane0; k < npix; k += nlanes) {
         const double pu = -0.5 * B.ext_u + ((double)x + 0.5) * du;
         const double pv = -0.5 * B.ext_v + ((double)y + 0.5) * dv;

@@ -63,6 +63,8 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
                            (ctypes.c_double * 2)(*view["slab"]) if view.get("slab") is not None else None,
                            1 if view.get("method", "tessellation") == "centroids" else 0,
                            1 if view.get("projection", "orthographic") == "perspective" else 0,
+                           1 if view.get("method", "tessellation") == "hybrid" else 0,
+                           ctypes.c_double(float(view.get("lod_radius", 0.0))),
                            out64.ctypes.data_as(P(ctypes.c_double)),
                            out32.ctypes.data_as(P(ctypes.c_float)), st.ctypes.data_as(P(ctypes.c_longlong)))
     if rc != 0:

@@ -17,7 +17,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                            int32_t periodic, double total_mass, int32_t precision, const double rot[9],
                            const double center[3], const double extent[2], int32_t W, int32_t H,
                            int32_t wrap, int32_t tile_rows, int32_t tile_cols, int32_t chunk,
-                           double crease_div, int32_t qpow, const double *slab, int32_t splat, int32_t persp,
+                           double crease_div, int32_t qpow, const double *slab, int32_t splat, int32_t persp, int32_t hybrid, double lod_radius,
                            double *out64, float *out32,
                            long long *stats /* [tets, zero, inverted, fp64_dets, fragments, spans,
                                                pairs, items, crease_records] */) {
@@ -48,6 +48,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.slab = slab ? 1 : 0;
     V.splat = splat;
     V.persp = persp;
+    V.hybrid = hybrid;
+    V.lod_radius = lod_radius;
     V.slab_t[0] = slab ? slab[0] : 0.0;
     V.slab_t[1] = slab ? slab[1] : 0.0;
     // q != rho: the crease threshold from the integral of q (as the library)

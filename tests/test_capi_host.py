@@ -107,9 +107,16 @@ def test_view_validation(tess):
     # perspective: no wrap, no slab, the tessellation method
     persp = W.perspective_view(np.eye(3), (0.5, 0.5, -1.0), 64)
     tess.check_view(persp, d)
-    for bad in (dict(persp, wrap=1), dict(persp, slab=(0.0, 0.1)), dict(persp, method="centroids")):
+    tess.check_view(dict(persp, method="centroids"), d)
+    tess.check_view(dict(persp, method="hybrid", lod_radius=0.3), d)
+    for bad in (dict(persp, wrap=1), dict(persp, slab=(0.0, 0.1)), dict(W.z_view(64), method="hybrid"),
+                dict(persp, method="hybrid", lod_radius=-1.0),
+                dict(persp, method="hybrid", lod_radius=float("inf"))):
         with pytest.raises(tess.TessError):
             tess.check_view(bad, d)
+    v = tess.make_view(W.z_view(64))
+    v.method = 3
+    assert tess.lib().tess_check_view(ctypes.byref(v), None) == tess.TESS_EINVAL
     # depth slabs: finite and ordered
     tess.check_view(dict(W.z_view(64), slab=(-0.1, 0.2)), d)
     for bad in ((0.2, 0.2), (0.3, -0.1), (float("nan"), 0.1), (-float("inf"), 0.0)):

@@ -208,6 +208,21 @@ def test_perspective_camera(tess, camera, quantity):
     assert abs(st["fragments"] - ost["fragments"]) <= 1e-5 * ost["fragments"]
 
 
+@pytest.mark.parametrize("method,radius", [("centroids", 0.0), ("hybrid", 0.9), ("hybrid", 1.6)])
+def test_perspective_billboards_and_hybrid(tess, method, radius):
+    # centroid billboards under the perspective camera, alone and beyond the
+    # hybrid's sphere around the camera (exact inside it)
+    n = 16
+    xyz = W.zeldovich(n, 5, 3.0, seed=9)
+    camera = (0.41, 0.55, 0.3) if radius < 1.0 else (0.45, 0.52, -1.2)
+    view = dict(W.perspective_view(np.eye(3), camera, 96, 80, extent=(1.5, 1.2)), method=method,
+                lod_radius=radius)
+    got, st = gpu_image(tess, xyz, (n, n, n), view)
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert_parity(got, ref, what=f"perspective {method} {radius}")
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-5 * ost["fragments"]
+
+
 def test_perspective_workload_sampled_pixels(tess):
     # the perspective workload at its size: the mid field, camera inside it
     w = W.PERSPECTIVE

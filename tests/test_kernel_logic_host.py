@@ -148,6 +148,20 @@ def test_perspective_matches_oracle(camera, quantity):
     assert st["fragments"] == ost["fragments"] and st["tets"] == ost["tets"]
 
 
+@pytest.mark.parametrize("method,radius", [("centroids", 0.0), ("hybrid", 0.9), ("hybrid", 1.6)])
+def test_perspective_billboards_and_hybrid_match_oracle(method, radius):
+    # billboards under the perspective camera, alone and beyond the hybrid's
+    # sphere (exact inside it); camera inside the volume for radius 0.9
+    n = 12
+    xyz = W.zeldovich(n, 4, 3.0, seed=9)
+    camera = (0.41, 0.55, 0.3) if radius < 1.0 else (0.45, 0.52, -1.2)
+    view = dict(W.perspective_view(np.eye(3), camera, 72, 56, extent=(1.5, 1.2)), method=method, lod_radius=radius)
+    img, _, st = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=8, tile_cols=40, chunk=500)
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert np.abs(img - ref).max() <= 1e-11 * np.abs(ref).max()
+    assert st["fragments"] == ost["fragments"] and st["tets"] == ost["tets"]
+
+
 def test_tallest_tiles_match_oracle():
     # 256-row tiles (the largest the library accepts): row offsets of up to 255
     # inside a tile, footprints taller than the lattice spacing wrapping in y

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -67,6 +68,7 @@ namespace {
 struct Workspace {
     DevBuf<RecHead> head;
     DevBuf<Payload> coef;
+    DevBuf<double> kinks;               // edge form: 6 slope changes per tetrahedron
     DevBuf<uint32_t> counts;
     DevBuf<uint64_t> base;
     DevBuf<uint64_t> scan;
@@ -350,6 +352,12 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     // q / rho needs |V| to full precision (the face form stores q itself, a
     // splat q |V| and |V|^(1/3))
     if (vp.qpow != 1 || vp.slab || vp.splat || vp.persp) lp.det_cond_k = -1.0;
+    // plain pyramids take the edge form, unless TESS_PER_TETRAHEDRON=1 asks
+    // for every crease per tetrahedron (the two give the same image up to
+    // rounding; the switch is there to compare them)
+    const char *per_tet = getenv("TESS_PER_TETRAHEDRON");
+    vp.edges = (view_form(vp) == kFormPyramid && !(per_tet && per_tet[0] == '1')) ? 1 : 0;
+    vp.kinks = nullptr;
 }
 
 struct Plan {
@@ -389,7 +397,8 @@ struct Geometry {
 
 tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Plan &plan, Geometry &g) {
     make_params(L, v, g.lp, g.vp);
-    g.ntet = 6 * g.lp.ncubes;
+    // records: the tetrahedra, then (edge form) seven edges per lattice vertex
+    g.ntet = 6 * g.lp.ncubes + (g.vp.edges ? 7 * (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2] : 0);
     BinParams &B = g.B;
     B.Th = plan.Th;
     B.Tw = plan.Tw;
@@ -403,7 +412,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
         return fail(TESS_ECAPACITY, "%lld tiles of %d x %d px exceed the limit of %d; use larger tiles",
                     (long long)g.ntiles, plan.Th, plan.Tw, kMaxTiles);
     // pair ids carry a work class (pyramid records, ids below the class bits)
-    B.nkey = (view_form(g.vp) == kFormPyramid && g.ntet < (int64_t)kIdMask) ? 32 : 1;
+    B.nkey = (view_form(g.vp) == kFormPyramid && !g.vp.edges && g.ntet < (int64_t)kIdMask) ? 32 : 1;
     // binning segments: enough for the device, few enough to keep the count matrix small
     int64_t seg_len = 4096;
     while ((g.ntet + seg_len - 1) / seg_len * g.ntiles > (int64_t)64 << 20) seg_len *= 2;
@@ -424,6 +433,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
 tess_status ensure_front(Workspace &ws, const Geometry &g) {
     TESS_HIP(ws.head.ensure((size_t)g.ntet));
     TESS_HIP(ws.coef.ensure((size_t)g.ntet));
+    if (g.vp.edges) TESS_HIP(ws.kinks.ensure((size_t)36 * (size_t)g.lp.ncubes));
     TESS_HIP(ws.counts.ensure((size_t)g.nmat));
     TESS_HIP(ws.base.ensure((size_t)g.nmat));
     TESS_HIP(ws.scan.ensure(scan_scratch_elems(g.nmat)));
@@ -453,7 +463,9 @@ tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipSt
         TESS_HIP(launch_qsum(g.lp, vp, &slot->qsum, s));
         vp.qsum = &slot->qsum;
     }
+    vp.kinks = ws.kinks.p;
     TESS_HIP(launch_setup(g.lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
+    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, ws.head.p, ws.head.p, ws.coef.p, s));
     return TESS_OK;
 }
 
@@ -664,9 +676,12 @@ std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *v
     put(views, sizeof(tess_view) * (size_t)n_views);
     put(&images, sizeof(images));
     put(&t, sizeof(t));
-    const void *bufs[] = {ws.head.p, ws.coef.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
+    const void *bufs[] = {ws.head.p, ws.coef.p, ws.kinks.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
                           ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p, ws.overflow.p};
     put(bufs, sizeof(bufs));
+    const char *per_tet = getenv("TESS_PER_TETRAHEDRON");
+    const char form = (per_tet && per_tet[0] == '1') ? 1 : 0;  // edge form or not
+    put(&form, 1);
     return k;
 }
 

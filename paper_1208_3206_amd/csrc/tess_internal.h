@@ -42,6 +42,11 @@ struct ViewParams {
     int32_t persp;           // 1: rays from the camera at `center` (perspective)
     int32_t hybrid;          // perspective: exact within lod_radius of the camera, billboards beyond
     double lod_radius;
+    // pyramid form: 1 = the creases of tetrahedra inside the image's columns
+    // are summed per mesh edge (setup writes each tetrahedron's kinks to
+    // `kinks`, 6 per tetrahedron, and the edge records carry the sums)
+    int32_t edges;
+    double *kinks;
 };
 
 // Record kinds of a launch (one per view): the pyramid (crease and line
@@ -112,6 +117,11 @@ struct WorkItem {
 //    coordinates; front or back face) or, for a wall, its half-plane as in
 //    the line form; c[12] the projected value q. The record's f(p) is q
 //    times the chord inside the tetrahedron and the slab;
+//  - edge form (REC_EDGE): one segment of the tetrahedral mesh, endpoints
+//    (c[0], c[1]) and (c[2], c[3]), the sum D over its tetrahedra of their
+//    slope changes across it (c[4]); the head's spare word counts the
+//    tetrahedra for which it is an entering (bits 0-7) and a leaving
+//    (bits 8-15) silhouette edge, for the fragment count;
 //  - splat (REC_SPLAT; the centroid method): centroid (c[0], c[1]), the
 //    kernel's s per pixel along x and y (c[2], c[3]) and its peak amplitude
 //    q |V| 10 / (7 pi h^2) (c[4]); deposited as values, not differences;
@@ -140,6 +150,8 @@ constexpr uint32_t REC_FACE_TIE_SHIFT = 18;   // face g's wall keeps pixels on i
 constexpr uint32_t REC_FACE_FRONT = 1u, REC_FACE_BACK = 2u, REC_FACE_WALL = 3u;
 constexpr uint32_t REC_SPLAT = 1u << 22;      // payload is a centroid splat
 constexpr uint32_t REC_PERSP = 1u << 23;      // payload: camera-frame vertices and q
+constexpr uint32_t REC_EDGE = 1u << 24;       // a mesh edge: its summed crease (edge form)
+constexpr uint32_t REC_EDGED = 1u << 25;      // a tetrahedron whose creases went to its edges
 
 struct alignas(128) Payload {
     double c[14];
@@ -155,6 +167,11 @@ hipError_t launch_qsum(const LatticeParams &L, const ViewParams &V, double *qsum
 
 hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream);
+
+// Edge records 6 ncubes + 7 v + tau of every lattice vertex v from the
+// kinks setup wrote (edge form).
+hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, const RecHead *tet_head, RecHead *head,
+                        Payload *coef, hipStream_t stream);
 
 hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
                         hipStream_t stream);

@@ -74,6 +74,26 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
     }
 }
 
+// Edge form: one thread per lattice vertex, its seven edge records after
+// the tetrahedra's (ids 6 ncubes + 7 v + tau).
+__global__ void __launch_bounds__(256) k_edges(LatticeParams L, ViewParams V, const RecHead *__restrict__ thead,
+                                               RecHead *__restrict__ head, Payload *__restrict__ coef) {
+    const int64_t nv = (int64_t)L.d[0] * L.d[1] * L.d[2];
+    const int64_t first = 6 * L.ncubes;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride)
+        setup_vertex_edges(L, V, v, thead, V.kinks, head + first + 7 * v, coef + first + 7 * v);
+}
+
+hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, const RecHead *tet_head, RecHead *head,
+                        Payload *coef, hipStream_t stream) {
+    const int64_t nv = (int64_t)L.d[0] * L.d[1] * L.d[2];
+    const int64_t want = (nv + 255) / 256;
+    const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    hipLaunchKernelGGL(k_edges, dim3(blocks), dim3(256), 0, stream, L, V, tet_head, head, coef);
+    return hipGetLastError();
+}
+
 // One thread per cube: the integral of the projected value q over all
 // tetrahedra, the image's scale for the crease threshold when q != rho.
 __global__ void __launch_bounds__(256) k_qsum(LatticeParams L, ViewParams V, double *__restrict__ qsum) {
@@ -435,12 +455,13 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     const int tsize = B.Th * stride;
     for (int i = threadIdx.x; i < tsize; i += TPB) sA[i] = 0.0;
     __syncthreads();
-    uint32_t frags = 0, spans = 0, kinks = 0;
+    long long frags = 0;  // edge records add signed terms
+    uint32_t spans = 0, kinks = 0;
     auto one = [&](uint32_t id) {
         if (id >= B.ntet) return;
         const RecHead h = coef[id].h;
         if (!(h.flags & REC_VALID)) return;
-        frags += raster_record<FORM>(h, coef[id].c, B, tx0, ty0, n, rows,
+        frags += (int32_t)raster_record<FORM>(h, coef[id].c, B, tx0, ty0, n, rows,
                                      [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
                                      spans, kinks);
     };

@@ -19,6 +19,35 @@ constexpr int kTet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4},
 
 constexpr double kPi = 3.14159265358979323846;
 
+// Mesh edges.  The table's tetrahedra fit together across cubes (every face
+// diagonal runs the same way on opposite faces), so each lattice vertex owns
+// seven edges, to cube corners 1, 2 and 4 from corner 0, the face diagonals
+// 1-2, 1-4 and 2-4, and the body diagonal 3-4 of the cube that has the vertex
+// as corner 0.  Edge tau runs between corners kEdgeEnds[tau][0] and [1];
+// the tetrahedra holding it are tetrahedron t of the cube moved by (dx, dy,
+// dz) in {-1, 0}^3, where it is local edge e (local edges of kTet[t]: vertex
+// pairs 01, 02, 03, 12, 13, 23).  36 entries: each of a cube's 6 x 6
+// tetrahedron edges once.
+constexpr int kEdgeEnds[7][2] = {{0, 1}, {0, 2}, {0, 4}, {1, 2}, {1, 4}, {2, 4}, {3, 4}};
+struct EdgeUse {
+    int8_t dx, dy, dz, t, e;
+};
+constexpr int kEdgeFirst[8] = {0, 6, 12, 16, 20, 26, 32, 36};
+constexpr EdgeUse kEdgeUse[36] = {
+    {0, -1, -1, 5, 4}, {0, -1, 0, 1, 1}, {0, -1, 0, 4, 0}, {0, 0, -1, 2, 4}, {0, 0, -1, 3, 5}, {0, 0, 0, 0, 0},
+    {-1, 0, -1, 5, 3}, {-1, 0, 0, 1, 0}, {-1, 0, 0, 2, 1}, {0, 0, -1, 3, 4}, {0, 0, -1, 4, 5}, {0, 0, 0, 0, 3},
+    {-1, -1, 0, 5, 0}, {-1, 0, 0, 2, 3}, {0, -1, 0, 4, 3}, {0, 0, 0, 0, 4},
+    {0, 0, -1, 3, 3}, {0, 0, -1, 5, 5}, {0, 0, 0, 0, 1}, {0, 0, 0, 1, 3},
+    {0, -1, 0, 3, 0}, {0, -1, 0, 4, 1}, {0, -1, 0, 5, 2}, {0, 0, 0, 0, 2}, {0, 0, 0, 1, 4}, {0, 0, 0, 2, 5},
+    {-1, 0, 0, 2, 0}, {-1, 0, 0, 3, 1}, {-1, 0, 0, 5, 1}, {0, 0, 0, 0, 5}, {0, 0, 0, 1, 5}, {0, 0, 0, 4, 4},
+    {0, 0, 0, 1, 2}, {0, 0, 0, 2, 2}, {0, 0, 0, 3, 2}, {0, 0, 0, 4, 2}};
+
+// local edge index of the tetrahedron vertex pair (u, v), u != v
+TESS_HD inline int local_edge(int u, int v) {
+    const int a = u < v ? u : v, b = u < v ? v : u;
+    return a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+}
+
 
 // Face a of a tetrahedron is the one opposite vertex a; its vertices in
 // increasing order.
@@ -172,12 +201,13 @@ TESS_HD inline bool footprint(const double qx[4], const double qy[4], double mas
 // pixel row the footprint's slope jumps by |b| at a silhouette edge and by
 // -|b_k-1 - b_k| at the ridge to V_k, with b the x slopes of the faces over
 // the silhouette edges.  Returns false if the edges do not close a cycle.
-TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const Footprint &fp,
-                                   double out[14]) {
+// The silhouette edges as a cycle: vertices V_0..V_m-1 and, for the cyclic
+// edge (V_k, V_k+1), its G function Lk[k].  False if they close no cycle.
+TESS_HD inline bool crease_cycle(const Footprint &fp, int V[4], int Lk[4]) {
     const int m = fp.ng;
     if (m != 3 && m != 4) return false;
-    int V[4] = {fp.ei[0], fp.ej[0], 0, 0};
-    int Lk[4] = {0, 0, 0, 0};  // silhouette edge g of cyclic edge (V_k, V_k+1)
+    V[0] = fp.ei[0]; V[1] = fp.ej[0]; V[2] = 0; V[3] = 0;
+    Lk[0] = 0; Lk[1] = 0; Lk[2] = 0; Lk[3] = 0;
 #pragma unroll
     for (int k = 1; k < 4; ++k) {
         if (k >= m) break;
@@ -193,6 +223,14 @@ TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const
         if (k + 1 < m) V[k + 1] = next;
         else if (next != V[0]) return false;
     }
+    return true;
+}
+
+TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const Footprint &fp,
+                                   double out[14]) {
+    const int m = fp.ng;
+    int V[4], Lk[4];  // silhouette edge g of cyclic edge (V_k, V_k+1)
+    if (!crease_cycle(fp, V, Lk)) return false;
     double vx[4], vy[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -224,6 +262,61 @@ TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const
     }
     out[8] = ax;
     out[9] = ay;
+    return true;
+}
+
+// The pyramid's creases by tetrahedron edge (the edge form): every crease
+// lies on the projection of one of the six edges (silhouette edges, the
+// ridges of a triangular silhouette, the diagonals of a quadrilateral one),
+// so the footprint is the sum over the six local edges e of a slope change
+// D[e] along the edge's projection.  sil gets 2 bits per local edge: 1 for an
+// entering silhouette edge (b > 0), 2 for a leaving one.  D[e] as in the
+// crease form: |b| on the silhouette, -|b_k-1 - b_k| on the ridge to V_k; the
+// two halves of a diagonal have the same change (both are the difference of
+// the two faces meeting along it), and the mean of the two is taken.
+TESS_HD inline bool crease_kinks(const Footprint &fp, double D[6], uint32_t &sil) {
+    int V[4], Lk[4];
+    if (!crease_cycle(fp, V, Lk)) return false;
+    const int m = fp.ng;
+    double b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int g = Lk[k];
+        b[k] = k < m ? (g == 0 ? fp.c[1] : g == 1 ? fp.c[4] : g == 2 ? fp.c[7] : fp.c[10]) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) D[e] = 0.0;
+    sil = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= m) continue;
+        const int k1 = k + 1 < m ? k + 1 : 0;
+        const int e = local_edge(V[k], V[k1]);
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            if (f == e) D[f] = fabs(b[k]);
+        sil |= (b[k] > 0.0 ? 1u : 2u) << (2 * e);
+    }
+    if (m == 3) {
+        const int p = 6 - V[0] - V[1] - V[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int e = local_edge(p, V[k]);
+            const double r = -fabs(b[k > 0 ? k - 1 : 2] - b[k]);
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+                if (f == e) D[f] = r;
+        }
+    } else {
+        const int e02 = local_edge(V[0], V[2]), e13 = local_edge(V[1], V[3]);
+        const double r02 = -0.5 * (fabs(b[3] - b[0]) + fabs(b[1] - b[2]));
+        const double r13 = -0.5 * (fabs(b[0] - b[1]) + fabs(b[2] - b[3]));
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (f == e02) D[f] = r02;
+            if (f == e13) D[f] = r13;
+        }
+    }
     return true;
 }
 
@@ -306,7 +399,9 @@ struct CubeCounts {
 
 // The eight corners of a lattice cube: corner 0's position X0 and every
 // corner's offset e[n] from it, unwrapped to the nearest periodic image.
-TESS_HD inline void cube_corners(const LatticeParams &L, int64_t cube, double X0[3], double e[8][3]) {
+// Returns true when some corner was moved by a box length.
+TESS_HD inline bool cube_corners(const LatticeParams &L, int64_t cube, double X0[3], double e[8][3]) {
+    bool moved = false;
     const int64_t i = cube % L.c[0];
     const int64_t rest = cube / L.c[0];
     const int64_t j = rest % L.c[1];
@@ -329,11 +424,16 @@ TESS_HD inline void cube_corners(const LatticeParams &L, int64_t cube, double X0
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 double d = p[a] - X0[a];  // exact: difference of two floats
-                if (L.periodic) d -= L.box[a] * ceil(d / L.box[a] - 0.5);
+                if (L.periodic) {
+                    const double sh = ceil(d / L.box[a] - 0.5);
+                    moved = moved || sh != 0.0;
+                    d -= L.box[a] * sh;
+                }
                 e[n][a] = d;
             }
         }
     }
+    return moved;
 }
 
 // Sum over the cube's six tetrahedra of q |V|, q = rho^qpow, rho = m / |V|:
@@ -368,7 +468,24 @@ template <int FORM>
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
                                Payload coef[6], CubeCounts &cnt) {
     double X0[3], e[8][3];
-    cube_corners(L, cube, X0, e);
+    const bool moved = cube_corners(L, cube, X0, e);
+    // edge form: the cube's edges are placed from their own vertices (corners
+    // of this cube).  That gives the same segments as this cube's corners if
+    // the corners lie within half a box of each other along every axis (then
+    // every vertex sees the others unmoved); without wrap the positions agree
+    // only if, besides, no corner was moved by a box length (with wrap they
+    // agree modulo the period)
+    bool same_frame = V.wrap || !moved;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double lo = 0.0, hi = 0.0;
+#pragma unroll
+        for (int n = 1; n < 8; ++n) {
+            lo = fmin(lo, e[n][a]);
+            hi = fmax(hi, e[n][a]);
+        }
+        same_frame = same_frame && hi - lo < 0.5 * L.box[a];
+    }
     // x slope beyond which a footprint keeps the line form, from the image's
     // scale: the mass in view, or the measured integral of q
     const double crease_bmax = V.qsum ? *V.qsum * V.bmax_per_q : V.crease_bmax;
@@ -398,6 +515,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         double pc[14];
 #pragma unroll
         for (int g = 0; g < 14; ++g) pc[g] = 0.0;
+        double kd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // edge form: slope change per local edge
         [&] {
             const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
             // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
@@ -623,6 +741,19 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 #pragma unroll
             for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
             if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, pc)) {
+                if constexpr (FORM == kFormPyramid) {
+                    // edge form: a tetrahedron within the image's columns (a
+                    // pixel of margin; under wrap, within one period) hands its
+                    // creases to the mesh edges, where they are summed over the
+                    // tetrahedra around each edge (when same_frame holds)
+                    uint32_t sil = 0u;
+                    if (V.edges && same_frame && xmin >= 1.0 && xmax <= (double)V.W - 1.0 &&
+                        crease_kinks(fp, kd, sil)) {
+                        R.flags = REC_EDGED | (uint32_t)fp.ng;
+                        R.spare = sil;
+                        return;
+                    }
+                }
                 R.flags |= REC_CREASE;
                 R.spare = crease_profile(pc, iy1 - iy0 + 1);
             } else {
@@ -635,7 +766,133 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 #pragma unroll
         for (int g = 0; g < 14; ++g) P.c[g] = pc[g];
         head[t] = R;
-        coef[t] = P;
+        if (R.flags & REC_VALID) coef[t] = P;  // nothing reads the payload of other records
+        if constexpr (FORM == kFormPyramid) {
+            if (V.edges) {
+                double *k6 = V.kinks + 36 * cube + 6 * t;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) k6[e] = kd[e];
+            }
+        }
+    }
+}
+
+// Edge records of lattice vertex v (edge form): for each of its seven edges
+// the sum of the slope changes setup wrote for the tetrahedra around it that
+// handed their creases to their edges, the counts of those for which it is
+// an entering or leaving silhouette edge, and its projected endpoints in the
+// frame of the cube with corner 0 at v (the frame setup uses for that cube).
+// An edge with nothing to draw gets flags 0.
+TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams &V, int64_t v,
+                                       const RecHead *__restrict__ thead, const double *__restrict__ kinks,
+                                       RecHead head[7], Payload coef[7]) {
+    const int64_t i = v % L.d[0];
+    const int64_t rest = v / L.d[0];
+    const int64_t j = rest % L.d[1];
+    const int64_t k = rest / L.d[1];
+    // corners 0..4 of the cube at v (they may lie past a non-periodic lattice)
+    double X0[3] = {0.0, 0.0, 0.0}, e[5][3];
+    bool has[5];
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+        int64_t ii = i + (n & 1), jj = j + ((n >> 1) & 1), kk = k + ((n >> 2) & 1);
+        if (L.periodic) {
+            if (ii == L.d[0]) ii = 0;
+            if (jj == L.d[1]) jj = 0;
+            if (kk == L.d[2]) kk = 0;
+        }
+        has[n] = ii < L.d[0] && jj < L.d[1] && kk < L.d[2];
+        e[n][0] = e[n][1] = e[n][2] = 0.0;
+        if (!has[n]) continue;
+        const int64_t id = ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk);
+        const double p[3] = {(double)L.x[id], (double)L.y[id], (double)L.z[id]};
+        if (n == 0) {
+            X0[0] = p[0]; X0[1] = p[1]; X0[2] = p[2];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double d = p[a] - X0[a];
+                if (L.periodic) d -= L.box[a] * ceil(d / L.box[a] - 0.5);
+                e[n][a] = d;
+            }
+        }
+    }
+    const double b0[3] = {X0[0] - V.center[0], X0[1] - V.center[1], X0[2] - V.center[2]};
+    double PX0 = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
+    double PY0 = (V.rot[3] * b0[0] + V.rot[4] * b0[1] + V.rot[5] * b0[2] - V.v_bottom) * V.inv_dv;
+    if (V.wrap) {
+        PX0 -= (double)V.W * floor(PX0 / (double)V.W);
+        PY0 -= (double)V.H * floor(PY0 / (double)V.H);
+    }
+#pragma unroll
+    for (int tau = 0; tau < 7; ++tau) {
+        RecHead R;
+        R.bx = 0; R.by = 0; R.flags = 0; R.spare = 0;
+        double pc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        [&] {
+            const int ca = kEdgeEnds[tau][0], cb = kEdgeEnds[tau][1];
+            if (!has[ca] || !has[cb]) return;
+            double D = 0.0;
+            uint32_t ne = 0, nl = 0;
+            for (int u = kEdgeFirst[tau]; u < kEdgeFirst[tau + 1]; ++u) {
+                const EdgeUse U = kEdgeUse[u];
+                int64_t ci = i + U.dx, cj = j + U.dy, ck = k + U.dz;
+                if (L.periodic) {
+                    if (ci < 0) ci += L.c[0];
+                    if (cj < 0) cj += L.c[1];
+                    if (ck < 0) ck += L.c[2];
+                } else if (ci < 0 || cj < 0 || ck < 0 || ci >= L.c[0] || cj >= L.c[1] || ck >= L.c[2]) {
+                    continue;
+                }
+                const int64_t tet = 6 * (ci + (int64_t)L.c[0] * (cj + (int64_t)L.c[1] * ck)) + U.t;
+                const RecHead th = thead[tet];
+                if (!(th.flags & REC_EDGED)) continue;
+                D += kinks[6 * tet + U.e];
+                const uint32_t sb = (th.spare >> (2 * U.e)) & 3u;
+                ne += sb == 1u ? 1u : 0u;
+                nl += sb == 2u ? 1u : 0u;
+            }
+            if (D == 0.0 && ne == 0u && nl == 0u) return;
+            double ax = PX0, ay = PY0, bx = PX0, by = PY0;
+#pragma unroll
+            for (int n = 1; n < 5; ++n) {
+                const double px = PX0 + (V.rot[0] * e[n][0] + V.rot[1] * e[n][1] + V.rot[2] * e[n][2]) * V.inv_du;
+                const double py = PY0 + (V.rot[3] * e[n][0] + V.rot[4] * e[n][1] + V.rot[5] * e[n][2]) * V.inv_dv;
+                if (n == ca) { ax = px; ay = py; }
+                if (n == cb) { bx = px; by = py; }
+            }
+            // columns receiving its deposits: floor(x - 1/2) + 1 (+ kRightReach);
+            // rows whose centre lies in [min y, max y)
+            const double lim = 1.0e8;
+            const double xlo = fmin(ax, bx), xhi = fmax(ax, bx), ylo = fmin(ay, by), yhi = fmax(ay, by);
+            int ix0 = (int)fmax(floor(xlo - 0.5), -lim) + 1, ix1 = (int)fmin(floor(xhi - 0.5), lim);
+            int iy0 = (int)fmax(ceil(ylo - 0.5), -lim), iy1 = (int)fmin(ceil(yhi - 0.5), lim) - 1;
+            if (ix1 < ix0) ix1 = ix0;
+            if (!V.wrap) {
+                ix0 = ix0 > 0 ? ix0 : 0;
+                iy0 = iy0 > 0 ? iy0 : 0;
+                ix1 = ix1 < V.W - 1 ? ix1 : V.W - 1;
+                iy1 = iy1 < V.H - 1 ? iy1 : V.H - 1;
+            }
+            if (ix0 > ix1 || iy0 > iy1) return;
+            pc[0] = ax - (double)ix0;
+            pc[1] = ay - (double)iy0;
+            pc[2] = bx - (double)ix0;
+            pc[3] = by - (double)iy0;
+            pc[4] = D;
+            R.bx = pack_range(ix0, ix1);
+            R.by = pack_range(iy0, iy1);
+            R.flags = REC_EDGE | REC_VALID;
+            R.spare = ne | (nl << 8);
+        }();
+        head[tau] = R;
+        if (R.flags & REC_VALID) {
+            // the five words and the head copy (the rest of the line is unused)
+            Payload &P = coef[tau];
+#pragma unroll
+            for (int g = 0; g < 5; ++g) P.c[g] = pc[g];
+            P.h = R;
+        }
     }
 }
 
@@ -1481,6 +1738,79 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
     return frags;
 }
 
+// Edge form: one mesh edge's summed slope change D along its projection from
+// P to Q, deposited on the rows whose centre lies in [min y, max y) (the
+// crease form's rule, so that at a vertex the edges above and below take
+// the row once between them).  Nothing is folded at the image's left edge:
+// the tetrahedra behind an edge lie within the image's columns, and under
+// wrap every crossing lands in the one tile copy whose columns hold it.
+// Fragments: a tetrahedron's row holds (samples left of its leaving
+// crossing) - (samples left of its entering crossing); each crossing adds
+// its terms, in image columns, once, in the tile holding the column right
+// of it.  Returns the count as the bits of a signed 32-bit value.
+template <typename Dep>
+TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0, int ty0,
+                                  int n, int rows, Dep &&dep, uint32_t &spans, uint32_t &kinks) {
+    const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
+    const int by0 = range_lo(h.by), by1 = range_hi(h.by);
+    int kx0, kx1, ky0, ky1;
+    axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
+    const double Px = cf[0], Py = cf[1], Qx = cf[2], Qy = cf[3], D = cf[4];
+    const int ne = (int)(h.spare & 255u), nl = (int)((h.spare >> 8) & 255u);
+    const bool count = (ne | nl) != 0;
+    // under wrap the edge lies in one period of its frame, m W + [1, W - 1]:
+    // only that copy of the tile meets it (another copy would carry the
+    // deposits past the image's right edge round to its left)
+    if (B.wrap) {
+        const int m = floor_div(range_lo(h.bx), B.W);
+        kx0 = max(kx0, m);
+        kx1 = min(kx1, m);
+    }
+    const double sl = (Qx - Px) * fast_rcp(Qy - Py);
+    const int qa = (int)ceil(fmin(Py, Qy) - 0.5), qb = (int)ceil(fmax(Py, Qy) - 0.5) - 1;
+    int frags = 0;
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        const int rshift = by0 - ky * B.H - ty0;
+        const int q0 = max(qa, max(-rshift, 0)), q1 = min(qb, min(rows - 1 - rshift, by1 - by0));
+        if (q0 > q1) continue;
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
+            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            const double xl = X0 - 3.0, xr = X0 + (double)n + 1.0;
+            int r0 = q0, r1 = q1;
+            if (Qx != Px) {
+                // the rows whose crossing lies in [xl, xr), with the margins
+                // of the crease form
+                const double iv = (Qy - Py) * fast_rcp(Qx - Px);
+                double ya = Py + (xl - Px) * iv, yb = Py + (xr - Px) * iv;
+                if (ya > yb) { const double t = ya; ya = yb; yb = t; }
+                ya = fmin(fmax(ya, (double)q0 - 1.0), (double)q1 + 2.0);
+                yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 2.0);
+                r0 = max(q0, (int)floor(ya - 0.5));
+                r1 = min(q1, (int)ceil(yb - 0.5));
+            }
+            double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
+            const int len = max(r1 - r0 + 1, 0);
+            kinks += (uint32_t)len;
+            for (int r = r0; r <= r1; ++r, w += sl) {
+                const int row = r + rshift;
+                const double fw = floor(w);
+                const int k = min(max((int)fmin(fmax(fw, -4.0), (double)n), -3), n - 1);
+                const double v1 = fma(D, (double)k - w, D);
+                dep(row, k + 1, v1);
+                dep(row, k + 2, D - v1);
+                if (count && fw >= -1.0 && fw <= (double)(n - 2)) {
+                    const int jl = tx0 + 1 + (int)floor(w - kSampleEps), je = tx0 + 1 + (int)floor(w + kSampleEps);
+                    frags += nl * jl - ne * je;
+                }
+            }
+        }
+    }
+    (void)spans;
+    return (uint32_t)frags;
+}
+
 // One record in one tile, in whichever form its payload has.
 // (A launch holds records of one kind: pyramids in crease or line form, face
 // form with a depth slab, or splats; FORM selects it at compile time.)
@@ -1495,6 +1825,7 @@ TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const 
     } else if constexpr (FORM == kFormPersp) {
         return persp_pair(h, cf, B, tx0, ty0, n, rows, 0, 1, dep, spans, kinks);
     } else {
+        if (h.flags & REC_EDGE) return edge_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
         if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
         return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     }

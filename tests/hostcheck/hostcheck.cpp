@@ -18,7 +18,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                            const double center[3], const double extent[2], int32_t W, int32_t H,
                            int32_t wrap, int32_t tile_rows, int32_t tile_cols, int32_t chunk,
                            double crease_div, int32_t qpow, const double *slab, int32_t splat, int32_t persp, int32_t hybrid, double lod_radius,
-                           double *out64, float *out32,
+                           int32_t edges, double *out64, float *out32,
                            long long *stats /* [tets, zero, inverted, fp64_dets, fragments, spans,
                                                pairs, items, crease_records] */) {
     LatticeParams L;
@@ -61,9 +61,14 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         for (int64_t cube = 0; cube < L.ncubes; ++cube) qsum += cube_qvol(L, V, cube);
         V.qsum = &qsum;
     }
-    const int64_t ntet = 6 * L.ncubes;
+    // the edge form (plain pyramids): seven edge records per lattice vertex after the tetrahedra
+    V.edges = (edges && !persp && !splat && !slab) ? 1 : 0;
+    const int64_t nvert = (int64_t)L.d[0] * L.d[1] * L.d[2];
+    const int64_t ntet = 6 * L.ncubes + (V.edges ? 7 * nvert : 0);
     std::vector<RecHead> head(ntet);
     std::vector<Payload> coef(ntet);
+    std::vector<double> kinks(V.edges ? 36 * L.ncubes : 0);
+    V.kinks = V.edges ? kinks.data() : nullptr;
     long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0;
     for (int64_t cube = 0; cube < L.ncubes; ++cube) {
         CubeCounts cnt;
@@ -72,8 +77,12 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         else if (slab) setup_cube<kFormFace>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else setup_cube<kFormPyramid>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
-        for (int t = 0; t < 6; ++t) creases += (head[6 * cube + t].flags & REC_CREASE) ? 1 : 0;
+        for (int t = 0; t < 6; ++t) creases += (head[6 * cube + t].flags & (REC_CREASE | REC_EDGED)) ? 1 : 0;
     }
+    if (V.edges)
+        for (int64_t v = 0; v < nvert; ++v)
+            setup_vertex_edges(L, V, v, head.data(), kinks.data(), &head[6 * L.ncubes + 7 * v],
+                               &coef[6 * L.ncubes + 7 * v]);
     BinParams B;
     B.Th = tile_rows;
     B.Tw = tile_cols;
@@ -89,7 +98,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     B.ext_u = extent[0];
     B.ext_v = extent[1];
     const int ntiles = B.ntx * B.nty;
-    B.nkey = (splat || slab || persp) ? 1 : 32;
+    B.nkey = (splat || slab || persp || V.edges) ? 1 : 32;
     // per tile: its records in id order; every pair's work class in range
     std::vector<std::vector<uint32_t>> lists(ntiles);
     for (int64_t id = 0; id < ntet; ++id) {
@@ -98,7 +107,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         const TileRange tr = tet_tiles(r, B);
         for (int s = 0; s < tr.count; ++s) {
             const int tile = tet_tile(B, tr, s);
-            const int cls = pair_class(r, B, tile / B.ntx);
+            const int cls = B.nkey > 1 ? pair_class(r, B, tile / B.ntx) : 0;
             if (cls < 0 || cls >= B.nkey || (cls != 0 && !(r.flags & REC_CREASE))) return -2;
             lists[tile].push_back((uint32_t)id);
         }
@@ -124,7 +133,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                          : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
                                 : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk);
                 };
-                frags += rr(
+                frags += (int32_t)rr(
                                      [&](int row, int j, double v) {
                                          if (row < 0 || row >= rows || j < -2 || j > n + 1) throw 1;
                                          if (j >= 0 && j < n) tile[(size_t)row * B.Tw + j] += v;

@@ -305,11 +305,18 @@ def test_repeatable_and_tiling_independent(tess, tiny_lattice):
         np.testing.assert_allclose(b, a, rtol=2.4e-7, atol=1e-12 * a.max())
 
 
-def test_work_classes_keep_the_image(tess):
+@pytest.fixture
+def per_tetrahedron(monkeypatch):
+    # every crease drawn per tetrahedron (the edge form off)
+    monkeypatch.setenv("TESS_PER_TETRAHEDRON", "1")
+
+
+def test_work_classes_keep_the_image(tess, per_tetrahedron):
     # many tiles: the tile lists are sorted into 32 work classes (default
     # 32 x 512 tiles), 2 (8 x 64) or none (4 x 32); the sorted plans must give
     # the unsorted plan's image and match the oracle's samples.  (The mean of
     # the pixel-centre samples is 1 only to the sampling error, ~2e-5 here.)
+    # Work classes sort per-tetrahedron creases, so the edge form is off.
     import torch
     n = 32
     xyz = W.zeldovich(n, 8, 4.0)
@@ -325,6 +332,32 @@ def test_work_classes_keep_the_image(tess):
     px, py = sample_pixels(1024, 1024, 200, 3)
     ref, _ = O.project_pixels(*xyz, (n, n, n), view, px, py)
     assert rel_err(imgs[0][py, px].astype(np.float32), ref).max() <= PIX_TOL
+
+
+@pytest.mark.parametrize("view_kind", ["z_wrap", "rotated"])
+def test_edge_form_equals_per_tetrahedron_form(tess, monkeypatch, view_kind):
+    # the creases summed per mesh edge and drawn per tetrahedron give the same
+    # image (up to the rounding of the sums) and the same fragment count, and
+    # the edge form draws fewer kinks
+    import torch
+    n = 32
+    xyz = W.zeldovich(n, 8, 6.0, seed=21)
+    lat = tess.build(*dev(xyz), (n, n, n))
+    view = W.z_view(768, 640) if view_kind == "z_wrap" else W.rotated_view(W.random_rotations(1, seed=8)[0], 700, 600)
+    out = {}
+    for per_tet in ("0", "1"):
+        monkeypatch.setenv("TESS_PER_TETRAHEDRON", per_tet)
+        img, st = tess.project(lat, view, stats=True)
+        out[per_tet] = (img.cpu().numpy().astype(np.float64), st)
+    torch.cuda.synchronize()
+    (a, sa), (b, sb) = out["0"], out["1"]
+    np.testing.assert_allclose(a, b, rtol=2.4e-7, atol=1e-9 * b.max())
+    assert sa["fragments"] == sb["fragments"] and sa["tets"] == sb["tets"]
+    # (without wrap, tetrahedra of cubes cut by the box's faces stay per tetrahedron)
+    assert sa["kinks"] < (0.5 if view_kind == "z_wrap" else 0.7) * sb["kinks"], (sa["kinks"], sb["kinks"])
+    px, py = sample_pixels(view["width"], view["height"], 150, 4)
+    ref, _ = O.project_pixels(*xyz, (n, n, n), view, px, py)
+    assert rel_err(a[py, px].astype(np.float32), ref).max() <= PIX_TOL
 
 
 def batch_case(tess, n=16, growths=(1.0, 4.0), nviews=3, size=64):

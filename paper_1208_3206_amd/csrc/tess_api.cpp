@@ -68,7 +68,8 @@ namespace {
 struct Workspace {
     DevBuf<RecHead> head;
     DevBuf<Payload> coef;
-    DevBuf<double> kinks;               // edge form: 6 slope changes per tetrahedron
+    DevBuf<double> kinks;               // edge form: 36 slope-change slots per lattice vertex
+    DevBuf<uint8_t> sil;                // and their silhouette kinds
     DevBuf<uint32_t> counts;
     DevBuf<uint64_t> base;
     DevBuf<uint64_t> scan;
@@ -358,6 +359,7 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     const char *per_tet = getenv("TESS_PER_TETRAHEDRON");
     vp.edges = (view_form(vp) == kFormPyramid && !(per_tet && per_tet[0] == '1')) ? 1 : 0;
     vp.kinks = nullptr;
+    vp.sil = nullptr;
 }
 
 struct Plan {
@@ -433,7 +435,11 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
 tess_status ensure_front(Workspace &ws, const Geometry &g) {
     TESS_HIP(ws.head.ensure((size_t)g.ntet));
     TESS_HIP(ws.coef.ensure((size_t)g.ntet));
-    if (g.vp.edges) TESS_HIP(ws.kinks.ensure((size_t)36 * (size_t)g.lp.ncubes));
+    if (g.vp.edges) {
+        const size_t slots = (size_t)36 * (size_t)g.lp.d[0] * (size_t)g.lp.d[1] * (size_t)g.lp.d[2];
+        TESS_HIP(ws.kinks.ensure(slots));
+        TESS_HIP(ws.sil.ensure(slots));
+    }
     TESS_HIP(ws.counts.ensure((size_t)g.nmat));
     TESS_HIP(ws.base.ensure((size_t)g.nmat));
     TESS_HIP(ws.scan.ensure(scan_scratch_elems(g.nmat)));
@@ -464,8 +470,9 @@ tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipSt
         vp.qsum = &slot->qsum;
     }
     vp.kinks = ws.kinks.p;
+    vp.sil = ws.sil.p;
     TESS_HIP(launch_setup(g.lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
-    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, ws.head.p, ws.head.p, ws.coef.p, s));
+    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, ws.head.p, ws.coef.p, s));
     return TESS_OK;
 }
 
@@ -676,7 +683,7 @@ std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *v
     put(views, sizeof(tess_view) * (size_t)n_views);
     put(&images, sizeof(images));
     put(&t, sizeof(t));
-    const void *bufs[] = {ws.head.p, ws.coef.p, ws.kinks.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
+    const void *bufs[] = {ws.head.p, ws.coef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
                           ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p, ws.overflow.p};
     put(bufs, sizeof(bufs));
     const char *per_tet = getenv("TESS_PER_TETRAHEDRON");

@@ -43,10 +43,13 @@ struct ViewParams {
     int32_t hybrid;          // perspective: exact within lod_radius of the camera, billboards beyond
     double lod_radius;
     // pyramid form: 1 = the creases of tetrahedra inside the image's columns
-    // are summed per mesh edge (setup writes each tetrahedron's kinks to
-    // `kinks`, 6 per tetrahedron, and the edge records carry the sums)
+    // are summed per mesh edge (setup writes each tetrahedron's slope change
+    // per edge, and whether the edge is an entering (1) or leaving (2)
+    // silhouette edge, into 36 slots per lattice vertex, slot-major; the
+    // edge records carry the sums)
     int32_t edges;
     double *kinks;
+    uint8_t *sil;
 };
 
 // Record kinds of a launch (one per view): the pyramid (crease and line
@@ -170,8 +173,8 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
 
 // Edge records 6 ncubes + 7 v + tau of every lattice vertex v from the
 // kinks setup wrote (edge form).
-hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, const RecHead *tet_head, RecHead *head,
-                        Payload *coef, hipStream_t stream);
+hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
+                        hipStream_t stream);
 
 hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
                         hipStream_t stream);

@@ -42,6 +42,28 @@ constexpr EdgeUse kEdgeUse[36] = {
     {-1, 0, 0, 2, 0}, {-1, 0, 0, 3, 1}, {-1, 0, 0, 5, 1}, {0, 0, 0, 0, 5}, {0, 0, 0, 1, 5}, {0, 0, 0, 4, 4},
     {0, 0, 0, 1, 2}, {0, 0, 0, 2, 2}, {0, 0, 0, 3, 2}, {0, 0, 0, 4, 2}};
 
+// The inverse of kEdgeUse: local edge e of tetrahedron t of cube c is entry
+// u of edge kind tau of the vertex at c + (ox, oy, oz), o = -d in {0, 1}^3
+// (a corner of c).  Setup writes each tetrahedron's slope changes into these
+// slots, 36 per vertex in the order of kEdgeUse and stored slot-major (slot u
+// of vertex w at u * nvert + w), so that both the writes of neighbouring
+// cubes and the reads of neighbouring vertices are contiguous.
+struct EdgeSlot {
+    int8_t u, ox, oy, oz;
+};
+struct EdgeSlots {
+    EdgeSlot s[6][6];
+};
+constexpr EdgeSlots make_edge_slots() {
+    EdgeSlots T{};
+    for (int u = 0; u < 36; ++u) {
+        const EdgeUse U = kEdgeUse[u];
+        T.s[U.t][U.e] = EdgeSlot{(int8_t)u, (int8_t)-U.dx, (int8_t)-U.dy, (int8_t)-U.dz};
+    }
+    return T;
+}
+constexpr EdgeSlots kEdgeSlots = make_edge_slots();
+
 // local edge index of the tetrahedron vertex pair (u, v), u != v
 TESS_HD inline int local_edge(int u, int v) {
     const int a = u < v ? u : v, b = u < v ? v : u;
@@ -469,6 +491,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                                Payload coef[6], CubeCounts &cnt) {
     double X0[3], e[8][3];
     const bool moved = cube_corners(L, cube, X0, e);
+    const int64_t ci = cube % L.c[0], cj = (cube / L.c[0]) % L.c[1], ck = cube / ((int64_t)L.c[0] * L.c[1]);
+    const int64_t nvert = (int64_t)L.d[0] * L.d[1] * L.d[2];
     // edge form: the cube's edges are placed from their own vertices (corners
     // of this cube).  That gives the same segments as this cube's corners if
     // the corners lie within half a box of each other along every axis (then
@@ -747,7 +771,9 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                     // creases to the mesh edges, where they are summed over the
                     // tetrahedra around each edge (when same_frame holds)
                     uint32_t sil = 0u;
-                    if (V.edges && same_frame && xmin >= 1.0 && xmax <= (double)V.W - 1.0 &&
+                    // (with wrap, the period that holds xmin)
+                    const double xsh = V.wrap ? (double)V.W * floor(xmin / (double)V.W) : 0.0;
+                    if (V.edges && same_frame && xmin - xsh >= 1.0 && xmax - xsh <= (double)V.W - 1.0 &&
                         crease_kinks(fp, kd, sil)) {
                         R.flags = REC_EDGED | (uint32_t)fp.ng;
                         R.spare = sil;
@@ -769,9 +795,19 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         if (R.flags & REC_VALID) coef[t] = P;  // nothing reads the payload of other records
         if constexpr (FORM == kFormPyramid) {
             if (V.edges) {
-                double *k6 = V.kinks + 36 * cube + 6 * t;
+                // every slot of the cube's tetrahedra is written (zeros for
+                // the tetrahedra that keep their own record)
+                const uint32_t sil = (R.flags & REC_EDGED) ? R.spare : 0u;
 #pragma unroll
-                for (int e = 0; e < 6; ++e) k6[e] = kd[e];
+                for (int e = 0; e < 6; ++e) {
+                    const EdgeSlot S = kEdgeSlots.s[t][e];
+                    const int64_t vx = ci + S.ox == L.d[0] ? 0 : ci + S.ox;
+                    const int64_t vy = cj + S.oy == L.d[1] ? 0 : cj + S.oy;
+                    const int64_t vz = ck + S.oz == L.d[2] ? 0 : ck + S.oz;
+                    const int64_t slot = (int64_t)S.u * nvert + vx + (int64_t)L.d[0] * (vy + (int64_t)L.d[1] * vz);
+                    V.kinks[slot] = kd[e];
+                    V.sil[slot] = (uint8_t)((sil >> (2 * e)) & 3u);
+                }
             }
         }
     }
@@ -784,12 +820,12 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 // frame of the cube with corner 0 at v (the frame setup uses for that cube).
 // An edge with nothing to draw gets flags 0.
 TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams &V, int64_t v,
-                                       const RecHead *__restrict__ thead, const double *__restrict__ kinks,
                                        RecHead head[7], Payload coef[7]) {
     const int64_t i = v % L.d[0];
     const int64_t rest = v / L.d[0];
     const int64_t j = rest % L.d[1];
     const int64_t k = rest / L.d[1];
+    const int64_t nvert = (int64_t)L.d[0] * L.d[1] * L.d[2];
     // corners 0..4 of the cube at v (they may lie past a non-periodic lattice)
     double X0[3] = {0.0, 0.0, 0.0}, e[5][3];
     bool has[5];
@@ -836,19 +872,12 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
             uint32_t ne = 0, nl = 0;
             for (int u = kEdgeFirst[tau]; u < kEdgeFirst[tau + 1]; ++u) {
                 const EdgeUse U = kEdgeUse[u];
-                int64_t ci = i + U.dx, cj = j + U.dy, ck = k + U.dz;
-                if (L.periodic) {
-                    if (ci < 0) ci += L.c[0];
-                    if (cj < 0) cj += L.c[1];
-                    if (ck < 0) ck += L.c[2];
-                } else if (ci < 0 || cj < 0 || ck < 0 || ci >= L.c[0] || cj >= L.c[1] || ck >= L.c[2]) {
-                    continue;
+                if (!L.periodic) {  // slots of cubes past the lattice are never written
+                    const int64_t ci = i + U.dx, cj = j + U.dy, ck = k + U.dz;
+                    if (ci < 0 || cj < 0 || ck < 0 || ci >= L.c[0] || cj >= L.c[1] || ck >= L.c[2]) continue;
                 }
-                const int64_t tet = 6 * (ci + (int64_t)L.c[0] * (cj + (int64_t)L.c[1] * ck)) + U.t;
-                const RecHead th = thead[tet];
-                if (!(th.flags & REC_EDGED)) continue;
-                D += kinks[6 * tet + U.e];
-                const uint32_t sb = (th.spare >> (2 * U.e)) & 3u;
+                D += V.kinks[(int64_t)u * nvert + v];
+                const uint32_t sb = V.sil[(int64_t)u * nvert + v];
                 ne += sb == 1u ? 1u : 0u;
                 nl += sb == 2u ? 1u : 0u;
             }
@@ -887,11 +916,12 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
         }();
         head[tau] = R;
         if (R.flags & REC_VALID) {
-            // the five words and the head copy (the rest of the line is unused)
-            Payload &P = coef[tau];
+            // the whole line (a partial one would cost a read-modify-write)
+            Payload P;
 #pragma unroll
-            for (int g = 0; g < 5; ++g) P.c[g] = pc[g];
+            for (int g = 0; g < 14; ++g) P.c[g] = g < 5 ? pc[g] : 0.0;
             P.h = R;
+            coef[tau] = P;
         }
     }
 }

@@ -51,7 +51,7 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
         crease_div = W / 64.0
     out64 = np.zeros((H, W), dtype=np.float64)
     out32 = np.zeros((H, W), dtype=np.float32)
-    st = np.zeros(9, dtype=np.int64)
+    st = np.zeros(10, dtype=np.int64)
     d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
     rot = (ctypes.c_double * 9)(*[float(v) for v in view["rot"]])
     cen = (ctypes.c_double * 3)(*[float(v) for v in view["center"]])
@@ -71,5 +71,5 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
     if rc != 0:
         raise RuntimeError(f"hostcheck pipeline failed: {rc}")
     keys = ("tets", "zero_volume", "inverted", "fp64_dets", "fragments", "spans", "pairs", "items",
-            "crease_records")
+            "crease_records", "edged")
     return out64, out32, dict(zip(keys, (int(v) for v in st)))

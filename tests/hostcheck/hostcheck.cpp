@@ -20,7 +20,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                            double crease_div, int32_t qpow, const double *slab, int32_t splat, int32_t persp, int32_t hybrid, double lod_radius,
                            int32_t edges, double *out64, float *out32,
                            long long *stats /* [tets, zero, inverted, fp64_dets, fragments, spans,
-                                               pairs, items, crease_records] */) {
+                                               pairs, items, crease_records, edged] */) {
     LatticeParams L;
     std::memset(&L, 0, sizeof(L));
     L.x = x; L.y = y; L.z = z;
@@ -67,9 +67,11 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     const int64_t ntet = 6 * L.ncubes + (V.edges ? 7 * nvert : 0);
     std::vector<RecHead> head(ntet);
     std::vector<Payload> coef(ntet);
-    std::vector<double> kinks(V.edges ? 36 * L.ncubes : 0);
+    std::vector<double> kinks(V.edges ? 36 * nvert : 0);
+    std::vector<uint8_t> sil(V.edges ? 36 * nvert : 0);
     V.kinks = V.edges ? kinks.data() : nullptr;
-    long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0;
+    V.sil = V.edges ? sil.data() : nullptr;
+    long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0, edged = 0;
     for (int64_t cube = 0; cube < L.ncubes; ++cube) {
         CubeCounts cnt;
         if (persp) setup_cube<kFormPersp>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
@@ -77,12 +79,14 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         else if (slab) setup_cube<kFormFace>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else setup_cube<kFormPyramid>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
-        for (int t = 0; t < 6; ++t) creases += (head[6 * cube + t].flags & (REC_CREASE | REC_EDGED)) ? 1 : 0;
+        for (int t = 0; t < 6; ++t) {
+            creases += (head[6 * cube + t].flags & (REC_CREASE | REC_EDGED)) ? 1 : 0;
+            edged += (head[6 * cube + t].flags & REC_EDGED) ? 1 : 0;
+        }
     }
     if (V.edges)
         for (int64_t v = 0; v < nvert; ++v)
-            setup_vertex_edges(L, V, v, head.data(), kinks.data(), &head[6 * L.ncubes + 7 * v],
-                               &coef[6 * L.ncubes + 7 * v]);
+            setup_vertex_edges(L, V, v, &head[6 * L.ncubes + 7 * v], &coef[6 * L.ncubes + 7 * v]);
     BinParams B;
     B.Th = tile_rows;
     B.Tw = tile_cols;
@@ -156,6 +160,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     if (stats) {
         stats[0] = tets; stats[1] = zero; stats[2] = inv; stats[3] = dets;
         stats[4] = frags; stats[5] = spans; stats[6] = pairs; stats[7] = items; stats[8] = creases;
+        stats[9] = edged;
     }
     return 0;
 }

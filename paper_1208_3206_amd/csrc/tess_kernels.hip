@@ -453,7 +453,9 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     // fall outside the tile, so that the raster needs no bounds tests
     const int stride = B.Tw + 2 * kPad;
     const int tsize = B.Th * stride;
-    for (int i = threadIdx.x; i < tsize; i += TPB) sA[i] = 0.0;
+    // then per tile row the seam line a + b j of the edge form (a, then b)
+    double *sSeam = sA + tsize;
+    for (int i = threadIdx.x; i < tsize + 2 * B.Th; i += TPB) sA[i] = 0.0;
     __syncthreads();
     long long frags = 0;  // edge records add signed terms
     uint32_t spans = 0, kinks = 0;
@@ -461,9 +463,14 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         if (id >= B.ntet) return;
         const RecHead h = coef[id].h;
         if (!(h.flags & REC_VALID)) return;
-        frags += (int32_t)raster_record<FORM>(h, coef[id].c, B, tx0, ty0, n, rows,
-                                     [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
-                                     spans, kinks);
+        frags += (int32_t)raster_record<FORM>(
+            h, coef[id].c, B, tx0, ty0, n, rows,
+            [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+            [&](int row, double a, double b) {
+                atomicAdd(&sSeam[row], a);
+                atomicAdd(&sSeam[B.Th + row], b);
+            },
+            spans, kinks);
     };
     // lane t takes entries t*per .. t*per+per-1: the list is in rough id order
     // (neighbouring cubes), so this spreads a wavefront's 64 footprints over
@@ -493,7 +500,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         // together then hold pairs of about the same work.  `per` is the same
         // for every lane, so the whole wavefront runs every round.
         const uint32_t lane = threadIdx.x & 63u;
-        uint32_t *cnt = reinterpret_cast<uint32_t *>(sA + tsize) + (threadIdx.x >> 6) * kSortWords;
+        uint32_t *cnt = reinterpret_cast<uint32_t *>(sA + tsize + 2 * B.Th) + (threadIdx.x >> 6) * kSortWords;
         uint32_t *ent = cnt + kNumClasses;
         for (uint32_t b = 0; b < per; b += kSortPer) {
             uint32_t v[kSortPer], rk[kSortPer];
@@ -549,6 +556,12 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         const double v = sA[r * stride + kPad + c];
         if (c < n && v != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + tx0 + c], v);
     }
+    // the seam lines: a at column 0 and b - a at column 1 of the second differences
+    for (int r = threadIdx.x; r < rows; r += TPB) {
+        const double a = sSeam[r], b = sSeam[B.Th + r];
+        if (a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W], a);
+        if (B.W > 1 && b - a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + 1], b - a);
+    }
     const unsigned long long f = wave_sum((unsigned long long)frags);
     const unsigned long long sp = wave_sum((unsigned long long)spans);
     const unsigned long long kk = wave_sum((unsigned long long)kinks);
@@ -586,7 +599,7 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_
     if (max_items == 0) return hipSuccess;
     if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
     // the tile's accumulator, and beside it (when it fits) the wavefronts' class sorts
-    const size_t tile_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
+    const size_t tile_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad + 2);  // tile and seam lines
     const size_t sort_lds = sizeof(uint32_t) * (size_t)(block / 64) * kSortWords;
     const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;
     const size_t lds = tile_lds + (sorted ? sort_lds : 0);

@@ -482,6 +482,17 @@ TESS_HD inline double cube_qvol(const LatticeParams &L, const ViewParams &V, int
     return sum;
 }
 
+// Pixel x of lattice vertex `id` in its own frame (the frame of the cube
+// that has it as corner 0; under wrap, moved into the first period), the
+// same arithmetic in setup and in the edge records.
+TESS_HD inline double vertex_px(const LatticeParams &L, const ViewParams &V, int64_t id) {
+    const double b0[3] = {(double)L.x[id] - V.center[0], (double)L.y[id] - V.center[1],
+                          (double)L.z[id] - V.center[2]};
+    double px = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
+    if (V.wrap) px -= (double)V.W * floor(px / (double)V.W);
+    return px;
+}
+
 // Setup of the six tetrahedra of lattice cube `cube`: gather and unwrap the
 // corners, volume determinant with its FP64 fallback, footprint.  head[t] and
 // coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
@@ -527,6 +538,24 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     for (int n = 0; n < 8; ++n) {
         PX[n] = PX0 + (V.rot[0] * e[n][0] + V.rot[1] * e[n][1] + V.rot[2] * e[n][2]) * V.inv_du;
         PY[n] = PY0 + (V.rot[3] * e[n][0] + V.rot[4] * e[n][1] + V.rot[5] * e[n][2]) * V.inv_dv;
+    }
+    // edge form under wrap: each corner's x in its own frame, where the edge
+    // records it owns are placed (the offset to this cube's frame is a whole
+    // number of periods)
+    double PXE[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) PXE[n] = 0.0;
+    if constexpr (FORM == kFormPyramid) {
+        if (V.edges && V.wrap) {
+#pragma unroll
+            for (int n = 0; n < 8; ++n) {
+                int64_t ii = ci + (n & 1), jj = cj + ((n >> 1) & 1), kk = ck + ((n >> 2) & 1);
+                if (ii == L.d[0]) ii = 0;
+                if (jj == L.d[1]) jj = 0;
+                if (kk == L.d[2]) kk = 0;
+                PXE[n] = vertex_px(L, V, ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk));
+            }
+        }
     }
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
@@ -770,13 +799,34 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                     // pixel of margin; under wrap, within one period) hands its
                     // creases to the mesh edges, where they are summed over the
                     // tetrahedra around each edge (when same_frame holds)
+                    // Without wrap the tetrahedron must lie within the image's
+                    // columns (a pixel of margin).  With wrap any one narrower
+                    // than the image will do: in the frame that puts its left
+                    // end in the first period, an edge lies s periods from
+                    // where its own vertex places it (s in -1..1, kept in bits
+                    // 2-3 of the silhouette kind as s + 1), and the raster
+                    // corrects the rows at the period's seam from it.
                     uint32_t sil = 0u;
-                    // (with wrap, the period that holds xmin)
-                    const double xsh = V.wrap ? (double)V.W * floor(xmin / (double)V.W) : 0.0;
-                    if (V.edges && same_frame && xmin - xsh >= 1.0 && xmax - xsh <= (double)V.W - 1.0 &&
-                        crease_kinks(fp, kd, sil)) {
+                    bool take = V.edges && same_frame;
+                    uint32_t shift = 0x555u;  // s + 1 = 1 for all six edges
+                    if (take && V.wrap) {
+                        const double xsh = (double)V.W * floor(xmin / (double)V.W);
+                        take = xmax - xmin < (double)V.W - 2.0;
+                        shift = 0u;
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) {
+                            const EdgeSlot S = kEdgeSlots.s[t][q];
+                            const int m = S.ox + 2 * S.oy + 4 * S.oz;
+                            const double per = rint((PX[m] - xsh - PXE[m]) / (double)V.W);
+                            take = take && per >= -1.0 && per <= 1.0;
+                            shift |= (uint32_t)((int)per + 1) << (2 * q);
+                        }
+                    } else if (take) {
+                        take = xmin >= 1.0 && xmax <= (double)V.W - 1.0;
+                    }
+                    if (take && crease_kinks(fp, kd, sil)) {
                         R.flags = REC_EDGED | (uint32_t)fp.ng;
-                        R.spare = sil;
+                        R.spare = sil | (shift << 12);
                         return;
                     }
                 }
@@ -798,6 +848,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 // every slot of the cube's tetrahedra is written (zeros for
                 // the tetrahedra that keep their own record)
                 const uint32_t sil = (R.flags & REC_EDGED) ? R.spare : 0u;
+                const uint32_t shf = (R.flags & REC_EDGED) ? (R.spare >> 12) : 0x555u;
 #pragma unroll
                 for (int e = 0; e < 6; ++e) {
                     const EdgeSlot S = kEdgeSlots.s[t][e];
@@ -806,7 +857,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                     const int64_t vz = ck + S.oz == L.d[2] ? 0 : ck + S.oz;
                     const int64_t slot = (int64_t)S.u * nvert + vx + (int64_t)L.d[0] * (vy + (int64_t)L.d[1] * vz);
                     V.kinks[slot] = kd[e];
-                    V.sil[slot] = (uint8_t)((sil >> (2 * e)) & 3u);
+                    V.sil[slot] = (uint8_t)(((sil >> (2 * e)) & 3u) | (((shf >> (2 * e)) & 3u) << 2));
                 }
             }
         }
@@ -854,34 +905,34 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
         }
     }
     const double b0[3] = {X0[0] - V.center[0], X0[1] - V.center[1], X0[2] - V.center[2]};
-    double PX0 = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
+    const double PX0 = vertex_px(L, V, v);
     double PY0 = (V.rot[3] * b0[0] + V.rot[4] * b0[1] + V.rot[5] * b0[2] - V.v_bottom) * V.inv_dv;
-    if (V.wrap) {
-        PX0 -= (double)V.W * floor(PX0 / (double)V.W);
-        PY0 -= (double)V.H * floor(PY0 / (double)V.H);
-    }
+    if (V.wrap) PY0 -= (double)V.H * floor(PY0 / (double)V.H);
 #pragma unroll
     for (int tau = 0; tau < 7; ++tau) {
         RecHead R;
         R.bx = 0; R.by = 0; R.flags = 0; R.spare = 0;
-        double pc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double pc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         [&] {
             const int ca = kEdgeEnds[tau][0], cb = kEdgeEnds[tau][1];
             if (!has[ca] || !has[cb]) return;
-            double D = 0.0;
-            uint32_t ne = 0, nl = 0;
+            double D[3] = {0.0, 0.0, 0.0};  // by period offset s + 1
+            uint32_t cnt = 0u;               // 3 bits each: entering s = -1, 0, 1, then leaving
             for (int u = kEdgeFirst[tau]; u < kEdgeFirst[tau + 1]; ++u) {
                 const EdgeUse U = kEdgeUse[u];
                 if (!L.periodic) {  // slots of cubes past the lattice are never written
                     const int64_t ci = i + U.dx, cj = j + U.dy, ck = k + U.dz;
                     if (ci < 0 || cj < 0 || ck < 0 || ci >= L.c[0] || cj >= L.c[1] || ck >= L.c[2]) continue;
                 }
-                D += V.kinks[(int64_t)u * nvert + v];
+                const double d = V.kinks[(int64_t)u * nvert + v];
                 const uint32_t sb = V.sil[(int64_t)u * nvert + v];
-                ne += sb == 1u ? 1u : 0u;
-                nl += sb == 2u ? 1u : 0u;
+                const uint32_t g = (sb >> 2) & 3u, kind = sb & 3u;
+                D[0] += g == 0u ? d : 0.0;
+                D[1] += g == 1u ? d : 0.0;
+                D[2] += g == 2u ? d : 0.0;
+                if (kind != 0u) cnt += 1u << (3 * g + (kind == 2u ? 9 : 0));
             }
-            if (D == 0.0 && ne == 0u && nl == 0u) return;
+            if (D[0] == 0.0 && D[1] == 0.0 && D[2] == 0.0 && cnt == 0u) return;
             double ax = PX0, ay = PY0, bx = PX0, by = PY0;
 #pragma unroll
             for (int n = 1; n < 5; ++n) {
@@ -908,18 +959,20 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
             pc[1] = ay - (double)iy0;
             pc[2] = bx - (double)ix0;
             pc[3] = by - (double)iy0;
-            pc[4] = D;
+            pc[4] = D[0];
+            pc[5] = D[1];
+            pc[6] = D[2];
             R.bx = pack_range(ix0, ix1);
             R.by = pack_range(iy0, iy1);
             R.flags = REC_EDGE | REC_VALID;
-            R.spare = ne | (nl << 8);
+            R.spare = cnt;
         }();
         head[tau] = R;
         if (R.flags & REC_VALID) {
             // the whole line (a partial one would cost a read-modify-write)
             Payload P;
 #pragma unroll
-            for (int g = 0; g < 14; ++g) P.c[g] = g < 5 ? pc[g] : 0.0;
+            for (int g = 0; g < 14; ++g) P.c[g] = g < 7 ? pc[g] : 0.0;
             P.h = R;
             coef[tau] = P;
         }
@@ -1768,37 +1821,47 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
     return frags;
 }
 
-// Edge form: one mesh edge's summed slope change D along its projection from
+// Edge form: one mesh edge's summed slope change along its projection from
 // P to Q, deposited on the rows whose centre lies in [min y, max y) (the
 // crease form's rule, so that at a vertex the edges above and below take
-// the row once between them).  Nothing is folded at the image's left edge:
-// the tetrahedra behind an edge lie within the image's columns, and under
-// wrap every crossing lands in the one tile copy whose columns hold it.
+// the row once between them).  Nothing is folded at the image's left edge.
+// Without wrap the tetrahedra behind an edge lie within the image's
+// columns.  With wrap every copy of the tile takes the crossings in its
+// columns, so each one's two entries land once, at its position u modulo
+// the width W (u: pixel-centre units, canonical position in [-1, W - 1)).
+// The running sums start at column 0, and a tetrahedron that reaches past
+// the period's right end (u_T >= W - 2 in the frame that puts its left end
+// in the first period) has its sums there corrected by a line a + b j added
+// to the row (at columns 0 and 1 of the tile's seam cells): with d the
+// slope change of one of its crossings, -d (j - u) for u_T >= W - 1 and
+// -d (u - W + 2)(j + 1) for W - 2 <= u_T < W - 1 (the two agree at
+// u_T = W - 1, so a crossing there may fall either way).  u_T = u + (s + kx)
+// W, s the period offset of the tetrahedron's frame from the edge record's
+// (c[4..6] hold the slope changes summed by s = -1, 0, 1), kx the tile copy.
 // Fragments: a tetrahedron's row holds (samples left of its leaving
 // crossing) - (samples left of its entering crossing); each crossing adds
-// its terms, in image columns, once, in the tile holding the column right
-// of it.  Returns the count as the bits of a signed 32-bit value.
-template <typename Dep>
+// its terms once, in the copy and tile holding the column right of it, in
+// image columns plus (s + kx) W.  Returns the count as the bits of a signed
+// 32-bit value.
+template <typename Dep, typename Seam>
 TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0, int ty0,
-                                  int n, int rows, Dep &&dep, uint32_t &spans, uint32_t &kinks) {
+                                  int n, int rows, Dep &&dep, Seam &&seam, uint32_t &spans, uint32_t &kinks) {
     const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
     const int by0 = range_lo(h.by), by1 = range_hi(h.by);
     int kx0, kx1, ky0, ky1;
     axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
     axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
-    const double Px = cf[0], Py = cf[1], Qx = cf[2], Qy = cf[3], D = cf[4];
-    const int ne = (int)(h.spare & 255u), nl = (int)((h.spare >> 8) & 255u);
-    const bool count = (ne | nl) != 0;
-    // under wrap the edge lies in one period of its frame, m W + [1, W - 1]:
-    // only that copy of the tile meets it (another copy would carry the
-    // deposits past the image's right edge round to its left)
-    if (B.wrap) {
-        const int m = floor_div(range_lo(h.bx), B.W);
-        kx0 = max(kx0, m);
-        kx1 = min(kx1, m);
-    }
+    const double Px = cf[0], Py = cf[1], Qx = cf[2], Qy = cf[3];
+    const double Dm = cf[4], D0 = cf[5], Dp = cf[6];
+    const double D = Dm + D0 + Dp;
+    const uint32_t cnt = h.spare;
+    const int ne[3] = {(int)(cnt & 7u), (int)((cnt >> 3) & 7u), (int)((cnt >> 6) & 7u)};
+    const int nl[3] = {(int)((cnt >> 9) & 7u), (int)((cnt >> 12) & 7u), (int)((cnt >> 15) & 7u)};
+    const bool count = cnt != 0u;
+    const bool seamed = B.wrap && (Dm != 0.0 || Dp != 0.0 || D0 != 0.0);
     const double sl = (Qx - Px) * fast_rcp(Qy - Py);
     const int qa = (int)ceil(fmin(Py, Qy) - 0.5), qb = (int)ceil(fmax(Py, Qy) - 0.5) - 1;
+    const double Wd = (double)B.W;
     int frags = 0;
     for (int ky = ky0; ky <= ky1; ++ky) {
         const int rshift = by0 - ky * B.H - ty0;
@@ -1820,6 +1883,8 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
                 r0 = max(q0, (int)floor(ya - 0.5));
                 r1 = min(q1, (int)ceil(yb - 0.5));
             }
+            // the wrap of each period group in this copy: s + kx
+            const int wm = kx - 1, w0 = kx, wp = kx + 1;
             double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
             const int len = max(r1 - r0 + 1, 0);
             kinks += (uint32_t)len;
@@ -1830,9 +1895,30 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
                 const double v1 = fma(D, (double)k - w, D);
                 dep(row, k + 1, v1);
                 dep(row, k + 2, D - v1);
-                if (count && fw >= -1.0 && fw <= (double)(n - 2)) {
-                    const int jl = tx0 + 1 + (int)floor(w - kSampleEps), je = tx0 + 1 + (int)floor(w + kSampleEps);
-                    frags += nl * jl - ne * je;
+                if (fw >= -1.0 && fw <= (double)(n - 2)) {  // this copy and tile hold the crossing
+                    if (seamed) {
+                        const double u = (double)tx0 + w;  // canonical position
+                        double a = 0.0, b = 0.0;
+                        const double near = u >= Wd - 2.0 ? u - Wd + 2.0 : 0.0;
+                        const int ws[3] = {wm, w0, wp};
+                        const double Ds[3] = {Dm, D0, Dp};
+#pragma unroll
+                        for (int g = 0; g < 3; ++g) {
+                            if (ws[g] == 1) {
+                                a += Ds[g] * u;
+                                b -= Ds[g];
+                            } else if (ws[g] == 0) {
+                                a -= Ds[g] * near;
+                                b -= Ds[g] * near;
+                            }
+                        }
+                        if (a != 0.0 || b != 0.0) seam(row, a, b);
+                    }
+                    if (count) {
+                        const int jl = tx0 + 1 + (int)floor(w - kSampleEps), je = tx0 + 1 + (int)floor(w + kSampleEps);
+                        frags += (nl[0] + nl[1] + nl[2]) * jl - (ne[0] + ne[1] + ne[2]) * je;
+                        frags += B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
+                    }
                 }
             }
         }
@@ -1844,9 +1930,9 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
 // One record in one tile, in whichever form its payload has.
 // (A launch holds records of one kind: pyramids in crease or line form, face
 // form with a depth slab, or splats; FORM selects it at compile time.)
-template <int FORM, typename Dep>
+template <int FORM, typename Dep, typename Seam>
 TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const BinParams &B, int tx0,
-                                      int ty0, int n, int rows, Dep &&dep, uint32_t &spans,
+                                      int ty0, int n, int rows, Dep &&dep, Seam &&seam, uint32_t &spans,
                                       uint32_t &kinks) {
     if constexpr (FORM == kFormFace) {
         return face_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
@@ -1855,7 +1941,7 @@ TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const 
     } else if constexpr (FORM == kFormPersp) {
         return persp_pair(h, cf, B, tx0, ty0, n, rows, 0, 1, dep, spans, kinks);
     } else {
-        if (h.flags & REC_EDGE) return edge_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
+        if (h.flags & REC_EDGE) return edge_pair(h, cf, B, tx0, ty0, n, rows, dep, seam, spans, kinks);
         if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
         return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     }

@@ -118,6 +118,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     }
     std::vector<double> acc((size_t)W * H, 0.0);
     std::vector<double> tile((size_t)tile_rows * tile_cols);
+    std::vector<double> seam((size_t)2 * tile_rows);  // per tile row: the seam line a + b j
     long long frags = 0, spans = 0, pairs = 0, items = 0;
     for (int t = 0; t < ntiles; ++t) {
         const int tx0 = (t % B.ntx) * B.Tw, ty0 = (t / B.ntx) * B.Th;
@@ -127,15 +128,21 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         for (size_t first = 0; first < lst.size(); first += (size_t)chunk) {
             ++items;
             std::fill(tile.begin(), tile.end(), 0.0);
+            std::fill(seam.begin(), seam.end(), 0.0);
             const size_t last = std::min(lst.size(), first + (size_t)chunk);
             for (size_t e = first; e < last; ++e) {
                 const uint32_t id = lst[e];
                 uint32_t sp = 0, kk = 0;
+                auto sl = [&](int row, double a, double b) {
+                    if (row < 0 || row >= rows) throw 2;
+                    seam[(size_t)row] += a;
+                    seam[(size_t)tile_rows + row] += b;
+                };
                 auto rr = [&](auto &&dep) {
-                    return persp ? raster_record<kFormPersp>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
-                         : splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
-                         : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk)
-                                : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sp, kk);
+                    return persp ? raster_record<kFormPersp>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                                : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk);
                 };
                 frags += (int32_t)rr(
                                      [&](int row, int j, double v) {
@@ -144,8 +151,11 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                                      });
                 spans += sp;
             }
-            for (int r = 0; r < rows; ++r)
+            for (int r = 0; r < rows; ++r) {
                 for (int c = 0; c < n; ++c) acc[(size_t)(ty0 + r) * W + tx0 + c] += tile[(size_t)r * B.Tw + c];
+                acc[(size_t)(ty0 + r) * W] += seam[(size_t)r];
+                if (W > 1) acc[(size_t)(ty0 + r) * W + 1] += seam[(size_t)tile_rows + r] - seam[(size_t)r];
+            }
         }
     }
     for (int iy = 0; iy < H; ++iy) {

@@ -539,24 +539,16 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         PX[n] = PX0 + (V.rot[0] * e[n][0] + V.rot[1] * e[n][1] + V.rot[2] * e[n][2]) * V.inv_du;
         PY[n] = PY0 + (V.rot[3] * e[n][0] + V.rot[4] * e[n][1] + V.rot[5] * e[n][2]) * V.inv_dv;
     }
-    // edge form under wrap: each corner's x in its own frame, where the edge
+    // edge form under wrap: corner n's x in its own frame, where the edge
     // records it owns are placed (the offset to this cube's frame is a whole
     // number of periods)
-    double PXE[8];
-#pragma unroll
-    for (int n = 0; n < 8; ++n) PXE[n] = 0.0;
-    if constexpr (FORM == kFormPyramid) {
-        if (V.edges && V.wrap) {
-#pragma unroll
-            for (int n = 0; n < 8; ++n) {
-                int64_t ii = ci + (n & 1), jj = cj + ((n >> 1) & 1), kk = ck + ((n >> 2) & 1);
-                if (ii == L.d[0]) ii = 0;
-                if (jj == L.d[1]) jj = 0;
-                if (kk == L.d[2]) kk = 0;
-                PXE[n] = vertex_px(L, V, ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk));
-            }
-        }
-    }
+    auto corner_px = [&](int n) {
+        int64_t ii = ci + (n & 1), jj = cj + ((n >> 1) & 1), kk = ck + ((n >> 2) & 1);
+        if (ii == L.d[0]) ii = 0;
+        if (jj == L.d[1]) jj = 0;
+        if (kk == L.d[2]) kk = 0;
+        return vertex_px(L, V, ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk));
+    };
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
         // the record is built in registers and stored once, in whole lines
@@ -817,7 +809,10 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                         for (int q = 0; q < 6; ++q) {
                             const EdgeSlot S = kEdgeSlots.s[t][q];
                             const int m = S.ox + 2 * S.oy + 4 * S.oz;
-                            const double per = rint((PX[m] - xsh - PXE[m]) / (double)V.W);
+                            double pxm = 0.0;  // PX[m] by selects (an indexed read would go to scratch)
+#pragma unroll
+                            for (int n = 0; n < 8; ++n) pxm = n == m ? PX[n] : pxm;
+                            const double per = rint((pxm - xsh - corner_px(m)) / (double)V.W);
                             take = take && per >= -1.0 && per <= 1.0;
                             shift |= (uint32_t)((int)per + 1) << (2 * q);
                         }
@@ -1858,7 +1853,7 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
     const int ne[3] = {(int)(cnt & 7u), (int)((cnt >> 3) & 7u), (int)((cnt >> 6) & 7u)};
     const int nl[3] = {(int)((cnt >> 9) & 7u), (int)((cnt >> 12) & 7u), (int)((cnt >> 15) & 7u)};
     const bool count = cnt != 0u;
-    const bool seamed = B.wrap && (Dm != 0.0 || Dp != 0.0 || D0 != 0.0);
+    const int nlt = nl[0] + nl[1] + nl[2], net = ne[0] + ne[1] + ne[2];
     const double sl = (Qx - Px) * fast_rcp(Qy - Py);
     const int qa = (int)ceil(fmin(Py, Qy) - 0.5), qb = (int)ceil(fmax(Py, Qy) - 0.5) - 1;
     const double Wd = (double)B.W;
@@ -1883,8 +1878,12 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
                 r0 = max(q0, (int)floor(ya - 0.5));
                 r1 = min(q1, (int)ceil(yb - 0.5));
             }
-            // the wrap of each period group in this copy: s + kx
+            // the wrap of each period group in this copy: s + kx; a crossing
+            // may need the seam line only in a shifted copy, for a group
+            // with s != 0, or near the period's right end
             const int wm = kx - 1, w0 = kx, wp = kx + 1;
+            const bool seamed = B.wrap && (kx != 0 || Dm != 0.0 || Dp != 0.0 || tx0 + n > B.W - 3);
+            const int fwrap = B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
             double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
             const int len = max(r1 - r0 + 1, 0);
             kinks += (uint32_t)len;
@@ -1916,8 +1915,7 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
                     }
                     if (count) {
                         const int jl = tx0 + 1 + (int)floor(w - kSampleEps), je = tx0 + 1 + (int)floor(w + kSampleEps);
-                        frags += (nl[0] + nl[1] + nl[2]) * jl - (ne[0] + ne[1] + ne[2]) * je;
-                        frags += B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
+                        frags += nlt * jl - net * je + fwrap;
                     }
                 }
             }

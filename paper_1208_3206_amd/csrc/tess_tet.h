@@ -540,15 +540,25 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         PY[n] = PY0 + (V.rot[3] * e[n][0] + V.rot[4] * e[n][1] + V.rot[5] * e[n][2]) * V.inv_dv;
     }
     // edge form under wrap: corner n's x in its own frame, where the edge
-    // records it owns are placed (the offset to this cube's frame is a whole
-    // number of periods)
-    auto corner_px = [&](int n) {
-        int64_t ii = ci + (n & 1), jj = cj + ((n >> 1) & 1), kk = ck + ((n >> 2) & 1);
-        if (ii == L.d[0]) ii = 0;
-        if (jj == L.d[1]) jj = 0;
-        if (kk == L.d[2]) kk = 0;
-        return vertex_px(L, V, ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk));
-    };
+    // records it owns are placed, lies a whole number q_n of periods before
+    // its x in this cube's frame
+    // number of periods q_n, packed as q_n + 2 in 4 bits per corner
+    uint32_t qpack = 0x22222222u;
+    if constexpr (FORM == kFormPyramid) {
+        if (V.edges && V.wrap) {
+            qpack = 0u;
+#pragma unroll
+            for (int n = 0; n < 8; ++n) {
+                int64_t ii = ci + (n & 1), jj = cj + ((n >> 1) & 1), kk = ck + ((n >> 2) & 1);
+                if (ii == L.d[0]) ii = 0;
+                if (jj == L.d[1]) jj = 0;
+                if (kk == L.d[2]) kk = 0;
+                const double pe = vertex_px(L, V, ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk));
+                const double q = fmin(fmax(rint((PX[n] - pe) / (double)V.W), -2.0), 13.0);
+                qpack |= (uint32_t)((int)q + 2) << (4 * n);
+            }
+        }
+    }
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
         // the record is built in registers and stored once, in whole lines
@@ -802,19 +812,16 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                     bool take = V.edges && same_frame;
                     uint32_t shift = 0x555u;  // s + 1 = 1 for all six edges
                     if (take && V.wrap) {
-                        const double xsh = (double)V.W * floor(xmin / (double)V.W);
+                        const int pt = (int)floor(xmin / (double)V.W);  // this frame's period of xmin
                         take = xmax - xmin < (double)V.W - 2.0;
                         shift = 0u;
 #pragma unroll
                         for (int q = 0; q < 6; ++q) {
                             const EdgeSlot S = kEdgeSlots.s[t][q];
                             const int m = S.ox + 2 * S.oy + 4 * S.oz;
-                            double pxm = 0.0;  // PX[m] by selects (an indexed read would go to scratch)
-#pragma unroll
-                            for (int n = 0; n < 8; ++n) pxm = n == m ? PX[n] : pxm;
-                            const double per = rint((pxm - xsh - corner_px(m)) / (double)V.W);
-                            take = take && per >= -1.0 && per <= 1.0;
-                            shift |= (uint32_t)((int)per + 1) << (2 * q);
+                            const int per = (int)((qpack >> (4 * m)) & 15u) - 2 - pt;
+                            take = take && per >= -1 && per <= 1;
+                            shift |= (uint32_t)(per + 1) << (2 * q);
                         }
                     } else if (take) {
                         take = xmin >= 1.0 && xmax <= (double)V.W - 1.0;

@@ -45,8 +45,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "93e82e4fa148c20315d5a651baeac79396ce73e378813aa799d18465773fa8e7",
-    "fetch_kib": 98138577.8, "write_kib": 2377923.2, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "969ca71dfea88ebfa0dd415d3923af649b643f352c35c3ac901efc6eb47f8114",
+    "fetch_kib": 52435275.7, "write_kib": 6137287.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

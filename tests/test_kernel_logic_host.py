@@ -249,3 +249,26 @@ def test_minimum_lattice_and_huge_footprints():
     ref, ost = O.project_region(*xyz, (n, n, n), view)
     assert rel(img, ref) < 1e-8
     assert st["fragments"] == ost["fragments"]
+
+
+@pytest.mark.parametrize("wrap", [1, 0])
+def test_edge_form_equals_per_tetrahedron_form(wrap):
+    # strongly shell-crossed lattice: many tetrahedra reach across the
+    # periodic seam (wrap) or past the image's columns (no wrap); the creases
+    # summed per mesh edge give the per-tetrahedron image to rounding and the
+    # same fragment count, and under wrap nearly every crease-form
+    # tetrahedron goes to its edges (all but those about as wide as the image)
+    n = 24
+    xyz = W.zeldovich(n, 8, 8.0, seed=13)
+    view = W.z_view(192, 160) if wrap else W.rotated_view(W.random_rotations(1, seed=6)[0], 150, 130)
+    a, _, sa = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=8, tile_cols=64, edges=True)
+    b, _, sb = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=8, tile_cols=64, edges=False)
+    assert np.abs(a - b).max() < 1e-9 * np.abs(b).max()
+    assert sa["fragments"] == sb["fragments"] and sa["crease_records"] == sb["crease_records"]
+    if wrap:
+        assert sa["edged"] > 0.99 * sa["crease_records"]
+    else:
+        assert 0 < sa["edged"] < sa["crease_records"]
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert np.abs(a - ref).max() < 1e-8 * np.abs(ref).max()
+    assert sa["fragments"] == ost["fragments"]

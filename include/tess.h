@@ -188,7 +188,8 @@ typedef struct {
     uint64_t fp64_dets;     /* volume determinants computed in FP64               */
     uint64_t degenerate;    /* |V| < det_v0_frac * V0                             */
     uint64_t fragments;     /* (pixel, tetrahedron) pairs with rho*dl > 0         */
-    uint64_t spans;         /* (tetrahedron, pixel row, tile) spans rastered      */
+    uint64_t spans;         /* (tetrahedron, pixel row, tile) spans rastered by   */
+                            /* per-tetrahedron records (edge records add none)    */
     uint64_t bin_pairs;     /* (tile, tetrahedron) pairs                          */
     uint32_t max_bin;       /* longest tile list                                  */
     uint32_t work_items;    /* raster work items                                  */
@@ -199,7 +200,8 @@ typedef struct {
     float raster_ms;        /* raster kernel                                      */
     float finalize_ms;      /* finalize kernel                                    */
     uint64_t kinks;         /* row crossings of creases (break points) rastered,  */
-                            /* the raster's unit of arithmetic                    */
+                            /* the raster's unit of arithmetic; in the edge form  */
+                            /* one per (mesh edge, row, tile)                     */
 } tess_stats;
 
 /*
@@ -214,6 +216,11 @@ typedef struct {
  *           HIP events on `stream`, synchronises it and returns the counters.
  * Pixel values are sums of FP64 terms accumulated with atomics, rounded to
  * FP32 at the end: repeated calls agree to FP64 rounding, not bit for bit.
+ * Plain pyramids (orthographic, no slab, exact method) are drawn in the edge
+ * form when a lattice cell spans at least 6 pixels: the creases of the
+ * tetrahedra around each mesh edge are summed before the raster, which
+ * regroups FP64 sums and changes nothing else.  The environment variable
+ * TESS_PER_TETRAHEDRON=1 (=0) forces the per-tetrahedron (edge) form.
  * The call synchronises the stream once internally to size its workspace
  * (the number of tile-tetrahedron pairs depends on the data).  The library
  * owns and reuses the workspace; concurrent calls on one handle must use

@@ -171,7 +171,7 @@ hipError_t launch_qsum(const LatticeParams &L, const ViewParams &V, double *qsum
 hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream);
 
-// Edge records 6 ncubes + 7 v + tau of every lattice vertex v from the
+// Edge records 6 ncubes + tau nvert + v of every lattice vertex v from the
 // kinks setup wrote (edge form).
 hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         hipStream_t stream);

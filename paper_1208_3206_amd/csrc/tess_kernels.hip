@@ -75,14 +75,14 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
 }
 
 // Edge form: one thread per lattice vertex, its seven edge records after
-// the tetrahedra's (ids 6 ncubes + 7 v + tau).
+// the tetrahedra's (ids 6 ncubes + tau nvert + v).
 __global__ void __launch_bounds__(256) k_edges(LatticeParams L, ViewParams V, RecHead *__restrict__ head,
                                                Payload *__restrict__ coef) {
     const int64_t nv = (int64_t)L.d[0] * L.d[1] * L.d[2];
     const int64_t first = 6 * L.ncubes;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride)
-        setup_vertex_edges(L, V, v, head + first + 7 * v, coef + first + 7 * v);
+        setup_vertex_edges(L, V, v, head + first + v, coef + first + v);
 }
 
 hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,

@@ -866,14 +866,16 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     }
 }
 
-// Edge records of lattice vertex v (edge form): for each of its seven edges
+// Edge records of lattice vertex v (edge form), at head[tau * nvert] and
+// coef[tau * nvert] for its edge kinds tau (the records are stored kind by
+// kind, so that neighbouring vertices write neighbouring records): for each of its seven edges
 // the sum of the slope changes setup wrote for the tetrahedra around it that
 // handed their creases to their edges, the counts of those for which it is
 // an entering or leaving silhouette edge, and its projected endpoints in the
 // frame of the cube with corner 0 at v (the frame setup uses for that cube).
 // An edge with nothing to draw gets flags 0.
 TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams &V, int64_t v,
-                                       RecHead head[7], Payload coef[7]) {
+                                       RecHead *head, Payload *coef) {
     const int64_t i = v % L.d[0];
     const int64_t rest = v / L.d[0];
     const int64_t j = rest % L.d[1];
@@ -969,14 +971,14 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
             R.flags = REC_EDGE | REC_VALID;
             R.spare = cnt;
         }();
-        head[tau] = R;
+        head[tau * nvert] = R;
         if (R.flags & REC_VALID) {
             // the whole line (a partial one would cost a read-modify-write)
             Payload P;
 #pragma unroll
             for (int g = 0; g < 14; ++g) P.c[g] = g < 7 ? pc[g] : 0.0;
             P.h = R;
-            coef[tau] = P;
+            coef[tau * nvert] = P;
         }
     }
 }

@@ -86,7 +86,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     }
     if (V.edges)
         for (int64_t v = 0; v < nvert; ++v)
-            setup_vertex_edges(L, V, v, &head[6 * L.ncubes + 7 * v], &coef[6 * L.ncubes + 7 * v]);
+            setup_vertex_edges(L, V, v, &head[6 * L.ncubes + v], &coef[6 * L.ncubes + v]);
     BinParams B;
     B.Th = tile_rows;
     B.Tw = tile_cols;

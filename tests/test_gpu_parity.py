@@ -360,6 +360,47 @@ def test_edge_form_equals_per_tetrahedron_form(tess, monkeypatch, view_kind):
     assert rel_err(a[py, px].astype(np.float32), ref).max() <= PIX_TOL
 
 
+def _edge_case(name):
+    # (xyz, dims, view, build kwargs) of small cases drawn in the forced edge form
+    if name == "rotated":
+        n = 16
+        return W.zeldovich(n, 5, 4.0, seed=5), (n, n, n), W.rotated_view(W.random_rotations(1, seed=31)[0], 96, 80), {}
+    if name == "non_periodic":
+        d = 9
+        r = np.arange(d) / (d - 1)
+        qz, qy, qx = np.meshgrid(r, r, r, indexing="ij")
+        rng = np.random.default_rng(3)
+        xyz = [(a.ravel() + rng.uniform(-0.03, 0.03, a.size)).astype(np.float32) for a in (qx, qy, qz)]
+        return xyz, (d, d, d), W.rotated_view(W.random_rotations(1, seed=2)[0], 64, 72), {"periodic": False}
+    if name in ("unit", "density2"):
+        n = 16
+        return W.zeldovich(n, 5, 4.0, seed=5), (n, n, n), dict(W.z_view(120, 88), quantity=name), {"total_mass": 2.0}
+    if name == "huge_footprints":
+        n = 2
+        return W.random_lattice(n, 0.45, seed=11), (n, n, n), W.z_view(23, 19), {}
+    if name == "seam":
+        n = 24
+        return W.zeldovich(n, 8, 8.0, seed=13), (n, n, n), W.z_view(192, 160), {}
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name", ["rotated", "non_periodic", "unit", "density2", "huge_footprints", "seam"])
+def test_forced_edge_form_small_cases(tess, monkeypatch, name):
+    # cases below 6 pixels per lattice cell (or with tetrahedra as wide as the
+    # image, and many across the periodic seam) drawn in the edge form: the
+    # oracle's image and, except for q != rho's empty-pixel floor, fragments
+    monkeypatch.setenv("TESS_PER_TETRAHEDRON", "0")
+    xyz, dims, view, kw = _edge_case(name)
+    got, st = gpu_image(tess, xyz, dims, view, **kw)
+    ref, ost = O.project_region(*xyz, dims, view, **kw)
+    if name in ("unit", "density2"):
+        assert_quantity_parity(got, ref, name, what=f"edge form {name}")
+    else:
+        assert_parity(got, ref, what=f"edge form {name}")
+    assert st["tets"] == ost["tets"]
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-6 * ost["fragments"] + 8
+
+
 def batch_case(tess, n=16, growths=(1.0, 4.0), nviews=3, size=64):
     lats, xyzs = [], []
     for D in growths:

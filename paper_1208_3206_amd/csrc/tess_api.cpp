@@ -356,9 +356,9 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     // Plain pyramids take the edge form when a lattice cell spans at least
     // 6 pixels: its cost per lattice vertex (the edge records) then buys a
     // larger saving in the raster, whose work grows with the rows each
-    // tetrahedron covers (measured: 4 pixels per cell, 512 images of 512^2
-    // from 128^3, favour the per-tetrahedron form; 8 pixels per cell favour
-    // the edge form at every size tried).  TESS_PER_TETRAHEDRON=1 forces the
+    // tetrahedron covers (measured: 2 pixels per cell, 512 rotated 512^2
+    // windows on 128^3, favour the per-tetrahedron form; 8 pixels per cell
+    // and more favour the edge form at every size tried).  TESS_PER_TETRAHEDRON=1 forces the
     // per-tetrahedron form and =0 the edge form (the two give the same image
     // up to rounding).
     const double cell_px = std::cbrt(d.box[0] * d.box[1] * d.box[2] / (double)lp.ncubes) *
@@ -435,6 +435,8 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.ext_u = v->extent[0];
     B.ext_v = v->extent[1];
     B.form = view_form(g.vp);
+    B.edges = g.vp.edges;
+    B.seam = g.vp.edges && v->wrap ? 1 : 0;
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
     return TESS_OK;

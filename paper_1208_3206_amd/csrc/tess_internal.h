@@ -55,6 +55,8 @@ struct ViewParams {
 // Record kinds of a launch (one per view): the pyramid (crease and line
 // forms), the face form of a depth slab, centroid splats.
 constexpr int kFormPyramid = 0, kFormFace = 1, kFormSplat = 2, kFormPersp = 3;
+// the raster's instantiation for pyramids whose lists also hold edge records
+constexpr int kFormEdge = 4;
 __host__ __device__ inline int view_form(const ViewParams &V) {
     return V.persp ? kFormPersp : V.splat ? kFormSplat : (V.slab ? kFormFace : kFormPyramid);
 }
@@ -73,6 +75,8 @@ struct BinParams {
     int32_t direct;          // 1: the accumulator holds values (splats, perspective), not second differences
     int32_t form;            // the records' kind (kFormPyramid, kFormFace, kFormSplat, kFormPersp)
     double ext_u, ext_v;     // the view's window (perspective: pixel rays)
+    int32_t edges;           // 1: edge form (the lists hold edge records)
+    int32_t seam;            // 1: edge form under wrap (tiles carry a seam line per row)
 };
 
 // Pair-list entries: the record id, with the pair's work class (0..31) in

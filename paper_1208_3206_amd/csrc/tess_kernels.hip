@@ -49,7 +49,7 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
 }
 
 // One thread per lattice cube; writes the six records 6*cube .. 6*cube+5.
-template <int FORM>
+template <int FORM, bool EDGES>
 __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
                                                RecHead *__restrict__ head,
                                                Payload *__restrict__ coef,
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
     for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
         // records written in place as they are built (holding six 144-byte
         // records in registers would cost the occupancy)
-        setup_cube<FORM>(L, V, cube, head + 6 * cube, coef + 6 * cube, cnt);
+        setup_cube<FORM, EDGES>(L, V, cube, head + 6 * cube, coef + 6 * cube, cnt);
     }
     const unsigned long long n_tets = wave_sum(cnt.n_tets), n_zero = wave_sum(cnt.n_zero),
                              n_inv = wave_sum(cnt.n_inv), n_dets = wave_sum(cnt.n_dets),
@@ -118,19 +118,23 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
     const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
     switch (view_form(V)) {
         case kFormFace:
-            hipLaunchKernelGGL((k_setup<kFormFace>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef, counters);
+            hipLaunchKernelGGL((k_setup<kFormFace, false>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef, counters);
             break;
         case kFormSplat:
-            hipLaunchKernelGGL((k_setup<kFormSplat>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
+            hipLaunchKernelGGL((k_setup<kFormSplat, false>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
                                counters);
             break;
         case kFormPersp:
-            hipLaunchKernelGGL((k_setup<kFormPersp>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
+            hipLaunchKernelGGL((k_setup<kFormPersp, false>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
                                counters);
             break;
         default:
-            hipLaunchKernelGGL((k_setup<kFormPyramid>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef,
-                               counters);
+            if (V.edges)
+                hipLaunchKernelGGL((k_setup<kFormPyramid, true>), dim3(blocks), dim3(256), 0, stream, L, V, head,
+                                   coef, counters);
+            else
+                hipLaunchKernelGGL((k_setup<kFormPyramid, false>), dim3(blocks), dim3(256), 0, stream, L, V, head,
+                                   coef, counters);
     }
     return hipGetLastError();
 }
@@ -453,9 +457,10 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     // fall outside the tile, so that the raster needs no bounds tests
     const int stride = B.Tw + 2 * kPad;
     const int tsize = B.Th * stride;
-    // then per tile row the seam line a + b j of the edge form (a, then b)
+    // then (edge form under wrap) per tile row the seam line a + b j (a, then b)
     double *sSeam = sA + tsize;
-    for (int i = threadIdx.x; i < tsize + 2 * B.Th; i += TPB) sA[i] = 0.0;
+    const int nseam = B.seam ? 2 * B.Th : 0;
+    for (int i = threadIdx.x; i < tsize + nseam; i += TPB) sA[i] = 0.0;
     __syncthreads();
     long long frags = 0;  // edge records add signed terms
     uint32_t spans = 0, kinks = 0;
@@ -500,7 +505,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         // together then hold pairs of about the same work.  `per` is the same
         // for every lane, so the whole wavefront runs every round.
         const uint32_t lane = threadIdx.x & 63u;
-        uint32_t *cnt = reinterpret_cast<uint32_t *>(sA + tsize + 2 * B.Th) + (threadIdx.x >> 6) * kSortWords;
+        uint32_t *cnt = reinterpret_cast<uint32_t *>(sA + tsize + nseam) + (threadIdx.x >> 6) * kSortWords;
         uint32_t *ent = cnt + kNumClasses;
         for (uint32_t b = 0; b < per; b += kSortPer) {
             uint32_t v[kSortPer], rk[kSortPer];
@@ -557,7 +562,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         if (c < n && v != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + tx0 + c], v);
     }
     // the seam lines: a at column 0 and b - a at column 1 of the second differences
-    for (int r = threadIdx.x; r < rows; r += TPB) {
+    for (int r = threadIdx.x; r < (B.seam ? rows : 0); r += TPB) {
         const double a = sSeam[r], b = sSeam[B.Th + r];
         if (a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W], a);
         if (B.W > 1 && b - a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + 1], b - a);
@@ -599,7 +604,7 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_
     if (max_items == 0) return hipSuccess;
     if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
     // the tile's accumulator, and beside it (when it fits) the wavefronts' class sorts
-    const size_t tile_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad + 2);  // tile and seam lines
+    const size_t tile_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad + (B.seam ? 2 : 0));  // tile, seam lines
     const size_t sort_lds = sizeof(uint32_t) * (size_t)(block / 64) * kSortWords;
     const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;
     const size_t lds = tile_lds + (sorted ? sort_lds : 0);
@@ -612,6 +617,9 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_
     else if (B.form == kFormPersp)
         launch_raster_form<kFormPersp>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                        stream, lds);
+    else if (B.edges)
+        launch_raster_form<kFormEdge>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+                                      stream, lds);
     else
         launch_raster_form<kFormPyramid>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc,
                                          counters, stream, lds);

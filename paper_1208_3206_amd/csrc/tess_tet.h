@@ -493,11 +493,12 @@ TESS_HD inline double vertex_px(const LatticeParams &L, const ViewParams &V, int
     return px;
 }
 
-// Setup of the six tetrahedra of lattice cube `cube`: gather and unwrap the
+// Setup of the six tetrahedra of lattice cube `cube` (EDGES: the edge form's
+// code, used when V.edges is set): gather and unwrap the
 // corners, volume determinant with its FP64 fallback, footprint.  head[t] and
 // coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
 // cover no pixel centre).
-template <int FORM>
+template <int FORM, bool EDGES = false>
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
                                Payload coef[6], CubeCounts &cnt) {
     double X0[3], e[8][3];
@@ -511,15 +512,17 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     // only if, besides, no corner was moved by a box length (with wrap they
     // agree modulo the period)
     bool same_frame = V.wrap || !moved;
+    if constexpr (EDGES) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double lo = 0.0, hi = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double lo = 0.0, hi = 0.0;
 #pragma unroll
-        for (int n = 1; n < 8; ++n) {
-            lo = fmin(lo, e[n][a]);
-            hi = fmax(hi, e[n][a]);
+            for (int n = 1; n < 8; ++n) {
+                lo = fmin(lo, e[n][a]);
+                hi = fmax(hi, e[n][a]);
+            }
+            same_frame = same_frame && hi - lo < 0.5 * L.box[a];
         }
-        same_frame = same_frame && hi - lo < 0.5 * L.box[a];
     }
     // x slope beyond which a footprint keeps the line form, from the image's
     // scale: the mass in view, or the measured integral of q
@@ -544,7 +547,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     // its x in this cube's frame
     // number of periods q_n, packed as q_n + 2 in 4 bits per corner
     uint32_t qpack = 0x22222222u;
-    if constexpr (FORM == kFormPyramid) {
+    if constexpr (FORM == kFormPyramid && EDGES) {
         if (V.edges && V.wrap) {
             qpack = 0u;
 #pragma unroll
@@ -796,7 +799,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 #pragma unroll
             for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
             if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, pc)) {
-                if constexpr (FORM == kFormPyramid) {
+                if constexpr (FORM == kFormPyramid && EDGES) {
                     // edge form: a tetrahedron within the image's columns (a
                     // pixel of margin; under wrap, within one period) hands its
                     // creases to the mesh edges, where they are summed over the
@@ -845,7 +848,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         for (int g = 0; g < 14; ++g) P.c[g] = pc[g];
         head[t] = R;
         if (R.flags & REC_VALID) coef[t] = P;  // nothing reads the payload of other records
-        if constexpr (FORM == kFormPyramid) {
+        if constexpr (FORM == kFormPyramid && EDGES) {
             if (V.edges) {
                 // every slot of the cube's tetrahedra is written (zeros for
                 // the tetrahedra that keep their own record)
@@ -1891,7 +1894,7 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
             // may need the seam line only in a shifted copy, for a group
             // with s != 0, or near the period's right end
             const int wm = kx - 1, w0 = kx, wp = kx + 1;
-            const bool seamed = B.wrap && (kx != 0 || Dm != 0.0 || Dp != 0.0 || tx0 + n > B.W - 3);
+            const bool seamed = B.seam && (kx != 0 || Dm != 0.0 || Dp != 0.0 || tx0 + n > B.W - 3);
             const int fwrap = B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
             double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
             const int len = max(r1 - r0 + 1, 0);
@@ -1948,7 +1951,9 @@ TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const 
     } else if constexpr (FORM == kFormPersp) {
         return persp_pair(h, cf, B, tx0, ty0, n, rows, 0, 1, dep, spans, kinks);
     } else {
-        if (h.flags & REC_EDGE) return edge_pair(h, cf, B, tx0, ty0, n, rows, dep, seam, spans, kinks);
+        if constexpr (FORM == kFormEdge) {
+            if (h.flags & REC_EDGE) return edge_pair(h, cf, B, tx0, ty0, n, rows, dep, seam, spans, kinks);
+        }
         if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
         return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     }

@@ -77,6 +77,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         if (persp) setup_cube<kFormPersp>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else if (splat) setup_cube<kFormSplat>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else if (slab) setup_cube<kFormFace>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        else if (V.edges) setup_cube<kFormPyramid, true>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         else setup_cube<kFormPyramid>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
         for (int t = 0; t < 6; ++t) {
@@ -103,6 +104,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     B.ext_v = extent[1];
     const int ntiles = B.ntx * B.nty;
     B.nkey = (splat || slab || persp || V.edges) ? 1 : 32;
+    B.edges = V.edges;
+    B.seam = V.edges && wrap ? 1 : 0;
     // per tile: its records in id order; every pair's work class in range
     std::vector<std::vector<uint32_t>> lists(ntiles);
     for (int64_t id = 0; id < ntet; ++id) {
@@ -142,6 +145,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                     return persp ? raster_record<kFormPersp>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : V.edges ? raster_record<kFormEdge>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                                 : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk);
                 };
                 frags += (int32_t)rr(

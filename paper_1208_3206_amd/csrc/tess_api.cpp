@@ -67,7 +67,8 @@ tess_lattice make_owned_lattice(const tess_build_desc &desc, float *owned, int d
 namespace {
 struct Workspace {
     DevBuf<RecHead> head;
-    DevBuf<Payload> coef;
+    DevBuf<Payload> coef;               // the tetrahedra's payloads
+    DevBuf<EdgePayload> ecoef;          // edge form: the edges' payloads
     DevBuf<double> kinks;               // edge form: 36 slope-change slots per lattice vertex
     DevBuf<uint8_t> sil;                // and their silhouette kinds
     DevBuf<uint32_t> counts;
@@ -436,6 +437,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.ext_v = v->extent[1];
     B.form = view_form(g.vp);
     B.edges = g.vp.edges;
+    B.first_edge = (uint32_t)(6 * g.lp.ncubes);
     B.seam = g.vp.edges && v->wrap ? 1 : 0;
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
@@ -444,7 +446,8 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
 
 tess_status ensure_front(Workspace &ws, const Geometry &g) {
     TESS_HIP(ws.head.ensure((size_t)g.ntet));
-    TESS_HIP(ws.coef.ensure((size_t)g.ntet));
+    TESS_HIP(ws.coef.ensure((size_t)(6 * g.lp.ncubes)));
+    if (g.vp.edges) TESS_HIP(ws.ecoef.ensure((size_t)(g.ntet - 6 * g.lp.ncubes)));
     if (g.vp.edges) {
         const size_t slots = (size_t)36 * (size_t)g.lp.d[0] * (size_t)g.lp.d[1] * (size_t)g.lp.d[2];
         TESS_HIP(ws.kinks.ensure(slots));
@@ -482,7 +485,7 @@ tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipSt
     vp.kinks = ws.kinks.p;
     vp.sil = ws.sil.p;
     TESS_HIP(launch_setup(g.lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
-    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, ws.head.p, ws.coef.p, s));
+    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, ws.head.p, ws.ecoef.p, s));
     return TESS_OK;
 }
 
@@ -506,7 +509,7 @@ tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigne
     TESS_HIP(launch_scatter(ws.head.p, g.ntet, g.B, ws.base.p, ws.pairs.p, cap, s));
     TESS_HIP(launch_zero(ws.acc.p, g.npix, s));
     if (after_bin) TESS_HIP(hipEventRecord(after_bin, s));
-    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.pairs.p, ws.items.p, max_items_for(g, chunk, cap), slot,
+    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.ecoef.p, ws.pairs.p, ws.items.p, max_items_for(g, chunk, cap), slot,
                            g.B, plan.block, ws.acc.p, ws.counters.p, s));
     if (after_raster) TESS_HIP(hipEventRecord(after_raster, s));
     TESS_HIP(launch_finalize(ws.acc.p, g.B, image, s));
@@ -693,7 +696,7 @@ std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *v
     put(views, sizeof(tess_view) * (size_t)n_views);
     put(&images, sizeof(images));
     put(&t, sizeof(t));
-    const void *bufs[] = {ws.head.p, ws.coef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
+    const void *bufs[] = {ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
                           ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p, ws.overflow.p};
     put(bufs, sizeof(bufs));
     const char *per_tet = getenv("TESS_PER_TETRAHEDRON");

@@ -76,6 +76,7 @@ struct BinParams {
     int32_t form;            // the records' kind (kFormPyramid, kFormFace, kFormSplat, kFormPersp)
     double ext_u, ext_v;     // the view's window (perspective: pixel rays)
     int32_t edges;           // 1: edge form (the lists hold edge records)
+    uint32_t first_edge;     // edge form: id of the first edge record (6 cubes)
     int32_t seam;            // 1: edge form under wrap (tiles carry a seam line per row)
 };
 
@@ -124,11 +125,10 @@ struct WorkItem {
 //    coordinates; front or back face) or, for a wall, its half-plane as in
 //    the line form; c[12] the projected value q. The record's f(p) is q
 //    times the chord inside the tetrahedron and the slab;
-//  - edge form (REC_EDGE): one segment of the tetrahedral mesh, endpoints
-//    (c[0], c[1]) and (c[2], c[3]), the sum D over its tetrahedra of their
-//    slope changes across it (c[4]); the head's spare word counts the
-//    tetrahedra for which it is an entering (bits 0-7) and a leaving
-//    (bits 8-15) silhouette edge, for the fragment count;
+//  - edge form (REC_EDGE): one segment of the tetrahedral mesh, in an
+//    EdgePayload (below); the head's spare word counts, by period offset, the
+//    tetrahedra for which it is an entering and a leaving silhouette edge
+//    (3 bits each), for the fragment count;
 //  - splat (REC_SPLAT; the centroid method): centroid (c[0], c[1]), the
 //    kernel's s per pixel along x and y (c[2], c[3]) and its peak amplitude
 //    q |V| 10 / (7 pi h^2) (c[4]); deposited as values, not differences;
@@ -164,6 +164,14 @@ struct alignas(128) Payload {
     double c[14];
     RecHead h;  // copy of the record's head: the raster reads one 128-byte line per record
 };
+// Edge-form payload of an edge record (REC_EDGE): endpoints (c[0], c[1]) and
+// (c[2], c[3]) relative to the box corner, the slope changes summed by period
+// offset s = -1, 0, 1 (c[4..6]); half a line, stored apart from the
+// tetrahedra's payloads (record id - BinParams::first_edge), its head only in
+// the head array.
+struct alignas(64) EdgePayload {
+    double c[8];
+};
 static_assert(sizeof(RecHead) == 16, "record head");
 static_assert(sizeof(Payload) == 128, "one 128-byte line per record");
 
@@ -177,7 +185,7 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
 
 // Edge records 6 ncubes + tau nvert + v of every lattice vertex v from the
 // kinks setup wrote (edge form).
-hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
+hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, EdgePayload *ecoef,
                         hipStream_t stream);
 
 hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
@@ -214,7 +222,7 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
 
 // Raster of the work items into the second-difference image acc[H][W];
 // max_items blocks are launched and those beyond plan->n_items return.
-hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_t *pairs,
+hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePayload *ecoef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
                          const BinParams &B, int block, double *acc, DevCounters *counters,
                          hipStream_t stream);

@@ -77,20 +77,20 @@ __global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
 // Edge form: one thread per lattice vertex, its seven edge records after
 // the tetrahedra's (ids 6 ncubes + tau nvert + v).
 __global__ void __launch_bounds__(256) k_edges(LatticeParams L, ViewParams V, RecHead *__restrict__ head,
-                                               Payload *__restrict__ coef) {
+                                               EdgePayload *__restrict__ ecoef) {
     const int64_t nv = (int64_t)L.d[0] * L.d[1] * L.d[2];
     const int64_t first = 6 * L.ncubes;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride)
-        setup_vertex_edges(L, V, v, head + first + v, coef + first + v);
+        setup_vertex_edges(L, V, v, head + first + v, ecoef + v);
 }
 
-hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
+hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, EdgePayload *ecoef,
                         hipStream_t stream) {
     const int64_t nv = (int64_t)L.d[0] * L.d[1] * L.d[2];
     const int64_t want = (nv + 255) / 256;
     const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
-    hipLaunchKernelGGL(k_edges, dim3(blocks), dim3(256), 0, stream, L, V, head, coef);
+    hipLaunchKernelGGL(k_edges, dim3(blocks), dim3(256), 0, stream, L, V, head, ecoef);
     return hipGetLastError();
 }
 
@@ -442,6 +442,7 @@ constexpr int kSortWords = kNumClasses + 64 * kSortPer;
 template <int TPB, int FORM>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
                                                 const Payload *__restrict__ coef,
+                                                const EdgePayload *__restrict__ ecoef,
                                                 const uint32_t *__restrict__ pairs,
                                                 const WorkItem *__restrict__ items,
                                                 const PlanOut *__restrict__ plan, BinParams B, int sorted,
@@ -466,10 +467,14 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     uint32_t spans = 0, kinks = 0;
     auto one = [&](uint32_t id) {
         if (id >= B.ntet) return;
-        const RecHead h = coef[id].h;
+        // the head: in the payload's line, or (edge form) from the head array
+        // beside the edge's half line
+        const bool is_edge = FORM == kFormEdge && id >= B.first_edge;
+        const RecHead h = FORM == kFormEdge ? head[id] : coef[id].h;
         if (!(h.flags & REC_VALID)) return;
+        const double *cf = is_edge ? ecoef[id - B.first_edge].c : coef[id].c;
         frags += (int32_t)raster_record<FORM>(
-            h, coef[id].c, B, tx0, ty0, n, rows,
+            h, cf, B, tx0, ty0, n, rows,
             [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
             [&](int row, double a, double b) {
                 atomicAdd(&sSeam[row], a);
@@ -578,26 +583,27 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
 }
 
 template <int FORM>
-static void launch_raster_form(const RecHead *head, const Payload *coef, const uint32_t *pairs,
+static void launch_raster_form(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
+                               const uint32_t *pairs,
                                const WorkItem *items, uint64_t max_items, const PlanOut *plan,
                                const BinParams &B, int sorted, int block, double *acc, DevCounters *counters,
                                hipStream_t stream, size_t lds) {
     switch (block) {
         case 256:
             hipLaunchKernelGGL((k_raster<256, FORM>), dim3((unsigned)max_items), dim3(256), lds, stream, head,
-                               coef, pairs, items, plan, B, sorted, acc, counters);
+                               coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
             break;
         case 512:
             hipLaunchKernelGGL((k_raster<512, FORM>), dim3((unsigned)max_items), dim3(512), lds, stream, head,
-                               coef, pairs, items, plan, B, sorted, acc, counters);
+                               coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
             break;
         default:
             hipLaunchKernelGGL((k_raster<1024, FORM>), dim3((unsigned)max_items), dim3(1024), lds, stream, head,
-                               coef, pairs, items, plan, B, sorted, acc, counters);
+                               coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
     }
 }
 
-hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_t *pairs,
+hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePayload *ecoef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
                          const BinParams &B, int block, double *acc, DevCounters *counters,
                          hipStream_t stream) {
@@ -609,19 +615,19 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const uint32_
     const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;
     const size_t lds = tile_lds + (sorted ? sort_lds : 0);
     if (B.form == kFormFace)
-        launch_raster_form<kFormFace>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+        launch_raster_form<kFormFace>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                       stream, lds);
     else if (B.form == kFormSplat)
-        launch_raster_form<kFormSplat>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+        launch_raster_form<kFormSplat>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                        stream, lds);
     else if (B.form == kFormPersp)
-        launch_raster_form<kFormPersp>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+        launch_raster_form<kFormPersp>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                        stream, lds);
     else if (B.edges)
-        launch_raster_form<kFormEdge>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+        launch_raster_form<kFormEdge>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                       stream, lds);
     else
-        launch_raster_form<kFormPyramid>(head, coef, pairs, items, max_items, plan, B, sorted, block, acc,
+        launch_raster_form<kFormPyramid>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
                                          counters, stream, lds);
     return hipGetLastError();
 }

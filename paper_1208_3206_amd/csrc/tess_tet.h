@@ -870,7 +870,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 }
 
 // Edge records of lattice vertex v (edge form), at head[tau * nvert] and
-// coef[tau * nvert] for its edge kinds tau (the records are stored kind by
+// ecoef[tau * nvert] for its edge kinds tau (the records are stored kind by
 // kind, so that neighbouring vertices write neighbouring records): for each of its seven edges
 // the sum of the slope changes setup wrote for the tetrahedra around it that
 // handed their creases to their edges, the counts of those for which it is
@@ -878,7 +878,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 // frame of the cube with corner 0 at v (the frame setup uses for that cube).
 // An edge with nothing to draw gets flags 0.
 TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams &V, int64_t v,
-                                       RecHead *head, Payload *coef) {
+                                       RecHead *head, EdgePayload *ecoef) {
     const int64_t i = v % L.d[0];
     const int64_t rest = v / L.d[0];
     const int64_t j = rest % L.d[1];
@@ -976,12 +976,11 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
         }();
         head[tau * nvert] = R;
         if (R.flags & REC_VALID) {
-            // the whole line (a partial one would cost a read-modify-write)
-            Payload P;
+            // the whole 64 bytes (a partial write would cost a read-modify-write)
+            EdgePayload P;
 #pragma unroll
-            for (int g = 0; g < 14; ++g) P.c[g] = g < 7 ? pc[g] : 0.0;
-            P.h = R;
-            coef[tau * nvert] = P;
+            for (int g = 0; g < 8; ++g) P.c[g] = g < 7 ? pc[g] : 0.0;
+            ecoef[tau * nvert] = P;
         }
     }
 }

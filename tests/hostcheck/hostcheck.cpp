@@ -66,7 +66,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     const int64_t nvert = (int64_t)L.d[0] * L.d[1] * L.d[2];
     const int64_t ntet = 6 * L.ncubes + (V.edges ? 7 * nvert : 0);
     std::vector<RecHead> head(ntet);
-    std::vector<Payload> coef(ntet);
+    std::vector<Payload> coef(6 * L.ncubes);
+    std::vector<EdgePayload> ecoef(V.edges ? 7 * nvert : 0);
     std::vector<double> kinks(V.edges ? 36 * nvert : 0);
     std::vector<uint8_t> sil(V.edges ? 36 * nvert : 0);
     V.kinks = V.edges ? kinks.data() : nullptr;
@@ -87,7 +88,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     }
     if (V.edges)
         for (int64_t v = 0; v < nvert; ++v)
-            setup_vertex_edges(L, V, v, &head[6 * L.ncubes + v], &coef[6 * L.ncubes + v]);
+            setup_vertex_edges(L, V, v, &head[6 * L.ncubes + v], &ecoef[v]);
     BinParams B;
     B.Th = tile_rows;
     B.Tw = tile_cols;
@@ -105,6 +106,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     const int ntiles = B.ntx * B.nty;
     B.nkey = (splat || slab || persp || V.edges) ? 1 : 32;
     B.edges = V.edges;
+    B.first_edge = (uint32_t)(6 * L.ncubes);
     B.seam = V.edges && wrap ? 1 : 0;
     // per tile: its records in id order; every pair's work class in range
     std::vector<std::vector<uint32_t>> lists(ntiles);
@@ -136,17 +138,18 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
             for (size_t e = first; e < last; ++e) {
                 const uint32_t id = lst[e];
                 uint32_t sp = 0, kk = 0;
+                const double *cf = id >= B.first_edge && V.edges ? ecoef[id - B.first_edge].c : coef[id].c;
                 auto sl = [&](int row, double a, double b) {
                     if (row < 0 || row >= rows) throw 2;
                     seam[(size_t)row] += a;
                     seam[(size_t)tile_rows + row] += b;
                 };
                 auto rr = [&](auto &&dep) {
-                    return persp ? raster_record<kFormPersp>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                         : splat ? raster_record<kFormSplat>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                         : slab ? raster_record<kFormFace>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                         : V.edges ? raster_record<kFormEdge>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                                : raster_record<kFormPyramid>(head[id], coef[id].c, B, tx0, ty0, n, rows, dep, sl, sp, kk);
+                    return persp ? raster_record<kFormPersp>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : splat ? raster_record<kFormSplat>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : slab ? raster_record<kFormFace>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : V.edges ? raster_record<kFormEdge>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                                : raster_record<kFormPyramid>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk);
                 };
                 frags += (int32_t)rr(
                                      [&](int row, int j, double v) {

@@ -296,10 +296,18 @@ TESS_HD inline bool crease_payload(const double qx[4], const double qy[4], const
 // crease form: |b| on the silhouette, -|b_k-1 - b_k| on the ridge to V_k; the
 // two halves of a diagonal have the same change (both are the difference of
 // the two faces meeting along it), and the mean of the two is taken.
-TESS_HD inline bool crease_kinks(const Footprint &fp, double D[6], uint32_t &sil) {
+TESS_HD inline bool crease_kinks(const double qx[4], const double qy[4], const Footprint &fp, double D[6],
+                                 uint32_t &sil) {
     int V[4], Lk[4];
     if (!crease_cycle(fp, V, Lk)) return false;
     const int m = fp.ng;
+    if (m == 4) {  // the diagonals must cross, as the crease form requires
+        auto px = [&](int v) { return v == 0 ? qx[0] : v == 1 ? qx[1] : v == 2 ? qx[2] : qx[3]; };
+        auto py = [&](int v) { return v == 0 ? qy[0] : v == 1 ? qy[1] : v == 2 ? qy[2] : qy[3]; };
+        const double den = (px(V[2]) - px(V[0])) * (py(V[3]) - py(V[1])) -
+                           (py(V[2]) - py(V[0])) * (px(V[3]) - px(V[1]));
+        if (den == 0.0) return false;
+    }
     double b[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -798,43 +806,44 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             double bmax = 0.0;
 #pragma unroll
             for (int g = 0; g < 4; ++g) bmax = fmax(bmax, fabs(fp.c[3 * g + 1]));
-            if (fp.nw == 0 && bmax <= crease_bmax && crease_payload(qx, qy, fp, pc)) {
-                if constexpr (FORM == kFormPyramid && EDGES) {
-                    // edge form: a tetrahedron within the image's columns (a
-                    // pixel of margin; under wrap, within one period) hands its
-                    // creases to the mesh edges, where they are summed over the
-                    // tetrahedra around each edge (when same_frame holds)
-                    // Without wrap the tetrahedron must lie within the image's
-                    // columns (a pixel of margin).  With wrap any one narrower
-                    // than the image will do: in the frame that puts its left
-                    // end in the first period, an edge lies s periods from
-                    // where its own vertex places it (s in -1..1, kept in bits
-                    // 2-3 of the silhouette kind as s + 1), and the raster
-                    // corrects the rows at the period's seam from it.
-                    uint32_t sil = 0u;
-                    bool take = V.edges && same_frame;
-                    uint32_t shift = 0x555u;  // s + 1 = 1 for all six edges
-                    if (take && V.wrap) {
-                        const int pt = (int)floor(xmin / (double)V.W);  // this frame's period of xmin
-                        take = xmax - xmin < (double)V.W - 2.0;
-                        shift = 0u;
+            const bool crease = fp.nw == 0 && bmax <= crease_bmax;
+            if constexpr (FORM == kFormPyramid && EDGES) {
+                // edge form: a tetrahedron within the image's columns (a
+                // pixel of margin; under wrap, within one period) hands its
+                // creases to the mesh edges, where they are summed over the
+                // tetrahedra around each edge (when same_frame holds)
+                // Without wrap the tetrahedron must lie within the image's
+                // columns (a pixel of margin).  With wrap any one narrower
+                // than the image will do: in the frame that puts its left
+                // end in the first period, an edge lies s periods from
+                // where its own vertex places it (s in -1..1, kept in bits
+                // 2-3 of the silhouette kind as s + 1), and the raster
+                // corrects the rows at the period's seam from it.
+                uint32_t sil = 0u;
+                bool take = crease && V.edges && same_frame;
+                uint32_t shift = 0x555u;  // s + 1 = 1 for all six edges
+                if (take && V.wrap) {
+                    const int pt = (int)floor(xmin / (double)V.W);  // this frame's period of xmin
+                    take = xmax - xmin < (double)V.W - 2.0;
+                    shift = 0u;
 #pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            const EdgeSlot S = kEdgeSlots.s[t][q];
-                            const int m = S.ox + 2 * S.oy + 4 * S.oz;
-                            const int per = (int)((qpack >> (4 * m)) & 15u) - 2 - pt;
-                            take = take && per >= -1 && per <= 1;
-                            shift |= (uint32_t)(per + 1) << (2 * q);
-                        }
-                    } else if (take) {
-                        take = xmin >= 1.0 && xmax <= (double)V.W - 1.0;
+                    for (int q = 0; q < 6; ++q) {
+                        const EdgeSlot S = kEdgeSlots.s[t][q];
+                        const int m = S.ox + 2 * S.oy + 4 * S.oz;
+                        const int per = (int)((qpack >> (4 * m)) & 15u) - 2 - pt;
+                        take = take && per >= -1 && per <= 1;
+                        shift |= (uint32_t)(per + 1) << (2 * q);
                     }
-                    if (take && crease_kinks(fp, kd, sil)) {
-                        R.flags = REC_EDGED | (uint32_t)fp.ng;
-                        R.spare = sil | (shift << 12);
-                        return;
-                    }
+                } else if (take) {
+                    take = xmin >= 1.0 && xmax <= (double)V.W - 1.0;
                 }
+                if (take && crease_kinks(qx, qy, fp, kd, sil)) {
+                    R.flags = REC_EDGED | (uint32_t)fp.ng;
+                    R.spare = sil | (shift << 12);
+                    return;
+                }
+            }
+            if (crease && crease_payload(qx, qy, fp, pc)) {
                 R.flags |= REC_CREASE;
                 R.spare = crease_profile(pc, iy1 - iy0 + 1);
             } else {

@@ -45,8 +45,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "0eeb59b9fe60353c8a5c9df3a2b5634d7e27c41003d4bccdc0bfdb9971d53d54",
-    "fetch_kib": 51235241.8, "write_kib": 1610053.7, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "cb4b571a3d9145a00fc767cee46b64acbcd4ca802376ed2597125c26762b061f",
+    "fetch_kib": 36918617.1, "write_kib": 1521155.0, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

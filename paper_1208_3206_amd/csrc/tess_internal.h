@@ -164,13 +164,16 @@ struct alignas(128) Payload {
     double c[14];
     RecHead h;  // copy of the record's head: the raster reads one 128-byte line per record
 };
-// Edge-form payload of an edge record (REC_EDGE): endpoints (c[0], c[1]) and
-// (c[2], c[3]) relative to the box corner, the slope changes summed by period
-// offset s = -1, 0, 1 (c[4..6]); half a line, stored apart from the
-// tetrahedra's payloads (record id - BinParams::first_edge), its head only in
-// the head array.
+// Edge-form payload of an edge record (REC_EDGE), all the raster reads of
+// it: endpoints (c[0], c[1]) and (c[2], c[3]) in pixel units of the edge's
+// frame (its box follows from them, edge_box), the slope changes summed by
+// period offset s = -1, 0, 1 (c[4..6]) and the head's spare word (the
+// silhouette counts).  Half a line, stored apart from the tetrahedra's
+// payloads (record id - BinParams::first_edge); the head array holds the box
+// and flags for the binning.
 struct alignas(64) EdgePayload {
-    double c[8];
+    double c[7];
+    uint64_t spare;
 };
 static_assert(sizeof(RecHead) == 16, "record head");
 static_assert(sizeof(Payload) == 128, "one 128-byte line per record");

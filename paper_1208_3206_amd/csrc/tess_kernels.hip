@@ -467,14 +467,24 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     uint32_t spans = 0, kinks = 0;
     auto one = [&](uint32_t id) {
         if (id >= B.ntet) return;
-        // the head: in the payload's line, or (edge form) from the head array
-        // beside the edge's half line
-        const bool is_edge = FORM == kFormEdge && id >= B.first_edge;
-        const RecHead h = FORM == kFormEdge ? head[id] : coef[id].h;
+        if constexpr (FORM == kFormEdge) {
+            // an edge record: its half line is all the raster reads
+            if (id >= B.first_edge) {
+                frags += (int32_t)edge_pair(
+                    ecoef[id - B.first_edge], B, tx0, ty0, n, rows,
+                    [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                    [&](int row, double a, double b) {
+                        atomicAdd(&sSeam[row], a);
+                        atomicAdd(&sSeam[B.Th + row], b);
+                    },
+                    kinks);
+                return;
+            }
+        }
+        const RecHead h = coef[id].h;
         if (!(h.flags & REC_VALID)) return;
-        const double *cf = is_edge ? ecoef[id - B.first_edge].c : coef[id].c;
         frags += (int32_t)raster_record<FORM>(
-            h, cf, B, tx0, ty0, n, rows,
+            h, coef[id].c, B, tx0, ty0, n, rows,
             [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
             [&](int row, double a, double b) {
                 atomicAdd(&sSeam[row], a);
@@ -544,6 +554,14 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         }
     } else {
         const uint32_t idmask = B.nkey > 1 ? kIdMask : 0xffffffffu;
+        if constexpr (FORM == kFormEdge) {
+            // edge pairs: the block takes the list in strides, so that a
+            // wavefront reads 64 neighbouring ids and, the list being in
+            // rough id order, 64 neighbouring 64-byte edge payloads (whole
+            // lines); neighbouring edges are parallel and a few pixels apart,
+            // so their atomics do not stack on the same LDS cells
+            for (uint32_t e = threadIdx.x; e < it.count; e += TPB) one(pairs[it.first + e] & idmask);
+        } else
         for (uint32_t e = e0; e < e1; e += kIdBurst) {
             // the next ids of the slice in one burst: one fetch of their cache
             // line serves kIdBurst pairs (read one at a time, microseconds

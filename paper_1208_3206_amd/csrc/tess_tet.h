@@ -878,6 +878,28 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     }
 }
 
+// Pixel box of an edge from (ax, ay) to (bx, by): the columns that receive
+// its deposits, floor(x - 1/2) + 1 (+ kRightReach), and the rows whose centre
+// lies in [min y, max y), clipped to the image without wrap.  False when it
+// has no row there.  The edge records and the raster both take it from here.
+TESS_HD inline bool edge_box(double ax, double ay, double bx, double by, const BinParams &B, int &ix0, int &ix1,
+                             int &iy0, int &iy1) {
+    const double lim = 1.0e8;
+    const double xlo = fmin(ax, bx), xhi = fmax(ax, bx), ylo = fmin(ay, by), yhi = fmax(ay, by);
+    ix0 = (int)fmax(floor(xlo - 0.5), -lim) + 1;
+    ix1 = (int)fmin(floor(xhi - 0.5), lim);
+    iy0 = (int)fmax(ceil(ylo - 0.5), -lim);
+    iy1 = (int)fmin(ceil(yhi - 0.5), lim) - 1;
+    if (ix1 < ix0) ix1 = ix0;
+    if (!B.wrap) {
+        ix0 = ix0 > 0 ? ix0 : 0;
+        iy0 = iy0 > 0 ? iy0 : 0;
+        ix1 = ix1 < B.W - 1 ? ix1 : B.W - 1;
+        iy1 = iy1 < B.H - 1 ? iy1 : B.H - 1;
+    }
+    return ix0 <= ix1 && iy0 <= iy1;
+}
+
 // Edge records of lattice vertex v (edge form), at head[tau * nvert] and
 // ecoef[tau * nvert] for its edge kinds tau (the records are stored kind by
 // kind, so that neighbouring vertices write neighbouring records): for each of its seven edges
@@ -957,24 +979,16 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
                 if (n == ca) { ax = px; ay = py; }
                 if (n == cb) { bx = px; by = py; }
             }
-            // columns receiving its deposits: floor(x - 1/2) + 1 (+ kRightReach);
-            // rows whose centre lies in [min y, max y)
-            const double lim = 1.0e8;
-            const double xlo = fmin(ax, bx), xhi = fmax(ax, bx), ylo = fmin(ay, by), yhi = fmax(ay, by);
-            int ix0 = (int)fmax(floor(xlo - 0.5), -lim) + 1, ix1 = (int)fmin(floor(xhi - 0.5), lim);
-            int iy0 = (int)fmax(ceil(ylo - 0.5), -lim), iy1 = (int)fmin(ceil(yhi - 0.5), lim) - 1;
-            if (ix1 < ix0) ix1 = ix0;
-            if (!V.wrap) {
-                ix0 = ix0 > 0 ? ix0 : 0;
-                iy0 = iy0 > 0 ? iy0 : 0;
-                ix1 = ix1 < V.W - 1 ? ix1 : V.W - 1;
-                iy1 = iy1 < V.H - 1 ? iy1 : V.H - 1;
-            }
-            if (ix0 > ix1 || iy0 > iy1) return;
-            pc[0] = ax - (double)ix0;
-            pc[1] = ay - (double)iy0;
-            pc[2] = bx - (double)ix0;
-            pc[3] = by - (double)iy0;
+            BinParams Bv;
+            Bv.W = V.W;
+            Bv.H = V.H;
+            Bv.wrap = V.wrap;
+            int ix0, ix1, iy0, iy1;
+            if (!edge_box(ax, ay, bx, by, Bv, ix0, ix1, iy0, iy1)) return;
+            pc[0] = ax;
+            pc[1] = ay;
+            pc[2] = bx;
+            pc[3] = by;
             pc[4] = D[0];
             pc[5] = D[1];
             pc[6] = D[2];
@@ -988,7 +1002,8 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
             // the whole 64 bytes (a partial write would cost a read-modify-write)
             EdgePayload P;
 #pragma unroll
-            for (int g = 0; g < 8; ++g) P.c[g] = g < 7 ? pc[g] : 0.0;
+            for (int g = 0; g < 7; ++g) P.c[g] = pc[g];
+            P.spare = R.spare;
             ecoef[tau * nvert] = P;
         }
     }
@@ -1859,17 +1874,21 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
 // image columns plus (s + kx) W.  Returns the count as the bits of a signed
 // 32-bit value.
 template <typename Dep, typename Seam>
-TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinParams &B, int tx0, int ty0,
-                                  int n, int rows, Dep &&dep, Seam &&seam, uint32_t &spans, uint32_t &kinks) {
-    const int bx0 = range_lo(h.bx), bx1 = range_hi(h.bx) + kRightReach;
-    const int by0 = range_lo(h.by), by1 = range_hi(h.by);
+TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int tx0, int ty0, int n, int rows,
+                                  Dep &&dep, Seam &&seam, uint32_t &kinks) {
+    // the box from the endpoints, as the record's head holds it, and the
+    // endpoints relative to its corner
+    int bx0, bx1, by0, by1;
+    edge_box(E.c[0], E.c[1], E.c[2], E.c[3], B, bx0, bx1, by0, by1);
+    bx1 += kRightReach;
     int kx0, kx1, ky0, ky1;
     axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
     axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
-    const double Px = cf[0], Py = cf[1], Qx = cf[2], Qy = cf[3];
-    const double Dm = cf[4], D0 = cf[5], Dp = cf[6];
+    const double Px = E.c[0] - (double)bx0, Py = E.c[1] - (double)by0;
+    const double Qx = E.c[2] - (double)bx0, Qy = E.c[3] - (double)by0;
+    const double Dm = E.c[4], D0 = E.c[5], Dp = E.c[6];
     const double D = Dm + D0 + Dp;
-    const uint32_t cnt = h.spare;
+    const uint32_t cnt = (uint32_t)E.spare;
     const int ne[3] = {(int)(cnt & 7u), (int)((cnt >> 3) & 7u), (int)((cnt >> 6) & 7u)};
     const int nl[3] = {(int)((cnt >> 9) & 7u), (int)((cnt >> 12) & 7u), (int)((cnt >> 15) & 7u)};
     const bool count = cnt != 0u;
@@ -1941,7 +1960,6 @@ TESS_HD inline uint32_t edge_pair(const RecHead &h, const double *cf, const BinP
             }
         }
     }
-    (void)spans;
     return (uint32_t)frags;
 }
 
@@ -1959,9 +1977,6 @@ TESS_HD inline uint32_t raster_record(const RecHead &h, const double *cf, const 
     } else if constexpr (FORM == kFormPersp) {
         return persp_pair(h, cf, B, tx0, ty0, n, rows, 0, 1, dep, spans, kinks);
     } else {
-        if constexpr (FORM == kFormEdge) {
-            if (h.flags & REC_EDGE) return edge_pair(h, cf, B, tx0, ty0, n, rows, dep, seam, spans, kinks);
-        }
         if (h.flags & REC_CREASE) return crease_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
         return raster_pair(h, cf, B, tx0, ty0, n, rows, dep, spans, kinks);
     }

@@ -138,7 +138,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
             for (size_t e = first; e < last; ++e) {
                 const uint32_t id = lst[e];
                 uint32_t sp = 0, kk = 0;
-                const double *cf = id >= B.first_edge && V.edges ? ecoef[id - B.first_edge].c : coef[id].c;
+                const bool is_edge = V.edges && id >= B.first_edge;
+                const double *cf = is_edge ? nullptr : coef[id].c;
                 auto sl = [&](int row, double a, double b) {
                     if (row < 0 || row >= rows) throw 2;
                     seam[(size_t)row] += a;
@@ -148,6 +149,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                     return persp ? raster_record<kFormPersp>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : splat ? raster_record<kFormSplat>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : slab ? raster_record<kFormFace>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
+                         : is_edge ? edge_pair(ecoef[id - B.first_edge], B, tx0, ty0, n, rows, dep, sl, kk)
                          : V.edges ? raster_record<kFormEdge>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                                 : raster_record<kFormPyramid>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk);
                 };

@@ -381,10 +381,17 @@ def _edge_case(name):
     if name == "seam":
         n = 24
         return W.zeldovich(n, 8, 8.0, seed=13), (n, n, n), W.z_view(192, 160), {}
+    if name in ("one_pixel", "narrow", "short"):
+        # tiny images: no tetrahedron fits a 1- or 2-pixel period (all keep
+        # their records); 16 x 3 has some in the edge form
+        n = 4
+        view = {"one_pixel": W.z_view(1, 1), "narrow": W.z_view(2, 10), "short": W.z_view(16, 3)}[name]
+        return W.random_lattice(n, 0.2, seed=2), (n, n, n), view, {}
     raise ValueError(name)
 
 
-@pytest.mark.parametrize("name", ["rotated", "non_periodic", "unit", "density2", "huge_footprints", "seam"])
+@pytest.mark.parametrize("name", ["rotated", "non_periodic", "unit", "density2", "huge_footprints", "seam",
+                                  "one_pixel", "narrow", "short"])
 def test_forced_edge_form_small_cases(tess, monkeypatch, name):
     # cases below 6 pixels per lattice cell (or with tetrahedra as wide as the
     # image, and many across the periodic seam) drawn in the edge form: the

@@ -89,7 +89,8 @@ tess_status tess_build_desc_default(tess_build_desc *desc);
  * ids is a permutation; this call synchronises `stream` once.
  * Errors: TESS_EINVAL (null pointer, dims < 2, box <= 0, mass <= 0, a
  * non-finite position -- the message names the first bad tracer id --, ids
- * not a permutation), TESS_ENOMEM, TESS_EHIP.
+ * not a permutation), TESS_ECAPACITY (6 x tracers at or above 2^32 - 1, the
+ * 32-bit record ids), TESS_ENOMEM, TESS_EHIP.
  */
 tess_status tess_build(const tess_build_desc *desc, const float *x, const float *y,
                        const float *z, const uint64_t *ids, void *stream, tess_lattice *out);
@@ -220,7 +221,9 @@ typedef struct {
  * form when a lattice cell spans at least 6 pixels: the creases of the
  * tetrahedra around each mesh edge are summed before the raster, which
  * regroups FP64 sums and changes nothing else.  The environment variable
- * TESS_PER_TETRAHEDRON=1 (=0) forces the per-tetrahedron (edge) form.
+ * TESS_PER_TETRAHEDRON=1 (=0) forces the per-tetrahedron (edge) form.  The
+ * edge form is not used when its 13 records per lattice point would not fit
+ * 32-bit ids.
  * The call synchronises the stream once internally to size its workspace
  * (the number of tile-tetrahedron pairs depends on the data).  The library
  * owns and reuses the workspace; concurrent calls on one handle must use

@@ -139,7 +139,7 @@ extern "C" tess_status tess_check_build_desc(const tess_build_desc *d) {
             return fail(TESS_EINVAL, "box[%d] must be positive and finite", a);
     }
     const double n = (double)d->dims[0] * d->dims[1] * d->dims[2];
-    if (n > 2147483647.0 / 6.0 * 4.0)  // tetrahedron ids are 32-bit
+    if (6.0 * n >= 4294967295.0)  // record ids are 32-bit (and 0xffffffff marks an empty entry)
         return fail(TESS_ECAPACITY, "lattice of %.0f tracers exceeds the 32-bit tetrahedron id range", n);
     if (!(d->total_mass > 0) || !std::isfinite(d->total_mass))
         return fail(TESS_EINVAL, "total_mass must be positive and finite");
@@ -408,8 +408,11 @@ struct Geometry {
 
 tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Plan &plan, Geometry &g) {
     make_params(L, v, g.lp, g.vp);
-    // records: the tetrahedra, then (edge form) seven edges per lattice vertex
-    g.ntet = 6 * g.lp.ncubes + (g.vp.edges ? 7 * (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2] : 0);
+    // records: the tetrahedra, then (edge form) seven edges per lattice vertex;
+    // the edge form only while all ids fit in 32 bits
+    const int64_t nvert = (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2];
+    if (g.vp.edges && 6 * g.lp.ncubes + 7 * nvert >= (int64_t)0xffffffff) g.vp.edges = 0;
+    g.ntet = 6 * g.lp.ncubes + (g.vp.edges ? 7 * nvert : 0);
     BinParams &B = g.B;
     B.Th = plan.Th;
     B.Tw = plan.Tw;

@@ -979,7 +979,7 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
                 if (n == ca) { ax = px; ay = py; }
                 if (n == cb) { bx = px; by = py; }
             }
-            BinParams Bv;
+            BinParams Bv{};
             Bv.W = V.W;
             Bv.H = V.H;
             Bv.wrap = V.wrap;

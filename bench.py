@@ -45,8 +45,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "0c86b11465324003ca488d2cb0e69d98783cd22d254209f717655922a6e52ef3",
-    "fetch_kib": 36918512.3, "write_kib": 1521154.8, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "add07a782c4fede285c6679b0d4ea8fc179f75ca220ad589dbe5865c1323dd85",
+    "fetch_kib": 37546624.4, "write_kib": 1433111.4, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -555,12 +555,16 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     } else {
         const uint32_t idmask = B.nkey > 1 ? kIdMask : 0xffffffffu;
         if constexpr (FORM == kFormEdge) {
-            // edge pairs: the block takes the list in strides, so that a
-            // wavefront reads 64 neighbouring ids and, the list being in
-            // rough id order, 64 neighbouring 64-byte edge payloads (whole
-            // lines); neighbouring edges are parallel and a few pixels apart,
-            // so their atomics do not stack on the same LDS cells
-            for (uint32_t e = threadIdx.x; e < it.count; e += TPB) one(pairs[it.first + e] & idmask);
+            // edge pairs: groups of 16 lanes take slices of the list and read
+            // it 16 entries at a time, so that, the list being in rough id
+            // order, a group reads 16 neighbouring 64-byte edge payloads
+            // (whole lines), while the wavefront's four groups draw in four
+            // places of the tile (16 neighbouring edges are parallel and a few
+            // pixels apart: a whole wavefront of them crowds the same LDS banks)
+            const uint32_t ns = TPB / 16, g = threadIdx.x >> 4, q = threadIdx.x & 15u;
+            const uint32_t C = ((it.count + ns - 1) / ns + 15u) & ~15u;
+            const uint32_t g0 = g * C, g1 = min(it.count, g0 + C);
+            for (uint32_t e = g0 + q; e < g1; e += 16) one(pairs[it.first + e] & idmask);
         } else
         for (uint32_t e = e0; e < e1; e += kIdBurst) {
             // the next ids of the slice in one burst: one fetch of their cache

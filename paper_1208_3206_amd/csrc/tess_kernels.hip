@@ -156,9 +156,14 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
     extern __shared__ uint32_t lds_bins[];  // per tile: count, or next slot relative to tile start
     const int ntiles = B.ntx * B.nty;
     const int seg = blockIdx.x;
+    // scatter: each tile's counter starts at this segment's first slot, as an
+    // absolute position when every pair fits 32 bits (no base read per pair),
+    // else relative to the tile's start
+    const bool abs32 = SCATTER && pair_cap <= 0xffffffffull;
     for (int t = threadIdx.x; t < ntiles; t += kBinBlock) {
         if (SCATTER)
-            lds_bins[t] = (uint32_t)(base[(int64_t)t * B.nseg + seg] - base[(int64_t)t * B.nseg]);
+            lds_bins[t] = abs32 ? (uint32_t)base[(int64_t)t * B.nseg + seg]
+                                : (uint32_t)(base[(int64_t)t * B.nseg + seg] - base[(int64_t)t * B.nseg]);
         else
             lds_bins[t] = 0;
     }
@@ -179,7 +184,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
                 const int tile = ty * B.ntx + (tr.sx + sx < B.ntx ? tr.sx + sx : tr.sx + sx - B.ntx);
                 const uint32_t slot = atomicAdd(&lds_bins[tile], 1u);
                 if (SCATTER) {
-                    const uint64_t pos = base[(int64_t)tile * B.nseg] + slot;
+                    const uint64_t pos = abs32 ? (uint64_t)slot : base[(int64_t)tile * B.nseg] + slot;
                     if (pos < pair_cap) pairs[pos] = (uint32_t)id | tag;
                 }
             }

@@ -49,8 +49,11 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
 }
 
 // One thread per lattice cube; writes the six records 6*cube .. 6*cube+5.
+// Two wavefronts per SIMD at least: the edge form's setup would otherwise
+// take 256 VGPRs and run one wavefront per SIMD; with the bound it spills a
+// little to scratch and runs 1.5x faster (measured at stress 256^3).
 template <int FORM, bool EDGES>
-__global__ void __launch_bounds__(256) k_setup(LatticeParams L, ViewParams V,
+__global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
                                                RecHead *__restrict__ head,
                                                Payload *__restrict__ coef,
                                                DevCounters *__restrict__ counters) {

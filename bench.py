@@ -45,8 +45,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "bd97e920b8ee5faf14eb492480a7135a008ac096fd4c3708d11325727dc23a4a",
-    "fetch_kib": 37520044.8, "write_kib": 1433111.3, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "18c89c0c7ab2aa2aa2891572346ce51f33082c8eb1fc43ded4e24dd3a48d968b",
+    "fetch_kib": 37522955.6, "write_kib": 1433111.1, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -76,45 +76,77 @@ def parse():
     return ap.parse_args()
 
 
+def host_cores():
+    """(threads to use, description): the CPUs this process may run on,
+    capped by the cgroup's CPU quota when one is set."""
+    import platform
+    nproc = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = nproc
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, period = fh.read().split()[:2]
+            if q != "max":
+                quota = max(1, int(int(q) // int(period)))
+    except (OSError, ValueError):
+        pass
+    threads = min(allowed, quota) if quota else allowed
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, {"nproc": nproc, "affinity": allowed, "cgroup_quota_cores": quota, "model": model}
+
+
 def cpu_baseline(xyz, w, view, full_fragments: float):
     """The FP64 oracle on a bounded sample of the same workload (test harness code).
 
-    A seeded random subset of the lattice's cubes (all six tetrahedra of each,
-    unwrapped as on the full lattice) projected onto the full image by the
-    oracle's tetrahedron-list entry (one thread).  Its time and fragments are
-    proportional to the tetrahedra, so the subset's tets/s is the oracle's
-    rate on the workload.  The subset is sized for about args.cpu_seconds."""
-    import numpy as np
+    The oracle's region mode (every tetrahedron's setup, then exact per-pixel
+    ray clipping of the crop's pixels, FP64, OpenMP over row bands) on a
+    square crop at the image centre, on all the host cores this process may
+    use.  A small crop calibrates the rate; the timed crop is sized for about
+    args.cpu_seconds.  The full image's time is extrapolated per fragment."""
     import oracle
-    ncubes = w.n ** 3
-    mass = 1.0 / (6.0 * ncubes)
-    rng = np.random.default_rng(12083206)
+    threads, host = host_cores()
+    dims = (w.n,) * 3
 
-    def run(k):
-        cubes = rng.choice(ncubes, size=k, replace=False)
-        verts = np.concatenate([oracle.cube_tets(*xyz, (w.n,) * 3, int(c))[0] for c in cubes])
+    def run(side):
+        x0 = max(0, w.width // 2 - side // 2)
+        y0 = max(0, w.height // 2 - side // 2)
+        crop = (x0, y0, min(side, w.width), min(side, w.height))
         t0 = time.perf_counter()
-        # orthographic splats have their own entry; perspective billboards and
-        # the hybrid go through the tetrahedron list
-        ortho_splats = view.get("method") == "centroids" and view.get("projection") != "perspective"
-        draw = oracle.splat_tets if ortho_splats else oracle.project_tets
-        _, st = draw(verts, mass, view)
-        return time.perf_counter() - t0, st, len(verts)
+        _, st = oracle.project_region(*xyz, dims, view, crop=crop, nthreads=threads)
+        return time.perf_counter() - t0, st, crop
 
-    t_probe, _, _ = run(64)
-    k = int(min(max(64 * args.cpu_seconds / max(t_probe, 1e-3), 64), ncubes))
-    t, st, ntet = run(k)
+    t_probe, st_probe, _ = run(16)
+    rate = st_probe["fragments"] / max(t_probe, 1e-3)
+    want = rate * args.cpu_seconds
+    side = 16
+    while side < min(w.width, w.height) and full_fragments * (2 * side) ** 2 / (w.width * w.height) <= want:
+        side *= 2
+    t, st, crop = run(side)
+    full_s = t * full_fragments / max(st["fragments"], 1)
     return {
-        "value": ntet / t,
+        "value": w.tets / full_s,
         "unit": "tets/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"FP64 oracle (tetrahedron-list entry, 1 thread): the {ntet} tetrahedra of {k} seeded "
-                   f"random cubes of the same lattice onto the full {w.width}x{w.height} image "
-                   f"({st['fragments']:.3e} fragments, {t:.1f} s); the full lattice would take "
-                   f"{w.tets * t / ntet:.0f} s"),
+        "sample": (f"FP64 oracle, region mode, {threads} threads: crop {crop[2]}x{crop[3]} at ({crop[0]}, "
+                   f"{crop[1]}) of the {w.width}x{w.height} image of the same lattice ({st['fragments']:.3e} "
+                   f"fragments, {t:.1f} s including the setup of all {w.tets} tetrahedra); the full image "
+                   f"({full_fragments:.3e} fragments) extrapolated per fragment: {full_s:.0f} s"),
         "fragments_per_s": st["fragments"] / t,
+        "ns_per_fragment_per_core": t * threads / max(st["fragments"], 1) * 1e9,
         "seconds": t,
+        "host": host,
     }
 
 
@@ -462,7 +494,9 @@ def main():
             "x_peak": OPS_PER_FRAGMENT * frags / raster_s / PEAK_VALU_OPS,
         },
     }
-    if not args.no_cpu_baseline:
+    # the oracle's region mode draws the exact projection (orthographic
+    # centroid splats have no region mode)
+    if not args.no_cpu_baseline and not (args.method == "centroids" and not persp):
         result["cpu_baseline"] = cpu_baseline(xyz, w, view, float(frags))
     print(json.dumps(result), flush=True)
 

@@ -171,6 +171,17 @@ typedef enum {
     TESS_QUANTITY_DENSITY2 = 2   /* q = rho^2  */
 } tess_quantity;
 
+/* How plain pyramids (orthographic, no slab, the exact method) are drawn.
+ * The edge form sums the creases of the tetrahedra around each mesh edge
+ * before the raster (the data-storage section's cubes and six-tetrahedron
+ * table form a conforming mesh); it regroups FP64 sums and changes nothing
+ * else.  Other views ignore the field. */
+typedef enum {
+    TESS_FORM_AUTO = 0,            /* edge form when a lattice cell spans >= 6 pixels */
+    TESS_FORM_PER_TETRAHEDRON = 1, /* every tetrahedron drawn on its own              */
+    TESS_FORM_EDGES = 2            /* edge form whenever the record ids fit 32 bits    */
+} tess_form;
+
 /* Raster parameters.  0 in a field means "choose automatically".  The image
  * is cut into tiles of tile_rows x tile_cols pixels (row bands when tile_cols
  * >= width); one raster work group holds a tile's FP64 accumulator, so
@@ -180,6 +191,12 @@ typedef struct {
     int32_t tile_cols;      /* 16 .. 16384                                        */
     int32_t chunk;          /* tile-list entries per raster work item (>= 64)     */
     int32_t block;          /* raster work-group size: 256, 512 or 1024          */
+    int32_t form;           /* tess_form                                          */
+    int32_t reserved;       /* must be 0                                          */
+    uint64_t pair_capacity; /* (record, tile) pairs the tile lists may hold; an
+                               image with more is drawn by the overflow raster
+                               (correct, much slower).  0: learned per lattice
+                               and view shape from earlier calls' counts        */
 } tess_tune;
 
 typedef struct {
@@ -203,6 +220,9 @@ typedef struct {
     uint64_t kinks;         /* row crossings of creases (break points) rastered,  */
                             /* the raster's unit of arithmetic; in the edge form  */
                             /* one per (mesh edge, row, tile)                     */
+    uint32_t overflow;      /* images whose pairs exceeded the pair capacity and  */
+                            /* were drawn by the overflow raster                  */
+    uint32_t reserved;
 } tess_stats;
 
 /*
@@ -212,22 +232,23 @@ typedef struct {
  * (Eq. Eqn:TetProjection with q = rho_loc of Eq. Eqn-rho_loc), every periodic
  * image of T counted when view->wrap is set.  Tetrahedra with V == 0 are
  * skipped.
- *   tune  : host, nullable (automatic choice).
+ *   tune  : host, nullable (automatic choice; see tess_tune and tess_form).
  *   stats : host, nullable; when non-null the call times its kernels with
  *           HIP events on `stream`, synchronises it and returns the counters.
  * Pixel values are sums of FP64 terms accumulated with atomics, rounded to
  * FP32 at the end: repeated calls agree to FP64 rounding, not bit for bit.
- * Plain pyramids (orthographic, no slab, exact method) are drawn in the edge
- * form when a lattice cell spans at least 6 pixels: the creases of the
- * tetrahedra around each mesh edge are summed before the raster, which
- * regroups FP64 sums and changes nothing else.  The environment variable
- * TESS_PER_TETRAHEDRON=1 (=0) forces the per-tetrahedron (edge) form.  The
- * edge form is not used when its 13 records per lattice point would not fit
- * 32-bit ids.
- * The call synchronises the stream once internally to size its workspace
- * (the number of tile-tetrahedron pairs depends on the data).  The library
- * owns and reuses the workspace; concurrent calls on one handle must use
- * different streams and output buffers.
+ * Plain pyramids are drawn in the form tune->form selects (automatic: the
+ * edge form when a lattice cell spans at least 6 pixels); the edge form is
+ * not used when its 13 records per lattice point would not fit 32-bit ids.
+ * With stats == NULL the call only enqueues work on `stream`: it never waits
+ * for the device, so it may be captured into a HIP graph once a first call
+ * with the same lattice, view shape and tune has sized the workspace (the
+ * workspace may grow, i.e. allocate, on a call with a new shape).  The
+ * (record, tile) pair buffer is sized from the counts of earlier calls, read
+ * back without waiting; an image whose pairs do not fit is drawn by the
+ * overflow raster instead, with the same result.  The library owns and
+ * reuses the workspace (one per device and stream); concurrent calls on one
+ * handle must use different streams and output buffers.
  * Errors: TESS_EINVAL (null handle/view/image, a view that fails the checks
  * above, a tune outside its ranges), TESS_ECAPACITY (more than 32768 tiles),
  * TESS_ENOMEM, TESS_EHIP.
@@ -238,10 +259,21 @@ tess_status tess_project(tess_lattice lat, const tess_view *view, const tess_tun
 /*
  * Projects n_snaps lattices (same dims) through n_views views of the same
  * width/height into images laid out [n_snaps][n_views][height][width]
- * (device float32).  The view-independent per-tetrahedron work runs once per
- * snapshot.  tune may be NULL (autotune once per shape, then cached).
- * stats (host, nullable) receives the sums over all images.
- * Errors: as tess_project; views of different sizes -> TESS_EINVAL.
+ * (device float32), each image the tess_project of its (snapshot, view).
+ * The images' pipelines are captured once into one HIP graph, which later
+ * calls with the same arguments replay on `stream` without waiting for the
+ * device (stats == NULL).  Tiling and pair capacity are chosen once per
+ * shape (lattice dims, image size, view kind, counts, tune): tune's fields
+ * where given, otherwise the fastest candidate tiling, timed on the image
+ * with the most pairs, and a capacity just above the largest pair count of
+ * all the images (measured); that first call synchronises.  When the
+ * environment variable TESS_TUNE_CACHE names a file, the choice is kept
+ * there as JSON keyed by shape and device and read back by later processes.
+ * An image whose pairs exceed the capacity is drawn by the overflow raster
+ * inside the graph, and later calls capture with a larger capacity.
+ * stats (host, nullable) receives the sums over all images (synchronises).
+ * Errors: as tess_project; views of different sizes, snapshots of different
+ * dims or periodicity -> TESS_EINVAL.
  */
 tess_status tess_project_batch(const tess_lattice *snaps, int32_t n_snaps,
                                const tess_view *views, int32_t n_views,
@@ -320,6 +352,25 @@ tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *desc, tess_
 tess_status tess_mlp_loss_grad(const float *params, const float *rff_B, const float *q,
                                const float *target, int64_t n, double *loss, float *grad,
                                float *pred, void *stream);
+
+/* One Adam update (Kingma & Ba, with bias correction), the update tess_refine
+ * applies to the FP32 master parameters after each training step, for
+ * checks: with m <- b1 m + (1 - b1) g and v <- b2 v + (1 - b2) g^2,
+ *     params <- params - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ *   params, m, v : host, TESS_MLP_PARAMS FP32 each, updated in place
+ *   grad         : host, TESS_MLP_PARAMS FP32
+ *   step         : t >= 1
+ * Runs the library's device kernel on `stream` and synchronises it.
+ * Errors: TESS_EINVAL (NULL pointer, step < 1, lr, b1, b2 or eps outside
+ * their ranges), TESS_ENOMEM, TESS_EHIP. */
+tess_status tess_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, double lr,
+                          double beta1, double beta2, double eps, void *stream);
+
+/* Copies a handle's tracer positions (tracer-id order; for a refined lattice
+ * the placed fine tracers) into caller device arrays x, y, z of d0 d1 d2
+ * floats each.  Asynchronous on `stream`.
+ * Errors: TESS_EINVAL (NULL argument), TESS_EHIP. */
+tess_status tess_lattice_positions(tess_lattice lat, float *x, float *y, float *z, void *stream);
 
 /* Host-only validation of a view against a lattice description, the same
  * checks tess_project performs; usable without a GPU.  desc may be NULL

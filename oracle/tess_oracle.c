@@ -554,6 +554,22 @@ int orc_project_tets(const orc_problem *P, int64_t ntet, const double *verts,
 
 /* Region mode: the image rectangle [cx0, cx0+cw) x [cy0, cy0+ch) of the
  * full projection.  out: ch*cw doubles, row-major, overwritten. */
+/* The unwrapped indices i in [lo, hi] whose image index (i modulo n under
+ * wrap, i itself otherwise) lies in the window [c0, c0 + cw): they form the
+ * runs [c0 + k n, c0 + cw - 1 + k n] for k = *k0 .. *k1 (k = 0 only without
+ * wrap), each clipped to [lo, hi]. */
+static void window_periods(int wrap, int64_t lo, int64_t hi, int64_t c0, int64_t cw, int64_t n,
+                           int64_t *k0, int64_t *k1) {
+    if (!wrap) { *k0 = 0; *k1 = (lo <= c0 + cw - 1 && hi >= c0) ? 0 : -1; return; }
+    int64_t a = lo - (c0 + cw - 1), b = hi - c0;  /* k n in [a, b] */
+    *k0 = a >= 0 ? (a + n - 1) / n : -((-a) / n);
+    *k1 = b >= 0 ? b / n : -((-b + n - 1) / n);
+}
+
+/* Region mode: the crop [cx0, cx0 + cw) x [cy0, cy0 + ch) of the image.
+ * Every pixel sums the tetrahedra covering it in tetrahedron-id order, so the
+ * result does not depend on the crop, the band height or the thread count;
+ * tetrahedra and pixels outside the crop are only skipped. */
 int orc_project_region(const orc_problem *P, const float *x, const float *y, const float *z,
                        int32_t cx0, int32_t cy0, int32_t cw, int32_t ch, double *out,
                        orc_stats *st, int32_t nthreads) {
@@ -564,13 +580,17 @@ int orc_project_region(const orc_problem *P, const float *x, const float *y, con
     const int64_t ncube = n_cubes(P);
     const int64_t ntet = 6 * ncube;
     const double mass = P->total_mass / (double)ntet;
-    const int BH = 4; /* rows per band */
+    /* rows per band: about 64 bands, at least 4 rows each (the listing below
+     * holds one entry per tetrahedron and band) */
+    const int BH = ch / 64 > 4 ? ch / 64 : 4;
     const int64_t nband = (ch + BH - 1) / BH;
 
-    /* pass 1: candidate row range of every tetrahedron */
+    /* pass 1: candidate pixel range of every tetrahedron, and the counts */
     int32_t *r0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntet);
     int32_t *r1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntet);
-    if (!r0 || !r1) { free(r0); free(r1); return ORC_ENOMEM; }
+    int32_t *q0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntet);
+    int32_t *q1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)ntet);
+    if (!r0 || !r1 || !q0 || !q1) { free(r0); free(r1); free(q0); free(q1); return ORC_ENOMEM; }
     int64_t zero_v = 0, inv = 0, live = 0;
 #pragma omp parallel for schedule(static) num_threads(nthreads) reduction(+ : zero_v, inv, live)
     for (int64_t c = 0; c < ncube; ++c) {
@@ -583,33 +603,46 @@ int orc_project_region(const orc_problem *P, const float *x, const float *y, con
             orc_tet tt;
             double V;
             int64_t id = 6 * c + t;
+            r0[id] = 1; r1[id] = 0;
             if (!tet_setup(P, v, mass, &tt, &V)) {
                 zero_v++;
-                r0[id] = 1; r1[id] = 0;
                 continue;
             }
             live++;
             if (V > 0) inv++;
+            int64_t k0, k1;
+            window_periods(P->wrap, tt.ix0, tt.ix1, cx0, cw, P->width, &k0, &k1);
+            if (k0 > k1) continue;  /* no column in the crop */
             r0[id] = (int32_t)tt.iy0;
             r1[id] = (int32_t)tt.iy1;
+            q0[id] = (int32_t)tt.ix0;
+            q1[id] = (int32_t)tt.ix1;
         }
     }
 
     /* band lists in tet-id order (each tet at most once per band) */
     int64_t *cnt = (int64_t *)calloc((size_t)nband + 1, sizeof(int64_t));
     int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)nband);
-    if (!cnt || !stamp) { free(r0); free(r1); free(cnt); free(stamp); return ORC_ENOMEM; }
+    if (!cnt || !stamp) {
+        free(r0); free(r1); free(q0); free(q1); free(cnt); free(stamp);
+        return ORC_ENOMEM;
+    }
     for (int64_t b = 0; b < nband; ++b) stamp[b] = -1;
 #define FOR_TET_BANDS(BODY)                                                   \
     for (int64_t id = 0; id < ntet; ++id) {                                   \
         if (r0[id] > r1[id]) continue;                                        \
-        for (int64_t iy = r0[id]; iy <= r1[id]; ++iy) {                       \
-            int64_t ry = map_row(P, iy);                                      \
-            if (ry < cy0 || ry >= cy0 + ch) continue;                         \
-            int64_t b = (ry - cy0) / BH;                                      \
-            if (stamp[b] == id) continue;                                     \
-            stamp[b] = id;                                                    \
-            BODY                                                              \
+        int64_t k0, k1;                                                       \
+        window_periods(P->wrap, r0[id], r1[id], cy0, ch, P->height, &k0, &k1); \
+        for (int64_t k = k0; k <= k1; ++k) {                                  \
+            int64_t lo = cy0 + k * P->height, hi = lo + ch - 1;               \
+            if (lo < r0[id]) lo = r0[id];                                     \
+            if (hi > r1[id]) hi = r1[id];                                     \
+            for (int64_t iy = lo; iy <= hi; ++iy) {                           \
+                int64_t b = (iy - k * P->height - cy0) / BH;                  \
+                if (stamp[b] == id) continue;                                 \
+                stamp[b] = id;                                                \
+                BODY                                                          \
+            }                                                                 \
         }                                                                     \
     }
     FOR_TET_BANDS(cnt[b + 1]++;)
@@ -618,7 +651,7 @@ int orc_project_region(const orc_problem *P, const float *x, const float *y, con
     int64_t *lst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(npair > 0 ? npair : 1));
     int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)nband);
     if (!lst || !fill) {
-        free(r0); free(r1); free(cnt); free(stamp); free(lst); free(fill);
+        free(r0); free(r1); free(q0); free(q1); free(cnt); free(stamp); free(lst); free(fill);
         return ORC_ENOMEM;
     }
     for (int64_t b = 0; b < nband; ++b) { fill[b] = cnt[b]; stamp[b] = -1; }
@@ -626,8 +659,10 @@ int orc_project_region(const orc_problem *P, const float *x, const float *y, con
 #undef FOR_TET_BANDS
     free(fill);
     free(stamp);
+    free(q0);
+    free(q1);
 
-    /* pass 2: every band, tetrahedra in id order */
+    /* pass 2: every band, tetrahedra in id order, the crop's pixels only */
     double *comp = (double *)calloc((size_t)cw * ch, sizeof(double));
     if (!comp) { free(r0); free(r1); free(cnt); free(lst); return ORC_ENOMEM; }
     memset(out, 0, sizeof(double) * (size_t)cw * ch);
@@ -649,18 +684,29 @@ int orc_project_region(const orc_problem *P, const float *x, const float *y, con
             orc_tet tt;
             double V;
             if (!tet_setup(P, v, mass, &tt, &V)) continue;
-            for (int64_t iy = tt.iy0; iy <= tt.iy1; ++iy) {
-                int64_t ry = map_row(P, iy);
-                if (ry < row_lo || ry >= row_hi) continue;
-                double pv = pixel_v(P, iy);
-                for (int64_t ix = tt.ix0; ix <= tt.ix1; ++ix) {
-                    int64_t rx = map_col(P, ix);
-                    if (rx < cx0 || rx >= cx0 + cw) continue;
-                    double dl = clip_dl(&tt, pixel_u(P, ix), pv);
-                    if (dl > 0) {
-                        frags++;
-                        int64_t o = (ry - cy0) * cw + (rx - cx0);
-                        neu_add(&out[o], &comp[o], tt.q * dl);
+            int64_t ky0, ky1, kx0, kx1;
+            window_periods(P->wrap, tt.iy0, tt.iy1, row_lo, row_hi - row_lo, P->height, &ky0, &ky1);
+            window_periods(P->wrap, tt.ix0, tt.ix1, cx0, cw, P->width, &kx0, &kx1);
+            for (int64_t ky = ky0; ky <= ky1; ++ky) {
+                int64_t ylo = row_lo + ky * P->height, yhi = row_hi - 1 + ky * P->height;
+                if (ylo < tt.iy0) ylo = tt.iy0;
+                if (yhi > tt.iy1) yhi = tt.iy1;
+                for (int64_t iy = ylo; iy <= yhi; ++iy) {
+                    int64_t ry = iy - ky * P->height;
+                    double pv = pixel_v(P, iy);
+                    for (int64_t kx = kx0; kx <= kx1; ++kx) {
+                        int64_t xlo = cx0 + kx * P->width, xhi = cx0 + cw - 1 + kx * P->width;
+                        if (xlo < tt.ix0) xlo = tt.ix0;
+                        if (xhi > tt.ix1) xhi = tt.ix1;
+                        for (int64_t ix = xlo; ix <= xhi; ++ix) {
+                            int64_t rx = ix - kx * P->width;
+                            double dl = clip_dl(&tt, pixel_u(P, ix), pv);
+                            if (dl > 0) {
+                                frags++;
+                                int64_t o = (ry - cy0) * cw + (rx - cx0);
+                                neu_add(&out[o], &comp[o], tt.q * dl);
+                            }
+                        }
                     }
                 }
             }

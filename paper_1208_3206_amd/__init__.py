@@ -53,7 +53,13 @@ QUANTITIES = {"density": 0, "unit": 1, "density2": 2}
 
 class TessTune(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pair_capacity", ctypes.c_uint64)]
+
+
+# tess_form by name (make_tune(form=...))
+FORMS = {"auto": 0, "per_tetrahedron": 1, "edges": 2}
 
 
 class TessStats(ctypes.Structure):
@@ -67,7 +73,8 @@ class TessStats(ctypes.Structure):
                 ("block", ctypes.c_int32), ("ms", ctypes.c_float),
                 ("setup_ms", ctypes.c_float), ("bin_ms", ctypes.c_float),
                 ("raster_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
-                ("kinks", ctypes.c_uint64)]
+                ("kinks", ctypes.c_uint64), ("overflow", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
     def as_dict(self) -> Dict:
         return {k: (float(getattr(self, k)) if k.endswith("ms") else int(getattr(self, k)))
@@ -125,6 +132,9 @@ def _load():
     L.tess_refine_desc_default.argtypes = [P(TessRefineDesc)]
     L.tess_refine.argtypes = [vp, P(TessRefineDesc), P(vp), P(TessRefineReport), vp]
     L.tess_mlp_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int64, P(ctypes.c_double), vp, vp, vp]
+    L.tess_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, vp]
+    L.tess_lattice_positions.argtypes = [vp, vp, vp, vp, vp]
     L.tess_last_error.argtypes = []
     L.tess_last_error.restype = ctypes.c_char_p
     L.tess_version.argtypes = []
@@ -133,7 +143,7 @@ def _load():
     L.tess_struct_size.restype = ctypes.c_uint64
     for f in (L.tess_build_desc_default, L.tess_build, L.tess_project, L.tess_project_batch,
               L.tess_check_view, L.tess_check_build_desc, L.tess_refine_desc_default,
-              L.tess_refine, L.tess_mlp_loss_grad):
+              L.tess_refine, L.tess_mlp_loss_grad, L.tess_mlp_adam, L.tess_lattice_positions):
         f.restype = ctypes.c_int
     return L
 
@@ -144,7 +154,7 @@ _lib = _load()
 EXPORTS = ("tess_build_desc_default", "tess_build", "tess_free", "tess_project",
            "tess_project_batch", "tess_check_view", "tess_check_build_desc",
            "tess_last_error", "tess_version", "tess_struct_size", "tess_refine_desc_default", "tess_refine",
-           "tess_mlp_loss_grad")
+           "tess_mlp_loss_grad", "tess_mlp_adam", "tess_lattice_positions")
 
 
 def lib():
@@ -207,10 +217,13 @@ def make_view(view: Dict) -> TessView:
     return v
 
 
-def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int = 0) -> TessTune:
-    """Raster parameters; 0 means automatic."""
+def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int = 0,
+              form: str = "auto", pair_capacity: int = 0) -> TessTune:
+    """Raster parameters; 0 (and form "auto") means automatic."""
     t = TessTune()
     t.tile_rows, t.tile_cols, t.chunk, t.block = int(tile_rows), int(tile_cols), int(chunk), int(block)
+    t.form = FORMS[form]
+    t.pair_capacity = int(pair_capacity)
     return t
 
 
@@ -260,6 +273,15 @@ class Lattice:
         _check(rc, "tess_build")
         self.handle = h
         self.dims = tuple(int(d) for d in dims)
+
+    def positions(self, stream=None):
+        """Copies of the handle's positions (x, y, z CUDA float32 tensors, tracer-id order)."""
+        import torch
+        n = int(self.dims[0]) * int(self.dims[1]) * int(self.dims[2])
+        out = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+        _check(_lib.tess_lattice_positions(self.handle, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                                           _stream_handle(stream)), "tess_lattice_positions")
+        return out
 
     def free(self):
         if getattr(self, "handle", None):
@@ -374,3 +396,17 @@ def mlp_loss_grad(params, rff_B, q, target, want_pred: bool = False, stream=None
                                    pred.data_ptr() if pred is not None else None,
                                    _stream_handle(stream)), "tess_mlp_loss_grad")
     return (loss.value, grad, pred) if want_pred else (loss.value, grad)
+
+
+def mlp_adam(params, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, stream=None):
+    """One Adam update by the library's kernel; returns new (params, m, v) as FP32 arrays."""
+    import numpy as np
+    arrs = [np.array(a, dtype=np.float32).reshape(-1) for a in (params, m, v, grad)]
+    if any(a.size != MLP_PARAMS for a in arrs):
+        raise ValueError("params, m, v and grad need MLP_PARAMS entries each")
+    p, mm, vv, g = arrs
+    _check(_lib.tess_mlp_adam(p.ctypes.data, mm.ctypes.data, vv.ctypes.data, g.ctypes.data, int(step),
+                              float(lr), float(beta1), float(beta2), float(eps), _stream_handle(stream)),
+           "tess_mlp_adam")
+    return p, mm, vv

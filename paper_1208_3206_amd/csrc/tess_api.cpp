@@ -86,6 +86,16 @@ struct Workspace {
     DevCounters *host_counters = nullptr;
     unsigned int *host_overflow = nullptr;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // pair counts of earlier calls, read back without waiting: the last
+    // call's PlanOut entries are copied to fb_plan (pinned) behind fb_event;
+    // the next call takes them once the event has completed
+    PlanOut *fb_plan = nullptr;
+    size_t fb_cap = 0;
+    int fb_n = 0;
+    bool fb_pending = false;
+    std::string fb_key;
+    hipEvent_t fb_event = nullptr;
+    std::map<std::string, unsigned long long> learned;  // largest pair count seen per shape key
     // batch graph (captured on `capture`, replayed on the caller's stream)
     hipStream_t capture = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -110,6 +120,9 @@ tess_status get_workspace(int device, hipStream_t s, Workspace **out) {
     TESS_HIP(hipHostMalloc((void **)&w->host_counters, sizeof(DevCounters), hipHostMallocDefault));
     TESS_HIP(hipHostMalloc((void **)&w->host_overflow, sizeof(unsigned int), hipHostMallocDefault));
     for (int i = 0; i < 6; ++i) TESS_HIP(hipEventCreate(&w->ev[i]));
+    TESS_HIP(hipEventCreateWithFlags(&w->fb_event, hipEventDisableTiming));
+    TESS_HIP(hipHostMalloc((void **)&w->fb_plan, sizeof(PlanOut), hipHostMallocDefault));
+    w->fb_cap = 1;
     TESS_HIP(hipStreamCreateWithFlags(&w->capture, hipStreamNonBlocking));
     g_ws[key] = w;
     *out = w;
@@ -294,6 +307,16 @@ extern "C" tess_status tess_build(const tess_build_desc *desc, const float *x, c
     return ok();
 }
 
+extern "C" tess_status tess_lattice_positions(tess_lattice L, float *x, float *y, float *z, void *stream) {
+    if (!L || !x || !y || !z) return fail(TESS_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = sizeof(float) * (size_t)L->n;
+    TESS_HIP(hipMemcpyAsync(x, L->x, bytes, hipMemcpyDeviceToDevice, s));
+    TESS_HIP(hipMemcpyAsync(y, L->y, bytes, hipMemcpyDeviceToDevice, s));
+    TESS_HIP(hipMemcpyAsync(z, L->z, bytes, hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
 extern "C" void tess_free(tess_lattice L) {
     if (!L) return;
     if (L->owned) (void)hipFree(L->owned);
@@ -302,7 +325,7 @@ extern "C" void tess_free(tess_lattice L) {
 
 // ------------------------------------------------------------ projection
 namespace {
-void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp, ViewParams &vp) {
+void make_params(const tess_lattice_s *L, const tess_view *v, int form, LatticeParams &lp, ViewParams &vp) {
     const tess_build_desc &d = L->desc;
     lp.x = L->x;
     lp.y = L->y;
@@ -359,13 +382,11 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
     // larger saving in the raster, whose work grows with the rows each
     // tetrahedron covers (measured: 2 pixels per cell, 512 rotated 512^2
     // windows on 128^3, favour the per-tetrahedron form; 8 pixels per cell
-    // and more favour the edge form at every size tried).  TESS_PER_TETRAHEDRON=1 forces the
-    // per-tetrahedron form and =0 the edge form (the two give the same image
-    // up to rounding).
+    // and more favour the edge form at every size tried).  tess_tune.form
+    // forces either (the two give the same image up to rounding).
     const double cell_px = std::cbrt(d.box[0] * d.box[1] * d.box[2] / (double)lp.ncubes) *
                            std::sqrt(vp.inv_du * vp.inv_dv);
-    const char *per_tet = getenv("TESS_PER_TETRAHEDRON");
-    const bool force_tet = per_tet && per_tet[0] == '1', force_edges = per_tet && per_tet[0] == '0';
+    const bool force_tet = form == TESS_FORM_PER_TETRAHEDRON, force_edges = form == TESS_FORM_EDGES;
     vp.edges = (view_form(vp) == kFormPyramid && !force_tet && (force_edges || cell_px >= 6.0)) ? 1 : 0;
     vp.kinks = nullptr;
     vp.sil = nullptr;
@@ -373,6 +394,8 @@ void make_params(const tess_lattice_s *L, const tess_view *v, LatticeParams &lp,
 
 struct Plan {
     int Th, Tw, chunk, block;  // chunk 0: from the pair count
+    int form;                  // tess_form
+    unsigned long long cap;    // pair capacity; 0: learned
 };
 
 // Default tiling: tiles of up to 512 columns with as many rows as the
@@ -389,6 +412,8 @@ Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     p.Tw = Tw;
     p.chunk = (tune && tune->chunk) ? tune->chunk : 0;
     p.block = (tune && tune->block) ? tune->block : 1024;
+    p.form = tune ? tune->form : TESS_FORM_AUTO;
+    p.cap = tune ? (unsigned long long)tune->pair_capacity : 0ull;
     return p;
 }
 
@@ -407,7 +432,7 @@ struct Geometry {
 };
 
 tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Plan &plan, Geometry &g) {
-    make_params(L, v, g.lp, g.vp);
+    make_params(L, v, plan.form, g.lp, g.vp);
     // records: the tetrahedra, then (edge form) seven edges per lattice vertex;
     // the edge form only while all ids fit in 32 bits
     const int64_t nvert = (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2];
@@ -447,36 +472,50 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     return TESS_OK;
 }
 
-tess_status ensure_front(Workspace &ws, const Geometry &g) {
-    TESS_HIP(ws.head.ensure((size_t)g.ntet));
-    TESS_HIP(ws.coef.ensure((size_t)(6 * g.lp.ncubes)));
-    if (g.vp.edges) TESS_HIP(ws.ecoef.ensure((size_t)(g.ntet - 6 * g.lp.ncubes)));
-    if (g.vp.edges) {
-        const size_t slots = (size_t)36 * (size_t)g.lp.d[0] * (size_t)g.lp.d[1] * (size_t)g.lp.d[2];
-        TESS_HIP(ws.kinks.ensure(slots));
-        TESS_HIP(ws.sil.ensure(slots));
+// Largest buffer sizes over the images of a call.
+struct Sizes {
+    int64_t records = 0, tets = 0, edges = 0, slots = 0, nmat = 0, ntiles = 0, npix = 0;
+    void add(const Geometry &g) {
+        records = std::max(records, g.ntet);
+        tets = std::max(tets, 6 * g.lp.ncubes);
+        if (g.vp.edges) {
+            edges = std::max(edges, g.ntet - 6 * g.lp.ncubes);
+            slots = std::max(slots, (int64_t)36 * g.lp.d[0] * g.lp.d[1] * g.lp.d[2]);
+        }
+        nmat = std::max(nmat, g.nmat);
+        ntiles = std::max(ntiles, g.ntiles);
+        npix = std::max(npix, g.npix);
     }
-    TESS_HIP(ws.counts.ensure((size_t)g.nmat));
-    TESS_HIP(ws.base.ensure((size_t)g.nmat));
-    TESS_HIP(ws.scan.ensure(scan_scratch_elems(g.nmat)));
-    TESS_HIP(ws.tile_items.ensure((size_t)g.ntiles + 1));
-    TESS_HIP(ws.acc.ensure((size_t)g.npix));
+};
+
+tess_status ensure_front(Workspace &ws, const Sizes &z) {
+    TESS_HIP(ws.head.ensure((size_t)z.records));
+    TESS_HIP(ws.coef.ensure((size_t)z.tets));
+    if (z.edges) {
+        TESS_HIP(ws.ecoef.ensure((size_t)z.edges));
+        TESS_HIP(ws.kinks.ensure((size_t)z.slots));
+        TESS_HIP(ws.sil.ensure((size_t)z.slots));
+    }
+    TESS_HIP(ws.counts.ensure((size_t)z.nmat));
+    TESS_HIP(ws.base.ensure((size_t)z.nmat));
+    TESS_HIP(ws.scan.ensure(scan_scratch_elems(z.nmat)));
+    TESS_HIP(ws.tile_items.ensure((size_t)z.ntiles + 1));
+    TESS_HIP(ws.acc.ensure((size_t)z.npix));
     TESS_HIP(ws.counters.ensure(1));
     TESS_HIP(ws.overflow.ensure(1));
     return TESS_OK;
 }
 
-unsigned long long max_items_for(const Geometry &g, int chunk, unsigned long long cap) {
-    return cap / (unsigned long long)chunk + (unsigned long long)g.ntiles;
+unsigned long long max_items_for(int64_t ntiles, int chunk, unsigned long long cap) {
+    return cap / (unsigned long long)chunk + (unsigned long long)ntiles;
 }
 
-tess_status ensure_back(Workspace &ws, const Geometry &g, int chunk, unsigned long long cap) {
-    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(max_items_for(g, chunk, cap), 1)));
+tess_status ensure_back(Workspace &ws, int64_t ntiles, int chunk, unsigned long long cap) {
+    TESS_HIP(ws.items.ensure((size_t)std::max<unsigned long long>(max_items_for(ntiles, chunk, cap), 1)));
     TESS_HIP(ws.pairs.ensure((size_t)std::max<unsigned long long>(cap, 1)));
     return TESS_OK;
 }
 
-// Setup, count, scan and totals of one image (no host synchronisation).
 // Setup of one image; for q = 1 first the integral of q into slot->qsum.
 tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipStream_t s) {
     ViewParams vp = g.vp;
@@ -492,6 +531,8 @@ tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipSt
     return TESS_OK;
 }
 
+// Setup, count, scan and totals of one image (no host synchronisation);
+// the totals flag *overflow when the pairs exceed cap.
 tess_status enqueue_front(const Geometry &g, Workspace &ws, PlanOut *slot, unsigned long long cap,
                           unsigned int *overflow, hipStream_t s) {
     tess_status st = enqueue_setup(g, ws, slot, s);
@@ -503,7 +544,8 @@ tess_status enqueue_front(const Geometry &g, Workspace &ws, PlanOut *slot, unsig
 }
 
 // Work items, scatter, raster and finalize of one image into `image`, for at
-// most `cap` pairs (the buffers hold that many).
+// most `cap` pairs (the buffers hold that many); an image with more pairs
+// gets no work items and is drawn by the overflow raster.
 tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigned long long cap,
                          Workspace &ws, PlanOut *slot, float *image, hipStream_t s, hipEvent_t after_bin,
                          hipEvent_t after_raster) {
@@ -512,8 +554,9 @@ tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigne
     TESS_HIP(launch_scatter(ws.head.p, g.ntet, g.B, ws.base.p, ws.pairs.p, cap, s));
     TESS_HIP(launch_zero(ws.acc.p, g.npix, s));
     if (after_bin) TESS_HIP(hipEventRecord(after_bin, s));
-    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.ecoef.p, ws.pairs.p, ws.items.p, max_items_for(g, chunk, cap), slot,
-                           g.B, plan.block, ws.acc.p, ws.counters.p, s));
+    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.ecoef.p, ws.pairs.p, ws.items.p,
+                           max_items_for(g.ntiles, chunk, cap), slot, g.B, plan.block, ws.acc.p, ws.counters.p, s));
+    TESS_HIP(launch_raster_direct(ws.head.p, ws.coef.p, ws.ecoef.p, slot, cap, g.B, ws.acc.p, ws.counters.p, s));
     if (after_raster) TESS_HIP(hipEventRecord(after_raster, s));
     TESS_HIP(launch_finalize(ws.acc.p, g.B, image, s));
     return TESS_OK;
@@ -534,15 +577,85 @@ void fill_stats(tess_stats *stats, const DevCounters &c, const Plan &plan, int c
     stats->block = plan.block;
 }
 
-// One image, synchronising once to size the pair buffer from its own count.
+// ------------------------------------------------------ pair capacities
+// The (record, tile) pair count is known only on the device.  Calls size the
+// pair buffer from the counts of earlier calls with the same shape, which
+// come back through pinned memory behind an event that is polled, never
+// waited for; until one is known, from a first guess.  An image that does
+// not fit is still drawn (the overflow raster), and its count raises the
+// capacity of later calls.
+std::string count_key(const Geometry &g) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%d:%d:%d:%d|%dx%d:%d:%d:%d:%d:%d|%dx%d", g.lp.d[0], g.lp.d[1], g.lp.d[2], g.lp.periodic,
+             g.B.W, g.B.H, g.B.wrap, g.B.form, g.B.edges, g.vp.qpow, g.vp.hybrid, g.B.Th, g.B.Tw);
+    return buf;
+}
+
+unsigned long long capacity_for(unsigned long long most) { return most + most / 4 + 4096; }
+
+// First guess without any count: four pairs per record (the stress workload
+// at 2048^2 with 32 x 512 tiles has 3.3), within [2^20, 2^31].
+unsigned long long first_guess(const Geometry &g) {
+    const unsigned long long want = 4ull * (unsigned long long)g.ntet;
+    return std::min<unsigned long long>(std::max<unsigned long long>(want, 1ull << 20), 1ull << 31);
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Takes the counts of the last call if they have arrived (never waits).
+void take_feedback(Workspace &ws, hipStream_t s) {
+    if (!ws.fb_pending || capturing(s)) return;
+    if (hipEventQuery(ws.fb_event) != hipSuccess) {
+        (void)hipGetLastError();  // not ready (or failed): try again on a later call
+        return;
+    }
+    unsigned long long most = 0;
+    for (int k = 0; k < ws.fb_n; ++k) most = std::max<unsigned long long>(most, ws.fb_plan[k].total_pairs);
+    unsigned long long &m = ws.learned[ws.fb_key];
+    m = std::max(m, most);
+    ws.fb_pending = false;
+}
+
+// Copies n PlanOut entries to the pinned feedback area behind an event.
+tess_status give_feedback(Workspace &ws, const PlanOut *plan, int n, const std::string &key, hipStream_t s) {
+    if (ws.fb_pending || capturing(s)) return TESS_OK;
+    if (ws.fb_cap < (size_t)n) {
+        TESS_HIP(hipHostFree(ws.fb_plan));
+        ws.fb_plan = nullptr;
+        ws.fb_cap = 0;
+        TESS_HIP(hipHostMalloc((void **)&ws.fb_plan, sizeof(PlanOut) * (size_t)n, hipHostMallocDefault));
+        ws.fb_cap = (size_t)n;
+    }
+    TESS_HIP(hipMemcpyAsync(ws.fb_plan, plan, sizeof(PlanOut) * (size_t)n, hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipEventRecord(ws.fb_event, s));
+    ws.fb_n = n;
+    ws.fb_key = key;
+    ws.fb_pending = true;
+    return TESS_OK;
+}
+
+// One image.  Without stats nothing waits for the device.
 tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan &plan, float *image,
                          tess_stats *stats, hipStream_t s, Workspace &ws) {
     Geometry g;
     tess_status st = make_geometry(L, v, plan, g);
     if (st != TESS_OK) return st;
-    st = ensure_front(ws, g);
+    Sizes z;
+    z.add(g);
+    st = ensure_front(ws, z);
     if (st != TESS_OK) return st;
     TESS_HIP(ws.plan.ensure(1));
+    take_feedback(ws, s);
+    const std::string key = count_key(g);
+    auto it = ws.learned.find(key);
+    const bool known = it != ws.learned.end();
+    const unsigned long long cap = plan.cap ? plan.cap : (known ? capacity_for(it->second) : first_guess(g));
+    const int chunk = plan.chunk ? plan.chunk : auto_chunk(known ? it->second : cap / 2);
+    st = ensure_back(ws, g.ntiles, chunk, cap);
+    if (st != TESS_OK) return st;
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
     TESS_HIP(launch_zero((double *)ws.counters.p, sizeof(DevCounters) / sizeof(double), s));
     st = enqueue_setup(g, ws, ws.plan.p, s);
@@ -550,39 +663,34 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
     TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
     TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));
-    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, ~0ull, ws.plan.p, nullptr, s));
-    TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
-    TESS_HIP(hipStreamSynchronize(s));
-    const unsigned long long total = ws.host_plan->total_pairs;
-    const int chunk = plan.chunk ? plan.chunk : auto_chunk(total);
-    st = ensure_back(ws, g, chunk, total);
-    if (st != TESS_OK) return st;
-    st = enqueue_back(g, plan, chunk, total, ws, ws.plan.p, image, s, stats ? ws.ev[2] : nullptr,
+    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, cap, ws.plan.p, nullptr, s));
+    st = enqueue_back(g, plan, chunk, cap, ws, ws.plan.p, image, s, stats ? ws.ev[2] : nullptr,
                       stats ? ws.ev[3] : nullptr);
     if (st != TESS_OK) return st;
-    if (stats) {
-        TESS_HIP(hipEventRecord(ws.ev[4], s));
-        TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters),
-                                hipMemcpyDeviceToHost, s));
-        TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
-        TESS_HIP(hipStreamSynchronize(s));
-        float ms = 0, t_setup = 0, t_bin = 0, t_raster = 0, t_fin = 0;
-        TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
-        TESS_HIP(hipEventElapsedTime(&t_setup, ws.ev[0], ws.ev[1]));
-        TESS_HIP(hipEventElapsedTime(&t_bin, ws.ev[1], ws.ev[2]));
-        TESS_HIP(hipEventElapsedTime(&t_raster, ws.ev[2], ws.ev[3]));
-        TESS_HIP(hipEventElapsedTime(&t_fin, ws.ev[3], ws.ev[4]));
-        const PlanOut &P = *ws.host_plan;
-        fill_stats(stats, *ws.host_counters, plan, chunk);
-        stats->bin_pairs = P.total_pairs;
-        stats->max_bin = (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull);
-        stats->work_items = (uint32_t)P.n_items;
-        stats->ms = ms;
-        stats->setup_ms = t_setup;
-        stats->bin_ms = t_bin;
-        stats->raster_ms = t_raster;
-        stats->finalize_ms = t_fin;
-    }
+    if (!stats) return give_feedback(ws, ws.plan.p, 1, key, s);
+    TESS_HIP(hipEventRecord(ws.ev[4], s));
+    TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut), hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipStreamSynchronize(s));
+    float ms = 0, t_setup = 0, t_bin = 0, t_raster = 0, t_fin = 0;
+    TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
+    TESS_HIP(hipEventElapsedTime(&t_setup, ws.ev[0], ws.ev[1]));
+    TESS_HIP(hipEventElapsedTime(&t_bin, ws.ev[1], ws.ev[2]));
+    TESS_HIP(hipEventElapsedTime(&t_raster, ws.ev[2], ws.ev[3]));
+    TESS_HIP(hipEventElapsedTime(&t_fin, ws.ev[3], ws.ev[4]));
+    const PlanOut &P = *ws.host_plan;
+    unsigned long long &m = ws.learned[key];
+    m = std::max<unsigned long long>(m, P.total_pairs);
+    fill_stats(stats, *ws.host_counters, plan, chunk);
+    stats->bin_pairs = P.total_pairs;
+    stats->max_bin = (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull);
+    stats->work_items = (uint32_t)P.n_items;
+    stats->overflow = P.total_pairs > cap ? 1u : 0u;
+    stats->ms = ms;
+    stats->setup_ms = t_setup;
+    stats->bin_ms = t_bin;
+    stats->raster_ms = t_raster;
+    stats->finalize_ms = t_fin;
     return TESS_OK;
 }
 
@@ -602,6 +710,9 @@ tess_status check_project_args(tess_lattice L, const tess_view *v, const tess_tu
         if (tune->chunk != 0 && tune->chunk < 64) return fail(TESS_EINVAL, "tune.chunk must be 0 or >= 64");
         if (tune->block != 0 && tune->block != 256 && tune->block != 512 && tune->block != 1024)
             return fail(TESS_EINVAL, "tune.block must be 0, 256, 512 or 1024");
+        if (tune->form != TESS_FORM_AUTO && tune->form != TESS_FORM_PER_TETRAHEDRON && tune->form != TESS_FORM_EDGES)
+            return fail(TESS_EINVAL, "tune.form must be 0 (automatic), 1 (per tetrahedron) or 2 (edges)");
+        if (tune->reserved != 0) return fail(TESS_EINVAL, "tune.reserved must be 0");
     }
     return TESS_OK;
 }
@@ -615,7 +726,9 @@ tess_status lock_workspace(tess_lattice L, hipStream_t s, Workspace **ws) {
 
 // ---------------------------------------------------------------- batches
 // Raster parameters and pair capacity chosen for a batch shape, kept for
-// later calls with the same lattice and image shape.
+// later calls with the same lattice and image shape, in this process and,
+// when the environment variable TESS_TUNE_CACHE names a file, in that JSON
+// file (keyed by the shape and the device).
 struct Tuned {
     Plan plan;
     int chunk;
@@ -624,65 +737,200 @@ struct Tuned {
 std::mutex g_tune_mu;
 std::map<std::string, Tuned> g_tuned;
 
-std::string shape_key(const tess_lattice_s *L, const tess_view *v, int n_snaps, int n_views) {
-    char buf[256];
-    snprintf(buf, sizeof(buf), "%d:%d:%d:%d|%dx%d:%d|%d:%d", L->desc.dims[0], L->desc.dims[1], L->desc.dims[2],
-             L->desc.periodic, v->width, v->height, v->wrap, n_snaps, n_views);
+std::string shape_key(const tess_lattice_s *L, const tess_view *v, int n_snaps, int n_views, const tess_tune *tune) {
+    char buf[384];
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof(prop));
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) (void)hipGetLastError();
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    snprintf(buf, sizeof(buf), "%s/%dcu|%d:%d:%d:%d|%dx%d:%d:%d:%d:%d:%d|%d:%d|tune %d %d %d %d %d %llu",
+             arch.c_str(), prop.multiProcessorCount, L->desc.dims[0], L->desc.dims[1], L->desc.dims[2],
+             L->desc.periodic, v->width, v->height, v->wrap, v->quantity, v->slab, v->method, v->projection,
+             n_snaps, n_views, tune ? tune->tile_rows : 0, tune ? tune->tile_cols : 0, tune ? tune->chunk : 0,
+             tune ? tune->block : 0, tune ? tune->form : 0,
+             tune ? (unsigned long long)tune->pair_capacity : 0ull);
     return buf;
 }
 
-// Times one image under each candidate tiling (synchronous calls) and keeps
-// the fastest; the pair capacity is 1.5 times the largest count seen over the
-// snapshots' first views.
-tess_status autotune(const tess_lattice *snaps, int n_snaps, const tess_view *views, float *scratch_image,
-                     hipStream_t s, Workspace &ws, Tuned &out) {
-    Plan base = choose_plan(&views[0], nullptr);
+// ---- the JSON tune cache: one object per line inside "entries", e.g.
+// {"key": "...", "tile_rows": 64, "tile_cols": 256, "chunk": 1024, "block": 1024, "form": 0, "pair_capacity": 123}
+const char *tune_cache_path() {
+    const char *p = getenv("TESS_TUNE_CACHE");
+    return (p && p[0]) ? p : nullptr;
+}
+
+bool json_string(const std::string &line, const char *field, std::string &out) {
+    const std::string pat = std::string("\"") + field + "\": \"";
+    const size_t a = line.find(pat);
+    if (a == std::string::npos) return false;
+    const size_t b = line.find('"', a + pat.size());
+    if (b == std::string::npos) return false;
+    out = line.substr(a + pat.size(), b - a - pat.size());
+    return true;
+}
+
+bool json_number(const std::string &line, const char *field, unsigned long long &out) {
+    const std::string pat = std::string("\"") + field + "\": ";
+    const size_t a = line.find(pat);
+    if (a == std::string::npos) return false;
+    char *end = nullptr;
+    out = strtoull(line.c_str() + a + pat.size(), &end, 10);
+    return end != line.c_str() + a + pat.size();
+}
+
+std::map<std::string, Tuned> read_tune_cache(const char *path) {
+    std::map<std::string, Tuned> m;
+    FILE *f = fopen(path, "r");
+    if (!f) return m;
+    char buf[1024];
+    while (fgets(buf, sizeof(buf), f)) {
+        const std::string line(buf);
+        std::string key;
+        unsigned long long th, tw, chunk, block, form, cap;
+        if (!json_string(line, "key", key) || !json_number(line, "tile_rows", th) ||
+            !json_number(line, "tile_cols", tw) || !json_number(line, "chunk", chunk) ||
+            !json_number(line, "block", block) || !json_number(line, "form", form) ||
+            !json_number(line, "pair_capacity", cap))
+            continue;
+        if (th < 1 || th > 256 || tw < 16 || tw > (unsigned long long)kMaxTileCells || th * tw > kMaxTileCells ||
+            chunk < 64 || (block != 256 && block != 512 && block != 1024) || form > 2 || cap < 1)
+            continue;
+        Tuned t;
+        t.plan.Th = (int)th;
+        t.plan.Tw = (int)tw;
+        t.plan.chunk = (int)chunk;
+        t.plan.block = (int)block;
+        t.plan.form = (int)form;
+        t.plan.cap = 0;
+        t.chunk = (int)chunk;
+        t.cap = cap;
+        m[key] = t;
+    }
+    fclose(f);
+    return m;
+}
+
+void write_tune_cache(const char *path, const std::string &key, const Tuned &t) {
+    std::map<std::string, Tuned> m = read_tune_cache(path);
+    m[key] = t;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;  // the cache is an optimisation: a failed write is ignored
+    fprintf(f, "{\"version\": 1, \"entries\": [\n");
+    size_t i = 0;
+    for (const auto &kv : m) {
+        const Tuned &e = kv.second;
+        fprintf(f,
+                "{\"key\": \"%s\", \"tile_rows\": %d, \"tile_cols\": %d, \"chunk\": %d, \"block\": %d, "
+                "\"form\": %d, \"pair_capacity\": %llu}%s\n",
+                kv.first.c_str(), e.plan.Th, e.plan.Tw, e.chunk, e.plan.block, e.plan.form, e.cap,
+                ++i < m.size() ? "," : "");
+    }
+    fprintf(f, "]}\n");
+    const bool ok = fclose(f) == 0;
+    if (ok) (void)rename(tmp.c_str(), path);
+}
+
+// Pair count of every (snapshot, view) image under `plan`: the front of each
+// image (setup, count, scan, totals) into its own PlanOut slot, then one
+// synchronisation.  Returns the counts in host_plan.
+tess_status count_all(const tess_lattice *snaps, int n_snaps, const tess_view *views, int n_views, const Plan &plan,
+                      hipStream_t s, Workspace &ws) {
+    const int n_img = n_snaps * n_views;
+    Sizes z;
+    for (int i = 0; i < n_snaps; ++i)
+        for (int v = 0; v < n_views; ++v) {
+            Geometry g;
+            tess_status st = make_geometry(snaps[i], &views[v], plan, g);
+            if (st != TESS_OK) return st;
+            z.add(g);
+        }
+    tess_status st = ensure_front(ws, z);
+    if (st != TESS_OK) return st;
+    TESS_HIP(ws.plan.ensure((size_t)n_img));
+    if (ws.host_plan_cap < (size_t)n_img) {
+        TESS_HIP(hipHostFree(ws.host_plan));
+        ws.host_plan = nullptr;
+        ws.host_plan_cap = 0;
+        TESS_HIP(hipHostMalloc((void **)&ws.host_plan, sizeof(PlanOut) * (size_t)n_img, hipHostMallocDefault));
+        ws.host_plan_cap = (size_t)n_img;
+    }
+    for (int i = 0; i < n_snaps; ++i)
+        for (int v = 0; v < n_views; ++v) {
+            Geometry g;
+            st = make_geometry(snaps[i], &views[v], plan, g);
+            if (st != TESS_OK) return st;
+            st = enqueue_front(g, ws, ws.plan.p + i * n_views + v, ~0ull, nullptr, s);
+            if (st != TESS_OK) return st;
+        }
+    TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut) * (size_t)n_img, hipMemcpyDeviceToHost, s));
+    TESS_HIP(hipStreamSynchronize(s));
+    return TESS_OK;
+}
+
+// The batch's tuning, done once per shape: the tiling (tune's, or the
+// fastest candidate, timed on the image with the most pairs) and the pair
+// capacity (tune's, or the largest count over all images under that tiling,
+// with a small margin, so that no image of these snapshots overflows).
+tess_status tune_batch(const tess_lattice *snaps, int n_snaps, const tess_view *views, int n_views,
+                       const tess_tune *tune, float *scratch_image, hipStream_t s, Workspace &ws, Tuned &out) {
+    const int n_img = n_snaps * n_views;
+    Plan plan = choose_plan(&views[0], tune);
+    if (!tune || (!tune->tile_rows && !tune->tile_cols)) {
+        tess_status st = count_all(snaps, n_snaps, views, n_views, plan, s, ws);
+        if (st != TESS_OK) return st;
+        int heavy = 0;
+        for (int k = 1; k < n_img; ++k)
+            if (ws.host_plan[k].total_pairs > ws.host_plan[heavy].total_pairs) heavy = k;
+        const tess_lattice hs = snaps[heavy / n_views];
+        const tess_view *hv = &views[heavy % n_views];
+        const int W = views[0].width;
+        std::vector<Plan> cands;
+        for (int Tw : {std::min(W, 1024), std::min(W, 512), std::min(W, 256)}) {
+            for (int Th : {8, 16, 32, 64}) {
+                if ((int64_t)Th * Tw > kMaxTileCells || (int64_t)Th * Tw < 2048) continue;
+                bool dup = false;
+                for (const Plan &c : cands) dup |= (c.Th == Th && c.Tw == Tw);
+                if (dup) continue;
+                Plan p = plan;
+                p.Th = Th;
+                p.Tw = Tw;
+                p.cap = 0;
+                cands.push_back(p);
+            }
+        }
+        if (!cands.empty()) {
+            float best_ms = 0;
+            Plan best = cands[0];
+            for (size_t c = 0; c < cands.size(); ++c) {
+                float ms = 0;
+                for (int rep = 0; rep < 2; ++rep) {  // the first call sizes the pair buffer
+                    tess_stats st;
+                    std::memset(&st, 0, sizeof(st));
+                    tess_status rc = project_impl(hs, hv, cands[c], scratch_image, &st, s, ws);
+                    if (rc != TESS_OK) return rc;
+                    ms = st.ms;
+                }
+                if (c == 0 || ms < best_ms) {
+                    best_ms = ms;
+                    best = cands[c];
+                }
+            }
+            best.cap = plan.cap;
+            plan = best;
+        }
+    }
     unsigned long long most = 0;
-    int heavy = 0;
-    for (int i = 0; i < n_snaps; ++i) {
-        tess_stats st;
-        std::memset(&st, 0, sizeof(st));
-        tess_status rc = project_impl(snaps[i], &views[0], base, scratch_image, &st, s, ws);
-        if (rc != TESS_OK) return rc;
-        if (st.bin_pairs >= most) {
-            most = st.bin_pairs;
-            heavy = i;
-        }
+    if (!plan.cap || !plan.chunk) {
+        tess_status st = count_all(snaps, n_snaps, views, n_views, plan, s, ws);
+        if (st != TESS_OK) return st;
+        for (int k = 0; k < n_img; ++k) most = std::max<unsigned long long>(most, ws.host_plan[k].total_pairs);
     }
-    const int W = views[0].width;
-    std::vector<Plan> cands;
-    for (int Tw : {std::min(W, 1024), std::min(W, 512), std::min(W, 256)}) {
-        for (int Th : {8, 16, 32, 64}) {
-            if ((int64_t)Th * Tw > kMaxTileCells || (int64_t)Th * Tw < 2048) continue;
-            bool dup = false;
-            for (const Plan &c : cands) dup |= (c.Th == Th && c.Tw == Tw);
-            if (dup) continue;
-            Plan p = base;
-            p.Th = Th;
-            p.Tw = Tw;
-            cands.push_back(p);
-        }
-    }
-    if (cands.empty()) cands.push_back(base);
-    float best_ms = 0;
-    Plan best = cands[0];
-    for (const Plan &p : cands) {
-        float ms = 0;
-        for (int rep = 0; rep < 2; ++rep) {
-            tess_stats st;
-            std::memset(&st, 0, sizeof(st));
-            tess_status rc = project_impl(snaps[heavy], &views[0], p, scratch_image, &st, s, ws);
-            if (rc != TESS_OK) return rc;
-            ms = st.ms;
-        }
-        if (&p == &cands[0] || ms < best_ms) {
-            best_ms = ms;
-            best = p;
-        }
-    }
-    out.plan = best;
-    out.chunk = auto_chunk(most);
-    out.cap = most + most / 2 + 4096;
+    out.plan = plan;
+    out.chunk = plan.chunk ? plan.chunk : auto_chunk(most);
+    out.cap = plan.cap ? plan.cap : most + most / 16 + 4096;
     return TESS_OK;
 }
 
@@ -702,9 +950,6 @@ std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *v
     const void *bufs[] = {ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
                           ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p, ws.overflow.p};
     put(bufs, sizeof(bufs));
-    const char *per_tet = getenv("TESS_PER_TETRAHEDRON");
-    const char form = per_tet ? per_tet[0] : 'x';  // the form switch
-    put(&form, 1);
     return k;
 }
 
@@ -713,14 +958,10 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
                                Workspace &ws) {
     const size_t img = (size_t)views[0].width * views[0].height;
     const int n_img = n_snaps * n_views;
-    // raster parameters and capacity, sized once per batch shape and tune
+    const std::string key = shape_key(snaps[0], &views[0], n_snaps, n_views, tune);
+    const std::string count_key = "batch|" + key;
+    // raster parameters and capacity: this process's, the cache file's, or tuned now
     Tuned t;
-    std::string key = shape_key(snaps[0], &views[0], n_snaps, n_views);
-    if (tune) {
-        char buf[96];
-        snprintf(buf, sizeof(buf), "|tune %d %d %d %d", tune->tile_rows, tune->tile_cols, tune->chunk, tune->block);
-        key += buf;
-    }
     bool have = false;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -728,40 +969,52 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
         if (it != g_tuned.end()) {
             t = it->second;
             have = true;
+        } else if (const char *path = tune_cache_path()) {
+            std::map<std::string, Tuned> m = read_tune_cache(path);
+            auto jt = m.find(key);
+            if (jt != m.end()) {
+                t = jt->second;
+                g_tuned[key] = t;
+                have = true;
+            }
         }
     }
     if (!have) {
-        if (tune) {
-            t.plan = choose_plan(&views[0], tune);
-            unsigned long long most = 0;
-            for (int i = 0; i < n_snaps; ++i) {
-                tess_stats st;
-                std::memset(&st, 0, sizeof(st));
-                tess_status rc = project_impl(snaps[i], &views[0], t.plan, images, &st, s, ws);
-                if (rc != TESS_OK) return rc;
-                most = std::max<unsigned long long>(most, st.bin_pairs);
-            }
-            t.chunk = t.plan.chunk ? t.plan.chunk : auto_chunk(most);
-            t.cap = most + most / 2 + 4096;
-        } else {
-            tess_status rc = autotune(snaps, n_snaps, views, images, s, ws, t);
-            if (rc != TESS_OK) return rc;
-        }
+        tess_status rc = tune_batch(snaps, n_snaps, views, n_views, tune, images, s, ws, t);
+        if (rc != TESS_OK) return rc;
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[key] = t;
+        if (const char *path = tune_cache_path()) write_tune_cache(path, key, t);
     }
-    // buffers for the largest image of the batch, then the graph
-    Geometry g0;
-    tess_status st = make_geometry(snaps[0], &views[0], t.plan, g0);
+    // counts of an earlier call that overflowed raise the capacity
+    take_feedback(ws, s);
+    {
+        auto it = ws.learned.find(count_key);
+        if (it != ws.learned.end() && it->second > t.cap && !t.plan.cap) {
+            t.cap = capacity_for(it->second);
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tuned[key] = t;
+        }
+    }
+    // buffers for the largest image of the batch (forms and sizes may differ
+    // between images), then the graph
+    Sizes z;
+    for (int i = 0; i < n_snaps; ++i)
+        for (int v = 0; v < n_views; ++v) {
+            Geometry g;
+            tess_status st = make_geometry(snaps[i], &views[v], t.plan, g);
+            if (st != TESS_OK) return st;
+            z.add(g);
+        }
+    tess_status st = ensure_front(ws, z);
     if (st != TESS_OK) return st;
-    st = ensure_front(ws, g0);
-    if (st != TESS_OK) return st;
-    st = ensure_back(ws, g0, t.chunk, t.cap);
+    st = ensure_back(ws, z.ntiles, t.chunk, t.cap);
     if (st != TESS_OK) return st;
     TESS_HIP(ws.plan.ensure((size_t)n_img));
     if (ws.host_plan_cap < (size_t)n_img) {
         TESS_HIP(hipHostFree(ws.host_plan));
         ws.host_plan = nullptr;
+        ws.host_plan_cap = 0;
         TESS_HIP(hipHostMalloc((void **)&ws.host_plan, sizeof(PlanOut) * (size_t)n_img, hipHostMallocDefault));
         ws.host_plan_cap = (size_t)n_img;
     }
@@ -773,17 +1026,15 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
         }
         hipStream_t c = ws.capture;
         TESS_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
-        tess_status cst = TESS_OK;
         auto record = [&]() -> tess_status {
             TESS_HIP(launch_zero((double *)ws.counters.p, sizeof(DevCounters) / sizeof(double), c));
-            TESS_HIP(launch_zero((double *)ws.overflow.p, 1, c));  // the buffer holds >= 64 words
             for (int i = 0; i < n_snaps; ++i)
                 for (int v = 0; v < n_views; ++v) {
                     const int k = i * n_views + v;
                     Geometry g;
                     tess_status r = make_geometry(snaps[i], &views[v], t.plan, g);
                     if (r != TESS_OK) return r;
-                    r = enqueue_front(g, ws, ws.plan.p + k, t.cap, ws.overflow.p, c);
+                    r = enqueue_front(g, ws, ws.plan.p + k, t.cap, nullptr, c);
                     if (r != TESS_OK) return r;
                     r = enqueue_back(g, t.plan, t.chunk, t.cap, ws, ws.plan.p + k, images + (size_t)k * img, c,
                                      nullptr, nullptr);
@@ -791,7 +1042,7 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
                 }
             return TESS_OK;
         };
-        cst = record();
+        const tess_status cst = record();
         hipGraph_t graph = nullptr;
         const hipError_t end = hipStreamEndCapture(c, &graph);
         if (cst != TESS_OK) {
@@ -809,56 +1060,29 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
     }
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
     TESS_HIP(hipGraphLaunch(ws.graph, s));
-    if (stats) TESS_HIP(hipEventRecord(ws.ev[4], s));
-    TESS_HIP(hipMemcpyAsync(ws.host_overflow, ws.overflow.p, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    if (!stats) return give_feedback(ws, ws.plan.p, n_img, count_key, s);
+    TESS_HIP(hipEventRecord(ws.ev[4], s));
     TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut) * (size_t)n_img, hipMemcpyDeviceToHost, s));
     TESS_HIP(hipMemcpyAsync(ws.host_counters, ws.counters.p, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     TESS_HIP(hipStreamSynchronize(s));
     tess_stats acc;
     std::memset(&acc, 0, sizeof(acc));
-    if (stats) {
-        float ms = 0;
-        TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
-        fill_stats(&acc, *ws.host_counters, t.plan, t.chunk);
-        acc.ms = ms;
-        for (int k = 0; k < n_img; ++k) {
-            acc.bin_pairs += ws.host_plan[k].total_pairs;
-            acc.max_bin = std::max<uint32_t>(acc.max_bin, (uint32_t)std::min<unsigned long long>(
-                                                              ws.host_plan[k].max_bin, 0xffffffffull));
-            acc.work_items += (uint32_t)ws.host_plan[k].n_items;
-        }
+    float ms = 0;
+    TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
+    fill_stats(&acc, *ws.host_counters, t.plan, t.chunk);
+    acc.ms = ms;
+    unsigned long long most = 0;
+    for (int k = 0; k < n_img; ++k) {
+        const PlanOut &P = ws.host_plan[k];
+        acc.bin_pairs += P.total_pairs;
+        acc.max_bin = std::max<uint32_t>(acc.max_bin, (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull));
+        acc.work_items += (uint32_t)P.n_items;
+        acc.overflow += P.total_pairs > t.cap ? 1u : 0u;
+        most = std::max<unsigned long long>(most, P.total_pairs);
     }
-    if (*ws.host_overflow) {
-        // images whose pairs exceeded the capacity: redo them one by one
-        std::vector<int> redo;
-        for (int k = 0; k < n_img; ++k)
-            if (ws.host_plan[k].total_pairs > t.cap) redo.push_back(k);
-        for (int k : redo) {
-            tess_stats one;
-            std::memset(&one, 0, sizeof(one));
-            const int i = k / n_views, v = k % n_views;
-            tess_status rc = project_impl(snaps[i], &views[v], t.plan, images + (size_t)k * img,
-                                          stats ? &one : nullptr, s, ws);
-            if (rc != TESS_OK) return rc;
-            if (stats) {
-                // the graph's counters missed this image's raster
-                acc.fragments += one.fragments;
-                acc.spans += one.spans;
-                acc.kinks += one.kinks;
-                acc.work_items += one.work_items;
-                acc.ms += one.ms;
-            }
-        }
-        // the next call sizes for the largest count seen
-        unsigned long long most = 0;
-        for (int k = 0; k < n_img; ++k) most = std::max<unsigned long long>(most, ws.host_plan[k].total_pairs);
-        {
-            std::lock_guard<std::mutex> lock(g_tune_mu);
-            auto it = g_tuned.find(key);
-            if (it != g_tuned.end()) it->second.cap = most + most / 2 + 4096;
-        }
-    }
-    if (stats) *stats = acc;
+    unsigned long long &m = ws.learned[count_key];
+    m = std::max(m, most);
+    *stats = acc;
     return TESS_OK;
 }
 }  // namespace

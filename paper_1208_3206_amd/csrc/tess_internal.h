@@ -230,6 +230,13 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
                          const BinParams &B, int block, double *acc, DevCounters *counters,
                          hipStream_t stream);
 
+// Overflow raster: when plan->total_pairs > cap (the image's tile lists were
+// dropped), every record over the whole image with L2 atomics into acc;
+// otherwise the launch returns at once.
+hipError_t launch_raster_direct(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
+                                const PlanOut *plan, unsigned long long cap, const BinParams &B, double *acc,
+                                DevCounters *counters, hipStream_t stream);
+
 // Row-wise double prefix sum of acc -> image (FP32).
 hipError_t launch_finalize(const double *acc, const BinParams &B, float *image, hipStream_t stream);
 

@@ -662,6 +662,94 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- overflow raster
+// When an image's (record, tile) pairs exceed the pair buffer, binning drops
+// its lists and this kernel draws every record over the whole image instead:
+// one thread per record, the image taken as row bands of kDirectRows rows
+// (the crease form's row offsets are 8-bit), entries added into `acc` with
+// L2 FP64 atomics.  Slow, but it needs no list, so the projection never has
+// to read the pair count back before launching the raster.  Every other
+// image returns at once.
+constexpr int kDirectRows = 256;
+
+template <int FORM>
+__global__ void __launch_bounds__(256) k_raster_direct(const RecHead *__restrict__ head,
+                                                       const Payload *__restrict__ coef,
+                                                       const EdgePayload *__restrict__ ecoef,
+                                                       const PlanOut *__restrict__ plan, unsigned long long cap,
+                                                       BinParams B, double *__restrict__ acc,
+                                                       DevCounters *__restrict__ counters) {
+    if (plan->total_pairs <= cap) return;
+    long long frags = 0;
+    uint32_t spans = 0, kinks = 0;
+    const int W = B.W;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < (int64_t)B.ntet;
+         id += (int64_t)gridDim.x * blockDim.x) {
+        for (int ty0 = 0; ty0 < B.H; ty0 += kDirectRows) {
+            const int rows = min(kDirectRows, B.H - ty0);
+            auto dep = [&](int row, int j, double v) {
+                if (j >= 0 && j < W) unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W + j], v);
+            };
+            auto seam = [&](int row, double a, double b) {
+                unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W], a);
+                if (W > 1) unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W + 1], b - a);
+            };
+            if constexpr (FORM == kFormEdge) {
+                if ((uint32_t)id >= B.first_edge) {
+                    const RecHead h = head[id];
+                    if (!(h.flags & REC_VALID)) break;
+                    frags += (int32_t)edge_pair(ecoef[id - B.first_edge], B, 0, ty0, W, rows, dep, seam, kinks);
+                    continue;
+                }
+            }
+            const RecHead h = head[id];
+            if (!(h.flags & REC_VALID)) break;
+            if constexpr (FORM == kFormPersp)
+                frags += persp_pair(h, coef[id].c, B, 0, ty0, W, rows, 0, 1, dep, spans, kinks);
+            else
+                frags += (int32_t)raster_record<FORM == kFormEdge ? kFormPyramid : FORM>(
+                    h, coef[id].c, B, 0, ty0, W, rows, dep, seam, spans, kinks);
+        }
+    }
+    const unsigned long long f = wave_sum((unsigned long long)frags);
+    const unsigned long long sp = wave_sum((unsigned long long)spans);
+    const unsigned long long kk = wave_sum((unsigned long long)kinks);
+    if ((threadIdx.x & 63) == 0) {
+        if (f) atomicAdd(&counters->fragments, f);
+        if (sp) atomicAdd(&counters->spans, sp);
+        if (kk) atomicAdd(&counters->kinks, kk);
+    }
+}
+
+hipError_t launch_raster_direct(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
+                                const PlanOut *plan, unsigned long long cap, const BinParams &B, double *acc,
+                                DevCounters *counters, hipStream_t stream) {
+    const int64_t want = ((int64_t)B.ntet + 255) / 256;
+    const dim3 grid((unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536)), block(256);
+    switch (B.form) {
+        case kFormFace:
+            hipLaunchKernelGGL(k_raster_direct<kFormFace>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,
+                               counters);
+            break;
+        case kFormSplat:
+            hipLaunchKernelGGL(k_raster_direct<kFormSplat>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,
+                               counters);
+            break;
+        case kFormPersp:
+            hipLaunchKernelGGL(k_raster_direct<kFormPersp>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,
+                               counters);
+            break;
+        default:
+            if (B.edges)
+                hipLaunchKernelGGL(k_raster_direct<kFormEdge>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B,
+                                   acc, counters);
+            else
+                hipLaunchKernelGGL(k_raster_direct<kFormPyramid>, grid, block, 0, stream, head, coef, ecoef, plan, cap,
+                                   B, acc, counters);
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- finalize
 // One block per image row: f = running sum of the running sum of acc's row.
 // Column densities are >= 0; a sum that rounding left a little below zero (a

@@ -8,6 +8,7 @@
 // loss is the mean over samples of |s - target|^2.  bf16 operands, FP32
 // accumulation, FP32 master weights.
 #include "tess_mlp.h"
+#include "tess_tet.h"  // the connectivity table (kTet)
 
 #include <hip/hip_runtime.h>
 
@@ -454,11 +455,10 @@ hipError_t launch_place_mlp(const float *cx, const float *cy, const float *cz, c
 // coordinates in it (Cramer's rule); -1 if none does (not reached for points
 // of the unit cube, which the six tetrahedra tile).
 __device__ inline int unit_cube_tet(const double p[3], double lam[4]) {
-    constexpr int tet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
     for (int t = 0; t < 6; ++t) {
         double R[4][3];
         for (int m = 0; m < 4; ++m) {
-            const int c = tet[t][m];
+            const int c = kTet[t][m];
             R[m][0] = c & 1; R[m][1] = (c >> 1) & 1; R[m][2] = (c >> 2) & 1;
         }
         double M[3][3], rhs[3];
@@ -484,10 +484,7 @@ __device__ inline int unit_cube_tet(const double p[3], double lam[4]) {
     return -1;
 }
 
-__device__ inline int cube_corner(int t, int m) {
-    constexpr int tet[6][4] = {{1, 0, 2, 4}, {3, 1, 2, 4}, {3, 5, 1, 4}, {3, 6, 5, 4}, {3, 2, 6, 4}, {3, 7, 5, 6}};
-    return tet[t][m];
-}
+__device__ inline int cube_corner(int t, int m) { return kTet[t][m]; }
 
 // Fine positions by the affine map of the coarse tetrahedron that contains
 // the vertex's Lagrangian point.

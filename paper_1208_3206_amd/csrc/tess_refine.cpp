@@ -182,6 +182,33 @@ extern "C" tess_status tess_mlp_loss_grad(const float *params, const float *rff_
     return ok();
 }
 
+extern "C" tess_status tess_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, double lr,
+                                     double beta1, double beta2, double eps, void *stream) {
+    if (!params || !m || !v || !grad) return fail(TESS_EINVAL, "NULL argument");
+    if (step < 1) return fail(TESS_EINVAL, "step must be >= 1");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(TESS_EINVAL, "need lr > 0, 0 <= beta1, beta2 < 1 and eps > 0");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<float> buf;  // params, m, v, grad
+    TESS_HIP(buf.ensure((size_t)4 * kParams));
+    float *dp = buf.p, *dm = buf.p + kParams, *dv = buf.p + 2 * kParams, *dg = buf.p + 3 * kParams;
+    auto run = [&]() -> tess_status {
+        TESS_HIP(hipMemcpyAsync(dp, params, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
+        TESS_HIP(hipMemcpyAsync(dm, m, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
+        TESS_HIP(hipMemcpyAsync(dv, v, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
+        TESS_HIP(hipMemcpyAsync(dg, grad, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
+        TESS_HIP(launch_adam(dp, dm, dv, dg, kParams, (float)lr, (float)beta1, (float)beta2, (float)eps, step, s));
+        TESS_HIP(hipMemcpyAsync(params, dp, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
+        TESS_HIP(hipMemcpyAsync(m, dm, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
+        TESS_HIP(hipMemcpyAsync(v, dv, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
+        TESS_HIP(hipStreamSynchronize(s));
+        return TESS_OK;
+    };
+    const tess_status st = run();
+    buf.release();
+    return st == TESS_OK ? ok() : st;
+}
+
 extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *d, tess_lattice *fine,
                                    tess_refine_report *report, void *stream) {
     if (!coarse || !d || !fine) return fail(TESS_EINVAL, "NULL argument");

@@ -6,6 +6,8 @@ accumulates in FP64, so the tests also hold every pixel with I_orc above
 1e-3 of the mean to 1e-6 (the FP32 output's rounding plus FP64 noise); empty
 pixels carry the row sums' FP64 cancellation noise, about 1e-12 of the mean.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -305,13 +307,7 @@ def test_repeatable_and_tiling_independent(tess, tiny_lattice):
         np.testing.assert_allclose(b, a, rtol=2.4e-7, atol=1e-12 * a.max())
 
 
-@pytest.fixture
-def per_tetrahedron(monkeypatch):
-    # every crease drawn per tetrahedron (the edge form off)
-    monkeypatch.setenv("TESS_PER_TETRAHEDRON", "1")
-
-
-def test_work_classes_keep_the_image(tess, per_tetrahedron):
+def test_work_classes_keep_the_image(tess):
     # many tiles: the tile lists are sorted into 32 work classes (default
     # 32 x 512 tiles), 2 (8 x 64) or none (4 x 32); the sorted plans must give
     # the unsorted plan's image and match the oracle's samples.  (The mean of
@@ -322,8 +318,9 @@ def test_work_classes_keep_the_image(tess, per_tetrahedron):
     xyz = W.zeldovich(n, 8, 4.0)
     lat = tess.build(*dev(xyz), (n, n, n))
     view = W.z_view(1024)
+    pt = "per_tetrahedron"
     imgs = [tess.project(lat, view, tune=t).cpu().numpy().astype(np.float64)
-            for t in (None, tess.make_tune(8, 64), tess.make_tune(4, 32))]
+            for t in (tess.make_tune(form=pt), tess.make_tune(8, 64, form=pt), tess.make_tune(4, 32, form=pt))]
     torch.cuda.synchronize()
     for im in imgs:
         assert abs(im.mean() - 1.0) < 1e-4, im.mean()
@@ -335,7 +332,7 @@ def test_work_classes_keep_the_image(tess, per_tetrahedron):
 
 
 @pytest.mark.parametrize("view_kind", ["z_wrap", "rotated"])
-def test_edge_form_equals_per_tetrahedron_form(tess, monkeypatch, view_kind):
+def test_edge_form_equals_per_tetrahedron_form(tess, view_kind):
     # the creases summed per mesh edge and drawn per tetrahedron give the same
     # image (up to the rounding of the sums) and the same fragment count, and
     # the edge form draws fewer kinks
@@ -345,12 +342,11 @@ def test_edge_form_equals_per_tetrahedron_form(tess, monkeypatch, view_kind):
     lat = tess.build(*dev(xyz), (n, n, n))
     view = W.z_view(768, 640) if view_kind == "z_wrap" else W.rotated_view(W.random_rotations(1, seed=8)[0], 700, 600)
     out = {}
-    for per_tet in ("0", "1"):
-        monkeypatch.setenv("TESS_PER_TETRAHEDRON", per_tet)
-        img, st = tess.project(lat, view, stats=True)
-        out[per_tet] = (img.cpu().numpy().astype(np.float64), st)
+    for form in ("edges", "per_tetrahedron"):
+        img, st = tess.project(lat, view, tune=tess.make_tune(form=form), stats=True)
+        out[form] = (img.cpu().numpy().astype(np.float64), st)
     torch.cuda.synchronize()
-    (a, sa), (b, sb) = out["0"], out["1"]
+    (a, sa), (b, sb) = out["edges"], out["per_tetrahedron"]
     np.testing.assert_allclose(a, b, rtol=2.4e-7, atol=1e-9 * b.max())
     assert sa["fragments"] == sb["fragments"] and sa["tets"] == sb["tets"]
     # (without wrap, tetrahedra of cubes cut by the box's faces stay per tetrahedron)
@@ -392,13 +388,12 @@ def _edge_case(name):
 
 @pytest.mark.parametrize("name", ["rotated", "non_periodic", "unit", "density2", "huge_footprints", "seam",
                                   "one_pixel", "narrow", "short"])
-def test_forced_edge_form_small_cases(tess, monkeypatch, name):
+def test_forced_edge_form_small_cases(tess, name):
     # cases below 6 pixels per lattice cell (or with tetrahedra as wide as the
     # image, and many across the periodic seam) drawn in the edge form: the
     # oracle's image and, except for q != rho's empty-pixel floor, fragments
-    monkeypatch.setenv("TESS_PER_TETRAHEDRON", "0")
     xyz, dims, view, kw = _edge_case(name)
-    got, st = gpu_image(tess, xyz, dims, view, **kw)
+    got, st = gpu_image(tess, xyz, dims, view, tune=tess.make_tune(form="edges"), **kw)
     ref, ost = O.project_region(*xyz, dims, view, **kw)
     if name in ("unit", "density2"):
         assert_quantity_parity(got, ref, name, what=f"edge form {name}")
@@ -448,23 +443,89 @@ def test_batch_with_explicit_tune_and_new_output(tess):
             torch.testing.assert_close(a[s, v], tess.project(lats[s], views[v]), rtol=2.4e-7, atol=1e-9)
 
 
-def test_batch_capacity_overflow_is_redone(tess):
-    # the pair buffer is sized from each snapshot's first view; here that view
-    # looks at empty space, so the second view's pairs overflow it and the
-    # image is redone after the graph
+def test_batch_capacity_overflow_uses_the_overflow_raster(tess):
+    # a pair capacity below the second view's count: its tile lists are
+    # dropped and the overflow raster draws it inside the same graph; the
+    # first view looks at empty space
     import torch
     n = 16
     lat = tess.build(*dev(W.zeldovich(n, 5, 3.0)), (n, n, n))
     R = W.random_rotations(1, seed=4)[0]
     empty = W.rotated_view(R, 40, 40, side=0.5, center=(9.0, 9.0, 9.0))
     full = W.rotated_view(R, 40, 40, side=2.0)
-    tune = tess.make_tune(4, 16)
-    imgs, st = tess.project_batch([lat], [empty, full], tune=tune, stats=True)
-    one, sst = tess.project(lat, full, tune=tune, stats=True)
-    assert sst["bin_pairs"] > 2 * 4096
+    imgs, st = tess.project_batch([lat], [empty, full], tune=tess.make_tune(4, 16, pair_capacity=1000), stats=True)
+    one, sst = tess.project(lat, full, tune=tess.make_tune(4, 16), stats=True)
+    assert sst["bin_pairs"] > 2000 and sst["overflow"] == 0
+    assert st["overflow"] == 1
     torch.testing.assert_close(imgs[0, 1], one, rtol=2.4e-7, atol=1e-9)
     assert float(imgs[0, 0].abs().max()) == 0.0
     assert st["fragments"] == sst["fragments"]
+
+
+@pytest.mark.parametrize("form", ["per_tetrahedron", "edges"])
+@pytest.mark.parametrize("kind", ["z_wrap", "rotated", "slab", "centroids", "perspective"])
+def test_overflow_raster_matches_the_oracle(tess, form, kind):
+    # a pair capacity of 64: every record drawn by the overflow raster (one
+    # thread per record over the whole image, L2 atomics)
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    view = {"z_wrap": W.z_view(120, 88), "rotated": W.rotated_view(W.random_rotations(1, seed=31)[0], 96, 80),
+            "slab": dict(W.z_view(64, 72), slab=(0.2, 0.5)),
+            "centroids": dict(W.z_view(64, 48), method="centroids"),
+            "perspective": W.perspective_view(np.eye(3), (0.45, 0.52, -1.4), 64, 48)}[kind]
+    got, st = gpu_image(tess, xyz, (n, n, n), view, tune=tess.make_tune(form=form, pair_capacity=64))
+    ref_small, _ = gpu_image(tess, xyz, (n, n, n), view, tune=tess.make_tune(form=form))
+    assert st["overflow"] == 1 and st["work_items"] == 0
+    if kind == "centroids":
+        ref, ost = O.splat_image(*xyz, (n, n, n), view)
+    else:
+        ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert_parity(got, ref, what=f"overflow raster {kind} {form}")
+    np.testing.assert_allclose(got, ref_small, rtol=2.4e-7, atol=1e-9 * ref.max())
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-6 * ost["fragments"] + 8
+
+
+def test_batch_with_mixed_forms_is_sized_for_every_image(tess):
+    # view 0 puts 4 pixels on a lattice cell (per-tetrahedron form), view 1
+    # puts 8 (edge form): the workspace must hold both images' records
+    import torch
+    n = 16
+    lats = [tess.build(*dev(W.zeldovich(n, 5, D)), (n, n, n)) for D in (2.0, 5.0)]
+    R = W.random_rotations(1, seed=12)[0]
+    views = [W.rotated_view(R, 128, 128, side=2.0), W.rotated_view(R, 128, 128, side=1.0)]
+    imgs = tess.project_batch(lats, views)
+    for s in range(2):
+        for v in range(2):
+            one, st = tess.project(lats[s], views[v], stats=True)
+            torch.testing.assert_close(imgs[s, v], one, rtol=2.4e-7, atol=1e-9)
+
+
+def test_project_is_capturable_and_needs_no_sync(tess):
+    # without stats tess_project only enqueues work: a call captured into a
+    # graph (after a first call sized the workspace) replays to the eager
+    # image, with eager work and synchronisations between the replays
+    import torch
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    lat = tess.build(*dev(xyz), (n, n, n))
+    view = W.z_view(160, 128)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        eager = tess.project(lat, view)
+        out = torch.empty_like(eager)
+        tess.project(lat, view, out=out)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        tess.project(lat, view, out=out)
+    for rep in range(3):
+        out.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        torch.testing.assert_close(out, eager, rtol=2.4e-7, atol=1e-9)
+        other = tess.project(lat, W.z_view(64, 64))  # eager work between replays
+        torch.cuda.synchronize()
+        assert float(other.sum()) > 0
 
 
 # ----------------------------------------------- full-size configurations
@@ -487,6 +548,101 @@ def test_mid_config_sampled_pixels(tess):
     assert r.max() <= PIX_TOL
     assert st["tets"] == w.tets
     assert abs(got.astype(np.float64).mean() - 1.0) < 1e-3
+
+
+GOLDEN_CROPS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "stress_crops.npz")
+
+
+@pytest.fixture(scope="module")
+def stress_crops():
+    # written by tests/golden/make_stress_crops.py (the oracle only)
+    return dict(np.load(GOLDEN_CROPS))
+
+
+@pytest.fixture(scope="module")
+def stress_input(stress_crops):
+    w = W.STRESS
+    xyz = W.zeldovich(w.n, w.kmax, w.growth[0])
+    # the same FP32 input the oracle saw
+    np.testing.assert_allclose(stress_fingerprint(xyz), stress_crops["fingerprint"], rtol=1e-12, atol=0)
+    return xyz
+
+
+def stress_fingerprint(xyz):
+    rows = []
+    for a in xyz:
+        a64 = a.astype(np.float64)
+        rows.append(np.concatenate([[a64.sum(), (a64 * a64).sum()], a64[:: max(1, a.size // 61)][:61]]))
+    return np.stack(rows)
+
+
+@pytest.mark.parametrize("side", [2048, 4096])
+def test_stress_crops_three_way(tess, stress_crops, stress_input, side):
+    # the stress workload's fixed 512^2 crops ([768, 1280)^2 at 2048^2,
+    # [1792, 2304)^2 at 4096^2) and, at 2048^2, a full-width strip of 16 rows
+    # whose running sums cross the periodic seam, element by element against
+    # the oracle: the default FP32 determinants (FP64 where the filter asks)
+    # and all-FP64 determinants, each against the oracle and against each other
+    import torch
+    w = W.STRESS
+    view = W.z_view(side)
+    imgs, stats = {}, {}
+    for prec in ("fp32", "fp64"):
+        lat = tess.build(*dev(stress_input), (w.n,) * 3, precision=prec)
+        img, st = tess.project(lat, view, stats=True)
+        imgs[prec], stats[prec] = img.cpu().numpy(), st
+        del lat
+        torch.cuda.synchronize()
+    print(f"stress {side}^2: fp64 dets {stats['fp32']['fp64_dets']} (filtered) / {stats['fp64']['fp64_dets']}, "
+          f"{stats['fp32']['ms']:.1f} ms, overflow {stats['fp32']['overflow']}", flush=True)
+    assert stats["fp32"]["tets"] == stats["fp64"]["tets"] == w.tets
+    assert stats["fp32"]["inverted"] == stats["fp64"]["inverted"]
+    names = [k for k in ("crop_2048", "crop_4096", "strip_2048") if int(stress_crops[k + "_side"]) == side]
+    for name in names:
+        x0, y0, cw, ch = (int(c) for c in stress_crops[name + "_crop"])
+        ref = stress_crops[name]
+        for prec in ("fp32", "fp64"):
+            assert_parity(imgs[prec][y0:y0 + ch, x0:x0 + cw], ref, what=f"{name} {prec} determinants")
+        a = imgs["fp32"][y0:y0 + ch, x0:x0 + cw].astype(np.float64)
+        b = imgs["fp64"][y0:y0 + ch, x0:x0 + cw].astype(np.float64)
+        d = np.abs(a - b) / np.maximum(np.abs(b), 1e-6 * np.abs(b).mean())
+        print(f"{name}: fp32 vs fp64 determinants max rel {d.max():.3e}", flush=True)
+        assert d.max() <= 1e-6
+
+
+GOLDEN_BATCH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_samples.npz")
+
+
+def test_batched_workload_subset_against_the_oracle(tess):
+    # the whole batched workload (8 snapshots x 64 rotated 512^2 views, one
+    # graph, autotuned) and, for the fixed 16-image subset (view 0 of every
+    # snapshot, views 1..8 of D = 8), 256 sampled pixels per image against
+    # the oracle's values (written by tests/golden/make_batched_samples.py)
+    import torch
+    g = dict(np.load(GOLDEN_BATCH))
+    w = W.BATCHED
+    views = W.workload_views(w)
+    psi = W.displacement_grid(w.n, w.kmax)
+    snaps = [W.zeldovich(w.n, w.kmax, D, psi=psi) for D in w.growth]
+    for k, xyz in enumerate(snaps):
+        np.testing.assert_allclose(stress_fingerprint(xyz), g["fingerprints"][k], rtol=1e-12, atol=0)
+    lats = [tess.build(*dev(xyz), (w.n,) * 3) for xyz in snaps]
+    imgs, st = tess.project_batch(lats, views, stats=True)
+    torch.cuda.synchronize()
+    print(f"batched: {len(lats)} x {len(views)} images in {st['ms']:.0f} ms, overflow {st['overflow']}, "
+          f"tile {st['tile_rows']} x {st['tile_cols']}", flush=True)
+    px, py = g["px"], g["py"]
+    worst = 0.0
+    for k, (i, v) in enumerate(g["pairs"]):
+        got = imgs[int(i), int(v)].cpu().numpy()[py, px].astype(np.float64)
+        ref = g["values"][k]
+        # the floor for empty samples: 1e-6 of the window's mean column
+        # density with all the mass (M = 1) in view
+        tau = 1e-6 / (views[int(v)]["extent"][0] * views[int(v)]["extent"][1])
+        r = np.abs(got - ref) / np.maximum(np.abs(ref), tau)
+        worst = max(worst, float(r.max()))
+        assert r.max() <= PIX_TOL, (int(i), int(v), float(r.max()))
+    print(f"batched subset: worst sampled rel {worst:.3e}", flush=True)
 
 
 def test_stress_config_sampled_pixels(tess):

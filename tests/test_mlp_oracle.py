@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp
+import workloads as W
 
 
 @pytest.fixture(scope="module")
@@ -115,3 +116,80 @@ def test_training_reduces_loss_on_a_smooth_field():
 def test_minimal_image_range():
     d = np.array([-0.75, -0.5, -0.25, 0.0, 0.5, 0.75])
     np.testing.assert_allclose(mlp.minimal_image(d), [0.25, 0.5, -0.25, 0.0, 0.5, -0.25])
+
+
+# ------------------------------------------------------- bf16 operands
+def test_bf16_round_known_values_and_ties_to_even():
+    v = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 2.0 ** -9, 1.0 + 3 * 2.0 ** -9, -2.5, 0.0, 3.0e38])
+    got = mlp.bf16_round(v)
+    # bf16 keeps 7 stored bits: the spacing at 1 is 2^-7, so 1 + 2^-8 is the
+    # halfway point and rounds to the even neighbour, 1.0
+    assert got[0] == 1.0 and got[1] == 1.0 and got[2] == 1.0
+    assert got[3] == 1.0 + 2.0 ** -7      # above halfway: up
+    assert got[4] == -2.5 and got[5] == 0.0
+    assert np.isfinite(got[6]) and abs(got[6] - 3.0e38) / 3.0e38 < 2.0 ** -8
+
+
+def test_bf16_round_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    a = (rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000))).astype(np.float32)
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(mlp.bf16_round(a), ref)
+
+
+def test_bf16_forward_rounds_the_product_operands(setup):
+    # the activations the bf16 mode feeds to the products are bf16 values,
+    # and the output moves by about the operands' rounding (2^-9 relative)
+    q, target, B, p = setup
+    out64, _ = mlp.forward(p, q, B)
+    out16, (hs, _) = mlp.forward(p, q, B, operands="bf16")
+    for h in hs:
+        np.testing.assert_array_equal(h, mlp.bf16_round(h))
+    rel = np.linalg.norm(out16 - out64) / np.linalg.norm(out64)
+    assert 1e-5 < rel < 3e-2, rel
+
+
+# ------------------------------------------------------------ placement
+def test_barycentric_coordinates_in_the_table():
+    rng = np.random.default_rng(7)
+    p = rng.uniform(0, 1, size=(5000, 3))
+    tet, lam = mlp.barycentric_in_table(p)
+    assert np.all(tet >= 0)
+    np.testing.assert_allclose(lam.sum(axis=1), 1.0, atol=1e-12)
+    assert lam.min() >= -1e-12
+    rec = np.zeros_like(p)
+    for m in range(4):
+        corners = np.array([mlp.corner_offset(mlp.TET_TABLE[t][m]) for t in tet])
+        rec += lam[:, m:m + 1] * corners
+    np.testing.assert_allclose(rec, p, atol=1e-12)
+
+
+def test_placement_of_an_undisplaced_lattice():
+    # raw with s = 0 and hybrid with any constant s put every fine tracer at
+    # its Lagrangian point; coarse tracers keep their data
+    n, r = 4, 3
+    xyz = [np.asarray(a) for a in W.undisplaced(n)]
+    q = mlp.fine_points((n, n, n), r).astype(np.float64)
+    raw = mlp.place(xyz, (n, n, n), r, np.zeros_like(q))
+    np.testing.assert_allclose(raw, q, atol=1e-7)
+    s = np.full_like(q, 0.123)
+    hyb = mlp.place(xyz, (n, n, n), r, s, s_coarse=np.full((n ** 3, 3), 0.123))
+    np.testing.assert_allclose(hyb, q, atol=2e-7)
+
+
+def test_hybrid_placement_with_zero_network_is_the_affine_map():
+    # s = 0: the residuals are the coarse positions minus their points, so a
+    # fine tracer lands on the affine map of its coarse tetrahedron
+    n, r = 5, 2
+    xyz = W.zeldovich(n, 2, 1.0)
+    q = mlp.fine_points((n, n, n), r).astype(np.float64)
+    got = mlp.place(xyz, (n, n, n), r, np.zeros_like(q), s_coarse=np.zeros((n ** 3, 3)))
+    # the midpoint of coarse edge 0-1 of cube (1, 2, 3) is fine tracer (3, 4, 6)
+    f = n * r
+    fid = 3 + f * (4 + f * 6)
+    c0 = 1 + n * (2 + n * 3)
+    c1 = 2 + n * (2 + n * 3)
+    X = np.stack([np.asarray(a, dtype=np.float64) for a in xyz], axis=1)
+    mid = X[c0] + 0.5 * mlp.minimal_image(X[c1] - X[c0])
+    np.testing.assert_allclose(got[fid], mlp.wrap_f32(mid, 1.0), atol=1e-7)

@@ -266,3 +266,28 @@ def workload_views(w: Workload) -> List[Dict]:
     if w.n_views == 1:
         return [z_view(w.width, w.height)]
     return [rotated_view(r, w.width, w.height) for r in random_rotations(w.n_views)]
+
+
+# --------------------------------------------------------------------------
+# refinement network inputs (random draws only)
+# --------------------------------------------------------------------------
+NET_WIDTH, NET_FREQ, NET_DEPTH = 128, 64, 4
+
+
+def rff_frequencies(sigma: float, seed: int) -> np.ndarray:
+    """(64, 3) N(0, sigma^2) draws rounded to integers, float32."""
+    rng = np.random.default_rng(seed)
+    return np.rint(rng.normal(0.0, sigma, size=(NET_FREQ, 3))).astype(np.float32)
+
+
+def network_params(seed: int, out_scale: float = 1.0) -> np.ndarray:
+    """Flat FP32 parameters W1, b1, ..., W4, b4, W5, b5 (rows = outputs),
+    uniform in +-1/sqrt(fan_in); the output layer's scaled by out_scale."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    dims = [(NET_WIDTH, 2 * NET_FREQ)] + [(NET_WIDTH, NET_WIDTH)] * (NET_DEPTH - 1) + [(3, NET_WIDTH)]
+    for i, (o, n) in enumerate(dims):
+        k = 1.0 / math.sqrt(n) * (out_scale if i == NET_DEPTH else 1.0)
+        parts.append(rng.uniform(-k, k, size=o * n))
+        parts.append(rng.uniform(-k, k, size=o))
+    return np.concatenate(parts).astype(np.float32)

@@ -109,11 +109,13 @@ def host_cores():
 def cpu_baseline(xyz, w, view, full_fragments: float):
     """The FP64 oracle on a bounded sample of the same workload (test harness code).
 
-    The oracle's region mode (every tetrahedron's setup, then exact per-pixel
-    ray clipping of the crop's pixels, FP64, OpenMP over row bands) on a
-    square crop at the image centre, on all the host cores this process may
-    use.  A small crop calibrates the rate; the timed crop is sized for about
-    args.cpu_seconds.  The full image's time is extrapolated per fragment."""
+    The oracle's region mode (a first pass sets up every tetrahedron, then
+    exact per-pixel ray clipping of the crop's pixels, FP64, OpenMP over row
+    bands) on square crops at the image centre, on all the host cores this
+    process may use.  Two crops give the fixed cost of the first pass and the
+    cost per fragment; the larger is sized for about args.cpu_seconds of
+    clipping.  The full image's time is the fixed cost plus its fragments at
+    that rate."""
     import oracle
     threads, host = host_cores()
     dims = (w.n,) * 3
@@ -124,28 +126,35 @@ def cpu_baseline(xyz, w, view, full_fragments: float):
         crop = (x0, y0, min(side, w.width), min(side, w.height))
         t0 = time.perf_counter()
         _, st = oracle.project_region(*xyz, dims, view, crop=crop, nthreads=threads)
-        return time.perf_counter() - t0, st, crop
+        return time.perf_counter() - t0, st["fragments"], crop
 
-    t_probe, st_probe, _ = run(16)
-    rate = st_probe["fragments"] / max(t_probe, 1e-3)
-    want = rate * args.cpu_seconds
-    side = 16
-    while side < min(w.width, w.height) and full_fragments * (2 * side) ** 2 / (w.width * w.height) <= want:
+    ta, fa, _ = run(32)
+    tb, fb, _ = run(64)
+    rate = (fb - fa) / max(tb - ta, 1e-3)          # fragments per second, marginal
+    side = 64
+    while 2 * side <= min(w.width, w.height) and full_fragments * (2 * side) ** 2 / (w.width * w.height) <= \
+            rate * args.cpu_seconds:
         side *= 2
-    t, st, crop = run(side)
-    full_s = t * full_fragments / max(st["fragments"], 1)
+    if side > 64:
+        tb, fb, _ = run(side)
+        rate = (fb - fa) / max(tb - ta, 1e-3)
+    fixed = max(ta - fa / rate, 0.0)
+    full_s = fixed + full_fragments / rate
     return {
         "value": w.tets / full_s,
         "unit": "tets/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"FP64 oracle, region mode, {threads} threads: crop {crop[2]}x{crop[3]} at ({crop[0]}, "
-                   f"{crop[1]}) of the {w.width}x{w.height} image of the same lattice ({st['fragments']:.3e} "
-                   f"fragments, {t:.1f} s including the setup of all {w.tets} tetrahedra); the full image "
-                   f"({full_fragments:.3e} fragments) extrapolated per fragment: {full_s:.0f} s"),
-        "fragments_per_s": st["fragments"] / t,
-        "ns_per_fragment_per_core": t * threads / max(st["fragments"], 1) * 1e9,
-        "seconds": t,
+        "sample": (f"FP64 oracle, region mode, {threads} threads: centre crops 32^2 ({fa:.3e} fragments, "
+                   f"{ta:.1f} s) and {side}^2 ({fb:.3e} fragments, {tb:.1f} s) of the {w.width}x{w.height} "
+                   f"image of the same lattice; fixed cost (setup of all {w.tets} tetrahedra) {fixed:.1f} s, "
+                   f"then {rate:.3e} fragments/s; the full image ({full_fragments:.3e} fragments) would take "
+                   f"{full_s:.0f} s"),
+        "fragments_per_s": rate,
+        "ns_per_fragment_per_core": threads / rate * 1e9,
+        "fixed_s": fixed,
+        "full_image_s": full_s,
+        "seconds": ta + tb,
         "host": host,
     }
 
@@ -416,17 +425,20 @@ def main():
     stream = torch.cuda.current_stream()
 
     tune = tess.make_tune(args.tile_rows, args.tile_cols, args.chunk, args.block)
+    # the first call counts fragments (untimed); the timed calls take the
+    # kernel times with HIP events on the stream and skip the count
     _, st0 = tess.project(lat, view, out=out, tune=tune, stats=True)
     frags, spans, kinks = st0["fragments"], st0["spans"], st0["kinks"]
+    timed_tune = tess.make_tune(args.tile_rows, args.tile_cols, args.chunk, args.block, counts=False)
     for _ in range(args.warmup):
-        tess.project(lat, view, out=out, tune=tune)
+        tess.project(lat, view, out=out, tune=timed_tune)
     torch.cuda.synchronize()
 
     per_step = []
     kernel = {"setup_ms": 0.0, "bin_ms": 0.0, "raster_ms": 0.0, "finalize_ms": 0.0}
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        _, st = tess.project(lat, view, out=out, tune=tune, stats=True)
+        _, st = tess.project(lat, view, out=out, tune=timed_tune, stats=True)
         per_step.append(st["ms"])
         for k in kernel:
             kernel[k] += st[k] / args.steps

@@ -192,7 +192,10 @@ typedef struct {
     int32_t chunk;          /* tile-list entries per raster work item (>= 64)     */
     int32_t block;          /* raster work-group size: 256, 512 or 1024          */
     int32_t form;           /* tess_form                                          */
-    int32_t reserved;       /* must be 0                                          */
+    int32_t no_counts;      /* 1: with stats, the edge form's raster skips the
+                               fragment count (tess_stats.fragments is then 0);
+                               timings and the other counters are kept.  Without
+                               stats fragments are never counted               */
     uint64_t pair_capacity; /* (record, tile) pairs the tile lists may hold; an
                                image with more is drawn by the overflow raster
                                (correct, much slower).  0: learned per lattice
@@ -255,6 +258,31 @@ typedef struct {
  */
 tess_status tess_project(tess_lattice lat, const tess_view *view, const tess_tune *tune,
                          float *image, tess_stats *stats, void *stream);
+
+/*
+ * tess_project for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * image, computed by the same kernels, but every device buffer is carved out
+ * of a fixed scratch array of the library (128 MiB per device, allocated
+ * when the library's code is loaded on that device and held until the
+ * process ends), and the call allocates nothing, device or host: no HIP
+ * allocation, no events, no streams.  It only enqueues kernels on `stream`
+ * and never waits for the device.  What tess_project's workspace would hold
+ * for this lattice and view must fit the scratch (about a 40^3 lattice in
+ * the edge form, 52^3 drawn per tetrahedron, with images of a few
+ * megapixels); the (record, tile) pair list takes the rest, and an image
+ * with more pairs is drawn by the overflow raster (same result, slower).
+ * The caller passes the inputs (the handle) and the output (image).  Every
+ * call on a device shares that device's scratch, which keeps the last
+ * call's contents: calls that overlap on one device (other streams or
+ * threads) race and must be ordered by the caller.  No statistics.
+ *   tune : host, nullable; pair_capacity (if set) caps the pair list below
+ *          what fits, no_counts is ignored.
+ * Errors: as tess_project; TESS_ECAPACITY when the lattice and view do not
+ * fit the scratch.
+ */
+tess_status tess_project_noalloc(tess_lattice lat, const tess_view *view, const tess_tune *tune,
+                                 float *image, void *stream);
 
 /*
  * Projects n_snaps lattices (same dims) through n_views views of the same

@@ -19,10 +19,9 @@ kernels and shares nothing with it.
 
 Precision.  Everything is FP64.  The network's products are specified with
 bf16 operands and wide accumulation, so ``forward(..., operands="bf16")``
-rounds exactly the operands of the products to bf16 (the features, the four
-hidden weight matrices and the hidden activations that feed the next
-product) and still accumulates in FP64; biases and the output layer's
-weights stay as given.
+rounds exactly the operands of the products to bf16 (the features, the five
+weight matrices and the hidden activations that feed the next product) and
+still accumulates in FP64; the biases stay as given.
 
 Placement of the refined lattice (r-fold sub-lattice of an N^3 lattice):
 fine tracer (I, J, K) has the Lagrangian point q = (I, J, K) / (r N); the
@@ -108,7 +107,7 @@ def forward(p: Dict[str, np.ndarray], q: np.ndarray, B: np.ndarray, operands: st
         zs.append(z)
         h = rnd(gelu(z))
         hs.append(h)
-    out = h @ p["W5"].T + p["b5"]
+    out = h @ rnd(p["W5"]).T + p["b5"]
     return out, (hs, zs)
 
 

@@ -54,7 +54,7 @@ QUANTITIES = {"density": 0, "unit": 1, "density2": 2}
 class TessTune(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("no_counts", ctypes.c_int32),
                 ("pair_capacity", ctypes.c_uint64)]
 
 
@@ -135,6 +135,7 @@ def _load():
     L.tess_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, vp]
     L.tess_lattice_positions.argtypes = [vp, vp, vp, vp, vp]
+    L.tess_project_noalloc.argtypes = [vp, P(TessView), P(TessTune), vp, vp]
     L.tess_last_error.argtypes = []
     L.tess_last_error.restype = ctypes.c_char_p
     L.tess_version.argtypes = []
@@ -143,7 +144,8 @@ def _load():
     L.tess_struct_size.restype = ctypes.c_uint64
     for f in (L.tess_build_desc_default, L.tess_build, L.tess_project, L.tess_project_batch,
               L.tess_check_view, L.tess_check_build_desc, L.tess_refine_desc_default,
-              L.tess_refine, L.tess_mlp_loss_grad, L.tess_mlp_adam, L.tess_lattice_positions):
+              L.tess_refine, L.tess_mlp_loss_grad, L.tess_mlp_adam, L.tess_lattice_positions,
+              L.tess_project_noalloc):
         f.restype = ctypes.c_int
     return L
 
@@ -154,7 +156,7 @@ _lib = _load()
 EXPORTS = ("tess_build_desc_default", "tess_build", "tess_free", "tess_project",
            "tess_project_batch", "tess_check_view", "tess_check_build_desc",
            "tess_last_error", "tess_version", "tess_struct_size", "tess_refine_desc_default", "tess_refine",
-           "tess_mlp_loss_grad", "tess_mlp_adam", "tess_lattice_positions")
+           "tess_mlp_loss_grad", "tess_mlp_adam", "tess_lattice_positions", "tess_project_noalloc")
 
 
 def lib():
@@ -218,11 +220,13 @@ def make_view(view: Dict) -> TessView:
 
 
 def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int = 0,
-              form: str = "auto", pair_capacity: int = 0) -> TessTune:
-    """Raster parameters; 0 (and form "auto") means automatic."""
+              form: str = "auto", pair_capacity: int = 0, counts: bool = True) -> TessTune:
+    """Raster parameters; 0 (and form "auto") means automatic.  counts=False:
+    calls with stats skip the edge form's fragment count (timings only)."""
     t = TessTune()
     t.tile_rows, t.tile_cols, t.chunk, t.block = int(tile_rows), int(tile_cols), int(chunk), int(block)
     t.form = FORMS[form]
+    t.no_counts = 0 if counts else 1
     t.pair_capacity = int(pair_capacity)
     return t
 
@@ -314,6 +318,17 @@ def project(lat: Lattice, view: Dict, out=None, tune: Optional[TessTune] = None,
                            out.data_ptr(), ctypes.byref(st) if stats else None, _stream_handle(stream))
     _check(rc, "tess_project")
     return (out, st.as_dict()) if stats else out
+
+
+def project_noalloc(lat: Lattice, view: Dict, out, tune: Optional[TessTune] = None, stream=None):
+    """tess_project_noalloc into `out` (float32 CUDA tensor [H, W]); allocates nothing."""
+    v = make_view(view)
+    if not (out.is_cuda and out.dtype.itemsize == 4 and out.is_floating_point() and out.is_contiguous()
+            and out.numel() == v.width * v.height):
+        raise ValueError("out must be a contiguous CUDA float32 tensor of height*width elements")
+    _check(_lib.tess_project_noalloc(lat.handle, ctypes.byref(v), ctypes.byref(tune) if tune is not None else None,
+                                     out.data_ptr(), _stream_handle(stream)), "tess_project_noalloc")
+    return out
 
 
 def project_batch(lats: List[Lattice], views: List[Dict], out=None, tune: Optional[TessTune] = None,

@@ -103,6 +103,29 @@ struct Workspace {
     std::mutex mu;
 };
 
+// The device buffers one projection uses (a workspace's, or views into the
+// allocation-free projection's scratch).
+struct Bufs {
+    RecHead *head;
+    Payload *coef;
+    EdgePayload *ecoef;
+    double *kinks;
+    uint8_t *sil;
+    uint32_t *counts;
+    uint64_t *base;
+    uint64_t *scan;
+    uint32_t *tile_items;
+    WorkItem *items;
+    uint32_t *pairs;
+    double *acc;
+    DevCounters *counters;
+};
+
+Bufs bufs_of(Workspace &ws) {
+    return Bufs{ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p,
+                ws.tile_items.p, ws.items.p, ws.pairs.p, ws.acc.p, ws.counters.p};
+}
+
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
@@ -396,6 +419,7 @@ struct Plan {
     int Th, Tw, chunk, block;  // chunk 0: from the pair count
     int form;                  // tess_form
     unsigned long long cap;    // pair capacity; 0: learned
+    int counts;                // 0: a call with stats skips the edge raster's fragment count
 };
 
 // Default tiling: tiles of up to 512 columns with as many rows as the
@@ -414,6 +438,7 @@ Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     p.block = (tune && tune->block) ? tune->block : 1024;
     p.form = tune ? tune->form : TESS_FORM_AUTO;
     p.cap = tune ? (unsigned long long)tune->pair_capacity : 0ull;
+    p.counts = tune ? !tune->no_counts : 1;
     return p;
 }
 
@@ -517,48 +542,48 @@ tess_status ensure_back(Workspace &ws, int64_t ntiles, int chunk, unsigned long 
 }
 
 // Setup of one image; for q = 1 first the integral of q into slot->qsum.
-tess_status enqueue_setup(const Geometry &g, Workspace &ws, PlanOut *slot, hipStream_t s) {
+tess_status enqueue_setup(const Geometry &g, const Bufs &b, PlanOut *slot, hipStream_t s) {
     ViewParams vp = g.vp;
     if (vp.qpow == 0 && !vp.slab && !vp.splat && !vp.persp) {
         TESS_HIP(launch_zero(&slot->qsum, 1, s));
         TESS_HIP(launch_qsum(g.lp, vp, &slot->qsum, s));
         vp.qsum = &slot->qsum;
     }
-    vp.kinks = ws.kinks.p;
-    vp.sil = ws.sil.p;
-    TESS_HIP(launch_setup(g.lp, vp, ws.head.p, ws.coef.p, ws.counters.p, s));
-    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, ws.head.p, ws.ecoef.p, s));
+    vp.kinks = b.kinks;
+    vp.sil = b.sil;
+    TESS_HIP(launch_setup(g.lp, vp, b.head, b.coef, b.counters, s));
+    if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, b.head, b.ecoef, s));
     return TESS_OK;
 }
 
 // Setup, count, scan and totals of one image (no host synchronisation);
 // the totals flag *overflow when the pairs exceed cap.
-tess_status enqueue_front(const Geometry &g, Workspace &ws, PlanOut *slot, unsigned long long cap,
+tess_status enqueue_front(const Geometry &g, const Bufs &b, PlanOut *slot, unsigned long long cap,
                           unsigned int *overflow, hipStream_t s) {
-    tess_status st = enqueue_setup(g, ws, slot, s);
+    tess_status st = enqueue_setup(g, b, slot, s);
     if (st != TESS_OK) return st;
-    TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
-    TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));
-    TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, cap, slot, overflow, s));
+    TESS_HIP(launch_count(b.head, g.ntet, g.B, b.counts, s));
+    TESS_HIP(launch_scan(b.counts, b.base, g.nmat, b.scan, s));
+    TESS_HIP(launch_totals(b.counts, b.base, g.B, cap, slot, overflow, s));
     return TESS_OK;
 }
 
 // Work items, scatter, raster and finalize of one image into `image`, for at
 // most `cap` pairs (the buffers hold that many); an image with more pairs
 // gets no work items and is drawn by the overflow raster.
-tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigned long long cap,
-                         Workspace &ws, PlanOut *slot, float *image, hipStream_t s, hipEvent_t after_bin,
+tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigned long long cap, bool count,
+                         const Bufs &b, PlanOut *slot, float *image, hipStream_t s, hipEvent_t after_bin,
                          hipEvent_t after_raster) {
-    TESS_HIP(launch_plan(ws.counts.p, ws.base.p, g.B, chunk, cap, ws.tile_items.p, slot, s));
-    TESS_HIP(launch_items(ws.base.p, ws.tile_items.p, g.B, chunk, slot, ws.items.p, s));
-    TESS_HIP(launch_scatter(ws.head.p, g.ntet, g.B, ws.base.p, ws.pairs.p, cap, s));
-    TESS_HIP(launch_zero(ws.acc.p, g.npix, s));
+    TESS_HIP(launch_plan(b.counts, b.base, g.B, chunk, cap, b.tile_items, slot, s));
+    TESS_HIP(launch_items(b.base, b.tile_items, g.B, chunk, slot, b.items, s));
+    TESS_HIP(launch_scatter(b.head, g.ntet, g.B, b.base, b.pairs, cap, s));
+    TESS_HIP(launch_zero(b.acc, g.npix, s));
     if (after_bin) TESS_HIP(hipEventRecord(after_bin, s));
-    TESS_HIP(launch_raster(ws.head.p, ws.coef.p, ws.ecoef.p, ws.pairs.p, ws.items.p,
-                           max_items_for(g.ntiles, chunk, cap), slot, g.B, plan.block, ws.acc.p, ws.counters.p, s));
-    TESS_HIP(launch_raster_direct(ws.head.p, ws.coef.p, ws.ecoef.p, slot, cap, g.B, ws.acc.p, ws.counters.p, s));
+    TESS_HIP(launch_raster(b.head, b.coef, b.ecoef, b.pairs, b.items, max_items_for(g.ntiles, chunk, cap), slot,
+                           g.B, plan.block, count, b.acc, b.counters, s));
+    TESS_HIP(launch_raster_direct(b.head, b.coef, b.ecoef, slot, cap, g.B, b.acc, b.counters, s));
     if (after_raster) TESS_HIP(hipEventRecord(after_raster, s));
-    TESS_HIP(launch_finalize(ws.acc.p, g.B, image, s));
+    TESS_HIP(launch_finalize(b.acc, g.B, image, s));
     return TESS_OK;
 }
 
@@ -658,14 +683,15 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     if (st != TESS_OK) return st;
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
     TESS_HIP(launch_zero((double *)ws.counters.p, sizeof(DevCounters) / sizeof(double), s));
-    st = enqueue_setup(g, ws, ws.plan.p, s);
+    const Bufs b = bufs_of(ws);
+    st = enqueue_setup(g, b, ws.plan.p, s);
     if (st != TESS_OK) return st;
     if (stats) TESS_HIP(hipEventRecord(ws.ev[1], s));
     TESS_HIP(launch_count(ws.head.p, g.ntet, g.B, ws.counts.p, s));
     TESS_HIP(launch_scan(ws.counts.p, ws.base.p, g.nmat, ws.scan.p, s));
     TESS_HIP(launch_totals(ws.counts.p, ws.base.p, g.B, cap, ws.plan.p, nullptr, s));
-    st = enqueue_back(g, plan, chunk, cap, ws, ws.plan.p, image, s, stats ? ws.ev[2] : nullptr,
-                      stats ? ws.ev[3] : nullptr);
+    st = enqueue_back(g, plan, chunk, cap, stats != nullptr && plan.counts, b, ws.plan.p, image, s,
+                      stats ? ws.ev[2] : nullptr, stats ? ws.ev[3] : nullptr);
     if (st != TESS_OK) return st;
     if (!stats) return give_feedback(ws, ws.plan.p, 1, key, s);
     TESS_HIP(hipEventRecord(ws.ev[4], s));
@@ -712,7 +738,7 @@ tess_status check_project_args(tess_lattice L, const tess_view *v, const tess_tu
             return fail(TESS_EINVAL, "tune.block must be 0, 256, 512 or 1024");
         if (tune->form != TESS_FORM_AUTO && tune->form != TESS_FORM_PER_TETRAHEDRON && tune->form != TESS_FORM_EDGES)
             return fail(TESS_EINVAL, "tune.form must be 0 (automatic), 1 (per tetrahedron) or 2 (edges)");
-        if (tune->reserved != 0) return fail(TESS_EINVAL, "tune.reserved must be 0");
+        if (tune->no_counts != 0 && tune->no_counts != 1) return fail(TESS_EINVAL, "tune.no_counts must be 0 or 1");
     }
     return TESS_OK;
 }
@@ -862,7 +888,7 @@ tess_status count_all(const tess_lattice *snaps, int n_snaps, const tess_view *v
             Geometry g;
             st = make_geometry(snaps[i], &views[v], plan, g);
             if (st != TESS_OK) return st;
-            st = enqueue_front(g, ws, ws.plan.p + i * n_views + v, ~0ull, nullptr, s);
+            st = enqueue_front(g, bufs_of(ws), ws.plan.p + i * n_views + v, ~0ull, nullptr, s);
             if (st != TESS_OK) return st;
         }
     TESS_HIP(hipMemcpyAsync(ws.host_plan, ws.plan.p, sizeof(PlanOut) * (size_t)n_img, hipMemcpyDeviceToHost, s));
@@ -1034,10 +1060,11 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
                     Geometry g;
                     tess_status r = make_geometry(snaps[i], &views[v], t.plan, g);
                     if (r != TESS_OK) return r;
-                    r = enqueue_front(g, ws, ws.plan.p + k, t.cap, nullptr, c);
+                    r = enqueue_front(g, bufs_of(ws), ws.plan.p + k, t.cap, nullptr, c);
                     if (r != TESS_OK) return r;
-                    r = enqueue_back(g, t.plan, t.chunk, t.cap, ws, ws.plan.p + k, images + (size_t)k * img, c,
-                                     nullptr, nullptr);
+                    // the graph serves calls with and without stats: it counts
+                    r = enqueue_back(g, t.plan, t.chunk, t.cap, true, bufs_of(ws), ws.plan.p + k, images + (size_t)k * img,
+                                     c, nullptr, nullptr);
                     if (r != TESS_OK) return r;
                 }
             return TESS_OK;
@@ -1098,6 +1125,77 @@ extern "C" tess_status tess_project(tess_lattice L, const tess_view *v, const te
     if (st != TESS_OK) return st;
     std::lock_guard<std::mutex> lock(ws->mu);
     st = project_impl(L, v, choose_plan(v, tune), image, stats, s, *ws);
+    return st == TESS_OK ? ok() : st;
+}
+
+// ------------------------------------------- allocation-free projection
+namespace {
+// Hands out 256-byte aligned pieces of the scratch, front to back.
+struct Carve {
+    unsigned char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = reinterpret_cast<T *>(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+};
+}  // namespace
+
+extern "C" tess_status tess_project_noalloc(tess_lattice L, const tess_view *v, const tess_tune *tune,
+                                            float *image, void *stream) {
+    tess_status st = check_project_args(L, v, tune, image);
+    if (st != TESS_OK) return st;
+    int dev = 0;
+    TESS_HIP(hipGetDevice(&dev));
+    if (dev != L->device) return fail(TESS_EINVAL, "lattice lives on device %d, current device is %d", L->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    const Plan plan = choose_plan(v, tune);
+    Geometry g;
+    st = make_geometry(L, v, plan, g);
+    if (st != TESS_OK) return st;
+    void *sp = nullptr;
+    TESS_HIP(scratch_buffer(&sp));
+    // what tess_project's workspace holds for this image, then the pair list
+    // (and its work items) in all the room that is left
+    Carve c{static_cast<unsigned char *>(sp)};
+    Bufs b;
+    b.head = c.take<RecHead>((size_t)g.ntet);
+    b.coef = c.take<Payload>((size_t)(6 * g.lp.ncubes));
+    const int64_t nvert = (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2];
+    b.ecoef = g.vp.edges ? c.take<EdgePayload>((size_t)(g.ntet - 6 * g.lp.ncubes)) : nullptr;
+    b.kinks = g.vp.edges ? c.take<double>((size_t)(36 * nvert)) : nullptr;
+    b.sil = g.vp.edges ? c.take<uint8_t>((size_t)(36 * nvert)) : nullptr;
+    b.counts = c.take<uint32_t>((size_t)g.nmat);
+    b.base = c.take<uint64_t>((size_t)g.nmat);
+    b.scan = c.take<uint64_t>(scan_scratch_elems(g.nmat));
+    b.tile_items = c.take<uint32_t>((size_t)g.ntiles + 1);
+    b.acc = c.take<double>((size_t)g.npix);
+    PlanOut *slot = c.take<PlanOut>(1);
+    b.counters = c.take<DevCounters>(1);
+    const int chunk = plan.chunk ? plan.chunk : 1024;
+    const size_t fixed = (c.off + 255) & ~(size_t)255;
+    const size_t need = fixed + 512 + 16 * ((size_t)g.ntiles + 1) + 4 * 1024;
+    if (need > kScratchBytes)
+        return fail(TESS_ECAPACITY,
+                    "this lattice and view need %.1f MiB of scratch; the allocation-free projection has %.0f MiB "
+                    "(use tess_project)", need / 1048576.0, kScratchBytes / 1048576.0);
+    // room for cap pairs (4 B) and cap / chunk + ntiles work items (16 B)
+    const size_t room = kScratchBytes - fixed - 512 - 16 * ((size_t)g.ntiles + 1);
+    unsigned long long cap = (unsigned long long)(room / (4.0 + 16.0 / chunk));
+    if (plan.cap && plan.cap < cap) cap = plan.cap;
+    b.items = c.take<WorkItem>((size_t)max_items_for(g.ntiles, chunk, cap));
+    b.pairs = c.take<uint32_t>((size_t)cap);
+    if (c.off > kScratchBytes) return fail(TESS_ECAPACITY, "scratch layout overflow");  // not reached
+    TESS_HIP(launch_zero((double *)b.counters, sizeof(DevCounters) / sizeof(double), s));
+    st = enqueue_setup(g, b, slot, s);
+    if (st != TESS_OK) return st;
+    TESS_HIP(launch_count(b.head, g.ntet, g.B, b.counts, s));
+    TESS_HIP(launch_scan(b.counts, b.base, g.nmat, b.scan, s));
+    TESS_HIP(launch_totals(b.counts, b.base, g.B, cap, slot, nullptr, s));
+    st = enqueue_back(g, plan, chunk, cap, false, b, slot, image, s, nullptr, nullptr);
     return st == TESS_OK ? ok() : st;
 }
 

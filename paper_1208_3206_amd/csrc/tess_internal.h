@@ -225,9 +225,10 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);
 
 // Raster of the work items into the second-difference image acc[H][W];
 // max_items blocks are launched and those beyond plan->n_items return.
+// count = false: the edge form's raster skips the fragment count.
 hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePayload *ecoef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
-                         const BinParams &B, int block, double *acc, DevCounters *counters,
+                         const BinParams &B, int block, bool count, double *acc, DevCounters *counters,
                          hipStream_t stream);
 
 // Overflow raster: when plan->total_pairs > cap (the image's tile lists were
@@ -239,6 +240,12 @@ hipError_t launch_raster_direct(const RecHead *head, const Payload *coef, const 
 
 // Row-wise double prefix sum of acc -> image (FP32).
 hipError_t launch_finalize(const double *acc, const BinParams &B, float *image, hipStream_t stream);
+
+// Bytes of the allocation-free projection's scratch, a file-scope device
+// array (one per device, held until the process ends).
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+// Device address of the current device's scratch (taken once per device).
+hipError_t scratch_buffer(void **ptr);
 
 // Build-time helpers.
 hipError_t launch_check_finite(const float *x, const float *y, const float *z, int64_t n,

@@ -39,6 +39,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <mutex>
 
 namespace tess {
 
@@ -447,7 +448,7 @@ __device__ inline void wave_sync() {
 // LDS of one wavefront's class sort: kNumClasses counters, then 64 * kSortPer entries
 constexpr int kSortWords = kNumClasses + 64 * kSortPer;
 
-template <int TPB, int FORM>
+template <int TPB, int FORM, bool COUNT = true>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
                                                 const Payload *__restrict__ coef,
                                                 const EdgePayload *__restrict__ ecoef,
@@ -478,7 +479,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         if constexpr (FORM == kFormEdge) {
             // an edge record: its half line is all the raster reads
             if (id >= B.first_edge) {
-                frags += (int32_t)edge_pair(
+                frags += (int32_t)edge_pair<COUNT>(
                     ecoef[id - B.first_edge], B, tx0, ty0, n, rows,
                     [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
                     [&](int row, double a, double b) {
@@ -612,7 +613,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     }
 }
 
-template <int FORM>
+template <int FORM, bool COUNT = true>
 static void launch_raster_form(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
                                const uint32_t *pairs,
                                const WorkItem *items, uint64_t max_items, const PlanOut *plan,
@@ -620,22 +621,22 @@ static void launch_raster_form(const RecHead *head, const Payload *coef, const E
                                hipStream_t stream, size_t lds) {
     switch (block) {
         case 256:
-            hipLaunchKernelGGL((k_raster<256, FORM>), dim3((unsigned)max_items), dim3(256), lds, stream, head,
+            hipLaunchKernelGGL((k_raster<256, FORM, COUNT>), dim3((unsigned)max_items), dim3(256), lds, stream, head,
                                coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
             break;
         case 512:
-            hipLaunchKernelGGL((k_raster<512, FORM>), dim3((unsigned)max_items), dim3(512), lds, stream, head,
+            hipLaunchKernelGGL((k_raster<512, FORM, COUNT>), dim3((unsigned)max_items), dim3(512), lds, stream, head,
                                coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
             break;
         default:
-            hipLaunchKernelGGL((k_raster<1024, FORM>), dim3((unsigned)max_items), dim3(1024), lds, stream, head,
-                               coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
+            hipLaunchKernelGGL((k_raster<1024, FORM, COUNT>), dim3((unsigned)max_items), dim3(1024), lds, stream,
+                               head, coef, ecoef, pairs, items, plan, B, sorted, acc, counters);
     }
 }
 
 hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePayload *ecoef, const uint32_t *pairs,
                          const WorkItem *items, uint64_t max_items, const PlanOut *plan,
-                         const BinParams &B, int block, double *acc, DevCounters *counters,
+                         const BinParams &B, int block, bool count, double *acc, DevCounters *counters,
                          hipStream_t stream) {
     if (max_items == 0) return hipSuccess;
     if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
@@ -653,9 +654,12 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
     else if (B.form == kFormPersp)
         launch_raster_form<kFormPersp>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
                                        stream, lds);
+    else if (B.edges && count)
+        launch_raster_form<kFormEdge, true>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
+                                            counters, stream, lds);
     else if (B.edges)
-        launch_raster_form<kFormEdge>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
-                                      stream, lds);
+        launch_raster_form<kFormEdge, false>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
+                                             counters, stream, lds);
     else
         launch_raster_form<kFormPyramid>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
                                          counters, stream, lds);
@@ -817,6 +821,37 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const double *__restrict
 hipError_t launch_finalize(const double *acc, const BinParams &B, float *image, hipStream_t stream) {
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)B.H), dim3(kFinBlock), 0, stream, acc, B, image);
     return hipGetLastError();
+}
+
+// ------------------------------------------------- allocation-free scratch
+// The workspace of tess_project_noalloc: one array per device, allocated when
+// the library's code object is loaded on that device and held until the
+// process ends.  Host code must not pass `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory): scratch_buffer() returns its
+// device address, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_buffer(void **ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------ build helpers

@@ -36,8 +36,8 @@ hipError_t launch_out_fwd(const __bf16 *H, int64_t n, const float *W5, const flo
 hipError_t launch_out_bwd(const float *pred, const float *target, int64_t n, const __bf16 *H,
                           const float *Z, const float *W5, __bf16 *dZ, float *part, hipStream_t s);
 int64_t out_blocks(int64_t n);
-hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t count, float lr, float b1,
-                       float b2, float eps, int t, hipStream_t s);
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t count, double lr, double b1,
+                       double b2, double eps, int t, hipStream_t s);
 hipError_t launch_cast_weights(const float *master, __bf16 *Wb, __bf16 *WTb, hipStream_t s);
 
 }  // namespace mlp

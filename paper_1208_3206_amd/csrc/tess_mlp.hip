@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 namespace tess {
 namespace mlp {
 
@@ -310,24 +312,28 @@ int64_t out_blocks(int64_t n) { return (n + kOutBlk - 1) / kOutBlk; }
 
 // ----------------------------------------------------------------- Adam
 // In-place Adam on the FP32 master parameters (bias-corrected, step t >= 1).
+// a1 = 1 - b1, a2 = 1 - b2 and the bias corrections c = 1 - b^t come from
+// the host in FP64: in FP32 each difference cancels several digits (with
+// b2 = 0.999, 1 - b2^t at small t keeps only about 4 of them)
 __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int64_t count, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       const float *__restrict__ g, int64_t count, float lr, float b1, float a1, float b2,
+                       float a2, float eps, float c1, float c2) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
     const float gi = g[e];
-    const float mi = b1 * m[e] + (1.0f - b1) * gi;
-    const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[e] + a1 * gi;
+    const float vi = b2 * v[e] + a2 * gi * gi;
     m[e] = mi;
     v[e] = vi;
     w[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t count, float lr, float b1,
-                       float b2, float eps, int t, hipStream_t s) {
-    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, w, m, v, g,
-                       count, lr, b1, b2, eps, c1, c2);
+hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t count, double lr, double b1,
+                       double b2, double eps, int t, hipStream_t s) {
+    const double c1 = 1.0 - std::pow(b1, (double)t), c2 = 1.0 - std::pow(b2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, w, m, v, g, count,
+                       (float)lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps,
+                       (float)c1, (float)c2);
     return hipGetLastError();
 }
 

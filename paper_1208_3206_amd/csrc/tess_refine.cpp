@@ -197,7 +197,7 @@ extern "C" tess_status tess_mlp_adam(float *params, float *m, float *v, const fl
         TESS_HIP(hipMemcpyAsync(dm, m, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
         TESS_HIP(hipMemcpyAsync(dv, v, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
         TESS_HIP(hipMemcpyAsync(dg, grad, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
-        TESS_HIP(launch_adam(dp, dm, dv, dg, kParams, (float)lr, (float)beta1, (float)beta2, (float)eps, step, s));
+        TESS_HIP(launch_adam(dp, dm, dv, dg, kParams, lr, beta1, beta2, eps, step, s));
         TESS_HIP(hipMemcpyAsync(params, dp, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
         TESS_HIP(hipMemcpyAsync(m, dm, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
         TESS_HIP(hipMemcpyAsync(v, dv, sizeof(float) * kParams, hipMemcpyDeviceToHost, s));
@@ -299,9 +299,8 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
                 rep.loss_last = lsum / (double)nb;
             }
             const double c = 0.5 * (1.0 + std::cos(3.141592653589793 * (double)(step - 1) / std::max(1, d->steps - 1)));
-            const float lr = (float)(d->lr1 + (d->lr0 - d->lr1) * c);
-            TESS_HIP(launch_adam(net.master.p, net.m.p, net.v.p, net.grad.p, kParams, lr, 0.9f, 0.999f, 1e-8f,
-                                 step, s));
+            const double lr = d->lr1 + (d->lr0 - d->lr1) * c;
+            TESS_HIP(launch_adam(net.master.p, net.m.p, net.v.p, net.grad.p, kParams, lr, 0.9, 0.999, 1e-8, step, s));
             TESS_HIP(launch_cast_weights(net.master.p, net.Wb.p, net.WTb.p, s));
         }
         TESS_HIP(hipStreamSynchronize(s));

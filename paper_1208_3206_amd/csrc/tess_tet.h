@@ -1872,8 +1872,12 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
 // crossing) - (samples left of its entering crossing); each crossing adds
 // its terms once, in the copy and tile holding the column right of it, in
 // image columns plus (s + kx) W.  Returns the count as the bits of a signed
-// 32-bit value.
-template <typename Dep, typename Seam>
+// 32-bit value.  COUNT = false skips the fragment count (returns 0), and the
+// rows of a pair that needs no seam line then take a short loop: a crossing
+// at w (tile pixel-centre units) in column k = floor(w) adds D (1 - f) at
+// k + 1 and D f at k + 2, f = w - k; a crossing outside the tile's columns
+// is clamped into the padding cells, whose values are dropped.
+template <bool COUNT = true, typename Dep, typename Seam>
 TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int tx0, int ty0, int n, int rows,
                                   Dep &&dep, Seam &&seam, uint32_t &kinks) {
     // the box from the endpoints, as the record's head holds it, and the
@@ -1926,6 +1930,21 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int 
             double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
             const int len = max(r1 - r0 + 1, 0);
             kinks += (uint32_t)len;
+            if (!COUNT && !seamed) {
+                // w + 4 >= 0 for every crossing inside the tile's columns, so
+                // truncation is the floor there
+                double wb = w + 4.0;
+                const double top = (double)(n + 3);
+                for (int r = r0; r <= r1; ++r, wb += sl) {
+                    const int row = r + rshift;
+                    const int k4 = max((int)fmin(wb, top), 1);   // k + 4, k clamped to [-3, n - 1]
+                    const double f = wb - floor(wb);
+                    const double v2 = D * f;
+                    dep(row, k4 - 3, D - v2);
+                    dep(row, k4 - 2, v2);
+                }
+                continue;
+            }
             for (int r = r0; r <= r1; ++r, w += sl) {
                 const int row = r + rshift;
                 const double fw = floor(w);

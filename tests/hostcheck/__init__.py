@@ -41,7 +41,9 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
     image and the counters.  crease_div: footprints steeper than the mean
     pixel value / crease_div per pixel keep the line form (the library uses
     width / 64); 0 puts every footprint in line form.  edges: the library's
-    edge form for plain pyramids (False: every crease per tetrahedron)."""
+    edge form for plain pyramids (False: every crease per tetrahedron;
+    "no_counts": the edge form's raster without its fragment count, which is
+    then not comparable)."""
     P = ctypes.POINTER
     x, y, z = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, z))
     W, H = int(view["width"]), int(view["height"])
@@ -65,7 +67,8 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
                            1 if view.get("method", "tessellation") == "centroids" else 0,
                            1 if view.get("projection", "orthographic") == "perspective" else 0,
                            1 if view.get("method", "tessellation") == "hybrid" else 0,
-                           ctypes.c_double(float(view.get("lod_radius", 0.0))), 1 if edges else 0,
+                           ctypes.c_double(float(view.get("lod_radius", 0.0))),
+                           2 if edges == "no_counts" else (1 if edges else 0),
                            out64.ctypes.data_as(P(ctypes.c_double)),
                            out32.ctypes.data_as(P(ctypes.c_float)), st.ctypes.data_as(P(ctypes.c_longlong)))
     if rc != 0:

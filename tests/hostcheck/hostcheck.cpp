@@ -149,7 +149,10 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                     return persp ? raster_record<kFormPersp>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : splat ? raster_record<kFormSplat>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : slab ? raster_record<kFormFace>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                         : is_edge ? edge_pair(ecoef[id - B.first_edge], B, tx0, ty0, n, rows, dep, sl, kk)
+                         : is_edge ? (edges == 2 ? edge_pair<false>(ecoef[id - B.first_edge], B, tx0, ty0, n,
+                                                                     rows, dep, sl, kk)
+                                                 : edge_pair<true>(ecoef[id - B.first_edge], B, tx0, ty0, n,
+                                                                   rows, dep, sl, kk))
                          : V.edges ? raster_record<kFormEdge>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                                 : raster_record<kFormPyramid>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk);
                 };

@@ -31,8 +31,11 @@ def as_dict(flat):
 
 
 def reference(params_flat, B, q, target):
-    """FP64 oracle with the products' operands rounded to bf16, as the GPU takes them."""
+    """FP64 oracle with the products' operands rounded to bf16, as the GPU takes
+    them (the backward's products take the same bf16 weights)."""
     p = as_dict(params_flat)
+    for k in ("W1", "W2", "W3", "W4", "W5"):
+        p[k] = mlp.bf16_round(p[k])
     pred, cache = mlp.forward(p, q.astype(np.float64), B, operands="bf16")
     return mlp.loss(pred, target), mlp.backward(p, cache, pred, target), pred
 

@@ -272,3 +272,23 @@ def test_edge_form_equals_per_tetrahedron_form(wrap):
     ref, ost = O.project_region(*xyz, (n, n, n), view)
     assert np.abs(a - ref).max() < 1e-8 * np.abs(ref).max()
     assert sa["fragments"] == ost["fragments"]
+
+
+@pytest.mark.parametrize("wrap", [True, False])
+@pytest.mark.parametrize("rows,cols", [(8, 64), (32, 512), (3, 37), (1, 200)])
+def test_edge_form_short_loop_without_counts(wrap, rows, cols):
+    # the edge raster's loop without the fragment count (the library's
+    # default without stats): the same image as the counting loop and the
+    # oracle's, on a strongly shell-crossed lattice with many tetrahedra
+    # across the periodic seam
+    n = 24
+    xyz = W.zeldovich(n, 8, 8.0, seed=13)
+    view = W.z_view(192, 160) if wrap else W.rotated_view(W.random_rotations(1, seed=6)[0], 150, 130)
+    a, _, _ = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=rows, tile_cols=cols, edges=True)
+    c, _, _ = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=rows, tile_cols=cols, edges="no_counts")
+    assert np.abs(c - a).max() < 1e-9 * np.abs(a).max()
+    ref, _ = O.project_region(*xyz, (n, n, n), view)
+    # FP64 row sums: ~1e-12 at the ends of rows, also on empty pixels of the
+    # rotated window (the contract's 1e-4 against its 1e-6-of-the-mean floor)
+    assert np.abs(c - ref).max() < 1e-8 * np.abs(ref).max()
+    assert rel(c, ref) < 1e-4

@@ -200,6 +200,10 @@ typedef struct {
                                image with more is drawn by the overflow raster
                                (correct, much slower).  0: learned per lattice
                                and view shape from earlier calls' counts        */
+    uint64_t workspace_limit; /* bytes of device memory the library's workspace
+                               for this stream may hold after the call; a call
+                               that would grow it beyond returns TESS_ENOMEM
+                               before allocating anything.  0: no limit         */
 } tess_tune;
 
 typedef struct {

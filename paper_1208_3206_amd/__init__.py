@@ -55,7 +55,7 @@ class TessTune(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("no_counts", ctypes.c_int32),
-                ("pair_capacity", ctypes.c_uint64)]
+                ("pair_capacity", ctypes.c_uint64), ("workspace_limit", ctypes.c_uint64)]
 
 
 # tess_form by name (make_tune(form=...))
@@ -220,7 +220,8 @@ def make_view(view: Dict) -> TessView:
 
 
 def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int = 0,
-              form: str = "auto", pair_capacity: int = 0, counts: bool = True) -> TessTune:
+              form: str = "auto", pair_capacity: int = 0, counts: bool = True,
+              workspace_limit: int = 0) -> TessTune:
     """Raster parameters; 0 (and form "auto") means automatic.  counts=False:
     calls with stats skip the edge form's fragment count (timings only)."""
     t = TessTune()
@@ -228,6 +229,7 @@ def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int
     t.form = FORMS[form]
     t.no_counts = 0 if counts else 1
     t.pair_capacity = int(pair_capacity)
+    t.workspace_limit = int(workspace_limit)
     return t
 
 

@@ -420,6 +420,7 @@ struct Plan {
     int form;                  // tess_form
     unsigned long long cap;    // pair capacity; 0: learned
     int counts;                // 0: a call with stats skips the edge raster's fragment count
+    unsigned long long limit;  // workspace bytes allowed after the call; 0: no limit
 };
 
 // Default tiling: tiles of up to 512 columns with as many rows as the
@@ -439,6 +440,7 @@ Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     p.form = tune ? tune->form : TESS_FORM_AUTO;
     p.cap = tune ? (unsigned long long)tune->pair_capacity : 0ull;
     p.counts = tune ? !tune->no_counts : 1;
+    p.limit = tune ? (unsigned long long)tune->workspace_limit : 0ull;
     return p;
 }
 
@@ -513,6 +515,37 @@ struct Sizes {
     }
 };
 
+// Bytes the workspace would hold after sizing for z and (chunk, cap), with
+// n_plan PlanOut slots; checked against a tune's workspace_limit before any
+// allocation.
+unsigned long long max_items_for(int64_t ntiles, int chunk, unsigned long long cap);
+size_t workspace_bytes_after(const Workspace &ws, const Sizes &z, int chunk, unsigned long long cap, size_t n_plan) {
+    size_t b = 0;
+    b += ws.head.bytes_after((size_t)z.records) + ws.coef.bytes_after((size_t)z.tets);
+    if (z.edges)
+        b += ws.ecoef.bytes_after((size_t)z.edges) + ws.kinks.bytes_after((size_t)z.slots) +
+             ws.sil.bytes_after((size_t)z.slots);
+    else
+        b += ws.ecoef.cap * sizeof(EdgePayload) + ws.kinks.cap * sizeof(double) + ws.sil.cap;
+    b += ws.counts.bytes_after((size_t)z.nmat) + ws.base.bytes_after((size_t)z.nmat) +
+         ws.scan.bytes_after(scan_scratch_elems(z.nmat)) + ws.tile_items.bytes_after((size_t)z.ntiles + 1) +
+         ws.acc.bytes_after((size_t)z.npix) + ws.counters.bytes_after(1) + ws.overflow.bytes_after(1) +
+         ws.plan.bytes_after(n_plan);
+    b += ws.items.bytes_after((size_t)std::max<unsigned long long>(max_items_for(z.ntiles, chunk, cap), 1)) +
+         ws.pairs.bytes_after((size_t)std::max<unsigned long long>(cap, 1));
+    return b;
+}
+
+tess_status check_limit(const Workspace &ws, const Plan &plan, const Sizes &z, int chunk, unsigned long long cap,
+                        size_t n_plan) {
+    if (!plan.limit) return TESS_OK;
+    const size_t b = workspace_bytes_after(ws, z, chunk, cap, n_plan);
+    if (b > plan.limit)
+        return fail(TESS_ENOMEM, "the workspace would hold %.1f MiB, above tune.workspace_limit (%.1f MiB)",
+                    b / 1048576.0, plan.limit / 1048576.0);
+    return TESS_OK;
+}
+
 tess_status ensure_front(Workspace &ws, const Sizes &z) {
     TESS_HIP(ws.head.ensure((size_t)z.records));
     TESS_HIP(ws.coef.ensure((size_t)z.tets));
@@ -576,7 +609,7 @@ tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigne
                          hipEvent_t after_raster) {
     TESS_HIP(launch_plan(b.counts, b.base, g.B, chunk, cap, b.tile_items, slot, s));
     TESS_HIP(launch_items(b.base, b.tile_items, g.B, chunk, slot, b.items, s));
-    TESS_HIP(launch_scatter(b.head, g.ntet, g.B, b.base, b.pairs, cap, s));
+    TESS_HIP(launch_scatter(b.head, g.ntet, g.B, b.counts, b.base, b.pairs, cap, s));
     TESS_HIP(launch_zero(b.acc, g.npix, s));
     if (after_bin) TESS_HIP(hipEventRecord(after_bin, s));
     TESS_HIP(launch_raster(b.head, b.coef, b.ecoef, b.pairs, b.items, max_items_for(g.ntiles, chunk, cap), slot,
@@ -670,15 +703,17 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     if (st != TESS_OK) return st;
     Sizes z;
     z.add(g);
-    st = ensure_front(ws, z);
-    if (st != TESS_OK) return st;
-    TESS_HIP(ws.plan.ensure(1));
     take_feedback(ws, s);
     const std::string key = count_key(g);
     auto it = ws.learned.find(key);
     const bool known = it != ws.learned.end();
     const unsigned long long cap = plan.cap ? plan.cap : (known ? capacity_for(it->second) : first_guess(g));
     const int chunk = plan.chunk ? plan.chunk : auto_chunk(known ? it->second : cap / 2);
+    st = check_limit(ws, plan, z, chunk, cap, 1);
+    if (st != TESS_OK) return st;
+    st = ensure_front(ws, z);
+    if (st != TESS_OK) return st;
+    TESS_HIP(ws.plan.ensure(1));
     st = ensure_back(ws, g.ntiles, chunk, cap);
     if (st != TESS_OK) return st;
     if (stats) TESS_HIP(hipEventRecord(ws.ev[0], s));
@@ -830,6 +865,8 @@ std::map<std::string, Tuned> read_tune_cache(const char *path) {
         t.plan.block = (int)block;
         t.plan.form = (int)form;
         t.plan.cap = 0;
+        t.plan.counts = 1;
+        t.plan.limit = 0;
         t.chunk = (int)chunk;
         t.cap = cap;
         m[key] = t;
@@ -1012,6 +1049,8 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
         g_tuned[key] = t;
         if (const char *path = tune_cache_path()) write_tune_cache(path, key, t);
     }
+    // this call's workspace limit, whatever tuning the shape got
+    t.plan.limit = choose_plan(&views[0], tune).limit;
     // counts of an earlier call that overflowed raise the capacity
     take_feedback(ws, s);
     {
@@ -1032,7 +1071,9 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
             if (st != TESS_OK) return st;
             z.add(g);
         }
-    tess_status st = ensure_front(ws, z);
+    tess_status st = check_limit(ws, t.plan, z, t.chunk, t.cap, (size_t)n_img);
+    if (st != TESS_OK) return st;
+    st = ensure_front(ws, z);
     if (st != TESS_OK) return st;
     st = ensure_back(ws, z.ntiles, t.chunk, t.cap);
     if (st != TESS_OK) return st;

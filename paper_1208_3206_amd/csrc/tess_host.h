@@ -55,6 +55,12 @@ struct DevBuf {
         cap = want;
         return hipSuccess;
     }
+    // bytes held after ensure(n)
+    size_t bytes_after(size_t n) const {
+        if (n <= cap) return cap * sizeof(T);
+        const size_t want = std::max(n, (size_t)64);
+        return (want + want / 8) * sizeof(T);
+    }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;

@@ -78,6 +78,7 @@ struct BinParams {
     int32_t edges;           // 1: edge form (the lists hold edge records)
     uint32_t first_edge;     // edge form: id of the first edge record (6 cubes)
     int32_t seam;            // 1: edge form under wrap (tiles carry a seam line per row)
+    int32_t seam_copies;     // the raster's copies of each tile row's seam line (set at launch)
 };
 
 // Pair-list entries: the record id, with the pair's work class (0..31) in
@@ -216,9 +217,9 @@ hipError_t launch_items(const uint64_t *base, const uint32_t *tile_items, const 
                         int32_t chunk, const PlanOut *plan, WorkItem *items, hipStream_t stream);
 
 // Writes beyond pair_cap entries are dropped (memory safety if the count and
-// scatter passes ever disagreed).
-hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint64_t *base,
-                          uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream);
+// scatter passes ever disagreed).  counts: the count pass's matrix (read only).
+hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint32_t *counts,
+                          const uint64_t *base, uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream);
 
 // Clears n doubles (a kernel, so that the call can sit in a captured graph).
 hipError_t launch_zero(double *p, int64_t n, hipStream_t stream);

@@ -37,6 +37,7 @@
 // its cost is per (tetrahedron, row), not per covered pixel.
 #include "tess_tet.h"
 
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 #include <mutex>
@@ -149,28 +150,78 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
 // counters.  The order inside one segment's share of a tile list follows the
 // atomics; the raster's sums do not depend on it beyond rounding.  With
 // nkey > 1 each placed id carries the pair's work class in its top bits.
+//
+// The scatter stages a segment's ids in LDS, sorted by tile (a counting sort
+// on this segment's counts from the count pass), then copies each tile's run
+// to its place in the pair list: whole runs instead of single 4-byte writes
+// all over the list.  A segment with more pairs than the stage holds writes
+// its ids directly.
 constexpr int kBinBlock = 256;
+constexpr int kStage = 8192;      // staged pair ids per segment (32 KiB of LDS)
+
+// Exclusive scan of v over the block's kBinBlock threads (sh: kBinBlock / 64 + 1 words).
+__device__ inline uint32_t bin_block_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kBinBlock / 64; ++w) {
+        before += w < wave ? sh[w] : 0u;
+        all += sh[w];
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - v;
+}
 
 template <bool SCATTER>
 __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ head, int64_t ntet,
                                                    BinParams B, uint32_t *__restrict__ counts,
                                                    const uint64_t *__restrict__ base,
                                                    uint32_t *__restrict__ pairs,
-                                                   unsigned long long pair_cap) {
-    extern __shared__ uint32_t lds_bins[];  // per tile: count, or next slot relative to tile start
+                                                   unsigned long long pair_cap, int staged) {
+    extern __shared__ uint32_t lds_bins[];  // per tile: count, or next slot; then (staged) the stage
+    __shared__ uint32_t sh_scan[kBinBlock / 64 + 1];
     const int ntiles = B.ntx * B.nty;
     const int seg = blockIdx.x;
-    // scatter: each tile's counter starts at this segment's first slot, as an
-    // absolute position when every pair fits 32 bits (no base read per pair),
-    // else relative to the tile's start
-    const bool abs32 = SCATTER && pair_cap <= 0xffffffffull;
-    for (int t = threadIdx.x; t < ntiles; t += kBinBlock) {
-        if (SCATTER)
-            lds_bins[t] = abs32 ? (uint32_t)base[(int64_t)t * B.nseg + seg]
-                                : (uint32_t)(base[(int64_t)t * B.nseg + seg] - base[(int64_t)t * B.nseg]);
-        else
-            lds_bins[t] = 0;
+    uint32_t *stage = lds_bins + ntiles;
+    // scatter: each tile's counter starts at this segment's first slot: in the
+    // stage (its offset among this segment's pairs), or as an absolute
+    // position when every pair fits 32 bits (no base read per pair), else
+    // relative to the tile's start
+    bool use_stage = false;
+    if (SCATTER && staged) {
+        // this segment's pairs per tile (from the count pass), scanned
+        const int per = (ntiles + kBinBlock - 1) / kBinBlock;
+        const int t0 = threadIdx.x * per;
+        uint32_t mine = 0;
+        for (int k = 0; k < per; ++k)
+            if (t0 + k < ntiles) mine += counts[(int64_t)(t0 + k) * B.nseg + seg];
+        uint32_t total;
+        uint32_t run = bin_block_scan(mine, sh_scan, total);
+        use_stage = total <= (uint32_t)kStage;  // the same for the whole block
+        if (use_stage)
+            for (int k = 0; k < per; ++k)
+                if (t0 + k < ntiles) {
+                    const uint32_t c = counts[(int64_t)(t0 + k) * B.nseg + seg];
+                    lds_bins[t0 + k] = run;
+                    run += c;
+                }
     }
+    const bool abs32 = SCATTER && pair_cap <= 0xffffffffull;
+    if (!use_stage)
+        for (int t = threadIdx.x; t < ntiles; t += kBinBlock) {
+            if (SCATTER)
+                lds_bins[t] = abs32 ? (uint32_t)base[(int64_t)t * B.nseg + seg]
+                                    : (uint32_t)(base[(int64_t)t * B.nseg + seg] - base[(int64_t)t * B.nseg]);
+            else
+                lds_bins[t] = 0;
+        }
     __syncthreads();
     const int64_t t0 = (int64_t)seg * B.seg_len;
     const int64_t t1 = min(ntet, t0 + B.seg_len);
@@ -188,10 +239,28 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
                 const int tile = ty * B.ntx + (tr.sx + sx < B.ntx ? tr.sx + sx : tr.sx + sx - B.ntx);
                 const uint32_t slot = atomicAdd(&lds_bins[tile], 1u);
                 if (SCATTER) {
-                    const uint64_t pos = abs32 ? (uint64_t)slot : base[(int64_t)tile * B.nseg] + slot;
-                    if (pos < pair_cap) pairs[pos] = (uint32_t)id | tag;
+                    if (use_stage) {
+                        if (slot < (uint32_t)kStage) stage[slot] = (uint32_t)id | tag;
+                    } else {
+                        const uint64_t pos = abs32 ? (uint64_t)slot : base[(int64_t)tile * B.nseg] + slot;
+                        if (pos < pair_cap) pairs[pos] = (uint32_t)id | tag;
+                    }
                 }
             }
+        }
+    }
+    if (SCATTER && use_stage) {
+        // each wavefront copies whole tile runs: the run of tile t ends at
+        // lds_bins[t] (its cursor) and has counts[t][seg] entries
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int t = wave; t < ntiles; t += kBinBlock / 64) {
+            const uint32_t c = counts[(int64_t)t * B.nseg + seg];
+            if (c == 0) continue;
+            const uint32_t first = lds_bins[t] - c;
+            const uint64_t dst = base[(int64_t)t * B.nseg + seg];
+            for (uint32_t j = lane; j < c; j += 64)
+                if (dst + j < pair_cap) pairs[dst + j] = stage[first + j];
         }
     }
     if (!SCATTER) {
@@ -200,22 +269,26 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
     }
 }
 
-// one 32-bit LDS counter per tile, in both passes
-static size_t bin_lds_bytes(const BinParams &B) { return sizeof(uint32_t) * (size_t)B.ntx * B.nty; }
+// one 32-bit LDS counter per tile, in both passes; the scatter's stage
+// beside them while the counters leave room for it in 64 KiB
+static bool bin_staged(const BinParams &B) { return (size_t)B.ntx * B.nty + kStage <= 16384; }
+static size_t bin_lds_bytes(const BinParams &B, bool scatter) {
+    return sizeof(uint32_t) * ((size_t)B.ntx * B.nty + (scatter && bin_staged(B) ? kStage : 0));
+}
 
 hipError_t launch_count(const RecHead *head, int64_t ntet, const BinParams &B, uint32_t *counts,
                         hipStream_t stream) {
-    const size_t lds = bin_lds_bytes(B);
+    const size_t lds = bin_lds_bytes(B, false);
     hipLaunchKernelGGL((k_bin<false>), dim3(B.nseg), dim3(kBinBlock), lds, stream, head, ntet, B, counts,
-                       (const uint64_t *)nullptr, (uint32_t *)nullptr, 0ull);
+                       (const uint64_t *)nullptr, (uint32_t *)nullptr, 0ull, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint64_t *base,
-                          uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream) {
-    const size_t lds = bin_lds_bytes(B);
+hipError_t launch_scatter(const RecHead *head, int64_t ntet, const BinParams &B, const uint32_t *counts,
+                          const uint64_t *base, uint32_t *pairs, unsigned long long pair_cap, hipStream_t stream) {
+    const size_t lds = bin_lds_bytes(B, true);
     hipLaunchKernelGGL((k_bin<true>), dim3(B.nseg), dim3(kBinBlock), lds, stream, head, ntet, B,
-                       (uint32_t *)nullptr, base, pairs, pair_cap);
+                       const_cast<uint32_t *>(counts), base, pairs, pair_cap, bin_staged(B) ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -467,9 +540,14 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     // fall outside the tile, so that the raster needs no bounds tests
     const int stride = B.Tw + 2 * kPad;
     const int tsize = B.Th * stride;
-    // then (edge form under wrap) per tile row the seam line a + b j (a, then b)
+    // then (edge form under wrap) per tile row the seam line a + b j, in
+    // seam_copies copies (lane t adds to copy t % seam_copies: the lanes of a
+    // 16-lane group draw 16 neighbouring edges over the same rows, and adds
+    // of one instruction to one cell are serialised); a values, then b
     double *sSeam = sA + tsize;
-    const int nseam = B.seam ? 2 * B.Th : 0;
+    const int nsc = B.seam ? B.seam_copies : 0;
+    const int nseam = 2 * B.Th * nsc;
+    const int sc = nsc ? (int)(threadIdx.x % (unsigned)nsc) : 0;
     for (int i = threadIdx.x; i < tsize + nseam; i += TPB) sA[i] = 0.0;
     __syncthreads();
     long long frags = 0;  // edge records add signed terms
@@ -483,8 +561,8 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                     ecoef[id - B.first_edge], B, tx0, ty0, n, rows,
                     [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
                     [&](int row, double a, double b) {
-                        atomicAdd(&sSeam[row], a);
-                        atomicAdd(&sSeam[B.Th + row], b);
+                        atomicAdd(&sSeam[row * nsc + sc], a);
+                        atomicAdd(&sSeam[(B.Th + row) * nsc + sc], b);
                     },
                     kinks);
                 return;
@@ -496,8 +574,8 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             h, coef[id].c, B, tx0, ty0, n, rows,
             [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
             [&](int row, double a, double b) {
-                atomicAdd(&sSeam[row], a);
-                atomicAdd(&sSeam[B.Th + row], b);
+                atomicAdd(&sSeam[row * nsc + sc], a);
+                atomicAdd(&sSeam[(B.Th + row) * nsc + sc], b);
             },
             spans, kinks);
     };
@@ -573,7 +651,40 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             const uint32_t ns = TPB / 16, g = threadIdx.x >> 4, q = threadIdx.x & 15u;
             const uint32_t C = ((it.count + ns - 1) / ns + 15u) & ~15u;
             const uint32_t g0 = g * C, g1 = min(it.count, g0 + C);
-            for (uint32_t e = g0 + q; e < g1; e += 16) one(pairs[it.first + e] & idmask);
+            // First the edge records.  A pair's id and payload are two
+            // dependent loads; the next pair's are issued before this one is
+            // drawn, so that they arrive while it is (one wavefront per SIMD
+            // quarter has too little other work to hide them otherwise).
+            auto id_at = [&](uint32_t e) { return e < g1 ? pairs[it.first + e] : 0xffffffffu; };
+            auto is_edge = [&](uint32_t id) { return id < B.ntet && id >= B.first_edge; };
+            auto dep = [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); };
+            auto seam = [&](int row, double a, double b) {
+                atomicAdd(&sSeam[row * nsc + sc], a);
+                atomicAdd(&sSeam[(B.Th + row) * nsc + sc], b);
+            };
+            uint32_t e = g0 + q;
+            uint32_t id = id_at(e), idn = id_at(e + 16);
+            EdgePayload P{};
+            if (is_edge(id)) P = ecoef[id - B.first_edge];
+            // the first payload has arrived before the loop: the loop then
+            // waits only for the loads it issued itself, at its end (without
+            // this the wait before each pair's first use also takes the next
+            // pair's loads)
+            __builtin_amdgcn_s_waitcnt(0);
+            for (; e < g1; e += 16) {
+                const uint32_t idnn = id_at(e + 32);
+                EdgePayload Pn{};
+                if (is_edge(idn)) Pn = ecoef[idn - B.first_edge];
+                if (is_edge(id)) frags += (int32_t)edge_pair<COUNT>(P, B, tx0, ty0, n, rows, dep, seam, kinks);
+                id = idn;
+                idn = idnn;
+                P = Pn;
+            }
+            // then the tetrahedra that kept their own records
+            for (uint32_t e2 = g0 + q; e2 < g1; e2 += 16) {
+                const uint32_t id2 = pairs[it.first + e2];
+                if (id2 < B.first_edge) one(id2);
+            }
         } else
         for (uint32_t e = e0; e < e1; e += kIdBurst) {
             // the next ids of the slice in one burst: one fetch of their cache
@@ -598,8 +709,12 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         if (c < n && v != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + tx0 + c], v);
     }
     // the seam lines: a at column 0 and b - a at column 1 of the second differences
-    for (int r = threadIdx.x; r < (B.seam ? rows : 0); r += TPB) {
-        const double a = sSeam[r], b = sSeam[B.Th + r];
+    for (int r = threadIdx.x; r < (nsc ? rows : 0); r += TPB) {
+        double a = 0.0, b = 0.0;
+        for (int c = 0; c < nsc; ++c) {
+            a += sSeam[r * nsc + c];
+            b += sSeam[(B.Th + r) * nsc + c];
+        }
         if (a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W], a);
         if (B.W > 1 && b - a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + 1], b - a);
     }
@@ -640,28 +755,33 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
                          hipStream_t stream) {
     if (max_items == 0) return hipSuccess;
     if (block != 256 && block != 512 && block != 1024) return hipErrorInvalidValue;
-    // the tile's accumulator, and beside it (when it fits) the wavefronts' class sorts
-    const size_t tile_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad + (B.seam ? 2 : 0));  // tile, seam lines
+    // the tile's accumulator, its seam lines (as many copies per row as fit,
+    // up to 16), and beside them (when they fit) the wavefronts' class sorts
+    BinParams Bl = B;
+    const size_t acc_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
+    const size_t row_seam = sizeof(double) * 2 * (size_t)B.Th;
+    Bl.seam_copies = B.seam ? (int)std::min<size_t>(16, std::max<size_t>(1, (kLdsBytes - acc_lds) / row_seam)) : 0;
+    const size_t tile_lds = acc_lds + row_seam * (size_t)Bl.seam_copies;
     const size_t sort_lds = sizeof(uint32_t) * (size_t)(block / 64) * kSortWords;
     const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;
     const size_t lds = tile_lds + (sorted ? sort_lds : 0);
-    if (B.form == kFormFace)
-        launch_raster_form<kFormFace>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+    if (Bl.form == kFormFace)
+        launch_raster_form<kFormFace>(head, coef, ecoef, pairs, items, max_items, plan, Bl, sorted, block, acc, counters,
                                       stream, lds);
     else if (B.form == kFormSplat)
-        launch_raster_form<kFormSplat>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+        launch_raster_form<kFormSplat>(head, coef, ecoef, pairs, items, max_items, plan, Bl, sorted, block, acc, counters,
                                        stream, lds);
     else if (B.form == kFormPersp)
-        launch_raster_form<kFormPersp>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc, counters,
+        launch_raster_form<kFormPersp>(head, coef, ecoef, pairs, items, max_items, plan, Bl, sorted, block, acc, counters,
                                        stream, lds);
     else if (B.edges && count)
-        launch_raster_form<kFormEdge, true>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
+        launch_raster_form<kFormEdge, true>(head, coef, ecoef, pairs, items, max_items, plan, Bl, sorted, block, acc,
                                             counters, stream, lds);
     else if (B.edges)
-        launch_raster_form<kFormEdge, false>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
+        launch_raster_form<kFormEdge, false>(head, coef, ecoef, pairs, items, max_items, plan, Bl, sorted, block, acc,
                                              counters, stream, lds);
     else
-        launch_raster_form<kFormPyramid>(head, coef, ecoef, pairs, items, max_items, plan, B, sorted, block, acc,
+        launch_raster_form<kFormPyramid>(head, coef, ecoef, pairs, items, max_items, plan, Bl, sorted, block, acc,
                                          counters, stream, lds);
     return hipGetLastError();
 }
@@ -728,8 +848,10 @@ __global__ void __launch_bounds__(256) k_raster_direct(const RecHead *__restrict
 hipError_t launch_raster_direct(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
                                 const PlanOut *plan, unsigned long long cap, const BinParams &B, double *acc,
                                 DevCounters *counters, hipStream_t stream) {
+    // a small grid (threads stride over the records): the launch costs next
+    // to nothing for the images that do not overflow
     const int64_t want = ((int64_t)B.ntet + 255) / 256;
-    const dim3 grid((unsigned)(want < 65536 ? (want > 0 ? want : 1) : 65536)), block(256);
+    const dim3 grid((unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048)), block(256);
     switch (B.form) {
         case kFormFace:
             hipLaunchKernelGGL(k_raster_direct<kFormFace>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,

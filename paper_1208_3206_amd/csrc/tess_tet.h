@@ -1240,16 +1240,19 @@ TESS_HD inline void span_geom(uint32_t flags, const double *cf, SpanGeom &G) {
     G.wall0 = 3u * (uint32_t)ng;
 }
 
-// One row of one record against one tile row: samples u = 0..n-1 at record
-// frame X = X0 + u, row centre Y; the image row spans u in (ulo, uhi) =
-// (-tx0 - 1/2, W - tx0 - 1/2).  cf: the record's coefficients (walls are read
-// from there).  Break points sit at their true positions, except that pieces
-// starting left of the image start at ulo; only the tile's own entries are
-// written: dep(j, v) adds v to A[j] for 0 <= j < n.  Returns the number of the
-// tile's samples with f > 0.
+// One row of one record against one tile row, evaluated in the record frame
+// (sample u = j at the record's column j, X = u + 1/2; row centre Y), so that
+// every tile computes the same break points: the tile's samples are
+// u = shift .. shift + n - 1, and the image row spans u in (ulo, uhi) (record
+// frame).  cf: the record's coefficients (walls are read from there).  Break
+// points sit at their true positions, except that pieces starting left of the
+// image start at ulo; only the tile's own entries are written: dep(j, v) adds
+// v to A[j] for the tile column 0 <= j < n.  Returns the number of the tile's
+// samples with f > 0.
 template <typename Dep>
-TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0, double Y, int n,
+TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, int shift, double Y, int n,
                                  double ulo, double uhi, Dep &&dep, uint32_t &kinks) {
+    constexpr double X0 = 0.5;
     double A[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) A[g] = G.a[g] + G.b[g] * X0 + G.c[g] * Y;  // G_g at sample u: A + b u
@@ -1284,7 +1287,8 @@ TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0,
     }
     if (!(ceil(uR) - floor(uL) > 1.0)) return 0;  // no sample in (uL, uR)
     // the tile's samples in (uL, uR)
-    const double span = ceil(fmin(uR, (double)n - 0.5)) - floor(fmax(uL, -0.5)) - 1.0;
+    const double dshift = (double)shift;
+    const double span = ceil(fmin(uR, dshift + (double)n - 0.5)) - floor(fmax(uL, dshift - 0.5)) - 1.0;
     double x[6];
 #pragma unroll
     for (int h = 0; h < 4; ++h)
@@ -1322,7 +1326,7 @@ TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0,
             const double J = (A[g] + G.b[g] * u) - (have ? pA + pB * u : 0.0);
             const double D = G.b[g] - (have ? pB : 0.0);
             const double fj = floor(u);
-            const int j = (int)fj + 1;
+            const int j = (int)fj + 1 - shift;
             const double v1 = J + D * ((fj + 1.0) - u);
             if (j >= 0 && j < n) dep(j, v1);
             if (j >= -1 && j + 1 < n) dep(j + 1, D - v1);
@@ -1338,7 +1342,7 @@ TESS_HD inline uint32_t row_span(const SpanGeom &G, const double *cf, double X0,
         const double u = pHi;
         const double J = -(pA + pB * u), D = -pB;
         const double fj = floor(u);
-        const int j = (int)fj + 1;
+        const int j = (int)fj + 1 - shift;
         const double v1 = J + D * ((fj + 1.0) - u);
         if (j >= 0 && j < n) dep(j, v1);
         if (j >= -1 && j + 1 < n) dep(j + 1, D - v1);
@@ -1366,12 +1370,13 @@ TESS_HD inline uint32_t raster_pair(const RecHead &h, const double *cf, const Bi
         const int ylo = max(ty0, by0 - ky * B.H), yhi = min(ty0 + rows - 1, by1 - ky * B.H);
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
-            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
-            const double ulo = -(double)tx0 - 0.5, uhi = (double)(B.W - tx0) - 0.5;
+            const int shift = tx0 + kx * B.W - bx0;  // record column of the tile's column 0
+            // the image row in the record frame
+            const double ulo = (double)(kx * B.W - bx0) - 0.5, uhi = (double)(B.W + kx * B.W - bx0) - 0.5;
             for (int y = ylo; y <= yhi; ++y) {
                 const double Y = (double)(y + ky * B.H - by0) + 0.5;
                 const int row = y - ty0;
-                frags += row_span(G, cf, X0, Y, n, ulo, uhi, [&](int j, double v) { dep(row, j, v); }, kinks);
+                frags += row_span(G, cf, shift, Y, n, ulo, uhi, [&](int j, double v) { dep(row, j, v); }, kinks);
                 ++spans;
             }
         }
@@ -1411,7 +1416,9 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
         if (rlo > rhi) continue;
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
-            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            // record column of the tile's column 0
+            const int shift = tx0 + kx * B.W - bx0;
+            const double X0 = (double)shift + 0.5;
             // record-frame x range whose kinks reach the tile (one pixel of margin)
             const double xl = left_edge ? -1e30 : X0 - 3.0, xr = X0 + (double)n + 1.0;
             spans += (uint32_t)(rhi - rlo + 1);
@@ -1480,27 +1487,32 @@ TESS_HD inline uint32_t crease_pair(const RecHead &h, const double *cf, const Bi
                     // rows right of the tile count its full width
                     acc = n * (sl > 0.0 ? q1 - r1 : r0 - q0);
                 }
-                // the crossing u = w relative to the tile's first pixel centre
-                // (small numbers: a footprint's kinks keep their relative
-                // positions to FP64 rounding of its box)
-                double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
-                // Fragments: an entering crossing has floor(u) + 1 samples left
-                // of it, a leaving one ceil(u) (a sample on the silhouette is
-                // outside). The column is taken in a frame shifted by
-                // kSampleEps, down for an entering crease and up for a leaving
-                // one: k = floor(u + s) and j = k + 1 is floor(u) + 1 or
-                // ceil(u), and the count is max(j, 0) (jlo <= 0). Any j next to
-                // the kink gives the same sum, since the deposits use the exact
-                // offset from column j: with t = k - u they are D (1 + t) at j
-                // and the rest of D at j + 1.
+                // the crossing u of row r in the record frame (pixel-centre
+                // units, u = j at the record's column j), computed from the row
+                // alone: every tile that draws it (its two entries may fall in
+                // two tiles) gets the same value, and a footprint's kinks keep
+                // their relative positions to the FP64 rounding of its box.
+                // Fragments: an entering crossing has floor(w) + 1 samples left
+                // of it in the tile frame (w = u - shift), a leaving one
+                // ceil(w) (a sample on the silhouette is outside). The column
+                // is taken in a frame shifted by kSampleEps, down for an
+                // entering crease and up for a leaving one: k = floor(w + s)
+                // and j = k + 1 is floor(w) + 1 or ceil(w), and the count is
+                // max(j, 0) (jlo <= 0). Any j next to the kink gives the same
+                // sum, since the deposits use the exact offset from column j:
+                // with t = k - w they are D (1 + t) at j and the rest of D at
+                // j + 1.
                 const double s_eps = enter ? kSampleEps : -kSampleEps;
+                const double cP = 0.5 - Py, xP = Px - 0.5;
                 const int len = max(r1 - r0 + 1, 0);
                 kinks += (uint32_t)len;
                 acc += len;
-                for (int r = r0; r <= r1; ++r, w += sl) {
+                double rv = (double)r0;
+                for (int r = r0; r <= r1; ++r, rv += 1.0) {
                     const int row = r + rshift;
-                    const int k = min(max((int)floor(w + s_eps), jlo - 1), n - 1);
-                    const double v1 = fma(D, (double)k - w, D);
+                    const double u = fma(rv + cP, sl, xP);
+                    const int k = min(max((int)floor(u + s_eps) - shift, jlo - 1), n - 1);
+                    const double v1 = fma(D, (double)(k + shift) - u, D);
                     dep(row, k + 1, v1);
                     dep(row, k + 2, D - v1);
                     acc += max(k, -1);
@@ -1560,12 +1572,18 @@ TESS_HD inline int upper_envelope(const double a[4], const double b[4], int nl, 
 // positions, pieces starting left of the image start at ulo. dep(j, v) takes
 // -2 <= j <= n + 1. Returns the tile's covered samples.
 template <typename Dep>
-TESS_HD inline uint32_t face_row(uint32_t flags, const double *cf, const BinParams &B, double X0,
+TESS_HD inline uint32_t face_row(uint32_t flags, const double *cf, const BinParams &B, int shift,
                                  double Y, int n, int jlo, double ulo, double uhi, Dep &&dep,
                                  uint32_t &kinks) {
+    // evaluated in the record frame (sample u = j at the record's column j,
+    // X = u + 1/2), so that every tile computes the same break points; the
+    // tile's samples are u = shift .. shift + n - 1, ulo and uhi bound the
+    // image row there
+    constexpr double X0 = 0.5;
+    const double dshift = (double)shift;
     double fa[4], fb[4], ba[4], bb[4];
     int nf = 0, nb = 0;
-    double uL = ulo, uR = uhi;  // tile frame
+    double uL = ulo, uR = uhi;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const uint32_t type = (flags >> (REC_FACE_TYPE_SHIFT + 2 * g)) & 3u;
@@ -1634,13 +1652,13 @@ TESS_HD inline uint32_t face_row(uint32_t flags, const double *cf, const BinPara
     const double L = fmax(zl, uL + X0), R = fmin(zr, uR + X0);
     const double Lu = L - X0, Ru = R - X0;
     if (!(ceil(Ru) - floor(Lu) > 1.0)) return 0;  // no sample in (L, R)
-    const double span = ceil(fmin(Ru, (double)n - 0.5)) - floor(fmax(Lu, -0.5)) - 1.0;
+    const double span = ceil(fmin(Ru, dshift + (double)n - 0.5)) - floor(fmax(Lu, dshift - 0.5)) - 1.0;
     const double q = cf[12];
     auto put = [&](double X, double J, double D) {
-        int j = (int)floor(X - X0) + 1;
+        int j = (int)floor(X - X0) + 1 - shift;  // tile column
         j = j > jlo ? j : jlo;
         j = j < n ? j : n;
-        const double v1 = J + D * (((double)j + X0) - X);
+        const double v1 = J + D * (((double)(j + shift) + X0) - X);
         dep(j, v1);
         dep(j + 1, D - v1);
         ++kinks;
@@ -1688,12 +1706,13 @@ TESS_HD inline uint32_t face_pair(const RecHead &h, const double *cf, const BinP
         const int ylo = max(ty0, by0 - ky * B.H), yhi = min(ty0 + rows - 1, by1 - ky * B.H);
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
-            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
-            const double ulo = -(double)tx0 - 0.5, uhi = (double)(B.W - tx0) - 0.5;
+            const int shift = tx0 + kx * B.W - bx0;  // record column of the tile's column 0
+            // the image row in the record frame
+            const double ulo = (double)(kx * B.W - bx0) - 0.5, uhi = (double)(B.W + kx * B.W - bx0) - 0.5;
             for (int y = ylo; y <= yhi; ++y) {
                 const double Y = (double)(y + ky * B.H - by0) + 0.5;
                 const int row = y - ty0;
-                frags += face_row(h.flags, cf, B, X0, Y, n, jlo, ulo, uhi,
+                frags += face_row(h.flags, cf, B, shift, Y, n, jlo, ulo, uhi,
                                   [&](int j, double v) { dep(row, j, v); }, kinks);
                 ++spans;
             }
@@ -1872,11 +1891,7 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
 // crossing) - (samples left of its entering crossing); each crossing adds
 // its terms once, in the copy and tile holding the column right of it, in
 // image columns plus (s + kx) W.  Returns the count as the bits of a signed
-// 32-bit value.  COUNT = false skips the fragment count (returns 0), and the
-// rows of a pair that needs no seam line then take a short loop: a crossing
-// at w (tile pixel-centre units) in column k = floor(w) adds D (1 - f) at
-// k + 1 and D f at k + 2, f = w - k; a crossing outside the tile's columns
-// is clamped into the padding cells, whose values are dropped.
+// 32-bit value.  COUNT = false skips the fragment count (returns 0).
 template <bool COUNT = true, typename Dep, typename Seam>
 TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int tx0, int ty0, int n, int rows,
                                   Dep &&dep, Seam &&seam, uint32_t &kinks) {
@@ -1907,7 +1922,8 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int 
         if (q0 > q1) continue;
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
-            const double X0 = (double)(tx0 + kx * B.W - bx0) + 0.5;
+            const int shift = tx0 + kx * B.W - bx0;  // record column of the tile's column 0
+            const double X0 = (double)shift + 0.5;
             const double xl = X0 - 3.0, xr = X0 + (double)n + 1.0;
             int r0 = q0, r1 = q1;
             if (Qx != Px) {
@@ -1923,56 +1939,52 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int 
             }
             // the wrap of each period group in this copy: s + kx; a crossing
             // may need the seam line only in a shifted copy, for a group
-            // with s != 0, or near the period's right end
+            // with s != 0, or within two columns of the period's right end
+            // (canonical position u >= W - 2; the edge's crossings lie
+            // between its endpoints, the rightmost at u = bx0 + max x - 1/2)
             const int wm = kx - 1, w0 = kx, wp = kx + 1;
-            const bool seamed = B.seam && (kx != 0 || Dm != 0.0 || Dp != 0.0 || tx0 + n > B.W - 3);
+            // the seam line of a crossing at canonical position u: the groups
+            // with s + kx = 1 add D (u - j), summed in A1; those with
+            // s + kx = 0 add -D (u - W + 2) (j + 1) when u >= W - 2, summed
+            // in A0 (the others add nothing)
+            const double A1 = kx == 0 ? Dp : kx == 1 ? D0 : kx == 2 ? Dm : 0.0;
+            const double A0 = kx == -1 ? Dp : kx == 0 ? D0 : kx == 1 ? Dm : 0.0;
+            // (in this copy a crossing's canonical position is its record
+            // position + bx0 - kx W; the edge's rightmost is at max x)
+            const bool near_end =
+                tx0 + n > B.W - 3 && (double)(bx0 - kx * B.W) + fmax(Px, Qx) - 0.5 >= (double)B.W - 2.0 - 1e-6;
+            const bool seamed = B.seam && (A1 != 0.0 || (A0 != 0.0 && near_end));
+            const double Wm2 = (double)B.W - 2.0;
             const int fwrap = B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
-            double w = (Px - X0) + ((double)r0 + 0.5 - Py) * sl;
+            // the crossing of row r in the record frame, from the row alone
+            // (the same in every tile that draws it; see crease_pair)
+            const double cP = 0.5 - Py, xP = Px - 0.5;
+            const double dshift = (double)shift;
             const int len = max(r1 - r0 + 1, 0);
             kinks += (uint32_t)len;
-            if (!COUNT && !seamed) {
-                // w + 4 >= 0 for every crossing inside the tile's columns, so
-                // truncation is the floor there
-                double wb = w + 4.0;
-                const double top = (double)(n + 3);
-                for (int r = r0; r <= r1; ++r, wb += sl) {
-                    const int row = r + rshift;
-                    const int k4 = max((int)fmin(wb, top), 1);   // k + 4, k clamped to [-3, n - 1]
-                    const double f = wb - floor(wb);
-                    const double v2 = D * f;
-                    dep(row, k4 - 3, D - v2);
-                    dep(row, k4 - 2, v2);
-                }
-                continue;
-            }
-            for (int r = r0; r <= r1; ++r, w += sl) {
+            double rv = (double)r0;
+            for (int r = r0; r <= r1; ++r, rv += 1.0) {
                 const int row = r + rshift;
-                const double fw = floor(w);
+                const double u_rec = fma(rv + cP, sl, xP);
+                const double fw = floor(u_rec) - dshift;  // the tile-frame column left of the crossing
                 const int k = min(max((int)fmin(fmax(fw, -4.0), (double)n), -3), n - 1);
-                const double v1 = fma(D, (double)k - w, D);
+                const double v1 = fma(D, (double)(k + shift) - u_rec, D);
                 dep(row, k + 1, v1);
                 dep(row, k + 2, D - v1);
-                if (fw >= -1.0 && fw <= (double)(n - 2)) {  // this copy and tile hold the crossing
+                // seam line and fragment count: only where this copy and tile
+                // hold the crossing (one loop for every lane: lanes on pairs
+                // that need neither skip this part, without a second loop)
+                if ((COUNT || seamed) && fw >= -1.0 && fw <= (double)(n - 2)) {
+                    const double w = u_rec - dshift;  // tile frame
                     if (seamed) {
                         const double u = (double)tx0 + w;  // canonical position
-                        double a = 0.0, b = 0.0;
-                        const double near = u >= Wd - 2.0 ? u - Wd + 2.0 : 0.0;
-                        const int ws[3] = {wm, w0, wp};
-                        const double Ds[3] = {Dm, D0, Dp};
-#pragma unroll
-                        for (int g = 0; g < 3; ++g) {
-                            if (ws[g] == 1) {
-                                a += Ds[g] * u;
-                                b -= Ds[g];
-                            } else if (ws[g] == 0) {
-                                a -= Ds[g] * near;
-                                b -= Ds[g] * near;
-                            }
-                        }
+                        const double near = fmax(u - Wm2, 0.0);
+                        const double a = A1 * u - A0 * near, b = -A1 - A0 * near;
                         if (a != 0.0 || b != 0.0) seam(row, a, b);
                     }
-                    if (count) {
-                        const int jl = tx0 + 1 + (int)floor(w - kSampleEps), je = tx0 + 1 + (int)floor(w + kSampleEps);
+                    if (COUNT && count) {
+                        const int jl = tx0 + 1 + (int)floor(u_rec - kSampleEps) - shift;
+                        const int je = tx0 + 1 + (int)floor(u_rec + kSampleEps) - shift;
                         frags += nlt * jl - net * je + fwrap;
                     }
                 }

@@ -693,6 +693,28 @@ def test_ids_scatter_and_permutation_check(tess):
         tess.build(*dev((xs, ys, zs)), (8, 8, 8), ids=torch.from_numpy(bad.astype(np.int64)).cuda())
 
 
+def test_workspace_limit_returns_enomem_before_allocating(tess):
+    # a host-set cap on the workspace (a fresh stream: an empty workspace):
+    # below what the call needs it fails with TESS_ENOMEM and allocates
+    # nothing; a limit above it gives the ordinary image
+    import torch
+    n = 16
+    xyz = W.zeldovich(n, 5, 4.0, seed=5)
+    lat = tess.build(*dev(xyz), (n, n, n))
+    view = W.z_view(128, 96)
+    s = torch.cuda.Stream()
+    free0 = torch.cuda.mem_get_info()[0]
+    with torch.cuda.stream(s):
+        with pytest.raises(tess.TessError) as err:
+            tess.project(lat, view, tune=tess.make_tune(workspace_limit=1 << 20))
+        assert err.value.status == -2 and "workspace_limit" in str(err.value)
+        assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)  # nothing sizeable allocated
+        img = tess.project(lat, view, tune=tess.make_tune(workspace_limit=1 << 33))
+    s.synchronize()
+    ref, _ = O.project_region(*xyz, (n, n, n), view)
+    assert_parity(img.cpu().numpy(), ref, what="under a workspace limit")
+
+
 def test_invalid_views_rejected(tess):
     lat = tess.build(*dev(W.undisplaced(4)), (4, 4, 4))
     R = W.random_rotations(1)[0]

@@ -292,3 +292,23 @@ def test_edge_form_short_loop_without_counts(wrap, rows, cols):
     # rotated window (the contract's 1e-4 against its 1e-6-of-the-mean floor)
     assert np.abs(c - ref).max() < 1e-8 * np.abs(ref).max()
     assert rel(c, ref) < 1e-4
+
+
+@pytest.mark.parametrize("edges", [False, True])
+def test_tile_columns_leave_no_residual_slope(edges):
+    # a kink whose two second-difference entries fall in two tiles is drawn
+    # by both; they must compute it identically (in the record's frame), or
+    # the entries no longer add up to its slope change and the row sums leave
+    # a slope on the empty pixels right of the footprints.  A rotated window
+    # (empty pixels) with 2 pixels per lattice cell, one tile per row against
+    # 16- to 256-column tiles: the same image to FP64 rounding, empty pixels
+    # included
+    n = 32
+    xyz = W.zeldovich(n, 8, 2.0, seed=17)
+    view = W.rotated_view(W.random_rotations(1, seed=5)[0], 128, 112)
+    one, _, _ = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=16, tile_cols=128, edges=edges)
+    ref, _ = O.project_region(*xyz, (n, n, n), view)
+    for cols in (64, 37, 16):
+        img, _, _ = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=16, tile_cols=cols, edges=edges)
+        assert np.abs(img - one).max() < 1e-12 * np.abs(one).max(), cols
+        assert rel(img, ref) < 1e-5, cols

@@ -494,6 +494,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.edges = g.vp.edges;
     B.first_edge = (uint32_t)(6 * g.lp.ncubes);
     B.seam = g.vp.edges && v->wrap ? 1 : 0;
+    B.groups = nullptr;
     g.nmat = g.ntiles * B.nseg;
     g.npix = (int64_t)B.W * B.H;
     return TESS_OK;
@@ -612,9 +613,11 @@ tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigne
     TESS_HIP(launch_scatter(b.head, g.ntet, g.B, b.counts, b.base, b.pairs, cap, s));
     TESS_HIP(launch_zero(b.acc, g.npix, s));
     if (after_bin) TESS_HIP(hipEventRecord(after_bin, s));
+    BinParams B = g.B;
+    B.groups = b.kinks;  // the edge records' sums by period offset (written over the slots)
     TESS_HIP(launch_raster(b.head, b.coef, b.ecoef, b.pairs, b.items, max_items_for(g.ntiles, chunk, cap), slot,
-                           g.B, plan.block, count, b.acc, b.counters, s));
-    TESS_HIP(launch_raster_direct(b.head, b.coef, b.ecoef, slot, cap, g.B, b.acc, b.counters, s));
+                           B, plan.block, count, b.acc, b.counters, s));
+    TESS_HIP(launch_raster_direct(b.head, b.coef, b.ecoef, slot, cap, B, b.acc, b.counters, s));
     if (after_raster) TESS_HIP(hipEventRecord(after_raster, s));
     TESS_HIP(launch_finalize(b.acc, g.B, image, s));
     return TESS_OK;

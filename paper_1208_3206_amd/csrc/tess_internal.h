@@ -79,6 +79,7 @@ struct BinParams {
     uint32_t first_edge;     // edge form: id of the first edge record (6 cubes)
     int32_t seam;            // 1: edge form under wrap (tiles carry a seam line per row)
     int32_t seam_copies;     // the raster's copies of each tile row's seam line (set at launch)
+    const double *groups;    // edge form: slope changes by period offset, [3][edges] (EdgePayload)
 };
 
 // Pair-list entries: the record id, with the pair's work class (0..31) in
@@ -165,17 +166,28 @@ struct alignas(128) Payload {
     double c[14];
     RecHead h;  // copy of the record's head: the raster reads one 128-byte line per record
 };
-// Edge-form payload of an edge record (REC_EDGE), all the raster reads of
-// it: endpoints (c[0], c[1]) and (c[2], c[3]) in pixel units of the edge's
-// frame (its box follows from them, edge_box), the slope changes summed by
-// period offset s = -1, 0, 1 (c[4..6]) and the head's spare word (the
-// silhouette counts).  Half a line, stored apart from the tetrahedra's
-// payloads (record id - BinParams::first_edge); the head array holds the box
-// and flags for the binning.
-struct alignas(64) EdgePayload {
-    double c[7];
-    uint64_t spare;
+// Edge-form payload of an edge record (REC_EDGE), what the raster reads of
+// it, in the record's frame (pixel units relative to the corner (x0, y0) of
+// its box; record row r has its centre at y0 + r + 1/2, record column c at
+// x0 + c): the crossing of record row r lies at column u(r) = fma(r, sl,
+// base), a function of the row alone, so every tile that draws the row
+// places its kink identically; D, the edge's summed slope change; the box
+// (x0 and y0 .. y1 as in the head, the width x1 - x0 in 15 bits, and bit
+// 31 set when some of D comes from tetrahedra in a frame one period away,
+// s = -1 or +1: the sums by s = -1, 0, 1 are then in the edge slots, at
+// slot s + 1 of the slots' edge-major view, which the edge's vertex no
+// longer needs once its records are written).  The box's rows are those
+// whose centre lies in the edge's half-open y range, clipped to the image
+// without wrap.  32 bytes, stored apart from the tetrahedra's payloads
+// (record id - BinParams::first_edge); the head array holds box, flags and
+// silhouette counts for the binning and the fragment count.
+struct alignas(32) EdgePayload {
+    double base, sl, D;
+    uint32_t bx;  // x0 (int16) | width << 16 (15 bits) | offsets << 31
+    uint32_t by;  // as RecHead
 };
+constexpr uint32_t kEdgeOffsets = 1u << 31;
+static_assert(sizeof(EdgePayload) == 32, "two edges per 64 bytes");
 static_assert(sizeof(RecHead) == 16, "record head");
 static_assert(sizeof(Payload) == 128, "one 128-byte line per record");
 

@@ -507,10 +507,11 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
 // the tile is added to the image-sized array `acc` (FP64 atomics in L2; a
 // tile has several items).
 constexpr int kPad = 2;
+__host__ __device__ inline int tile_stride(int Tw) { return Tw + 2 * kPad; }
 constexpr int kIdBurst = 8;     // pair ids a lane loads at once
 constexpr int kSortPer = 7;     // pair ids per lane in one wavefront's class sort
 constexpr int kNumClasses = 32;
-constexpr size_t kLdsBytes = 160 * 1024;
+constexpr size_t kLdsBytes = 160 * 1024 - 64;  // dynamic LDS: 64 bytes stay for the static counter
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -538,33 +539,54 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     const int n = min(B.Tw, B.W - tx0), rows = min(B.Th, B.H - ty0);
     // rows of Tw + 4 cells: two padding cells each side take the adds that
     // fall outside the tile, so that the raster needs no bounds tests
-    const int stride = B.Tw + 2 * kPad;
+    const int stride = tile_stride(B.Tw);
     const int tsize = B.Th * stride;
+    auto cell = [&](int row, int j) { return row * stride + kPad + j; };
     // then (edge form under wrap) per tile row the seam line a + b j, in
     // seam_copies copies (lane t adds to copy t % seam_copies: the lanes of a
     // 16-lane group draw 16 neighbouring edges over the same rows, and adds
     // of one instruction to one cell are serialised); a values, then b
+    // then the range updates of the seam lines in difference form, Th + 1
+    // cells each (added at a range's first row, taken off after its last):
+    // alpha, beta (a += alpha + beta rho) and gamma (b += gamma), in
+    // seam_copies copies too
     double *sSeam = sA + tsize;
     const int nsc = B.seam ? B.seam_copies : 0;
-    const int nseam = 2 * B.Th * nsc;
+    const int nseam = (2 * B.Th + 3 * (B.Th + 1)) * nsc;
     const int sc = nsc ? (int)(threadIdx.x % (unsigned)nsc) : 0;
+    double *sDiff = sSeam + 2 * B.Th * nsc;
+    const int dstride = (B.Th + 1) * nsc;  // one difference array (all copies)
     for (int i = threadIdx.x; i < tsize + nseam; i += TPB) sA[i] = 0.0;
+    __shared__ uint32_t s_next;  // edge form: chunks handed out so far
+    if (threadIdx.x == 0) s_next = 0u;
     __syncthreads();
     long long frags = 0;  // edge records add signed terms
     uint32_t spans = 0, kinks = 0;
+    auto seam_range = [&](int lo, int hi, double alpha, double beta, double gamma) {
+        atomicAdd(&sDiff[lo * nsc + sc], alpha);
+        atomicAdd(&sDiff[(hi + 1) * nsc + sc], -alpha);
+        atomicAdd(&sDiff[dstride + lo * nsc + sc], beta);
+        atomicAdd(&sDiff[dstride + (hi + 1) * nsc + sc], -beta);
+        atomicAdd(&sDiff[2 * dstride + lo * nsc + sc], gamma);
+        atomicAdd(&sDiff[2 * dstride + (hi + 1) * nsc + sc], -gamma);
+    };
     auto one = [&](uint32_t id) {
         if (id >= B.ntet) return;
         if constexpr (FORM == kFormEdge) {
             // an edge record: its half line is all the raster reads
             if (id >= B.first_edge) {
                 frags += (int32_t)edge_pair<COUNT>(
-                    ecoef[id - B.first_edge], B, tx0, ty0, n, rows,
-                    [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                    ecoef[id - B.first_edge], id - B.first_edge, COUNT ? head[id].spare : 0u, B, tx0, ty0, n, rows,
+                    [&](int row, int j, double v1, double v2) {
+                        const int x = cell(row, j);
+                        atomicAdd(&sA[x], v1);
+                        atomicAdd(&sA[x + 1], v2);
+                    },
                     [&](int row, double a, double b) {
                         atomicAdd(&sSeam[row * nsc + sc], a);
                         atomicAdd(&sSeam[(B.Th + row) * nsc + sc], b);
                     },
-                    kinks);
+                    seam_range, kinks);
                 return;
             }
         }
@@ -572,7 +594,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
         if (!(h.flags & REC_VALID)) return;
         frags += (int32_t)raster_record<FORM>(
             h, coef[id].c, B, tx0, ty0, n, rows,
-            [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+            [&](int row, int j, double v) { atomicAdd(&sA[cell(row, j)], v); },
             [&](int row, double a, double b) {
                 atomicAdd(&sSeam[row * nsc + sc], a);
                 atomicAdd(&sSeam[(B.Th + row) * nsc + sc], b);
@@ -597,7 +619,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             const RecHead h = coef[id].h;
             if (!(h.flags & REC_VALID)) continue;
             frags += persp_pair(h, coef[id].c, B, tx0, ty0, n, rows, (int)lane, 64,
-                                [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); },
+                                [&](int row, int j, double v) { atomicAdd(&sA[cell(row, j)], v); },
                                 spans, kinks);
         }
     } else if (FORM == kFormPyramid && sorted) {
@@ -642,28 +664,53 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     } else {
         const uint32_t idmask = B.nkey > 1 ? kIdMask : 0xffffffffu;
         if constexpr (FORM == kFormEdge) {
-            // edge pairs: groups of 16 lanes take slices of the list and read
-            // it 16 entries at a time, so that, the list being in rough id
-            // order, a group reads 16 neighbouring 64-byte edge payloads
-            // (whole lines), while the wavefront's four groups draw in four
-            // places of the tile (16 neighbouring edges are parallel and a few
-            // pixels apart: a whole wavefront of them crowds the same LDS banks)
-            const uint32_t ns = TPB / 16, g = threadIdx.x >> 4, q = threadIdx.x & 15u;
-            const uint32_t C = ((it.count + ns - 1) / ns + 15u) & ~15u;
-            const uint32_t g0 = g * C, g1 = min(it.count, g0 + C);
-            // First the edge records.  A pair's id and payload are two
-            // dependent loads; the next pair's are issued before this one is
-            // drawn, so that they arrive while it is (one wavefront per SIMD
-            // quarter has too little other work to hide them otherwise).
-            auto id_at = [&](uint32_t e) { return e < g1 ? pairs[it.first + e] : 0xffffffffu; };
+            // edge pairs: groups of 16 lanes read the list 16 entries (a
+            // chunk) at a time, so that, the list being in rough id order, a
+            // group reads 16 neighbouring 64-byte edge payloads (whole lines).
+            // The list is cut into G stripes, one per group of the block;
+            // chunk c is position c / G of stripe c % G, and each wavefront
+            // takes the next four chunks from a counter in LDS.  Concurrent
+            // groups then draw in separate stripes (16 neighbouring edges are
+            // parallel and a few pixels apart: a whole wavefront of them would
+            // crowd the same LDS banks), and a wavefront that finishes early
+            // takes over chunks that a static share would have left to a
+            // slow one (which holds up the whole block, as the tile's LDS
+            // admits one block per CU).
+            const uint32_t G = TPB / 16, g = threadIdx.x >> 4, q = threadIdx.x & 15u, gw = g & 3u;
+            const uint32_t C = ((it.count + G - 1) / G + 15u) & ~15u;  // entries per stripe
+            const uint32_t nchunk = G * (C / 16u);
+            constexpr uint32_t kDone = 0xffffffffu, kNone = 0xfffffffeu;
+            // this lane's entry of the wavefront's next chunk: kDone when the
+            // chunks are used up (the same for the group's 16 lanes, and the
+            // wavefront's first group is the last to run out, so its lane 0
+            // is active for every call), kNone past the end of the list
+            auto take = [&]() -> uint32_t {
+                uint32_t c0 = 0u;
+                if ((threadIdx.x & 63u) == 0u) c0 = atomicAdd(&s_next, 4u);
+                const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c0) + gw;
+                if (c >= nchunk) return kDone;
+                const uint32_t e = (c % G) * C + (c / G) * 16u + q;
+                return e < it.count ? e : kNone;
+            };
+            // A pair's id and payload are two dependent loads; the next
+            // pair's are issued before this one is drawn, so that they arrive
+            // while it is (one wavefront per SIMD quarter has too little
+            // other work to hide them otherwise).
+            auto id_at = [&](uint32_t e) { return e < it.count ? pairs[it.first + e] : 0xffffffffu; };
             auto is_edge = [&](uint32_t id) { return id < B.ntet && id >= B.first_edge; };
-            auto dep = [&](int row, int j, double v) { atomicAdd(&sA[row * stride + kPad + j], v); };
+            // a kink's two entries, at columns j and j + 1
+            auto dep = [&](int row, int j, double v1, double v2) {
+                const int x = cell(row, j);
+                atomicAdd(&sA[x], v1);
+                atomicAdd(&sA[x + 1], v2);
+            };
             auto seam = [&](int row, double a, double b) {
                 atomicAdd(&sSeam[row * nsc + sc], a);
                 atomicAdd(&sSeam[(B.Th + row) * nsc + sc], b);
             };
-            uint32_t e = g0 + q;
-            uint32_t id = id_at(e), idn = id_at(e + 16);
+            uint32_t e = take();
+            uint32_t en = take();
+            uint32_t id = id_at(e), idn = id_at(en);
             EdgePayload P{};
             if (is_edge(id)) P = ecoef[id - B.first_edge];
             // the first payload has arrived before the loop: the loop then
@@ -671,15 +718,21 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             // this the wait before each pair's first use also takes the next
             // pair's loads)
             __builtin_amdgcn_s_waitcnt(0);
-            for (; e < g1; e += 16) {
-                const uint32_t idnn = id_at(e + 32);
+            while (e != kDone) {
+                const uint32_t enn = take();
+                const uint32_t idnn = id_at(enn);
                 EdgePayload Pn{};
                 if (is_edge(idn)) Pn = ecoef[idn - B.first_edge];
-                if (is_edge(id)) frags += (int32_t)edge_pair<COUNT>(P, B, tx0, ty0, n, rows, dep, seam, kinks);
+                if (is_edge(id))
+                    frags += (int32_t)edge_pair<COUNT>(P, id - B.first_edge, COUNT ? head[id].spare : 0u, B, tx0,
+                                                       ty0, n, rows, dep, seam, seam_range, kinks);
+                e = en;
+                en = enn;
                 id = idn;
                 idn = idnn;
                 P = Pn;
             }
+            const uint32_t g0 = g * C, g1 = min(it.count, g0 + C);
             // then the tetrahedra that kept their own records
             for (uint32_t e2 = g0 + q; e2 < g1; e2 += 16) {
                 const uint32_t id2 = pairs[it.first + e2];
@@ -705,18 +758,37 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     __syncthreads();
     for (int i = threadIdx.x; i < rows * B.Tw; i += TPB) {
         const int r = i / B.Tw, c = i - r * B.Tw;
-        const double v = sA[r * stride + kPad + c];
+        const double v = sA[cell(r, c)];
         if (c < n && v != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + tx0 + c], v);
     }
-    // the seam lines: a at column 0 and b - a at column 1 of the second differences
-    for (int r = threadIdx.x; r < (nsc ? rows : 0); r += TPB) {
-        double a = 0.0, b = 0.0;
-        for (int c = 0; c < nsc; ++c) {
-            a += sSeam[r * nsc + c];
-            b += sSeam[(B.Th + r) * nsc + c];
+    // the seam lines: a at column 0 and b - a at column 1 of the second
+    // differences; the range updates first summed over their copies (into
+    // copy 0), then over the rows up to each row
+    if (nsc) {
+        for (int i = threadIdx.x; i < 3 * rows; i += TPB) {
+            const int arr = i / rows, q = i - arr * rows;
+            double *p = &sDiff[arr * dstride + q * nsc];
+            double t = 0.0;
+            for (int c = 0; c < nsc; ++c) t += p[c];
+            p[0] = t;
         }
-        if (a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W], a);
-        if (B.W > 1 && b - a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + 1], b - a);
+        __syncthreads();
+        for (int r = threadIdx.x; r < rows; r += TPB) {
+            double a = 0.0, b = 0.0, pa = 0.0, pb = 0.0, pg = 0.0;
+            for (int c = 0; c < nsc; ++c) {
+                a += sSeam[r * nsc + c];
+                b += sSeam[(B.Th + r) * nsc + c];
+            }
+            for (int q = 0; q <= r; ++q) {
+                pa += sDiff[q * nsc];
+                pb += sDiff[dstride + q * nsc];
+                pg += sDiff[2 * dstride + q * nsc];
+            }
+            a += pa + pb * (double)r;
+            b += pg;
+            if (a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W], a);
+            if (B.W > 1 && b - a != 0.0) unsafeAtomicAdd(&acc[(int64_t)(ty0 + r) * B.W + 1], b - a);
+        }
     }
     const unsigned long long f = wave_sum((unsigned long long)frags);
     const unsigned long long sp = wave_sum((unsigned long long)spans);
@@ -758,10 +830,11 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
     // the tile's accumulator, its seam lines (as many copies per row as fit,
     // up to 16), and beside them (when they fit) the wavefronts' class sorts
     BinParams Bl = B;
-    const size_t acc_lds = sizeof(double) * (size_t)B.Th * (B.Tw + 2 * kPad);
-    const size_t row_seam = sizeof(double) * 2 * (size_t)B.Th;
+    const size_t acc_lds = sizeof(double) * (size_t)B.Th * tile_stride(B.Tw);
+    const size_t row_seam = sizeof(double) * (2 * (size_t)B.Th + 3 * ((size_t)B.Th + 1));
     Bl.seam_copies = B.seam ? (int)std::min<size_t>(16, std::max<size_t>(1, (kLdsBytes - acc_lds) / row_seam)) : 0;
     const size_t tile_lds = acc_lds + row_seam * (size_t)Bl.seam_copies;
+    if (tile_lds > kLdsBytes) return hipErrorInvalidValue;  // (tiles of at most 16384 cells fit)
     const size_t sort_lds = sizeof(uint32_t) * (size_t)(block / 64) * kSortWords;
     const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;
     const size_t lds = tile_lds + (sorted ? sort_lds : 0);
@@ -822,7 +895,17 @@ __global__ void __launch_bounds__(256) k_raster_direct(const RecHead *__restrict
                 if ((uint32_t)id >= B.first_edge) {
                     const RecHead h = head[id];
                     if (!(h.flags & REC_VALID)) break;
-                    frags += (int32_t)edge_pair(ecoef[id - B.first_edge], B, 0, ty0, W, rows, dep, seam, kinks);
+                    frags += (int32_t)edge_pair(
+                        ecoef[id - B.first_edge], (uint32_t)id - B.first_edge, h.spare, B, 0, ty0, W, rows,
+                        [&](int row, int j, double v1, double v2) {
+                            dep(row, j, v1);
+                            dep(row, j + 1, v2);
+                        },
+                        seam,
+                        [&](int lo, int hi, double alpha, double beta, double gamma) {
+                            for (int r = lo; r <= hi; ++r) seam(r, alpha + beta * (double)r, gamma);
+                        },
+                        kinks);
                     continue;
                 }
             }

@@ -91,15 +91,29 @@ TESS_HD inline int64_t imod64(int64_t a, int64_t m) {
     int64_t r = a % m;
     return r < 0 ? r + m : r;
 }
-TESS_HD inline int imod(int a, int m) {
-    int r = a % m;
-    return r < 0 ? r + m : r;
+// floor(a / b) for b > 0 and |a|, b below 2^22 (pixel and tile sizes): the
+// FP32 quotient from the reciprocal, then one correction step makes it exact
+// (the estimate is within one of the quotient), about a fifth of the cost
+// of an integer division on the GPU
+TESS_HD inline int floor_div_r(int a, int b, float rb) {  // rb: 1/b within a few ulp
+    int q = (int)floorf((float)a * rb);
+    const int r = a - q * b;
+    if (r < 0) --q;
+    else if (r >= b) ++q;
+    return q;
 }
-TESS_HD inline int floor_div(int a, int b) {  // b > 0
-    return a >= 0 ? a / b : -((-a + b - 1) / b);
+TESS_HD inline int floor_div(int a, int b) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return floor_div_r(a, b, __builtin_amdgcn_rcpf((float)b));
+#else
+    return floor_div_r(a, b, 1.0f / (float)b);
+#endif
 }
 TESS_HD inline int ceil_div(int a, int b) {  // b > 0
     return -floor_div(-a, b);
+}
+TESS_HD inline int imod(int a, int m) {  // in [0, m), m > 0 (as floor_div)
+    return a - m * floor_div(a, m);
 }
 // 1/s to within a few ulp: the hardware estimate refined by one Newton step
 // (the host build divides).
@@ -946,11 +960,17 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
     const double PX0 = vertex_px(L, V, v);
     double PY0 = (V.rot[3] * b0[0] + V.rot[4] * b0[1] + V.rot[5] * b0[2] - V.v_bottom) * V.inv_dv;
     if (V.wrap) PY0 -= (double)V.H * floor(PY0 / (double)V.H);
+    // the slope changes by period offset of the edges that have offsets: kept
+    // until every slot of this vertex has been read, then written over slots
+    // 7 g + tau of this vertex (the slots' edge-major view, BinParams::groups)
+    double G[7][3];
+    uint32_t offs = 0u;
 #pragma unroll
     for (int tau = 0; tau < 7; ++tau) {
         RecHead R;
         R.bx = 0; R.by = 0; R.flags = 0; R.spare = 0;
-        double pc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        EdgePayload P;
+        G[tau][0] = G[tau][1] = G[tau][2] = 0.0;
         [&] {
             const int ca = kEdgeEnds[tau][0], cb = kEdgeEnds[tau][1];
             if (!has[ca] || !has[cb]) return;
@@ -984,27 +1004,41 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
             Bv.H = V.H;
             Bv.wrap = V.wrap;
             int ix0, ix1, iy0, iy1;
+            // (a row's centre strictly inside the y range: the edge is not
+            // horizontal, so sl below is finite)
             if (!edge_box(ax, ay, bx, by, Bv, ix0, ix1, iy0, iy1)) return;
-            pc[0] = ax;
-            pc[1] = ay;
-            pc[2] = bx;
-            pc[3] = by;
-            pc[4] = D[0];
-            pc[5] = D[1];
-            pc[6] = D[2];
+            // the endpoints in the record frame (exact: integer offsets)
+            const double Px = ax - (double)ix0, Py = ay - (double)iy0;
+            const double Qx = bx - (double)ix0, Qy = by - (double)iy0;
+            P.sl = (Qx - Px) / (Qy - Py);
+            P.base = fma(0.5 - Py, P.sl, Px - 0.5);
+            P.D = D[0] + D[1] + D[2];
+            const bool off = D[0] != 0.0 || D[2] != 0.0;
             R.bx = pack_range(ix0, ix1);
             R.by = pack_range(iy0, iy1);
             R.flags = REC_EDGE | REC_VALID;
             R.spare = cnt;
+            // (an edge narrower than the image, as those of the tetrahedra
+            // that hand their creases to their edges are: the width fits)
+            P.bx = ((uint32_t)(uint16_t)(int16_t)ix0) | ((uint32_t)(ix1 - ix0) << 16) | (off ? kEdgeOffsets : 0u);
+            P.by = R.by;
+            if (off) {
+                G[tau][0] = D[0];
+                G[tau][1] = D[1];
+                G[tau][2] = D[2];
+                offs |= 1u << tau;
+            }
         }();
         head[tau * nvert] = R;
-        if (R.flags & REC_VALID) {
-            // the whole 64 bytes (a partial write would cost a read-modify-write)
-            EdgePayload P;
+        // the whole 32 bytes (a partial write would cost a read-modify-write)
+        if (R.flags & REC_VALID) ecoef[tau * nvert] = P;
+    }
+    if (offs) {
 #pragma unroll
-            for (int g = 0; g < 7; ++g) P.c[g] = pc[g];
-            P.spare = R.spare;
-            ecoef[tau * nvert] = P;
+        for (int tau = 0; tau < 7; ++tau) {
+            if (!(offs & (1u << tau))) continue;
+#pragma unroll
+            for (int g = 0; g < 3; ++g) V.kinks[(int64_t)(7 * g + tau) * nvert + v] = G[tau][g];
         }
     }
 }
@@ -1017,15 +1051,15 @@ TESS_HD inline void axis_tiles(int b0, int b1, int n, int T, int ntiles, int wra
     if (!wrap) {
         const int lo = max(b0, 0), hi = min(b1, n - 1);
         if (lo > hi) { start = 0; count = 0; return; }
-        start = lo / T;
-        count = hi / T - start + 1;
+        start = floor_div(lo, T);
+        count = floor_div(hi, T) - start + 1;
         return;
     }
     if (b1 - b0 + 1 >= n) { start = 0; count = ntiles; return; }
     const int a = imod(b0, n);
     const int b = a + (b1 - b0);
-    if (b < n) { start = a / T; count = b / T - a / T + 1; return; }
-    const int ta = a / T, tb = (b - n) / T;
+    if (b < n) { start = floor_div(a, T); count = floor_div(b, T) - start + 1; return; }
+    const int ta = floor_div(a, T), tb = floor_div(b - n, T);
     if (tb >= ta) { start = 0; count = ntiles; return; }
     start = ta;
     count = ntiles - ta + tb + 1;
@@ -1870,8 +1904,8 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
     return frags;
 }
 
-// Edge form: one mesh edge's summed slope change along its projection from
-// P to Q, deposited on the rows whose centre lies in [min y, max y) (the
+// Edge form: one mesh edge's summed slope change along its projection,
+// deposited on the rows whose centre lies in its half-open y range (the
 // crease form's rule, so that at a vertex the edges above and below take
 // the row once between them).  Nothing is folded at the image's left edge.
 // Without wrap the tetrahedra behind an edge lie within the image's
@@ -1886,105 +1920,178 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
 // -d (u - W + 2)(j + 1) for W - 2 <= u_T < W - 1 (the two agree at
 // u_T = W - 1, so a crossing there may fall either way).  u_T = u + (s + kx)
 // W, s the period offset of the tetrahedron's frame from the edge record's
-// (c[4..6] hold the slope changes summed by s = -1, 0, 1), kx the tile copy.
+// (Dm, D0, Dp: the slope changes summed by s = -1, 0, 1; all of D is at
+// s = 0 unless the payload flags offsets), kx the tile copy.  eid: the
+// edge's index among the edge records; cnt: its silhouette counts (the
+// head's spare word; with COUNT only).
 // Fragments: a tetrahedron's row holds (samples left of its leaving
 // crossing) - (samples left of its entering crossing); each crossing adds
 // its terms once, in the copy and tile holding the column right of it, in
 // image columns plus (s + kx) W.  Returns the count as the bits of a signed
 // 32-bit value.  COUNT = false skips the fragment count (returns 0).
-template <bool COUNT = true, typename Dep, typename Seam>
-TESS_HD inline uint32_t edge_pair(const EdgePayload &E, const BinParams &B, int tx0, int ty0, int n, int rows,
-                                  Dep &&dep, Seam &&seam, uint32_t &kinks) {
-    // the box from the endpoints, as the record's head holds it, and the
-    // endpoints relative to its corner
-    int bx0, bx1, by0, by1;
-    edge_box(E.c[0], E.c[1], E.c[2], E.c[3], B, bx0, bx1, by0, by1);
-    bx1 += kRightReach;
+//
+// A row's crossing u = fma(r, sl, base) is in the record's frame and depends
+// on the row alone, so a kink whose two entries fall in two tiles adds
+// exactly its slope change.  Its entries: D (1 - f) at column floor(u) + 1
+// and D f at floor(u) + 2, f = u - floor(u), as tile columns; the column is
+// clamped so that a crossing outside the tile's columns (the rows kept are
+// those whose crossing lies within a few columns of it) writes only the two
+// padding cells each side, which are never read.  dep(row, j, v1, v2) adds
+// v1 at tile column j and v2 at j + 1; seam(row, a, b) adds a and b to the
+// row's seam line; seam_range(lo, hi, alpha, beta, gamma) adds alpha +
+// beta rho to a and gamma to b on the tile rows rho in [lo, hi].
+template <bool COUNT = true, typename Dep, typename Seam, typename SeamRange>
+TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t cnt, const BinParams &B, int tx0,
+                                  int ty0, int n, int rows, Dep &&dep, Seam &&seam, SeamRange &&seam_range,
+                                  uint32_t &kinks) {
+    const int bx0 = range_lo(E.bx), bx1 = bx0 + (int)((E.bx >> 16) & 0x7fffu) + kRightReach;
+    const int by0 = range_lo(E.by), by1 = range_hi(E.by);
     int kx0, kx1, ky0, ky1;
     axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
     axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
-    const double Px = E.c[0] - (double)bx0, Py = E.c[1] - (double)by0;
-    const double Qx = E.c[2] - (double)bx0, Qy = E.c[3] - (double)by0;
-    const double Dm = E.c[4], D0 = E.c[5], Dp = E.c[6];
-    const double D = Dm + D0 + Dp;
-    const uint32_t cnt = (uint32_t)E.spare;
+    const double D = E.D;
+    // the sums by period offset (all of D at s = 0 for most edges)
+    double Dm = 0.0, D0 = D, Dp = 0.0;
+    if (E.bx & kEdgeOffsets) {
+        const int64_t nedge = (int64_t)B.ntet - B.first_edge;
+        Dm = B.groups[eid];
+        D0 = B.groups[nedge + eid];
+        Dp = B.groups[2 * nedge + eid];
+    }
+    const double sl = E.sl, base = E.base;
+    // rows per column, for the rows that reach a tile's columns (only the
+    // choice of rows depends on it, with a margin: an estimate will do)
+    const double iv = sl != 0.0 ? fast_rcp(sl) : 0.0;
     const int ne[3] = {(int)(cnt & 7u), (int)((cnt >> 3) & 7u), (int)((cnt >> 6) & 7u)};
     const int nl[3] = {(int)((cnt >> 9) & 7u), (int)((cnt >> 12) & 7u), (int)((cnt >> 15) & 7u)};
     const bool count = cnt != 0u;
     const int nlt = nl[0] + nl[1] + nl[2], net = ne[0] + ne[1] + ne[2];
-    const double sl = (Qx - Px) * fast_rcp(Qy - Py);
-    const int qa = (int)ceil(fmin(Py, Qy) - 0.5), qb = (int)ceil(fmax(Py, Qy) - 0.5) - 1;
-    const double Wd = (double)B.W;
     int frags = 0;
     for (int ky = ky0; ky <= ky1; ++ky) {
-        const int rshift = by0 - ky * B.H - ty0;
-        const int q0 = max(qa, max(-rshift, 0)), q1 = min(qb, min(rows - 1 - rshift, by1 - by0));
+        const int rshift = by0 - ky * B.H - ty0;  // tile row of record row 0
+        const int q0 = max(-rshift, 0), q1 = min(rows - 1 - rshift, by1 - by0);
         if (q0 > q1) continue;
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
             const int shift = tx0 + kx * B.W - bx0;  // record column of the tile's column 0
-            const double X0 = (double)shift + 0.5;
-            const double xl = X0 - 3.0, xr = X0 + (double)n + 1.0;
             int r0 = q0, r1 = q1;
-            if (Qx != Px) {
-                // the rows whose crossing lies in [xl, xr), with the margins
-                // of the crease form
-                const double iv = (Qy - Py) * fast_rcp(Qx - Px);
-                double ya = Py + (xl - Px) * iv, yb = Py + (xr - Px) * iv;
+            if (iv != 0.0) {
+                // the rows whose crossing lies in [shift - 3, shift + n + 1)
+                double ya = ((double)(shift - 3) - base) * iv, yb = ((double)(shift + n + 1) - base) * iv;
                 if (ya > yb) { const double t = ya; ya = yb; yb = t; }
-                ya = fmin(fmax(ya, (double)q0 - 1.0), (double)q1 + 2.0);
-                yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 2.0);
-                r0 = max(q0, (int)floor(ya - 0.5));
-                r1 = min(q1, (int)ceil(yb - 0.5));
+                ya = fmin(fmax(ya, (double)q0 - 1.0), (double)q1 + 1.0);
+                yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 1.0);
+                r0 = max(q0, (int)floor(ya));
+                r1 = min(q1, (int)ceil(yb));
             }
-            // the wrap of each period group in this copy: s + kx; a crossing
-            // may need the seam line only in a shifted copy, for a group
-            // with s != 0, or within two columns of the period's right end
-            // (canonical position u >= W - 2; the edge's crossings lie
-            // between its endpoints, the rightmost at u = bx0 + max x - 1/2)
-            const int wm = kx - 1, w0 = kx, wp = kx + 1;
+            // record columns of the clamp: tile columns -3 .. n - 1
+            const int klo = shift - 3, khi = shift + n - 1;
             // the seam line of a crossing at canonical position u: the groups
             // with s + kx = 1 add D (u - j), summed in A1; those with
             // s + kx = 0 add -D (u - W + 2) (j + 1) when u >= W - 2, summed
             // in A0 (the others add nothing)
             const double A1 = kx == 0 ? Dp : kx == 1 ? D0 : kx == 2 ? Dm : 0.0;
             const double A0 = kx == -1 ? Dp : kx == 0 ? D0 : kx == 1 ? Dm : 0.0;
-            // (in this copy a crossing's canonical position is its record
-            // position + bx0 - kx W; the edge's rightmost is at max x)
-            const bool near_end =
-                tx0 + n > B.W - 3 && (double)(bx0 - kx * B.W) + fmax(Px, Qx) - 0.5 >= (double)B.W - 2.0 - 1e-6;
+            // A0 can act only where a crossing reaches the period's last two
+            // columns: in this copy the rightmost crossing lies before column
+            // x1 + 1 of the box (x1 = bx1 - kRightReach), moved by -kx W
+            const bool near_end = tx0 + n > B.W - 3 && bx1 - kRightReach - kx * B.W >= B.W - 3;
             const bool seamed = B.seam && (A1 != 0.0 || (A0 != 0.0 && near_end));
-            const double Wm2 = (double)B.W - 2.0;
-            const int fwrap = B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
-            // the crossing of row r in the record frame, from the row alone
-            // (the same in every tile that draws it; see crease_pair)
-            const double cP = 0.5 - Py, xP = Px - 0.5;
-            const double dshift = (double)shift;
-            const int len = max(r1 - r0 + 1, 0);
-            kinks += (uint32_t)len;
             double rv = (double)r0;
+            if (!COUNT) {
+                // The rows with an entry in the tile's columns, kf = floor(u)
+                // - shift in [-2, n - 2] (contiguous: kf is monotone in r), the
+                // guesses moved to the exact ends with the loop's own
+                // arithmetic; in between, every kf lies between those at the
+                // ends, so the entries need no clamp.  A kink is counted in
+                // the tile that holds the column right of it (kf >= -1).
+                auto kf_at = [&](int r) { return (int)floor(fma((double)r, sl, base)) - shift; };
+                int a0 = r0, a1 = r1, k0 = 0, k1 = 0;
+                for (; a0 <= a1; ++a0) {
+                    k0 = kf_at(a0);
+                    if (k0 >= -2 && k0 <= n - 2) break;
+                }
+                for (; a1 >= a0; --a1) {
+                    k1 = kf_at(a1);
+                    if (k1 >= -2 && k1 <= n - 2) break;
+                }
+                if (a0 <= a1) kinks += (uint32_t)(a1 - a0 + 1 - (k0 == -2) - (a1 > a0 && k1 == -2));
+                const double rend = (double)a1 + 0.5;
+                const int c1 = 1 - shift;
+                int row = a0 + rshift;
+                for (rv = (double)a0; rv < rend; rv += 1.0, ++row) {
+                    const double u = fma(rv, sl, base);
+                    const double fl = floor(u);
+                    const double v1 = fma(D, fl - u, D);
+                    dep(row, (int)fl + c1, v1, D - v1);
+                }
+                if (!seamed) continue;
+                // the seam line, on the rows whose crossing this copy and tile
+                // hold (floor(u) - shift in [-1, n - 2]; contiguous, as u is
+                // monotone in r): the A1 part, A1 (u_c - j) with canonical
+                // position u_c = tx0 - shift + u linear in the tile row rho =
+                // r + rshift, as one range update a += alpha + beta rho,
+                // b += -A1; then the A0 part row by row where u_c >= W - 2
+                auto held = [&](int r) {
+                    const int kf = (int)floor(fma((double)r, sl, base)) - shift;
+                    return kf >= -1 && kf <= n - 2;
+                };
+                int ha = r0, hb = r1;
+                if (sl != 0.0) {
+                    // first guesses from iv, then moved to the exact ends
+                    double ya = ((double)(shift - 1) - base) * iv, yb = ((double)(shift + n - 1) - base) * iv;
+                    if (ya > yb) { const double t = ya; ya = yb; yb = t; }
+                    ya = fmin(fmax(ya, (double)r0), (double)r1);
+                    yb = fmin(fmax(yb, (double)r0), (double)r1);
+                    ha = (int)ya;
+                    hb = (int)yb;
+                }
+                while (ha <= hb && !held(ha)) ++ha;
+                while (hb >= ha && !held(hb)) --hb;
+                if (ha > hb) continue;
+                while (ha > r0 && held(ha - 1)) --ha;
+                while (hb < r1 && held(hb + 1)) ++hb;
+                if (A1 != 0.0) {
+                    const double c0 = (double)(tx0 - shift) + base - (double)rshift * sl;
+                    seam_range(ha + rshift, hb + rshift, A1 * c0, A1 * sl, -A1);
+                }
+                if (A0 != 0.0 && near_end) {
+                    // from the end where u_c is largest, while u_c > W - 2
+                    const int step = sl >= 0.0 ? -1 : 1;
+                    const double Wm2 = (double)B.W - 2.0;
+                    for (int r = sl >= 0.0 ? hb : ha; r >= ha && r <= hb; r += step) {
+                        const double uc = (double)tx0 + (fma((double)r, sl, base) - (double)shift);
+                        const double near = uc - Wm2;
+                        if (!(near > 0.0)) break;
+                        seam(r + rshift, -A0 * near, -A0 * near);
+                    }
+                }
+                continue;
+            }
+            const int wm = kx - 1, w0 = kx, wp = kx + 1;
+            const int fwrap = B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
+            const double Wm2 = (double)B.W - 2.0;
             for (int r = r0; r <= r1; ++r, rv += 1.0) {
                 const int row = r + rshift;
-                const double u_rec = fma(rv + cP, sl, xP);
-                const double fw = floor(u_rec) - dshift;  // the tile-frame column left of the crossing
-                const int k = min(max((int)fmin(fmax(fw, -4.0), (double)n), -3), n - 1);
-                const double v1 = fma(D, (double)(k + shift) - u_rec, D);
-                dep(row, k + 1, v1);
-                dep(row, k + 2, D - v1);
+                const double u = fma(rv, sl, base);
+                const double fl = floor(u);
+                const int kf = (int)fl - shift;  // the tile column left of the crossing
+                const int k = min(max(kf, -3), n - 1);
+                const double v1 = fma(D, fl - u, D);
+                dep(row, k + 1, v1, D - v1);
                 // seam line and fragment count: only where this copy and tile
-                // hold the crossing (one loop for every lane: lanes on pairs
-                // that need neither skip this part, without a second loop)
-                if ((COUNT || seamed) && fw >= -1.0 && fw <= (double)(n - 2)) {
-                    const double w = u_rec - dshift;  // tile frame
+                // hold the crossing
+                if (kf >= -1 && kf <= n - 2) {
+                    ++kinks;
                     if (seamed) {
-                        const double u = (double)tx0 + w;  // canonical position
-                        const double near = fmax(u - Wm2, 0.0);
-                        const double a = A1 * u - A0 * near, b = -A1 - A0 * near;
+                        const double uc = (double)tx0 + (u - (double)shift);  // canonical position
+                        const double near = fmax(uc - Wm2, 0.0);
+                        const double a = A1 * uc - A0 * near, b = -A1 - A0 * near;
                         if (a != 0.0 || b != 0.0) seam(row, a, b);
                     }
                     if (COUNT && count) {
-                        const int jl = tx0 + 1 + (int)floor(u_rec - kSampleEps) - shift;
-                        const int je = tx0 + 1 + (int)floor(u_rec + kSampleEps) - shift;
+                        const int jl = tx0 + 1 + (int)floor(u - kSampleEps) - shift;
+                        const int je = tx0 + 1 + (int)floor(u + kSampleEps) - shift;
                         frags += nlt * jl - net * je + fwrap;
                     }
                 }

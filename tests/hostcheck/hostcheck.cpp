@@ -108,6 +108,7 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     B.edges = V.edges;
     B.first_edge = (uint32_t)(6 * L.ncubes);
     B.seam = V.edges && wrap ? 1 : 0;
+    B.groups = V.edges ? kinks.data() : nullptr;
     // per tile: its records in id order; every pair's work class in range
     std::vector<std::vector<uint32_t>> lists(ntiles);
     for (int64_t id = 0; id < ntet; ++id) {
@@ -146,13 +147,21 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                     seam[(size_t)tile_rows + row] += b;
                 };
                 auto rr = [&](auto &&dep) {
+                    auto dep2 = [&](int row, int j, double a, double b) {
+                        dep(row, j, a);
+                        dep(row, j + 1, b);
+                    };
+                    auto slr = [&](int lo, int hi, double alpha, double beta, double gamma) {
+                        if (lo < 0 || hi >= rows || lo > hi) throw 3;
+                        for (int r = lo; r <= hi; ++r) sl(r, alpha + beta * (double)r, gamma);
+                    };
                     return persp ? raster_record<kFormPersp>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : splat ? raster_record<kFormSplat>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : slab ? raster_record<kFormFace>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                         : is_edge ? (edges == 2 ? edge_pair<false>(ecoef[id - B.first_edge], B, tx0, ty0, n,
-                                                                     rows, dep, sl, kk)
-                                                 : edge_pair<true>(ecoef[id - B.first_edge], B, tx0, ty0, n,
-                                                                   rows, dep, sl, kk))
+                         : is_edge ? (edges == 2 ? edge_pair<false>(ecoef[id - B.first_edge], id - B.first_edge, 0u, B, tx0, ty0, n,
+                                                                     rows, dep2, sl, slr, kk)
+                                                 : edge_pair<true>(ecoef[id - B.first_edge], id - B.first_edge, head[id].spare, B, tx0, ty0, n,
+                                                                   rows, dep2, sl, slr, kk))
                          : V.edges ? raster_record<kFormEdge>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                                 : raster_record<kFormPyramid>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk);
                 };
@@ -185,4 +194,23 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         stats[9] = edged;
     }
     return 0;
+}
+
+// floor_div_r against exact floor division over pixel-sized arguments, with
+// its reciprocal moved `ulps` units in the last place either way (the GPU's
+// reciprocal estimate is within one); returns the number of mismatches
+extern "C" int64_t hc_floor_div_check(int ulps) {
+    const int divisors[] = {1, 2, 3, 7, 16, 31, 32, 37, 64, 100, 128, 255, 256, 333, 512, 1000, 1024, 2048,
+                            4096, 4097, 8191, 16384, 32767};
+    int64_t bad = 0;
+    for (int b : divisors)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            float rb = 1.0f / (float)b;
+            for (int k = 0; k < ulps; ++k) rb = std::nextafter(rb, sgn > 0 ? 2.0f : 0.0f);
+            for (int a = -70000; a <= 70000; ++a) {
+                const int exact = a >= 0 ? a / b : -((-a + b - 1) / b);
+                if (floor_div_r(a, b, rb) != exact) ++bad;
+            }
+        }
+    return bad;
 }

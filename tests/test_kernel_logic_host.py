@@ -312,3 +312,14 @@ def test_tile_columns_leave_no_residual_slope(edges):
         img, _, _ = hostcheck.pipeline(*xyz, (n, n, n), view, tile_rows=16, tile_cols=cols, edges=edges)
         assert np.abs(img - one).max() < 1e-12 * np.abs(one).max(), cols
         assert rel(img, ref) < 1e-5, cols
+
+
+def test_fast_floor_division_is_exact():
+    # the binning's and the raster's floor division of pixel coordinates by
+    # tile and image sizes takes the FP32 reciprocal plus one correction; it
+    # must be exact even with the reciprocal a few ulp off
+    import ctypes
+    f = hostcheck.lib().hc_floor_div_check
+    f.restype = ctypes.c_int64
+    for ulps in (0, 1, 4):
+        assert f(ulps) == 0, ulps

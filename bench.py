@@ -427,6 +427,8 @@ def main():
     tune = tess.make_tune(args.tile_rows, args.tile_cols, args.chunk, args.block)
     # the first call counts fragments (untimed); the timed calls take the
     # kernel times with HIP events on the stream and skip the count
+    torch.cuda.synchronize()
+    free_before = torch.cuda.mem_get_info()[0]
     _, st0 = tess.project(lat, view, out=out, tune=tune, stats=True)
     frags, spans, kinks = st0["fragments"], st0["spans"], st0["kinks"]
     timed_tune = tess.make_tune(args.tile_rows, args.tile_cols, args.chunk, args.block, counts=False)
@@ -445,6 +447,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms = wall * 1e3 / args.steps
+    # device memory the library's workspace took (its buffers only grow)
+    workspace_gb = (free_before - torch.cuda.mem_get_info()[0]) / 1e9
     img = out.double()
     checksum = float(img.mean().item())
 
@@ -481,6 +485,8 @@ def main():
         "spans": spans,
         "kinks": kinks,
         "kernel_ms": kernel,
+        "workspace_gb": workspace_gb,
+        "own_records": st0.get("own_records"),
         "fp64_dets": st["fp64_dets"],
         "bin_pairs": st["bin_pairs"],
         "work_items": st["work_items"],

@@ -204,6 +204,12 @@ typedef struct {
                                for this stream may hold after the call; a call
                                that would grow it beyond returns TESS_ENOMEM
                                before allocating anything.  0: no limit         */
+    uint64_t own_capacity;  /* edge form: payloads kept for the tetrahedra that
+                               keep their own record (steep or wide footprints,
+                               a fraction of a percent); those beyond are set
+                               up again and drawn by the overflow raster
+                               (correct, slower).  0: learned per shape from
+                               earlier calls (first guess: one in 64)          */
 } tess_tune;
 
 typedef struct {
@@ -227,9 +233,11 @@ typedef struct {
     uint64_t kinks;         /* row crossings of creases (break points) rastered,  */
                             /* the raster's unit of arithmetic; in the edge form  */
                             /* one per (mesh edge, row, tile)                     */
-    uint32_t overflow;      /* images whose pairs exceeded the pair capacity and  */
-                            /* were drawn by the overflow raster                  */
-    uint32_t reserved;
+    uint32_t overflow;      /* images drawn (in part) by the overflow raster: their */
+                            /* pairs exceeded the pair capacity, or (edge form)    */
+                            /* their tetrahedra with own records the payloads     */
+    uint32_t own_records;   /* edge form: tetrahedra that kept their own record   */
+                            /* (steep or wide footprints; summed over a batch)    */
 } tess_stats;
 
 /*

@@ -55,7 +55,8 @@ class TessTune(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("no_counts", ctypes.c_int32),
-                ("pair_capacity", ctypes.c_uint64), ("workspace_limit", ctypes.c_uint64)]
+                ("pair_capacity", ctypes.c_uint64), ("workspace_limit", ctypes.c_uint64),
+                ("own_capacity", ctypes.c_uint64)]
 
 
 # tess_form by name (make_tune(form=...))
@@ -74,7 +75,7 @@ class TessStats(ctypes.Structure):
                 ("setup_ms", ctypes.c_float), ("bin_ms", ctypes.c_float),
                 ("raster_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
                 ("kinks", ctypes.c_uint64), ("overflow", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("own_records", ctypes.c_uint32)]
 
     def as_dict(self) -> Dict:
         return {k: (float(getattr(self, k)) if k.endswith("ms") else int(getattr(self, k)))
@@ -221,7 +222,7 @@ def make_view(view: Dict) -> TessView:
 
 def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int = 0,
               form: str = "auto", pair_capacity: int = 0, counts: bool = True,
-              workspace_limit: int = 0) -> TessTune:
+              workspace_limit: int = 0, own_capacity: int = 0) -> TessTune:
     """Raster parameters; 0 (and form "auto") means automatic.  counts=False:
     calls with stats skip the edge form's fragment count (timings only)."""
     t = TessTune()
@@ -230,6 +231,7 @@ def make_tune(tile_rows: int = 0, tile_cols: int = 0, chunk: int = 0, block: int
     t.no_counts = 0 if counts else 1
     t.pair_capacity = int(pair_capacity)
     t.workspace_limit = int(workspace_limit)
+    t.own_capacity = int(own_capacity)
     return t
 
 

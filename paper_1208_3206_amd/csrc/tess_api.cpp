@@ -71,6 +71,7 @@ struct Workspace {
     DevBuf<EdgePayload> ecoef;          // edge form: the edges' payloads
     DevBuf<double> kinks;               // edge form: 36 slope-change slots per lattice vertex
     DevBuf<uint8_t> sil;                // and their silhouette kinds
+    DevBuf<uint32_t> spill;             // edge form: tetrahedra beyond the payload capacity (bits)
     DevBuf<uint32_t> counts;
     DevBuf<uint64_t> base;
     DevBuf<uint64_t> scan;
@@ -96,6 +97,7 @@ struct Workspace {
     std::string fb_key;
     hipEvent_t fb_event = nullptr;
     std::map<std::string, unsigned long long> learned;  // largest pair count seen per shape key
+    std::map<std::string, unsigned long long> learned_own;  // edge form: most tetrahedra with own records
     // batch graph (captured on `capture`, replayed on the caller's stream)
     hipStream_t capture = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -111,6 +113,7 @@ struct Bufs {
     EdgePayload *ecoef;
     double *kinks;
     uint8_t *sil;
+    uint32_t *spill;
     uint32_t *counts;
     uint64_t *base;
     uint64_t *scan;
@@ -122,8 +125,8 @@ struct Bufs {
 };
 
 Bufs bufs_of(Workspace &ws) {
-    return Bufs{ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p,
-                ws.tile_items.p, ws.items.p, ws.pairs.p, ws.acc.p, ws.counters.p};
+    return Bufs{ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.spill.p, ws.counts.p, ws.base.p,
+                ws.scan.p, ws.tile_items.p, ws.items.p, ws.pairs.p, ws.acc.p, ws.counters.p};
 }
 
 std::mutex g_ws_mu;
@@ -421,6 +424,7 @@ struct Plan {
     unsigned long long cap;    // pair capacity; 0: learned
     int counts;                // 0: a call with stats skips the edge raster's fragment count
     unsigned long long limit;  // workspace bytes allowed after the call; 0: no limit
+    unsigned long long own;    // edge form: payloads for tetrahedra with own records; 0: learned
 };
 
 // Default tiling: tiles of up to 512 columns with as many rows as the
@@ -441,6 +445,7 @@ Plan choose_plan(const tess_view *v, const tess_tune *tune) {
     p.cap = tune ? (unsigned long long)tune->pair_capacity : 0ull;
     p.counts = tune ? !tune->no_counts : 1;
     p.limit = tune ? (unsigned long long)tune->workspace_limit : 0ull;
+    p.own = tune ? (unsigned long long)tune->own_capacity : 0ull;
     return p;
 }
 
@@ -456,15 +461,27 @@ struct Geometry {
     ViewParams vp;
     BinParams B;
     int64_t ntet, ntiles, nmat, npix;
+    int64_t stored;  // tetrahedron payloads: all (6 ncubes), or (edge form) own_cap
+    int64_t spill;   // edge form: 32-bit words of the spill bit set (one spare)
 };
 
-tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Plan &plan, Geometry &g) {
+// own_cap: edge form, the payloads for the tetrahedra that keep their own
+// record (< 0: one per tetrahedron)
+tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Plan &plan, Geometry &g,
+                          int64_t own_cap = -1) {
     make_params(L, v, plan.form, g.lp, g.vp);
-    // records: the tetrahedra, then (edge form) seven edges per lattice vertex;
-    // the edge form only while all ids fit in 32 bits
+    // records: the tetrahedra (edge form: the few that keep their own record,
+    // own_cap of them), then (edge form) seven edges per lattice vertex; the
+    // edge form only while all ids fit in 32 bits
     const int64_t nvert = (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2];
-    if (g.vp.edges && 6 * g.lp.ncubes + 7 * nvert >= (int64_t)0xffffffff) g.vp.edges = 0;
-    g.ntet = 6 * g.lp.ncubes + (g.vp.edges ? 7 * nvert : 0);
+    const int64_t ntets = 6 * g.lp.ncubes;
+    if (g.vp.edges && ntets + 7 * nvert >= (int64_t)0xffffffff) g.vp.edges = 0;
+    g.stored = g.vp.edges && own_cap >= 0 ? std::min<int64_t>(own_cap, ntets) : ntets;
+    g.spill = g.vp.edges ? (ntets + 31) / 32 + 1 : 0;
+    g.vp.own_cap = (uint64_t)g.stored;
+    g.vp.own = nullptr;
+    g.vp.spill = nullptr;
+    g.ntet = g.stored + (g.vp.edges ? 7 * nvert : 0);
     BinParams &B = g.B;
     B.Th = plan.Th;
     B.Tw = plan.Tw;
@@ -492,7 +509,7 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
     B.ext_v = v->extent[1];
     B.form = view_form(g.vp);
     B.edges = g.vp.edges;
-    B.first_edge = (uint32_t)(6 * g.lp.ncubes);
+    B.first_edge = (uint32_t)g.stored;
     B.seam = g.vp.edges && v->wrap ? 1 : 0;
     B.groups = nullptr;
     g.nmat = g.ntiles * B.nseg;
@@ -502,13 +519,14 @@ tess_status make_geometry(const tess_lattice_s *L, const tess_view *v, const Pla
 
 // Largest buffer sizes over the images of a call.
 struct Sizes {
-    int64_t records = 0, tets = 0, edges = 0, slots = 0, nmat = 0, ntiles = 0, npix = 0;
+    int64_t records = 0, tets = 0, edges = 0, slots = 0, spill = 0, nmat = 0, ntiles = 0, npix = 0;
     void add(const Geometry &g) {
         records = std::max(records, g.ntet);
-        tets = std::max(tets, 6 * g.lp.ncubes);
+        tets = std::max(tets, g.stored);
         if (g.vp.edges) {
-            edges = std::max(edges, g.ntet - 6 * g.lp.ncubes);
+            edges = std::max(edges, g.ntet - g.stored);
             slots = std::max(slots, (int64_t)36 * g.lp.d[0] * g.lp.d[1] * g.lp.d[2]);
+            spill = std::max(spill, g.spill);
         }
         nmat = std::max(nmat, g.nmat);
         ntiles = std::max(ntiles, g.ntiles);
@@ -525,9 +543,10 @@ size_t workspace_bytes_after(const Workspace &ws, const Sizes &z, int chunk, uns
     b += ws.head.bytes_after((size_t)z.records) + ws.coef.bytes_after((size_t)z.tets);
     if (z.edges)
         b += ws.ecoef.bytes_after((size_t)z.edges) + ws.kinks.bytes_after((size_t)z.slots) +
-             ws.sil.bytes_after((size_t)z.slots);
+             ws.sil.bytes_after((size_t)z.slots) + ws.spill.bytes_after((size_t)z.spill);
     else
-        b += ws.ecoef.cap * sizeof(EdgePayload) + ws.kinks.cap * sizeof(double) + ws.sil.cap;
+        b += ws.ecoef.cap * sizeof(EdgePayload) + ws.kinks.cap * sizeof(double) + ws.sil.cap +
+             ws.spill.cap * sizeof(uint32_t);
     b += ws.counts.bytes_after((size_t)z.nmat) + ws.base.bytes_after((size_t)z.nmat) +
          ws.scan.bytes_after(scan_scratch_elems(z.nmat)) + ws.tile_items.bytes_after((size_t)z.ntiles + 1) +
          ws.acc.bytes_after((size_t)z.npix) + ws.counters.bytes_after(1) + ws.overflow.bytes_after(1) +
@@ -554,6 +573,7 @@ tess_status ensure_front(Workspace &ws, const Sizes &z) {
         TESS_HIP(ws.ecoef.ensure((size_t)z.edges));
         TESS_HIP(ws.kinks.ensure((size_t)z.slots));
         TESS_HIP(ws.sil.ensure((size_t)z.slots));
+        TESS_HIP(ws.spill.ensure((size_t)z.spill));
     }
     TESS_HIP(ws.counts.ensure((size_t)z.nmat));
     TESS_HIP(ws.base.ensure((size_t)z.nmat));
@@ -585,6 +605,16 @@ tess_status enqueue_setup(const Geometry &g, const Bufs &b, PlanOut *slot, hipSt
     }
     vp.kinks = b.kinks;
     vp.sil = b.sil;
+    TESS_HIP(launch_zero((double *)&slot->own, 1, s));  // (+0.0: all bits zero)
+    if (vp.edges) {
+        // the numbered records start invalid (setup fills as many as it
+        // finds), the spill set empty
+        vp.own = &slot->own;
+        vp.spill = b.spill;
+        static_assert(sizeof(RecHead) == 2 * sizeof(double), "head as two doubles");
+        TESS_HIP(launch_zero((double *)b.head, 2 * g.stored, s));
+        TESS_HIP(launch_zero((double *)b.spill, g.spill / 2, s));
+    }
     TESS_HIP(launch_setup(g.lp, vp, b.head, b.coef, b.counters, s));
     if (vp.edges) TESS_HIP(launch_edges(g.lp, vp, b.head, b.ecoef, s));
     return TESS_OK;
@@ -617,7 +647,12 @@ tess_status enqueue_back(const Geometry &g, const Plan &plan, int chunk, unsigne
     B.groups = b.kinks;  // the edge records' sums by period offset (written over the slots)
     TESS_HIP(launch_raster(b.head, b.coef, b.ecoef, b.pairs, b.items, max_items_for(g.ntiles, chunk, cap), slot,
                            B, plan.block, count, b.acc, b.counters, s));
-    TESS_HIP(launch_raster_direct(b.head, b.coef, b.ecoef, slot, cap, B, b.acc, b.counters, s));
+    ViewParams vp = g.vp;
+    vp.kinks = b.kinks;
+    vp.sil = b.sil;
+    vp.own = &slot->own;
+    vp.spill = b.spill;
+    TESS_HIP(launch_raster_direct(g.lp, vp, b.head, b.coef, b.ecoef, slot, cap, B, b.acc, b.counters, s));
     if (after_raster) TESS_HIP(hipEventRecord(after_raster, s));
     TESS_HIP(launch_finalize(b.acc, g.B, image, s));
     return TESS_OK;
@@ -654,6 +689,18 @@ std::string count_key(const Geometry &g) {
 
 unsigned long long capacity_for(unsigned long long most) { return most + most / 4 + 4096; }
 
+// Edge form: payloads for the tetrahedra that keep their own record (steep
+// or wide footprints): from the most seen for this shape, else a first guess
+// of one in 64 (measured: 0.2 % on a 64^3 lattice at 8 pixels per cell);
+// those beyond are drawn by the overflow raster and raise the next call's.
+int64_t own_capacity(const Workspace &ws, const Geometry &g0, const std::string &key, const Plan &plan) {
+    const int64_t ntets = 6 * g0.lp.ncubes;
+    if (plan.own) return std::min<int64_t>((int64_t)plan.own, ntets);
+    auto it = ws.learned_own.find(key);
+    const int64_t want = it != ws.learned_own.end() ? (int64_t)capacity_for(it->second) : ntets / 64 + 65536;
+    return std::min<int64_t>(want, ntets);
+}
+
 // First guess without any count: four pairs per record (the stress workload
 // at 2048^2 with 32 x 512 tiles has 3.3), within [2^20, 2^31].
 unsigned long long first_guess(const Geometry &g) {
@@ -673,10 +720,17 @@ void take_feedback(Workspace &ws, hipStream_t s) {
         (void)hipGetLastError();  // not ready (or failed): try again on a later call
         return;
     }
-    unsigned long long most = 0;
-    for (int k = 0; k < ws.fb_n; ++k) most = std::max<unsigned long long>(most, ws.fb_plan[k].total_pairs);
+    unsigned long long most = 0, own = 0;
+    for (int k = 0; k < ws.fb_n; ++k) {
+        most = std::max<unsigned long long>(most, ws.fb_plan[k].total_pairs);
+        own = std::max<unsigned long long>(own, ws.fb_plan[k].own);
+    }
     unsigned long long &m = ws.learned[ws.fb_key];
     m = std::max(m, most);
+    if (own) {
+        unsigned long long &o = ws.learned_own[ws.fb_key];
+        o = std::max(o, own);
+    }
     ws.fb_pending = false;
 }
 
@@ -704,10 +758,14 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     Geometry g;
     tess_status st = make_geometry(L, v, plan, g);
     if (st != TESS_OK) return st;
-    Sizes z;
-    z.add(g);
     take_feedback(ws, s);
     const std::string key = count_key(g);
+    if (g.vp.edges) {
+        st = make_geometry(L, v, plan, g, own_capacity(ws, g, key, plan));
+        if (st != TESS_OK) return st;
+    }
+    Sizes z;
+    z.add(g);
     auto it = ws.learned.find(key);
     const bool known = it != ws.learned.end();
     const unsigned long long cap = plan.cap ? plan.cap : (known ? capacity_for(it->second) : first_guess(g));
@@ -745,11 +803,16 @@ tess_status project_impl(const tess_lattice_s *L, const tess_view *v, const Plan
     const PlanOut &P = *ws.host_plan;
     unsigned long long &m = ws.learned[key];
     m = std::max<unsigned long long>(m, P.total_pairs);
+    if (g.vp.edges) {
+        unsigned long long &o = ws.learned_own[key];
+        o = std::max<unsigned long long>(o, P.own);
+    }
     fill_stats(stats, *ws.host_counters, plan, chunk);
     stats->bin_pairs = P.total_pairs;
     stats->max_bin = (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull);
     stats->work_items = (uint32_t)P.n_items;
-    stats->overflow = P.total_pairs > cap ? 1u : 0u;
+    stats->overflow = P.total_pairs > cap || (g.vp.edges && P.own > g.vp.own_cap) ? 1u : 0u;
+    stats->own_records = (uint32_t)std::min<unsigned long long>(P.own, 0xffffffffull);
     stats->ms = ms;
     stats->setup_ms = t_setup;
     stats->bin_ms = t_bin;
@@ -809,12 +872,13 @@ std::string shape_key(const tess_lattice_s *L, const tess_view *v, int n_snaps, 
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) (void)hipGetLastError();
     std::string arch(prop.gcnArchName);
     arch = arch.substr(0, arch.find(':'));
-    snprintf(buf, sizeof(buf), "%s/%dcu|%d:%d:%d:%d|%dx%d:%d:%d:%d:%d:%d|%d:%d|tune %d %d %d %d %d %llu",
+    snprintf(buf, sizeof(buf), "%s/%dcu|%d:%d:%d:%d|%dx%d:%d:%d:%d:%d:%d|%d:%d|tune %d %d %d %d %d %llu %llu",
              arch.c_str(), prop.multiProcessorCount, L->desc.dims[0], L->desc.dims[1], L->desc.dims[2],
              L->desc.periodic, v->width, v->height, v->wrap, v->quantity, v->slab, v->method, v->projection,
              n_snaps, n_views, tune ? tune->tile_rows : 0, tune ? tune->tile_cols : 0, tune ? tune->chunk : 0,
              tune ? tune->block : 0, tune ? tune->form : 0,
-             tune ? (unsigned long long)tune->pair_capacity : 0ull);
+             tune ? (unsigned long long)tune->pair_capacity : 0ull,
+             tune ? (unsigned long long)tune->own_capacity : 0ull);
     return buf;
 }
 
@@ -1001,7 +1065,7 @@ tess_status tune_batch(const tess_lattice *snaps, int n_snaps, const tess_view *
 }
 
 std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *views, int n_views, float *images,
-                      const Tuned &t, const Workspace &ws) {
+                      const Tuned &t, int64_t own_cap, const Workspace &ws) {
     std::string k;
     auto put = [&](const void *p, size_t n) { k.append((const char *)p, n); };
     for (int i = 0; i < n_snaps; ++i) {
@@ -1013,8 +1077,10 @@ std::string graph_key(const tess_lattice *snaps, int n_snaps, const tess_view *v
     put(views, sizeof(tess_view) * (size_t)n_views);
     put(&images, sizeof(images));
     put(&t, sizeof(t));
-    const void *bufs[] = {ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.counts.p, ws.base.p, ws.scan.p, ws.tile_items.p,
-                          ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p, ws.overflow.p};
+    put(&own_cap, sizeof(own_cap));
+    const void *bufs[] = {ws.head.p, ws.coef.p, ws.ecoef.p, ws.kinks.p, ws.sil.p, ws.spill.p, ws.counts.p, ws.base.p,
+                          ws.scan.p, ws.tile_items.p, ws.items.p, ws.pairs.p, ws.acc.p, ws.plan.p, ws.counters.p,
+                          ws.overflow.p};
     put(bufs, sizeof(bufs));
     return k;
 }
@@ -1065,12 +1131,20 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
         }
     }
     // buffers for the largest image of the batch (forms and sizes may differ
-    // between images), then the graph
+    // between images), then the graph; edge-form images store the payloads of
+    // as many tetrahedra with own records as the batch was seen to need
+    int64_t own_cap = -1;
+    {
+        Geometry g0;
+        tess_status st = make_geometry(snaps[0], &views[0], t.plan, g0);
+        if (st != TESS_OK) return st;
+        own_cap = own_capacity(ws, g0, count_key, t.plan);
+    }
     Sizes z;
     for (int i = 0; i < n_snaps; ++i)
         for (int v = 0; v < n_views; ++v) {
             Geometry g;
-            tess_status st = make_geometry(snaps[i], &views[v], t.plan, g);
+            tess_status st = make_geometry(snaps[i], &views[v], t.plan, g, own_cap);
             if (st != TESS_OK) return st;
             z.add(g);
         }
@@ -1088,7 +1162,7 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
         TESS_HIP(hipHostMalloc((void **)&ws.host_plan, sizeof(PlanOut) * (size_t)n_img, hipHostMallocDefault));
         ws.host_plan_cap = (size_t)n_img;
     }
-    const std::string gkey = graph_key(snaps, n_snaps, views, n_views, images, t, ws);
+    const std::string gkey = graph_key(snaps, n_snaps, views, n_views, images, t, own_cap, ws);
     if (!ws.graph || ws.graph_key != gkey) {
         if (ws.graph) {
             TESS_HIP(hipGraphExecDestroy(ws.graph));
@@ -1102,7 +1176,7 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
                 for (int v = 0; v < n_views; ++v) {
                     const int k = i * n_views + v;
                     Geometry g;
-                    tess_status r = make_geometry(snaps[i], &views[v], t.plan, g);
+                    tess_status r = make_geometry(snaps[i], &views[v], t.plan, g, own_cap);
                     if (r != TESS_OK) return r;
                     r = enqueue_front(g, bufs_of(ws), ws.plan.p + k, t.cap, nullptr, c);
                     if (r != TESS_OK) return r;
@@ -1142,17 +1216,24 @@ tess_status project_batch_impl(const tess_lattice *snaps, int n_snaps, const tes
     TESS_HIP(hipEventElapsedTime(&ms, ws.ev[0], ws.ev[4]));
     fill_stats(&acc, *ws.host_counters, t.plan, t.chunk);
     acc.ms = ms;
-    unsigned long long most = 0;
+    unsigned long long most = 0, own = 0;
     for (int k = 0; k < n_img; ++k) {
         const PlanOut &P = ws.host_plan[k];
         acc.bin_pairs += P.total_pairs;
         acc.max_bin = std::max<uint32_t>(acc.max_bin, (uint32_t)std::min<unsigned long long>(P.max_bin, 0xffffffffull));
         acc.work_items += (uint32_t)P.n_items;
-        acc.overflow += P.total_pairs > t.cap ? 1u : 0u;
+        // (P.own is 0 for images not in the edge form)
+        acc.overflow += P.total_pairs > t.cap || (own_cap >= 0 && P.own > (unsigned long long)own_cap) ? 1u : 0u;
+        acc.own_records += (uint32_t)std::min<unsigned long long>(P.own, 0xffffffffull);
         most = std::max<unsigned long long>(most, P.total_pairs);
+        own = std::max<unsigned long long>(own, P.own);
     }
     unsigned long long &m = ws.learned[count_key];
     m = std::max(m, most);
+    if (own) {
+        unsigned long long &o = ws.learned_own[count_key];
+        o = std::max(o, own);
+    }
     *stats = acc;
     return TESS_OK;
 }
@@ -1207,11 +1288,12 @@ extern "C" tess_status tess_project_noalloc(tess_lattice L, const tess_view *v, 
     Carve c{static_cast<unsigned char *>(sp)};
     Bufs b;
     b.head = c.take<RecHead>((size_t)g.ntet);
-    b.coef = c.take<Payload>((size_t)(6 * g.lp.ncubes));
+    b.coef = c.take<Payload>((size_t)g.stored);
     const int64_t nvert = (int64_t)g.lp.d[0] * g.lp.d[1] * g.lp.d[2];
-    b.ecoef = g.vp.edges ? c.take<EdgePayload>((size_t)(g.ntet - 6 * g.lp.ncubes)) : nullptr;
+    b.ecoef = g.vp.edges ? c.take<EdgePayload>((size_t)(g.ntet - g.stored)) : nullptr;
     b.kinks = g.vp.edges ? c.take<double>((size_t)(36 * nvert)) : nullptr;
     b.sil = g.vp.edges ? c.take<uint8_t>((size_t)(36 * nvert)) : nullptr;
+    b.spill = g.vp.edges ? c.take<uint32_t>((size_t)g.spill) : nullptr;
     b.counts = c.take<uint32_t>((size_t)g.nmat);
     b.base = c.take<uint64_t>((size_t)g.nmat);
     b.scan = c.take<uint64_t>(scan_scratch_elems(g.nmat));

@@ -46,7 +46,7 @@ struct DevBuf {
             cap = 0;
         }
         size_t want = std::max(n, (size_t)64);
-        want += want / 8;  // headroom against small growth steps
+        want += std::min(want / 8, headroom_max());  // headroom against small growth steps
         hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
         if (e != hipSuccess) {
             p = nullptr;
@@ -59,8 +59,10 @@ struct DevBuf {
     size_t bytes_after(size_t n) const {
         if (n <= cap) return cap * sizeof(T);
         const size_t want = std::max(n, (size_t)64);
-        return (want + want / 8) * sizeof(T);
+        return (want + std::min(want / 8, headroom_max())) * sizeof(T);
     }
+    // at most 64 MiB of headroom (an eighth of a multi-GB buffer would be GBs)
+    static size_t headroom_max() { return ((size_t)64 << 20) / sizeof(T); }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;

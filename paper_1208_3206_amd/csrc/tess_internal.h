@@ -50,6 +50,15 @@ struct ViewParams {
     int32_t edges;
     double *kinks;
     uint8_t *sil;
+    // edge form: the few tetrahedra that keep their own record are numbered
+    // in the order setup reaches them (*own counts them); the first own_cap
+    // become records 0 .. own_cap - 1 (head and payload, the edge records
+    // follow from id own_cap); the others are marked in the bit set `spill`
+    // (bit 6 cube + t) and drawn by the overflow raster, which sets them up
+    // again
+    uint64_t own_cap;
+    unsigned long long *own;
+    uint32_t *spill;
 };
 
 // Record kinds of a launch (one per view): the pyramid (crease and line
@@ -103,6 +112,7 @@ struct PlanOut {
     unsigned long long n_items;
     unsigned long long max_bin;
     double qsum;                    // integral of q over the tetrahedra (qpow != 1)
+    unsigned long long own;         // edge form: tetrahedra that keep their own record
 };
 
 // Raster work item: a chunk of one tile's list.
@@ -199,7 +209,7 @@ hipError_t launch_qsum(const LatticeParams &L, const ViewParams &V, double *qsum
 hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream);
 
-// Edge records 6 ncubes + tau nvert + v of every lattice vertex v from the
+// Edge records V.own_cap + tau nvert + v of every lattice vertex v from the
 // kinks setup wrote (edge form).
 hipError_t launch_edges(const LatticeParams &L, const ViewParams &V, RecHead *head, EdgePayload *ecoef,
                         hipStream_t stream);
@@ -246,10 +256,13 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
 
 // Overflow raster: when plan->total_pairs > cap (the image's tile lists were
 // dropped), every record over the whole image with L2 atomics into acc;
-// otherwise the launch returns at once.
-hipError_t launch_raster_direct(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
-                                const PlanOut *plan, unsigned long long cap, const BinParams &B, double *acc,
-                                DevCounters *counters, hipStream_t stream);
+// and (edge form) when plan->own > V.own_cap, the tetrahedra marked in
+// V.spill, set up again from the lattice; otherwise the launch returns at
+// once.
+hipError_t launch_raster_direct(const LatticeParams &L, const ViewParams &V, const RecHead *head,
+                                const Payload *coef, const EdgePayload *ecoef, const PlanOut *plan,
+                                unsigned long long cap, const BinParams &B, double *acc, DevCounters *counters,
+                                hipStream_t stream);
 
 // Row-wise double prefix sum of acc -> image (FP32).
 hipError_t launch_finalize(const double *acc, const BinParams &B, float *image, hipStream_t stream);

@@ -62,10 +62,48 @@ __global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
     CubeCounts cnt;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
-    for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
-        // records written in place as they are built (holding six 144-byte
-        // records in registers would cost the occupancy)
-        setup_cube<FORM, EDGES>(L, V, cube, head + 6 * cube, coef + 6 * cube, cnt);
+    if constexpr (EDGES) {
+        // edge form: only the few tetrahedra that keep their own record are
+        // stored, numbered as they come (their heads and payloads; the
+        // others' creases went to the edge slots)
+        for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride)
+            setup_cube<FORM, EDGES>(
+                L, V, cube,
+                [&](int t, const RecHead &R, const Payload &P) {
+                    if (!(R.flags & REC_VALID)) return;
+                    const unsigned long long slot = atomicAdd(V.own, 1ull);
+                    if (slot < V.own_cap) {
+                        head[slot] = R;
+                        coef[slot] = P;
+                    } else {
+                        const int64_t tet = 6 * cube + t;
+                        atomicOr(&V.spill[tet >> 5], 1u << (tet & 31));
+                    }
+                },
+                cnt);
+    } else {
+        // The block's heads are built in LDS and then written as one
+        // contiguous run: a thread's six 16-byte heads written in place would
+        // make every store instruction touch 64 lines a quarter each (partial
+        // lines cost a read-modify-write in HBM).  Payloads are written in
+        // place as they are built (holding six 144-byte records in registers
+        // would cost the occupancy; they are whole 128-byte lines).
+        __shared__ RecHead sh_head[6 * 256];
+        for (int64_t first = (int64_t)blockIdx.x * blockDim.x; first < L.ncubes; first += stride) {
+            const int64_t cube = first + threadIdx.x;
+            if (cube < L.ncubes)
+                setup_cube<FORM, EDGES>(
+                    L, V, cube,
+                    [&](int t, const RecHead &R, const Payload &P) {
+                        sh_head[6 * threadIdx.x + t] = R;
+                        if (R.flags & REC_VALID) coef[6 * cube + t] = P;  // nothing reads other payloads
+                    },
+                    cnt);
+            __syncthreads();
+            const int nh = 6 * (int)(L.ncubes - first < 256 ? L.ncubes - first : 256);
+            for (int i = threadIdx.x; i < nh; i += 256) head[6 * first + i] = sh_head[i];
+            __syncthreads();
+        }
     }
     const unsigned long long n_tets = wave_sum(cnt.n_tets), n_zero = wave_sum(cnt.n_zero),
                              n_inv = wave_sum(cnt.n_inv), n_dets = wave_sum(cnt.n_dets),
@@ -80,11 +118,11 @@ __global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
 }
 
 // Edge form: one thread per lattice vertex, its seven edge records after
-// the tetrahedra's (ids 6 ncubes + tau nvert + v).
+// the tetrahedra's (ids own_cap + tau nvert + v).
 __global__ void __launch_bounds__(256) k_edges(LatticeParams L, ViewParams V, RecHead *__restrict__ head,
                                                EdgePayload *__restrict__ ecoef) {
     const int64_t nv = (int64_t)L.d[0] * L.d[1] * L.d[2];
-    const int64_t first = 6 * L.ncubes;
+    const int64_t first = (int64_t)V.own_cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride)
         setup_vertex_edges(L, V, v, head + first + v, ecoef + v);
@@ -156,8 +194,8 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
 // to its place in the pair list: whole runs instead of single 4-byte writes
 // all over the list.  A segment with more pairs than the stage holds writes
 // its ids directly.
-constexpr int kBinBlock = 256;
-constexpr int kStage = 8192;      // staged pair ids per segment (32 KiB of LDS)
+constexpr int kBinBlock = 512;
+constexpr int kStage = 16384;     // staged pair ids per segment (64 KiB of LDS)
 
 // Exclusive scan of v over the block's kBinBlock threads (sh: kBinBlock / 64 + 1 words).
 __device__ inline uint32_t bin_block_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
@@ -270,8 +308,8 @@ __global__ void __launch_bounds__(kBinBlock) k_bin(const RecHead *__restrict__ h
 }
 
 // one 32-bit LDS counter per tile, in both passes; the scatter's stage
-// beside them while the counters leave room for it in 64 KiB
-static bool bin_staged(const BinParams &B) { return (size_t)B.ntx * B.nty + kStage <= 16384; }
+// beside them while the counters leave room for it in 96 KiB
+static bool bin_staged(const BinParams &B) { return (size_t)B.ntx * B.nty + kStage <= 24576; }
 static size_t bin_lds_bytes(const BinParams &B, bool scatter) {
     return sizeof(uint32_t) * ((size_t)B.ntx * B.nty + (scatter && bin_staged(B) ? kStage : 0));
 }
@@ -695,7 +733,8 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             // A pair's id and payload are two dependent loads; the next
             // pair's are issued before this one is drawn, so that they arrive
             // while it is (one wavefront per SIMD quarter has too little
-            // other work to hide them otherwise).
+            // other work to hide them otherwise).  (Two pairs ahead measured
+            // slower: more registers in flight.)
             auto id_at = [&](uint32_t e) { return e < it.count ? pairs[it.first + e] : 0xffffffffu; };
             auto is_edge = [&](uint32_t id) { return id < B.ntet && id >= B.first_edge; };
             // a kink's two entries, at columns j and j + 1
@@ -870,18 +909,22 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
 constexpr int kDirectRows = 256;
 
 template <int FORM>
-__global__ void __launch_bounds__(256) k_raster_direct(const RecHead *__restrict__ head,
+__global__ void __launch_bounds__(256) k_raster_direct(LatticeParams L, ViewParams V,
+                                                       const RecHead *__restrict__ head,
                                                        const Payload *__restrict__ coef,
                                                        const EdgePayload *__restrict__ ecoef,
                                                        const PlanOut *__restrict__ plan, unsigned long long cap,
                                                        BinParams B, double *__restrict__ acc,
                                                        DevCounters *__restrict__ counters) {
-    if (plan->total_pairs <= cap) return;
+    const bool lists_dropped = plan->total_pairs > cap;
+    const bool spilled = FORM == kFormEdge && plan->own > V.own_cap;
+    if (!lists_dropped && !spilled) return;
     long long frags = 0;
     uint32_t spans = 0, kinks = 0;
     const int W = B.W;
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < (int64_t)B.ntet;
-         id += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+    // one record over the whole image, row band by row band
+    auto draw = [&](const RecHead &h, const double *cf) {
         for (int ty0 = 0; ty0 < B.H; ty0 += kDirectRows) {
             const int rows = min(kDirectRows, B.H - ty0);
             auto dep = [&](int row, int j, double v) {
@@ -891,31 +934,74 @@ __global__ void __launch_bounds__(256) k_raster_direct(const RecHead *__restrict
                 unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W], a);
                 if (W > 1) unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W + 1], b - a);
             };
+            if constexpr (FORM == kFormPersp)
+                frags += persp_pair(h, cf, B, 0, ty0, W, rows, 0, 1, dep, spans, kinks);
+            else
+                frags += (int32_t)raster_record<FORM == kFormEdge ? kFormPyramid : FORM>(
+                    h, cf, B, 0, ty0, W, rows, dep, seam, spans, kinks);
+        }
+    };
+    if (lists_dropped)
+        for (int64_t id = tid; id < (int64_t)B.ntet; id += nth) {
+            const RecHead h = head[id];
+            if (!(h.flags & REC_VALID)) continue;
             if constexpr (FORM == kFormEdge) {
                 if ((uint32_t)id >= B.first_edge) {
-                    const RecHead h = head[id];
-                    if (!(h.flags & REC_VALID)) break;
-                    frags += (int32_t)edge_pair(
-                        ecoef[id - B.first_edge], (uint32_t)id - B.first_edge, h.spare, B, 0, ty0, W, rows,
-                        [&](int row, int j, double v1, double v2) {
-                            dep(row, j, v1);
-                            dep(row, j + 1, v2);
-                        },
-                        seam,
-                        [&](int lo, int hi, double alpha, double beta, double gamma) {
-                            for (int r = lo; r <= hi; ++r) seam(r, alpha + beta * (double)r, gamma);
-                        },
-                        kinks);
+                    for (int ty0 = 0; ty0 < B.H; ty0 += kDirectRows) {
+                        const int rows = min(kDirectRows, B.H - ty0);
+                        auto dep = [&](int row, int j, double v) {
+                            if (j >= 0 && j < W) unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W + j], v);
+                        };
+                        auto seam = [&](int row, double a, double b) {
+                            unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W], a);
+                            if (W > 1) unsafeAtomicAdd(&acc[(int64_t)(ty0 + row) * W + 1], b - a);
+                        };
+                        frags += (int32_t)edge_pair(
+                            ecoef[id - B.first_edge], (uint32_t)id - B.first_edge, h.spare, B, 0, ty0, W, rows,
+                            [&](int row, int j, double v1, double v2) {
+                                dep(row, j, v1);
+                                dep(row, j + 1, v2);
+                            },
+                            seam,
+                            [&](int lo, int hi, double alpha, double beta, double gamma) {
+                                for (int r = lo; r <= hi; ++r) seam(r, alpha + beta * (double)r, gamma);
+                            },
+                            kinks);
+                    }
                     continue;
                 }
             }
-            const RecHead h = head[id];
-            if (!(h.flags & REC_VALID)) break;
-            if constexpr (FORM == kFormPersp)
-                frags += persp_pair(h, coef[id].c, B, 0, ty0, W, rows, 0, 1, dep, spans, kinks);
-            else
-                frags += (int32_t)raster_record<FORM == kFormEdge ? kFormPyramid : FORM>(
-                    h, coef[id].c, B, 0, ty0, W, rows, dep, seam, spans, kinks);
+            draw(h, coef[id].c);
+        }
+    if constexpr (FORM == kFormEdge) {
+        // tetrahedra beyond the payload capacity: set up again (the same
+        // record: the per-tetrahedron code of the edge form's setup without
+        // its edge branch, which these did not take) and drawn
+        if (spilled) {
+            const int64_t nwords = (6 * L.ncubes + 31) / 32;
+            for (int64_t w = tid; w < nwords; w += nth) {
+                uint32_t bits = V.spill[w];
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const int64_t tet = 32 * w + b;
+                    const int64_t cube = tet / 6;
+                    const int t = (int)(tet - 6 * cube);
+                    RecHead h{};
+                    Payload P;
+                    CubeCounts cc;
+                    setup_cube<kFormPyramid, false>(
+                        L, V, cube,
+                        [&](int tt, const RecHead &R, const Payload &Q) {
+                            if (tt == t) {
+                                h = R;
+                                P = Q;
+                            }
+                        },
+                        cc);
+                    if (h.flags & REC_VALID) draw(h, P.c);
+                }
+            }
         }
     }
     const unsigned long long f = wave_sum((unsigned long long)frags);
@@ -928,33 +1014,34 @@ __global__ void __launch_bounds__(256) k_raster_direct(const RecHead *__restrict
     }
 }
 
-hipError_t launch_raster_direct(const RecHead *head, const Payload *coef, const EdgePayload *ecoef,
-                                const PlanOut *plan, unsigned long long cap, const BinParams &B, double *acc,
-                                DevCounters *counters, hipStream_t stream) {
+hipError_t launch_raster_direct(const LatticeParams &L, const ViewParams &V, const RecHead *head,
+                                const Payload *coef, const EdgePayload *ecoef, const PlanOut *plan,
+                                unsigned long long cap, const BinParams &B, double *acc, DevCounters *counters,
+                                hipStream_t stream) {
     // a small grid (threads stride over the records): the launch costs next
     // to nothing for the images that do not overflow
     const int64_t want = ((int64_t)B.ntet + 255) / 256;
     const dim3 grid((unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048)), block(256);
     switch (B.form) {
         case kFormFace:
-            hipLaunchKernelGGL(k_raster_direct<kFormFace>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,
-                               counters);
+            hipLaunchKernelGGL(k_raster_direct<kFormFace>, grid, block, 0, stream, L, V, head, coef, ecoef, plan, cap,
+                               B, acc, counters);
             break;
         case kFormSplat:
-            hipLaunchKernelGGL(k_raster_direct<kFormSplat>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,
-                               counters);
+            hipLaunchKernelGGL(k_raster_direct<kFormSplat>, grid, block, 0, stream, L, V, head, coef, ecoef, plan, cap,
+                               B, acc, counters);
             break;
         case kFormPersp:
-            hipLaunchKernelGGL(k_raster_direct<kFormPersp>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B, acc,
-                               counters);
+            hipLaunchKernelGGL(k_raster_direct<kFormPersp>, grid, block, 0, stream, L, V, head, coef, ecoef, plan, cap,
+                               B, acc, counters);
             break;
         default:
             if (B.edges)
-                hipLaunchKernelGGL(k_raster_direct<kFormEdge>, grid, block, 0, stream, head, coef, ecoef, plan, cap, B,
-                                   acc, counters);
+                hipLaunchKernelGGL(k_raster_direct<kFormEdge>, grid, block, 0, stream, L, V, head, coef, ecoef, plan,
+                                   cap, B, acc, counters);
             else
-                hipLaunchKernelGGL(k_raster_direct<kFormPyramid>, grid, block, 0, stream, head, coef, ecoef, plan, cap,
-                                   B, acc, counters);
+                hipLaunchKernelGGL(k_raster_direct<kFormPyramid>, grid, block, 0, stream, L, V, head, coef, ecoef, plan,
+                                   cap, B, acc, counters);
     }
     return hipGetLastError();
 }

@@ -517,12 +517,13 @@ TESS_HD inline double vertex_px(const LatticeParams &L, const ViewParams &V, int
 
 // Setup of the six tetrahedra of lattice cube `cube` (EDGES: the edge form's
 // code, used when V.edges is set): gather and unwrap the
-// corners, volume determinant with its FP64 fallback, footprint.  head[t] and
-// coef[t] form the record of tetrahedron 6*cube + t (flags 0 when it can
-// cover no pixel centre).
-template <int FORM, bool EDGES = false>
-TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, RecHead head[6],
-                               Payload coef[6], CubeCounts &cnt) {
+// corners, volume determinant with its FP64 fallback, footprint.  Each
+// tetrahedron t's record goes to emit(t, head, payload) (flags 0 when it can
+// cover no pixel centre; REC_EDGED when its creases went to its edges' slots,
+// which setup_cube writes itself).
+template <int FORM, bool EDGES = false, typename Emit>
+TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, Emit &&emit,
+                               CubeCounts &cnt) {
     double X0[3], e[8][3];
     const bool moved = cube_corners(L, cube, X0, e);
     const int64_t ci = cube % L.c[0], cj = (cube / L.c[0]) % L.c[1], ck = cube / ((int64_t)L.c[0] * L.c[1]);
@@ -869,8 +870,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         P.h = R;
 #pragma unroll
         for (int g = 0; g < 14; ++g) P.c[g] = pc[g];
-        head[t] = R;
-        if (R.flags & REC_VALID) coef[t] = P;  // nothing reads the payload of other records
+        emit(t, R, P);
         if constexpr (FORM == kFormPyramid && EDGES) {
             if (V.edges) {
                 // every slot of the cube's tetrahedra is written (zeros for
@@ -1984,6 +1984,7 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
                 r0 = max(q0, (int)floor(ya));
                 r1 = min(q1, (int)ceil(yb));
             }
+            kinks += (uint32_t)max(r1 - r0 + 1, 0);
             // record columns of the clamp: tile columns -3 .. n - 1
             const int klo = shift - 3, khi = shift + n - 1;
             // the seam line of a crossing at canonical position u: the groups
@@ -1999,31 +2000,14 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
             const bool seamed = B.seam && (A1 != 0.0 || (A0 != 0.0 && near_end));
             double rv = (double)r0;
             if (!COUNT) {
-                // The rows with an entry in the tile's columns, kf = floor(u)
-                // - shift in [-2, n - 2] (contiguous: kf is monotone in r), the
-                // guesses moved to the exact ends with the loop's own
-                // arithmetic; in between, every kf lies between those at the
-                // ends, so the entries need no clamp.  A kink is counted in
-                // the tile that holds the column right of it (kf >= -1).
-                auto kf_at = [&](int r) { return (int)floor(fma((double)r, sl, base)) - shift; };
-                int a0 = r0, a1 = r1, k0 = 0, k1 = 0;
-                for (; a0 <= a1; ++a0) {
-                    k0 = kf_at(a0);
-                    if (k0 >= -2 && k0 <= n - 2) break;
-                }
-                for (; a1 >= a0; --a1) {
-                    k1 = kf_at(a1);
-                    if (k1 >= -2 && k1 <= n - 2) break;
-                }
-                if (a0 <= a1) kinks += (uint32_t)(a1 - a0 + 1 - (k0 == -2) - (a1 > a0 && k1 == -2));
-                const double rend = (double)a1 + 0.5;
-                const int c1 = 1 - shift;
-                int row = a0 + rshift;
-                for (rv = (double)a0; rv < rend; rv += 1.0, ++row) {
+                // kinks (a crossing outside the tile's columns is clamped
+                // into the padding cells)
+                for (int r = r0; r <= r1; ++r, rv += 1.0) {
                     const double u = fma(rv, sl, base);
                     const double fl = floor(u);
+                    const int k = min(max((int)fl, klo), khi) - shift;
                     const double v1 = fma(D, fl - u, D);
-                    dep(row, (int)fl + c1, v1, D - v1);
+                    dep(r + rshift, k + 1, v1, D - v1);
                 }
                 if (!seamed) continue;
                 // the seam line, on the rows whose crossing this copy and tile
@@ -2082,7 +2066,6 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
                 // seam line and fragment count: only where this copy and tile
                 // hold the crossing
                 if (kf >= -1 && kf <= n - 2) {
-                    ++kinks;
                     if (seamed) {
                         const double uc = (double)tx0 + (u - (double)shift);  // canonical position
                         const double near = fmax(uc - Wm2, 0.0);

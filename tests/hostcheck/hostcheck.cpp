@@ -72,14 +72,22 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     std::vector<uint8_t> sil(V.edges ? 36 * nvert : 0);
     V.kinks = V.edges ? kinks.data() : nullptr;
     V.sil = V.edges ? sil.data() : nullptr;
+    V.own_cap = (uint64_t)(6 * L.ncubes);
+    V.own = nullptr;
+    V.spill = nullptr;
     long long tets = 0, zero = 0, inv = 0, dets = 0, creases = 0, edged = 0;
     for (int64_t cube = 0; cube < L.ncubes; ++cube) {
         CubeCounts cnt;
-        if (persp) setup_cube<kFormPersp>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
-        else if (splat) setup_cube<kFormSplat>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
-        else if (slab) setup_cube<kFormFace>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
-        else if (V.edges) setup_cube<kFormPyramid, true>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
-        else setup_cube<kFormPyramid>(L, V, cube, &head[6 * cube], &coef[6 * cube], cnt);
+        // (records stay at 6 cube + t here, every one with a payload slot)
+        auto emit = [&](int t, const RecHead &R, const Payload &P) {
+            head[6 * cube + t] = R;
+            if (R.flags & REC_VALID) coef[6 * cube + t] = P;
+        };
+        if (persp) setup_cube<kFormPersp>(L, V, cube, emit, cnt);
+        else if (splat) setup_cube<kFormSplat>(L, V, cube, emit, cnt);
+        else if (slab) setup_cube<kFormFace>(L, V, cube, emit, cnt);
+        else if (V.edges) setup_cube<kFormPyramid, true>(L, V, cube, emit, cnt);
+        else setup_cube<kFormPyramid>(L, V, cube, emit, cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
         for (int t = 0; t < 6; ++t) {
             creases += (head[6 * cube + t].flags & (REC_CREASE | REC_EDGED)) ? 1 : 0;

@@ -462,6 +462,31 @@ def test_batch_capacity_overflow_uses_the_overflow_raster(tess):
     assert st["fragments"] == sst["fragments"]
 
 
+@pytest.mark.parametrize("kind", ["z_wrap", "rotated"])
+@pytest.mark.parametrize("own_capacity", [1, 40])
+def test_own_records_beyond_the_payload_capacity(tess, kind, own_capacity):
+    # edge form: the tetrahedra that keep their own record (steep or wide
+    # footprints) beyond own_capacity are marked in the spill set and drawn by
+    # the overflow raster, which sets them up again from the lattice; the
+    # image is the oracle's, and the next call without the cap learns enough
+    # payloads to need none
+    n = 24
+    xyz = W.zeldovich(n, 8, 8.0, seed=13)
+    view = W.z_view(192, 160) if kind == "z_wrap" else W.rotated_view(W.random_rotations(1, seed=6)[0], 150, 130)
+    # (the full call first: a call with spilled records lists fewer pairs, and
+    # the pair capacity learned from it would send the next full call to the
+    # overflow raster once)
+    full, sf = gpu_image(tess, xyz, (n, n, n), view, tune=tess.make_tune(form="edges", own_capacity=6 * n ** 3))
+    got, st = gpu_image(tess, xyz, (n, n, n), view, tune=tess.make_tune(form="edges", own_capacity=own_capacity))
+    assert sf["own_records"] > 2 * own_capacity and sf["overflow"] == 0, sf
+    assert st["overflow"] == 1 and st["own_records"] == sf["own_records"]
+    ref, ost = O.project_region(*xyz, (n, n, n), view)
+    assert_parity(got, ref, what=f"spilled own records {kind} cap {own_capacity}")
+    np.testing.assert_allclose(got, full, rtol=2.4e-7, atol=1e-9 * ref.max())
+    assert st["fragments"] == sf["fragments"]
+    assert abs(st["fragments"] - ost["fragments"]) <= 1e-6 * ost["fragments"] + 8
+
+
 @pytest.mark.parametrize("form", ["per_tetrahedron", "edges"])
 @pytest.mark.parametrize("kind", ["z_wrap", "rotated", "slab", "centroids", "perspective"])
 def test_overflow_raster_matches_the_oracle(tess, form, kind):

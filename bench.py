@@ -358,15 +358,20 @@ def run_learned(args, w, tess, W, torch):
 
 
 def copy_probe(torch):
-    """A plain device copy of known size: what FETCH_SIZE / WRITE_SIZE read
-    for it scales the raster's counters to bytes."""
+    """Kernels of known traffic: what FETCH_SIZE / WRITE_SIZE read for them
+    scales the raster's counters to bytes.  A device copy (1 GiB read, 1 GiB
+    written; the runtime's copy kernel) and a sum over the same 1 GiB (plain
+    vector loads, as the raster's)."""
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
     for _ in range(2):
         b.copy_(a)
+    s = 0.0
+    for _ in range(2):
+        s += float(a.sum())
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 2}), flush=True)
+    print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 2, "sums": 2, "sum": s}), flush=True)
 
 
 def raster_traffic(workload, tile, block):

@@ -393,6 +393,20 @@ tess_status tess_mlp_loss_grad(const float *params, const float *rff_B, const fl
                                const float *target, int64_t n, double *loss, float *grad,
                                float *pred, void *stream);
 
+/*
+ * The network's forward pass as tess_refine's inference runs it (one fused
+ * kernel: features, hidden layers and output per 16-sample tile, bf16
+ * operands rounded from the FP32 parameters, FP32 accumulation).
+ *   params : host, TESS_MLP_PARAMS FP32
+ *   rff_B  : host, TESS_MLP_FREQS x 3 integer-valued frequencies
+ *   q      : device, n x 3 FP32 (unit torus)
+ *   pred   : device, n x 3 FP32 displacements (box units), caller-owned
+ * Synchronises the stream.  Errors: TESS_EINVAL (NULL, n outside 1..2^30,
+ * frequencies not integers), TESS_ENOMEM, TESS_EHIP.
+ */
+tess_status tess_mlp_forward(const float *params, const float *rff_B, const float *q, int64_t n, float *pred,
+                             void *stream);
+
 /* One Adam update (Kingma & Ba, with bias correction), the update tess_refine
  * applies to the FP32 master parameters after each training step, for
  * checks: with m <- b1 m + (1 - b1) g and v <- b2 v + (1 - b2) g^2,

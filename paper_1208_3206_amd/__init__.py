@@ -136,6 +136,7 @@ def _load():
     L.tess_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, vp]
     L.tess_lattice_positions.argtypes = [vp, vp, vp, vp, vp]
+    L.tess_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     L.tess_project_noalloc.argtypes = [vp, P(TessView), P(TessTune), vp, vp]
     L.tess_last_error.argtypes = []
     L.tess_last_error.restype = ctypes.c_char_p
@@ -146,7 +147,7 @@ def _load():
     for f in (L.tess_build_desc_default, L.tess_build, L.tess_project, L.tess_project_batch,
               L.tess_check_view, L.tess_check_build_desc, L.tess_refine_desc_default,
               L.tess_refine, L.tess_mlp_loss_grad, L.tess_mlp_adam, L.tess_lattice_positions,
-              L.tess_project_noalloc):
+              L.tess_project_noalloc, L.tess_mlp_forward):
         f.restype = ctypes.c_int
     return L
 
@@ -157,7 +158,8 @@ _lib = _load()
 EXPORTS = ("tess_build_desc_default", "tess_build", "tess_free", "tess_project",
            "tess_project_batch", "tess_check_view", "tess_check_build_desc",
            "tess_last_error", "tess_version", "tess_struct_size", "tess_refine_desc_default", "tess_refine",
-           "tess_mlp_loss_grad", "tess_mlp_adam", "tess_lattice_positions", "tess_project_noalloc")
+           "tess_mlp_loss_grad", "tess_mlp_adam", "tess_lattice_positions", "tess_project_noalloc",
+           "tess_mlp_forward")
 
 
 def lib():
@@ -415,6 +417,24 @@ def mlp_loss_grad(params, rff_B, q, target, want_pred: bool = False, stream=None
                                    pred.data_ptr() if pred is not None else None,
                                    _stream_handle(stream)), "tess_mlp_loss_grad")
     return (loss.value, grad, pred) if want_pred else (loss.value, grad)
+
+
+def mlp_forward(params, rff_B, q, stream=None):
+    """The network's predictions (n, 3) for q (contiguous CUDA float32 (n, 3)),
+    by the fused inference kernel tess_refine uses."""
+    import numpy as np
+    import torch
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    b = np.ascontiguousarray(rff_B, dtype=np.float32).reshape(-1)
+    if p.size != MLP_PARAMS or b.size != 3 * MLP_FREQS:
+        raise ValueError("params / rff_B have the wrong size")
+    n = q.shape[0]
+    if not (q.is_cuda and q.dtype == torch.float32 and q.is_contiguous() and q.numel() == 3 * n):
+        raise ValueError("q must be a contiguous CUDA float32 (n, 3) tensor")
+    pred = torch.empty((n, 3), dtype=torch.float32, device=q.device)
+    _check(_lib.tess_mlp_forward(p.ctypes.data, b.ctypes.data, q.data_ptr(), int(n), pred.data_ptr(),
+                                 _stream_handle(stream)), "tess_mlp_forward")
+    return pred
 
 
 def mlp_adam(params, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,

@@ -687,7 +687,7 @@ std::string count_key(const Geometry &g) {
     return buf;
 }
 
-unsigned long long capacity_for(unsigned long long most) { return most + most / 4 + 4096; }
+unsigned long long capacity_for(unsigned long long most) { return most + most / 8 + 4096; }
 
 // Edge form: payloads for the tetrahedra that keep their own record (steep
 // or wide footprints): from the most seen for this shape, else a first guess
@@ -701,10 +701,11 @@ int64_t own_capacity(const Workspace &ws, const Geometry &g0, const std::string 
     return std::min<int64_t>(want, ntets);
 }
 
-// First guess without any count: four pairs per record (the stress workload
-// at 2048^2 with 32 x 512 tiles has 3.3), within [2^20, 2^31].
+// First guess without any count: four pairs per record, seven in the edge
+// form, whose records are nearly all edges (the stress workload at 2048^2
+// with 32 x 512 tiles has 6.0 pairs per edge), within [2^20, 2^31].
 unsigned long long first_guess(const Geometry &g) {
-    const unsigned long long want = 4ull * (unsigned long long)g.ntet;
+    const unsigned long long want = (g.vp.edges ? 7ull : 4ull) * (unsigned long long)g.ntet;
     return std::min<unsigned long long>(std::max<unsigned long long>(want, 1ull << 20), 1ull << 31);
 }
 

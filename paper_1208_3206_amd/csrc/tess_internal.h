@@ -182,21 +182,23 @@ struct alignas(128) Payload {
 // x0 + c): the crossing of record row r lies at column u(r) = fma(r, sl,
 // base), a function of the row alone, so every tile that draws the row
 // places its kink identically; D, the edge's summed slope change; the box
-// (x0 and y0 .. y1 as in the head, the width x1 - x0 in 15 bits, and bit
-// 31 set when some of D comes from tetrahedra in a frame one period away,
-// s = -1 or +1: the sums by s = -1, 0, 1 are then in the edge slots, at
-// slot s + 1 of the slots' edge-major view, which the edge's vertex no
-// longer needs once its records are written).  The box's rows are those
+// (x0 and y0 .. y1 as in the head, the width x1 - x0 in 14 bits, and bits 30
+// and 31 set when some of D comes from tetrahedra in a frame one period
+// away, s = -1 and s = +1: the sums by s = -1, 0, 1 are then in the edge
+// slots, at slot s + 1 of the slots' edge-major view, which the edge's
+// vertex no longer needs once its records are written; the raster reads
+// them only where a seam line needs them).  The box's rows are those
 // whose centre lies in the edge's half-open y range, clipped to the image
 // without wrap.  32 bytes, stored apart from the tetrahedra's payloads
 // (record id - BinParams::first_edge); the head array holds box, flags and
 // silhouette counts for the binning and the fragment count.
 struct alignas(32) EdgePayload {
     double base, sl, D;
-    uint32_t bx;  // x0 (int16) | width << 16 (15 bits) | offsets << 31
+    uint32_t bx;  // x0 (int16) | width << 16 (14 bits) | kEdgeMinus | kEdgePlus
     uint32_t by;  // as RecHead
 };
-constexpr uint32_t kEdgeOffsets = 1u << 31;
+constexpr uint32_t kEdgeMinus = 1u << 30, kEdgePlus = 1u << 31;  // slope change at s = -1, +1
+constexpr uint32_t kEdgeWidthMask = 0x3fffu;
 static_assert(sizeof(EdgePayload) == 32, "two edges per 64 bytes");
 static_assert(sizeof(RecHead) == 16, "record head");
 static_assert(sizeof(Payload) == 128, "one 128-byte line per record");

@@ -39,6 +39,11 @@ int64_t out_blocks(int64_t n);
 hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t count, double lr, double b1,
                        double b2, double eps, int t, hipStream_t s);
 hipError_t launch_cast_weights(const float *master, __bf16 *Wb, __bf16 *WTb, hipStream_t s);
+// Inference: pred[n][3] from q[n][3] in one pass (features, hidden layers
+// and output layer per 16-sample tile in registers; bf16 operands rounded
+// from the FP32 master parameters, FP32 accumulation).
+hipError_t launch_mlp_infer(const float *q, int64_t n, const float *B, const float *master, float *pred,
+                            hipStream_t s);
 
 }  // namespace mlp
 }  // namespace tess

@@ -12,6 +12,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 namespace tess {
@@ -334,6 +335,131 @@ hipError_t launch_adam(float *w, float *m, float *v, const float *g, int64_t cou
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, w, m, v, g, count,
                        (float)lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps,
                        (float)c1, (float)c2);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ fused inference
+// The whole forward pass of one 16-sample tile on one wavefront, for
+// inference: the features, the four hidden layers and the output layer stay
+// in registers.  Each layer is computed transposed, D = W H^T (the weights
+// as the MFMA's A operand, the activations as its B operand), so that after
+// a layer the lane holding sample r = l % 16 has outputs o = 16 ot + 4 q + i
+// (q = l / 16, i < 4, ot < 8): exactly the B operand of the next layer if
+// that layer takes its input columns in the order k = 32 ks + 8 q + j <->
+// input feature perm(k) = 16 (2 ks + j / 4) + 4 q + j % 4.  The weights are
+// staged in LDS in that order, one 16-byte A fragment per lane per (layer,
+// ot, ks); the first layer takes the features in their natural order, which
+// the lanes compute for themselves.
+constexpr int kInferWaves = 8;            // 512 threads; the staged weights admit one block per CU
+constexpr int kFragsHidden = kDepth * 8 * 4 * 64;  // 16-byte fragments of the four hidden layers
+constexpr int kFragsOut = 4 * 64;         // of the output layer (3 of its 16 rows are real)
+
+__device__ __host__ inline int infer_perm(int k) {
+    const int ks = k >> 5, q = (k >> 3) & 3, j = k & 7;
+    return 16 * (2 * ks + (j >> 2)) + 4 * q + (j & 3);
+}
+
+__global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(const float *__restrict__ q, int64_t n,
+                                                                const float *__restrict__ B,
+                                                                const float *__restrict__ master,
+                                                                float *__restrict__ pred) {
+    extern __shared__ bf16x8 sFrag[];                 // hidden, then output fragments
+    __shared__ float sBias[kDepth * kWidth + 4];
+    __shared__ float sB[3 * kFreq];
+    // stage: fragment f of (layer, ot, ks, lane) holds W[o][perm or natural k .. +7]
+    for (int f = threadIdx.x; f < kFragsHidden + kFragsOut; f += blockDim.x) {
+        const int lane = f & 63, ks = (f >> 6) & 3;
+        const bool out = f >= kFragsHidden;
+        const int ot = out ? 0 : (f >> 8) & 7, l = out ? kDepth : f >> 11;
+        const int o = 16 * ot + (lane & 15);
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 32 * ks + 8 * (lane >> 4) + j;
+            const int kin = l == 0 ? k : infer_perm(k);
+            float w = 0.f;
+            if (!out)
+                w = master[param_offset_W(l) + (int64_t)o * kWidth + kin];
+            else if (o < 3)
+                w = master[kOffW5 + (int64_t)o * kWidth + kin];
+            v[j] = (bf16)w;
+        }
+        sFrag[f] = v;
+    }
+    for (int e = threadIdx.x; e < kDepth * kWidth; e += blockDim.x)
+        sBias[e] = master[param_offset_b(e / kWidth) + e % kWidth];
+    if (threadIdx.x < 3) sBias[kDepth * kWidth + threadIdx.x] = master[kOffB5 + threadIdx.x];
+    for (int e = threadIdx.x; e < 3 * kFreq; e += blockDim.x) sB[e] = B[e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lq = lane >> 4, lr = lane & 15;
+    const int64_t ntile = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * kInferWaves + wave; tile < ntile;
+         tile += (int64_t)gridDim.x * kInferWaves) {
+        const int64_t row = tile * 16 + lr;
+        const bool live = row < n;
+        // features of sample `row`, k = 32 ks + 8 q + j (natural order: sin
+        // of frequency k for k < 64, cos of frequency k - 64 above)
+        // (columns 64 apart are the sine and cosine of one frequency: k and
+        // k + 64 sit in blocks ks and ks + 2 of the same lane)
+        bf16x8 h[4];
+        {
+            const float q0 = live ? q[3 * row] : 0.f, q1 = live ? q[3 * row + 1] : 0.f,
+                        q2 = live ? q[3 * row + 2] : 0.f;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int f = 32 * ks + 8 * lq + j;
+                    const float t = 2.0f * (sB[3 * f] * q0 + sB[3 * f + 1] * q1 + sB[3 * f + 2] * q2);
+                    float sv, cv;
+                    sincospif(t, &sv, &cv);
+                    h[ks][j] = (bf16)sv;
+                    h[ks + 2][j] = (bf16)cv;
+                }
+        }
+#pragma unroll 1
+        for (int l = 0; l < kDepth; ++l) {
+            floatx4 acc[8];
+#pragma unroll
+            for (int ot = 0; ot < 8; ++ot) {
+                acc[ot] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+                    acc[ot] = mma16(sFrag[((l * 8 + ot) * 4 + ks) * 64 + lane], h[ks], acc[ot]);
+            }
+            // bias, GELU, bf16: the next layer's operand (outputs 16 ot + 4 q + i
+            // of this lane's sample, in the next layer's column order)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int ot = 2 * ks + (j >> 2), i = j & 3;
+                    const float z = acc[ot][i] + sBias[l * kWidth + 16 * ot + 4 * lq + i];
+                    h[ks][j] = (bf16)gelu(z);
+                }
+        }
+        floatx4 out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) out = mma16(sFrag[kFragsHidden + ks * 64 + lane], h[ks], out);
+        // lanes 0..15 hold outputs 0..3 of their sample (3 are real)
+        if (lq == 0 && live) {
+            pred[3 * row] = out[0] + sBias[kDepth * kWidth];
+            pred[3 * row + 1] = out[1] + sBias[kDepth * kWidth + 1];
+            pred[3 * row + 2] = out[2] + sBias[kDepth * kWidth + 2];
+        }
+    }
+}
+
+hipError_t launch_mlp_infer(const float *q, int64_t n, const float *B, const float *master, float *pred,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t want = (tiles + kInferWaves - 1) / kInferWaves;
+    const int blocks = (int)std::min<int64_t>(want, (int64_t)cus);
+    const size_t lds = sizeof(bf16x8) * (size_t)(kFragsHidden + kFragsOut);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(64 * kInferWaves), lds, s, q, n, B, master, pred);
     return hipGetLastError();
 }
 

@@ -182,6 +182,25 @@ extern "C" tess_status tess_mlp_loss_grad(const float *params, const float *rff_
     return ok();
 }
 
+extern "C" tess_status tess_mlp_forward(const float *params, const float *rff_B, const float *q, int64_t n,
+                                        float *pred, void *stream) {
+    if (!params || !rff_B || !q || !pred) return fail(TESS_EINVAL, "NULL argument");
+    if (n < 1 || n > (int64_t)1 << 30) return fail(TESS_EINVAL, "n = %lld outside 1..2^30", (long long)n);
+    tess_status st = check_rff(rff_B);
+    if (st != TESS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<float> buf;  // params, then the frequencies
+    TESS_HIP(buf.ensure((size_t)kParams + 3 * kFreq));
+    TESS_HIP(hipMemcpyAsync(buf.p, params, sizeof(float) * kParams, hipMemcpyHostToDevice, s));
+    TESS_HIP(hipMemcpyAsync(buf.p + kParams, rff_B, sizeof(float) * 3 * kFreq, hipMemcpyHostToDevice, s));
+    const hipError_t e = launch_mlp_infer(q, n, buf.p + kParams, buf.p, pred, s);
+    const hipError_t w = hipStreamSynchronize(s);
+    buf.release();
+    if (e != hipSuccess || w != hipSuccess)
+        return fail(TESS_EHIP, "inference: %s", hipGetErrorString(e != hipSuccess ? e : w));
+    return ok();
+}
+
 extern "C" tess_status tess_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, double lr,
                                      double beta1, double beta2, double eps, void *stream) {
     if (!params || !m || !v || !grad) return fail(TESS_EINVAL, "NULL argument");
@@ -317,7 +336,9 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
             for (int64_t first = 0; first < ncoarse; first += cap) {
                 const int64_t n = std::min<int64_t>(cap, ncoarse - first);
                 TESS_HIP(launch_fine_q(first, n, cd, net.q.p, s));
-                st = net_forward(net, n, false, s);
+                st = launch_mlp_infer(net.q.p, n, net.B.p, net.master.p, net.pred.p, s) == hipSuccess
+                         ? TESS_OK
+                         : fail(TESS_EHIP, "inference failed");
                 if (st == TESS_OK &&
                     launch_coarse_residual(coarse->x, coarse->y, coarse->z, first, n, net.q.p, net.pred.p, box,
                                            res, res + ncoarse, res + 2 * ncoarse, s) != hipSuccess)
@@ -331,7 +352,9 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
         for (int64_t first = 0; first < nfine; first += cap) {
             const int64_t n = std::min<int64_t>(cap, nfine - first);
             TESS_HIP(launch_fine_q(first, n, fd, net.q.p, s));
-            st = net_forward(net, n, false, s);
+            st = launch_mlp_infer(net.q.p, n, net.B.p, net.master.p, net.pred.p, s) == hipSuccess
+                     ? TESS_OK
+                     : fail(TESS_EHIP, "inference failed");
             hipError_t e = hipSuccess;
             if (st == TESS_OK) {
                 if (res)

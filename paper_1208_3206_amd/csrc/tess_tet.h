@@ -1014,13 +1014,14 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
             P.base = fma(0.5 - Py, P.sl, Px - 0.5);
             P.D = D[0] + D[1] + D[2];
             const bool off = D[0] != 0.0 || D[2] != 0.0;
+            const uint32_t offbits = (D[0] != 0.0 ? kEdgeMinus : 0u) | (D[2] != 0.0 ? kEdgePlus : 0u);
             R.bx = pack_range(ix0, ix1);
             R.by = pack_range(iy0, iy1);
             R.flags = REC_EDGE | REC_VALID;
             R.spare = cnt;
             // (an edge narrower than the image, as those of the tetrahedra
             // that hand their creases to their edges are: the width fits)
-            P.bx = ((uint32_t)(uint16_t)(int16_t)ix0) | ((uint32_t)(ix1 - ix0) << 16) | (off ? kEdgeOffsets : 0u);
+            P.bx = ((uint32_t)(uint16_t)(int16_t)ix0) | ((uint32_t)(ix1 - ix0) << 16) | offbits;
             P.by = R.by;
             if (off) {
                 G[tau][0] = D[0];
@@ -1944,20 +1945,16 @@ template <bool COUNT = true, typename Dep, typename Seam, typename SeamRange>
 TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t cnt, const BinParams &B, int tx0,
                                   int ty0, int n, int rows, Dep &&dep, Seam &&seam, SeamRange &&seam_range,
                                   uint32_t &kinks) {
-    const int bx0 = range_lo(E.bx), bx1 = bx0 + (int)((E.bx >> 16) & 0x7fffu) + kRightReach;
+    const int bx0 = range_lo(E.bx), bx1 = bx0 + (int)((E.bx >> 16) & kEdgeWidthMask) + kRightReach;
     const int by0 = range_lo(E.by), by1 = range_hi(E.by);
     int kx0, kx1, ky0, ky1;
     axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
     axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
     const double D = E.D;
-    // the sums by period offset (all of D at s = 0 for most edges)
-    double Dm = 0.0, D0 = D, Dp = 0.0;
-    if (E.bx & kEdgeOffsets) {
-        const int64_t nedge = (int64_t)B.ntet - B.first_edge;
-        Dm = B.groups[eid];
-        D0 = B.groups[nedge + eid];
-        Dp = B.groups[2 * nedge + eid];
-    }
+    // the sums by period offset: all of D at s = 0 unless the payload flags
+    // some at s = -1 or +1; those are read only for a tile copy that draws a
+    // seam line (below)
+    const bool hasm = (E.bx & kEdgeMinus) != 0u, hasp = (E.bx & kEdgePlus) != 0u;
     const double sl = E.sl, base = E.base;
     // rows per column, for the rows that reach a tile's columns (only the
     // choice of rows depends on it, with a margin: an estimate will do)
@@ -1991,13 +1988,27 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
             // with s + kx = 1 add D (u - j), summed in A1; those with
             // s + kx = 0 add -D (u - W + 2) (j + 1) when u >= W - 2, summed
             // in A0 (the others add nothing)
-            const double A1 = kx == 0 ? Dp : kx == 1 ? D0 : kx == 2 ? Dm : 0.0;
-            const double A0 = kx == -1 ? Dp : kx == 0 ? D0 : kx == 1 ? Dm : 0.0;
+            // (which of them can be nonzero follows from the flags, taking
+            // the s = 0 sum as nonzero)
+            const bool a1 = kx == 0 ? hasp : kx == 1 ? true : kx == 2 ? hasm : false;
+            const bool a0 = kx == -1 ? hasp : kx == 0 ? true : kx == 1 ? hasm : false;
             // A0 can act only where a crossing reaches the period's last two
             // columns: in this copy the rightmost crossing lies before column
             // x1 + 1 of the box (x1 = bx1 - kRightReach), moved by -kx W
             const bool near_end = tx0 + n > B.W - 3 && bx1 - kRightReach - kx * B.W >= B.W - 3;
-            const bool seamed = B.seam && (A1 != 0.0 || (A0 != 0.0 && near_end));
+            const bool seamed = B.seam && (a1 || (a0 && near_end));
+            double A1 = 0.0, A0 = 0.0;
+            if (seamed) {
+                double Dm = 0.0, D0 = D, Dp = 0.0;
+                if (hasm || hasp) {
+                    const int64_t nedge = (int64_t)B.ntet - B.first_edge;
+                    Dm = B.groups[eid];
+                    D0 = B.groups[nedge + eid];
+                    Dp = B.groups[2 * nedge + eid];
+                }
+                A1 = kx == 0 ? Dp : kx == 1 ? D0 : kx == 2 ? Dm : 0.0;
+                A0 = kx == -1 ? Dp : kx == 0 ? D0 : kx == 1 ? Dm : 0.0;
+            }
             double rv = (double)r0;
             if (!COUNT) {
                 // kinks (a crossing outside the tile's columns is clamped

@@ -64,6 +64,31 @@ def test_forward_matches_oracle(tess):
     assert abs(loss - rl) / rl < 2e-3
 
 
+@pytest.mark.parametrize("n", [1, 17, 1000, 40000])
+def test_fused_inference_matches_oracle_and_training_forward(tess, n):
+    # the inference kernel (whole network per 16-sample tile, layers computed
+    # transposed with permuted input columns) against the oracle's bf16-operand
+    # forward pass and the training path's layer-by-layer forward; n covers a
+    # partial tile, several blocks and a ragged tail
+    import torch
+    q, target, B, params = problem(n, 100 + n)
+    qd = torch.from_numpy(q).cuda()
+    pred = tess.mlp_forward(params, B, qd).cpu().numpy().astype(np.float64)
+    _, _, rpred = reference(params, B.astype(np.float64), q, target.astype(np.float64))
+    err = np.linalg.norm(pred - rpred) / np.linalg.norm(rpred)
+    _, _, tpred = tess.mlp_loss_grad(params, B, qd, torch.from_numpy(target).cuda(), want_pred=True)
+    tpred = tpred.cpu().numpy().astype(np.float64)
+    d = np.abs(pred - tpred).max() / np.abs(tpred).max()
+    dl2 = np.linalg.norm(pred - tpred) / np.linalg.norm(tpred)
+    print(f"fused inference n={n}: rel L2 vs oracle {err:.3e}, vs training forward rel L2 {dl2:.3e} "
+          f"max {d:.3e}", flush=True)
+    assert err < 1e-3
+    # the same operands, summed in another order (the columns of each 32-wide
+    # k block are permuted), so now and then a bf16 activation rounds the
+    # other way (one bf16 ulp, 2^-8 relative, on one of 512 activations)
+    assert dl2 < 2e-4 and d < 1e-2
+
+
 @pytest.mark.parametrize("n", [64, 1000, 8192])
 def test_gradients_match_oracle(tess, n):
     import torch

@@ -39,14 +39,16 @@ PEAK_LDS_BYTES = 256 * 128 * 2.4e9            # 128 B/clk/CU: 78.6 TB/s
 # compensated add); reported alongside as the fragment-equivalent rate.
 OPS_PER_FRAGMENT = 16
 # k_raster's HBM bytes at stress 2048^2 from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (KiB per dispatch), scaled by what the same counters read for a 1 GiB
-# device copy (--copy-probe); valid only for the sources they were taken on.
+# passes (KiB per dispatch), scaled by what the same counters read for 1 GiB
+# read and written by a device copy and read by a sum (--copy-probe: both
+# read back half their bytes, the write counter all); valid only for the
+# sources they were taken on.
 TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "18c89c0c7ab2aa2aa2891572346ce51f33082c8eb1fc43ded4e24dd3a48d968b",
-    "fetch_kib": 37522955.6, "write_kib": 1433111.1, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "9123da131e97b751fbf6ec8db826a1fca800b0062588d421c624aa5e9de0bc1e",
+    "fetch_kib": 44901289.4, "write_kib": 1427621.9, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -545,16 +545,73 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t stream) {
 // the tile is added to the image-sized array `acc` (FP64 atomics in L2; a
 // tile has several items).
 constexpr int kPad = 2;
-__host__ __device__ inline int tile_stride(int Tw) { return Tw + 2 * kPad; }
 constexpr int kIdBurst = 8;     // pair ids a lane loads at once
 constexpr int kSortPer = 7;     // pair ids per lane in one wavefront's class sort
 constexpr int kNumClasses = 32;
 constexpr size_t kLdsBytes = 160 * 1024 - 64;  // dynamic LDS: 64 bytes stay for the static counter
+// Row stride of the tile accumulator: Tw + 4 cells, rounded up to 1 modulo
+// 32 doubles (cells of one column in consecutive rows then fall in different
+// LDS banks) where the rounded rows leave room for one copy of the seam lines.
+__host__ __device__ inline int tile_stride(int Tw, int Th) {
+    const int plain = Tw + 2 * kPad, padded = ((plain + 30) & ~31) + 1;
+    const size_t need = sizeof(double) * ((size_t)Th * padded + 2 * (size_t)Th + 3 * ((size_t)Th + 1));
+    return need <= kLdsBytes ? padded : plain;
+}
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane I's value of its 16-lane row, in every lane of the row (a DPP row
+// broadcast: no LDS traffic).
+template <int I>
+__device__ __forceinline__ uint32_t row_bcast(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x150 + I, 0xf, 0xf, true);
+}
+template <int I>
+__device__ __forceinline__ double row_bcast(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint64_t lo = row_bcast<I>((uint32_t)b), hi = row_bcast<I>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
+// The kinks of the edge jobs of a 16-lane group, edge I first: its rows
+// r0 + s, s = q, q + 16, ... < cnt, on lane q (pk: ta | cnt << 8), into the
+// tile rows of `stride` cells at sA (padding included).  Each kink's terms
+// are edge_pair's: crossing u = fma(r, sl, base), D (1 - f) at tile column
+// clamp(floor(u) - shift) + 1 and D f beside it.  TWO: every job has at
+// most 32 rows (tiles of at most 32 rows), two steps unrolled.
+template <int I, bool TWO>
+__device__ __forceinline__ void group_kinks(const EdgeJob &J, uint32_t pk, int q, int n, double *sA, int stride) {
+    const uint32_t pki = row_bcast<I>(pk);
+    const int cnt = (int)(pki >> 8);
+    if (__builtin_amdgcn_ballot_w64(cnt > q) != 0ull) {  // some group has rows of its edge I
+        const int ta = (int)(pki & 0xffu);
+        const int r0 = (int)row_bcast<I>((uint32_t)J.r0), shift = (int)row_bcast<I>((uint32_t)J.shift);
+        const double base = row_bcast<I>(J.base), sl = row_bcast<I>(J.sl), D = row_bcast<I>(J.D);
+        const int klo = shift - 3, khi = shift + n - 1;
+        // cell of column floor(u) - shift + 1 in row ta + q: xb + floor(u)
+        const int xb = (ta + q) * stride + kPad + 1 - shift;
+        auto kink = [&](int x0, double rv) {
+            const double u = fma(rv, sl, base);
+            const double fl = floor(u);
+            const int x = x0 + min(max((int)fl, klo), khi);
+            const double v1 = fma(D, fl - u, D);
+            atomicAdd(&sA[x], v1);
+            atomicAdd(&sA[x + 1], D - v1);
+        };
+        if constexpr (TWO) {
+            const double rv = (double)(r0 + q);
+            if (q < cnt) kink(xb, rv);
+            if (q + 16 < cnt) kink(xb + 16 * stride, rv + 16.0);
+        } else {
+            int x0 = xb;
+            for (int s = q; s < cnt; s += 16, x0 += 16 * stride) kink(x0, (double)(r0 + s));
+        }
+    }
+    if constexpr (I < 15) group_kinks<I + 1, TWO>(J, pk, q, n, sA, stride);
 }
 
 // LDS of one wavefront's class sort: kNumClasses counters, then 64 * kSortPer entries
@@ -575,9 +632,9 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     const int tx = (int)(it.tile % (uint32_t)B.ntx), ty = (int)(it.tile / (uint32_t)B.ntx);
     const int tx0 = tx * B.Tw, ty0 = ty * B.Th;
     const int n = min(B.Tw, B.W - tx0), rows = min(B.Th, B.H - ty0);
-    // rows of Tw + 4 cells: two padding cells each side take the adds that
+    // rows of at least Tw + 4 cells: two padding cells each side take the adds that
     // fall outside the tile, so that the raster needs no bounds tests
-    const int stride = tile_stride(B.Tw);
+    const int stride = tile_stride(B.Tw, B.Th);
     const int tsize = B.Th * stride;
     auto cell = [&](int row, int j) { return row * stride + kPad + j; };
     // then (edge form under wrap) per tile row the seam line a + b j, in
@@ -762,9 +819,26 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                 const uint32_t idnn = id_at(enn);
                 EdgePayload Pn{};
                 if (is_edge(idn)) Pn = ecoef[idn - B.first_edge];
-                if (is_edge(id))
-                    frags += (int32_t)edge_pair<COUNT>(P, id - B.first_edge, COUNT ? head[id].spare : 0u, B, tx0,
-                                                       ty0, n, rows, dep, seam, seam_range, kinks);
+                if constexpr (COUNT) {
+                    if (is_edge(id))
+                        frags += (int32_t)edge_pair<COUNT>(P, id - B.first_edge, head[id].spare, B, tx0, ty0, n,
+                                                           rows, dep, seam, seam_range, kinks);
+                } else {
+                    // the group's 16 edges one after another, each one's rows
+                    // over the 16 lanes (consecutive rows: cells a row stride
+                    // apart, in different banks), then whatever else a lane's
+                    // own edge has here (a seam line, further copies)
+                    EdgeJob J{};
+                    if (is_edge(id)) J = edge_job(P, B, tx0, ty0, n, rows, kinks);
+                    const uint32_t pk = (uint32_t)J.ta | ((uint32_t)J.cnt << 8);
+                    if (rows <= 32)
+                        group_kinks<0, true>(J, pk, (int)q, n, sA, stride);
+                    else
+                        group_kinks<0, false>(J, pk, (int)q, n, sA, stride);
+                    if (J.rest)
+                        frags += (int32_t)edge_pair<false, true>(P, id - B.first_edge, 0u, B, tx0, ty0, n, rows, dep,
+                                                                 seam, seam_range, kinks);
+                }
                 e = en;
                 en = enn;
                 id = idn;
@@ -869,7 +943,7 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
     // the tile's accumulator, its seam lines (as many copies per row as fit,
     // up to 16), and beside them (when they fit) the wavefronts' class sorts
     BinParams Bl = B;
-    const size_t acc_lds = sizeof(double) * (size_t)B.Th * tile_stride(B.Tw);
+    const size_t acc_lds = sizeof(double) * (size_t)B.Th * tile_stride(B.Tw, B.Th);
     const size_t row_seam = sizeof(double) * (2 * (size_t)B.Th + 3 * ((size_t)B.Th + 1));
     Bl.seam_copies = B.seam ? (int)std::min<size_t>(16, std::max<size_t>(1, (kLdsBytes - acc_lds) / row_seam)) : 0;
     const size_t tile_lds = acc_lds + row_seam * (size_t)Bl.seam_copies;

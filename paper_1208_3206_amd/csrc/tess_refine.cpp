@@ -50,26 +50,33 @@ struct Net {
     }
 };
 
-tess_status net_alloc(Net &net, int64_t cap, bool train) {
+// Training buffers (activations, gradient partials) for batches of up to
+// `batch` samples when `train`; the sample and prediction buffers hold the
+// larger of that and `infer_cap`, the chunk of the fused inference, which
+// needs nothing else.
+tess_status net_alloc(Net &net, int64_t batch, bool train, int64_t infer_cap = 0) {
+    const int64_t cap = std::max(train ? batch : (int64_t)0, infer_cap);
     TESS_HIP(net.master.ensure(kParams));
-    TESS_HIP(net.grad.ensure(kParams));
     TESS_HIP(net.B.ensure(3 * kFreq));
-    TESS_HIP(net.Wb.ensure((size_t)kDepth * kWidth * kWidth));
-    TESS_HIP(net.WTb.ensure((size_t)kDepth * kWidth * kWidth));
     TESS_HIP(net.q.ensure((size_t)3 * cap));
-    TESS_HIP(net.target.ensure((size_t)3 * cap));
     TESS_HIP(net.pred.ensure((size_t)3 * cap));
-    TESS_HIP(net.X.ensure((size_t)kWidth * cap));
-    for (int l = 0; l < kDepth; ++l) TESS_HIP(net.H[l].ensure((size_t)kWidth * cap));
     if (train) {
+        TESS_HIP(net.grad.ensure(kParams));
         TESS_HIP(net.m.ensure(kParams));
         TESS_HIP(net.v.ensure(kParams));
-        for (int l = 0; l < kDepth; ++l) TESS_HIP(net.Z[l].ensure((size_t)kWidth * cap));
-        TESS_HIP(net.dZ[0].ensure((size_t)kWidth * cap));
-        TESS_HIP(net.dZ[1].ensure((size_t)kWidth * cap));
-        const int64_t slices = (cap + kSlice - 1) / kSlice;
+        TESS_HIP(net.Wb.ensure((size_t)kDepth * kWidth * kWidth));
+        TESS_HIP(net.WTb.ensure((size_t)kDepth * kWidth * kWidth));
+        TESS_HIP(net.target.ensure((size_t)3 * batch));
+        TESS_HIP(net.X.ensure((size_t)kWidth * batch));
+        for (int l = 0; l < kDepth; ++l) {
+            TESS_HIP(net.H[l].ensure((size_t)kWidth * batch));
+            TESS_HIP(net.Z[l].ensure((size_t)kWidth * batch));
+        }
+        TESS_HIP(net.dZ[0].ensure((size_t)kWidth * batch));
+        TESS_HIP(net.dZ[1].ensure((size_t)kWidth * batch));
+        const int64_t slices = (batch + kSlice - 1) / kSlice;
         TESS_HIP(net.part.ensure((size_t)slices * (kWidth * kWidth + kWidth)));
-        TESS_HIP(net.outpart.ensure((size_t)out_blocks(cap) * kOutPart));
+        TESS_HIP(net.outpart.ensure((size_t)out_blocks(batch) * kOutPart));
     }
     net.cap = cap;
     return TESS_OK;
@@ -288,16 +295,19 @@ extern "C" tess_status tess_refine(tess_lattice coarse, const tess_refine_desc *
             init_params(params, d->seed);
         }
         Net net;
-        const int64_t cap = std::max<int64_t>(d->batch, (int64_t)1 << 20);
-        tess_status st = net_alloc(net, cap, true);
+        const int64_t cap = (int64_t)1 << 20;  // inference chunk
+        const bool train = d->steps > 0;
+        tess_status st = net_alloc(net, d->batch, train, cap);
         if (st != TESS_OK) return fail_free(st);
         TESS_HIP(hipMemcpyAsync(net.master.p, params.data(), sizeof(float) * kParams, hipMemcpyHostToDevice, s));
         TESS_HIP(hipMemcpyAsync(net.B.p, B.data(), sizeof(float) * B.size(), hipMemcpyHostToDevice, s));
-        TESS_HIP(hipMemsetAsync(net.m.p, 0, sizeof(float) * kParams, s));
-        TESS_HIP(hipMemsetAsync(net.v.p, 0, sizeof(float) * kParams, s));
-        TESS_HIP(launch_cast_weights(net.master.p, net.Wb.p, net.WTb.p, s));
         float *dloss = nullptr;
-        TESS_HIP(hipMalloc((void **)&dloss, sizeof(float)));
+        if (train) {
+            TESS_HIP(hipMemsetAsync(net.m.p, 0, sizeof(float) * kParams, s));
+            TESS_HIP(hipMemsetAsync(net.v.p, 0, sizeof(float) * kParams, s));
+            TESS_HIP(launch_cast_weights(net.master.p, net.Wb.p, net.WTb.p, s));
+            TESS_HIP(hipMalloc((void **)&dloss, sizeof(float)));
+        }
         auto t0 = std::chrono::steady_clock::now();
         float lsum = 0.f;
         const int64_t nb = d->batch;

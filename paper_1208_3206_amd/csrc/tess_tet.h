@@ -1905,6 +1905,24 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
     return frags;
 }
 
+// The rows of an edge copy that can reach a tile's columns: those whose
+// crossing lies in [shift - 3, shift + n + 1), found from the rows per
+// column iv (an estimate will do: only the choice of rows depends on it,
+// and it keeps a row's margin each way), within the rows [q0, q1] the tile
+// holds.
+TESS_HD inline void edge_copy_rows(double base, double iv, int shift, int n, int q0, int q1, int &r0, int &r1) {
+    r0 = q0;
+    r1 = q1;
+    if (iv != 0.0) {
+        double ya = ((double)(shift - 3) - base) * iv, yb = ((double)(shift + n + 1) - base) * iv;
+        if (ya > yb) { const double t = ya; ya = yb; yb = t; }
+        ya = fmin(fmax(ya, (double)q0 - 1.0), (double)q1 + 1.0);
+        yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 1.0);
+        r0 = max(q0, (int)floor(ya));
+        r1 = min(q1, (int)ceil(yb));
+    }
+}
+
 // Edge form: one mesh edge's summed slope change along its projection,
 // deposited on the rows whose centre lies in its half-open y range (the
 // crease form's rule, so that at a vertex the edges above and below take
@@ -1941,10 +1959,11 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
 // v1 at tile column j and v2 at j + 1; seam(row, a, b) adds a and b to the
 // row's seam line; seam_range(lo, hi, alpha, beta, gamma) adds alpha +
 // beta rho to a and gamma to b on the tile rows rho in [lo, hi].
-template <bool COUNT = true, typename Dep, typename Seam, typename SeamRange>
+template <bool COUNT = true, bool SKIP_FIRST = false, typename Dep, typename Seam, typename SeamRange>
 TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t cnt, const BinParams &B, int tx0,
                                   int ty0, int n, int rows, Dep &&dep, Seam &&seam, SeamRange &&seam_range,
                                   uint32_t &kinks) {
+    static_assert(!(COUNT && SKIP_FIRST), "the counting pass draws every copy itself");
     const int bx0 = range_lo(E.bx), bx1 = bx0 + (int)((E.bx >> 16) & kEdgeWidthMask) + kRightReach;
     const int by0 = range_lo(E.by), by1 = range_hi(E.by);
     int kx0, kx1, ky0, ky1;
@@ -1964,6 +1983,7 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
     const bool count = cnt != 0u;
     const int nlt = nl[0] + nl[1] + nl[2], net = ne[0] + ne[1] + ne[2];
     int frags = 0;
+    bool seen = false;  // a copy met already (the first one met is edge_job's)
     for (int ky = ky0; ky <= ky1; ++ky) {
         const int rshift = by0 - ky * B.H - ty0;  // tile row of record row 0
         const int q0 = max(-rshift, 0), q1 = min(rows - 1 - rshift, by1 - by0);
@@ -1971,17 +1991,12 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
             const int shift = tx0 + kx * B.W - bx0;  // record column of the tile's column 0
-            int r0 = q0, r1 = q1;
-            if (iv != 0.0) {
-                // the rows whose crossing lies in [shift - 3, shift + n + 1)
-                double ya = ((double)(shift - 3) - base) * iv, yb = ((double)(shift + n + 1) - base) * iv;
-                if (ya > yb) { const double t = ya; ya = yb; yb = t; }
-                ya = fmin(fmax(ya, (double)q0 - 1.0), (double)q1 + 1.0);
-                yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 1.0);
-                r0 = max(q0, (int)floor(ya));
-                r1 = min(q1, (int)ceil(yb));
-            }
-            kinks += (uint32_t)max(r1 - r0 + 1, 0);
+            int r0, r1;
+            edge_copy_rows(base, iv, shift, n, q0, q1, r0, r1);
+            // the first copy's kinks: drawn by the caller (edge_job's copy)
+            const bool first = !seen;
+            seen = true;
+            if (!(SKIP_FIRST && first)) kinks += (uint32_t)max(r1 - r0 + 1, 0);
             // record columns of the clamp: tile columns -3 .. n - 1
             const int klo = shift - 3, khi = shift + n - 1;
             // the seam line of a crossing at canonical position u: the groups
@@ -2013,13 +2028,14 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
             if (!COUNT) {
                 // kinks (a crossing outside the tile's columns is clamped
                 // into the padding cells)
-                for (int r = r0; r <= r1; ++r, rv += 1.0) {
-                    const double u = fma(rv, sl, base);
-                    const double fl = floor(u);
-                    const int k = min(max((int)fl, klo), khi) - shift;
-                    const double v1 = fma(D, fl - u, D);
-                    dep(r + rshift, k + 1, v1, D - v1);
-                }
+                if (!(SKIP_FIRST && first))
+                    for (int r = r0; r <= r1; ++r, rv += 1.0) {
+                        const double u = fma(rv, sl, base);
+                        const double fl = floor(u);
+                        const int k = min(max((int)fl, klo), khi) - shift;
+                        const double v1 = fma(D, fl - u, D);
+                        dep(r + rshift, k + 1, v1, D - v1);
+                    }
                 if (!seamed) continue;
                 // the seam line, on the rows whose crossing this copy and tile
                 // hold (floor(u) - shift in [-1, n - 2]; contiguous, as u is
@@ -2093,6 +2109,68 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
         }
     }
     return (uint32_t)frags;
+}
+
+// The kinks of an edge's first copy in a tile (the first (ky, kx) that
+// edge_pair meets), for a caller that draws them apart from the rest: row r
+// of r0 .. r0 + cnt - 1 has its crossing at fma(r, sl, base), tile row
+// ta + (r - r0) and column clamp floor(crossing) - shift to [-3, n - 1].
+// rest: the edge has more to draw in this tile (a seam line for this copy,
+// or further copies), for edge_pair<false, true>, which skips the kinks of
+// exactly this copy.  cnt = 0: no kinks here (rest may still be set).
+struct EdgeJob {
+    double base, sl, D;
+    int shift;
+    int r0, ta, cnt;
+    bool rest;
+};
+
+TESS_HD inline EdgeJob edge_job(const EdgePayload &E, const BinParams &B, int tx0, int ty0, int n, int rows,
+                                uint32_t &kinks) {
+    EdgeJob J;
+    J.base = E.base;
+    J.sl = E.sl;
+    J.D = E.D;
+    J.shift = 0;
+    J.r0 = 0;
+    J.ta = 0;
+    J.cnt = 0;
+    J.rest = false;
+    const int bx0 = range_lo(E.bx), bx1 = bx0 + (int)((E.bx >> 16) & kEdgeWidthMask) + kRightReach;
+    const int by0 = range_lo(E.by), by1 = range_hi(E.by);
+    int kx0, kx1, ky0, ky1;
+    axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
+    axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
+    const bool hasm = (E.bx & kEdgeMinus) != 0u, hasp = (E.bx & kEdgePlus) != 0u;
+    const double iv = E.sl != 0.0 ? fast_rcp(E.sl) : 0.0;
+    bool seen = false;
+    for (int ky = ky0; ky <= ky1; ++ky) {
+        const int rshift = by0 - ky * B.H - ty0;
+        const int q0 = max(-rshift, 0), q1 = min(rows - 1 - rshift, by1 - by0);
+        if (q0 > q1) continue;
+        for (int kx = kx0; kx <= kx1; ++kx) {
+            if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
+            if (seen) {
+                J.rest = true;
+                return J;
+            }
+            seen = true;
+            const int shift = tx0 + kx * B.W - bx0;
+            int r0, r1;
+            edge_copy_rows(E.base, iv, shift, n, q0, q1, r0, r1);
+            J.shift = shift;
+            J.r0 = r0;
+            J.ta = r0 + rshift;
+            J.cnt = max(r1 - r0 + 1, 0);
+            kinks += (uint32_t)J.cnt;
+            // a seam line for this copy: edge_pair's test
+            const bool a1 = kx == 0 ? hasp : kx == 1 ? true : kx == 2 ? hasm : false;
+            const bool a0 = kx == -1 ? hasp : kx == 0 ? true : kx == 1 ? hasm : false;
+            const bool near_end = tx0 + n > B.W - 3 && bx1 - kRightReach - kx * B.W >= B.W - 3;
+            if (B.seam && (a1 || (a0 && near_end))) J.rest = true;
+        }
+    }
+    return J;
 }
 
 // One record in one tile, in whichever form its payload has.

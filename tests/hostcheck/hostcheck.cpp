@@ -13,6 +13,25 @@
 
 using namespace tess;
 
+// The edge raster's split drawing: the first tile copy's kinks from the
+// edge job (rows r0 .. r0 + cnt - 1, the terms the kernel's 16-lane groups
+// compute), then the pair routine without those kinks.
+template <typename Dep, typename Seam, typename SeamRange>
+static uint32_t split_pair(const EdgePayload &E, uint32_t eid, const BinParams &B, int tx0, int ty0, int n, int rows,
+                           Dep &&dep, Seam &&seam, SeamRange &&seam_range, uint32_t &kinks) {
+    const EdgeJob J = edge_job(E, B, tx0, ty0, n, rows, kinks);
+    const int klo = J.shift - 3, khi = J.shift + n - 1;
+    for (int s = 0; s < J.cnt; ++s) {
+        const double u = fma((double)(J.r0 + s), J.sl, J.base);
+        const double fl = floor(u);
+        const int k = std::min(std::max((int)fl, klo), khi) - J.shift;
+        const double v1 = fma(J.D, fl - u, J.D);
+        dep(J.ta + s, k + 1, v1, J.D - v1);
+    }
+    if (J.rest) return edge_pair<false, true>(E, eid, 0u, B, tx0, ty0, n, rows, dep, seam, seam_range, kinks);
+    return 0u;
+}
+
 extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const int32_t dims[3],
                            int32_t periodic, double total_mass, int32_t precision, const double rot[9],
                            const double center[3], const double extent[2], int32_t W, int32_t H,
@@ -166,7 +185,9 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
                     return persp ? raster_record<kFormPersp>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : splat ? raster_record<kFormSplat>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
                          : slab ? raster_record<kFormFace>(head[id], cf, B, tx0, ty0, n, rows, dep, sl, sp, kk)
-                         : is_edge ? (edges == 2 ? edge_pair<false>(ecoef[id - B.first_edge], id - B.first_edge, 0u, B, tx0, ty0, n,
+                         : is_edge ? (edges == 3 ? split_pair(ecoef[id - B.first_edge], id - B.first_edge, B, tx0, ty0, n, rows,
+                                                              dep2, sl, slr, kk)
+                                      : edges == 2 ? edge_pair<false>(ecoef[id - B.first_edge], id - B.first_edge, 0u, B, tx0, ty0, n,
                                                                      rows, dep2, sl, slr, kk)
                                                  : edge_pair<true>(ecoef[id - B.first_edge], id - B.first_edge, head[id].spare, B, tx0, ty0, n,
                                                                    rows, dep2, sl, slr, kk))

@@ -585,7 +585,9 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             }
         }
     }
-#pragma unroll
+    // (one copy of the body for the six tetrahedra: unrolled, the setup
+    // kernels' code outgrew the instruction cache)
+#pragma unroll 1
     for (int t = 0; t < 6; ++t) {
         // the record is built in registers and stored once, in whole lines
         RecHead R;

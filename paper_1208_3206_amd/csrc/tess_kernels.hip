@@ -826,8 +826,8 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                 } else {
                     // the group's 16 edges one after another, each one's rows
                     // over the 16 lanes (consecutive rows: cells a row stride
-                    // apart, in different banks), then whatever else a lane's
-                    // own edge has here (a seam line, further copies)
+                    // apart, in different banks), then the rest of a lane's own
+                    // edge here: that copy's seam line, further copies (rare)
                     EdgeJob J{};
                     if (is_edge(id)) J = edge_job(P, B, tx0, ty0, n, rows, kinks);
                     const uint32_t pk = (uint32_t)J.ta | ((uint32_t)J.cnt << 8);
@@ -835,7 +835,10 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                         group_kinks<0, true>(J, pk, (int)q, n, sA, stride);
                     else
                         group_kinks<0, false>(J, pk, (int)q, n, sA, stride);
-                    if (J.rest)
+                    if (J.seamed)
+                        edge_copy_seam(P, id - B.first_edge, B, tx0, n, J.kx, J.shift, J.ta - J.r0, J.r0,
+                                       J.r0 + J.cnt - 1, P.sl != 0.0 ? fast_rcp(P.sl) : 0.0, seam, seam_range);
+                    if (J.more)
                         frags += (int32_t)edge_pair<false, true>(P, id - B.first_edge, 0u, B, tx0, ty0, n, rows, dep,
                                                                  seam, seam_range, kinks);
                 }

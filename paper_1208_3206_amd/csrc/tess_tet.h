@@ -1907,6 +1907,34 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
     return frags;
 }
 
+// The rows r0 .. r1 of an edge copy whose crossing the tile holds
+// (floor(fma(r, sl, base)) - shift in [-1, n - 2]; contiguous, as the
+// crossing is monotone in r) as [ha, hb]: first guesses from the rows per
+// column iv, then moved to the exact ends.  false: none.
+TESS_HD inline bool edge_held_rows(double base, double sl, double iv, int shift, int n, int r0, int r1, int &ha,
+                                   int &hb) {
+    auto held = [&](int r) {
+        const int kf = (int)floor(fma((double)r, sl, base)) - shift;
+        return kf >= -1 && kf <= n - 2;
+    };
+    ha = r0;
+    hb = r1;
+    if (sl != 0.0) {
+        double ya = ((double)(shift - 1) - base) * iv, yb = ((double)(shift + n - 1) - base) * iv;
+        if (ya > yb) { const double t = ya; ya = yb; yb = t; }
+        ya = fmin(fmax(ya, (double)r0), (double)r1);
+        yb = fmin(fmax(yb, (double)r0), (double)r1);
+        ha = (int)ya;
+        hb = (int)yb;
+    }
+    while (ha <= hb && !held(ha)) ++ha;
+    while (hb >= ha && !held(hb)) --hb;
+    if (ha > hb) return false;
+    while (ha > r0 && held(ha - 1)) --ha;
+    while (hb < r1 && held(hb + 1)) ++hb;
+    return true;
+}
+
 // The rows of an edge copy that can reach a tile's columns: those whose
 // crossing lies in [shift - 3, shift + n + 1), found from the rows per
 // column iv (an estimate will do: only the choice of rows depends on it,
@@ -1922,6 +1950,70 @@ TESS_HD inline void edge_copy_rows(double base, double iv, int shift, int n, int
         yb = fmin(fmax(yb, (double)q0 - 1.0), (double)q1 + 1.0);
         r0 = max(q0, (int)floor(ya));
         r1 = min(q1, (int)ceil(yb));
+    }
+}
+
+// The seam line of a crossing at canonical position u in copy kx of an
+// edge: the groups with s + kx = 1 add D (u - j), summed in A1; those with
+// s + kx = 0 add -D (u - W + 2) (j + 1) when u >= W - 2, summed in A0 (the
+// others add nothing).  Which of them can be nonzero follows from the
+// payload's flags, taking the s = 0 sum as nonzero; A0 can act only where a
+// crossing reaches the period's last two columns (in this copy the rightmost
+// crossing lies before column x1 + 1 of the box, x1 = bx1 - kRightReach,
+// moved by -kx W).  Returns whether the copy has a seam line; A1 and A0 its
+// coefficients (the group sums read only then).
+TESS_HD inline bool edge_seam_coefs(const EdgePayload &E, uint32_t eid, const BinParams &B, int tx0, int n, int kx,
+                                    double &A1, double &A0) {
+    const bool hasm = (E.bx & kEdgeMinus) != 0u, hasp = (E.bx & kEdgePlus) != 0u;
+    const int bx1 = range_lo(E.bx) + (int)((E.bx >> 16) & kEdgeWidthMask) + kRightReach;
+    const bool a1 = kx == 0 ? hasp : kx == 1 ? true : kx == 2 ? hasm : false;
+    const bool a0 = kx == -1 ? hasp : kx == 0 ? true : kx == 1 ? hasm : false;
+    const bool near_end = tx0 + n > B.W - 3 && bx1 - kRightReach - kx * B.W >= B.W - 3;
+    A1 = 0.0;
+    A0 = 0.0;
+    if (!(B.seam && (a1 || (a0 && near_end)))) return false;
+    double Dm = 0.0, D0 = E.D, Dp = 0.0;
+    if (hasm || hasp) {
+        const int64_t nedge = (int64_t)B.ntet - B.first_edge;
+        Dm = B.groups[eid];
+        D0 = B.groups[nedge + eid];
+        Dp = B.groups[2 * nedge + eid];
+    }
+    A1 = kx == 0 ? Dp : kx == 1 ? D0 : kx == 2 ? Dm : 0.0;
+    A0 = near_end ? (kx == -1 ? Dp : kx == 0 ? D0 : kx == 1 ? Dm : 0.0) : 0.0;
+    return true;
+}
+
+// The seam line of edge copy kx (record column of the tile's column 0:
+// shift, tile row of record row 0: rshift, rows r0 .. r1) without the
+// fragment count, on the rows whose crossing this copy and tile hold
+// (floor(u) - shift in [-1, n - 2]; contiguous, as u is monotone in r): the
+// A1 part, A1 (u_c - j) with canonical position u_c = tx0 - shift + u linear
+// in the tile row rho = r + rshift, as one range update a += alpha + beta
+// rho, b += -A1; then the A0 part row by row where u_c >= W - 2.
+template <typename Seam, typename SeamRange>
+TESS_HD inline void edge_copy_seam(const EdgePayload &E, uint32_t eid, const BinParams &B, int tx0, int n, int kx,
+                                   int shift, int rshift, int r0, int r1, double iv, Seam &&seam,
+                                   SeamRange &&seam_range) {
+    double A1, A0;
+    if (!edge_seam_coefs(E, eid, B, tx0, n, kx, A1, A0)) return;
+    const double sl = E.sl, base = E.base;
+    int ha, hb;
+    if (!edge_held_rows(base, sl, iv, shift, n, r0, r1, ha, hb)) return;
+    if (A1 != 0.0) {
+        const double c0 = (double)(tx0 - shift) + base - (double)rshift * sl;
+        seam_range(ha + rshift, hb + rshift, A1 * c0, A1 * sl, -A1);
+    }
+    if (A0 != 0.0) {
+        // from the end where u_c is largest, while u_c > W - 2
+        const int step = sl >= 0.0 ? -1 : 1;
+        const double Wm2 = (double)B.W - 2.0;
+        for (int r = sl >= 0.0 ? hb : ha; r >= ha && r <= hb; r += step) {
+            const double uc = (double)tx0 + (fma((double)r, sl, base) - (double)shift);
+            const double near = uc - Wm2;
+            if (!(near > 0.0)) break;
+            seam(r + rshift, -A0 * near, -A0 * near);
+        }
     }
 }
 
@@ -1972,10 +2064,6 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
     axis_offsets(tx0, tx0 + n - 1, bx0, bx1, B.W, B.wrap, kx0, kx1);
     axis_offsets(ty0, ty0 + rows - 1, by0, by1, B.H, B.wrap, ky0, ky1);
     const double D = E.D;
-    // the sums by period offset: all of D at s = 0 unless the payload flags
-    // some at s = -1 or +1; those are read only for a tile copy that draws a
-    // seam line (below)
-    const bool hasm = (E.bx & kEdgeMinus) != 0u, hasp = (E.bx & kEdgePlus) != 0u;
     const double sl = E.sl, base = E.base;
     // rows per column, for the rows that reach a tile's columns (only the
     // choice of rows depends on it, with a margin: an estimate will do)
@@ -1993,94 +2081,31 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
             const int shift = tx0 + kx * B.W - bx0;  // record column of the tile's column 0
-            int r0, r1;
-            edge_copy_rows(base, iv, shift, n, q0, q1, r0, r1);
-            // the first copy's kinks: drawn by the caller (edge_job's copy)
+            // the first copy: drawn by the caller (edge_job's copy)
             const bool first = !seen;
             seen = true;
-            if (!(SKIP_FIRST && first)) kinks += (uint32_t)max(r1 - r0 + 1, 0);
+            if (SKIP_FIRST && first) continue;
+            int r0, r1;
+            edge_copy_rows(base, iv, shift, n, q0, q1, r0, r1);
+            kinks += (uint32_t)max(r1 - r0 + 1, 0);
             // record columns of the clamp: tile columns -3 .. n - 1
             const int klo = shift - 3, khi = shift + n - 1;
-            // the seam line of a crossing at canonical position u: the groups
-            // with s + kx = 1 add D (u - j), summed in A1; those with
-            // s + kx = 0 add -D (u - W + 2) (j + 1) when u >= W - 2, summed
-            // in A0 (the others add nothing)
-            // (which of them can be nonzero follows from the flags, taking
-            // the s = 0 sum as nonzero)
-            const bool a1 = kx == 0 ? hasp : kx == 1 ? true : kx == 2 ? hasm : false;
-            const bool a0 = kx == -1 ? hasp : kx == 0 ? true : kx == 1 ? hasm : false;
-            // A0 can act only where a crossing reaches the period's last two
-            // columns: in this copy the rightmost crossing lies before column
-            // x1 + 1 of the box (x1 = bx1 - kRightReach), moved by -kx W
-            const bool near_end = tx0 + n > B.W - 3 && bx1 - kRightReach - kx * B.W >= B.W - 3;
-            const bool seamed = B.seam && (a1 || (a0 && near_end));
-            double A1 = 0.0, A0 = 0.0;
-            if (seamed) {
-                double Dm = 0.0, D0 = D, Dp = 0.0;
-                if (hasm || hasp) {
-                    const int64_t nedge = (int64_t)B.ntet - B.first_edge;
-                    Dm = B.groups[eid];
-                    D0 = B.groups[nedge + eid];
-                    Dp = B.groups[2 * nedge + eid];
-                }
-                A1 = kx == 0 ? Dp : kx == 1 ? D0 : kx == 2 ? Dm : 0.0;
-                A0 = kx == -1 ? Dp : kx == 0 ? D0 : kx == 1 ? Dm : 0.0;
-            }
             double rv = (double)r0;
             if (!COUNT) {
                 // kinks (a crossing outside the tile's columns is clamped
-                // into the padding cells)
-                if (!(SKIP_FIRST && first))
-                    for (int r = r0; r <= r1; ++r, rv += 1.0) {
-                        const double u = fma(rv, sl, base);
-                        const double fl = floor(u);
-                        const int k = min(max((int)fl, klo), khi) - shift;
-                        const double v1 = fma(D, fl - u, D);
-                        dep(r + rshift, k + 1, v1, D - v1);
-                    }
-                if (!seamed) continue;
-                // the seam line, on the rows whose crossing this copy and tile
-                // hold (floor(u) - shift in [-1, n - 2]; contiguous, as u is
-                // monotone in r): the A1 part, A1 (u_c - j) with canonical
-                // position u_c = tx0 - shift + u linear in the tile row rho =
-                // r + rshift, as one range update a += alpha + beta rho,
-                // b += -A1; then the A0 part row by row where u_c >= W - 2
-                auto held = [&](int r) {
-                    const int kf = (int)floor(fma((double)r, sl, base)) - shift;
-                    return kf >= -1 && kf <= n - 2;
-                };
-                int ha = r0, hb = r1;
-                if (sl != 0.0) {
-                    // first guesses from iv, then moved to the exact ends
-                    double ya = ((double)(shift - 1) - base) * iv, yb = ((double)(shift + n - 1) - base) * iv;
-                    if (ya > yb) { const double t = ya; ya = yb; yb = t; }
-                    ya = fmin(fmax(ya, (double)r0), (double)r1);
-                    yb = fmin(fmax(yb, (double)r0), (double)r1);
-                    ha = (int)ya;
-                    hb = (int)yb;
+                // into the padding cells), then the copy's seam line
+                for (int r = r0; r <= r1; ++r, rv += 1.0) {
+                    const double u = fma(rv, sl, base);
+                    const double fl = floor(u);
+                    const int k = min(max((int)fl, klo), khi) - shift;
+                    const double v1 = fma(D, fl - u, D);
+                    dep(r + rshift, k + 1, v1, D - v1);
                 }
-                while (ha <= hb && !held(ha)) ++ha;
-                while (hb >= ha && !held(hb)) --hb;
-                if (ha > hb) continue;
-                while (ha > r0 && held(ha - 1)) --ha;
-                while (hb < r1 && held(hb + 1)) ++hb;
-                if (A1 != 0.0) {
-                    const double c0 = (double)(tx0 - shift) + base - (double)rshift * sl;
-                    seam_range(ha + rshift, hb + rshift, A1 * c0, A1 * sl, -A1);
-                }
-                if (A0 != 0.0 && near_end) {
-                    // from the end where u_c is largest, while u_c > W - 2
-                    const int step = sl >= 0.0 ? -1 : 1;
-                    const double Wm2 = (double)B.W - 2.0;
-                    for (int r = sl >= 0.0 ? hb : ha; r >= ha && r <= hb; r += step) {
-                        const double uc = (double)tx0 + (fma((double)r, sl, base) - (double)shift);
-                        const double near = uc - Wm2;
-                        if (!(near > 0.0)) break;
-                        seam(r + rshift, -A0 * near, -A0 * near);
-                    }
-                }
+                edge_copy_seam(E, eid, B, tx0, n, kx, shift, rshift, r0, r1, iv, seam, seam_range);
                 continue;
             }
+            double A1 = 0.0, A0 = 0.0;
+            const bool seamed = edge_seam_coefs(E, eid, B, tx0, n, kx, A1, A0);
             const int wm = kx - 1, w0 = kx, wp = kx + 1;
             const int fwrap = B.W * (wm * (nl[0] - ne[0]) + w0 * (nl[1] - ne[1]) + wp * (nl[2] - ne[2]));
             const double Wm2 = (double)B.W - 2.0;
@@ -2117,14 +2142,14 @@ TESS_HD inline uint32_t edge_pair(const EdgePayload &E, uint32_t eid, uint32_t c
 // edge_pair meets), for a caller that draws them apart from the rest: row r
 // of r0 .. r0 + cnt - 1 has its crossing at fma(r, sl, base), tile row
 // ta + (r - r0) and column clamp floor(crossing) - shift to [-3, n - 1].
-// rest: the edge has more to draw in this tile (a seam line for this copy,
-// or further copies), for edge_pair<false, true>, which skips the kinks of
-// exactly this copy.  cnt = 0: no kinks here (rest may still be set).
+// seamed: that copy has a seam line (edge_copy_seam with copy kx and rows
+// r0 .. r0 + cnt - 1 draws it); more: further copies, for edge_pair<false,
+// true>, which skips exactly this one.  cnt = 0: no kinks here.
 struct EdgeJob {
     double base, sl, D;
     int shift;
-    int r0, ta, cnt;
-    bool rest;
+    int r0, ta, cnt, kx;
+    bool seamed, more;
 };
 
 TESS_HD inline EdgeJob edge_job(const EdgePayload &E, const BinParams &B, int tx0, int ty0, int n, int rows,
@@ -2137,7 +2162,9 @@ TESS_HD inline EdgeJob edge_job(const EdgePayload &E, const BinParams &B, int tx
     J.r0 = 0;
     J.ta = 0;
     J.cnt = 0;
-    J.rest = false;
+    J.kx = 0;
+    J.seamed = false;
+    J.more = false;
     const int bx0 = range_lo(E.bx), bx1 = bx0 + (int)((E.bx >> 16) & kEdgeWidthMask) + kRightReach;
     const int by0 = range_lo(E.by), by1 = range_hi(E.by);
     int kx0, kx1, ky0, ky1;
@@ -2153,7 +2180,7 @@ TESS_HD inline EdgeJob edge_job(const EdgePayload &E, const BinParams &B, int tx
         for (int kx = kx0; kx <= kx1; ++kx) {
             if (tx0 + kx * B.W > bx1 || tx0 + n - 1 + kx * B.W < bx0) continue;
             if (seen) {
-                J.rest = true;
+                J.more = true;
                 return J;
             }
             seen = true;
@@ -2164,12 +2191,13 @@ TESS_HD inline EdgeJob edge_job(const EdgePayload &E, const BinParams &B, int tx
             J.r0 = r0;
             J.ta = r0 + rshift;
             J.cnt = max(r1 - r0 + 1, 0);
+            J.kx = kx;
             kinks += (uint32_t)J.cnt;
-            // a seam line for this copy: edge_pair's test
+            // edge_seam_coefs's test (without reading the group sums)
             const bool a1 = kx == 0 ? hasp : kx == 1 ? true : kx == 2 ? hasm : false;
             const bool a0 = kx == -1 ? hasp : kx == 0 ? true : kx == 1 ? hasm : false;
             const bool near_end = tx0 + n > B.W - 3 && bx1 - kRightReach - kx * B.W >= B.W - 3;
-            if (B.seam && (a1 || (a0 && near_end))) J.rest = true;
+            J.seamed = B.seam && (a1 || (a0 && near_end)) && J.cnt > 0;
         }
     }
     return J;

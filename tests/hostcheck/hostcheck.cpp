@@ -15,7 +15,8 @@ using namespace tess;
 
 // The edge raster's split drawing: the first tile copy's kinks from the
 // edge job (rows r0 .. r0 + cnt - 1, the terms the kernel's 16-lane groups
-// compute), then the pair routine without those kinks.
+// compute) and that copy's seam line, then the pair routine for the further
+// copies.
 template <typename Dep, typename Seam, typename SeamRange>
 static uint32_t split_pair(const EdgePayload &E, uint32_t eid, const BinParams &B, int tx0, int ty0, int n, int rows,
                            Dep &&dep, Seam &&seam, SeamRange &&seam_range, uint32_t &kinks) {
@@ -28,7 +29,10 @@ static uint32_t split_pair(const EdgePayload &E, uint32_t eid, const BinParams &
         const double v1 = fma(J.D, fl - u, J.D);
         dep(J.ta + s, k + 1, v1, J.D - v1);
     }
-    if (J.rest) return edge_pair<false, true>(E, eid, 0u, B, tx0, ty0, n, rows, dep, seam, seam_range, kinks);
+    if (J.seamed)
+        edge_copy_seam(E, eid, B, tx0, n, J.kx, J.shift, J.ta - J.r0, J.r0, J.r0 + J.cnt - 1,
+                       E.sl != 0.0 ? fast_rcp(E.sl) : 0.0, seam, seam_range);
+    if (J.more) return edge_pair<false, true>(E, eid, 0u, B, tx0, ty0, n, rows, dep, seam, seam_range, kinks);
     return 0u;
 }
 

@@ -549,13 +549,16 @@ constexpr int kIdBurst = 8;     // pair ids a lane loads at once
 constexpr int kSortPer = 7;     // pair ids per lane in one wavefront's class sort
 constexpr int kNumClasses = 32;
 constexpr size_t kLdsBytes = 160 * 1024 - 64;  // dynamic LDS: 64 bytes stay for the static counter
-// Row stride of the tile accumulator: Tw + 4 cells, rounded up to 1 modulo
-// 32 doubles (cells of one column in consecutive rows then fall in different
-// LDS banks) where the rounded rows leave room for one copy of the seam lines.
-__host__ __device__ inline int tile_stride(int Tw, int Th) {
+// Row stride of the tile accumulator: Tw + 4 cells; for the edge form
+// (`banked`) rounded up to 1 modulo 32 doubles, so that cells of one column
+// in consecutive rows fall in different LDS banks, where the rounded rows
+// leave room for one copy of the seam lines.  (The other forms draw a
+// record per lane, at cells with no such pattern, and need the LDS for the
+// wavefronts' class sorts.)
+__host__ __device__ inline int tile_stride(int Tw, int Th, bool banked) {
     const int plain = Tw + 2 * kPad, padded = ((plain + 30) & ~31) + 1;
     const size_t need = sizeof(double) * ((size_t)Th * padded + 2 * (size_t)Th + 3 * ((size_t)Th + 1));
-    return need <= kLdsBytes ? padded : plain;
+    return banked && need <= kLdsBytes ? padded : plain;
 }
 
 __device__ inline void wave_sync() {
@@ -634,7 +637,7 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
     const int n = min(B.Tw, B.W - tx0), rows = min(B.Th, B.H - ty0);
     // rows of at least Tw + 4 cells: two padding cells each side take the adds that
     // fall outside the tile, so that the raster needs no bounds tests
-    const int stride = tile_stride(B.Tw, B.Th);
+    const int stride = tile_stride(B.Tw, B.Th, FORM == kFormEdge);
     const int tsize = B.Th * stride;
     auto cell = [&](int row, int j) { return row * stride + kPad + j; };
     // then (edge form under wrap) per tile row the seam line a + b j, in
@@ -946,7 +949,8 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
     // the tile's accumulator, its seam lines (as many copies per row as fit,
     // up to 16), and beside them (when they fit) the wavefronts' class sorts
     BinParams Bl = B;
-    const size_t acc_lds = sizeof(double) * (size_t)B.Th * tile_stride(B.Tw, B.Th);
+    const bool edge_form = B.form != kFormFace && B.form != kFormSplat && B.form != kFormPersp && B.edges;
+    const size_t acc_lds = sizeof(double) * (size_t)B.Th * tile_stride(B.Tw, B.Th, edge_form);
     const size_t row_seam = sizeof(double) * (2 * (size_t)B.Th + 3 * ((size_t)B.Th + 1));
     Bl.seam_copies = B.seam ? (int)std::min<size_t>(16, std::max<size_t>(1, (kLdsBytes - acc_lds) / row_seam)) : 0;
     const size_t tile_lds = acc_lds + row_seam * (size_t)Bl.seam_copies;

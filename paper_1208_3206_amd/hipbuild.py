@@ -1,4 +1,5 @@
-"""Compiles the HIP library libtess.so for gfx950 (in-tree)."""
+"""Compiles the HIP library libtess.so for gfx950 (in-tree), and beside it
+the stand-alone memory probe `probe_mem` (LDS atomic and HBM gather rates)."""
 from __future__ import annotations
 
 import os
@@ -10,6 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libtess.so")
 SOURCES = ["tess_kernels.hip", "tess_mlp.hip", "tess_api.cpp", "tess_refine.cpp"]
+PROBE = os.path.join(HERE, "probe_mem")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -33,6 +35,13 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(LIB + ".tmp", LIB)
+    cmd = [HIPCC, *[f for f in FLAGS if f not in ("-fPIC", "-shared")], os.path.join(CSRC, "probe_mem.hip"),
+           "-o", PROBE + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building probe_mem")
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

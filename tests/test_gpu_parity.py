@@ -443,6 +443,67 @@ def test_batch_with_explicit_tune_and_new_output(tess):
             torch.testing.assert_close(a[s, v], tess.project(lats[s], views[v]), rtol=2.4e-7, atol=1e-9)
 
 
+_TUNE_CHILD = r"""
+import json, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_1208_3206_amd as tess
+import workloads as W
+import torch
+lats, keep = [], []
+for D in (1.0, 3.0):
+    xyz = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in W.zeldovich(12, 4, D)]
+    keep.append(xyz)
+    lats.append(tess.build(*xyz, (12, 12, 12)))
+views = [W.rotated_view(R, 72, 72) for R in W.random_rotations(2, seed=21)]
+img, st = tess.project_batch(lats, views, stats=True)
+np.save(sys.argv[2], img.cpu().numpy())
+print(json.dumps({"tile": [st["tile_rows"], st["tile_cols"]], "overflow": st["overflow"]}), flush=True)
+"""
+
+
+def test_tune_cache_roundtrip(tess, tmp_path, monkeypatch):
+    # the autotuner's choice for a batch shape goes to the JSON file that
+    # TESS_TUNE_CACHE names, and a fresh process takes it from there instead
+    # of tuning: this process tunes (12^3, 2 snapshots x 2 views of 72^2, a
+    # shape no other test uses) and writes the file; a child process then
+    # finds there an entry with another tiling for the shape, planted here,
+    # uses it and gives the same images
+    import json
+    import subprocess
+    import sys
+    import torch
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("TESS_TUNE_CACHE", str(cache))
+    lats, keep = [], []
+    for D in (1.0, 3.0):
+        xyz = dev(W.zeldovich(12, 4, D))
+        keep.append(xyz)
+        lats.append(tess.build(*xyz, (12, 12, 12)))
+    views = [W.rotated_view(R, 72, 72) for R in W.random_rotations(2, seed=21)]
+    img, st = tess.project_batch(lats, views, stats=True)
+    torch.cuda.synchronize()
+    lines = [ln for ln in cache.read_text().splitlines() if '"key":' in ln]
+    assert len(lines) == 1, cache.read_text()
+    entry = json.loads(lines[0].rstrip(","))
+    assert (entry["tile_rows"], entry["tile_cols"]) == (st["tile_rows"], st["tile_cols"])
+    assert entry["pair_capacity"] >= st["bin_pairs"] // 4  # the largest image's count, with a margin
+    # plant another tiling (and room for its pairs) under the same key
+    planted = dict(entry, tile_rows=8 if entry["tile_rows"] != 8 else 16, tile_cols=64, chunk=256,
+                   pair_capacity=64 * entry["pair_capacity"])
+    text = cache.read_text().replace(lines[0].rstrip(","), json.dumps(planted))
+    cache.write_text(text)
+    out = tmp_path / "child.npy"
+    env = dict(os.environ, TESS_TUNE_CACHE=str(cache))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root, str(out)], env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    got = json.loads(r.stdout.strip().splitlines()[-1])
+    assert got["tile"] == [planted["tile_rows"], 64] and got["overflow"] == 0
+    np.testing.assert_allclose(np.load(out), img.cpu().numpy(), rtol=2.4e-7, atol=1e-9)
+
+
 def test_batch_capacity_overflow_uses_the_overflow_raster(tess):
     # a pair capacity below the second view's count: its tile lists are
     # dropped and the overflow raster draws it inside the same graph; the

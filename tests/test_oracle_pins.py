@@ -458,6 +458,141 @@ def test_c5_point_sampled_mass_converges():
     assert errs[2] < errs[0] and errs[2] < 2e-3
 
 
+# ------------------------------------------- area-average mode (C2, C5, C6)
+def _random_tet(rng, lo=0.2, hi=0.8):
+    while True:
+        v = rng.uniform(lo, hi, size=(4, 3))
+        if abs(np.linalg.det(v[1:] - v[0])) > 1e-3:
+            return v
+
+
+def test_c2_area_mode_single_tet_carries_its_mass_exactly():
+    # the integral of dl over the projection is the volume, so a tetrahedron
+    # inside the window deposits exactly m (any view, any shape)
+    from oracle import area as A
+    rng = np.random.default_rng(11)
+    for k in range(6):
+        v = _random_tet(rng)
+        m = rng.uniform(0.5, 2.0)
+        if k % 2:
+            view = W.rotated_view(W.random_rotations(1, seed=30 + k)[0], 19, 23, side=1.6)
+        else:
+            view = W.z_view(24, 20)
+        img = A.project_tets_area(v[None], m, view)
+        apix = view["extent"][0] * view["extent"][1] / (view["width"] * view["height"])
+        assert abs(img.sum() * apix - m) <= 1e-12 * m, k
+
+
+def test_c2_area_mode_pixel_is_the_mean_of_the_tent():
+    # an area-mode pixel against a fine midpoint average of the independent
+    # tent closed form of rho * dl over the pixel square
+    from oracle import area as A
+    rng = np.random.default_rng(12)
+    v = _random_tet(rng)
+    m = 1.0
+    w = 8
+    img = A.project_tets_area(v[None], m, W.z_view(w))
+    s = 240
+    for (j, i) in zip(*np.nonzero(img > 0.05 * img.max())):
+        g = (np.arange(s) + 0.5) / s
+        uu, vv = np.meshgrid((i + g) / w, (j + g) / w)
+        mean = tent_value(v[:, :2], m, np.stack([uu.ravel(), vv.ravel()], 1)).mean()
+        assert abs(mean - img[j, i]) <= 4e-3 * img.max(), (i, j, mean, img[j, i])
+
+
+def test_c5_area_mode_mass_is_exact():
+    # a displaced periodic lattice under the wrapped z-view: the area mode
+    # carries the total mass exactly (point sampling only converges to it)
+    from oracle import area as A
+    n = 3
+    x, y, z = W.random_lattice(n, 0.1, seed=5)
+    tets = A.lattice_tets(x, y, z, (n, n, n))
+    assert tets.shape == (6 * n ** 3, 4, 3)
+    mass = 1.0 / len(tets)
+    for w, h in ((9, 9), (13, 7)):
+        img = A.project_tets_area(tets, mass, W.z_view(w, h))
+        assert abs(img.mean() - 1.0) <= 1e-12, (w, h, img.mean())
+        pt, _ = O.project_region(x, y, z, (n, n, n), W.z_view(w, h))
+        assert abs(pt.mean() - 1.0) > 1e-9  # the point mode is not exact at this resolution
+
+
+def test_c6_area_mode_against_dirichlet_deposits():
+    # K points uniform in each tetrahedron (Dirichlet(1,1,1,1) weights), each
+    # depositing m/K in the pixel its projection falls in: every pixel within
+    # 5 sigma of the area mode, and the normalised squared deviations average
+    # about 1
+    from oracle import area as A
+    n = 2
+    x, y, z = W.random_lattice(n, 0.12, seed=7)
+    tets = A.lattice_tets(x, y, z, (n, n, n))
+    mass = 1.0 / len(tets)
+    view = W.z_view(7, 6)
+    ref = A.project_tets_area(tets, mass, view)
+    K = 20000
+    mc = A.dirichlet_deposits(tets, mass, view, K, seed=3)
+    apix = 1.0 / (7 * 6)
+    # variance per pixel: sum over tets of (m/K)^2 K p (1 - p) / apix^2
+    var = np.zeros_like(ref)
+    rot, center = np.eye(3), np.array([0.5, 0.5, 0.5])
+    for tv in tets:
+        one = A.project_tets_area(tv[None], mass, view)
+        p = one * apix / mass
+        var += (mass / K) ** 2 * K * p * (1.0 - p) / apix ** 2
+    zs = (mc - ref) / np.sqrt(np.maximum(var, 1e-300))
+    assert np.abs(zs).max() < 5.0, np.abs(zs).max()
+    assert 0.4 < float((zs ** 2).mean()) < 2.0
+    assert abs(mc.mean() - 1.0) < 1e-12
+
+
+# ------------------------------------- C8: the entry/exit form of the sum
+def test_c8_entry_exit_form_and_its_fp32_cancellation():
+    # Eq. Eqn:TetSum writes a pixel as sum rho (t_exit - t_ref) - sum rho
+    # (t_entry - t_ref) over the tetrahedra the ray meets: in FP64 it is the
+    # projection (against the oracle's point mode); with the depths measured
+    # from a reference far in front (a camera 10^4 box lengths away) and the
+    # terms summed in FP32, the two sums cancel and the error reaches
+    # eps * (distance / chord) * sqrt(terms), far above the 1e-4 bar
+    from oracle import area as A
+    n = 3
+    x, y, z = W.random_lattice(n, 0.1, seed=6)
+    tets = A.lattice_tets(x, y, z, (n, n, n))
+    mass = 1.0 / len(tets)
+    w = 9
+    img, _ = O.project_region(x, y, z, (n, n, n), W.z_view(w))
+    t_ref = -1.0e4
+    planes, rhos = [], []
+    for tv in tets:
+        for sx in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                yv = tv + np.array([sx, sy, 0.0]) - 0.5
+                vol = np.dot(yv[1] - yv[0], np.cross(yv[2] - yv[0], yv[3] - yv[0])) / 6.0
+                planes.append(A.face_planes(yv))
+                rhos.append(mass / abs(vol))
+    worst64, worst32, pred = 0.0, 0.0, 0.0
+    for (j, i) in [(0, 0), (4, 4), (7, 2), (3, 8)]:
+        pu, pv = (i + 0.5) / w - 0.5, (j + 0.5) / w - 0.5
+        ex, en = [], []
+        for pl, r in zip(planes, rhos):
+            lo, hi = A.ray_interval(pl, pu, pv)
+            if np.isfinite(lo) and np.isfinite(hi) and hi > lo:
+                ex.append(r * (hi - t_ref))
+                en.append(r * (lo - t_ref))
+        ref = img[j, i]
+        f64 = sum(ex) - sum(en)
+        e32 = np.float32(0.0)
+        n32 = np.float32(0.0)
+        for a in ex:
+            e32 = np.float32(e32 + np.float32(a))
+        for a in en:
+            n32 = np.float32(n32 + np.float32(a))
+        worst64 = max(worst64, abs(f64 - ref) / ref)
+        worst32 = max(worst32, abs(float(e32 - n32) - ref) / ref)
+        pred = max(pred, 2.0 ** -24 * abs(t_ref) * max(rhos) * math.sqrt(2 * len(ex)) / ref)
+    assert worst64 < 1e-9, worst64
+    assert worst32 > 1e-3, worst32          # the cancellation: ten times the per-pixel bar and more
+    assert worst32 < 50 * pred, (worst32, pred)
+
+
 # ------------------------------------------------- C6: Monte Carlo on rays
 def test_c6_monte_carlo_along_rays():
     n = 2

@@ -373,6 +373,8 @@ void make_params(const tess_lattice_s *L, const tess_view *v, int form, LatticeP
     vp.v_bottom = -0.5 * v->extent[1];
     vp.inv_du = v->width / v->extent[0];
     vp.inv_dv = v->height / v->extent[1];
+    vp.inv_W = 1.0 / v->width;
+    vp.inv_H = 1.0 / v->height;
     vp.mass_px = 6.0 * lp.tet_mass * vp.inv_du * vp.inv_dv;
     // steepest x slope a crease-form footprint may have: a kink's rounding
     // (2^-53 of its slope change) grows by up to the image width along the

@@ -27,6 +27,7 @@ struct ViewParams {
     double center[3];
     double u_left, v_bottom;
     double inv_du, inv_dv;
+    double inv_W, inv_H;     // 1 / W and 1 / H (the period tests of a wrapped image)
     double mass_px;          // 6 m * inv_du * inv_dv (density scale in pixel units)
     double crease_bmax;      // footprints with a steeper x slope keep the line form
     int32_t W, H;

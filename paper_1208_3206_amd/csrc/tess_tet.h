@@ -444,12 +444,27 @@ struct CubeCounts {
 // The eight corners of a lattice cube: corner 0's position X0 and every
 // corner's offset e[n] from it, unwrapped to the nearest periodic image.
 // Returns true when some corner was moved by a box length.
+// Lattice coordinates (i, j, k) of cube `cube` = i + c0 (j + c1 k): in
+// 32-bit arithmetic (two divisions) below 2^31 cubes.
+TESS_HD inline void cube_ijk(const LatticeParams &L, int64_t cube, int64_t &i, int64_t &j, int64_t &k) {
+    if (L.ncubes <= 0x7fffffff) {
+        const uint32_t c = (uint32_t)cube, c0 = (uint32_t)L.c[0], c1 = (uint32_t)L.c[1];
+        const uint32_t r = c / c0, kk = r / c1;
+        i = (int64_t)(c - r * c0);
+        j = (int64_t)(r - kk * c1);
+        k = (int64_t)kk;
+    } else {
+        const int64_t r = cube / L.c[0];
+        i = cube - r * L.c[0];
+        k = r / L.c[1];
+        j = r - k * L.c[1];
+    }
+}
+
 TESS_HD inline bool cube_corners(const LatticeParams &L, int64_t cube, double X0[3], double e[8][3]) {
     bool moved = false;
-    const int64_t i = cube % L.c[0];
-    const int64_t rest = cube / L.c[0];
-    const int64_t j = rest % L.c[1];
-    const int64_t k = rest / L.c[1];
+    int64_t i, j, k;
+    cube_ijk(L, cube, i, j, k);
     // gather the eight corners (tracer id = i + d0 (j + d1 k))
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
@@ -511,7 +526,7 @@ TESS_HD inline double vertex_px(const LatticeParams &L, const ViewParams &V, int
     const double b0[3] = {(double)L.x[id] - V.center[0], (double)L.y[id] - V.center[1],
                           (double)L.z[id] - V.center[2]};
     double px = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
-    if (V.wrap) px -= (double)V.W * floor(px / (double)V.W);
+    if (V.wrap) px -= (double)V.W * floor(px * V.inv_W);
     return px;
 }
 
@@ -526,7 +541,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                                CubeCounts &cnt) {
     double X0[3], e[8][3];
     const bool moved = cube_corners(L, cube, X0, e);
-    const int64_t ci = cube % L.c[0], cj = (cube / L.c[0]) % L.c[1], ck = cube / ((int64_t)L.c[0] * L.c[1]);
+    int64_t ci, cj, ck;
+    cube_ijk(L, cube, ci, cj, ck);
     const int64_t nvert = (int64_t)L.d[0] * L.d[1] * L.d[2];
     // edge form: the cube's edges are placed from their own vertices (corners
     // of this cube).  That gives the same segments as this cube's corners if
@@ -556,8 +572,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
     double PX0 = (V.rot[0] * b0[0] + V.rot[1] * b0[1] + V.rot[2] * b0[2] - V.u_left) * V.inv_du;
     double PY0 = (V.rot[3] * b0[0] + V.rot[4] * b0[1] + V.rot[5] * b0[2] - V.v_bottom) * V.inv_dv;
     if (V.wrap) {  // a periodic image: move corner 0 into the first period
-        PX0 -= (double)V.W * floor(PX0 / (double)V.W);
-        PY0 -= (double)V.H * floor(PY0 / (double)V.H);
+        PX0 -= (double)V.W * floor(PX0 * V.inv_W);
+        PY0 -= (double)V.H * floor(PY0 * V.inv_H);
     }
     double PX[8], PY[8];
 #pragma unroll
@@ -580,7 +596,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 if (jj == L.d[1]) jj = 0;
                 if (kk == L.d[2]) kk = 0;
                 const double pe = vertex_px(L, V, ii + (int64_t)L.d[0] * (jj + (int64_t)L.d[1] * kk));
-                const double q = fmin(fmax(rint((PX[n] - pe) / (double)V.W), -2.0), 13.0);
+                const double q = fmin(fmax(rint((PX[n] - pe) * V.inv_W), -2.0), 13.0);
                 qpack |= (uint32_t)((int)q + 2) << (4 * n);
             }
         }
@@ -840,7 +856,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 bool take = crease && V.edges && same_frame;
                 uint32_t shift = 0x555u;  // s + 1 = 1 for all six edges
                 if (take && V.wrap) {
-                    const int pt = (int)floor(xmin / (double)V.W);  // this frame's period of xmin
+                    const int pt = (int)floor(xmin * V.inv_W);  // this frame's period of xmin
                     take = xmax - xmin < (double)V.W - 2.0;
                     shift = 0u;
 #pragma unroll
@@ -926,11 +942,11 @@ TESS_HD inline bool edge_box(double ax, double ay, double bx, double by, const B
 // An edge with nothing to draw gets flags 0.
 TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams &V, int64_t v,
                                        RecHead *head, EdgePayload *ecoef) {
-    const int64_t i = v % L.d[0];
-    const int64_t rest = v / L.d[0];
-    const int64_t j = rest % L.d[1];
-    const int64_t k = rest / L.d[1];
     const int64_t nvert = (int64_t)L.d[0] * L.d[1] * L.d[2];
+    const int64_t rest = v / L.d[0];
+    const int64_t i = v - rest * L.d[0];
+    const int64_t k = rest / L.d[1];
+    const int64_t j = rest - k * L.d[1];
     // corners 0..4 of the cube at v (they may lie past a non-periodic lattice)
     double X0[3] = {0.0, 0.0, 0.0}, e[5][3];
     bool has[5];
@@ -961,7 +977,7 @@ TESS_HD inline void setup_vertex_edges(const LatticeParams &L, const ViewParams 
     const double b0[3] = {X0[0] - V.center[0], X0[1] - V.center[1], X0[2] - V.center[2]};
     const double PX0 = vertex_px(L, V, v);
     double PY0 = (V.rot[3] * b0[0] + V.rot[4] * b0[1] + V.rot[5] * b0[2] - V.v_bottom) * V.inv_dv;
-    if (V.wrap) PY0 -= (double)V.H * floor(PY0 / (double)V.H);
+    if (V.wrap) PY0 -= (double)V.H * floor(PY0 * V.inv_H);
     // the slope changes by period offset of the edges that have offsets: kept
     // until every slot of this vertex has been read, then written over slots
     // 7 g + tau of this vertex (the slots' edge-major view, BinParams::groups)

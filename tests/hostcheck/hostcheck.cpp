@@ -65,6 +65,8 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
     V.v_bottom = -0.5 * extent[1];
     V.inv_du = W / extent[0];
     V.inv_dv = H / extent[1];
+    V.inv_W = 1.0 / W;
+    V.inv_H = 1.0 / H;
     V.mass_px = 6.0 * L.tet_mass * V.inv_du * V.inv_dv;
     V.crease_bmax = crease_div > 0 ? V.mass_px * (double)L.ncubes / ((double)W * H) / crease_div : -1.0;
     V.W = W; V.H = H; V.wrap = wrap; V.qpow = qpow;

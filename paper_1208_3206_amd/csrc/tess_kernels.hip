@@ -619,6 +619,9 @@ __device__ __forceinline__ void group_kinks(const EdgeJob &J, uint32_t pk, int q
 
 // LDS of one wavefront's class sort: kNumClasses counters, then 64 * kSortPer entries
 constexpr int kSortWords = kNumClasses + 64 * kSortPer;
+// edge form: a wavefront's queue of pairs whose seam lines are still to draw
+// (at most 63 waiting plus 64 added in one round)
+constexpr int kSeamQueue = 128;
 
 template <int TPB, int FORM, bool COUNT = true>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,
@@ -817,6 +820,30 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
             // this the wait before each pair's first use also takes the next
             // pair's loads)
             __builtin_amdgcn_s_waitcnt(0);
+            // Seam lines are queued per wavefront (pair ids in LDS, after the
+            // tile's seam arrays) and drawn 64 at a time with every lane busy:
+            // about one pair in seven has one, and drawn as it comes each
+            // held up its whole wavefront.  qn is the same in every active
+            // lane; lane 0 is active for every round (its group runs out
+            // last), so it holds the count after the loop.
+            uint32_t *sQueue = reinterpret_cast<uint32_t *>(sA + tsize + nseam) + (threadIdx.x >> 6) * kSeamQueue;
+            uint32_t qn = 0u;
+            // queue entries first .. first + cnt - 1, taken in turn by the
+            // active lanes (the edge job recomputed for its copy and rows)
+            auto seam_entries = [&](uint32_t first, uint32_t cnt) {
+                const uint64_t act = __builtin_amdgcn_read_exec();
+                const uint32_t nact = (uint32_t)__builtin_popcountll(act);
+                const uint32_t rank =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+                for (uint32_t k = rank; k < cnt; k += nact) {
+                    const uint32_t sid = sQueue[first + k];
+                    const EdgePayload Q = ecoef[sid - B.first_edge];
+                    uint32_t counted = 0u;  // (its kinks were counted when the pair was drawn)
+                    const EdgeJob K = edge_job(Q, B, tx0, ty0, n, rows, counted);
+                    edge_copy_seam(Q, sid - B.first_edge, B, tx0, n, K.kx, K.shift, K.ta - K.r0, K.r0,
+                                   K.r0 + K.cnt - 1, Q.sl != 0.0 ? fast_rcp(Q.sl) : 0.0, seam, seam_range);
+                }
+            };
             while (e != kDone) {
                 const uint32_t enn = take();
                 const uint32_t idnn = id_at(enn);
@@ -838,9 +865,27 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                         group_kinks<0, true>(J, pk, (int)q, n, sA, stride);
                     else
                         group_kinks<0, false>(J, pk, (int)q, n, sA, stride);
-                    if (J.seamed)
-                        edge_copy_seam(P, id - B.first_edge, B, tx0, n, J.kx, J.shift, J.ta - J.r0, J.r0,
-                                       J.r0 + J.cnt - 1, P.sl != 0.0 ? fast_rcp(P.sl) : 0.0, seam, seam_range);
+                    const uint64_t sm = __builtin_amdgcn_ballot_w64(J.seamed);
+                    if (sm != 0ull) {
+                        const uint32_t below =
+                            __builtin_amdgcn_mbcnt_hi((uint32_t)(sm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)sm, 0u));
+                        if (J.seamed) sQueue[qn + below] = id;
+                        qn += (uint32_t)__builtin_popcountll(sm);  // at most 63 + 64 < kSeamQueue
+                        if (qn >= 64u) {
+                            wave_sync();
+                            seam_entries(0u, 64u);
+                            // the rest (fewer than 64) to the front
+                            const uint32_t rest = qn - 64u;
+                            const uint64_t act = __builtin_amdgcn_read_exec();
+                            const uint32_t nact = (uint32_t)__builtin_popcountll(act);
+                            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+                            wave_sync();
+                            for (uint32_t k = rank; k < rest; k += nact) sQueue[k] = sQueue[64u + k];
+                            wave_sync();
+                            qn = rest;
+                        }
+                    }
                     if (J.more)
                         frags += (int32_t)edge_pair<false, true>(P, id - B.first_edge, 0u, B, tx0, ty0, n, rows, dep,
                                                                  seam, seam_range, kinks);
@@ -850,6 +895,11 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                 id = idn;
                 idn = idnn;
                 P = Pn;
+            }
+            if constexpr (!COUNT) {
+                qn = (uint32_t)__builtin_amdgcn_readfirstlane((int)qn);
+                wave_sync();
+                seam_entries(0u, qn);
             }
             const uint32_t g0 = g * C, g1 = min(it.count, g0 + C);
             // then the tetrahedra that kept their own records
@@ -952,8 +1002,10 @@ hipError_t launch_raster(const RecHead *head, const Payload *coef, const EdgePay
     const bool edge_form = B.form != kFormFace && B.form != kFormSplat && B.form != kFormPersp && B.edges;
     const size_t acc_lds = sizeof(double) * (size_t)B.Th * tile_stride(B.Tw, B.Th, edge_form);
     const size_t row_seam = sizeof(double) * (2 * (size_t)B.Th + 3 * ((size_t)B.Th + 1));
-    Bl.seam_copies = B.seam ? (int)std::min<size_t>(16, std::max<size_t>(1, (kLdsBytes - acc_lds) / row_seam)) : 0;
-    const size_t tile_lds = acc_lds + row_seam * (size_t)Bl.seam_copies;
+    const size_t queue_lds = edge_form ? sizeof(uint32_t) * (size_t)(block / 64) * kSeamQueue : 0;
+    const size_t room = kLdsBytes > acc_lds + queue_lds ? kLdsBytes - acc_lds - queue_lds : 0;
+    Bl.seam_copies = B.seam ? (int)std::min<size_t>(16, std::max<size_t>(1, room / row_seam)) : 0;
+    const size_t tile_lds = acc_lds + row_seam * (size_t)Bl.seam_copies + queue_lds;
     if (tile_lds > kLdsBytes) return hipErrorInvalidValue;  // (tiles of at most 16384 cells fit)
     const size_t sort_lds = sizeof(uint32_t) * (size_t)(block / 64) * kSortWords;
     const int sorted = B.nkey > 1 && tile_lds + sort_lds <= kLdsBytes ? 1 : 0;

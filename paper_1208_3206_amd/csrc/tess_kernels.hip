@@ -567,6 +567,14 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// min(max(x, lo), hi) for lo <= hi in one instruction (the compiler forms
+// v_med3_i32 only for constant bounds).
+__device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
+    int r;
+    asm volatile("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
 // Lane I's value of its 16-lane row, in every lane of the row (a DPP row
 // broadcast: no LDS traffic).
 template <int I>
@@ -594,24 +602,25 @@ __device__ __forceinline__ void group_kinks(const EdgeJob &J, uint32_t pk, int q
         const int ta = (int)(pki & 0xffu);
         const int r0 = (int)row_bcast<I>((uint32_t)J.r0), shift = (int)row_bcast<I>((uint32_t)J.shift);
         const double base = row_bcast<I>(J.base), sl = row_bcast<I>(J.sl), D = row_bcast<I>(J.D);
-        const int klo = shift - 3, khi = shift + n - 1;
-        // cell of column floor(u) - shift + 1 in row ta + q: xb + floor(u)
-        const int xb = (ta + q) * stride + kPad + 1 - shift;
-        auto kink = [&](int x0, double rv) {
+        const int klo = shift - 3, khi = shift + n - 1;  // klo < khi
+        // row ta + q of the tile, moved so that column floor(u) - shift + 1
+        // is element floor(u)
+        double *const rowp = sA + ((ta + q) * stride + kPad + 1 - shift);
+        auto kink = [&](double *row, double rv) {
             const double u = fma(rv, sl, base);
             const double fl = floor(u);
-            const int x = x0 + min(max((int)fl, klo), khi);
+            const int x = med3_i32((int)fl, klo, khi);
             const double v1 = fma(D, fl - u, D);
-            atomicAdd(&sA[x], v1);
-            atomicAdd(&sA[x + 1], D - v1);
+            atomicAdd(&row[x], v1);
+            atomicAdd(&row[x + 1], D - v1);
         };
         if constexpr (TWO) {
             const double rv = (double)(r0 + q);
-            if (q < cnt) kink(xb, rv);
-            if (q + 16 < cnt) kink(xb + 16 * stride, rv + 16.0);
+            if (q < cnt) kink(rowp, rv);
+            if (q + 16 < cnt) kink(rowp + 16 * stride, rv + 16.0);
         } else {
-            int x0 = xb;
-            for (int s = q; s < cnt; s += 16, x0 += 16 * stride) kink(x0, (double)(r0 + s));
+            double *row = rowp;
+            for (int s = q; s < cnt; s += 16, row += 16 * stride) kink(row, (double)(r0 + s));
         }
     }
     if constexpr (I < 15) group_kinks<I + 1, TWO>(J, pk, q, n, sA, stride);

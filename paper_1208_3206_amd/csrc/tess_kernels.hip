@@ -50,10 +50,12 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// One thread per lattice cube; writes the six records 6*cube .. 6*cube+5.
-// Two wavefronts per SIMD at least: the edge form's setup would otherwise
-// take 256 VGPRs and run one wavefront per SIMD; with the bound it spills a
-// little to scratch and runs 1.5x faster (measured at stress 256^3).
+// One thread per lattice cube; writes the six records 6*cube .. 6*cube+5
+// (edge form: the edge slots of the tetrahedra that edge_tet_fast settles,
+// the others left to k_setup_rest).  Two wavefronts per SIMD at least: the
+// general setup would otherwise take 256 VGPRs and run one wavefront per
+// SIMD.  The edge form's kernel indexes no array by tetrahedron and takes
+// no scratch memory, which would cap the wavefronts in flight.
 template <int FORM, bool EDGES>
 __global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
                                                RecHead *__restrict__ head,
@@ -63,24 +65,19 @@ __global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
     if constexpr (EDGES) {
-        // edge form: only the few tetrahedra that keep their own record are
-        // stored, numbered as they come (their heads and payloads; the
-        // others' creases went to the edge slots)
-        for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride)
-            setup_cube<FORM, EDGES>(
-                L, V, cube,
-                [&](int t, const RecHead &R, const Payload &P) {
-                    if (!(R.flags & REC_VALID)) return;
-                    const unsigned long long slot = atomicAdd(V.own, 1ull);
-                    if (slot < V.own_cap) {
-                        head[slot] = R;
-                        coef[slot] = P;
-                    } else {
-                        const int64_t tet = 6 * cube + t;
-                        atomicOr(&V.spill[tet >> 5], 1u << (tet & 31));
-                    }
-                },
-                cnt);
+        // edge form, the common case of every tetrahedron (no record: its
+        // creases go to the edge slots); the others are marked in the spill
+        // bit set, which k_setup_rest reads next
+        for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
+            uint32_t todo = 0u;
+            setup_cube<FORM, EDGES, 1>(L, V, cube, [](int, const RecHead &, const Payload &) {}, cnt, &todo);
+            while (todo) {
+                const int t = __builtin_ctz(todo);
+                todo &= todo - 1u;
+                const int64_t tet = 6 * cube + t;
+                atomicOr(&V.spill[tet >> 5], 1u << (tet & 31));
+            }
+        }
     } else {
         // The block's heads are built in LDS and then written as one
         // contiguous run: a thread's six 16-byte heads written in place would
@@ -109,6 +106,54 @@ __global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
                              n_inv = wave_sum(cnt.n_inv), n_dets = wave_sum(cnt.n_dets),
                              n_deg = wave_sum(cnt.n_deg);
     if (lane == 0) {
+        if (n_tets) atomicAdd(&counters->tets, n_tets);
+        if (n_zero) atomicAdd(&counters->zero_volume, n_zero);
+        if (n_inv) atomicAdd(&counters->inverted, n_inv);
+        if (n_dets) atomicAdd(&counters->fp64_dets, n_dets);
+        if (n_deg) atomicAdd(&counters->degenerate, n_deg);
+    }
+}
+
+// Edge form, after k_setup: the tetrahedra it left to the general code, one
+// thread per 32-bit word of the spill bit set (the bits k_setup marked).  A
+// word is cleared, then each of its tetrahedra set up; those whose own
+// record finds no room mark their bit again, the set's meaning for the
+// raster (every tetrahedron in one word belongs to this thread).
+__global__ void __launch_bounds__(256) k_setup_rest(LatticeParams L, ViewParams V, RecHead *__restrict__ head,
+                                                    Payload *__restrict__ coef, DevCounters *__restrict__ counters) {
+    CubeCounts cnt;
+    const int64_t nwords = (6 * L.ncubes + 31) / 32;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        uint32_t bits = V.spill[w];
+        if (bits == 0u) continue;
+        V.spill[w] = 0u;
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            const int64_t tet = 32 * w + b;
+            const int64_t cube = tet / 6;
+            uint32_t todo = 1u << (int)(tet - 6 * cube);
+            setup_cube<kFormPyramid, true, 2>(
+                L, V, cube,
+                [&](int t, const RecHead &R, const Payload &P) {
+                    if (!(R.flags & REC_VALID)) return;
+                    const unsigned long long slot = atomicAdd(V.own, 1ull);
+                    if (slot < V.own_cap) {
+                        head[slot] = R;
+                        coef[slot] = P;
+                    } else {
+                        const int64_t id = 6 * cube + t;
+                        atomicOr(&V.spill[id >> 5], 1u << (id & 31));
+                    }
+                },
+                cnt, &todo);
+        }
+    }
+    const unsigned long long n_tets = wave_sum(cnt.n_tets), n_zero = wave_sum(cnt.n_zero),
+                             n_inv = wave_sum(cnt.n_inv), n_dets = wave_sum(cnt.n_dets),
+                             n_deg = wave_sum(cnt.n_deg);
+    if ((threadIdx.x & 63) == 0) {
         if (n_tets) atomicAdd(&counters->tets, n_tets);
         if (n_zero) atomicAdd(&counters->zero_volume, n_zero);
         if (n_inv) atomicAdd(&counters->inverted, n_inv);
@@ -148,17 +193,26 @@ __global__ void __launch_bounds__(256) k_qsum(LatticeParams L, ViewParams V, dou
     if ((threadIdx.x & 63) == 0 && sum != 0.0) atomicAdd(qsum, sum);
 }
 
+// Blocks of 256 threads for a grid-stride loop over n items: at most
+// kCubeBlocks, so that a thread takes several cubes.  One cube per thread
+// ran a quarter of a million short wavefronts per frame at 256^3, whose
+// start-up and end-of-wavefront counter atomics (all on the same few
+// addresses) took longer than the setup's arithmetic.
+constexpr int kCubeBlocks = 8192;
+inline int cube_blocks(int64_t n, int cap = kCubeBlocks) {
+    const int64_t want = (n + 255) / 256;
+    return (int)(want < cap ? (want > 0 ? want : 1) : cap);
+}
+
 hipError_t launch_qsum(const LatticeParams &L, const ViewParams &V, double *qsum, hipStream_t stream) {
-    const int64_t want = (L.ncubes + 255) / 256;
-    const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    const int blocks = cube_blocks(L.ncubes);
     hipLaunchKernelGGL(k_qsum, dim3(blocks), dim3(256), 0, stream, L, V, qsum);
     return hipGetLastError();
 }
 
 hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *head, Payload *coef,
                         DevCounters *counters, hipStream_t stream) {
-    const int64_t want = (L.ncubes + 255) / 256;
-    const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    const int blocks = cube_blocks(L.ncubes);
     switch (view_form(V)) {
         case kFormFace:
             hipLaunchKernelGGL((k_setup<kFormFace, false>), dim3(blocks), dim3(256), 0, stream, L, V, head, coef, counters);
@@ -172,10 +226,12 @@ hipError_t launch_setup(const LatticeParams &L, const ViewParams &V, RecHead *he
                                counters);
             break;
         default:
-            if (V.edges)
+            if (V.edges) {
                 hipLaunchKernelGGL((k_setup<kFormPyramid, true>), dim3(blocks), dim3(256), 0, stream, L, V, head,
                                    coef, counters);
-            else
+                hipLaunchKernelGGL(k_setup_rest, dim3(cube_blocks((6 * L.ncubes + 31) / 32, 1024)), dim3(256), 0,
+                                   stream, L, V, head, coef, counters);
+            } else
                 hipLaunchKernelGGL((k_setup<kFormPyramid, false>), dim3(blocks), dim3(256), 0, stream, L, V, head,
                                    coef, counters);
     }

@@ -441,6 +441,45 @@ struct CubeCounts {
     unsigned n_tets = 0, n_zero = 0, n_inv = 0, n_dets = 0, n_deg = 0;
 };
 
+// 6 V of the tetrahedron on cube corners v0..v3 (offsets e from corner 0),
+// Eq. Eqn:TetVolume: FP32 with a forward error bound, FP64 when the bound
+// cannot certify it or it is small (flagged).
+TESS_HD inline double tet_det6(const LatticeParams &L, const double e[8][3], int v0, int v1, int v2, int v3,
+                               bool &flagged) {
+    double a64[3], b64[3], c64[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        a64[q] = e[v1][q] - e[v0][q];
+        b64[q] = e[v2][q] - e[v0][q];
+        c64[q] = e[v3][q] - e[v0][q];
+    }
+    const float a[3] = {(float)a64[0], (float)a64[1], (float)a64[2]};
+    const float b[3] = {(float)b64[0], (float)b64[1], (float)b64[2]};
+    const float c[3] = {(float)c64[0], (float)c64[1], (float)c64[2]};
+    const float p1 = b[1] * c[2], p2 = b[2] * c[1];
+    const float p3 = b[2] * c[0], p4 = b[0] * c[2];
+    const float p5 = b[0] * c[1], p6 = b[1] * c[0];
+    const float d32 = a[0] * (p1 - p2) + a[1] * (p3 - p4) + a[2] * (p5 - p6);
+    const float perm = fabsf(a[0]) * (fabsf(p1) + fabsf(p2)) + fabsf(a[1]) * (fabsf(p3) + fabsf(p4)) +
+                       fabsf(a[2]) * (fabsf(p5) + fabsf(p6));
+    const double ad = fabs((double)d32);
+    flagged = L.det_cond_k < 0.0 || ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
+              ad < 2.0 * 6.0 * L.det_v0_frac * L.v0;
+    return flagged ? det6_fp64(a64, b64, c64) : (double)d32;
+}
+
+// The setup's counts for one tetrahedron of determinant det6.
+TESS_HD inline void count_tet(const LatticeParams &L, double det6, bool flagged, CubeCounts &cnt) {
+    cnt.n_dets += flagged ? 1 : 0;
+    if (det6 == 0.0) {
+        ++cnt.n_zero;
+        return;
+    }
+    ++cnt.n_tets;
+    cnt.n_inv += det6 > 0 ? 1 : 0;
+    cnt.n_deg += fabs(det6) < 6.0 * L.det_v0_frac * L.v0 ? 1 : 0;
+}
+
 // The eight corners of a lattice cube: corner 0's position X0 and every
 // corner's offset e[n] from it, unwrapped to the nearest periodic image.
 // Returns true when some corner was moved by a box length.
@@ -530,15 +569,158 @@ TESS_HD inline double vertex_px(const LatticeParams &L, const ViewParams &V, int
     return px;
 }
 
+// Edge form, the common case of one tetrahedron taken directly: its six
+// slope changes kd (the crease form's, as crease_kinks gives them), the
+// silhouette kinds sil (2 bits per local edge) and the period offsets shf (2
+// bits per local edge, s + 1), with the counts.  The pyramid's creases
+// follow from the silhouette set alone: a silhouette edge (i, j) changes the
+// row slope by |b|, b the x slope of its face function (footprint's K
+// times -dy); any other edge is a ridge or a diagonal, whose change is
+// -|b(v, k) - b(v, l)| at an end v whose edges to the other two vertices k,
+// l are both silhouette edges (one end for a ridge of a triangular
+// silhouette, both ends for a diagonal of a quadrilateral one, averaged).
+// Returns -1, having counted nothing, when the tetrahedron needs the
+// general setup: a face seen edge-on, a silhouette set that is neither a
+// triangle nor a quadrilateral, crossing diagonals not found, a slope past
+// the line-form bound, or a period or margin test that fails; 0 (zeros)
+// when it has no volume or covers no pixel centre; else its number of
+// silhouette edges.
+TESS_HD inline int edge_tet_fast(const LatticeParams &L, const ViewParams &V, int t, const double e[8][3],
+                                  const double PX[8], const double PY[8], double crease_bmax, bool same_frame,
+                                  uint32_t qpack, double kd[6], uint32_t &sil, uint32_t &shf, CubeCounts &cnt) {
+    const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
+    bool flagged;
+    const double det6 = tet_det6(L, e, v0, v1, v2, v3, flagged);
+    if (det6 == 0.0) {
+        count_tet(L, det6, flagged, cnt);
+        return 0;
+    }
+    const int vi[4] = {v0, v1, v2, v3};
+    double xmin = PX[v0], xmax = PX[v0], ymin = PY[v0], ymax = PY[v0];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) {
+        xmin = fmin(xmin, PX[vi[m]]); xmax = fmax(xmax, PX[vi[m]]);
+        ymin = fmin(ymin, PY[vi[m]]); ymax = fmax(ymax, PY[vi[m]]);
+    }
+    const double lim = 1.0e8;
+    int ix0 = (int)fmax(ceil(xmin - 0.5), -lim), ix1 = (int)fmin(floor(xmax - 0.5), lim);
+    int iy0 = (int)fmax(ceil(ymin - 0.5), -lim), iy1 = (int)fmin(floor(ymax - 0.5), lim);
+    if (!V.wrap) {
+        ix0 = ix0 > 0 ? ix0 : 0;
+        iy0 = iy0 > 0 ? iy0 : 0;
+        ix1 = ix1 < V.W - 1 ? ix1 : V.W - 1;
+        iy1 = iy1 < V.H - 1 ? iy1 : V.H - 1;
+    }
+    if (ix0 > ix1 || iy0 > iy1) {
+        count_tet(L, det6, flagged, cnt);
+        return 0;
+    }
+    // the period and margin tests of the edge form (as in setup_cube)
+    if (!same_frame) return -1;
+    uint32_t shift = 0x555u;
+    if (V.wrap) {
+        if (!(xmax - xmin < (double)V.W - 2.0)) return -1;
+        const int pt = (int)floor(xmin * V.inv_W);
+        shift = 0u;
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const EdgeSlot S = kEdgeSlots.s[t][q];
+            const int m = S.ox + 2 * S.oy + 4 * S.oz;
+            const int per = (int)((qpack >> (4 * m)) & 15u) - 2 - pt;
+            ok = ok && per >= -1 && per <= 1;
+            shift |= (uint32_t)(per + 1) << (2 * q);
+        }
+        if (!ok) return -1;
+    } else if (!(xmin >= 1.0 && xmax <= (double)V.W - 1.0)) {
+        return -1;
+    }
+    double qx[4], qy[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        qx[m] = PX[vi[m]] - (double)ix0;
+        qy[m] = PY[vi[m]] - (double)iy0;
+    }
+    const double rho_m = 6.0 / fabs(det6);
+    const double qscale = V.qpow == 1 ? 1.0 : (V.qpow == 0 ? 1.0 / (L.tet_mass * rho_m) : L.tet_mass * rho_m);
+    const double mass_px = V.mass_px * qscale;
+    double D[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int b = kFace[a][0], c = kFace[a][1], d = kFace[a][2];
+        const double ex = qx[c] - qx[b], ey = qy[c] - qy[b];
+        const double fx = qx[d] - qx[b], fy = qy[d] - qy[b];
+        D[a] = ex * fy - ey * fx;
+    }
+    if (D[0] == 0.0 || D[1] == 0.0 || D[2] == 0.0 || D[3] == 0.0) return -1;
+    double b[6];
+    uint32_t smask = 0u;
+    double bmax = 0.0;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        const EdgeInfo E = kEdge[g];
+        const double ck = (double)E.sk * D[E.l];
+        const double cl = (double)E.sl * D[E.k];
+        const double K = mass_px / (ck * fabs(cl));
+        b[g] = -K * (qy[E.j] - qy[E.i]);
+        if ((ck > 0 && cl > 0) || (ck < 0 && cl < 0)) {
+            smask |= 1u << g;
+            bmax = fmax(bmax, fabs(b[g]));
+        }
+    }
+    // a triangle: the three edges avoiding one vertex; a quadrilateral: all
+    // but a pair of opposite edges (local edges g and 5 - g are opposite)
+    const bool tri = smask == 0x38u || smask == 0x26u || smask == 0x15u || smask == 0x0bu;
+    const bool quad = smask == 0x1eu || smask == 0x2du || smask == 0x33u;
+    if (!(tri || quad) || !(bmax <= crease_bmax)) return -1;
+    if (quad) {
+        // the two diagonals (the edges off the silhouette) must cross
+        const int g = smask == 0x1eu ? 0 : (smask == 0x2du ? 1 : 2);
+        const EdgeInfo E = kEdge[0];
+        const EdgeInfo F = kEdge[1];
+        const EdgeInfo G = kEdge[2];
+        const int i = g == 0 ? E.i : (g == 1 ? F.i : G.i), j = g == 0 ? E.j : (g == 1 ? F.j : G.j);
+        const int k = g == 0 ? E.k : (g == 1 ? F.k : G.k), l = g == 0 ? E.l : (g == 1 ? F.l : G.l);
+        auto px = [&](int v) { return v == 0 ? qx[0] : v == 1 ? qx[1] : v == 2 ? qx[2] : qx[3]; };
+        auto py = [&](int v) { return v == 0 ? qy[0] : v == 1 ? qy[1] : v == 2 ? qy[2] : qy[3]; };
+        const double den = (px(j) - px(i)) * (py(l) - py(k)) - (py(j) - py(i)) * (px(l) - px(k));
+        if (den == 0.0) return -1;
+    }
+    count_tet(L, det6, flagged, cnt);
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+        const EdgeInfo E = kEdge[g];
+        if (smask & (1u << g)) {
+            kd[g] = fabs(b[g]);
+            bits |= (b[g] > 0.0 ? 1u : 2u) << (2 * g);
+        } else {
+            // the ends' terms: edges (i, k), (i, l) and (j, k), (j, l)
+            const int ik = local_edge(E.i, E.k), il = local_edge(E.i, E.l);
+            const int jk = local_edge(E.j, E.k), jl = local_edge(E.j, E.l);
+            const bool oi = (smask >> ik & 1u) && (smask >> il & 1u);
+            const bool oj = (smask >> jk & 1u) && (smask >> jl & 1u);
+            const double ti = fabs(b[ik] - b[il]), tj = fabs(b[jk] - b[jl]);
+            kd[g] = oi && oj ? -0.5 * (ti + tj) : -(oi ? ti : tj);
+        }
+    }
+    sil = bits;
+    shf = shift;
+    return tri ? 3 : 4;
+}
+
 // Setup of the six tetrahedra of lattice cube `cube` (EDGES: the edge form's
-// code, used when V.edges is set): gather and unwrap the
+// code, used when V.edges is set; PASS 1 of it takes only the common case,
+// edge_tet_fast, and returns the tetrahedra left over in *todo_io, bit t for
+// tetrahedron t, which PASS 2 then sets up by the general code; PASS 0 does
+// both): gather and unwrap the
 // corners, volume determinant with its FP64 fallback, footprint.  Each
 // tetrahedron t's record goes to emit(t, head, payload) (flags 0 when it can
 // cover no pixel centre; REC_EDGED when its creases went to its edges' slots,
 // which setup_cube writes itself).
-template <int FORM, bool EDGES = false, typename Emit>
+template <int FORM, bool EDGES = false, int PASS = 0, typename Emit>
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, Emit &&emit,
-                               CubeCounts &cnt) {
+                               CubeCounts &cnt, uint32_t *todo_io = nullptr) {
     double X0[3], e[8][3];
     const bool moved = cube_corners(L, cube, X0, e);
     int64_t ci, cj, ck;
@@ -601,10 +783,73 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             }
         }
     }
-    // (one copy of the body for the six tetrahedra: unrolled, the setup
-    // kernels' code outgrew the instruction cache)
+    // edge form: slot u of vertex w at u * nvert + w; the cube's corner n is
+    // vertex cvert[n]
+    int64_t cvert[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const int64_t vx = ci + (n & 1) == L.d[0] ? 0 : ci + (n & 1);
+        const int64_t vy = cj + ((n >> 1) & 1) == L.d[1] ? 0 : cj + ((n >> 1) & 1);
+        const int64_t vz = ck + ((n >> 2) & 1) == L.d[2] ? 0 : ck + ((n >> 2) & 1);
+        cvert[n] = vx + (int64_t)L.d[0] * (vy + (int64_t)L.d[1] * vz);
+    }
+    // every slot of the cube's tetrahedra is written (zeros for the
+    // tetrahedra that keep their own record)
+    auto edge_slots = [&](int t, const double kd[6], uint32_t sil, uint32_t shf) {
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            const EdgeSlot S = kEdgeSlots.s[t][g];
+            const int64_t slot = (int64_t)S.u * nvert + cvert[S.ox + 2 * S.oy + 4 * S.oz];
+            V.kinks[slot] = kd[g];
+            V.sil[slot] = (uint8_t)(((sil >> (2 * g)) & 3u) | (((shf >> (2 * g)) & 3u) << 2));
+        }
+    };
+    // the tetrahedra the general code below takes
+    uint32_t todo = 0x3fu;
+    if constexpr (FORM == kFormPyramid && EDGES && PASS == 2) {
+        todo = *todo_io;
+    } else if constexpr (FORM == kFormPyramid && EDGES) {
+        // edge form (this instantiation runs only with V.edges set): the
+        // common case of each tetrahedron first, unrolled so that every
+        // corner index is a constant
+        todo = 0u;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            double kd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            uint32_t ksil = 0u, kshf = 0x555u;
+            const int fast = edge_tet_fast(L, V, t, e, PX, PY, crease_bmax, same_frame, qpack, kd, ksil, kshf, cnt);
+            if (fast < 0) {
+                todo |= 1u << t;
+                continue;
+            }
+            // (no payload: the head says whether its creases went to the edges)
+            RecHead R;
+            R.bx = 0;
+            R.by = 0;
+            R.flags = fast > 0 ? REC_EDGED | ((uint32_t)fast & REC_NG_MASK) : 0u;
+            R.spare = fast > 0 ? ksil | (kshf << 12) : 0u;
+            Payload P;
+            P.h = R;
+#pragma unroll
+            for (int g = 0; g < 14; ++g) P.c[g] = 0.0;
+            emit(t, R, P);
+            edge_slots(t, kd, ksil, kshf);
+        }
+        if constexpr (PASS == 1) {
+            *todo_io = todo;
+            return;
+        }
+        if (todo == 0u) return;
+    }
+    // The general code, one copy of the body for the six tetrahedra (unrolled,
+    // the setup kernels' code outgrew the instruction cache).  Its arrays are
+    // indexed by tetrahedron and live in scratch memory; the edge form hands
+    // it copies, so that its own stay in registers.
+    auto general = [&](const double (&e)[8][3], const double (&PX)[8], const double (&PY)[8]) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
+        if (!((todo >> t) & 1u)) continue;
+        double kd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // edge form: slope change per local edge
         // the record is built in registers and stored once, in whole lines
         RecHead R;
         R.bx = 0;
@@ -614,39 +859,12 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         double pc[14];
 #pragma unroll
         for (int g = 0; g < 14; ++g) pc[g] = 0.0;
-        double kd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // edge form: slope change per local edge
         [&] {
             const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
-            // ---- volume determinant (Eq. Eqn:TetVolume), 6 V: FP32 with a forward
-            // error bound, FP64 when the bound cannot certify it or it is small
-            double a64[3], b64[3], c64[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                a64[q] = e[v1][q] - e[v0][q];
-                b64[q] = e[v2][q] - e[v0][q];
-                c64[q] = e[v3][q] - e[v0][q];
-            }
-            const float a[3] = {(float)a64[0], (float)a64[1], (float)a64[2]};
-            const float b[3] = {(float)b64[0], (float)b64[1], (float)b64[2]};
-            const float c[3] = {(float)c64[0], (float)c64[1], (float)c64[2]};
-            const float p1 = b[1] * c[2], p2 = b[2] * c[1];
-            const float p3 = b[2] * c[0], p4 = b[0] * c[2];
-            const float p5 = b[0] * c[1], p6 = b[1] * c[0];
-            const float d32 = a[0] * (p1 - p2) + a[1] * (p3 - p4) + a[2] * (p5 - p6);
-            const float perm = fabsf(a[0]) * (fabsf(p1) + fabsf(p2)) + fabsf(a[1]) * (fabsf(p3) + fabsf(p4)) +
-                               fabsf(a[2]) * (fabsf(p5) + fabsf(p6));
-            const double ad = fabs((double)d32);
-            const bool flagged = L.det_cond_k < 0.0 || ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
-                                 ad < 2.0 * 6.0 * L.det_v0_frac * L.v0;
-            const double det6 = flagged ? det6_fp64(a64, b64, c64) : (double)d32;
-            cnt.n_dets += flagged ? 1 : 0;
-            if (det6 == 0.0) {
-                ++cnt.n_zero;
-                return;
-            }
-            ++cnt.n_tets;
-            cnt.n_inv += det6 > 0 ? 1 : 0;
-            cnt.n_deg += fabs(det6) < 6.0 * L.det_v0_frac * L.v0 ? 1 : 0;
+            bool flagged;
+            const double det6 = tet_det6(L, e, v0, v1, v2, v3, flagged);
+            count_tet(L, det6, flagged, cnt);
+            if (det6 == 0.0) return;
             if constexpr (FORM == kFormSplat) {
                 // the centroid method: a kernel of size h = |V|^(1/3) at the
                 // projected centroid, carrying q |V|
@@ -890,23 +1108,24 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         for (int g = 0; g < 14; ++g) P.c[g] = pc[g];
         emit(t, R, P);
         if constexpr (FORM == kFormPyramid && EDGES) {
-            if (V.edges) {
-                // every slot of the cube's tetrahedra is written (zeros for
-                // the tetrahedra that keep their own record)
-                const uint32_t sil = (R.flags & REC_EDGED) ? R.spare : 0u;
-                const uint32_t shf = (R.flags & REC_EDGED) ? (R.spare >> 12) : 0x555u;
-#pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    const EdgeSlot S = kEdgeSlots.s[t][e];
-                    const int64_t vx = ci + S.ox == L.d[0] ? 0 : ci + S.ox;
-                    const int64_t vy = cj + S.oy == L.d[1] ? 0 : cj + S.oy;
-                    const int64_t vz = ck + S.oz == L.d[2] ? 0 : ck + S.oz;
-                    const int64_t slot = (int64_t)S.u * nvert + vx + (int64_t)L.d[0] * (vy + (int64_t)L.d[1] * vz);
-                    V.kinks[slot] = kd[e];
-                    V.sil[slot] = (uint8_t)(((sil >> (2 * e)) & 3u) | (((shf >> (2 * e)) & 3u) << 2));
-                }
-            }
+            const bool edged = (R.flags & REC_EDGED) != 0u;
+            edge_slots(t, kd, edged ? R.spare & 0xfffu : 0u, edged ? R.spare >> 12 : 0x555u);
         }
+    }
+    };
+    if constexpr (FORM == kFormPyramid && EDGES) {
+        double e2[8][3], PX2[8], PY2[8];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            e2[n][0] = e[n][0];
+            e2[n][1] = e[n][1];
+            e2[n][2] = e[n][2];
+            PX2[n] = PX[n];
+            PY2[n] = PY[n];
+        }
+        general(e2, PX2, PY2);
+    } else {
+        general(e, PX, PY);
     }
 }
 

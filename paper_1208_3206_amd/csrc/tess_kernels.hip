@@ -606,13 +606,18 @@ constexpr int kSortPer = 7;     // pair ids per lane in one wavefront's class so
 constexpr int kNumClasses = 32;
 constexpr size_t kLdsBytes = 160 * 1024 - 64;  // dynamic LDS: 64 bytes stay for the static counter
 // Row stride of the tile accumulator: Tw + 4 cells; for the edge form
-// (`banked`) rounded up to 1 modulo 32 doubles, so that cells of one column
-// in consecutive rows fall in different LDS banks, where the rounded rows
-// leave room for one copy of the seam lines.  (The other forms draw a
-// record per lane, at cells with no such pattern, and need the LDS for the
-// wavefronts' class sorts.)
+// (`banked`) rounded up to 3 modulo 32 doubles.  A 16-lane group adds to
+// 16 consecutive rows at columns x0 + floor(r s), s the edge's columns per
+// row, so lane r's cell lies r (3 + s) doubles (mod 32) from lane 0's: 16
+// different banks for s = 0 and s = -1, the slopes of two of the lattice's
+// seven edge kinds seen along an axis, and two lanes a bank for s = +1.  (At
+// 1 modulo 32, s = -1 put all 16 in one bank; measured at stress 2048^2 the
+// raster took 24.2 ms there, 22.2 ms at 3, 22.3-22.6 at 5, 7, 9 and 11.)
+// The rounded rows leave room for one copy of the seam lines.  (The other
+// forms draw a record per lane, at cells with no such pattern, and need the
+// LDS for the wavefronts' class sorts.)
 __host__ __device__ inline int tile_stride(int Tw, int Th, bool banked) {
-    const int plain = Tw + 2 * kPad, padded = ((plain + 30) & ~31) + 1;
+    const int plain = Tw + 2 * kPad, padded = ((plain + 28) & ~31) + 3;
     const size_t need = sizeof(double) * ((size_t)Th * padded + 2 * (size_t)Th + 3 * ((size_t)Th + 1));
     return banked && need <= kLdsBytes ? padded : plain;
 }
@@ -644,42 +649,47 @@ __device__ __forceinline__ double row_bcast(double x) {
     return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
+// A double in LDS addressed by its byte offset: the kink loop clamps cell
+// addresses, not column indices, and the atomics take them as they are.
+typedef __attribute__((address_space(3))) double lds_f64;
+
 // The kinks of the edge jobs of a 16-lane group, edge I first: its rows
-// r0 + s, s = q, q + 16, ... < cnt, on lane q (pk: ta | cnt << 8), into the
-// tile rows of `stride` cells at sA (padding included).  Each kink's terms
-// are edge_pair's: crossing u = fma(r, sl, base), D (1 - f) at tile column
-// clamp(floor(u) - shift) + 1 and D f beside it.  TWO: every job has at
-// most 32 rows (tiles of at most 32 rows), two steps unrolled.
+// r0 + s, s = q, q + 16, ... < cnt, on lane q (pk: cnt << 8), into the tile
+// rows of stride8 bytes.  Each kink's terms are edge_pair's: crossing u =
+// fma(r, sl, base), D (1 - f) at tile column clamp(floor(u) - shift) + 1 and
+// D f beside it.  The job's owner lane precomputed the LDS byte offsets of
+// its first tile row: p1 of record column 0 (so that floor(u) * 8 + p1 is
+// the first cell) and p2 of the row's first padding cell (the clamp's lower
+// end; its upper end n8 bytes on); qs8 moves them to lane q's row.  TWO:
+// every job has at most 32 rows (tiles of at most 32 rows), two steps
+// unrolled.
 template <int I, bool TWO>
-__device__ __forceinline__ void group_kinks(const EdgeJob &J, uint32_t pk, int q, int n, double *sA, int stride) {
+__device__ __forceinline__ void group_kinks(const EdgeJob &J, uint32_t pk, uint32_t p1, uint32_t p2, int q, int qs8,
+                                            int n8, int stride8) {
     const uint32_t pki = row_bcast<I>(pk);
     const int cnt = (int)(pki >> 8);
     if (__builtin_amdgcn_ballot_w64(cnt > q) != 0ull) {  // some group has rows of its edge I
-        const int ta = (int)(pki & 0xffu);
-        const int r0 = (int)row_bcast<I>((uint32_t)J.r0), shift = (int)row_bcast<I>((uint32_t)J.shift);
+        const int r0 = (int)row_bcast<I>((uint32_t)J.r0);
+        const int rowp = (int)row_bcast<I>(p1) + qs8, lo = (int)row_bcast<I>(p2) + qs8;
         const double base = row_bcast<I>(J.base), sl = row_bcast<I>(J.sl), D = row_bcast<I>(J.D);
-        const int klo = shift - 3, khi = shift + n - 1;  // klo < khi
-        // row ta + q of the tile, moved so that column floor(u) - shift + 1
-        // is element floor(u)
-        double *const rowp = sA + ((ta + q) * stride + kPad + 1 - shift);
-        auto kink = [&](double *row, double rv) {
+        auto kink = [&](int rowb, int lob, double rv) {
             const double u = fma(rv, sl, base);
             const double fl = floor(u);
-            const int x = med3_i32((int)fl, klo, khi);
+            lds_f64 *const c = (lds_f64 *)(uintptr_t)(uint32_t)med3_i32(((int)fl << 3) + rowb, lob, lob + n8);
             const double v1 = fma(D, fl - u, D);
-            atomicAdd(&row[x], v1);
-            atomicAdd(&row[x + 1], D - v1);
+            __hip_atomic_fetch_add(c, v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(c + 1, D - v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         };
         if constexpr (TWO) {
             const double rv = (double)(r0 + q);
-            if (q < cnt) kink(rowp, rv);
-            if (q + 16 < cnt) kink(rowp + 16 * stride, rv + 16.0);
+            if (q < cnt) kink(rowp, lo, rv);
+            if (q + 16 < cnt) kink(rowp + 16 * stride8, lo + 16 * stride8, rv + 16.0);
         } else {
-            double *row = rowp;
-            for (int s = q; s < cnt; s += 16, row += 16 * stride) kink(row, (double)(r0 + s));
+            int rb = rowp, lb = lo;
+            for (int s = q; s < cnt; s += 16, rb += 16 * stride8, lb += 16 * stride8) kink(rb, lb, (double)(r0 + s));
         }
     }
-    if constexpr (I < 15) group_kinks<I + 1, TWO>(J, pk, q, n, sA, stride);
+    if constexpr (I < 15) group_kinks<I + 1, TWO>(J, pk, p1, p2, q, qs8, n8, stride8);
 }
 
 // LDS of one wavefront's class sort: kNumClasses counters, then 64 * kSortPer entries
@@ -925,11 +935,15 @@ __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head
                     // edge here: that copy's seam line, further copies (rare)
                     EdgeJob J{};
                     if (is_edge(id)) J = edge_job(P, B, tx0, ty0, n, rows, kinks);
-                    const uint32_t pk = (uint32_t)J.ta | ((uint32_t)J.cnt << 8);
+                    const uint32_t pk = (uint32_t)J.cnt << 8;
+                    const int row8 = (int)(uint32_t)(uintptr_t)(lds_f64 *)sA + J.ta * stride * 8;
+                    const uint32_t p1 = (uint32_t)(row8 + (kPad + 1 - J.shift) * 8);
+                    const uint32_t p2 = (uint32_t)(row8 + (kPad - 2) * 8);
+                    const int qs8 = (int)q * stride * 8;
                     if (rows <= 32)
-                        group_kinks<0, true>(J, pk, (int)q, n, sA, stride);
+                        group_kinks<0, true>(J, pk, p1, p2, (int)q, qs8, (n + 2) * 8, stride * 8);
                     else
-                        group_kinks<0, false>(J, pk, (int)q, n, sA, stride);
+                        group_kinks<0, false>(J, pk, p1, p2, (int)q, qs8, (n + 2) * 8, stride * 8);
                     const uint64_t sm = __builtin_amdgcn_ballot_w64(J.seamed);
                     if (sm != 0ull) {
                         const uint32_t below =

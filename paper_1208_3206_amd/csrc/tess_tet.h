@@ -445,13 +445,15 @@ struct CubeCounts {
 // Eq. Eqn:TetVolume: FP32 with a forward error bound, FP64 when the bound
 // cannot certify it or it is small (flagged).
 TESS_HD inline double tet_det6(const LatticeParams &L, const double e[8][3], int v0, int v1, int v2, int v3,
-                               bool &flagged) {
+                               bool &flagged);
+// The same from the tetrahedron's own four corner offsets ev.
+TESS_HD inline double tet_det6(const LatticeParams &L, const double ev[4][3], bool &flagged) {
     double a64[3], b64[3], c64[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        a64[q] = e[v1][q] - e[v0][q];
-        b64[q] = e[v2][q] - e[v0][q];
-        c64[q] = e[v3][q] - e[v0][q];
+        a64[q] = ev[1][q] - ev[0][q];
+        b64[q] = ev[2][q] - ev[0][q];
+        c64[q] = ev[3][q] - ev[0][q];
     }
     const float a[3] = {(float)a64[0], (float)a64[1], (float)a64[2]};
     const float b[3] = {(float)b64[0], (float)b64[1], (float)b64[2]};
@@ -466,6 +468,40 @@ TESS_HD inline double tet_det6(const LatticeParams &L, const double e[8][3], int
     flagged = L.det_cond_k < 0.0 || ad <= L.det_cond_k * 0x1p-24 * (double)perm ||
               ad < 2.0 * 6.0 * L.det_v0_frac * L.v0;
     return flagged ? det6_fp64(a64, b64, c64) : (double)d32;
+}
+TESS_HD inline double tet_det6(const LatticeParams &L, const double e[8][3], int v0, int v1, int v2, int v3,
+                               bool &flagged) {
+    const double ev[4][3] = {{e[v0][0], e[v0][1], e[v0][2]}, {e[v1][0], e[v1][1], e[v1][2]},
+                             {e[v2][0], e[v2][1], e[v2][2]}, {e[v3][0], e[v3][1], e[v3][2]}};
+    return tet_det6(L, ev, flagged);
+}
+
+// Tetrahedron T's corners from the cube's arrays, by constant index.
+template <int T>
+TESS_HD inline void tet_corners_t(const double e[8][3], const double PX[8], const double PY[8], double ev[4][3],
+                                  double pxv[4], double pyv[4]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        ev[m][0] = e[kTet[T][m]][0];
+        ev[m][1] = e[kTet[T][m]][1];
+        ev[m][2] = e[kTet[T][m]][2];
+        pxv[m] = PX[kTet[T][m]];
+        pyv[m] = PY[kTet[T][m]];
+    }
+}
+// The same for a tetrahedron t known only at run time: a switch (one
+// branch when t is the same across the wavefront) instead of an array
+// indexed by t, which the compiler would put in scratch memory.
+TESS_HD inline void tet_corners(int t, const double e[8][3], const double PX[8], const double PY[8],
+                                double ev[4][3], double pxv[4], double pyv[4]) {
+    switch (t) {
+        case 0: tet_corners_t<0>(e, PX, PY, ev, pxv, pyv); break;
+        case 1: tet_corners_t<1>(e, PX, PY, ev, pxv, pyv); break;
+        case 2: tet_corners_t<2>(e, PX, PY, ev, pxv, pyv); break;
+        case 3: tet_corners_t<3>(e, PX, PY, ev, pxv, pyv); break;
+        case 4: tet_corners_t<4>(e, PX, PY, ev, pxv, pyv); break;
+        default: tet_corners_t<5>(e, PX, PY, ev, pxv, pyv); break;
+    }
 }
 
 // The setup's counts for one tetrahedron of determinant det6.
@@ -842,14 +878,14 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         if (todo == 0u) return;
     }
     // The general code, one copy of the body for the six tetrahedra (unrolled,
-    // the setup kernels' code outgrew the instruction cache).  Its arrays are
-    // indexed by tetrahedron and live in scratch memory; the edge form hands
-    // it copies, so that its own stay in registers.
+    // the setup kernels' code outgrew the instruction cache).
     auto general = [&](const double (&e)[8][3], const double (&PX)[8], const double (&PY)[8]) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
         if (!((todo >> t) & 1u)) continue;
         double kd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // edge form: slope change per local edge
+        double ev[4][3], pxv[4], pyv[4];                 // the tetrahedron's corners
+        tet_corners(t, e, PX, PY, ev, pxv, pyv);
         // the record is built in registers and stored once, in whole lines
         RecHead R;
         R.bx = 0;
@@ -860,9 +896,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
 #pragma unroll
         for (int g = 0; g < 14; ++g) pc[g] = 0.0;
         [&] {
-            const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
             bool flagged;
-            const double det6 = tet_det6(L, e, v0, v1, v2, v3, flagged);
+            const double det6 = tet_det6(L, ev, flagged);
             count_tet(L, det6, flagged, cnt);
             if (det6 == 0.0) return;
             if constexpr (FORM == kFormSplat) {
@@ -875,9 +910,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 double cxp = 0.0, cyp = 0.0;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const int vm = kTet[t][m];
-                    cxp += 0.25 * PX[vm];
-                    cyp += 0.25 * PY[vm];
+                    cxp += 0.25 * pxv[m];
+                    cyp += 0.25 * pyv[m];
                 }
                 const double rx = 2.0 * hh * V.inv_du, ry = 2.0 * hh * V.inv_dv, lim = 1.0e8;
                 int sx0 = (int)fmax(ceil(cxp - rx - 0.5), -lim), sx1 = (int)fmin(floor(cxp + rx - 0.5), lim);
@@ -905,7 +939,6 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 // and the pixel box of their projection onto the window
                 const double rho = L.tet_mass * 6.0 / fabs(det6);
                 const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
-                const int vi[4] = {v0, v1, v2, v3};
                 double ybase[3];
 #pragma unroll
                 for (int r = 0; r < 3; ++r) ybase[r] = V.rot[3 * r] * b0[0] + V.rot[3 * r + 1] * b0[1] + V.rot[3 * r + 2] * b0[2];
@@ -918,8 +951,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                         double acc = 0.0;
 #pragma unroll
                         for (int m = 0; m < 4; ++m)
-                            acc += 0.25 * (ybase[r] + (V.rot[3 * r] * e[vi[m]][0] + V.rot[3 * r + 1] * e[vi[m]][1] +
-                                                       V.rot[3 * r + 2] * e[vi[m]][2]));
+                            acc += 0.25 * (ybase[r] + (V.rot[3 * r] * ev[m][0] + V.rot[3 * r + 1] * ev[m][1] +
+                                                       V.rot[3 * r + 2] * ev[m][2]));
                         yc[r] = acc;
                     }
                     if (V.splat || sqrt(yc[0] * yc[0] + yc[1] * yc[1] + yc[2] * yc[2]) > V.lod_radius) {
@@ -959,8 +992,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                     double yv[3];
 #pragma unroll
                     for (int r = 0; r < 3; ++r)
-                        yv[r] = ybase[r] + (V.rot[3 * r] * e[vi[m]][0] + V.rot[3 * r + 1] * e[vi[m]][1] +
-                                            V.rot[3 * r + 2] * e[vi[m]][2]);
+                        yv[r] = ybase[r] + (V.rot[3 * r] * ev[m][0] + V.rot[3 * r + 1] * ev[m][1] +
+                                            V.rot[3 * r + 2] * ev[m][2]);
                     pc[3 * m + 0] = yv[0];
                     pc[3 * m + 1] = yv[1];
                     pc[3 * m + 2] = yv[2];
@@ -999,12 +1032,11 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 return;
             }
             // ---- screen footprint (FP64)
-            const int vi[4] = {v0, v1, v2, v3};
-            double xmin = PX[v0], xmax = PX[v0], ymin = PY[v0], ymax = PY[v0];
+            double xmin = pxv[0], xmax = pxv[0], ymin = pyv[0], ymax = pyv[0];
 #pragma unroll
             for (int m = 1; m < 4; ++m) {
-                xmin = fmin(xmin, PX[vi[m]]); xmax = fmax(xmax, PX[vi[m]]);
-                ymin = fmin(ymin, PY[vi[m]]); ymax = fmax(ymax, PY[vi[m]]);
+                xmin = fmin(xmin, pxv[m]); xmax = fmax(xmax, pxv[m]);
+                ymin = fmin(ymin, pyv[m]); ymax = fmax(ymax, pyv[m]);
             }
             // pixel centres ix + 1/2 inside [xmin, xmax] (clamped far outside any image)
             const double lim = 1.0e8;
@@ -1020,8 +1052,8 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
             double qx[4], qy[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                qx[m] = PX[vi[m]] - (double)ix0;
-                qy[m] = PY[vi[m]] - (double)iy0;
+                qx[m] = pxv[m] - (double)ix0;
+                qy[m] = pyv[m] - (double)iy0;
             }
             const double rho_m = 6.0 / fabs(det6);  // rho / m
             if constexpr (FORM == kFormFace) {
@@ -1029,7 +1061,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
                 double T[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
-                    T[m] = Tc + V.rot[6] * e[vi[m]][0] + V.rot[7] * e[vi[m]][1] + V.rot[8] * e[vi[m]][2];
+                    T[m] = Tc + V.rot[6] * ev[m][0] + V.rot[7] * ev[m][1] + V.rot[8] * ev[m][2];
                 const double rho = L.tet_mass * rho_m;
                 const double qv = V.qpow == 0 ? 1.0 : (V.qpow == 1 ? rho : rho * rho);
                 uint32_t ff = 0;
@@ -1113,20 +1145,7 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         }
     }
     };
-    if constexpr (FORM == kFormPyramid && EDGES) {
-        double e2[8][3], PX2[8], PY2[8];
-#pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            e2[n][0] = e[n][0];
-            e2[n][1] = e[n][1];
-            e2[n][2] = e[n][2];
-            PX2[n] = PX[n];
-            PY2[n] = PY[n];
-        }
-        general(e2, PX2, PY2);
-    } else {
-        general(e, PX, PY);
-    }
+    general(e, PX, PY);
 }
 
 // Pixel box of an edge from (ax, ay) to (bx, by): the columns that receive

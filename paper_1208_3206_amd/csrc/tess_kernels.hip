@@ -65,12 +65,32 @@ __global__ void __launch_bounds__(256, 2) k_setup(LatticeParams L, ViewParams V,
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
     if constexpr (EDGES) {
-        // edge form, the common case of every tetrahedron (no record: its
-        // creases go to the edge slots); the others are marked in the spill
-        // bit set, which k_setup_rest reads next
+        // edge form, the common cases of every tetrahedron (its creases to
+        // the edge slots, or a line-form record of its own, stored compactly
+        // as it comes); the others, and line-form records that found no
+        // room, are marked in the spill bit set, which k_setup_rest reads
+        // next
         for (int64_t cube = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cube < L.ncubes; cube += stride) {
             uint32_t todo = 0u;
-            setup_cube<FORM, EDGES, 1>(L, V, cube, [](int, const RecHead &, const Payload &) {}, cnt, &todo);
+            setup_cube<FORM, EDGES, 1>(
+                L, V, cube, [](int, const RecHead &, const Payload &) {}, cnt, &todo,
+                [&](int t, const RecHead &R) -> Payload * {
+                    // a line-form record: its slot first, then its values
+                    // straight to memory (held in registers they would cost
+                    // the kernel its occupancy)
+                    const unsigned long long slot = atomicAdd(V.own, 1ull);
+                    if (slot < V.own_cap) {
+                        head[slot] = R;
+                        return &coef[slot];
+                    }
+                    // no room: the count taken back (it stays at or above the
+                    // capacity, so no slot below it is handed out twice); the
+                    // tetrahedron is marked for k_setup_rest, which counts it
+                    // and marks it again
+                    atomicAdd(V.own, ~0ull);
+                    return nullptr;
+                },
+                [](int) {});
             while (todo) {
                 const int t = __builtin_ctz(todo);
                 todo &= todo - 1u;

@@ -617,13 +617,16 @@ TESS_HD inline double vertex_px(const LatticeParams &L, const ViewParams &V, int
 // silhouette, both ends for a diagonal of a quadrilateral one, averaged).
 // Returns -1, having counted nothing, when the tetrahedron needs the
 // general setup: a face seen edge-on, a silhouette set that is neither a
-// triangle nor a quadrilateral, crossing diagonals not found, a slope past
-// the line-form bound, or a period or margin test that fails; 0 (zeros)
-// when it has no volume or covers no pixel centre; else its number of
-// silhouette edges.
+// triangle nor a quadrilateral, crossing diagonals not found, or a period
+// or margin test that fails; 0 (zeros) when it has no volume or covers no
+// pixel centre; 8 when its footprint is steep along x, past the crease
+// form's bound: it then keeps its own record in the line form, returned in
+// own; else its number of silhouette edges.
+template <typename OwnSink>
 TESS_HD inline int edge_tet_fast(const LatticeParams &L, const ViewParams &V, int t, const double e[8][3],
-                                  const double PX[8], const double PY[8], double crease_bmax, bool same_frame,
-                                  uint32_t qpack, double kd[6], uint32_t &sil, uint32_t &shf, CubeCounts &cnt) {
+                                 const double PX[8], const double PY[8], double crease_bmax, bool same_frame,
+                                 uint32_t qpack, double kd[6], uint32_t &sil, uint32_t &shf, OwnSink &&own_sink,
+                                 CubeCounts &cnt) {
     const int v0 = kTet[t][0], v1 = kTet[t][1], v2 = kTet[t][2], v3 = kTet[t][3];
     bool flagged;
     const double det6 = tet_det6(L, e, v0, v1, v2, v3, flagged);
@@ -650,26 +653,6 @@ TESS_HD inline int edge_tet_fast(const LatticeParams &L, const ViewParams &V, in
     if (ix0 > ix1 || iy0 > iy1) {
         count_tet(L, det6, flagged, cnt);
         return 0;
-    }
-    // the period and margin tests of the edge form (as in setup_cube)
-    if (!same_frame) return -1;
-    uint32_t shift = 0x555u;
-    if (V.wrap) {
-        if (!(xmax - xmin < (double)V.W - 2.0)) return -1;
-        const int pt = (int)floor(xmin * V.inv_W);
-        shift = 0u;
-        bool ok = true;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const EdgeSlot S = kEdgeSlots.s[t][q];
-            const int m = S.ox + 2 * S.oy + 4 * S.oz;
-            const int per = (int)((qpack >> (4 * m)) & 15u) - 2 - pt;
-            ok = ok && per >= -1 && per <= 1;
-            shift |= (uint32_t)(per + 1) << (2 * q);
-        }
-        if (!ok) return -1;
-    } else if (!(xmin >= 1.0 && xmax <= (double)V.W - 1.0)) {
-        return -1;
     }
     double qx[4], qy[4];
 #pragma unroll
@@ -708,7 +691,62 @@ TESS_HD inline int edge_tet_fast(const LatticeParams &L, const ViewParams &V, in
     // but a pair of opposite edges (local edges g and 5 - g are opposite)
     const bool tri = smask == 0x38u || smask == 0x26u || smask == 0x15u || smask == 0x0bu;
     const bool quad = smask == 0x1eu || smask == 0x2du || smask == 0x33u;
-    if (!(tri || quad) || !(bmax <= crease_bmax)) return -1;
+    if (!(tri || quad)) return -1;
+    if (!(bmax <= crease_bmax)) {
+        // steep along x: the line form, whatever the edge form's tests say;
+        // its record holds the silhouette edges' face functions in edge
+        // order (footprint's G functions a + b u + c v: K times the cross
+        // product with the edge)
+        RecHead R;
+        R.bx = pack_range(ix0, ix1);
+        R.by = pack_range(iy0, iy1);
+        R.flags = (tri ? 3u : 4u) | REC_VALID;
+        R.spare = 0u;
+        // the payload is written where own_sink places it, a value at a time
+        // (no place: the general setup takes the tetrahedron)
+        Payload *const P = own_sink(t, R);
+        if (!P) return -1;
+        {
+            int k = 0;
+#pragma unroll
+            for (int g = 0; g < 6; ++g) {
+                if (!((smask >> g) & 1u)) continue;
+                const EdgeInfo E = kEdge[g];
+                const double dx = qx[E.j] - qx[E.i], dy = qy[E.j] - qy[E.i];
+                const double ck = (double)E.sk * D[E.l];
+                const double cl = (double)E.sl * D[E.k];
+                const double K = mass_px / (ck * fabs(cl));
+                P->c[3 * k + 0] = K * (dy * qx[E.i] - dx * qy[E.i]);
+                P->c[3 * k + 1] = -K * dy;
+                P->c[3 * k + 2] = K * dx;
+                ++k;
+            }
+            for (int g = 3 * k; g < 14; ++g) P->c[g] = 0.0;
+            P->h = R;
+        }
+        count_tet(L, det6, flagged, cnt);
+        return 8;
+    }
+    // the period and margin tests of the edge form (as in setup_cube)
+    if (!same_frame) return -1;
+    uint32_t shift = 0x555u;
+    if (V.wrap) {
+        if (!(xmax - xmin < (double)V.W - 2.0)) return -1;
+        const int pt = (int)floor(xmin * V.inv_W);
+        shift = 0u;
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const EdgeSlot S = kEdgeSlots.s[t][q];
+            const int m = S.ox + 2 * S.oy + 4 * S.oz;
+            const int per = (int)((qpack >> (4 * m)) & 15u) - 2 - pt;
+            ok = ok && per >= -1 && per <= 1;
+            shift |= (uint32_t)(per + 1) << (2 * q);
+        }
+        if (!ok) return -1;
+    } else if (!(xmin >= 1.0 && xmax <= (double)V.W - 1.0)) {
+        return -1;
+    }
     if (quad) {
         // the two diagonals (the edges off the silhouette) must cross
         const int g = smask == 0x1eu ? 0 : (smask == 0x2du ? 1 : 2);
@@ -746,7 +784,7 @@ TESS_HD inline int edge_tet_fast(const LatticeParams &L, const ViewParams &V, in
 }
 
 // Setup of the six tetrahedra of lattice cube `cube` (EDGES: the edge form's
-// code, used when V.edges is set; PASS 1 of it takes only the common case,
+// code, used when V.edges is set; PASS 1 of it takes only the common cases,
 // edge_tet_fast, and returns the tetrahedra left over in *todo_io, bit t for
 // tetrahedron t, which PASS 2 then sets up by the general code; PASS 0 does
 // both): gather and unwrap the
@@ -754,9 +792,24 @@ TESS_HD inline int edge_tet_fast(const LatticeParams &L, const ViewParams &V, in
 // tetrahedron t's record goes to emit(t, head, payload) (flags 0 when it can
 // cover no pixel centre; REC_EDGED when its creases went to its edges' slots,
 // which setup_cube writes itself).
+//
+// The edge form's common path writes a line-form record (edge_tet_fast) to
+// where own_sink(t, head) says, then calls own_done(t); without them the
+// record is built in a local payload and goes to emit like the others.
+template <int FORM, bool EDGES, int PASS, typename Emit, typename OwnSink, typename OwnDone>
+TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, Emit &&emit,
+                               CubeCounts &cnt, uint32_t *todo_io, OwnSink &&own_sink, OwnDone &&own_done);
 template <int FORM, bool EDGES = false, int PASS = 0, typename Emit>
 TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, Emit &&emit,
                                CubeCounts &cnt, uint32_t *todo_io = nullptr) {
+    Payload own;
+    setup_cube<FORM, EDGES, PASS>(
+        L, V, cube, emit, cnt, todo_io, [&](int, const RecHead &) -> Payload * { return &own; },
+        [&](int t) { emit(t, own.h, own); });
+}
+template <int FORM, bool EDGES, int PASS, typename Emit, typename OwnSink, typename OwnDone>
+TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int64_t cube, Emit &&emit,
+                               CubeCounts &cnt, uint32_t *todo_io, OwnSink &&own_sink, OwnDone &&own_done) {
     double X0[3], e[8][3];
     const bool moved = cube_corners(L, cube, X0, e);
     int64_t ci, cj, ck;
@@ -853,9 +906,15 @@ TESS_HD inline void setup_cube(const LatticeParams &L, const ViewParams &V, int6
         for (int t = 0; t < 6; ++t) {
             double kd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             uint32_t ksil = 0u, kshf = 0x555u;
-            const int fast = edge_tet_fast(L, V, t, e, PX, PY, crease_bmax, same_frame, qpack, kd, ksil, kshf, cnt);
+            const int fast =
+                edge_tet_fast(L, V, t, e, PX, PY, crease_bmax, same_frame, qpack, kd, ksil, kshf, own_sink, cnt);
             if (fast < 0) {
                 todo |= 1u << t;
+                continue;
+            }
+            if (fast == 8) {  // its own record is written
+                own_done(t);
+                edge_slots(t, kd, 0u, 0x555u);
                 continue;
             }
             // (no payload: the head says whether its creases went to the edges)

@@ -47,8 +47,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "7e09b40e29ab90025dd5495c8b6c99a60bdacc857f713a8a5da2e0fd99b44f79",
-    "fetch_kib": 46725656.4, "write_kib": 1427621.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "3d36055f8955f913dc939aab1697738f9cd059ee0be9b59166b728ca1c5e901f",
+    "fetch_kib": 46863033.8, "write_kib": 1427620.9, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

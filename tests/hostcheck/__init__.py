@@ -45,7 +45,9 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
     "no_counts": the edge form's raster without its fragment count, which is
     then not comparable; "split": as "no_counts", with each pair's first
     tile copy drawn from its edge job, row by row, as the GPU's 16-lane
-    groups do, and the rest by the pair routine that skips that copy)."""
+    groups do, and the rest by the pair routine that skips that copy;
+    "general": the edge form with every tetrahedron set up by the general
+    code, without the common-case path)."""
     P = ctypes.POINTER
     x, y, z = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, z))
     W, H = int(view["width"]), int(view["height"])
@@ -70,7 +72,7 @@ def pipeline(x, y, z, dims, view, periodic=True, total_mass=1.0, precision=0, ti
                            1 if view.get("projection", "orthographic") == "perspective" else 0,
                            1 if view.get("method", "tessellation") == "hybrid" else 0,
                            ctypes.c_double(float(view.get("lod_radius", 0.0))),
-                           {"no_counts": 2, "split": 3}.get(edges, 1 if edges else 0),
+                           {"no_counts": 2, "split": 3, "general": 4}.get(edges, 1 if edges else 0),
                            out64.ctypes.data_as(P(ctypes.c_double)),
                            out32.ctypes.data_as(P(ctypes.c_float)), st.ctypes.data_as(P(ctypes.c_longlong)))
     if rc != 0:

@@ -111,7 +111,11 @@ extern "C" int hc_pipeline(const float *x, const float *y, const float *z, const
         if (persp) setup_cube<kFormPersp>(L, V, cube, emit, cnt);
         else if (splat) setup_cube<kFormSplat>(L, V, cube, emit, cnt);
         else if (slab) setup_cube<kFormFace>(L, V, cube, emit, cnt);
-        else if (V.edges) setup_cube<kFormPyramid, true>(L, V, cube, emit, cnt);
+        else if (V.edges && edges == 4) {
+            // every tetrahedron by the general setup (the kernels' k_setup_rest path)
+            uint32_t all = 0x3fu;
+            setup_cube<kFormPyramid, true, 2>(L, V, cube, emit, cnt, &all);
+        } else if (V.edges) setup_cube<kFormPyramid, true>(L, V, cube, emit, cnt);
         else setup_cube<kFormPyramid>(L, V, cube, emit, cnt);
         tets += cnt.n_tets; zero += cnt.n_zero; inv += cnt.n_inv; dets += cnt.n_dets;
         for (int t = 0; t < 6; ++t) {

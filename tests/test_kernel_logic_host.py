@@ -327,3 +327,36 @@ def test_fast_floor_division_is_exact():
     f.restype = ctypes.c_int64
     for ulps in (0, 1, 4):
         assert f(ulps) == 0, ulps
+
+@pytest.mark.parametrize("case", ["wrap", "rotated", "density2", "steep", "undisplaced"])
+def test_edge_setup_common_path_equals_general_setup(case):
+    # The edge form's setup takes the common tetrahedron directly (its six
+    # slope changes from the silhouette set alone, a steep one's line-form
+    # record from its silhouette edges' face functions) and leaves the rest
+    # to the general code.  Run every tetrahedron through the general code
+    # instead: the slots, records, image and counts must not change, bit for
+    # bit.  "steep" lowers the crease form's slope bound so that many
+    # footprints keep the line form; "undisplaced" has faces seen edge-on
+    # (walls), which only the general code takes.
+    n = 16
+    kw = {}
+    if case == "undisplaced":
+        xyz = W.undisplaced(n)
+        view = W.z_view(96)
+    else:
+        xyz = W.zeldovich(n, 4, 4.0, seed=7)
+        if case == "rotated":
+            view = W.rotated_view(W.random_rotations(1, seed=3)[0], 120, 110)
+        elif case == "density2":
+            view = dict(W.z_view(128), quantity="density2")
+        else:
+            view = W.z_view(128)
+        if case == "steep":
+            kw["crease_div"] = 128 / 4.0
+    fast = hostcheck.pipeline(*xyz, (n, n, n), view, edges=True, **kw)
+    general = hostcheck.pipeline(*xyz, (n, n, n), view, edges="general", **kw)
+    assert np.array_equal(fast[0], general[0]) and np.array_equal(fast[1], general[1])
+    assert fast[2] == general[2]
+    assert fast[2]["edged"] > 0
+    if case == "steep":
+        assert fast[2]["crease_records"] < 0.95 * fast[2]["tets"]  # many line-form records

@@ -625,6 +625,9 @@ constexpr int kIdBurst = 8;     // pair ids a lane loads at once
 constexpr int kSortPer = 7;     // pair ids per lane in one wavefront's class sort
 constexpr int kNumClasses = 32;
 constexpr size_t kLdsBytes = 160 * 1024 - 64;  // dynamic LDS: 64 bytes stay for the static counter
+// edge form: a wavefront's queue of pairs whose seam lines are still to draw
+// (at most 63 waiting plus 64 added in one round)
+constexpr int kSeamQueue = 128;
 // Row stride of the tile accumulator: Tw + 4 cells; for the edge form
 // (`banked`) rounded up to 3 modulo 32 doubles.  A 16-lane group adds to
 // 16 consecutive rows at columns x0 + floor(r s), s the edge's columns per
@@ -633,12 +636,14 @@ constexpr size_t kLdsBytes = 160 * 1024 - 64;  // dynamic LDS: 64 bytes stay for
 // seven edge kinds seen along an axis, and two lanes a bank for s = +1.  (At
 // 1 modulo 32, s = -1 put all 16 in one bank; measured at stress 2048^2 the
 // raster took 24.2 ms there, 22.2 ms at 3, 22.3-22.6 at 5, 7, 9 and 11.)
-// The rounded rows leave room for one copy of the seam lines.  (The other
-// forms draw a record per lane, at cells with no such pattern, and need the
-// LDS for the wavefronts' class sorts.)
+// The rounded rows leave room for one copy of the seam lines and the seam
+// queues of a 1024-thread block.  (The other forms draw a record per lane,
+// at cells with no such pattern, and need the LDS for the wavefronts' class
+// sorts.)
 __host__ __device__ inline int tile_stride(int Tw, int Th, bool banked) {
     const int plain = Tw + 2 * kPad, padded = ((plain + 28) & ~31) + 3;
-    const size_t need = sizeof(double) * ((size_t)Th * padded + 2 * (size_t)Th + 3 * ((size_t)Th + 1));
+    const size_t need = sizeof(double) * ((size_t)Th * padded + 2 * (size_t)Th + 3 * ((size_t)Th + 1)) +
+                        sizeof(uint32_t) * 16 * kSeamQueue;
     return banked && need <= kLdsBytes ? padded : plain;
 }
 
@@ -714,9 +719,6 @@ __device__ __forceinline__ void group_kinks(const EdgeJob &J, uint32_t pk, uint3
 
 // LDS of one wavefront's class sort: kNumClasses counters, then 64 * kSortPer entries
 constexpr int kSortWords = kNumClasses + 64 * kSortPer;
-// edge form: a wavefront's queue of pairs whose seam lines are still to draw
-// (at most 63 waiting plus 64 added in one round)
-constexpr int kSeamQueue = 128;
 
 template <int TPB, int FORM, bool COUNT = true>
 __global__ void __launch_bounds__(TPB) k_raster(const RecHead *__restrict__ head,

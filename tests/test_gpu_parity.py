@@ -89,7 +89,7 @@ def test_tiny_config_full_image(tess, tiny_lattice):
 
 @pytest.mark.parametrize("rows,cols,chunk,block", [(0, 0, 0, 0), (4, 64, 256, 256), (16, 16, 64, 512),
                                                    (1, 200, 100, 1024), (3, 37, 1000, 256),
-                                                   (64, 256, 128, 1024)])
+                                                   (64, 256, 128, 1024), (100, 160, 0, 1024)])
 def test_ragged_image_all_tilings(tess, rows, cols, chunk, block):
     n = 16
     xyz = W.zeldovich(n, 5, 6.0, seed=99)

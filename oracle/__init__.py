@@ -60,9 +60,9 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (FP64, OpenMP).  Returns the library path."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", _LIB + ".tmp", "-lm"]
+               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", _LIB + ".tmp%x" % os.getpid(), "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
+        os.replace(_LIB + ".tmp%x" % os.getpid(), _LIB)  # (a file per process: parallel test workers)
     return _LIB
 
 

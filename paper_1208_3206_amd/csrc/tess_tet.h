@@ -2186,9 +2186,9 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
         off[a] = nn[0] * cf[3 * b] + nn[1] * cf[3 * b + 1] + nn[2] * cf[3 * b + 2];
     }
     const double q = cf[12];
-    // row-major walk of the box: k -> (y, x), stepping nlanes at a time
-    int y = y0 + lane0 / bw, x = x0 + lane0 % bw;
-    for (int k = lane0; k < npix; k += nlanes) {
+    // the chord through pixel (x, y): q |ray| (t_exit - t_entry), the ray's
+    // depths where it crosses the face planes
+    auto sample = [&](int x, int y) {
         const double pu = -0.5 * B.ext_u + ((double)x + 0.5) * du;
         const double pv = -0.5 * B.ext_v + ((double)y + 0.5) * dv;
         ++kinks;
@@ -2210,6 +2210,60 @@ TESS_HD inline uint32_t persp_pair(const RecHead &h, const double *cf, const Bin
             dep(y - ty0, x - tx0, q * ((hi - lo) * sqrt(pu * pu + pv * pv + 1.0)));
             ++frags;
         }
+    };
+    // (FP32: the spans only bound the columns to test, with a pixel to spare,
+    // and projections within 1000 window units round to well under a pixel)
+    float ex[4], ey[4];
+    bool spans_ok = nlanes == 64;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const double z = cf[3 * m + 2];
+        const double px = cf[3 * m] / z, py = cf[3 * m + 1] / z;
+        spans_ok = spans_ok && z > 0.0 && fabs(px) < 1.0e3 && fabs(py) < 1.0e3;
+        ex[m] = (float)px;
+        ey[m] = (float)py;
+    }
+    if (spans_ok) {
+        // all four vertices in front of the camera (and not near its plane):
+        // the tetrahedron covers the convex hull of their projections, so a
+        // row needs only the columns between its crossings with the six
+        // projected edges (one pixel wider each side; the per-pixel test
+        // decides).  A 16-lane group takes every fourth row of the box, its
+        // lanes the row's columns (the box holds three samples per covered
+        // pixel at the perspective workload).
+        float sl[6];  // edge (i, j)'s x step per unit of height (a level edge: 0)
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 4; ++j, ++k) sl[k] = ey[j] != ey[i] ? (ex[j] - ex[i]) / (ey[j] - ey[i]) : 0.0f;
+        const int g = lane0 >> 4, lq = lane0 & 15;
+        for (int y = y0 + g; y <= y1; y += 4) {
+            const float pv = (float)(-0.5 * B.ext_v + ((double)y + 0.5) * dv);
+            float xl = 1e30f, xr = -1e30f;
+            k = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = i + 1; j < 4; ++j, ++k) {
+                    if (pv < fminf(ey[i], ey[j]) || pv > fmaxf(ey[i], ey[j])) continue;
+                    const bool level = ey[j] == ey[i];
+                    const float xa = level ? fminf(ex[i], ex[j]) : fmaf(pv - ey[i], sl[k], ex[i]);
+                    const float xb = level ? fmaxf(ex[i], ex[j]) : xa;
+                    xl = fminf(xl, xa);
+                    xr = fmaxf(xr, xb);
+                }
+            if (!(xl <= xr)) continue;
+            const double fa = ((double)xl + 0.5 * B.ext_u) / du - 0.5, fb = ((double)xr + 0.5 * B.ext_u) / du - 0.5;
+            const int xa = max((int)floor(fa) - 1, x0), xb = min((int)ceil(fb) + 1, x1);
+            for (int x = xa + lq; x <= xb; x += 16) sample(x, y);
+        }
+        return frags;
+    }
+    // row-major walk of the box: k -> (y, x), stepping nlanes at a time
+    int y = y0 + lane0 / bw, x = x0 + lane0 % bw;
+    for (int k = lane0; k < npix; k += nlanes) {
+        sample(x, y);
         x += sx;
         y += sy;
         if (x > x1) {

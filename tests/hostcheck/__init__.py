@@ -19,9 +19,11 @@ def build():
     if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
         cmd = ["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-arch=gfx950", "-O2", "-std=c++17",
                "-fPIC", "-shared", "-I", os.path.join(ROOT, "paper_1208_3206_amd", "csrc"),
-               "-I", os.path.join(ROOT, "include"), SRC, "-o", LIB + ".tmp"]
+               "-I", os.path.join(ROOT, "include"), SRC, "-o", LIB + ".tmp%x" % os.getpid()]
+        # (a file of its own per process: parallel test workers may all
+        # rebuild after a header change, and each replaces the library whole)
         subprocess.run(cmd, check=True, capture_output=True)
-        os.replace(LIB + ".tmp", LIB)
+        os.replace(LIB + ".tmp%x" % os.getpid(), LIB)
     return LIB
 
 

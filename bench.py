@@ -47,8 +47,8 @@ TRAFFIC = {
     "sources": ["paper_1208_3206_amd/csrc/tess_kernels.hip", "paper_1208_3206_amd/csrc/tess_tet.h",
                 "paper_1208_3206_amd/csrc/tess_internal.h"],
     "workload": "stress_256^3_to_2048^2", "tile": [32, 512], "block": 1024,
-    "sha256": "dd9f6be5fee34686b6a021424a058678ab932933a255a2c8efa161dbe935b0c5",
-    "fetch_kib": 46854247.7, "write_kib": 1427621.9, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "946348e51242f5fc4224eedefa6189e91ca0dea5dc6aea1e21062f10b9e75107",
+    "fetch_kib": 46861873.6, "write_kib": 1427621.1, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 

@@ -401,7 +401,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
-              "(this build shows one GPU's share of the work)", file=sys.stderr)
+              "(the path is measured on one GPU's share of the work)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -177,7 +177,7 @@ typedef enum {
  * table form a conforming mesh); it regroups FP64 sums and changes nothing
  * else.  Other views ignore the field. */
 typedef enum {
-    TESS_FORM_AUTO = 0,            /* edge form when a lattice cell spans >= 6 pixels */
+    TESS_FORM_AUTO = 0,            /* edge form when a lattice cell spans >= 1.5 pixels (wrapped image) or >= 6 */
     TESS_FORM_PER_TETRAHEDRON = 1, /* every tetrahedron drawn on its own              */
     TESS_FORM_EDGES = 2            /* edge form whenever the record ids fit 32 bits    */
 } tess_form;
@@ -253,8 +253,9 @@ typedef struct {
  * Pixel values are sums of FP64 terms accumulated with atomics, rounded to
  * FP32 at the end: repeated calls agree to FP64 rounding, not bit for bit.
  * Plain pyramids are drawn in the form tune->form selects (automatic: the
- * edge form when a lattice cell spans at least 6 pixels); the edge form is
- * not used when its 13 records per lattice point would not fit 32-bit ids.
+ * edge form when a lattice cell spans at least 1.5 pixels of a periodic
+ * image, or 6 pixels of a window without wrap); the edge form is not used
+ * when its 13 records per lattice point would not fit 32-bit ids.
  * With stats == NULL the call only enqueues work on `stream`: it never waits
  * for the device, so it may be captured into a HIP graph once a first call
  * with the same lattice, view shape and tune has sized the workspace (the

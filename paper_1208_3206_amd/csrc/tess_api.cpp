@@ -405,17 +405,20 @@ void make_params(const tess_lattice_s *L, const tess_view *v, int form, LatticeP
     // q / rho needs |V| to full precision (the face form stores q itself, a
     // splat q |V| and |V|^(1/3))
     if (vp.qpow != 1 || vp.slab || vp.splat || vp.persp) lp.det_cond_k = -1.0;
-    // Plain pyramids take the edge form when a lattice cell spans at least
-    // 6 pixels: its cost per lattice vertex (the edge records) then buys a
+    // Plain pyramids take the edge form when a lattice cell spans enough
+    // pixels: its cost per lattice vertex (the edge records) then buys a
     // larger saving in the raster, whose work grows with the rows each
-    // tetrahedron covers (measured: 2 pixels per cell, 512 rotated 512^2
-    // windows on 128^3, favour the per-tetrahedron form; 8 pixels per cell
-    // and more favour the edge form at every size tried).  tess_tune.form
-    // forces either (the two give the same image up to rounding).
+    // tetrahedron covers.  Measured on Zel'dovich lattices (128^3, 256^3):
+    // periodic images favour the edge form from 1.5 pixels per cell up (1.1x
+    // to 5x faster at 1.5 to 5 pixels, more beyond); windows without wrap
+    // favour the per-tetrahedron form at 2 to 4 pixels per cell (rotated
+    // views, 2x) and the edge form from 8 up.  tess_tune.form forces either
+    // (the two give the same image up to rounding).
     const double cell_px = std::cbrt(d.box[0] * d.box[1] * d.box[2] / (double)lp.ncubes) *
                            std::sqrt(vp.inv_du * vp.inv_dv);
     const bool force_tet = form == TESS_FORM_PER_TETRAHEDRON, force_edges = form == TESS_FORM_EDGES;
-    vp.edges = (view_form(vp) == kFormPyramid && !force_tet && (force_edges || cell_px >= 6.0)) ? 1 : 0;
+    const double min_cell_px = vp.wrap ? 1.5 : 6.0;
+    vp.edges = (view_form(vp) == kFormPyramid && !force_tet && (force_edges || cell_px >= min_cell_px)) ? 1 : 0;
     vp.kinks = nullptr;
     vp.sil = nullptr;
 }
